@@ -1,0 +1,161 @@
+"""Benchmark: MPPI control steps per second on one MI355X.
+
+One benchmark step = one MPPI control step of Algorithm 1 on the device: one
+iteration (noise, rollouts with the likelihood-ratio cost, min-shifted weights, FP64
+normaliser and weighted update), emission of u0, the warm shift, and the harness
+plant step, with the state and the emitted control resident in HBM.  The timed
+region replays these steps back to back; `value` is rollout-steps per second
+(K * T * iterations / wall time).
+
+Default workload: the kinematic bicycle on a 256 x 256 cost map, K = 4096, T = 100,
+nu = 2.  Other single-GPU workloads can be chosen with --workload.
+
+The JSON line also carries the dominant kernel's roofline (its mean duration from
+HIP events recorded on the library's own stream during a profiled pass of the same
+length) and the CPU oracle's throughput on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "rollout-steps/sec (K*T) and MPPI iters/sec; p50/p99 step latency batched vs plain"
+
+# Algorithmic operations per rollout-step of the rollout kernel (FMA = 2, every other
+# FP32/FP64 arithmetic op, transcendental and Philox integer op = 1).  Derivation in
+# DESIGN.md ("Roofline").
+ALG_OPS_PER_ROLLOUT_STEP = {"cartpole": 87, "bicycle": 164, "quadrotor": 740, "linear": 90}
+
+# VALU peak without packed FP32 (the build forbids v_pk_*_f32): 256 CUs x 4 SIMD x 16 lanes
+# x 2 (FMA) x 2.4 GHz.
+ALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+PUBLISHED_FP32_TFLOPS = 157.3
+
+
+def make_workload(name):
+    import workloads as W
+    if name == "bicycle":
+        return W.bicycle().replace(seed=0)
+    if name == "cartpole":
+        return W.cartpole(nu=2.0).replace(seed=0)
+    if name == "quadrotor":
+        return W.quadrotor(nu=2.0).replace(seed=0)
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(wl, seconds):
+    """The FP64 oracle, as it stands, on a bounded closed-loop sample of the workload."""
+    from oracle import mppi
+    x = np.asarray(wl.x0, float).copy()
+    U = mppi.initial_sequence(wl)
+    it = 0
+    t0 = time.perf_counter()
+    while True:
+        u0, U, it, _ = mppi.control_step(wl, x, U, it)
+        x = mppi.plant_step(wl, x, u0)
+        el = time.perf_counter() - t0
+        if el >= seconds:
+            break
+    return dict(value=wl.K * wl.T * it / el, unit="rollout-steps/s", cores=1, kind="oracle",
+                sample=f"{it} closed-loop control steps of the same workload (K={wl.K}, T={wl.T}), "
+                       f"{el:.1f} s, NumPy FP64 on one host thread")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--warmup", type=int, default=30)
+    ap.add_argument("--workload", default="bicycle")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-parity", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only: the MPPI path shards over samples with one small "
+              f"exchange per iteration, which is designed but not built; --gpus {args.gpus} is not supported.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1509_01149_amd as P
+    P.load()
+    if not torch.cuda.is_available():
+        raise SystemExit("no GPU visible: bench.py runs the HIP path only")
+    dev = torch.device("cuda:0")
+    wl = make_workload(args.workload)
+    stream = torch.cuda.current_stream(dev)
+    ctrl = P.controller_for(wl, device=0, torch_stream=stream, torch_workspace=True)
+    x_dev = torch.tensor(np.asarray(wl.x0, float), dtype=torch.float64, device=dev)
+    u_dev = torch.zeros(wl.m, dtype=torch.float64, device=dev)
+    xp, up = x_dev.data_ptr(), u_dev.data_ptr()
+
+    def run(n):
+        for _ in range(n):
+            ctrl.step_async(xp, up, 1)
+            ctrl.plant_step_async(xp, up)
+
+    run(args.warmup)
+    ctrl.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run(args.steps)
+    ctrl.sync()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    rollout_steps = wl.K * wl.T
+    value = rollout_steps / (ms_per_step / 1e3)
+
+    # profiled pass of the same length: per-kernel HIP events on the library's stream
+    ctrl.set_profiling(True)
+    run(args.steps)
+    times = ctrl.kernel_times()
+    ctrl.set_profiling(False)
+    kind, (k_ms, k_n) = max(times.items(), key=lambda kv: kv[1][0])
+    roll_ms = times["rollout"][0]
+    ops = ALG_OPS_PER_ROLLOUT_STEP[wl.name] * rollout_steps
+    achieved = ops / (roll_ms / 1e3) / 1e12
+    roofline = dict(bound="alu", kernel="rollout", achieved=round(achieved, 4), peak=round(ALU_PEAK_TFLOPS, 2),
+                    unit="TFLOP/s", frac=round(achieved / ALU_PEAK_TFLOPS, 5), traffic=None,
+                    peak_published_fp32=PUBLISHED_FP32_TFLOPS,
+                    alg_ops_per_launch=ops, kernel_ms=round(roll_ms, 5),
+                    kernel_ms_all={k: round(v[0], 5) for k, v in times.items()}, launches_timed=times["rollout"][1])
+
+    parity = None
+    if not args.no_parity:
+        from oracle import mppi
+        x = x_dev.cpu().numpy()
+        U = ctrl.get_controls()
+        it = ctrl.iteration()
+        u0 = ctrl.step(x)
+        U_gpu = ctrl.get_controls()
+        u0_r, U_r, _, _ = mppi.control_step(wl, x, U, it)
+        scale = max(1.0, float(np.max(np.abs(U_r))))
+        parity = dict(U_rel_err=float(max(np.max(np.abs(U_gpu - U_r)), np.max(np.abs(u0 - u0_r))) / scale),
+                      tolerance=1e-4, at_iteration=it)
+
+    out = dict(metric=METRIC, value=round(value, 1), unit="rollout-steps/s", n_gpus=1, steps=args.steps,
+               warmup=args.warmup, ms_per_step=round(ms_per_step, 5), higher_is_better=True, scaling="weak",
+               vs_baseline=None, dtype="f32", data="synthetic",
+               config=dict(workload=f"{wl.name} K={wl.K} T={wl.T} nu={wl.nu} (1 iteration per control step)",
+                           K=wl.K, T=wl.T, n=wl.n, m=wl.m, nu=wl.nu, lam=wl.lam, n_iters=1,
+                           precision="FP32 rollouts, FP64 weights/normaliser/update", parallelism="single GPU"),
+               mppi_iters_per_s=round(1e3 / ms_per_step, 1), roofline=roofline)
+    if parity is not None:
+        out["parity"] = parity
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
+        out["cpu_baseline"]["value"] = round(out["cpu_baseline"]["value"], 1)
+    ctrl.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,213 @@
+/*
+ * mppi.h -- C ABI of libmppi: Model Predictive Path Integral control with
+ * covariance-variable importance sampling on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Williams, Aldrich & Theodorou, "Model Predictive Path Integral Control
+ * using Covariance Variable Importance Sampling" (arXiv 1509.01149).
+ *   - problem statement (control-affine dynamics, state cost q, terminal cost phi,
+ *     control cost R): Section II;
+ *   - likelihood-ratio running cost for the special case A = sqrt(nu) I and the
+ *     Monte-Carlo update law: Section III-C;
+ *   - the control loop (sample, roll out, weight, update, send u0, shift, u_init):
+ *     Algorithm 1, Section IV.
+ *
+ * Conventions for every function below:
+ *   - Every call returns an mppi_status; nothing throws across the ABI.  On failure
+ *     mppi_last_error() returns a thread-local message describing the first error.
+ *   - Host arrays passed in are owned by the caller and copied before the call
+ *     returns; the library never keeps or frees a caller pointer, except a lent
+ *     workspace (mppi_config.workspace), which must outlive the context.
+ *   - Matrices are row-major, FP64 on the host.  The library rounds to FP32 where the
+ *     rollouts need it and keeps the nominal control sequence, the weights'
+ *     normaliser and the weighted update in FP64 on the device.
+ *   - A context is used by one host thread at a time and runs its work in order on
+ *     its stream.  A server (mppi_server_*) is internally synchronised.
+ *   - "Device pointer" means memory on the context's device (hipMalloc or a torch
+ *     CUDA tensor); "host pointer" means ordinary or pinned host memory.
+ */
+#ifndef MPPI_H
+#define MPPI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MPPI_ABI_VERSION 1
+
+typedef enum {
+  MPPI_OK = 0,
+  MPPI_EINVAL = -1,    /* invalid argument or configuration; nothing was changed      */
+  MPPI_ENOMEM = -2,    /* device or host allocation failed, or workspace too small    */
+  MPPI_EDEVICE = -3,   /* a HIP call failed or no usable GPU is present               */
+  MPPI_EBUSY = -4,     /* server: no slot or HBM budget free right now; retry later   */
+  MPPI_ENUMERIC = -5,  /* every sample of some iteration had a non-finite path cost:  */
+                       /* that iteration left the control sequence unchanged          */
+  MPPI_ENOTFOUND = -6  /* server: unknown slot or request                             */
+} mppi_status;
+
+/* Compiled-in systems.  The dynamics f, G and the costs q, phi of Section II cannot be
+ * host callbacks on a GPU, so they are chosen from this registry and parameterised by
+ * the matching mppi_*_params block passed in mppi_config.params. */
+typedef enum {
+  MPPI_SYS_LINEAR = 0,        /* x' = A x + B u,  q = x'Qx, phi = x'Qf x         */
+  MPPI_SYS_CARTPOLE = 1,      /* cart with uniform pole, force input             */
+  MPPI_SYS_BICYCLE = 2,       /* kinematic bicycle on a bilinear cost map        */
+  MPPI_SYS_QUADROTOR = 3,     /* 12-state rigid-body quadrotor, spherical obstacles */
+  MPPI_SYS_QUADROTOR_MLP = 4  /* quadrotor cost, dynamics by a learned MLP (mppi_mlp) */
+} mppi_system;
+
+/* MPPI_SYS_LINEAR: n_state <= 4, n_ctrl in {1, 2, 4}.  A (n x n), B (n x m), Q (n x n),
+ * Qf (n x n), all row-major FP64, copied at create. */
+typedef struct {
+  const double *A, *B, *Q, *Qf;
+} mppi_linear_params;
+
+/* MPPI_SYS_CARTPOLE: state (x, xdot, theta, thetadot), theta = 0 upright, n = 4, m = 1.
+ *   h = (F + mp l thetadot^2 sin theta) / (mc + mp)
+ *   thetaddot = (g sin theta - cos theta h) / (l (4/3 - mp cos^2 theta / (mc + mp)))
+ *   xddot = h - mp l thetaddot cos theta / (mc + mp)
+ * q(x) = sum_i q_diag[i] x_i^2, phi(x) = sum_i qf_diag[i] x_i^2. */
+typedef struct {
+  double mass_cart, mass_pole, half_length, gravity;
+  double q_diag[4];
+  double qf_diag[4];
+} mppi_cartpole_params;
+
+/* MPPI_SYS_BICYCLE: state (x, y, yaw, v, delta), controls (accel, steer rate), n = 5, m = 2.
+ *   x' = v cos yaw, y' = v sin yaw, yaw' = v tan(clamp(delta, +-steer_limit)) / wheelbase,
+ *   v' = a, delta' = omega   (steer_limit <= 0: no clamp)
+ * q = bilinear(map, x / cell_size, y / cell_size) + w_speed (v - v_target)^2, phi = 0.
+ * The map is map_h x map_w FP32, row-major [y][x], cell (0,0) centred at the origin,
+ * coordinates clamped to the grid; copied at create.  map_w, map_h >= 2. */
+typedef struct {
+  double wheelbase, v_target, w_speed, cell_size, steer_limit;
+  int32_t map_w, map_h;
+  const float *map;
+} mppi_bicycle_params;
+
+/* MPPI_SYS_QUADROTOR: state (p[3], v[3], roll, pitch, yaw, body rates w[3]), n = 12,
+ * controls = rotor thrusts (f1 on +x, f2 on +y, f3 on -x, f4 on -y), m = 4.
+ *   p' = v,  v' = (sum f / mass) R_zyx(roll, pitch, yaw) e3 - gravity e3,
+ *   euler' = W(euler)^-1 w,  w' = J^-1 (tau - w x J w),
+ *   tau = (arm (f2 - f4), arm (f3 - f1), yaw_coef (f1 - f2 + f3 - f4)),  J = diag(inertia)
+ * q = w_goal |p - goal|^2 + w_obs sum_j max(0, (r_j + obs_margin)^2 - |p - c_j|^2)^2,
+ * phi = 0.  obstacles: n_obstacles x 4 (cx, cy, cz, r) FP64, copied; n_obstacles <= 256. */
+typedef struct {
+  double mass, gravity, arm, yaw_coef;
+  double inertia[3];
+  double goal[3];
+  double w_goal, w_obs, obs_margin;
+  int32_t n_obstacles;
+  const double *obstacles;
+} mppi_quadrotor_params;
+
+/* MPPI_SYS_QUADROTOR_MLP: the quadrotor's cost with dynamics x <- x + MLP(x, u)
+ * (a trained mppi_mlp, see below).  The network is copied at create. */
+typedef struct mppi_mlp mppi_mlp;
+typedef struct {
+  mppi_quadrotor_params quad;
+  const mppi_mlp *mlp;
+} mppi_quadrotor_mlp_params;
+
+/* Everything Algorithm 1 is "given" (Section IV), plus device placement. */
+typedef struct {
+  int32_t abi_version;        /* must be MPPI_ABI_VERSION                                  */
+  int32_t system;             /* mppi_system                                               */
+  int32_t n_state, n_ctrl;    /* n, m; must match the system                               */
+  int32_t K;                  /* samples (rollouts) per iteration, 1 <= K <= 4194304        */
+  int32_t T;                  /* horizon steps N of Algorithm 1, 1 <= T <= 1024            */
+  double dt;                  /* time step of the Euler discretisation (Section II-A)      */
+  double lambda;              /* temperature, > 0                                          */
+  double nu;                  /* exploration factor: perturbations ~ N(0, nu Sigma), > 0;  */
+                              /* the paper's experiments use nu >= 1                      */
+  const double *sigma;        /* m x m natural per-step covariance of the perturbation     */
+  const double *R;            /* m x m control-cost matrix; NULL => lambda * inv(sigma)    */
+  const double *u_init;       /* m: value of the control appended by the warm shift        */
+  const double *u_nominal0;   /* T x m initial nominal sequence; NULL => u_init repeated   */
+  const void *params;         /* the system's mppi_*_params block                          */
+  uint64_t params_bytes;      /* sizeof that block                                         */
+  uint64_t seed;              /* Philox4x32-10 key of the rollout noise                    */
+  int32_t device;             /* HIP device ordinal                                        */
+  int32_t use_graph;          /* nonzero: replay each step as a captured hipGraph          */
+  void *stream;               /* hipStream_t to run on; NULL => the library makes its own  */
+  void *workspace;            /* optional caller-owned device memory for all device state  */
+  uint64_t workspace_bytes;   /* its size; must be >= mppi_workspace_bytes()               */
+} mppi_config;
+
+typedef struct mppi_ctx mppi_ctx;
+
+/* Bytes of device memory a context for cfg needs (to size a lent workspace). */
+int mppi_workspace_bytes(const mppi_config *cfg, uint64_t *bytes);
+
+/* Validate cfg, copy its arrays, allocate (or carve the lent workspace into) device
+ * buffers and upload the nominal sequence.  The iteration counter starts at 0. */
+int mppi_create(const mppi_config *cfg, mppi_ctx **out);
+
+/* Wait for the context's work and free everything it owns.  NULL is accepted. */
+int mppi_destroy(mppi_ctx *ctx);
+
+/* One control step of Algorithm 1 from state x0 (host, n): n_iters >= 1 iterations of
+ * {sample, roll out, weight, update}, then write u0 = u_0 (host, m) and shift the
+ * sequence (u_i <- u_{i+1}, u_{T-1} <- u_init).  Blocks until done.
+ * Returns MPPI_ENUMERIC if some iteration had no finite path cost (u0 and the shift are
+ * still produced). */
+int mppi_step(mppi_ctx *ctx, const double *x0, int32_t n_iters, double *u0);
+
+/* As mppi_step with device pointers x0_dev (n FP64) and u0_dev (m FP64), enqueued on
+ * the context's stream; returns without waiting.  The numeric status is collected by
+ * mppi_sync. */
+int mppi_step_async(mppi_ctx *ctx, const double *x0_dev, int32_t n_iters, double *u0_dev);
+
+/* Wait for the context's stream.  Returns MPPI_ENUMERIC if any iteration since the
+ * previous mppi_sync / mppi_step had no finite path cost, and clears that flag. */
+int mppi_sync(mppi_ctx *ctx);
+
+/* Harness plant (Algorithm 1: "update the current state after receiving feedback"):
+ * x_dev <- x_dev + dt (f(x) + G(x) u_dev) in FP64 with the context's model, no noise.
+ * Device pointers, enqueued on the context's stream. */
+int mppi_plant_step_async(mppi_ctx *ctx, double *x_dev, const double *u_dev);
+
+/* Copy the current (post-shift) nominal sequence, T x m FP64, to / from the host. */
+int mppi_get_controls(mppi_ctx *ctx, double *u, uint64_t len);
+int mppi_set_controls(mppi_ctx *ctx, const double *u, uint64_t len);
+
+/* Snapshot / restore of the controller state: the FP64 nominal sequence and the
+ * iteration counter that keys the noise.  buf is host memory of *needed bytes
+ * (query with buf = NULL). */
+int mppi_get_state(mppi_ctx *ctx, void *buf, uint64_t len, uint64_t *needed);
+int mppi_set_state(mppi_ctx *ctx, const void *buf, uint64_t len);
+int mppi_get_iteration(mppi_ctx *ctx, uint64_t *iteration);
+
+/* Diagnostics of the last iteration (host outputs; any pointer may be NULL):
+ * path costs S-tilde (K, FP64; +inf for non-finite), rho = min_k S_k, the normaliser
+ * eta = sum_k exp(-(S_k - rho) / lambda), and the applied update dU (T x m FP64). */
+int mppi_debug_last(mppi_ctx *ctx, double *costs, double *rho, double *eta, double *dU);
+
+/* The standard normals the device draws for samples [k0, k0 + nk) at `iteration`
+ * (nk x T x m FP32, host), from the same device code the rollouts use. */
+int mppi_debug_normals(mppi_ctx *ctx, uint64_t iteration, int32_t k0, int32_t nk, float *eps);
+
+/* Raw Philox4x32-10 blocks on `device`: out[4i..4i+3] = philox(counters[4i..4i+3], seed).
+ * counters and out are host arrays of 4n uint32. */
+int mppi_debug_philox(int32_t device, uint64_t seed, const uint32_t *counters, int32_t n, uint32_t *out);
+
+/* Kernel timing.  While profiling is on, every kernel of mppi_step / mppi_step_async is
+ * launched directly (no graph) between two hipEvents recorded on the context's stream.
+ * mppi_kernel_times waits for the stream and returns, per kernel kind (0 = rollout,
+ * 1 = update, 2 = finalize), the mean duration in milliseconds and the number of
+ * launches timed since profiling was switched on (avg_ms[3], count[3], host). */
+int mppi_set_profiling(mppi_ctx *ctx, int32_t on);
+int mppi_kernel_times(mppi_ctx *ctx, double *avg_ms, int64_t *count);
+
+/* Thread-local description of the last failure ("" if none). */
+const char *mppi_last_error(void);
+
+/* Library version string. */
+const char *mppi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MPPI_H */

@@ -47,14 +47,17 @@ def likelihood_ratio_cost(du, U_i, R, nu):
     return 0.5 * (1.0 - 1.0 / nu) * quad + lin + const
 
 
-def rollout_costs(system, x0, U, du, dt, R, nu):
-    """Path costs S-tilde for all samples: the K-loop of Algorithm 1."""
+def rollout_costs(system, x0, U, du, dt, R, nu, observer=None):
+    """Path costs S-tilde for all samples: the K-loop of Algorithm 1.
+    ``observer(i, x)``, if given, sees the states x_{i+1} of all samples (tests only)."""
     K, T, m = du.shape
     x = np.repeat(np.asarray(x0, float)[None, :], K, axis=0)
     S = np.zeros(K)
     for i in range(T):
         v = U[i][None, :] + du[:, i, :]
         x = _systems.euler_step(system, x, v, dt)
+        if observer is not None:
+            observer(i, x)
         S = S + (system.q(x) + likelihood_ratio_cost(du[:, i, :], U[i], R, nu))
     S = S + system.phi(x)
     S[~np.isfinite(S)] = np.inf
@@ -75,14 +78,14 @@ def weights_and_update(S, du, lam):
     return w, eta, rho, dU, STATUS_OK
 
 
-def iteration(wl, x0, U, iteration_index, system=None, nu=None, du=None):
+def iteration(wl, x0, U, iteration_index, system=None, nu=None, du=None, observer=None):
     """One MPPI iteration on workload ``wl`` from state x0 around sequence U."""
     system = system or _systems.make(wl)
     nu = wl.nu if nu is None else nu
     U = np.asarray(U, float)
     if du is None:
         du = control_noise(wl.seed, iteration_index, wl.K, wl.T, wl.sigma, nu)
-    S = rollout_costs(system, x0, U, du, wl.dt, np.asarray(wl.R, float), nu)
+    S = rollout_costs(system, x0, U, du, wl.dt, np.asarray(wl.R, float), nu, observer)
     w, eta, rho, dU, status = weights_and_update(S, du, wl.lam)
     return IterationResult(U=U + dU, S=S, w=w, eta=eta, rho=rho, dU=dU, du=du, status=status)
 
@@ -95,13 +98,13 @@ def shift(U, u_init):
     return out
 
 
-def control_step(wl, x0, U, iteration_start, system=None):
+def control_step(wl, x0, U, iteration_start, system=None, observer=None):
     """``n_iters`` iterations, emit u0, shift.  Returns (u0, U_shifted, next_iteration, results)."""
     system = system or _systems.make(wl)
     results = []
     it = iteration_start
     for _ in range(wl.n_iters):
-        r = iteration(wl, x0, U, it, system=system)
+        r = iteration(wl, x0, U, it, system=system, observer=observer)
         results.append(r)
         U = r.U
         it += 1

@@ -1,0 +1,302 @@
+"""ctypes binding of libmppi (argument marshalling only).
+
+Every step of the MPPI iteration runs in the HIP kernels behind the C ABI declared in
+include/mppi.h; this module only converts Python/NumPy arguments into the ABI's
+structs and pointers.  PyTorch is used, when asked, for device memory (a lent
+workspace) and for the stream to run on.  There is no fallback: if libmppi.so is not
+built, loading fails with an error.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Dict, Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmppi.so")
+
+ABI_VERSION = 1
+OK, EINVAL, ENOMEM, EDEVICE, EBUSY, ENUMERIC, ENOTFOUND = 0, -1, -2, -3, -4, -5, -6
+SYS_LINEAR, SYS_CARTPOLE, SYS_BICYCLE, SYS_QUADROTOR, SYS_QUADROTOR_MLP = 0, 1, 2, 3, 4
+
+_dp = C.POINTER(C.c_double)
+_fp = C.POINTER(C.c_float)
+_u32p = C.POINTER(C.c_uint32)
+_u64p = C.POINTER(C.c_uint64)
+
+
+class MppiError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libmppi error {code}: {msg}")
+        self.code = code
+
+
+class NumericError(MppiError):
+    """An iteration had no sample with a finite path cost (status MPPI_ENUMERIC)."""
+
+
+class LinearParams(C.Structure):
+    _fields_ = [("A", _dp), ("B", _dp), ("Q", _dp), ("Qf", _dp)]
+
+
+class CartPoleParams(C.Structure):
+    _fields_ = [("mass_cart", C.c_double), ("mass_pole", C.c_double), ("half_length", C.c_double),
+                ("gravity", C.c_double), ("q_diag", C.c_double * 4), ("qf_diag", C.c_double * 4)]
+
+
+class BicycleParams(C.Structure):
+    _fields_ = [("wheelbase", C.c_double), ("v_target", C.c_double), ("w_speed", C.c_double),
+                ("cell_size", C.c_double), ("steer_limit", C.c_double), ("map_w", C.c_int32),
+                ("map_h", C.c_int32), ("map", _fp)]
+
+
+class QuadrotorParams(C.Structure):
+    _fields_ = [("mass", C.c_double), ("gravity", C.c_double), ("arm", C.c_double), ("yaw_coef", C.c_double),
+                ("inertia", C.c_double * 3), ("goal", C.c_double * 3), ("w_goal", C.c_double),
+                ("w_obs", C.c_double), ("obs_margin", C.c_double), ("n_obstacles", C.c_int32),
+                ("obstacles", _dp)]
+
+
+class QuadrotorMlpParams(C.Structure):
+    _fields_ = [("quad", QuadrotorParams), ("mlp", C.c_void_p)]
+
+
+class Config(C.Structure):
+    _fields_ = [("abi_version", C.c_int32), ("system", C.c_int32), ("n_state", C.c_int32), ("n_ctrl", C.c_int32),
+                ("K", C.c_int32), ("T", C.c_int32), ("dt", C.c_double), ("lambda_", C.c_double),
+                ("nu", C.c_double), ("sigma", _dp), ("R", _dp), ("u_init", _dp), ("u_nominal0", _dp),
+                ("params", C.c_void_p), ("params_bytes", C.c_uint64), ("seed", C.c_uint64),
+                ("device", C.c_int32), ("use_graph", C.c_int32), ("stream", C.c_void_p),
+                ("workspace", C.c_void_p), ("workspace_bytes", C.c_uint64)]
+
+
+_lib = None
+
+
+def load() -> C.CDLL:
+    """Load libmppi.so (built in-tree); raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run paper_1509_01149_amd.build.build() first")
+    lib = C.CDLL(LIB_PATH)
+    sig = {
+        "mppi_workspace_bytes": [C.POINTER(Config), _u64p],
+        "mppi_create": [C.POINTER(Config), C.POINTER(C.c_void_p)],
+        "mppi_destroy": [C.c_void_p],
+        "mppi_step": [C.c_void_p, _dp, C.c_int32, _dp],
+        "mppi_step_async": [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p],
+        "mppi_sync": [C.c_void_p],
+        "mppi_plant_step_async": [C.c_void_p, C.c_void_p, C.c_void_p],
+        "mppi_get_controls": [C.c_void_p, _dp, C.c_uint64],
+        "mppi_set_controls": [C.c_void_p, _dp, C.c_uint64],
+        "mppi_get_state": [C.c_void_p, C.c_void_p, C.c_uint64, _u64p],
+        "mppi_set_state": [C.c_void_p, C.c_void_p, C.c_uint64],
+        "mppi_get_iteration": [C.c_void_p, _u64p],
+        "mppi_debug_last": [C.c_void_p, _dp, _dp, _dp, _dp],
+        "mppi_debug_normals": [C.c_void_p, C.c_uint64, C.c_int32, C.c_int32, _fp],
+        "mppi_debug_philox": [C.c_int32, C.c_uint64, _u32p, C.c_int32, _u32p],
+        "mppi_set_profiling": [C.c_void_p, C.c_int32],
+        "mppi_kernel_times": [C.c_void_p, _dp, C.POINTER(C.c_int64)],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = C.c_int
+    lib.mppi_last_error.restype = C.c_char_p
+    lib.mppi_last_error.argtypes = []
+    lib.mppi_version.restype = C.c_char_p
+    lib.mppi_version.argtypes = []
+    _lib = lib
+    return lib
+
+
+def check(rc: int) -> int:
+    if rc == OK:
+        return rc
+    msg = load().mppi_last_error().decode()
+    if rc == ENUMERIC:
+        raise NumericError(rc, msg)
+    raise MppiError(rc, msg)
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def _ptr(a: Optional[np.ndarray], t=_dp):
+    return None if a is None else a.ctypes.data_as(t)
+
+
+def make_params(system: int, params: Dict, keep: list):
+    """Pack the system parameter dict (field names as in include/mppi.h) into its C struct."""
+    if system == SYS_LINEAR:
+        mats = [_f64(params[k]) for k in ("A", "B", "Q", "Qf")]
+        keep.extend(mats)
+        return LinearParams(*[_ptr(m) for m in mats])
+    if system == SYS_CARTPOLE:
+        p = CartPoleParams(params["mass_cart"], params["mass_pole"], params["half_length"], params["gravity"])
+        p.q_diag[:] = list(_f64(params["q_diag"]))
+        p.qf_diag[:] = list(_f64(params["qf_diag"]))
+        return p
+    if system == SYS_BICYCLE:
+        m = np.ascontiguousarray(np.asarray(params["map"], dtype=np.float32))
+        keep.append(m)
+        return BicycleParams(params["wheelbase"], params["v_target"], params["w_speed"], params["cell_size"],
+                             params["steer_limit"], m.shape[1], m.shape[0], _ptr(m, _fp))
+    if system in (SYS_QUADROTOR, SYS_QUADROTOR_MLP):
+        ob = _f64(params["obstacles"]).reshape(-1, 4)
+        keep.append(ob)
+        q = QuadrotorParams(params["mass"], params["gravity"], params["arm"], params["yaw_coef"])
+        q.inertia[:] = list(_f64(params["inertia"]))
+        q.goal[:] = list(_f64(params["goal"]))
+        q.w_goal, q.w_obs, q.obs_margin = params["w_goal"], params["w_obs"], params["obs_margin"]
+        q.n_obstacles = ob.shape[0]
+        q.obstacles = _ptr(ob) if ob.shape[0] else None
+        if system == SYS_QUADROTOR:
+            return q
+        mlp = params["mlp"]
+        keep.append(mlp)
+        return QuadrotorMlpParams(q, C.c_void_p(mlp.handle))
+    raise ValueError(f"unknown system {system}")
+
+
+class Controller:
+    """One MPPI controller context (mppi_create ... mppi_destroy)."""
+
+    def __init__(self, *, system: int, n: int, m: int, K: int, T: int, dt: float, lam: float, nu: float,
+                 sigma, R=None, u_init, params: Dict, u_nominal0=None, seed: int = 0, device: int = 0,
+                 use_graph: bool = True, torch_stream=None, torch_workspace: bool = False):
+        lib = load()
+        self._keep = []
+        self.n, self.m, self.K, self.T = n, m, K, T
+        sig = _f64(sigma).reshape(m, m)
+        Rm = None if R is None else _f64(R).reshape(m, m)
+        ui = _f64(u_init).reshape(m)
+        un = None if u_nominal0 is None else _f64(u_nominal0).reshape(T, m)
+        self._keep += [sig, Rm, ui, un]
+        self._params = make_params(system, params, self._keep)
+        cfg = Config()
+        cfg.abi_version = ABI_VERSION
+        cfg.system, cfg.n_state, cfg.n_ctrl, cfg.K, cfg.T = system, n, m, K, T
+        cfg.dt, cfg.lambda_, cfg.nu = dt, lam, nu
+        cfg.sigma, cfg.R, cfg.u_init, cfg.u_nominal0 = _ptr(sig), _ptr(Rm), _ptr(ui), _ptr(un)
+        cfg.params = C.cast(C.pointer(self._params), C.c_void_p)
+        cfg.params_bytes = C.sizeof(self._params)
+        cfg.seed = seed & 0xFFFFFFFFFFFFFFFF
+        cfg.device = device
+        cfg.use_graph = 1 if use_graph else 0
+        self._workspace = None
+        if torch_stream is not None:
+            cfg.stream = C.c_void_p(torch_stream.cuda_stream)
+        if torch_workspace:
+            import torch
+            nbytes = C.c_uint64(0)
+            check(lib.mppi_workspace_bytes(C.byref(cfg), C.byref(nbytes)))
+            self._workspace = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device=f"cuda:{device}")
+            base = self._workspace.data_ptr()
+            cfg.workspace = C.c_void_p((base + 255) & ~255)
+            cfg.workspace_bytes = nbytes.value
+        self.cfg = cfg
+        h = C.c_void_p()
+        check(lib.mppi_create(C.byref(cfg), C.byref(h)))
+        self.handle = h
+        self._lib = lib
+
+    # -- control -----------------------------------------------------------------
+    def step(self, x0, n_iters: int = 1) -> np.ndarray:
+        """One control step from host state x0; returns u0 (m,)."""
+        x = _f64(x0).reshape(self.n)
+        u0 = np.zeros(self.m)
+        check(self._lib.mppi_step(self.handle, _ptr(x), int(n_iters), _ptr(u0)))
+        return u0
+
+    def step_async(self, x0_dev_ptr: int, u0_dev_ptr: int, n_iters: int = 1):
+        check(self._lib.mppi_step_async(self.handle, C.c_void_p(x0_dev_ptr), int(n_iters), C.c_void_p(u0_dev_ptr)))
+
+    def sync(self):
+        check(self._lib.mppi_sync(self.handle))
+
+    def plant_step_async(self, x_dev_ptr: int, u_dev_ptr: int):
+        check(self._lib.mppi_plant_step_async(self.handle, C.c_void_p(x_dev_ptr), C.c_void_p(u_dev_ptr)))
+
+    def get_controls(self) -> np.ndarray:
+        u = np.zeros((self.T, self.m))
+        check(self._lib.mppi_get_controls(self.handle, _ptr(u), u.size))
+        return u
+
+    def set_controls(self, U):
+        u = _f64(U).reshape(self.T, self.m)
+        check(self._lib.mppi_set_controls(self.handle, _ptr(u), u.size))
+
+    def get_state(self) -> bytes:
+        need = C.c_uint64(0)
+        check(self._lib.mppi_get_state(self.handle, None, 0, C.byref(need)))
+        buf = C.create_string_buffer(need.value)
+        check(self._lib.mppi_get_state(self.handle, buf, need.value, C.byref(need)))
+        return buf.raw
+
+    def set_state(self, blob: bytes):
+        buf = C.create_string_buffer(blob, len(blob))
+        check(self._lib.mppi_set_state(self.handle, buf, len(blob)))
+
+    def iteration(self) -> int:
+        v = C.c_uint64(0)
+        check(self._lib.mppi_get_iteration(self.handle, C.byref(v)))
+        return int(v.value)
+
+    def debug_last(self):
+        S = np.zeros(self.K)
+        rho = C.c_double(0)
+        eta = C.c_double(0)
+        dU = np.zeros((self.T, self.m))
+        check(self._lib.mppi_debug_last(self.handle, _ptr(S), C.byref(rho), C.byref(eta), _ptr(dU)))
+        return S, rho.value, eta.value, dU
+
+    def debug_normals(self, iteration: int, k0: int, nk: int) -> np.ndarray:
+        out = np.zeros((nk, self.T, self.m), dtype=np.float32)
+        check(self._lib.mppi_debug_normals(self.handle, int(iteration), int(k0), int(nk), _ptr(out, _fp)))
+        return out
+
+    def set_profiling(self, on: bool):
+        check(self._lib.mppi_set_profiling(self.handle, 1 if on else 0))
+
+    def kernel_times(self):
+        """Mean kernel durations (ms) and launch counts: {'rollout': (ms, n), 'update': ..., 'finalize': ...}."""
+        avg = np.zeros(3)
+        cnt = (C.c_int64 * 3)()
+        check(self._lib.mppi_kernel_times(self.handle, _ptr(avg), cnt))
+        return {k: (float(avg[i]), int(cnt[i])) for i, k in enumerate(("rollout", "update", "finalize"))}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self._lib.mppi_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def philox(counters: np.ndarray, seed: int, device: int = 0) -> np.ndarray:
+    """Raw Philox4x32-10 blocks computed on the GPU: counters (n, 4) uint32 -> (n, 4) uint32."""
+    lib = load()
+    c = np.ascontiguousarray(np.asarray(counters, dtype=np.uint32).reshape(-1, 4))
+    out = np.zeros_like(c)
+    check(lib.mppi_debug_philox(device, seed & 0xFFFFFFFFFFFFFFFF, _ptr(c, _u32p), c.shape[0], _ptr(out, _u32p)))
+    return out
+
+
+def version() -> str:
+    return load().mppi_version().decode()

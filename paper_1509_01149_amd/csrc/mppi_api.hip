@@ -1,0 +1,783 @@
+// Host runtime and C ABI of libmppi (declarations and contracts: include/mppi.h).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/mppi.h"
+#include "mppi_kernels.h"
+#include "mppi_runtime.h"
+
+using namespace mppi;
+
+// ----------------------------------------------------------------------- errors
+namespace mppi {
+thread_local std::string g_last_error;
+
+int fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+  return fail(MPPI_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+}  // namespace mppi
+
+#define HIP_TRY(call)                                   \
+  do {                                                  \
+    hipError_t _e = (call);                             \
+    if (_e != hipSuccess) return hip_fail(_e, #call);   \
+  } while (0)
+
+extern "C" const char *mppi_last_error(void) { return g_last_error.c_str(); }
+extern "C" const char *mppi_version(void) { return "libmppi 1.0 (gfx950)"; }
+
+// ------------------------------------------------------------- config validation
+namespace mppi {
+
+static bool finite_all(const double *p, int n) {
+  for (int i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+// Lower Cholesky factor of an m x m SPD matrix (row-major); all-zero => zero factor.
+static bool cholesky(const double *S, int m, double *L) {
+  bool zero = true;
+  for (int i = 0; i < m * m; ++i) zero = zero && S[i] == 0.0;
+  for (int i = 0; i < m * m; ++i) L[i] = 0.0;
+  if (zero) return true;
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j <= i; ++j) {
+      double s = S[i * m + j];
+      for (int k = 0; k < j; ++k) s -= L[i * m + k] * L[j * m + k];
+      if (i == j) {
+        if (!(s > 0.0)) return false;
+        L[i * m + i] = std::sqrt(s);
+      } else {
+        L[i * m + j] = s / L[j * m + j];
+      }
+    }
+  return true;
+}
+
+static bool invert(const double *A, int m, double *Ai) {
+  double a[16], b[16];
+  for (int i = 0; i < m * m; ++i) { a[i] = A[i]; b[i] = 0.0; }
+  for (int i = 0; i < m; ++i) b[i * m + i] = 1.0;
+  for (int c = 0; c < m; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < m; ++r)
+      if (std::fabs(a[r * m + c]) > std::fabs(a[piv * m + c])) piv = r;
+    if (a[piv * m + c] == 0.0) return false;
+    for (int k = 0; k < m; ++k) { std::swap(a[c * m + k], a[piv * m + k]); std::swap(b[c * m + k], b[piv * m + k]); }
+    const double d = a[c * m + c];
+    for (int k = 0; k < m; ++k) { a[c * m + k] /= d; b[c * m + k] /= d; }
+    for (int r = 0; r < m; ++r)
+      if (r != c) {
+        const double f = a[r * m + c];
+        for (int k = 0; k < m; ++k) { a[r * m + k] -= f * a[c * m + k]; b[r * m + k] -= f * b[c * m + k]; }
+      }
+  }
+  for (int i = 0; i < m * m; ++i) Ai[i] = b[i];
+  return true;
+}
+
+static int expected_dims(int sys, int *n, int *m) {
+  switch (sys) {
+    case MPPI_SYS_LINEAR: return 0;  // checked separately
+    case MPPI_SYS_CARTPOLE: *n = 4; *m = 1; return 1;
+    case MPPI_SYS_BICYCLE: *n = 5; *m = 2; return 1;
+    case MPPI_SYS_QUADROTOR: *n = 12; *m = 4; return 1;
+    case MPPI_SYS_QUADROTOR_MLP: *n = 12; *m = 4; return 1;
+    default: return -1;
+  }
+}
+
+int validate_config(const mppi_config *c) {
+  if (!c) return fail(MPPI_EINVAL, "config is NULL");
+  if (c->abi_version != MPPI_ABI_VERSION) return fail(MPPI_EINVAL, "abi_version %d != %d", c->abi_version, MPPI_ABI_VERSION);
+  int n = 0, m = 0;
+  const int d = expected_dims(c->system, &n, &m);
+  if (d < 0) return fail(MPPI_EINVAL, "unknown system %d", c->system);
+  if (d == 1 && (c->n_state != n || c->n_ctrl != m))
+    return fail(MPPI_EINVAL, "system %d needs n_state=%d n_ctrl=%d (got %d, %d)", c->system, n, m, c->n_state, c->n_ctrl);
+  if (c->system == MPPI_SYS_LINEAR) {
+    if (c->n_state < 1 || c->n_state > 4) return fail(MPPI_EINVAL, "linear system: n_state must be in [1, 4]");
+    if (c->n_ctrl != 1 && c->n_ctrl != 2 && c->n_ctrl != 4) return fail(MPPI_EINVAL, "linear system: n_ctrl must be 1, 2 or 4");
+  }
+  if (c->K < 1 || c->K > (1 << 22)) return fail(MPPI_EINVAL, "K=%d outside [1, 4194304]", c->K);
+  if (c->T < 1 || c->T > 1024) return fail(MPPI_EINVAL, "T=%d outside [1, 1024]", c->T);
+  if ((int64_t)c->T * c->n_ctrl > kMaxTM) return fail(MPPI_EINVAL, "T*n_ctrl exceeds %d", kMaxTM);
+  if (!(c->dt > 0.0) || !std::isfinite(c->dt)) return fail(MPPI_EINVAL, "dt must be finite and > 0");
+  if (!(c->lambda > 0.0) || !std::isfinite(c->lambda)) return fail(MPPI_EINVAL, "lambda must be finite and > 0");
+  if (!(c->nu > 0.0) || !std::isfinite(c->nu)) return fail(MPPI_EINVAL, "nu must be finite and > 0");
+  if (!c->sigma) return fail(MPPI_EINVAL, "sigma is NULL");
+  if (!c->u_init) return fail(MPPI_EINVAL, "u_init is NULL");
+  if (!c->params) return fail(MPPI_EINVAL, "params is NULL");
+  const int mm = c->n_ctrl;
+  if (!finite_all(c->sigma, mm * mm)) return fail(MPPI_EINVAL, "sigma has non-finite entries");
+  if (c->R && !finite_all(c->R, mm * mm)) return fail(MPPI_EINVAL, "R has non-finite entries");
+  if (!finite_all(c->u_init, mm)) return fail(MPPI_EINVAL, "u_init has non-finite entries");
+  if (c->u_nominal0 && !finite_all(c->u_nominal0, c->T * mm)) return fail(MPPI_EINVAL, "u_nominal0 has non-finite entries");
+  for (int i = 0; i < mm; ++i)
+    for (int j = 0; j < i; ++j)
+      if (c->sigma[i * mm + j] != c->sigma[j * mm + i]) return fail(MPPI_EINVAL, "sigma is not symmetric");
+  double L[16];
+  if (!cholesky(c->sigma, mm, L)) return fail(MPPI_EINVAL, "sigma is not positive definite (or zero)");
+  if (!c->R) {
+    double Si[16];
+    if (!invert(c->sigma, mm, Si)) return fail(MPPI_EINVAL, "R = NULL needs an invertible sigma");
+  }
+  size_t want = 0;
+  switch (c->system) {
+    case MPPI_SYS_LINEAR: want = sizeof(mppi_linear_params); break;
+    case MPPI_SYS_CARTPOLE: want = sizeof(mppi_cartpole_params); break;
+    case MPPI_SYS_BICYCLE: want = sizeof(mppi_bicycle_params); break;
+    case MPPI_SYS_QUADROTOR: want = sizeof(mppi_quadrotor_params); break;
+    case MPPI_SYS_QUADROTOR_MLP: want = sizeof(mppi_quadrotor_mlp_params); break;
+  }
+  if (c->params_bytes != want) return fail(MPPI_EINVAL, "params_bytes %llu != %zu for system %d",
+                                           (unsigned long long)c->params_bytes, want, c->system);
+  if (c->system == MPPI_SYS_LINEAR) {
+    const auto *p = (const mppi_linear_params *)c->params;
+    if (!p->A || !p->B || !p->Q || !p->Qf) return fail(MPPI_EINVAL, "linear params: NULL matrix");
+  } else if (c->system == MPPI_SYS_BICYCLE) {
+    const auto *p = (const mppi_bicycle_params *)c->params;
+    if (!p->map || p->map_w < 2 || p->map_h < 2 || p->map_w > 16384 || p->map_h > 16384)
+      return fail(MPPI_EINVAL, "bicycle params: need a map of at least 2 x 2 cells (at most 16384 per side)");
+    if (!(p->cell_size > 0) || !(p->wheelbase > 0)) return fail(MPPI_EINVAL, "bicycle params: cell_size and wheelbase must be > 0");
+  } else if (c->system == MPPI_SYS_QUADROTOR || c->system == MPPI_SYS_QUADROTOR_MLP) {
+    const mppi_quadrotor_params *p = c->system == MPPI_SYS_QUADROTOR
+                                         ? (const mppi_quadrotor_params *)c->params
+                                         : &((const mppi_quadrotor_mlp_params *)c->params)->quad;
+    if (p->n_obstacles < 0 || p->n_obstacles > QuadrotorSys::kMaxObstacles)
+      return fail(MPPI_EINVAL, "quadrotor params: n_obstacles outside [0, %d]", QuadrotorSys::kMaxObstacles);
+    if (p->n_obstacles > 0 && !p->obstacles) return fail(MPPI_EINVAL, "quadrotor params: obstacles is NULL");
+    if (!(p->mass > 0) || !(p->inertia[0] > 0) || !(p->inertia[1] > 0) || !(p->inertia[2] > 0))
+      return fail(MPPI_EINVAL, "quadrotor params: mass and inertia must be > 0");
+    if (c->system == MPPI_SYS_QUADROTOR_MLP && !((const mppi_quadrotor_mlp_params *)c->params)->mlp)
+      return fail(MPPI_EINVAL, "quadrotor_mlp params: mlp is NULL");
+  }
+  return MPPI_OK;
+}
+
+// ------------------------------------------------------------ workspace layout
+static uint64_t align256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
+
+void compute_layout(const mppi_config *c, Layout *L) {
+  const int K = c->K, T = c->T, m = c->n_ctrl;
+  L->TM = T * m;
+  L->G = (L->TM + 3) / 4;
+  L->n_roll_blocks = (K + kBlock - 1) / kBlock;
+  L->n_kc = (K + kUpdChunk - 1) / kUpdChunk;
+  uint64_t o = 0;
+  auto take = [&](uint64_t bytes) { uint64_t r = o; o = align256(o + bytes); return r; };
+  L->off_x0 = take(16 * sizeof(double));
+  L->off_res = take(8 * sizeof(double));      // u0[4], flags (int[4]) packed after
+  L->off_iter = take(sizeof(uint64_t));
+  L->off_U64 = take((uint64_t)L->TM * 8);
+  L->off_U32 = take((uint64_t)L->TM * 4);
+  L->off_S = take((uint64_t)K * 8);
+  L->off_blk_min = take((uint64_t)L->n_roll_blocks * 8);
+  L->off_eta_part = take((uint64_t)L->n_kc * 8);
+  L->off_part = take((uint64_t)L->n_kc * L->G * 4 * 8);
+  L->off_dbg = take((uint64_t)(2 + L->TM) * 8);
+  uint64_t sys_bytes = 0;
+  if (c->system == MPPI_SYS_BICYCLE) {
+    const auto *p = (const mppi_bicycle_params *)c->params;
+    sys_bytes = (uint64_t)p->map_w * p->map_h * 4;
+  } else if (c->system == MPPI_SYS_QUADROTOR || c->system == MPPI_SYS_QUADROTOR_MLP) {
+    const mppi_quadrotor_params *p = c->system == MPPI_SYS_QUADROTOR
+                                         ? (const mppi_quadrotor_params *)c->params
+                                         : &((const mppi_quadrotor_mlp_params *)c->params)->quad;
+    sys_bytes = (uint64_t)(p->n_obstacles > 0 ? p->n_obstacles : 1) * 16;
+  }
+  L->off_sys = take(sys_bytes > 0 ? sys_bytes : 16);
+  L->off_extra = o;
+  L->extra_bytes = extra_workspace_bytes(c);
+  L->total = align256(o + L->extra_bytes);
+}
+
+}  // namespace mppi
+
+// ---------------------------------------------------------------------- context
+
+extern "C" int mppi_workspace_bytes(const mppi_config *cfg, uint64_t *bytes) {
+  int rc = validate_config(cfg);
+  if (rc) return rc;
+  if (!bytes) return fail(MPPI_EINVAL, "bytes is NULL");
+  Layout L;
+  compute_layout(cfg, &L);
+  *bytes = L.total;
+  return MPPI_OK;
+}
+
+namespace mppi {
+
+// Fill the per-system device parameter blocks from the host description.
+static int build_params(mppi_ctx *c) {
+  const mppi_config &cfg = c->cfg;
+  switch (cfg.system) {
+    case MPPI_SYS_LINEAR: {
+      const auto *p = (const mppi_linear_params *)cfg.params;
+      const int n = cfg.n_state, m = cfg.n_ctrl;
+      LinearParams lp;
+      std::memset(&lp, 0, sizeof(lp));
+      lp.n = n;
+      for (int r = 0; r < n; ++r) {
+        for (int k = 0; k < n; ++k) {
+          lp.A[r * 4 + k] = (float)p->A[r * n + k];
+          lp.Ad[r * 4 + k] = p->A[r * n + k];
+          lp.Q[r * 4 + k] = (float)p->Q[r * n + k];
+          lp.Qf[r * 4 + k] = (float)p->Qf[r * n + k];
+        }
+        for (int k = 0; k < m; ++k) {
+          lp.B[r * m + k] = (float)p->B[r * m + k];
+          lp.Bd[r * m + k] = p->B[r * m + k];
+        }
+      }
+      c->linear = lp;
+      break;
+    }
+    case MPPI_SYS_CARTPOLE: {
+      const auto *p = (const mppi_cartpole_params *)cfg.params;
+      CartPoleSys::Params cp;
+      cp.mc = (float)p->mass_cart; cp.mp = (float)p->mass_pole; cp.l = (float)p->half_length; cp.g = (float)p->gravity;
+      cp.dmc = p->mass_cart; cp.dmp = p->mass_pole; cp.dl = p->half_length; cp.dg = p->gravity;
+      for (int i = 0; i < 4; ++i) { cp.qd[i] = (float)p->q_diag[i]; cp.qfd[i] = (float)p->qf_diag[i]; }
+      c->cartpole = cp;
+      break;
+    }
+    case MPPI_SYS_BICYCLE: {
+      const auto *p = (const mppi_bicycle_params *)cfg.params;
+      BicycleSys::Params bp;
+      bp.L_inv = (float)(1.0 / p->wheelbase); bp.dL_inv = 1.0 / p->wheelbase;
+      bp.vt = (float)p->v_target; bp.ws = (float)p->w_speed;
+      bp.cell_inv = (float)(1.0 / p->cell_size);
+      bp.lim = (float)p->steer_limit; bp.dlim = p->steer_limit;
+      bp.W = p->map_w; bp.H = p->map_h;
+      bp.map = (const float *)(c->base + c->L.off_sys);
+      HIP_TRY(hipMemcpy((void *)bp.map, p->map, (size_t)p->map_w * p->map_h * 4, hipMemcpyHostToDevice));
+      c->bicycle = bp;
+      break;
+    }
+    case MPPI_SYS_QUADROTOR:
+    case MPPI_SYS_QUADROTOR_MLP: {
+      const mppi_quadrotor_params *p = cfg.system == MPPI_SYS_QUADROTOR
+                                           ? (const mppi_quadrotor_params *)cfg.params
+                                           : &((const mppi_quadrotor_mlp_params *)cfg.params)->quad;
+      QuadrotorSys::Params qp;
+      qp.m_inv = (float)(1.0 / p->mass); qp.dm_inv = 1.0 / p->mass;
+      qp.g = (float)p->gravity; qp.dg = p->gravity;
+      qp.arm = (float)p->arm; qp.darm = p->arm;
+      qp.kap = (float)p->yaw_coef; qp.dkap = p->yaw_coef;
+      for (int i = 0; i < 3; ++i) {
+        qp.J[i] = (float)p->inertia[i]; qp.dJ[i] = p->inertia[i];
+        qp.Jinv[i] = (float)(1.0 / p->inertia[i]); qp.dJinv[i] = 1.0 / p->inertia[i];
+        qp.goal[i] = (float)p->goal[i];
+      }
+      qp.wg = (float)p->w_goal; qp.wo = (float)p->w_obs; qp.margin = (float)p->obs_margin;
+      qp.n_obs = p->n_obstacles;
+      std::vector<float> ob((size_t)(p->n_obstacles > 0 ? p->n_obstacles : 1) * 4, 0.f);
+      for (int j = 0; j < p->n_obstacles; ++j) {
+        const double *o = p->obstacles + 4 * j;
+        const double rr = o[3] + p->obs_margin;
+        ob[4 * j + 0] = (float)o[0]; ob[4 * j + 1] = (float)o[1]; ob[4 * j + 2] = (float)o[2];
+        ob[4 * j + 3] = (float)(rr * rr);
+      }
+      qp.obs = (const float4 *)(c->base + c->L.off_sys);
+      HIP_TRY(hipMemcpy((void *)qp.obs, ob.data(), ob.size() * 4, hipMemcpyHostToDevice));
+      c->quad = qp;
+      break;
+    }
+  }
+  return MPPI_OK;
+}
+
+template <class Sys>
+static size_t rollout_lds_bytes(const mppi_ctx *c) {
+  const int T = c->cfg.T, m = c->cfg.n_ctrl;
+  size_t fl = (size_t)2 * T * m + ((T + 3) & ~3);
+  fl = (fl + 3) & ~size_t(3);
+  int a = 0, b = 0;
+  if (c->cfg.system == MPPI_SYS_BICYCLE) { a = c->bicycle.W; b = c->bicycle.H; }
+  if (c->cfg.system == MPPI_SYS_QUADROTOR || c->cfg.system == MPPI_SYS_QUADROTOR_MLP) a = c->quad.n_obs;
+  fl += Sys::stage_floats(a, b);
+  return fl * 4;
+}
+
+template <class Sys>
+static int launch_rollout(mppi_ctx *c, const IterArgs &a, const typename Sys::Params &p, hipStream_t s) {
+  const size_t lds = rollout_lds_bytes<Sys>(c);
+  hipLaunchKernelGGL(rollout_kernel<Sys>, dim3(c->L.n_roll_blocks), dim3(kBlock), lds, s, a, p);
+  return MPPI_OK;
+}
+
+template <class Sys>
+static int prepare_rollout(mppi_ctx *c) {
+  const size_t lds = rollout_lds_bytes<Sys>(c);
+  if (lds > 160 * 1024 - 64) return fail(MPPI_EINVAL, "rollout needs %zu B of LDS (T too large)", lds);
+  HIP_TRY(hipFuncSetAttribute((const void *)rollout_kernel<Sys>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  return MPPI_OK;
+}
+
+static IterArgs make_iter_args(mppi_ctx *c, const double *x0) {
+  IterArgs a;
+  std::memset(&a, 0, sizeof(a));
+  const Layout &L = c->L;
+  a.x0 = x0;
+  a.U32 = (const float *)(c->base + L.off_U32);
+  a.S = (double *)(c->base + L.off_S);
+  a.blk_min = (double *)(c->base + L.off_blk_min);
+  a.iter = (const uint64_t *)(c->base + L.off_iter);
+  a.part = (double *)(c->base + L.off_part);
+  a.eta_part = (double *)(c->base + L.off_eta_part);
+  a.key0 = (uint32_t)c->cfg.seed;
+  a.key1 = (uint32_t)(c->cfg.seed >> 32);
+  a.n = c->cfg.n_state;
+  a.K = c->cfg.K; a.T = c->cfg.T; a.m = c->cfg.n_ctrl; a.G = L.G;
+  a.n_roll_blocks = L.n_roll_blocks; a.n_kc = L.n_kc;
+  a.dt = (float)c->cfg.dt;
+  a.lr_quad = (float)(0.5 * (1.0 - 1.0 / c->cfg.nu));
+  const int m = c->cfg.n_ctrl;
+  for (int i = 0; i < m * m; ++i) { a.Ls[i] = (float)c->Ls[i]; a.R[i] = (float)c->R[i]; }
+  a.inv_lambda = 1.0 / c->cfg.lambda;
+  return a;
+}
+
+static FinalizeArgs make_fin_args(mppi_ctx *c, double *u0_out, int emit) {
+  FinalizeArgs f;
+  std::memset(&f, 0, sizeof(f));
+  const Layout &L = c->L;
+  f.U64 = (double *)(c->base + L.off_U64);
+  f.U32 = (float *)(c->base + L.off_U32);
+  f.blk_min = (const double *)(c->base + L.off_blk_min);
+  f.part = (const double *)(c->base + L.off_part);
+  f.eta_part = (const double *)(c->base + L.off_eta_part);
+  f.iter = (uint64_t *)(c->base + L.off_iter);
+  f.flags = (int *)(c->base + L.off_res + 4 * sizeof(double));
+  f.dbg = (double *)(c->base + L.off_dbg);
+  f.u0_out = u0_out;
+  f.T = c->cfg.T; f.m = c->cfg.n_ctrl; f.G = L.G; f.n_roll_blocks = L.n_roll_blocks; f.n_kc = L.n_kc;
+  f.emit = emit;
+  for (int i = 0; i < 16; ++i) f.Ls[i] = c->Ls[i];
+  for (int j = 0; j < c->cfg.n_ctrl; ++j) f.u_init[j] = c->u_init[j];
+  return f;
+}
+
+static hipEvent_t take_event(mppi_ctx *c) {
+  if (!c->event_pool.empty()) {
+    hipEvent_t e = c->event_pool.back();
+    c->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Record the start event of a timed kernel (profiling mode only).
+static hipEvent_t prof_begin(mppi_ctx *c, hipStream_t s) {
+  if (!c->profiling) return nullptr;
+  hipEvent_t e = take_event(c);
+  if (e) (void)hipEventRecord(e, s);
+  return e;
+}
+
+static void prof_end(mppi_ctx *c, hipStream_t s, int kind, hipEvent_t start) {
+  if (!c->profiling || !start) return;
+  hipEvent_t e = take_event(c);
+  if (!e) return;
+  (void)hipEventRecord(e, s);
+  c->pending.push_back({kind, start, e});
+}
+
+// Enqueue n_iters iterations (+ emit/shift) on stream s.
+int enqueue_iterations(mppi_ctx *c, const double *x0_dev, int n_iters, double *u0_dev, hipStream_t s) {
+  const IterArgs a = make_iter_args(c, x0_dev);
+  for (int it = 0; it < n_iters; ++it) {
+    int rc = MPPI_OK;
+    hipEvent_t t0 = prof_begin(c, s);
+    switch (c->cfg.system) {
+      case MPPI_SYS_LINEAR:
+        if (c->cfg.n_ctrl == 1) rc = launch_rollout<LinearSys<1>>(c, a, c->linear_as<1>(), s);
+        else if (c->cfg.n_ctrl == 2) rc = launch_rollout<LinearSys<2>>(c, a, c->linear_as<2>(), s);
+        else rc = launch_rollout<LinearSys<4>>(c, a, c->linear_as<4>(), s);
+        break;
+      case MPPI_SYS_CARTPOLE: rc = launch_rollout<CartPoleSys>(c, a, c->cartpole, s); break;
+      case MPPI_SYS_BICYCLE: rc = launch_rollout<BicycleSys>(c, a, c->bicycle, s); break;
+      case MPPI_SYS_QUADROTOR: rc = launch_rollout<QuadrotorSys>(c, a, c->quad, s); break;
+      case MPPI_SYS_QUADROTOR_MLP: rc = launch_mlp_rollout(c, a, s); break;
+    }
+    if (rc) return rc;
+    prof_end(c, s, 0, t0);
+    t0 = prof_begin(c, s);
+    hipLaunchKernelGGL(update_kernel, dim3(c->L.n_kc, (c->L.G + kUpdGroups - 1) / kUpdGroups), dim3(kBlock), 0, s, a);
+    prof_end(c, s, 1, t0);
+    const FinalizeArgs f = make_fin_args(c, u0_dev, it == n_iters - 1);
+    t0 = prof_begin(c, s);
+    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kFinBlock), 0, s, f);
+    prof_end(c, s, 2, t0);
+  }
+  HIP_TRY(hipGetLastError());
+  return MPPI_OK;
+}
+
+// Run n_iters iterations, through a cached hipGraph when enabled.
+static int run_iterations(mppi_ctx *c, const double *x0_dev, int n_iters, double *u0_dev) {
+  if (!c->cfg.use_graph || c->profiling) return enqueue_iterations(c, x0_dev, n_iters, u0_dev, c->stream);
+  auto key = std::make_tuple(n_iters, (const void *)x0_dev, (const void *)u0_dev);
+  auto itg = c->graphs.find(key);
+  if (itg == c->graphs.end()) {
+    hipGraph_t g;
+    hipGraphExec_t ge;
+    HIP_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    int rc = enqueue_iterations(c, x0_dev, n_iters, u0_dev, c->cap_stream);
+    hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+    if (rc) return rc;
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+    itg = c->graphs.emplace(key, ge).first;
+  }
+  HIP_TRY(hipGraphLaunch(itg->second, c->stream));
+  return MPPI_OK;
+}
+
+static int set_device(int dev) {
+  int n = 0;
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess || n == 0) return fail(MPPI_EDEVICE, "no HIP device available");
+  if (dev < 0 || dev >= n) return fail(MPPI_EINVAL, "device %d outside [0, %d)", dev, n);
+  HIP_TRY(hipSetDevice(dev));
+  return MPPI_OK;
+}
+
+}  // namespace mppi
+
+extern "C" int mppi_create(const mppi_config *cfg, mppi_ctx **out) {
+  if (!out) return fail(MPPI_EINVAL, "out is NULL");
+  *out = nullptr;
+  int rc = validate_config(cfg);
+  if (rc) return rc;
+  rc = set_device(cfg->device);
+  if (rc) return rc;
+  auto *c = new mppi_ctx();
+  c->cfg = *cfg;
+  const int m = cfg->n_ctrl, T = cfg->T;
+  cholesky(cfg->sigma, m, c->L64);
+  const double sq = std::sqrt(cfg->nu);
+  for (int i = 0; i < 16; ++i) c->Ls[i] = 0.0;
+  for (int i = 0; i < m * m; ++i) c->Ls[i] = sq * c->L64[i];
+  if (cfg->R) {
+    for (int i = 0; i < m * m; ++i) c->R[i] = cfg->R[i];
+  } else {
+    double Si[16];
+    invert(cfg->sigma, m, Si);
+    for (int i = 0; i < m * m; ++i) c->R[i] = cfg->lambda * Si[i];
+  }
+  for (int j = 0; j < m; ++j) c->u_init[j] = cfg->u_init[j];
+  c->cfg.sigma = c->cfg.R = c->cfg.u_init = c->cfg.u_nominal0 = nullptr;  // not kept
+  compute_layout(cfg, &c->L);
+  // device memory
+  if (cfg->workspace) {
+    if (cfg->workspace_bytes < c->L.total) {
+      delete c;
+      return fail(MPPI_ENOMEM, "workspace of %llu B < %llu B needed", (unsigned long long)cfg->workspace_bytes,
+                  (unsigned long long)c->L.total);
+    }
+    if (((uintptr_t)cfg->workspace & 255) != 0) {
+      delete c;
+      return fail(MPPI_EINVAL, "workspace must be 256-byte aligned");
+    }
+    c->base = (char *)cfg->workspace;
+    c->owns_ws = false;
+  } else {
+    hipError_t e = hipMalloc((void **)&c->base, c->L.total);
+    if (e != hipSuccess) { delete c; return fail(MPPI_ENOMEM, "hipMalloc(%llu): %s", (unsigned long long)c->L.total, hipGetErrorString(e)); }
+    c->owns_ws = true;
+  }
+  if (cfg->stream) {
+    c->stream = (hipStream_t)cfg->stream;
+    c->owns_stream = false;
+  } else {
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) { mppi_destroy(c); return fail(MPPI_EDEVICE, "stream create failed"); }
+    c->owns_stream = true;
+  }
+  if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) { mppi_destroy(c); return fail(MPPI_EDEVICE, "stream create failed"); }
+  if (hipHostMalloc((void **)&c->pinned, 4096, hipHostMallocDefault) != hipSuccess) { mppi_destroy(c); return fail(MPPI_ENOMEM, "hipHostMalloc failed"); }
+  rc = build_params(c);
+  if (!rc) rc = init_extra(c, cfg);
+  if (!rc) {
+    switch (cfg->system) {
+      case MPPI_SYS_LINEAR:
+        rc = m == 1 ? prepare_rollout<LinearSys<1>>(c) : (m == 2 ? prepare_rollout<LinearSys<2>>(c) : prepare_rollout<LinearSys<4>>(c));
+        break;
+      case MPPI_SYS_CARTPOLE: rc = prepare_rollout<CartPoleSys>(c); break;
+      case MPPI_SYS_BICYCLE: rc = prepare_rollout<BicycleSys>(c); break;
+      case MPPI_SYS_QUADROTOR: rc = prepare_rollout<QuadrotorSys>(c); break;
+      default: break;
+    }
+  }
+  if (rc) { std::string msg = g_last_error; mppi_destroy(c); g_last_error = msg; return rc; }
+  // initial state: U (FP64 + FP32), iteration 0, zero flags
+  std::vector<double> U((size_t)T * m);
+  for (int i = 0; i < T; ++i)
+    for (int j = 0; j < m; ++j) U[(size_t)i * m + j] = cfg->u_nominal0 ? cfg->u_nominal0[(size_t)i * m + j] : cfg->u_init[j];
+  std::vector<float> U32(U.begin(), U.end());
+  std::vector<char> zeros(c->L.off_U64, 0);
+  hipError_t e = hipMemcpy(c->base, zeros.data(), zeros.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(c->base + c->L.off_U64, U.data(), U.size() * 8, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(c->base + c->L.off_U32, U32.data(), U32.size() * 4, hipMemcpyHostToDevice);
+  if (e != hipSuccess) { mppi_destroy(c); return hip_fail(e, "initial upload"); }
+  *out = c;
+  return MPPI_OK;
+}
+
+extern "C" int mppi_destroy(mppi_ctx *c) {
+  if (!c) return MPPI_OK;
+  (void)hipSetDevice(c->cfg.device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  for (auto &kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+  for (auto &t : c->pending) { (void)hipEventDestroy(t.a); (void)hipEventDestroy(t.b); }
+  for (auto e : c->event_pool) (void)hipEventDestroy(e);
+  destroy_extra(c);
+  if (c->pinned) (void)hipHostFree(c->pinned);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  if (c->owns_stream && c->stream) (void)hipStreamDestroy(c->stream);
+  if (c->owns_ws && c->base) (void)hipFree(c->base);
+  delete c;
+  return MPPI_OK;
+}
+
+static int check_ctx(mppi_ctx *c) {
+  if (!c) return fail(MPPI_EINVAL, "ctx is NULL");
+  HIP_TRY(hipSetDevice(c->cfg.device));
+  return MPPI_OK;
+}
+
+static int collect_flags(mppi_ctx *c, int count) {
+  if (count != c->seen_numeric) {
+    c->seen_numeric = count;
+    return fail(MPPI_ENUMERIC, "an iteration had no sample with a finite path cost; U was left unchanged");
+  }
+  return MPPI_OK;
+}
+
+extern "C" int mppi_step(mppi_ctx *c, const double *x0, int32_t n_iters, double *u0) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (!x0 || !u0) return fail(MPPI_EINVAL, "x0 and u0 must be non-NULL");
+  if (n_iters < 1 || n_iters > 1000) return fail(MPPI_EINVAL, "n_iters=%d outside [1, 1000]", n_iters);
+  if (!finite_all(x0, c->cfg.n_state)) return fail(MPPI_EINVAL, "x0 has non-finite entries");
+  double *px = (double *)c->pinned;
+  const int n = c->cfg.n_state, m = c->cfg.n_ctrl;
+  std::memcpy(px, x0, n * sizeof(double));
+  double *d_x0 = (double *)(c->base + c->L.off_x0);
+  double *d_res = (double *)(c->base + c->L.off_res);
+  HIP_TRY(hipMemcpyAsync(d_x0, px, n * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  rc = run_iterations(c, d_x0, n_iters, d_res);
+  if (rc) return rc;
+  char *pres = c->pinned + 1024;
+  HIP_TRY(hipMemcpyAsync(pres, d_res, 8 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  std::memcpy(u0, pres, m * sizeof(double));
+  int count;
+  std::memcpy(&count, pres + 4 * sizeof(double), sizeof(int));
+  return collect_flags(c, count);
+}
+
+extern "C" int mppi_step_async(mppi_ctx *c, const double *x0_dev, int32_t n_iters, double *u0_dev) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (!x0_dev || !u0_dev) return fail(MPPI_EINVAL, "x0_dev and u0_dev must be non-NULL");
+  if (n_iters < 1 || n_iters > 1000) return fail(MPPI_EINVAL, "n_iters=%d outside [1, 1000]", n_iters);
+  return run_iterations(c, x0_dev, n_iters, u0_dev);
+}
+
+extern "C" int mppi_sync(mppi_ctx *c) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  char *pres = c->pinned + 2048;
+  HIP_TRY(hipMemcpyAsync(pres, c->base + c->L.off_res + 4 * sizeof(double), sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  int count;
+  std::memcpy(&count, pres, sizeof(int));
+  return collect_flags(c, count);
+}
+
+extern "C" int mppi_plant_step_async(mppi_ctx *c, double *x_dev, const double *u_dev) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (!x_dev || !u_dev) return fail(MPPI_EINVAL, "x_dev and u_dev must be non-NULL");
+  const double dt = c->cfg.dt;
+  switch (c->cfg.system) {
+    case MPPI_SYS_LINEAR:
+      if (c->cfg.n_ctrl == 1) hipLaunchKernelGGL(plant_kernel<LinearSys<1>>, dim3(1), dim3(64), 0, c->stream, x_dev, u_dev, dt, c->cfg.n_state, c->linear_as<1>());
+      else if (c->cfg.n_ctrl == 2) hipLaunchKernelGGL(plant_kernel<LinearSys<2>>, dim3(1), dim3(64), 0, c->stream, x_dev, u_dev, dt, c->cfg.n_state, c->linear_as<2>());
+      else hipLaunchKernelGGL(plant_kernel<LinearSys<4>>, dim3(1), dim3(64), 0, c->stream, x_dev, u_dev, dt, c->cfg.n_state, c->linear_as<4>());
+      break;
+    case MPPI_SYS_CARTPOLE: hipLaunchKernelGGL(plant_kernel<CartPoleSys>, dim3(1), dim3(64), 0, c->stream, x_dev, u_dev, dt, c->cfg.n_state, c->cartpole); break;
+    case MPPI_SYS_BICYCLE: hipLaunchKernelGGL(plant_kernel<BicycleSys>, dim3(1), dim3(64), 0, c->stream, x_dev, u_dev, dt, c->cfg.n_state, c->bicycle); break;
+    case MPPI_SYS_QUADROTOR:
+    case MPPI_SYS_QUADROTOR_MLP:
+      hipLaunchKernelGGL(plant_kernel<QuadrotorSys>, dim3(1), dim3(64), 0, c->stream, x_dev, u_dev, dt, c->cfg.n_state, c->quad); break;
+  }
+  HIP_TRY(hipGetLastError());
+  return MPPI_OK;
+}
+
+extern "C" int mppi_get_controls(mppi_ctx *c, double *u, uint64_t len) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (!u || len != (uint64_t)c->L.TM) return fail(MPPI_EINVAL, "u must hold T*n_ctrl = %d doubles", c->L.TM);
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  HIP_TRY(hipMemcpy(u, c->base + c->L.off_U64, (size_t)c->L.TM * 8, hipMemcpyDeviceToHost));
+  return MPPI_OK;
+}
+
+extern "C" int mppi_set_controls(mppi_ctx *c, const double *u, uint64_t len) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (!u || len != (uint64_t)c->L.TM) return fail(MPPI_EINVAL, "u must hold T*n_ctrl = %d doubles", c->L.TM);
+  if (!finite_all(u, c->L.TM)) return fail(MPPI_EINVAL, "u has non-finite entries");
+  std::vector<float> f(u, u + c->L.TM);
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  HIP_TRY(hipMemcpy(c->base + c->L.off_U64, u, (size_t)c->L.TM * 8, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(c->base + c->L.off_U32, f.data(), (size_t)c->L.TM * 4, hipMemcpyHostToDevice));
+  return MPPI_OK;
+}
+
+// State blob: magic, T*m, iteration, U64[T*m].
+extern "C" int mppi_get_state(mppi_ctx *c, void *buf, uint64_t len, uint64_t *needed) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  const uint64_t need = 3 * 8 + (uint64_t)c->L.TM * 8;
+  if (needed) *needed = need;
+  if (!buf) return MPPI_OK;
+  if (len < need) return fail(MPPI_EINVAL, "state buffer of %llu B < %llu B", (unsigned long long)len, (unsigned long long)need);
+  uint64_t *h = (uint64_t *)buf;
+  h[0] = 0x4d50504953544131ull;  // "MPPISTA1"
+  h[1] = (uint64_t)c->L.TM;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  HIP_TRY(hipMemcpy(&h[2], c->base + c->L.off_iter, 8, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(&h[3], c->base + c->L.off_U64, (size_t)c->L.TM * 8, hipMemcpyDeviceToHost));
+  return MPPI_OK;
+}
+
+extern "C" int mppi_set_state(mppi_ctx *c, const void *buf, uint64_t len) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  const uint64_t need = 3 * 8 + (uint64_t)c->L.TM * 8;
+  if (!buf || len < need) return fail(MPPI_EINVAL, "state buffer too small");
+  const uint64_t *h = (const uint64_t *)buf;
+  if (h[0] != 0x4d50504953544131ull || h[1] != (uint64_t)c->L.TM) return fail(MPPI_EINVAL, "state blob does not match this context");
+  rc = mppi_set_controls(c, (const double *)&h[3], (uint64_t)c->L.TM);
+  if (rc) return rc;
+  HIP_TRY(hipMemcpy(c->base + c->L.off_iter, &h[2], 8, hipMemcpyHostToDevice));
+  return MPPI_OK;
+}
+
+extern "C" int mppi_get_iteration(mppi_ctx *c, uint64_t *iteration) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (!iteration) return fail(MPPI_EINVAL, "iteration is NULL");
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  HIP_TRY(hipMemcpy(iteration, c->base + c->L.off_iter, 8, hipMemcpyDeviceToHost));
+  return MPPI_OK;
+}
+
+extern "C" int mppi_debug_last(mppi_ctx *c, double *costs, double *rho, double *eta, double *dU) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  if (costs) HIP_TRY(hipMemcpy(costs, c->base + c->L.off_S, (size_t)c->cfg.K * 8, hipMemcpyDeviceToHost));
+  double head[2];
+  HIP_TRY(hipMemcpy(head, c->base + c->L.off_dbg, 16, hipMemcpyDeviceToHost));
+  if (rho) *rho = head[0];
+  if (eta) *eta = head[1];
+  if (dU) HIP_TRY(hipMemcpy(dU, c->base + c->L.off_dbg + 16, (size_t)c->L.TM * 8, hipMemcpyDeviceToHost));
+  return MPPI_OK;
+}
+
+extern "C" int mppi_debug_normals(mppi_ctx *c, uint64_t iteration, int32_t k0, int32_t nk, float *eps) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (!eps || k0 < 0 || nk < 1 || nk > (1 << 20)) return fail(MPPI_EINVAL, "bad k0/nk/eps");
+  const int TM = c->L.TM, G = c->L.G;
+  float *d = nullptr;
+  HIP_TRY(hipMalloc((void **)&d, (size_t)nk * TM * 4));
+  const int total = nk * G;
+  hipLaunchKernelGGL(normals_kernel, dim3((total + 255) / 256), dim3(256), 0, c->stream, d, iteration,
+                     (uint32_t)c->cfg.seed, (uint32_t)(c->cfg.seed >> 32), k0, nk, TM);
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (e == hipSuccess) e = hipMemcpy(eps, d, (size_t)nk * TM * 4, hipMemcpyDeviceToHost);
+  (void)hipFree(d);
+  if (e != hipSuccess) return hip_fail(e, "debug_normals");
+  return MPPI_OK;
+}
+
+extern "C" int mppi_debug_philox(int32_t device, uint64_t seed, const uint32_t *counters, int32_t n, uint32_t *out) {
+  if (!counters || !out || n < 1 || n > (1 << 24)) return fail(MPPI_EINVAL, "bad counters/out/n");
+  int rc = set_device(device);
+  if (rc) return rc;
+  uint4 *dc = nullptr, *dout = nullptr;
+  HIP_TRY(hipMalloc((void **)&dc, (size_t)n * 16));
+  hipError_t e = hipMalloc((void **)&dout, (size_t)n * 16);
+  if (e == hipSuccess) e = hipMemcpy(dc, counters, (size_t)n * 16, hipMemcpyHostToDevice);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(philox_kernel, dim3((n + 255) / 256), dim3(256), 0, 0, dc, dout, n, (uint32_t)seed, (uint32_t)(seed >> 32));
+    e = hipDeviceSynchronize();
+  }
+  if (e == hipSuccess) e = hipMemcpy(out, dout, (size_t)n * 16, hipMemcpyDeviceToHost);
+  (void)hipFree(dc);
+  if (dout) (void)hipFree(dout);
+  if (e != hipSuccess) return hip_fail(e, "debug_philox");
+  return MPPI_OK;
+}
+
+extern "C" int mppi_set_profiling(mppi_ctx *c, int32_t on) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  for (auto &t : c->pending) { c->event_pool.push_back(t.a); c->event_pool.push_back(t.b); }
+  c->pending.clear();
+  c->profiling = on != 0;
+  for (int k = 0; k < 3; ++k) { c->prof_ms[k] = 0.0; c->prof_n[k] = 0; }
+  return MPPI_OK;
+}
+
+extern "C" int mppi_kernel_times(mppi_ctx *c, double *avg_ms, int64_t *count) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (!avg_ms || !count) return fail(MPPI_EINVAL, "avg_ms and count must be non-NULL");
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  for (auto &t : c->pending) {
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, t.a, t.b));
+    c->prof_ms[t.kind] += ms;
+    c->prof_n[t.kind] += 1;
+    c->event_pool.push_back(t.a);
+    c->event_pool.push_back(t.b);
+  }
+  c->pending.clear();
+  for (int k = 0; k < 3; ++k) {
+    count[k] = c->prof_n[k];
+    avg_ms[k] = c->prof_n[k] ? c->prof_ms[k] / (double)c->prof_n[k] : 0.0;
+  }
+  return MPPI_OK;
+}

@@ -1,0 +1,112 @@
+// Device helpers shared by every kernel of libmppi: the counter-based noise source,
+// fast FP32 transcendentals and wave64 reductions.  gfx950 only.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mppi {
+
+constexpr int kBlock = 256;       // threads per block in every kernel (4 wave64s)
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11, Section 4).  Ten rounds; each
+// round forms the two 32x32->64 products of counter words 0 and 2 with the round
+// multipliers, XORs their high halves into the other two words together with the
+// key, and permutes; the key advances by the two Weyl increments between rounds.
+// Integer work only: v_mul_lo_u32 / v_mul_hi_u32 / v_xor on the VALU.
+// ---------------------------------------------------------------------------------
+constexpr uint32_t kPhiloxM0 = 0xD2511F53u;
+constexpr uint32_t kPhiloxM1 = 0xCD9E8D57u;
+constexpr uint32_t kPhiloxW0 = 0x9E3779B9u;
+constexpr uint32_t kPhiloxW1 = 0xBB67AE85u;
+
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t lo0 = c.x * kPhiloxM0;
+    const uint32_t hi0 = __umulhi(c.x, kPhiloxM0);
+    const uint32_t lo1 = c.z * kPhiloxM1;
+    const uint32_t hi1 = __umulhi(c.z, kPhiloxM1);
+    c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+    k0 += kPhiloxW0;
+    k1 += kPhiloxW1;
+  }
+  return c;
+}
+
+// Uniform in (0, 1]: the top 24 bits plus one, times 2^-24 -- exact in FP32.
+__device__ __forceinline__ float uniform01(uint32_t x) {
+  return (float)((x >> 8) + 1u) * 0x1p-24f;
+}
+
+// Box-Muller (1958) on one pair: r = sqrt(-2 ln ua), angle 2 pi ub.  v_log_f32 is log2,
+// v_sin_f32 / v_cos_f32 take the angle in revolutions, so no range reduction is needed.
+__device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, float &e0, float &e1) {
+  const float ua = uniform01(a);
+  const float ub = uniform01(b);
+  const float r = __builtin_amdgcn_sqrtf(-1.38629436111989061883f * __builtin_amdgcn_logf(ua));
+  e0 = r * __builtin_amdgcn_cosf(ub);
+  e1 = r * __builtin_amdgcn_sinf(ub);
+}
+
+// Four standard normals with flat indices 4g .. 4g+3 of sample k at iteration `it`
+// (flat index of control j at step i is i*m + j).
+__device__ __forceinline__ void normals4(uint32_t g, uint32_t k, uint64_t it, uint32_t key0, uint32_t key1,
+                                         float e[4]) {
+  const uint4 r = philox4x32_10(make_uint4(g, k, (uint32_t)it, (uint32_t)(it >> 32)), key0, key1);
+  box_muller(r.x, r.y, e[0], e[1]);
+  box_muller(r.z, r.w, e[2], e[3]);
+}
+
+// ---------------------------------------------------------------------------------
+// FP32 trigonometry for the dynamics: reduce to revolutions in [-1/2, 1/2] and use the
+// hardware sin/cos.  Absolute error ~1e-6 for moderate arguments.
+// ---------------------------------------------------------------------------------
+__device__ __forceinline__ float rev(float x) {
+  const float r = x * 0.159154943091895335769f;
+  return r - __builtin_rintf(r);
+}
+__device__ __forceinline__ float fsin(float x) { return __builtin_amdgcn_sinf(rev(x)); }
+__device__ __forceinline__ float fcos(float x) { return __builtin_amdgcn_cosf(rev(x)); }
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+__device__ __forceinline__ double fsin(double x) { return sin(x); }
+__device__ __forceinline__ double fcos(double x) { return cos(x); }
+__device__ __forceinline__ double frcp(double x) { return 1.0 / x; }
+
+// ---------------------------------------------------------------------------------
+// Wave64 / block reductions (fixed order: results do not depend on timing).
+// ---------------------------------------------------------------------------------
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, kWave));
+  return v;
+}
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+// Min over a 256-thread block; every thread gets the result.
+__device__ __forceinline__ double block_min(double v, double *scratch4) {
+  v = wave_min(v);
+  const int w = threadIdx.x / kWave;
+  __syncthreads();
+  if ((threadIdx.x & (kWave - 1)) == 0) scratch4[w] = v;
+  __syncthreads();
+  return fmin(fmin(scratch4[0], scratch4[1]), fmin(scratch4[2], scratch4[3]));
+}
+
+// Sum over a 256-thread block in a fixed tree order; every thread gets the result.
+__device__ __forceinline__ double block_sum(double v, double *scratch4) {
+  v = wave_sum(v);
+  const int w = threadIdx.x / kWave;
+  __syncthreads();
+  if ((threadIdx.x & (kWave - 1)) == 0) scratch4[w] = v;
+  __syncthreads();
+  return (scratch4[0] + scratch4[1]) + (scratch4[2] + scratch4[3]);
+}
+
+}  // namespace mppi

@@ -1,0 +1,69 @@
+// Host-side context of libmppi (internal; the public contract is include/mppi.h).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/mppi.h"
+#include "mppi_kernels.h"
+
+namespace mppi {
+
+// Offsets (bytes) of every device buffer inside one workspace allocation.
+struct Layout {
+  int TM, G, n_roll_blocks, n_kc;
+  uint64_t off_x0, off_res, off_iter, off_U64, off_U32, off_S, off_blk_min, off_eta_part, off_part, off_dbg,
+      off_sys, off_extra, extra_bytes, total;
+};
+
+struct MlpState;  // learned-dynamics extension (mppi_mlp.hip)
+
+}  // namespace mppi
+
+struct mppi_ctx {
+  mppi_config cfg;                 // copy; its host pointers are cleared after create
+  mppi::Layout L;
+  char *base = nullptr;            // device workspace
+  bool owns_ws = false;
+  hipStream_t stream = nullptr;
+  bool owns_stream = false;
+  hipStream_t cap_stream = nullptr;
+  char *pinned = nullptr;          // 4 KiB pinned staging for x0 / results
+  double L64[16] = {0};            // chol(sigma)
+  double Ls[16] = {0};             // sqrt(nu) chol(sigma)
+  double R[16] = {0};
+  double u_init[4] = {0};
+  int seen_numeric = 0;
+  mppi::LinearParams linear;
+  mppi::CartPoleSys::Params cartpole;
+  mppi::BicycleSys::Params bicycle;
+  mppi::QuadrotorSys::Params quad;
+  mppi::MlpState *mlp = nullptr;
+  std::map<std::tuple<int, const void *, const void *>, hipGraphExec_t> graphs;
+  // profiling: pending (kind, start, stop) event triples and accumulated totals
+  bool profiling = false;
+  struct Timed { int kind; hipEvent_t a, b; };
+  std::vector<Timed> pending;
+  std::vector<hipEvent_t> event_pool;
+  double prof_ms[3] = {0, 0, 0};
+  int64_t prof_n[3] = {0, 0, 0};
+  template <int M>
+  const mppi::LinearParams &linear_as() const { return linear; }
+};
+
+namespace mppi {
+int fail(int code, const char *fmt, ...);
+int hip_fail(hipError_t e, const char *what);
+int validate_config(const mppi_config *c);
+void compute_layout(const mppi_config *c, Layout *L);
+int enqueue_iterations(mppi_ctx *c, const double *x0_dev, int n_iters, double *u0_dev, hipStream_t s);
+
+// learned-dynamics hooks (mppi_mlp.hip)
+uint64_t extra_workspace_bytes(const mppi_config *c);
+int init_extra(mppi_ctx *c, const mppi_config *cfg);
+void destroy_extra(mppi_ctx *c);
+int launch_mlp_rollout(mppi_ctx *c, const IterArgs &a, hipStream_t s);
+}  // namespace mppi

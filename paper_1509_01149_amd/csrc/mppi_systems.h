@@ -1,0 +1,220 @@
+// Compiled-in systems: dynamics x' = f(x) + G(x) u and state costs q, phi of the
+// problem statement (Section II of the paper), one struct per system.  Dynamics are
+// templated on the scalar type: FP32 in the rollouts, FP64 in the harness plant.
+// The costs run in FP32 inside the rollout and may read system data staged in LDS.
+#pragma once
+#include "mppi_device.h"
+
+namespace mppi {
+
+// LDS view handed to a system's cost: its staged data (map tile, obstacles).
+struct StageView {
+  const float *lds;      // system region of the block's LDS
+  int i0, j0;            // bicycle: origin cell of the staged map tile
+};
+
+// ------------------------------------------------------------------- linear (tests)
+struct LinearParams {
+  int n;
+  float A[16], B[16], Q[16], Qf[16];   // row-major, leading dimension 4 (B: M)
+  double Ad[16], Bd[16];
+};
+template <int M_>
+struct LinearSys {
+  static constexpr int N = 4, M = M_;
+  using Params = LinearParams;
+  template <typename F>
+  __device__ static void xdot(const Params &p, const F *x, const F *v, F *xd) {
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+      F s = 0;
+#pragma unroll
+      for (int c = 0; c < N; ++c) s += (sizeof(F) == 8 ? (F)p.Ad[r * 4 + c] : (F)p.A[r * 4 + c]) * x[c];
+#pragma unroll
+      for (int c = 0; c < M; ++c) s += (sizeof(F) == 8 ? (F)p.Bd[r * M + c] : (F)p.B[r * M + c]) * v[c];
+      xd[r] = s;
+    }
+  }
+  __device__ static float quad(const float *W, const float *x) {
+    float s = 0.f;
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+      float t = 0.f;
+#pragma unroll
+      for (int c = 0; c < N; ++c) t += W[r * 4 + c] * x[c];
+      s += x[r] * t;
+    }
+    return s;
+  }
+  __device__ static float q(const Params &p, const StageView &, const float *x) { return quad(p.Q, x); }
+  __device__ static float phi(const Params &p, const float *x) { return quad(p.Qf, x); }
+  static constexpr int stage_floats(int, int) { return 0; }
+  __device__ static void stage(const Params &, float *, const double *, int *, int *) {}
+};
+
+// ------------------------------------------------------------------------ cart-pole
+struct CartPoleSys {
+  static constexpr int N = 4, M = 1;
+  struct Params {
+    float mc, mp, l, g, qd[4], qfd[4];
+    double dmc, dmp, dl, dg;
+  };
+  template <typename F>
+  __device__ static void xdot(const Params &p, const F *x, const F *v, F *xd) {
+    const bool d = sizeof(F) == 8;
+    const F mc = d ? (F)p.dmc : (F)p.mc, mp = d ? (F)p.dmp : (F)p.mp;
+    const F l = d ? (F)p.dl : (F)p.l, g = d ? (F)p.dg : (F)p.g;
+    const F Mt = mc + mp;
+    const F iM = frcp(Mt);
+    const F s = fsin(x[2]), c = fcos(x[2]);
+    const F h = (v[0] + mp * l * x[3] * x[3] * s) * iM;
+    const F thdd = (g * s - c * h) * frcp(l * ((F)(4.0 / 3.0) - mp * c * c * iM));
+    xd[0] = x[1];
+    xd[1] = h - mp * l * thdd * c * iM;
+    xd[2] = x[3];
+    xd[3] = thdd;
+  }
+  __device__ static float q(const Params &p, const StageView &, const float *x) {
+    return p.qd[0] * x[0] * x[0] + p.qd[1] * x[1] * x[1] + p.qd[2] * x[2] * x[2] + p.qd[3] * x[3] * x[3];
+  }
+  __device__ static float phi(const Params &p, const float *x) {
+    return p.qfd[0] * x[0] * x[0] + p.qfd[1] * x[1] * x[1] + p.qfd[2] * x[2] * x[2] + p.qfd[3] * x[3] * x[3];
+  }
+  static constexpr int stage_floats(int, int) { return 0; }
+  __device__ static void stage(const Params &, float *, const double *, int *, int *) {}
+};
+
+// ------------------------------------------------------------ kinematic bicycle + map
+// The cost map (FP32, [y][x]) stays in HBM; each block stages the kTile x kTile window
+// around the current start position into LDS (the horizon's reachable region at the
+// configured speeds) and reads the bilinear taps from LDS whenever all four lie inside
+// the window, from global memory (L2) otherwise.  Both paths read identical values.
+struct BicycleSys {
+  static constexpr int N = 5, M = 2;
+  static constexpr int kTile = 160;   // 160 x 160 x 4 B = 100 KiB of LDS
+  struct Params {
+    float L_inv, vt, ws, cell_inv, lim;
+    int W, H;
+    const float *map;                 // device
+    double dL_inv, dlim;
+  };
+  template <typename F>
+  __device__ static void xdot(const Params &p, const F *x, const F *v, F *xd) {
+    const bool d = sizeof(F) == 8;
+    const F lim = d ? (F)p.dlim : (F)p.lim;
+    F dl = x[4];
+    if (lim > 0) dl = dl < -lim ? -lim : (dl > lim ? lim : dl);
+    const F s = fsin(x[2]), c = fcos(x[2]);
+    const F tn = fsin(dl) * frcp(fcos(dl));
+    xd[0] = x[3] * c;
+    xd[1] = x[3] * s;
+    xd[2] = x[3] * tn * (d ? (F)p.dL_inv : (F)p.L_inv);
+    xd[3] = v[0];
+    xd[4] = v[1];
+  }
+  static int tile_w(int W) { return W < kTile ? W : kTile; }
+  static constexpr int stage_floats(int W, int H) { return (W < kTile ? W : kTile) * (H < kTile ? H : kTile); }
+  // Stage the window centred on the start position x0 (device, FP64).
+  __device__ static void stage(const Params &p, float *lds, const double *x0, int *i0, int *j0) {
+    const int tw = p.W < kTile ? p.W : kTile, th = p.H < kTile ? p.H : kTile;
+    int ci = (int)floor(x0[0] * (double)p.cell_inv) - tw / 2;
+    int cj = (int)floor(x0[1] * (double)p.cell_inv) - th / 2;
+    ci = ci < 0 ? 0 : (ci > p.W - tw ? p.W - tw : ci);
+    cj = cj < 0 ? 0 : (cj > p.H - th ? p.H - th : cj);
+    for (int e = threadIdx.x; e < tw * th; e += kBlock) {
+      const int r = e / tw, c = e - r * tw;
+      lds[e] = p.map[(size_t)(cj + r) * p.W + (ci + c)];
+    }
+    *i0 = ci;
+    *j0 = cj;
+  }
+  __device__ static float q(const Params &p, const StageView &sv, const float *x) {
+    float gx = x[0] * p.cell_inv, gy = x[1] * p.cell_inv;
+    gx = fminf(fmaxf(gx, 0.f), (float)(p.W - 1));
+    gy = fminf(fmaxf(gy, 0.f), (float)(p.H - 1));
+    const int i0 = min((int)floorf(gx), p.W - 2);
+    const int j0 = min((int)floorf(gy), p.H - 2);
+    const float fx = gx - (float)i0, fy = gy - (float)j0;
+    const int tw = p.W < kTile ? p.W : kTile, th = p.H < kTile ? p.H : kTile;
+    const int li = i0 - sv.i0, lj = j0 - sv.j0;
+    float m00, m01, m10, m11;
+    if (li >= 0 && lj >= 0 && li + 1 < tw && lj + 1 < th) {
+      const float *t = sv.lds + lj * tw + li;
+      m00 = t[0]; m01 = t[1]; m10 = t[tw]; m11 = t[tw + 1];
+    } else {
+      const float *t = p.map + (size_t)j0 * p.W + i0;
+      m00 = t[0]; m01 = t[1]; m10 = t[p.W]; m11 = t[p.W + 1];
+    }
+    const float top = (1.f - fx) * m00 + fx * m01;
+    const float bot = (1.f - fx) * m10 + fx * m11;
+    const float dv = x[3] - p.vt;
+    return (1.f - fy) * top + fy * bot + p.ws * dv * dv;
+  }
+  __device__ static float phi(const Params &, const float *) { return 0.f; }
+};
+
+// ------------------------------------------------------------------------ quadrotor
+struct QuadrotorSys {
+  static constexpr int N = 12, M = 4;
+  static constexpr int kMaxObstacles = 256;
+  struct Params {
+    float m_inv, g, arm, kap, J[3], Jinv[3], goal[3], wg, wo, margin;
+    int n_obs;
+    const float4 *obs;   // device: (cx, cy, cz, (r + margin)^2)
+    double dm_inv, dg, darm, dkap, dJ[3], dJinv[3];
+  };
+  template <typename F>
+  __device__ static void xdot(const Params &p, const F *x, const F *f, F *xd) {
+    const bool d = sizeof(F) == 8;
+    const F m_inv = d ? (F)p.dm_inv : (F)p.m_inv, g = d ? (F)p.dg : (F)p.g;
+    const F arm = d ? (F)p.darm : (F)p.arm, kap = d ? (F)p.dkap : (F)p.kap;
+    const F J0 = d ? (F)p.dJ[0] : (F)p.J[0], J1 = d ? (F)p.dJ[1] : (F)p.J[1], J2 = d ? (F)p.dJ[2] : (F)p.J[2];
+    const F Ji0 = d ? (F)p.dJinv[0] : (F)p.Jinv[0], Ji1 = d ? (F)p.dJinv[1] : (F)p.Jinv[1],
+            Ji2 = d ? (F)p.dJinv[2] : (F)p.Jinv[2];
+    const F sr = fsin(x[6]), cr = fcos(x[6]);
+    const F sp = fsin(x[7]), cp = fcos(x[7]);
+    const F sy = fsin(x[8]), cy = fcos(x[8]);
+    const F a = (f[0] + f[1] + f[2] + f[3]) * m_inv;
+    xd[0] = x[3];
+    xd[1] = x[4];
+    xd[2] = x[5];
+    // third column of R = Rz(yaw) Ry(pitch) Rx(roll)
+    xd[3] = a * (cy * sp * cr + sy * sr);
+    xd[4] = a * (sy * sp * cr - cy * sr);
+    xd[5] = a * (cp * cr) - g;
+    const F icp = frcp(cp);
+    const F tp = sp * icp;
+    const F wx = x[9], wy = x[10], wz = x[11];
+    xd[6] = wx + sr * tp * wy + cr * tp * wz;
+    xd[7] = cr * wy - sr * wz;
+    xd[8] = (sr * wy + cr * wz) * icp;
+    const F tx = arm * (f[1] - f[3]);
+    const F ty = arm * (f[2] - f[0]);
+    const F tz = kap * (f[0] - f[1] + f[2] - f[3]);
+    // w x (J w)
+    const F hx = J0 * wx, hy = J1 * wy, hz = J2 * wz;
+    xd[9] = (tx - (wy * hz - wz * hy)) * Ji0;
+    xd[10] = (ty - (wz * hx - wx * hz)) * Ji1;
+    xd[11] = (tz - (wx * hy - wy * hx)) * Ji2;
+  }
+  static constexpr int stage_floats(int n_obs, int) { return 4 * n_obs; }
+  __device__ static void stage(const Params &p, float *lds, const double *, int *, int *) {
+    for (int e = threadIdx.x; e < p.n_obs; e += kBlock) reinterpret_cast<float4 *>(lds)[e] = p.obs[e];
+  }
+  __device__ static float q(const Params &p, const StageView &sv, const float *x) {
+    const float dx = x[0] - p.goal[0], dy = x[1] - p.goal[1], dz = x[2] - p.goal[2];
+    float c = p.wg * (dx * dx + dy * dy + dz * dz);
+    const float4 *ob = reinterpret_cast<const float4 *>(sv.lds);
+    float barrier = 0.f;
+    for (int j = 0; j < p.n_obs; ++j) {
+      const float4 o = ob[j];
+      const float ex = x[0] - o.x, ey = x[1] - o.y, ez = x[2] - o.z;
+      const float pen = fmaxf(0.f, o.w - (ex * ex + ey * ey + ez * ez));
+      barrier += pen * pen;
+    }
+    return c + p.wo * barrier;
+  }
+  __device__ static float phi(const Params &, const float *) { return 0.f; }
+};
+
+}  // namespace mppi

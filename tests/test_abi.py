@@ -1,0 +1,125 @@
+"""The C ABI without a GPU: the library loads, exports every function include/mppi.h
+declares, and rejects invalid configurations before touching a device."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import paper_1509_01149_amd as P
+import workloads as W
+from paper_1509_01149_amd import binding as B
+
+ROOT = os.path.abspath(os.path.join(os.path.dirname(__file__), ".."))
+
+
+def declared_functions():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", fn)).read()
+            names |= set(re.findall(r"^\s*(?:int|const char \*|void)\s+\*?(mppi_\w+)\s*\(", text, re.M))
+    return sorted(names)
+
+
+def test_every_declared_symbol_is_exported():
+    names = declared_functions()
+    assert "mppi_create" in names and "mppi_step" in names and "mppi_get_controls" in names
+    lib = P.load()
+    for n in names:
+        assert hasattr(lib, n), n
+    out = subprocess.run(["nm", "-D", "--defined-only", B.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r" T (mppi_\w+)", out))
+    assert set(names) <= exported
+
+
+def test_library_is_built_for_gfx950():
+    out = subprocess.run(["strings", B.LIB_PATH], capture_output=True, text=True).stdout
+    assert "gfx950" in out
+
+
+def _cfg(wl, **over):
+    keep = []
+    params = B.make_params(wl.system, wl.params, keep)
+    sig = np.ascontiguousarray(wl.sigma, dtype=np.float64)
+    R = np.ascontiguousarray(wl.R, dtype=np.float64)
+    ui = np.ascontiguousarray(wl.u_init, dtype=np.float64)
+    keep += [sig, R, ui, params]
+    c = B.Config()
+    c.abi_version = B.ABI_VERSION
+    c.system, c.n_state, c.n_ctrl, c.K, c.T = wl.system, wl.n, wl.m, wl.K, wl.T
+    c.dt, c.lambda_, c.nu = wl.dt, wl.lam, wl.nu
+    c.sigma, c.R, c.u_init = B._ptr(sig), B._ptr(R), B._ptr(ui)
+    c.params = C.cast(C.pointer(params), C.c_void_p)
+    c.params_bytes = C.sizeof(params)
+    for k, v in over.items():
+        setattr(c, k, v)
+    return c, keep
+
+
+def _ws(c):
+    n = C.c_uint64(0)
+    rc = P.load().mppi_workspace_bytes(C.byref(c), C.byref(n))
+    return rc, n.value
+
+
+@pytest.mark.parametrize("make", [W.cartpole, W.bicycle, W.quadrotor, W.linear_double_integrator])
+def test_valid_configs_size_their_workspace(make):
+    wl = make()
+    c, keep = _cfg(wl)
+    rc, n = _ws(c)
+    assert rc == B.OK and n >= wl.K * 8 + wl.T * wl.m * 12
+    c2, keep2 = _cfg(wl, K=wl.K * 2)
+    assert _ws(c2)[1] > n
+
+
+@pytest.mark.parametrize("field,value", [
+    ("abi_version", 99), ("K", 0), ("K", (1 << 22) + 1), ("T", 0), ("T", 1025), ("n_state", 3),
+    ("n_ctrl", 2), ("dt", 0.0), ("dt", float("nan")), ("lambda_", 0.0), ("lambda_", -1.0), ("nu", 0.0),
+    ("system", 17), ("params_bytes", 8), ("sigma", None), ("u_init", None), ("params", None)])
+def test_invalid_configs_are_rejected(field, value):
+    c, keep = _cfg(W.cartpole(), **{field: value})
+    rc, _ = _ws(c)
+    assert rc == B.EINVAL
+    assert len(P.load().mppi_last_error()) > 0
+
+
+def test_sigma_must_be_positive_definite_and_symmetric():
+    wl = W.bicycle()
+    for bad in (np.array([[1.0, 2.0], [2.0, 1.0]]), np.array([[1.0, 0.1], [0.2, 1.0]]), np.array([[-1.0, 0], [0, 1.0]])):
+        c, keep = _cfg(wl.replace(sigma=bad))
+        assert _ws(c)[0] == B.EINVAL
+    c, keep = _cfg(wl.replace(sigma=np.zeros((2, 2))))   # zero noise is allowed
+    assert _ws(c)[0] == B.OK
+
+
+def test_bicycle_map_and_quadrotor_obstacles_are_validated():
+    wl = W.bicycle()
+    c, keep = _cfg(wl.replace(params=dict(wl.params, map=np.zeros((1, 5), np.float32))))
+    assert _ws(c)[0] == B.EINVAL
+    q = W.quadrotor()
+    c, keep = _cfg(q.replace(params=dict(q.params, obstacles=np.zeros((300, 4)))))
+    assert _ws(c)[0] == B.EINVAL
+    c, keep = _cfg(q.replace(params=dict(q.params, mass=0.0)))
+    assert _ws(c)[0] == B.EINVAL
+
+
+def test_create_needs_a_device_or_fails_cleanly():
+    """Without a GPU, mppi_create reports MPPI_EDEVICE (never a silent CPU fallback)."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(P.MppiError) as e:
+        P.controller_for(W.cartpole())
+    assert e.value.code == B.EDEVICE
+    with pytest.raises(P.MppiError):
+        P.philox(np.zeros((1, 4), np.uint32), 0)
+
+
+def test_null_handles_are_rejected():
+    lib = P.load()
+    u = np.zeros(4)
+    assert lib.mppi_step(None, B._ptr(u), 1, B._ptr(u)) == B.EINVAL
+    assert lib.mppi_destroy(None) == B.OK

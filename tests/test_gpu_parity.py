@@ -1,0 +1,113 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle on the same seeded
+inputs, for every compiled-in system at the workloads' full sizes, plus the edge cases
+(one sample, ragged sample counts, one-step horizons, horizons that leave a partial
+noise group, zero noise)."""
+import numpy as np
+import pytest
+
+import paper_1509_01149_amd as P
+import workloads as W
+from oracle import mppi, noise, philox
+from tests._parity import assert_parity, controller, one_step
+
+pytestmark = pytest.mark.gpu
+
+
+def test_philox_bits_match_oracle():
+    rng = np.random.default_rng(0)
+    ctr = rng.integers(0, 2 ** 32, size=(4096, 4), dtype=np.uint64).astype(np.uint32)
+    for seed in (0, 0xDEADBEEF12345678, 1 << 40):
+        out = P.philox(ctr, seed)
+        ref = np.stack(philox.philox4x32_10(ctr[:, 0], ctr[:, 1], ctr[:, 2], ctr[:, 3],
+                                            seed & 0xFFFFFFFF, seed >> 32), axis=1)
+        assert np.array_equal(out, ref)
+
+
+@pytest.mark.parametrize("T,m", [(100, 1), (7, 2), (150, 4)])
+def test_normals_match_oracle(T, m):
+    wl = {1: W.cartpole(K=64, T=T), 2: W.bicycle(K=64, T=T), 4: W.quadrotor(K=64, T=T)}[m].replace(seed=77)
+    with controller(wl) as c:
+        it = (1 << 32) + 3
+        g = c.debug_normals(it, 100, 300)
+        ref = noise.standard_normals(77, it, 300, T, m, k_offset=100)
+        err = np.abs(g - ref) / np.maximum(1.0, np.abs(ref))
+        assert err.max() < 2e-6, err.max()
+
+
+CASES = {
+    "cartpole_nu1": lambda: W.cartpole(nu=1.0),
+    "cartpole_nu2": lambda: W.cartpole(nu=2.0),
+    "bicycle": lambda: W.bicycle(),
+    "quadrotor_nu1": lambda: W.quadrotor(nu=1.0),
+    "quadrotor_nu2": lambda: W.quadrotor(nu=2.0),
+    "quadrotor_nu4": lambda: W.quadrotor(nu=4.0),
+    "linear": lambda: W.linear_double_integrator(K=4096, R=0.3),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_first_iteration_parity(name):
+    wl = CASES[name]().replace(seed=3)
+    U0 = mppi.initial_sequence(wl)
+    with controller(wl) as c:
+        m = one_step(wl, c, wl.x0, U0, 0)
+    print(name, {k: v for k, v in m.items() if isinstance(v, (float, int, bool))})
+    assert_parity(m)
+
+
+@pytest.mark.parametrize("name", ["bicycle", "quadrotor_nu2"])
+def test_warm_started_steps_parity(name):
+    """Several control steps; before each the oracle is given the GPU's own nominal
+    sequence and state, so only one step's arithmetic is compared at a time."""
+    wl = CASES[name]().replace(seed=5, n_iters=2)
+    x = wl.x0.copy()
+    it = 0
+    with controller(wl) as c:
+        for step in range(3):
+            U_before = c.get_controls()
+            m = one_step(wl, c, x, U_before, it, n_iters=2)
+            assert_parity(m)
+            it = m["iteration"]
+            x = mppi.plant_step(wl, x, m["u0_gpu"])
+
+
+def test_closed_loop_cartpole_per_step():
+    """The 200-step cart-pole run, with the oracle re-seeded from the GPU each step."""
+    wl = W.cartpole(nu=2.0).replace(seed=1)
+    x = wl.x0.copy()
+    worst = 0.0
+    with controller(wl) as c:
+        for step in range(wl.control_steps):
+            U_before = c.get_controls()
+            m = one_step(wl, c, x, U_before, step)
+            assert_parity(m)
+            worst = max(worst, m["U_err"])
+            x = mppi.plant_step(wl, x, m["u0_gpu"])
+    print("closed-loop worst U_err", worst, "final x", x)
+    assert abs(x[2]) < 0.2
+
+
+@pytest.mark.parametrize("K,T", [(1, 10), (257, 7), (1000, 1), (4097, 13), (300, 3)])
+def test_ragged_and_tiny_shapes(K, T):
+    for wl in (W.bicycle(K=K, T=T), W.cartpole(nu=2.0, K=K, T=T), W.quadrotor(K=K, T=T)):
+        wl = wl.replace(seed=11)
+        with controller(wl) as c:
+            m = one_step(wl, c, wl.x0, mppi.initial_sequence(wl), 0)
+        assert_parity(m)
+
+
+def test_zero_noise_only_shifts():
+    wl = W.cartpole(K=300, T=20).replace(sigma=np.zeros((1, 1)), R=np.array([[0.01]]))
+    U = np.linspace(-1, 1, 20)[:, None]
+    with controller(wl, u_nominal0=U) as c:
+        u0 = c.step(wl.x0)
+        assert u0[0] == U[0, 0]
+        assert np.array_equal(c.get_controls(), np.vstack([U[1:], [[0.0]]]))
+
+
+def test_linear_small_state():
+    """n = 2 < 4: the linear system must not touch state words beyond n."""
+    wl = W.linear_double_integrator(K=2048, R=0.3).replace(seed=2)
+    with controller(wl) as c:
+        m = one_step(wl, c, wl.x0, mppi.initial_sequence(wl), 0)
+    assert_parity(m)
