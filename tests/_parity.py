@@ -11,7 +11,7 @@ from oracle import mppi, systems
 #          rounding (6e-8 per step) amplified by at most exp(4/s * 2 s) ~ 3e3 along the
 #          cart-pole's unstable upright manifold; <= 0.1 on quadrotor samples whose attitude
 #          passes 1.2 rad (1/cos(pitch) of the Euler-angle rates is ill-conditioned there)
-#   impact sum_k w_k |dS_k| / lambda <= 1e-3: first-order change of the update, in units of du
+#   impact sum_k w_k |dS_k - <dS>_w| / lambda <= 1e-3: first-order change of the update, in du units
 #   stage  the GPU's costs through the oracle's FP64 weights and update: <= 1e-5 relative
 TOL_U = 1e-4
 TOL_S = 1e-4
@@ -21,6 +21,17 @@ TUMBLE_ANGLE = 1.2
 
 def controller(wl, **kw):
     return P.controller_for(wl, **kw)
+
+
+def _impact(last, S_gpu, fin, lam):
+    """First-order change of the update caused by the cost errors, in units of du:
+    d(dU) = -(1/lam) sum_k w_k (dS_k - sum_j w_j dS_j) du_k, bounded by
+    (1/lam) sum_k w_k |dS_k - sum_j w_j dS_j| max|du|."""
+    if last.status != 0:
+        return 0.0
+    d = S_gpu[fin] - last.S[fin]
+    w = last.w[fin]
+    return float(np.sum(w * np.abs(d - np.sum(w * d))) / lam)
 
 
 def one_step(wl, ctrl, x0, U_before, iteration, n_iters=1):
@@ -53,7 +64,7 @@ def one_step(wl, ctrl, x0, U_before, iteration, n_iters=1):
         S_err=float(dS.max()) if dS.size else 0.0,
         S_err_tumble=float(rel[fin & tumble].max()) if np.any(fin & tumble) else 0.0,
         n_tumble=int(np.sum(tumble)),
-        impact=float(np.sum(last.w[fin] * np.abs(S_gpu[fin] - last.S[fin])) / wl.lam) if last.status == 0 else 0.0,
+        impact=_impact(last, S_gpu, fin, wl.lam),
         S_inf_match=bool(np.array_equal(np.isfinite(S_gpu), fin)),
         rho_err=float(abs(rho_gpu - last.rho) / max(1.0, abs(last.rho))),
         eta_rel=float(abs(eta_gpu - last.eta) / last.eta) if last.eta else 0.0,
