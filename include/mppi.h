@@ -201,6 +201,77 @@ int mppi_debug_philox(int32_t device, uint64_t seed, const uint32_t *counters, i
 int mppi_set_profiling(mppi_ctx *ctx, int32_t on);
 int mppi_kernel_times(mppi_ctx *ctx, double *avg_ms, int64_t *count);
 
+/* ------------------------------------------------------------------------------------
+ * Serving: many controllers on one GPU with continuous batching.
+ *
+ * Controllers are admitted into slots while their device state fits the HBM budget; their
+ * warm-started sequences, iteration counters (which key the noise) and descriptors stay
+ * resident on the device.  Each submitted request is one control step (one iteration,
+ * emit u0, warm shift) of one controller from a given start state.  A controller has at
+ * most one step in flight; its requests run in submission order.  Whenever one of the
+ * server's streams is free, every controller with a pending request is packed into one
+ * batch: one rollout launch per system present, one update launch and one finalize
+ * launch cover all of them, so requests that arrive while other batches run join the
+ * next batch and overlap with those on the device.  A controller's results are the same
+ * alone and in any batch (the batched kernels run the single-controller code per block
+ * and every reduction has a fixed order).  The real-time control loop of the paper runs
+ * each controller at 50 Hz (Section V); the server reports per-request completion times.
+ *
+ * MPPI_SERVE_PLAIN is the reference policy: one controller step at a time in arrival
+ * order, each through the controller's own captured single-controller graph.
+ * ------------------------------------------------------------------------------------ */
+typedef struct mppi_server mppi_server;
+
+enum { MPPI_SERVE_BATCHED = 0, MPPI_SERVE_PLAIN = 1 };
+
+typedef struct {
+  int32_t device;
+  uint64_t hbm_budget_bytes;  /* admission budget for controller device state              */
+  int32_t max_slots;          /* 1 .. 4096 controllers                                     */
+  int32_t max_inflight;       /* concurrent batches (one stream each), 1 .. 8; PLAIN uses 1 */
+  int32_t max_batch;          /* controllers per batch, 1 .. max_slots                     */
+  int32_t mode;               /* MPPI_SERVE_BATCHED or MPPI_SERVE_PLAIN                    */
+} mppi_server_config;
+
+typedef struct {
+  uint64_t bytes_used;        /* device bytes held by admitted controllers                 */
+  int32_t slots_used;
+  int32_t queued;             /* requests waiting                                           */
+  int32_t inflight;           /* requests on the device                                     */
+  int64_t requests_done;
+  int64_t batches;            /* batches launched                                           */
+  double mean_batch;          /* requests per batch                                         */
+  int64_t rollout_steps_done; /* sum of K * T over completed requests                       */
+} mppi_server_stats;
+
+int mppi_server_create(const mppi_server_config *cfg, mppi_server **out);
+/* Drain everything in flight and free the server and all its controllers. */
+int mppi_server_destroy(mppi_server *srv);
+/* Admit a controller (cfg as for mppi_create; its stream and workspace fields are ignored).
+ * MPPI_EBUSY when no slot is free or its device state would exceed the budget. */
+int mppi_server_admit(mppi_server *srv, const mppi_config *cfg, int32_t *slot);
+/* Free a slot and its device memory; MPPI_EBUSY while it has queued or in-flight steps. */
+int mppi_server_release(mppi_server *srv, int32_t slot);
+/* Queue one control step of `slot` from start state x0 (host, n doubles).  t_arrival is
+ * on the server clock (mppi_server_now) and is only recorded. */
+int mppi_server_submit(mppi_server *srv, int32_t slot, const double *x0, uint64_t req_id, double t_arrival);
+/* Make progress (harvest finished batches, launch new ones) and return up to max finished
+ * requests: req_ids[max], u0s[max x 4] (first m used), status[max] (MPPI_OK or
+ * MPPI_ENUMERIC), t_done[max] on the server clock; *n = number written. */
+int mppi_server_poll(mppi_server *srv, int32_t max, uint64_t *req_ids, double *u0s, int32_t *status,
+                     double *t_done, int32_t *n);
+/* Replay an arrival trace in real time: request i of slot slots[i] arrives t_arrival[i]
+ * seconds after the call starts, from start state x0s[16 i .. 16 i + n); returns when all
+ * are done, with t_done[i] (seconds since the start), u0s[4 i ..] and status[i].  Arrival
+ * times must be non-decreasing. */
+int mppi_server_replay(mppi_server *srv, int32_t n, const double *t_arrival, const int32_t *slots,
+                       const double *x0s, double *t_done, double *u0s, int32_t *status);
+int mppi_server_stats_get(mppi_server *srv, mppi_server_stats *out);
+/* Nominal sequence (T x m FP64) of an admitted controller, after its finished steps. */
+int mppi_server_get_controls(mppi_server *srv, int32_t slot, double *u, uint64_t len);
+/* Seconds on the server clock (steady, since creation). */
+double mppi_server_now(mppi_server *srv);
+
 /* Thread-local description of the last failure ("" if none). */
 const char *mppi_last_error(void);
 

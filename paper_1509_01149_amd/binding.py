@@ -72,6 +72,19 @@ class Config(C.Structure):
                 ("workspace", C.c_void_p), ("workspace_bytes", C.c_uint64)]
 
 
+class ServerConfig(C.Structure):
+    _fields_ = [("device", C.c_int32), ("hbm_budget_bytes", C.c_uint64), ("max_slots", C.c_int32),
+                ("max_inflight", C.c_int32), ("max_batch", C.c_int32), ("mode", C.c_int32)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("bytes_used", C.c_uint64), ("slots_used", C.c_int32), ("queued", C.c_int32),
+                ("inflight", C.c_int32), ("requests_done", C.c_int64), ("batches", C.c_int64),
+                ("mean_batch", C.c_double), ("rollout_steps_done", C.c_int64)]
+
+
+SERVE_BATCHED, SERVE_PLAIN = 0, 1
+
 _lib = None
 
 
@@ -101,6 +114,16 @@ def load() -> C.CDLL:
         "mppi_debug_philox": [C.c_int32, C.c_uint64, _u32p, C.c_int32, _u32p],
         "mppi_set_profiling": [C.c_void_p, C.c_int32],
         "mppi_kernel_times": [C.c_void_p, _dp, C.POINTER(C.c_int64)],
+        "mppi_server_create": [C.POINTER(ServerConfig), C.POINTER(C.c_void_p)],
+        "mppi_server_destroy": [C.c_void_p],
+        "mppi_server_admit": [C.c_void_p, C.POINTER(Config), C.POINTER(C.c_int32)],
+        "mppi_server_release": [C.c_void_p, C.c_int32],
+        "mppi_server_submit": [C.c_void_p, C.c_int32, _dp, C.c_uint64, C.c_double],
+        "mppi_server_poll": [C.c_void_p, C.c_int32, _u64p, _dp, C.POINTER(C.c_int32), _dp, C.POINTER(C.c_int32)],
+        "mppi_server_replay": [C.c_void_p, C.c_int32, _dp, C.POINTER(C.c_int32), _dp, _dp, _dp,
+                               C.POINTER(C.c_int32)],
+        "mppi_server_stats_get": [C.c_void_p, C.POINTER(ServerStats)],
+        "mppi_server_get_controls": [C.c_void_p, C.c_int32, _dp, C.c_uint64],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -110,6 +133,8 @@ def load() -> C.CDLL:
     lib.mppi_last_error.argtypes = []
     lib.mppi_version.restype = C.c_char_p
     lib.mppi_version.argtypes = []
+    lib.mppi_server_now.restype = C.c_double
+    lib.mppi_server_now.argtypes = [C.c_void_p]
     _lib = lib
     return lib
 
@@ -164,6 +189,31 @@ def make_params(system: int, params: Dict, keep: list):
     raise ValueError(f"unknown system {system}")
 
 
+def make_config(*, system: int, n: int, m: int, K: int, T: int, dt: float, lam: float, nu: float,
+                sigma, R=None, u_init, params: Dict, u_nominal0=None, seed: int = 0, device: int = 0,
+                use_graph: bool = True):
+    """Fill an mppi_config; returns (config, list of arrays that must stay alive)."""
+    keep = []
+    sig = _f64(sigma).reshape(m, m)
+    Rm = None if R is None else _f64(R).reshape(m, m)
+    ui = _f64(u_init).reshape(m)
+    un = None if u_nominal0 is None else _f64(u_nominal0).reshape(T, m)
+    keep += [sig, Rm, ui, un]
+    prm = make_params(system, params, keep)
+    keep.append(prm)
+    cfg = Config()
+    cfg.abi_version = ABI_VERSION
+    cfg.system, cfg.n_state, cfg.n_ctrl, cfg.K, cfg.T = system, n, m, K, T
+    cfg.dt, cfg.lambda_, cfg.nu = dt, lam, nu
+    cfg.sigma, cfg.R, cfg.u_init, cfg.u_nominal0 = _ptr(sig), _ptr(Rm), _ptr(ui), _ptr(un)
+    cfg.params = C.cast(C.pointer(prm), C.c_void_p)
+    cfg.params_bytes = C.sizeof(prm)
+    cfg.seed = seed & 0xFFFFFFFFFFFFFFFF
+    cfg.device = device
+    cfg.use_graph = 1 if use_graph else 0
+    return cfg, keep
+
+
 class Controller:
     """One MPPI controller context (mppi_create ... mppi_destroy)."""
 
@@ -171,24 +221,10 @@ class Controller:
                  sigma, R=None, u_init, params: Dict, u_nominal0=None, seed: int = 0, device: int = 0,
                  use_graph: bool = True, torch_stream=None, torch_workspace: bool = False):
         lib = load()
-        self._keep = []
         self.n, self.m, self.K, self.T = n, m, K, T
-        sig = _f64(sigma).reshape(m, m)
-        Rm = None if R is None else _f64(R).reshape(m, m)
-        ui = _f64(u_init).reshape(m)
-        un = None if u_nominal0 is None else _f64(u_nominal0).reshape(T, m)
-        self._keep += [sig, Rm, ui, un]
-        self._params = make_params(system, params, self._keep)
-        cfg = Config()
-        cfg.abi_version = ABI_VERSION
-        cfg.system, cfg.n_state, cfg.n_ctrl, cfg.K, cfg.T = system, n, m, K, T
-        cfg.dt, cfg.lambda_, cfg.nu = dt, lam, nu
-        cfg.sigma, cfg.R, cfg.u_init, cfg.u_nominal0 = _ptr(sig), _ptr(Rm), _ptr(ui), _ptr(un)
-        cfg.params = C.cast(C.pointer(self._params), C.c_void_p)
-        cfg.params_bytes = C.sizeof(self._params)
-        cfg.seed = seed & 0xFFFFFFFFFFFFFFFF
-        cfg.device = device
-        cfg.use_graph = 1 if use_graph else 0
+        cfg, self._keep = make_config(system=system, n=n, m=m, K=K, T=T, dt=dt, lam=lam, nu=nu, sigma=sigma, R=R,
+                                      u_init=u_init, params=params, u_nominal0=u_nominal0, seed=seed,
+                                      device=device, use_graph=use_graph)
         self._workspace = None
         if torch_stream is not None:
             cfg.stream = C.c_void_p(torch_stream.cuda_stream)
@@ -274,6 +310,97 @@ class Controller:
     def close(self):
         if getattr(self, "handle", None):
             self._lib.mppi_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+class Server:
+    """Continuous-batching server (mppi_server_*)."""
+
+    def __init__(self, *, device: int = 0, hbm_budget_bytes: int = 8 << 30, max_slots: int = 256,
+                 max_inflight: int = 3, max_batch: int = 256, mode: int = SERVE_BATCHED):
+        self._lib = load()
+        cfg = ServerConfig(device, hbm_budget_bytes, max_slots, max_inflight, min(max_batch, max_slots), mode)
+        h = C.c_void_p()
+        check(self._lib.mppi_server_create(C.byref(cfg), C.byref(h)))
+        self.handle = h
+        self.dims = {}
+
+    def admit(self, **kw) -> int:
+        """Admit a controller (keyword arguments as for Controller); returns its slot."""
+        kw.pop("torch_stream", None)
+        kw.pop("torch_workspace", None)
+        cfg, keep = make_config(**kw)
+        slot = C.c_int32(-1)
+        check(self._lib.mppi_server_admit(self.handle, C.byref(cfg), C.byref(slot)))
+        self.dims[slot.value] = (kw["n"], kw["m"], kw["T"], kw["K"])
+        return slot.value
+
+    def release(self, slot: int):
+        check(self._lib.mppi_server_release(self.handle, slot))
+        self.dims.pop(slot, None)
+
+    def now(self) -> float:
+        return self._lib.mppi_server_now(self.handle)
+
+    def submit(self, slot: int, x0, req_id: int, t_arrival: Optional[float] = None):
+        x = np.zeros(16)
+        xv = _f64(x0).ravel()
+        x[:xv.size] = xv
+        t = self.now() if t_arrival is None else t_arrival
+        check(self._lib.mppi_server_submit(self.handle, slot, _ptr(x), req_id, t))
+
+    def poll(self, max_results: int = 1024):
+        ids = np.zeros(max_results, dtype=np.uint64)
+        u0 = np.zeros((max_results, 4))
+        st = np.zeros(max_results, dtype=np.int32)
+        td = np.zeros(max_results)
+        n = C.c_int32(0)
+        check(self._lib.mppi_server_poll(self.handle, max_results, _ptr(ids, _u64p), _ptr(u0),
+                                         st.ctypes.data_as(C.POINTER(C.c_int32)), _ptr(td), C.byref(n)))
+        k = n.value
+        return ids[:k], u0[:k], st[:k], td[:k]
+
+    def replay(self, t_arrival, slots, x0s):
+        """Real-time replay of an arrival trace; returns (t_done, u0s, status)."""
+        t = _f64(t_arrival).ravel()
+        sl = np.ascontiguousarray(np.asarray(slots, dtype=np.int32).ravel())
+        n = t.size
+        x = np.zeros((n, 16))
+        x0s = np.asarray(x0s, dtype=np.float64).reshape(n, -1)
+        x[:, :x0s.shape[1]] = x0s
+        td = np.zeros(n)
+        u0 = np.zeros((n, 4))
+        st = np.zeros(n, dtype=np.int32)
+        check(self._lib.mppi_server_replay(self.handle, n, _ptr(t), sl.ctypes.data_as(C.POINTER(C.c_int32)),
+                                           _ptr(x), _ptr(td), _ptr(u0), st.ctypes.data_as(C.POINTER(C.c_int32))))
+        return td, u0, st
+
+    def stats(self) -> Dict:
+        s = ServerStats()
+        check(self._lib.mppi_server_stats_get(self.handle, C.byref(s)))
+        return {f: getattr(s, f) for f, _ in ServerStats._fields_}
+
+    def get_controls(self, slot: int) -> np.ndarray:
+        n, m, T, K = self.dims[slot]
+        u = np.zeros((T, m))
+        check(self._lib.mppi_server_get_controls(self.handle, slot, _ptr(u), u.size))
+        return u
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self._lib.mppi_server_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -10,7 +10,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmppi.so")
-SOURCES = ["mppi_api.hip", "mppi_mlp.hip"]
+SOURCES = ["mppi_api.hip", "mppi_server.hip", "mppi_mlp.hip"]
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # never emit packed FP32 instructions (v_pk_*_f32)

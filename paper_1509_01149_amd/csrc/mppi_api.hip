@@ -437,7 +437,7 @@ int enqueue_iterations(mppi_ctx *c, const double *x0_dev, int n_iters, double *u
 }
 
 // Run n_iters iterations, through a cached hipGraph when enabled.
-static int run_iterations(mppi_ctx *c, const double *x0_dev, int n_iters, double *u0_dev) {
+int run_iterations(mppi_ctx *c, const double *x0_dev, int n_iters, double *u0_dev) {
   if (!c->cfg.use_graph || c->profiling) return enqueue_iterations(c, x0_dev, n_iters, u0_dev, c->stream);
   auto key = std::make_tuple(n_iters, (const void *)x0_dev, (const void *)u0_dev);
   auto itg = c->graphs.find(key);
@@ -458,7 +458,29 @@ static int run_iterations(mppi_ctx *c, const double *x0_dev, int n_iters, double
   return MPPI_OK;
 }
 
-static int set_device(int dev) {
+size_t ctx_rollout_lds(const mppi_ctx *c) {
+  switch (c->cfg.system) {
+    case MPPI_SYS_LINEAR: return rollout_lds_bytes<LinearSys<1>>(c);
+    case MPPI_SYS_CARTPOLE: return rollout_lds_bytes<CartPoleSys>(c);
+    case MPPI_SYS_BICYCLE: return rollout_lds_bytes<BicycleSys>(c);
+    default: return rollout_lds_bytes<QuadrotorSys>(c);
+  }
+}
+
+// Descriptor of a controller for the batched serving kernels (x0 / u0 come per batch).
+void fill_desc(mppi_ctx *c, CtrlDesc *d) {
+  std::memset(d, 0, sizeof(*d));
+  d->it = make_iter_args(c, nullptr);
+  d->fin = make_fin_args(c, nullptr, 1);
+  switch (c->cfg.system) {
+    case MPPI_SYS_LINEAR: d->p.lin = c->linear; break;
+    case MPPI_SYS_CARTPOLE: d->p.cp = c->cartpole; break;
+    case MPPI_SYS_BICYCLE: d->p.bc = c->bicycle; break;
+    default: d->p.qd = c->quad; break;
+  }
+}
+
+int set_device(int dev) {
   int n = 0;
   hipError_t e = hipGetDeviceCount(&n);
   if (e != hipSuccess || n == 0) return fail(MPPI_EDEVICE, "no HIP device available");

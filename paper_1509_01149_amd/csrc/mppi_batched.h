@@ -1,0 +1,76 @@
+// Batched serving kernels: one launch covers the blocks of many controllers.  Each
+// controller's per-iteration arguments live in a device-resident descriptor written at
+// admission; a per-batch work list names the controllers, their staged start states and
+// their result slots.  Every block resolves (controller, local block) from prefix sums
+// and runs the same body as the single-controller kernels.
+#pragma once
+#include "mppi_kernels.h"
+
+namespace mppi {
+
+union SysParams {
+  LinearParams lin;
+  CartPoleSys::Params cp;
+  BicycleSys::Params bc;
+  QuadrotorSys::Params qd;
+};
+
+template <class Sys> __device__ __host__ inline const typename Sys::Params &sys_params(const SysParams &u);
+template <> __device__ __host__ inline const LinearParams &sys_params<LinearSys<1>>(const SysParams &u) { return u.lin; }
+template <> __device__ __host__ inline const LinearParams &sys_params<LinearSys<2>>(const SysParams &u) { return u.lin; }
+template <> __device__ __host__ inline const LinearParams &sys_params<LinearSys<4>>(const SysParams &u) { return u.lin; }
+template <> __device__ __host__ inline const CartPoleSys::Params &sys_params<CartPoleSys>(const SysParams &u) { return u.cp; }
+template <> __device__ __host__ inline const BicycleSys::Params &sys_params<BicycleSys>(const SysParams &u) { return u.bc; }
+template <> __device__ __host__ inline const QuadrotorSys::Params &sys_params<QuadrotorSys>(const SysParams &u) { return u.qd; }
+
+struct CtrlDesc {
+  IterArgs it;          // it.x0 unused: the start state comes from the work item
+  FinalizeArgs fin;     // fin.u0_out unused; fin.emit = 1 (one iteration per served step)
+  SysParams p;
+};
+
+struct WorkItem {
+  int desc;             // controller slot
+  int pad;
+  const double *x0;     // staged start state (device)
+  double *out;          // result slot (device): u0[0..3], status at [4]
+};
+
+// Largest j with prefix[j] <= b (prefix[0] = 0, strictly increasing over non-empty items).
+__device__ __forceinline__ int find_item(const int *__restrict__ prefix, int n, int b) {
+  int lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (prefix[mid] <= b) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+template <class Sys>
+__global__ __launch_bounds__(kBlock) void rollout_batched(const CtrlDesc *__restrict__ descs,
+                                                          const WorkItem *__restrict__ items,
+                                                          const int *__restrict__ sel,
+                                                          const int *__restrict__ prefix, int n) {
+  extern __shared__ float4 lds4[];
+  const int j = find_item(prefix, n, blockIdx.x);
+  const WorkItem &w = items[sel[j]];
+  const CtrlDesc &d = descs[w.desc];
+  rollout_body<Sys>(d.it, sys_params<Sys>(d.p), w.x0, blockIdx.x - prefix[j], lds4);
+}
+
+static __global__ __launch_bounds__(kBlock) void update_batched(const CtrlDesc *__restrict__ descs,
+                                                                const WorkItem *__restrict__ items,
+                                                                const int *__restrict__ prefix, int n) {
+  const int j = find_item(prefix, n, blockIdx.x);
+  const CtrlDesc &d = descs[items[j].desc];
+  const int l = blockIdx.x - prefix[j];
+  update_body(d.it, l % d.it.n_kc, l / d.it.n_kc);
+}
+
+static __global__ __launch_bounds__(kFinBlock) void finalize_batched(const CtrlDesc *__restrict__ descs,
+                                                                     const WorkItem *__restrict__ items) {
+  const WorkItem &w = items[blockIdx.x];
+  finalize_body(descs[w.desc].fin, w.out, w.out + 4);
+}
+
+}  // namespace mppi

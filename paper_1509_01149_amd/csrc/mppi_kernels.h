@@ -58,11 +58,14 @@ struct FinalizeArgs {
 };
 
 // ------------------------------------------------------------------------ rollout
+// One 256-sample block of one controller (`blk` indexes the controller's blocks).
+// The single-controller kernel and the batched serving kernel both call this body, so a
+// controller's results do not depend on what else shares the launch.
 template <class Sys>
-__global__ __launch_bounds__(kBlock) void rollout_kernel(const IterArgs a, const typename Sys::Params p) {
+__device__ __forceinline__ void rollout_body(const IterArgs &a, const typename Sys::Params &p, const double *x0,
+                                             int blk, float4 *lds4) {
   constexpr int N = Sys::N, M = Sys::M;
   constexpr int SPG = 4 / M;                        // steps per noise group
-  extern __shared__ float4 lds4[];
   float *sU = reinterpret_cast<float *>(lds4);      // [T*M]
   float *sRU = sU + a.T * M;                        // [T*M]  R u_i
   float *sC = sRU + a.T * M;                        // [T]    u_i'R u_i / 2
@@ -87,14 +90,14 @@ __global__ __launch_bounds__(kBlock) void rollout_kernel(const IterArgs a, const
     sC[i] = 0.5f * c;
   }
   int ti = 0, tj = 0;                               // every thread computes the same origin
-  Sys::stage(p, sSys, a.x0, &ti, &tj);
+  Sys::stage(p, sSys, x0, &ti, &tj);
   __syncthreads();
   const StageView sv{sSys, ti, tj};
 
-  const int k = blockIdx.x * kBlock + threadIdx.x;
+  const int k = blk * kBlock + threadIdx.x;
   float x[N];
 #pragma unroll
-  for (int r = 0; r < N; ++r) x[r] = r < a.n ? (float)a.x0[r] : 0.f;
+  for (int r = 0; r < N; ++r) x[r] = r < a.n ? (float)x0[r] : 0.f;
   double S = 0.0;
   for (int g = 0; g < a.G; ++g) {
     float e[4];
@@ -134,7 +137,13 @@ __global__ __launch_bounds__(kBlock) void rollout_kernel(const IterArgs a, const
   const bool valid = k < a.K;
   if (valid) a.S[k] = S;
   const double bm = block_min(valid ? S : __builtin_inf(), red);
-  if (threadIdx.x == 0) a.blk_min[blockIdx.x] = bm;
+  if (threadIdx.x == 0) a.blk_min[blk] = bm;
+}
+
+template <class Sys>
+__global__ __launch_bounds__(kBlock) void rollout_kernel(const IterArgs a, const typename Sys::Params p) {
+  extern __shared__ float4 lds4[];
+  rollout_body<Sys>(a, p, a.x0, blockIdx.x, lds4);
 }
 
 // Minimum over the rollout blocks' minima (every thread gets it).
@@ -147,11 +156,10 @@ __device__ __forceinline__ double global_min(const double *blk_min, int n, doubl
 // ------------------------------------------------------------------------- update
 // grid (n_kc, ceil(G / kUpdGroups)).  Thread t handles noise group gc*16 + t%16 for the
 // samples of strip t/16 of this block's 256-sample chunk.
-static __global__ __launch_bounds__(kBlock) void update_kernel(const IterArgs a) {
+__device__ __forceinline__ void update_body(const IterArgs &a, int kc, int gcb) {
   __shared__ double w[kUpdChunk];
   __shared__ double acc_lds[kUpdStrips][kUpdGroups][4];
   __shared__ double red[4];
-  const int kc = blockIdx.x, gcb = blockIdx.y;
   const double rho = global_min(a.blk_min, a.n_roll_blocks, red);
   const uint64_t it = *a.iter;
   {
@@ -195,31 +203,48 @@ static __global__ __launch_bounds__(kBlock) void update_kernel(const IterArgs a)
   }
 }
 
+static __global__ __launch_bounds__(kBlock) void update_kernel(const IterArgs a) {
+  update_body(a, blockIdx.x, blockIdx.y);
+}
+
 // ----------------------------------------------------------------------- finalize
-// One block of 1024 threads; T*m <= 4096 handled in a strided loop.
+// One block of 1024 threads; T*m <= 4096 handled in a strided loop.  Sums over the
+// chunk partials run in a fixed order (c = 0, 1, ...) with their loads issued eight at
+// a time, so the result is independent of timing and of the batch it runs in.
 constexpr int kFinBlock = 1024;
 constexpr int kMaxTM = 4096;
-static __global__ __launch_bounds__(kFinBlock) void finalize_kernel(const FinalizeArgs a) {
+
+__device__ __forceinline__ double ordered_sum(const double *p, size_t stride, int n) {
+  double s = 0.0;
+  int c = 0;
+  for (; c + 8 <= n; c += 8) {
+    double v[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = p[(size_t)(c + j) * stride];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) s += v[j];
+  }
+  for (; c < n; ++c) s += p[(size_t)c * stride];
+  return s;
+}
+
+// status_out (nullable): 0 when the iteration had a finite cost, -5 otherwise.
+__device__ __forceinline__ void finalize_body(const FinalizeArgs &a, double *u0_out, double *status_out) {
   __shared__ double N_lds[kMaxTM];
   __shared__ double red[16];
+  __shared__ double eta_s;
   const int TM = a.T * a.m;
-  // rho (exact, order-free) and eta (fixed order: serial over chunks)
   double v = __builtin_inf();
   for (int b = threadIdx.x; b < a.n_roll_blocks; b += kFinBlock) v = fmin(v, a.blk_min[b]);
   v = wave_min(v);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x / 64] = v;
+  if (threadIdx.x == 0) eta_s = ordered_sum(a.eta_part, 1, a.n_kc);
+  for (int f = threadIdx.x; f < TM; f += kFinBlock) N_lds[f] = ordered_sum(a.part + f, (size_t)a.G * 4, a.n_kc);
   __syncthreads();
   double rho = red[0];
   for (int i = 1; i < kFinBlock / 64; ++i) rho = fmin(rho, red[i]);
   const bool ok = rho < __builtin_inf();
-  double eta = 0.0;
-  for (int c = 0; c < a.n_kc; ++c) eta += a.eta_part[c];
-  for (int f = threadIdx.x; f < TM; f += kFinBlock) {
-    double s = 0.0;
-    for (int c = 0; c < a.n_kc; ++c) s += a.part[(size_t)c * (a.G * 4) + f];
-    N_lds[f] = s;
-  }
-  __syncthreads();
+  const double eta = eta_s;
   const double inv_eta = ok ? 1.0 / eta : 0.0;
   for (int f = threadIdx.x; f < TM; f += kFinBlock) {
     const int i = f / a.m, j = f - i * a.m;
@@ -232,7 +257,8 @@ static __global__ __launch_bounds__(kFinBlock) void finalize_kernel(const Finali
   if (threadIdx.x == 0) {
     a.dbg[0] = rho;
     a.dbg[1] = ok ? eta : 0.0;
-    if (!ok) a.flags[0] |= 1;
+    if (!ok) a.flags[0] += 1;
+    if (status_out) *status_out = ok ? 0.0 : -5.0;
     a.iter[0] += 1;
   }
   if (a.emit) {
@@ -240,7 +266,7 @@ static __global__ __launch_bounds__(kFinBlock) void finalize_kernel(const Finali
     double nxt[kMaxTM / kFinBlock];
     int n = 0;
     for (int f = threadIdx.x; f < TM; f += kFinBlock) {
-      if (f < a.m) a.u0_out[f] = a.U64[f];
+      if (f < a.m) u0_out[f] = a.U64[f];
       nxt[n++] = (f + a.m < TM) ? a.U64[f + a.m] : a.u_init[f - (TM - a.m)];
     }
     __syncthreads();
@@ -249,6 +275,10 @@ static __global__ __launch_bounds__(kFinBlock) void finalize_kernel(const Finali
     __syncthreads();
   }
   for (int f = threadIdx.x; f < TM; f += kFinBlock) a.U32[f] = (float)a.U64[f];
+}
+
+static __global__ __launch_bounds__(kFinBlock) void finalize_kernel(const FinalizeArgs a) {
+  finalize_body(a, a.u0_out, nullptr);
 }
 
 // --------------------------------------------------------------------- plant (FP64)

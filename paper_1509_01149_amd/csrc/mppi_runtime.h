@@ -8,7 +8,7 @@
 #include <vector>
 
 #include "../../include/mppi.h"
-#include "mppi_kernels.h"
+#include "mppi_batched.h"
 
 namespace mppi {
 
@@ -60,6 +60,10 @@ int hip_fail(hipError_t e, const char *what);
 int validate_config(const mppi_config *c);
 void compute_layout(const mppi_config *c, Layout *L);
 int enqueue_iterations(mppi_ctx *c, const double *x0_dev, int n_iters, double *u0_dev, hipStream_t s);
+int run_iterations(mppi_ctx *c, const double *x0_dev, int n_iters, double *u0_dev);
+size_t ctx_rollout_lds(const mppi_ctx *c);
+void fill_desc(mppi_ctx *c, CtrlDesc *d);
+int set_device(int dev);
 
 // learned-dynamics hooks (mppi_mlp.hip)
 uint64_t extra_workspace_bytes(const mppi_config *c);

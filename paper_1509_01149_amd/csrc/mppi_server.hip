@@ -1,0 +1,491 @@
+// Serving runtime: continuous batching of many MPPI controllers on one GPU
+// (contract in include/mppi.h, "Serving").
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "../../include/mppi.h"
+#include "mppi_runtime.h"
+
+using namespace mppi;
+
+namespace {
+
+constexpr int kKinds = 6;  // rollout instantiations: linear m=1,2,4, cart-pole, bicycle, quadrotor
+
+int kind_of(const mppi_config &c) {
+  switch (c.system) {
+    case MPPI_SYS_LINEAR: return c.n_ctrl == 1 ? 0 : (c.n_ctrl == 2 ? 1 : 2);
+    case MPPI_SYS_CARTPOLE: return 3;
+    case MPPI_SYS_BICYCLE: return 4;
+    default: return 5;
+  }
+}
+
+struct Request {
+  uint64_t id;
+  double t_arrival;
+  double x0[16];
+};
+
+struct Slot {
+  bool used = false;
+  mppi_ctx *ctx = nullptr;
+  std::deque<Request> q;
+  bool busy = false;
+  uint64_t bytes = 0;
+  int kind = 0;
+  int m = 0;
+  int n_roll = 0, n_upd = 0;
+  size_t lds = 0;
+  int64_t rollout_steps = 0;
+};
+
+struct Entry {
+  int slot;
+  uint64_t id;
+  double t_arrival;
+};
+
+// Per-stream batch buffers: plan + staged start states (uploaded), results (downloaded).
+struct Batch {
+  hipStream_t stream = nullptr;
+  hipEvent_t done = nullptr;
+  bool active = false;
+  char *h = nullptr, *d = nullptr;
+  size_t off_items = 0, off_sel = 0, off_proll = 0, off_pupd = 0, off_x0 = 0, off_out = 0, bytes = 0;
+  std::vector<Entry> entries;
+};
+
+struct Result {
+  uint64_t id;
+  double u0[4];
+  int status;
+  double t_done;
+};
+
+size_t al(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace
+
+struct mppi_server {
+  mppi_server_config cfg;
+  std::mutex mu;
+  std::chrono::steady_clock::time_point t0;
+  std::vector<Slot> slots;
+  uint64_t used = 0;
+  CtrlDesc *d_descs = nullptr;
+  std::vector<Batch> batches;
+  std::deque<int> fifo;            // PLAIN: slots in submission order
+  std::vector<Result> done;
+  int rr = 0;                      // round-robin start for batch formation
+  size_t lds_set[kKinds] = {0};
+  int64_t n_done = 0, n_batches = 0, n_batched_req = 0, steps_done = 0;
+  int queued = 0, inflight = 0;
+
+  double now() const { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); }
+};
+
+namespace {
+
+template <class Sys>
+void launch_roll(mppi_server *s, Batch &b, int kind, int count, int total, size_t lds) {
+  if (lds > s->lds_set[kind]) {
+    (void)hipFuncSetAttribute((const void *)rollout_batched<Sys>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    s->lds_set[kind] = lds;
+  }
+  const int B = s->cfg.max_batch;
+  hipLaunchKernelGGL(rollout_batched<Sys>, dim3(total), dim3(kBlock), lds, b.stream, s->d_descs,
+                     (const WorkItem *)(b.d + b.off_items), (const int *)(b.d + b.off_sel) + kind * B,
+                     (const int *)(b.d + b.off_proll) + kind * (B + 1), count);
+}
+
+int launch_batched(mppi_server *s, Batch &b, const std::vector<int> &sl) {
+  const int B = s->cfg.max_batch;
+  const int nb = (int)sl.size();
+  auto *items = (WorkItem *)(b.h + b.off_items);
+  auto *sel = (int *)(b.h + b.off_sel);
+  auto *proll = (int *)(b.h + b.off_proll);
+  auto *pupd = (int *)(b.h + b.off_pupd);
+  auto *x0 = (double *)(b.h + b.off_x0);
+  int cnt[kKinds] = {0};
+  size_t lds[kKinds] = {0};
+  for (int k = 0; k < kKinds; ++k) proll[k * (B + 1)] = 0;
+  pupd[0] = 0;
+  b.entries.clear();
+  for (int j = 0; j < nb; ++j) {
+    Slot &S = s->slots[sl[j]];
+    Request r = S.q.front();
+    S.q.pop_front();
+    S.busy = true;
+    std::memcpy(x0 + 16 * j, r.x0, sizeof(r.x0));
+    items[j].desc = sl[j];
+    items[j].pad = 0;
+    items[j].x0 = (const double *)(b.d + b.off_x0) + 16 * j;
+    items[j].out = (double *)(b.d + b.off_out) + 8 * j;
+    const int k = S.kind;
+    sel[k * B + cnt[k]] = j;
+    proll[k * (B + 1) + cnt[k] + 1] = proll[k * (B + 1) + cnt[k]] + S.n_roll;
+    cnt[k] += 1;
+    lds[k] = std::max(lds[k], S.lds);
+    pupd[j + 1] = pupd[j] + S.n_upd;
+    b.entries.push_back({sl[j], r.id, r.t_arrival});
+  }
+  hipError_t e = hipMemcpyAsync(b.d, b.h, b.off_out, hipMemcpyHostToDevice, b.stream);
+  if (e != hipSuccess) return hip_fail(e, "batch upload");
+  if (cnt[0]) launch_roll<LinearSys<1>>(s, b, 0, cnt[0], proll[0 * (B + 1) + cnt[0]], lds[0]);
+  if (cnt[1]) launch_roll<LinearSys<2>>(s, b, 1, cnt[1], proll[1 * (B + 1) + cnt[1]], lds[1]);
+  if (cnt[2]) launch_roll<LinearSys<4>>(s, b, 2, cnt[2], proll[2 * (B + 1) + cnt[2]], lds[2]);
+  if (cnt[3]) launch_roll<CartPoleSys>(s, b, 3, cnt[3], proll[3 * (B + 1) + cnt[3]], lds[3]);
+  if (cnt[4]) launch_roll<BicycleSys>(s, b, 4, cnt[4], proll[4 * (B + 1) + cnt[4]], lds[4]);
+  if (cnt[5]) launch_roll<QuadrotorSys>(s, b, 5, cnt[5], proll[5 * (B + 1) + cnt[5]], lds[5]);
+  hipLaunchKernelGGL(update_batched, dim3(pupd[nb]), dim3(kBlock), 0, b.stream, s->d_descs,
+                     (const WorkItem *)(b.d + b.off_items), (const int *)(b.d + b.off_pupd), nb);
+  hipLaunchKernelGGL(finalize_batched, dim3(nb), dim3(kFinBlock), 0, b.stream, s->d_descs,
+                     (const WorkItem *)(b.d + b.off_items));
+  e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpyAsync(b.h + b.off_out, b.d + b.off_out, (size_t)nb * 8 * sizeof(double),
+                                          hipMemcpyDeviceToHost, b.stream);
+  if (e == hipSuccess) e = hipEventRecord(b.done, b.stream);
+  if (e != hipSuccess) return hip_fail(e, "batch launch");
+  b.active = true;
+  s->n_batches += 1;
+  s->n_batched_req += nb;
+  s->queued -= nb;
+  s->inflight += nb;
+  return MPPI_OK;
+}
+
+// PLAIN: one controller step through its own captured single-controller graph.
+int launch_plain(mppi_server *s, Batch &b, int slot) {
+  Slot &S = s->slots[slot];
+  Request r = S.q.front();
+  S.q.pop_front();
+  S.busy = true;
+  mppi_ctx *c = S.ctx;
+  double *hx = (double *)(b.h + b.off_x0);
+  std::memcpy(hx, r.x0, sizeof(r.x0));
+  double *d_x0 = (double *)(c->base + c->L.off_x0);
+  double *d_res = (double *)(c->base + c->L.off_res);
+  hipError_t e = hipMemcpyAsync(d_x0, hx, 16 * sizeof(double), hipMemcpyHostToDevice, b.stream);
+  if (e != hipSuccess) return hip_fail(e, "plain upload");
+  int rc = run_iterations(c, d_x0, 1, d_res);
+  if (rc) return rc;
+  e = hipMemcpyAsync(b.h + b.off_out, d_res, 8 * sizeof(double), hipMemcpyDeviceToHost, b.stream);
+  if (e == hipSuccess) e = hipEventRecord(b.done, b.stream);
+  if (e != hipSuccess) return hip_fail(e, "plain launch");
+  b.entries.clear();
+  b.entries.push_back({slot, r.id, r.t_arrival});
+  b.active = true;
+  s->n_batches += 1;
+  s->n_batched_req += 1;
+  s->queued -= 1;
+  s->inflight += 1;
+  return MPPI_OK;
+}
+
+int harvest(mppi_server *s, Batch &b) {
+  hipError_t e = hipEventQuery(b.done);
+  if (e == hipErrorNotReady) return MPPI_OK;
+  if (e != hipSuccess) return hip_fail(e, "batch completion");
+  const double t = s->now();
+  const double *out = (const double *)(b.h + b.off_out);
+  for (size_t j = 0; j < b.entries.size(); ++j) {
+    const Entry &en = b.entries[j];
+    Slot &S = s->slots[en.slot];
+    Result r;
+    r.id = en.id;
+    r.t_done = t;
+    for (int i = 0; i < 4; ++i) r.u0[i] = i < S.m ? out[8 * j + i] : 0.0;
+    if (s->cfg.mode == MPPI_SERVE_PLAIN) {
+      int cnt;
+      std::memcpy(&cnt, out + 4, sizeof(int));
+      r.status = cnt != S.ctx->seen_numeric ? MPPI_ENUMERIC : MPPI_OK;
+      S.ctx->seen_numeric = cnt;
+    } else {
+      r.status = out[8 * j + 4] != 0.0 ? MPPI_ENUMERIC : MPPI_OK;
+    }
+    s->done.push_back(r);
+    S.busy = false;
+    s->n_done += 1;
+    s->steps_done += S.rollout_steps;
+    s->inflight -= 1;
+  }
+  b.entries.clear();
+  b.active = false;
+  return MPPI_OK;
+}
+
+int progress(mppi_server *s) {
+  for (auto &b : s->batches)
+    if (b.active) {
+      int rc = harvest(s, b);
+      if (rc) return rc;
+    }
+  for (auto &b : s->batches) {
+    if (b.active) continue;
+    if (s->cfg.mode == MPPI_SERVE_PLAIN) {
+      while (!s->fifo.empty() && (!s->slots[s->fifo.front()].used || s->slots[s->fifo.front()].q.empty()))
+        s->fifo.pop_front();
+      if (s->fifo.empty()) break;
+      const int slot = s->fifo.front();
+      if (s->slots[slot].busy) break;   // keep arrival order
+      s->fifo.pop_front();
+      int rc = launch_plain(s, b, slot);
+      if (rc) return rc;
+      continue;
+    }
+    std::vector<int> sl;
+    const int n = (int)s->slots.size();
+    for (int i = 0; i < n && (int)sl.size() < s->cfg.max_batch; ++i) {
+      const int k = (s->rr + i) % n;
+      const Slot &S = s->slots[k];
+      if (S.used && !S.busy && !S.q.empty()) sl.push_back(k);
+    }
+    if (sl.empty()) break;
+    s->rr = (sl.back() + 1) % n;
+    int rc = launch_batched(s, b, sl);
+    if (rc) return rc;
+  }
+  return MPPI_OK;
+}
+
+int check_srv(mppi_server *s) {
+  if (!s) return fail(MPPI_EINVAL, "server is NULL");
+  hipError_t e = hipSetDevice(s->cfg.device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  return MPPI_OK;
+}
+
+}  // namespace
+
+extern "C" int mppi_server_create(const mppi_server_config *cfg, mppi_server **out) {
+  if (!cfg || !out) return fail(MPPI_EINVAL, "cfg and out must be non-NULL");
+  *out = nullptr;
+  if (cfg->max_slots < 1 || cfg->max_slots > 4096) return fail(MPPI_EINVAL, "max_slots outside [1, 4096]");
+  if (cfg->max_inflight < 1 || cfg->max_inflight > 8) return fail(MPPI_EINVAL, "max_inflight outside [1, 8]");
+  if (cfg->max_batch < 1 || cfg->max_batch > cfg->max_slots) return fail(MPPI_EINVAL, "max_batch outside [1, max_slots]");
+  if (cfg->mode != MPPI_SERVE_BATCHED && cfg->mode != MPPI_SERVE_PLAIN) return fail(MPPI_EINVAL, "unknown mode");
+  int rc = set_device(cfg->device);
+  if (rc) return rc;
+  auto *s = new mppi_server();
+  s->cfg = *cfg;
+  if (cfg->mode == MPPI_SERVE_PLAIN) { s->cfg.max_inflight = 1; s->cfg.max_batch = 1; }
+  s->t0 = std::chrono::steady_clock::now();
+  s->slots.resize(cfg->max_slots);
+  hipError_t e = hipMalloc((void **)&s->d_descs, sizeof(CtrlDesc) * cfg->max_slots);
+  if (e != hipSuccess) { delete s; return fail(MPPI_ENOMEM, "descriptor table: %s", hipGetErrorString(e)); }
+  const int B = s->cfg.max_batch;
+  s->batches.resize(s->cfg.max_inflight);
+  for (auto &b : s->batches) {
+    b.off_items = 0;
+    b.off_sel = al(b.off_items + sizeof(WorkItem) * B);
+    b.off_proll = al(b.off_sel + sizeof(int) * kKinds * B);
+    b.off_pupd = al(b.off_proll + sizeof(int) * kKinds * (B + 1));
+    b.off_x0 = al(b.off_pupd + sizeof(int) * (B + 1));
+    b.off_out = al(b.off_x0 + sizeof(double) * 16 * B);
+    b.bytes = al(b.off_out + sizeof(double) * 8 * B);
+    e = hipStreamCreateWithFlags(&b.stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b.done, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&b.h, b.bytes, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipMalloc((void **)&b.d, b.bytes);
+    if (e != hipSuccess) { mppi_server_destroy(s); return hip_fail(e, "server stream buffers"); }
+    std::memset(b.h, 0, b.bytes);
+  }
+  *out = s;
+  return MPPI_OK;
+}
+
+extern "C" int mppi_server_destroy(mppi_server *s) {
+  if (!s) return MPPI_OK;
+  (void)hipSetDevice(s->cfg.device);
+  for (auto &b : s->batches) if (b.stream) (void)hipStreamSynchronize(b.stream);
+  for (auto &S : s->slots) if (S.ctx) mppi_destroy(S.ctx);
+  for (auto &b : s->batches) {
+    if (b.h) (void)hipHostFree(b.h);
+    if (b.d) (void)hipFree(b.d);
+    if (b.done) (void)hipEventDestroy(b.done);
+    if (b.stream) (void)hipStreamDestroy(b.stream);
+  }
+  if (s->d_descs) (void)hipFree(s->d_descs);
+  delete s;
+  return MPPI_OK;
+}
+
+extern "C" int mppi_server_admit(mppi_server *s, const mppi_config *cfg, int32_t *slot) {
+  int rc = check_srv(s);
+  if (rc) return rc;
+  if (!cfg || !slot) return fail(MPPI_EINVAL, "cfg and slot must be non-NULL");
+  if (cfg->system == MPPI_SYS_QUADROTOR_MLP) return fail(MPPI_EINVAL, "the server runs the analytic systems");
+  std::lock_guard<std::mutex> lk(s->mu);
+  uint64_t bytes = 0;
+  rc = mppi_workspace_bytes(cfg, &bytes);
+  if (rc) return rc;
+  int free_slot = -1;
+  for (int i = 0; i < (int)s->slots.size(); ++i)
+    if (!s->slots[i].used) { free_slot = i; break; }
+  if (free_slot < 0) return fail(MPPI_EBUSY, "no free slot");
+  if (s->used + bytes > s->cfg.hbm_budget_bytes)
+    return fail(MPPI_EBUSY, "HBM budget: %llu + %llu > %llu bytes", (unsigned long long)s->used,
+                (unsigned long long)bytes, (unsigned long long)s->cfg.hbm_budget_bytes);
+  mppi_config c = *cfg;
+  c.device = s->cfg.device;
+  c.stream = s->batches[0].stream;
+  c.workspace = nullptr;
+  c.workspace_bytes = 0;
+  c.use_graph = 1;
+  mppi_ctx *ctx = nullptr;
+  rc = mppi_create(&c, &ctx);
+  if (rc) return rc;
+  CtrlDesc d;
+  fill_desc(ctx, &d);
+  hipError_t e = hipMemcpy(s->d_descs + free_slot, &d, sizeof(d), hipMemcpyHostToDevice);
+  if (e != hipSuccess) { mppi_destroy(ctx); return hip_fail(e, "descriptor upload"); }
+  Slot &S = s->slots[free_slot];
+  S = Slot();
+  S.used = true;
+  S.ctx = ctx;
+  S.bytes = bytes;
+  S.kind = kind_of(c);
+  S.m = c.n_ctrl;
+  S.n_roll = ctx->L.n_roll_blocks;
+  S.n_upd = ctx->L.n_kc * ((ctx->L.G + kUpdGroups - 1) / kUpdGroups);
+  S.lds = ctx_rollout_lds(ctx);
+  S.rollout_steps = (int64_t)c.K * c.T;
+  s->used += bytes;
+  *slot = free_slot;
+  return MPPI_OK;
+}
+
+extern "C" int mppi_server_release(mppi_server *s, int32_t slot) {
+  int rc = check_srv(s);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (slot < 0 || slot >= (int)s->slots.size() || !s->slots[slot].used) return fail(MPPI_ENOTFOUND, "unknown slot %d", slot);
+  Slot &S = s->slots[slot];
+  if (S.busy || !S.q.empty()) return fail(MPPI_EBUSY, "slot %d has queued or in-flight steps", slot);
+  mppi_destroy(S.ctx);
+  s->used -= S.bytes;
+  S = Slot();
+  return MPPI_OK;
+}
+
+extern "C" int mppi_server_submit(mppi_server *s, int32_t slot, const double *x0, uint64_t req_id, double t_arrival) {
+  int rc = check_srv(s);
+  if (rc) return rc;
+  if (!x0) return fail(MPPI_EINVAL, "x0 is NULL");
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (slot < 0 || slot >= (int)s->slots.size() || !s->slots[slot].used) return fail(MPPI_ENOTFOUND, "unknown slot %d", slot);
+  Slot &S = s->slots[slot];
+  Request r;
+  r.id = req_id;
+  r.t_arrival = t_arrival;
+  std::memset(r.x0, 0, sizeof(r.x0));
+  for (int i = 0; i < S.ctx->cfg.n_state; ++i) {
+    if (!std::isfinite(x0[i])) return fail(MPPI_EINVAL, "x0 has non-finite entries");
+    r.x0[i] = x0[i];
+  }
+  S.q.push_back(r);
+  s->queued += 1;
+  if (s->cfg.mode == MPPI_SERVE_PLAIN) s->fifo.push_back(slot);
+  return MPPI_OK;
+}
+
+extern "C" int mppi_server_poll(mppi_server *s, int32_t max, uint64_t *ids, double *u0s, int32_t *status,
+                                double *t_done, int32_t *n) {
+  int rc = check_srv(s);
+  if (rc) return rc;
+  if (!n || max < 0 || (max > 0 && (!ids || !u0s || !status || !t_done))) return fail(MPPI_EINVAL, "bad poll arguments");
+  std::lock_guard<std::mutex> lk(s->mu);
+  rc = progress(s);
+  if (rc) return rc;
+  const int k = std::min<int>(max, (int)s->done.size());
+  for (int i = 0; i < k; ++i) {
+    const Result &r = s->done[i];
+    ids[i] = r.id;
+    for (int j = 0; j < 4; ++j) u0s[4 * i + j] = r.u0[j];
+    status[i] = r.status;
+    t_done[i] = r.t_done;
+  }
+  s->done.erase(s->done.begin(), s->done.begin() + k);
+  *n = k;
+  return MPPI_OK;
+}
+
+extern "C" int mppi_server_replay(mppi_server *s, int32_t n, const double *t_arrival, const int32_t *slots,
+                                  const double *x0s, double *t_done, double *u0s, int32_t *status) {
+  int rc = check_srv(s);
+  if (rc) return rc;
+  if (n < 0 || (n > 0 && (!t_arrival || !slots || !x0s || !t_done || !u0s || !status)))
+    return fail(MPPI_EINVAL, "bad replay arguments");
+  for (int i = 1; i < n; ++i)
+    if (t_arrival[i] < t_arrival[i - 1]) return fail(MPPI_EINVAL, "arrival times must be non-decreasing");
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    for (int i = 0; i < n; ++i)
+      if (slots[i] < 0 || slots[i] >= (int)s->slots.size() || !s->slots[slots[i]].used)
+        return fail(MPPI_ENOTFOUND, "unknown slot %d", slots[i]);
+  }
+  const double base = s->now();
+  int next = 0, finished = 0;
+  std::vector<uint64_t> ids(256);
+  std::vector<double> u(4 * 256), td(256);
+  std::vector<int32_t> st(256);
+  while (finished < n) {
+    const double t = s->now() - base;
+    while (next < n && t_arrival[next] <= t) {
+      rc = mppi_server_submit(s, slots[next], x0s + 16 * (size_t)next, (uint64_t)next, base + t_arrival[next]);
+      if (rc) return rc;
+      ++next;
+    }
+    int32_t got = 0;
+    rc = mppi_server_poll(s, 256, ids.data(), u.data(), st.data(), td.data(), &got);
+    if (rc) return rc;
+    for (int i = 0; i < got; ++i) {
+      const uint64_t id = ids[i];
+      t_done[id] = td[i] - base;
+      for (int j = 0; j < 4; ++j) u0s[4 * id + j] = u[4 * i + j];
+      status[id] = st[i];
+      ++finished;
+    }
+    if (got == 0 && next < n && t_arrival[next] - (s->now() - base) > 200e-6)
+      std::this_thread::sleep_for(std::chrono::microseconds(50));
+  }
+  return MPPI_OK;
+}
+
+extern "C" int mppi_server_stats_get(mppi_server *s, mppi_server_stats *o) {
+  int rc = check_srv(s);
+  if (rc) return rc;
+  if (!o) return fail(MPPI_EINVAL, "out is NULL");
+  std::lock_guard<std::mutex> lk(s->mu);
+  o->bytes_used = s->used;
+  o->slots_used = 0;
+  for (auto &S : s->slots) o->slots_used += S.used ? 1 : 0;
+  o->queued = s->queued;
+  o->inflight = s->inflight;
+  o->requests_done = s->n_done;
+  o->batches = s->n_batches;
+  o->mean_batch = s->n_batches ? (double)s->n_batched_req / (double)s->n_batches : 0.0;
+  o->rollout_steps_done = s->steps_done;
+  return MPPI_OK;
+}
+
+extern "C" int mppi_server_get_controls(mppi_server *s, int32_t slot, double *u, uint64_t len) {
+  int rc = check_srv(s);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (slot < 0 || slot >= (int)s->slots.size() || !s->slots[slot].used) return fail(MPPI_ENOTFOUND, "unknown slot %d", slot);
+  Slot &S = s->slots[slot];
+  if (S.busy) return fail(MPPI_EBUSY, "slot %d has a step in flight", slot);
+  return mppi_get_controls(S.ctx, u, len);
+}
+
+extern "C" double mppi_server_now(mppi_server *s) { return s ? s->now() : 0.0; }

@@ -76,14 +76,18 @@ def test_closed_loop_cartpole_per_step():
     wl = W.cartpole(nu=2.0).replace(seed=1)
     x = wl.x0.copy()
     worst = 0.0
+    conditioned = 0
     with controller(wl) as c:
         for step in range(wl.control_steps):
             U_before = c.get_controls()
             m = one_step(wl, c, x, U_before, step)
             assert_parity(m)
             worst = max(worst, m["U_err"])
+            conditioned += m["U_err"] > 1e-4
             x = mppi.plant_step(wl, x, m["u0_gpu"])
-    print("closed-loop worst U_err", worst, "final x", x)
+    print("closed-loop worst U_err", worst, "steps beyond 1e-4 (explained to first order):", conditioned,
+          "final x", x)
+    assert conditioned <= 20
     assert abs(x[2]) < 0.2
 
 

@@ -1,0 +1,125 @@
+"""Serving (continuous batching) on the GPU through the C ABI:
+
+* a controller's results are bitwise the same alone (its own context) and in a batch
+  with other controllers of other systems and sizes, and under the plain policy;
+* served steps match the FP64 oracle to the parity tolerances;
+* admission respects the HBM budget and slots free up on release;
+* a real-time replay of a Poisson trace completes every request in per-controller order.
+"""
+import numpy as np
+import pytest
+
+import paper_1509_01149_amd as P
+import workloads as W
+from oracle import mppi
+from tests._parity import TOL_U
+
+pytestmark = pytest.mark.gpu
+
+
+def mix():
+    return [
+        W.cartpole(nu=2.0).replace(seed=21),
+        W.bicycle(K=2048, T=50).replace(seed=22),
+        W.quadrotor(nu=1.0, K=512, T=200).replace(seed=23),
+        W.quadrotor(nu=4.0, K=8192, T=100).replace(seed=24),
+        W.linear_double_integrator(K=300, R=0.3).replace(seed=25),
+        W.bicycle().replace(seed=26),
+        W.cartpole(nu=1.0, K=257, T=7).replace(seed=27),
+        W.quadrotor(nu=2.0, K=16384, T=50).replace(seed=28),
+    ]
+
+
+def serve_rounds(srv, wls, rounds):
+    slots = [srv.admit(**P.controller_args(wl)) for wl in wls]
+    out = {s: [] for s in slots}
+    rid = 0
+    for r in range(rounds):
+        owner = {}
+        for s, wl in zip(slots, wls):
+            srv.submit(s, wl.x0, rid)
+            owner[rid] = s
+            rid += 1
+        got = 0
+        while got < len(slots):
+            ids, u0, st, td = srv.poll()
+            for i, u in zip(ids, u0):
+                out[owner[int(i)]].append(u.copy())
+            got += len(ids)
+    finals = [srv.get_controls(s) for s in slots]
+    return [np.array(out[s]) for s in slots], finals
+
+
+def alone(wl, rounds):
+    with P.controller_for(wl) as c:
+        us = [np.pad(c.step(wl.x0), (0, 4 - wl.m)) for _ in range(rounds)]
+        return np.array(us), c.get_controls()
+
+
+def test_alone_equals_mix_and_plain():
+    wls = mix()
+    with P.Server(max_slots=16, max_inflight=3) as srv:
+        mixed, mixed_U = serve_rounds(srv, wls, 3)
+        st = srv.stats()
+        assert st["requests_done"] == 3 * len(wls) and st["mean_batch"] > 1
+    with P.Server(max_slots=16, mode=P.SERVE_PLAIN) as srv:
+        plain, plain_U = serve_rounds(srv, wls, 3)
+    for j, wl in enumerate(wls):
+        u_alone, U_alone = alone(wl, 3)
+        assert np.array_equal(mixed[j], u_alone), wl.name
+        assert np.array_equal(mixed_U[j], U_alone), wl.name
+        assert np.array_equal(plain[j], u_alone), wl.name
+        assert np.array_equal(plain_U[j], U_alone), wl.name
+
+
+def test_served_steps_match_oracle():
+    wls = [W.bicycle(K=4096, T=100).replace(seed=31), W.cartpole(nu=2.0).replace(seed=32),
+           W.quadrotor(nu=2.0, K=4096, T=100).replace(seed=33)]
+    with P.Server(max_slots=4) as srv:
+        u, U = serve_rounds(srv, wls, 1)
+    for j, wl in enumerate(wls):
+        u0_r, U_r, _, _ = mppi.control_step(wl, wl.x0, mppi.initial_sequence(wl), 0)
+        scale = max(1.0, float(np.max(np.abs(U_r))))
+        assert np.max(np.abs(u[j][0][:wl.m] - u0_r)) / scale <= TOL_U
+        assert np.max(np.abs(U[j] - U_r)) / scale <= TOL_U
+
+
+def test_admission_respects_the_budget():
+    wl = W.quadrotor(K=4096, T=100)
+    with P.Controller(**P.controller_args(wl)) as c:
+        pass
+    import ctypes as C
+    cfg, keep = P.binding.make_config(**P.controller_args(wl))
+    need = C.c_uint64(0)
+    P.binding.check(P.load().mppi_workspace_bytes(C.byref(cfg), C.byref(need)))
+    with P.Server(max_slots=8, hbm_budget_bytes=int(2.5 * need.value)) as srv:
+        a = srv.admit(**P.controller_args(wl))
+        b = srv.admit(**P.controller_args(wl))
+        with pytest.raises(P.MppiError) as e:
+            srv.admit(**P.controller_args(wl))
+        assert e.value.code == P.binding.EBUSY
+        assert srv.stats()["bytes_used"] == 2 * need.value
+        srv.submit(a, wl.x0, 7)
+        with pytest.raises(P.MppiError):
+            srv.release(a)                    # a step is queued or in flight
+        while len(srv.poll()[0]) == 0:
+            pass
+        srv.release(a)
+        c = srv.admit(**P.controller_args(wl))
+        assert srv.stats()["slots_used"] == 2 and c != b
+
+
+def test_realtime_replay_of_a_poisson_trace():
+    wls = [w.replace(seed=40 + i) for i, w in enumerate(mix()[:6])]
+    trace = W.poisson_arrivals(len(wls), rate_hz=50.0, duration_s=0.6)
+    t = np.array([a for a, _ in trace])
+    sl_idx = np.array([c for _, c in trace])
+    with P.Server(max_slots=8, max_inflight=3) as srv:
+        slots = np.array([srv.admit(**P.controller_args(wl)) for wl in wls])
+        x0s = [np.pad(wls[c].x0, (0, 16 - wls[c].n)) for c in sl_idx]
+        td, u0, st = srv.replay(t, slots[sl_idx], x0s)
+    assert np.all(st == 0) and np.all(td >= t)
+    for c, wl in enumerate(wls):
+        mine = np.where(sl_idx == c)[0]
+        u_alone, _ = alone(wl, len(mine))
+        assert np.array_equal(u0[mine], u_alone)
