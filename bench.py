@@ -49,6 +49,60 @@ def make_workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
+def serving_mix_workloads(n_controllers):
+    import workloads as W
+    out = []
+    for i, (sysid, K, T) in enumerate(W.serving_mix(n_controllers)):
+        if sysid == 0:
+            wl = W.cartpole(nu=2.0, K=K, T=T)
+        elif sysid == 1:
+            wl = W.bicycle(K=K, T=T)
+        else:
+            wl = W.quadrotor(nu=2.0, K=K, T=T)
+        out.append(wl.replace(seed=1000 + i))
+    return out
+
+
+def serving_bench(seconds, plain_seconds, n_controllers=256, rate_hz=50.0, inflight=3):
+    """Replay the same Poisson trace (rate_hz per controller) through the batched server
+    and through the plain one-controller-at-a-time policy; report latency percentiles and
+    aggregate rollout-steps/s."""
+    import workloads as W
+    import paper_1509_01149_amd as P
+    wls = serving_mix_workloads(n_controllers)
+    trace = W.poisson_arrivals(n_controllers, rate_hz, max(seconds, plain_seconds))
+    res = dict(controllers=n_controllers, rate_hz_per_controller=rate_hz,
+               offered_requests_per_s=n_controllers * rate_hz,
+               offered_rollout_steps_per_s=rate_hz * sum(w.K * w.T for w in wls))
+    for mode, dur in (("batched", seconds), ("plain", plain_seconds)):
+        if dur <= 0:
+            continue
+        ev = [(t, c) for t, c in trace if t < dur]
+        t = np.array([a for a, _ in ev])
+        ci = np.array([c for _, c in ev])
+        kw = dict(max_slots=n_controllers, max_inflight=inflight, max_batch=n_controllers,
+                  mode=P.SERVE_BATCHED if mode == "batched" else P.SERVE_PLAIN, hbm_budget_bytes=64 << 30)
+        with P.Server(**kw) as srv:
+            slots = np.array([srv.admit(**P.controller_args(wl)) for wl in wls])
+            # warm up: one request per controller, not timed
+            srv.replay(np.zeros(n_controllers), slots, [np.pad(w.x0, (0, 16 - w.n)) for w in wls])
+            st0 = srv.stats()
+            x0s = [np.pad(wls[c].x0, (0, 16 - wls[c].n)) for c in ci]
+            td, u0, status = srv.replay(t, slots[ci], x0s)
+            st1 = srv.stats()
+        lat = (td - t) * 1e3
+        span = float(td.max())
+        steps = float(sum(wls[c].K * wls[c].T for c in ci))
+        res[mode] = dict(trace_seconds=dur, requests=int(t.size), p50_ms=round(float(np.percentile(lat, 50)), 3),
+                         p99_ms=round(float(np.percentile(lat, 99)), 3), max_ms=round(float(lat.max()), 3),
+                         mean_ms=round(float(lat.mean()), 3), completion_span_s=round(span, 3),
+                         rollout_steps_per_s=round(steps / span, 1), requests_per_s=round(t.size / span, 1),
+                         mean_batch=round((st1["batches"] and (st1["requests_done"] - st0["requests_done"]) /
+                                           max(1, st1["batches"] - st0["batches"])), 2),
+                         numeric_failures=int(np.sum(status != 0)))
+    return res
+
+
 def cpu_baseline(wl, seconds):
     """The FP64 oracle, as it stands, on a bounded closed-loop sample of the workload."""
     from oracle import mppi
@@ -76,6 +130,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--serving-seconds", type=float, default=2.0,
+                    help="length of the batched serving trace (0 disables the serving leg)")
+    ap.add_argument("--plain-seconds", type=float, default=1.0,
+                    help="length of the same trace replayed one controller at a time")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: the MPPI path shards over samples with one small "
@@ -150,6 +208,8 @@ def main():
                mppi_iters_per_s=round(1e3 / ms_per_step, 1), roofline=roofline)
     if parity is not None:
         out["parity"] = parity
+    if args.serving_seconds > 0:
+        out["serving"] = serving_bench(args.serving_seconds, args.plain_seconds)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
         out["cpu_baseline"]["value"] = round(out["cpu_baseline"]["value"], 1)
