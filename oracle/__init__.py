@@ -11,4 +11,4 @@ Everything is written for readability against the paper, not speed: FP64 NumPy,
 vectorised over the K samples, a Python loop over time.  Each function names the
 section / equation / algorithm of the paper it follows.
 """
-from . import philox, noise, systems, mppi, lqr  # noqa: F401
+from . import philox, noise, systems, mppi, lqr, mlp  # noqa: F401

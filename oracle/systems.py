@@ -13,7 +13,10 @@ import numpy as np
 
 
 def euler_step(system, x, v, dt):
-    """Algorithm 1's transition: x + (f(x) + G(x) v) dt."""
+    """Algorithm 1's transition: x + (f(x) + G(x) v) dt.  A system with its own discrete
+    ``step`` (the learned one-step model) uses that instead."""
+    if hasattr(system, "step"):
+        return system.step(x, v, dt)
     return x + dt * system.xdot(x, v)
 
 

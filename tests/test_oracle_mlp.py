@@ -1,0 +1,121 @@
+"""Pins of the oracle's learned-dynamics MLP (CPU only), against independent
+implementations: torch's CPU bfloat16 conversion, torch autograd for the gradients,
+torch.optim.Adam for the optimiser, and central finite differences."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import mlp
+
+
+def _net(seed=5):
+    w = W.mlp_init_weights(seed)
+    rng = np.random.default_rng(seed)
+    b1, b2, b3 = (0.1 * rng.standard_normal(n) for n in (128, 128, 12))
+    return mlp.Net(w["W1"], b1, w["W2"], b2, w["W3"], b3, rng.standard_normal(16), rng.uniform(0.5, 2, 16),
+                   rng.standard_normal(12), rng.uniform(0.1, 1, 12))
+
+
+def test_bf16_round_matches_torch():
+    rng = np.random.default_rng(0)
+    x = np.concatenate([rng.standard_normal(10000) * 10.0 ** rng.integers(-5, 5, 10000),
+                        [1.0, 1.0 + 2 ** -8, 1.0 + 3 * 2 ** -8, -2.5, 0.0, 65504.0]])
+    ref = torch.tensor(x, dtype=torch.float32).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(mlp.bf16_round(x), ref)
+
+
+def _torch_forward(net, zn, bf16):
+    t = lambda a: torch.tensor(a, dtype=torch.float64)
+    r = (lambda a: a.to(torch.float32).to(torch.bfloat16).to(torch.float64)) if bf16 else (lambda a: a)
+    W1, b1, W2, b2, W3, b3 = (t(p).requires_grad_(True) for p in net.params())
+    h1 = torch.tanh(r(t(zn)) @ r(W1).T + b1)
+    h2 = torch.tanh(r(h1) @ r(W2).T + b2)
+    y = r(h2) @ r(W3).T + b3
+    return y, [W1, b1, W2, b2, W3, b3]
+
+
+def test_forward_matches_torch():
+    net = _net()
+    zn = np.random.default_rng(1).standard_normal((64, 16))
+    for bf16 in (False, True):
+        y, _ = mlp.forward_normalised(net, zn, bf16)
+        yt, _ = _torch_forward(net, zn, bf16)
+        assert np.allclose(y, yt.detach().numpy(), rtol=1e-12, atol=1e-12)
+
+
+def test_gradients_match_autograd_and_finite_differences():
+    net = _net()
+    rng = np.random.default_rng(2)
+    zn, tn = rng.standard_normal((32, 16)), rng.standard_normal((32, 12))
+    loss, g = mlp.loss_and_grads(net, zn, tn)
+    y, ps = _torch_forward(net, zn, False)
+    lt = torch.mean((y - torch.tensor(tn)) ** 2)
+    lt.backward()
+    assert loss == pytest.approx(lt.item(), rel=1e-13)
+    for gi, p in zip(g, ps):
+        assert np.allclose(gi, p.grad.numpy(), rtol=1e-10, atol=1e-14)
+    # central differences on a few entries of every parameter
+    h = 1e-6
+    for pi, p in enumerate(net.params()):
+        flat = p.reshape(-1)
+        for idx in rng.choice(flat.size, 4, replace=False):
+            old = flat[idx]
+            flat[idx] = old + h
+            lp, _ = mlp.loss_and_grads(net, zn, tn)
+            flat[idx] = old - h
+            lm, _ = mlp.loss_and_grads(net, zn, tn)
+            flat[idx] = old
+            assert (lp - lm) / (2 * h) == pytest.approx(g[pi].reshape(-1)[idx], rel=1e-5, abs=1e-10)
+
+
+def test_adam_matches_torch():
+    net = _net()
+    rng = np.random.default_rng(3)
+    ref = [torch.tensor(p.copy(), requires_grad=True) for p in net.params()]
+    opt_t = torch.optim.Adam(ref, lr=1e-3, betas=(0.9, 0.999), eps=1e-8)
+    opt = mlp.Adam(net, lr=1e-3)
+    for _ in range(5):
+        grads = [rng.standard_normal(p.shape) for p in net.params()]
+        opt.step(net, grads)
+        for r, gr in zip(ref, grads):
+            r.grad = torch.tensor(gr)
+        opt_t.step()
+    for p, r in zip(net.params(), ref):
+        assert np.allclose(p, r.detach().numpy(), rtol=1e-12, atol=1e-14)
+
+
+def test_targets_are_one_euler_step():
+    wl = W.quadrotor()
+    x, u = W.mlp_training_inputs(100)
+    from oracle import systems
+    d = mlp.transitions(wl, x, u)
+    assert np.allclose(d, wl.dt * systems.Quadrotor(wl.params).xdot(x, u), rtol=1e-13, atol=1e-16)
+
+
+def test_training_reduces_the_loss():
+    wl = W.quadrotor()
+    x, u = W.mlp_training_inputs(20000)
+    d = mlp.transitions(wl, x, u)
+    z = np.concatenate([x, u], 1)
+    mi, si, mo, so = mlp.standardisation(z, d)
+    w = W.mlp_init_weights()
+    net = mlp.Net(w["W1"], w["b1"], w["W2"], w["b2"], w["W3"], w["b3"], mi, si, mo, so)
+    zn, tn = (z - mi) / si, (d - mo) / so
+    l0, _ = mlp.loss_and_grads(net, zn, tn)
+    opt = mlp.Adam(net, lr=2e-3)
+    for ep, order in enumerate(W.minibatch_order(20000, 3)):
+        for s in range(0, 20000, 1000):
+            _, g = mlp.loss_and_grads(net, zn[order[s:s + 1000]], tn[order[s:s + 1000]], bf16=True)
+            opt.step(net, g)
+    l1, _ = mlp.loss_and_grads(net, zn, tn)
+    assert l1 < 0.25 * l0
+
+
+def test_learned_step_replaces_euler():
+    net = _net()
+    wl = W.quadrotor()
+    sysm = mlp.QuadrotorMLP(wl.params, net, bf16=False)
+    x, u = W.mlp_training_inputs(10)
+    from oracle import systems
+    assert np.allclose(systems.euler_step(sysm, x, u, wl.dt), x + mlp.predict_delta(net, x, u), rtol=1e-14)

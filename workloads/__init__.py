@@ -218,6 +218,27 @@ def mlp_training_inputs(n: int = 1_000_000, seed: int = SEED_MLP_DATA, control_s
     return x, u
 
 
+def mlp_init_weights(seed: int = SEED_MLP_INIT, hidden: int = 128, n_in: int = 16, n_out: int = 12):
+    """Initial MLP weights (Glorot & Bengio 2010 uniform, zero biases): W1 (h, n_in),
+    W2 (h, h), W3 (n_out, h); FP32 values, returned as float64 arrays."""
+    rng = np.random.default_rng(seed)
+
+    def glorot(fan_out, fan_in):
+        a = math.sqrt(6.0 / (fan_in + fan_out))
+        return rng.uniform(-a, a, (fan_out, fan_in)).astype(np.float32).astype(np.float64)
+
+    W1 = glorot(hidden, n_in)
+    W2 = glorot(hidden, hidden)
+    W3 = glorot(n_out, hidden)
+    return dict(W1=W1, b1=np.zeros(hidden), W2=W2, b2=np.zeros(hidden), W3=W3, b3=np.zeros(n_out))
+
+
+def minibatch_order(n: int, epochs: int, seed: int = SEED_MLP_DATA + 1):
+    """Sample order of each training epoch (a seeded permutation per epoch)."""
+    rng = np.random.default_rng(seed)
+    return [rng.permutation(n) for _ in range(epochs)]
+
+
 # --------------------------------------------------------------------- serving trace
 
 def serving_mix(n_controllers: int = 256, seed: int = SEED_SERVING):
