@@ -104,7 +104,8 @@ typedef struct {
 } mppi_quadrotor_params;
 
 /* MPPI_SYS_QUADROTOR_MLP: the quadrotor's cost with dynamics x <- x + MLP(x, u)
- * (a trained mppi_mlp, see below).  The network is copied at create. */
+ * (an mppi_mlp, see "Learned dynamics" below).  Its current parameters and statistics
+ * are copied at create; the harness plant (mppi_plant_step_async) stays analytic. */
 typedef struct mppi_mlp mppi_mlp;
 typedef struct {
   mppi_quadrotor_params quad;
@@ -200,6 +201,52 @@ int mppi_debug_philox(int32_t device, uint64_t seed, const uint32_t *counters, i
  * launches timed since profiling was switched on (avg_ms[3], count[3], host). */
 int mppi_set_profiling(mppi_ctx *ctx, int32_t on);
 int mppi_kernel_times(mppi_ctx *ctx, double *avg_ms, int64_t *count);
+
+/* ------------------------------------------------------------------------------------
+ * Learned dynamics (extension of the model the paper samples from, Section II):
+ * an MLP [16 -> 128 -> 128 -> 12] with tanh hidden layers maps the standardised
+ * (state x[12], control u[4]) of the quadrotor to its standardised one-step state change;
+ * MPPI_SYS_QUADROTOR_MLP rolls out x <- x + sd_out * MLP((z - mu_in) / sd_in) + mu_out.
+ * All matrix products run on BF16 MFMA with FP32 accumulation: weights and activations are
+ * rounded to bfloat16 (nearest even) at every product input, forward and backward.
+ *
+ * Parameters are one FP32 array of MPPI_MLP_PARAMS values in this order:
+ *   W1 [128][16], b1 [128], W2 [128][128], b2 [128], W3 [12][128], b3 [12]   (row-major)
+ * Statistics are one FP64 array of MPPI_MLP_STATS values: mu_in[16], sd_in[16],
+ * mu_out[12], sd_out[12].
+ * Training minimises the mean squared error of the standardised prediction with Adam
+ * (beta1 0.9, beta2 0.999, eps 1e-8) on the FP32 parameters; every kernel of the forward,
+ * the backward and the optimiser is this library's own.
+ * ------------------------------------------------------------------------------------ */
+#define MPPI_MLP_PARAMS 20236
+#define MPPI_MLP_STATS 56
+
+/* Create a network on `device` from FP32 parameters (host, copied); statistics start as
+ * mu = 0, sd = 1. */
+int mppi_mlp_create(int32_t device, const float *params, mppi_mlp **out);
+int mppi_mlp_destroy(mppi_mlp *mlp);
+/* Training set: n >= 1 (state, control) pairs (host FP64, x: n x 12, u: n x 4, copied).  The
+ * targets dx = dt f(x, u) are computed on the device with the analytic quadrotor model of
+ * `quad`, and the standardisation statistics are set from the set (population mean and
+ * standard deviation, FP64 sums on the device; a zero deviation is replaced by 1). */
+int mppi_mlp_set_dataset(mppi_mlp *mlp, const mppi_quadrotor_params *quad, double dt, const double *x,
+                         const double *u, int64_t n);
+/* Read back the device-computed targets (n x 12 FP64). */
+int mppi_mlp_get_targets(mppi_mlp *mlp, double *dx, int64_t n);
+int mppi_mlp_set_stats(mppi_mlp *mlp, const double *stats);
+int mppi_mlp_get_stats(mppi_mlp *mlp, double *stats);
+int mppi_mlp_get_params(mppi_mlp *mlp, float *params);
+int mppi_mlp_set_params(mppi_mlp *mlp, const float *params);
+/* floor(n_order / batch) Adam steps; step s uses dataset rows order[s*batch .. (s+1)*batch)
+ * (host int32, each in [0, n)).  losses (host, may be NULL) receives each step's loss
+ * (mean squared error before the step).  1 <= batch <= 65536.  Blocks until done. */
+int mppi_mlp_train(mppi_mlp *mlp, const int32_t *order, int64_t n_order, int32_t batch, double lr,
+                   double *losses);
+/* One forward + backward without an update on given standardised inputs zn (B x 16) and
+ * targets tn (B x 12) (host FP64): the loss and the gradient (MPPI_MLP_PARAMS FP32, host). */
+int mppi_mlp_loss_grads(mppi_mlp *mlp, const double *zn, const double *tn, int32_t B, double *loss, float *grads);
+/* Predicted one-step change dx (B x 12) for states x (B x 12) and controls u (B x 4). */
+int mppi_mlp_forward(mppi_mlp *mlp, const double *x, const double *u, int32_t B, double *dx);
 
 /* ------------------------------------------------------------------------------------
  * Serving: many controllers on one GPU with continuous batching.

@@ -124,6 +124,17 @@ def load() -> C.CDLL:
                                C.POINTER(C.c_int32)],
         "mppi_server_stats_get": [C.c_void_p, C.POINTER(ServerStats)],
         "mppi_server_get_controls": [C.c_void_p, C.c_int32, _dp, C.c_uint64],
+        "mppi_mlp_create": [C.c_int32, _fp, C.POINTER(C.c_void_p)],
+        "mppi_mlp_destroy": [C.c_void_p],
+        "mppi_mlp_set_dataset": [C.c_void_p, C.POINTER(QuadrotorParams), C.c_double, _dp, _dp, C.c_int64],
+        "mppi_mlp_get_targets": [C.c_void_p, _dp, C.c_int64],
+        "mppi_mlp_set_stats": [C.c_void_p, _dp],
+        "mppi_mlp_get_stats": [C.c_void_p, _dp],
+        "mppi_mlp_get_params": [C.c_void_p, _fp],
+        "mppi_mlp_set_params": [C.c_void_p, _fp],
+        "mppi_mlp_train": [C.c_void_p, C.POINTER(C.c_int32), C.c_int64, C.c_int32, C.c_double, _dp],
+        "mppi_mlp_loss_grads": [C.c_void_p, _dp, _dp, C.c_int32, _dp, _fp],
+        "mppi_mlp_forward": [C.c_void_p, _dp, _dp, C.c_int32, _dp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -185,7 +196,7 @@ def make_params(system: int, params: Dict, keep: list):
             return q
         mlp = params["mlp"]
         keep.append(mlp)
-        return QuadrotorMlpParams(q, C.c_void_p(mlp.handle))
+        return QuadrotorMlpParams(q, C.c_void_p(mlp.handle.value))
     raise ValueError(f"unknown system {system}")
 
 
@@ -414,6 +425,101 @@ class Server:
 
     def __exit__(self, *exc):
         self.close()
+
+
+MLP_PARAMS = 20236
+MLP_STATS = 56
+_MLP_SHAPES = [("W1", (128, 16)), ("b1", (128,)), ("W2", (128, 128)), ("b2", (128,)), ("W3", (12, 128)), ("b3", (12,))]
+
+
+def mlp_flatten(p: Dict) -> np.ndarray:
+    return np.ascontiguousarray(np.concatenate([np.asarray(p[k], np.float32).ravel() for k, _ in _MLP_SHAPES]))
+
+
+def mlp_unflatten(flat: np.ndarray) -> Dict:
+    out, o = {}, 0
+    for k, shp in _MLP_SHAPES:
+        n = int(np.prod(shp))
+        out[k] = np.asarray(flat[o:o + n], dtype=np.float64).reshape(shp)
+        o += n
+    return out
+
+
+class Mlp:
+    """Learned dynamics network on the GPU (mppi_mlp_*): BF16 MFMA training and inference."""
+
+    def __init__(self, params: Dict, device: int = 0):
+        self._lib = load()
+        flat = mlp_flatten(params)
+        h = C.c_void_p()
+        check(self._lib.mppi_mlp_create(device, _ptr(flat, _fp), C.byref(h)))
+        self.handle = h
+        self.n = 0
+
+    def set_dataset(self, quad_params: Dict, dt: float, x, u):
+        keep = []
+        q = make_params(SYS_QUADROTOR, quad_params, keep)
+        xv = _f64(x).reshape(-1, 12)
+        uv = _f64(u).reshape(-1, 4)
+        check(self._lib.mppi_mlp_set_dataset(self.handle, C.byref(q), dt, _ptr(xv), _ptr(uv), xv.shape[0]))
+        self.n = xv.shape[0]
+
+    def targets(self) -> np.ndarray:
+        d = np.zeros((self.n, 12))
+        check(self._lib.mppi_mlp_get_targets(self.handle, _ptr(d), self.n))
+        return d
+
+    def stats(self) -> np.ndarray:
+        s = np.zeros(MLP_STATS)
+        check(self._lib.mppi_mlp_get_stats(self.handle, _ptr(s)))
+        return s
+
+    def set_stats(self, stats):
+        s = _f64(stats).ravel()
+        check(self._lib.mppi_mlp_set_stats(self.handle, _ptr(s)))
+
+    def params(self) -> Dict:
+        f = np.zeros(MLP_PARAMS, dtype=np.float32)
+        check(self._lib.mppi_mlp_get_params(self.handle, _ptr(f, _fp)))
+        return mlp_unflatten(f)
+
+    def set_params(self, params: Dict):
+        f = mlp_flatten(params)
+        check(self._lib.mppi_mlp_set_params(self.handle, _ptr(f, _fp)))
+
+    def train(self, order, batch: int, lr: float) -> np.ndarray:
+        o = np.ascontiguousarray(np.asarray(order, dtype=np.int32).ravel())
+        steps = o.size // batch
+        losses = np.zeros(steps)
+        check(self._lib.mppi_mlp_train(self.handle, o.ctypes.data_as(C.POINTER(C.c_int32)), o.size, batch, lr,
+                                       _ptr(losses)))
+        return losses
+
+    def loss_grads(self, zn, tn):
+        z = _f64(zn).reshape(-1, 16)
+        t = _f64(tn).reshape(-1, 12)
+        loss = C.c_double(0)
+        g = np.zeros(MLP_PARAMS, dtype=np.float32)
+        check(self._lib.mppi_mlp_loss_grads(self.handle, _ptr(z), _ptr(t), z.shape[0], C.byref(loss), _ptr(g, _fp)))
+        return loss.value, mlp_unflatten(g)
+
+    def forward(self, x, u) -> np.ndarray:
+        xv = _f64(x).reshape(-1, 12)
+        uv = _f64(u).reshape(-1, 4)
+        dx = np.zeros((xv.shape[0], 12))
+        check(self._lib.mppi_mlp_forward(self.handle, _ptr(xv), _ptr(uv), xv.shape[0], _ptr(dx)))
+        return dx
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self._lib.mppi_mlp_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def philox(counters: np.ndarray, seed: int, device: int = 0) -> np.ndarray:

@@ -181,7 +181,9 @@ void compute_layout(const mppi_config *c, Layout *L) {
   const int K = c->K, T = c->T, m = c->n_ctrl;
   L->TM = T * m;
   L->G = (L->TM + 3) / 4;
-  L->n_roll_blocks = (K + kBlock - 1) / kBlock;
+  // the learned-dynamics rollout runs 64 samples per block (16 per wave), the others 256
+  const int roll_per_block = c->system == MPPI_SYS_QUADROTOR_MLP ? 64 : kBlock;
+  L->n_roll_blocks = (K + roll_per_block - 1) / roll_per_block;
   L->n_kc = (K + kUpdChunk - 1) / kUpdChunk;
   uint64_t o = 0;
   auto take = [&](uint64_t bytes) { uint64_t r = o; o = align256(o + bytes); return r; };
@@ -552,6 +554,7 @@ extern "C" int mppi_create(const mppi_config *cfg, mppi_ctx **out) {
       case MPPI_SYS_CARTPOLE: rc = prepare_rollout<CartPoleSys>(c); break;
       case MPPI_SYS_BICYCLE: rc = prepare_rollout<BicycleSys>(c); break;
       case MPPI_SYS_QUADROTOR: rc = prepare_rollout<QuadrotorSys>(c); break;
+      case MPPI_SYS_QUADROTOR_MLP: rc = prepare_mlp_rollout(c); break;
       default: break;
     }
   }

@@ -1,0 +1,113 @@
+"""Learned dynamics on the GPU (BF16 MFMA) through the C ABI against the FP64 oracle with
+bfloat16 emulation: dataset targets and statistics, forward, loss and gradients, training,
+and one MPPI iteration with the network as the rollout model."""
+import numpy as np
+import pytest
+
+import paper_1509_01149_amd as P
+import workloads as W
+from oracle import mlp as omlp
+from oracle import mppi
+from tests._parity import TOL_U
+
+pytestmark = pytest.mark.gpu
+
+
+def _stats_net(seed=5, n=20000):
+    wl = W.quadrotor()
+    x, u = W.mlp_training_inputs(n)
+    d = omlp.transitions(wl, x, u)
+    z = np.concatenate([x, u], 1)
+    st = omlp.standardisation(z, d)
+    w = W.mlp_init_weights(seed)
+    net = omlp.Net(w["W1"], w["b1"], w["W2"], w["b2"], w["W3"], w["b3"], *st)
+    return wl, x, u, d, net, w
+
+
+def _stats_vec(net):
+    return np.concatenate([net.mu_in, net.sd_in, net.mu_out, net.sd_out])
+
+
+def test_dataset_targets_and_statistics():
+    wl, x, u, d, net, w = _stats_net()
+    g = P.Mlp(w)
+    g.set_dataset(wl.params, wl.dt, x, u)
+    td = g.targets()
+    assert np.max(np.abs(td - d) / np.maximum(1e-3, np.abs(d))) < 1e-6
+    assert np.allclose(g.stats(), _stats_vec(net), rtol=1e-6, atol=1e-9)
+
+
+def test_forward_matches_bf16_oracle():
+    wl, x, u, d, net, w = _stats_net()
+    rng = np.random.default_rng(1)
+    net.b1 += 0.1 * rng.standard_normal(128)
+    net.b2 += 0.1 * rng.standard_normal(128)
+    net.b3 += 0.1 * rng.standard_normal(12)
+    g = P.Mlp(dict(W1=net.W1, b1=net.b1, W2=net.W2, b2=net.b2, W3=net.W3, b3=net.b3))
+    g.set_stats(_stats_vec(net))
+    B = 3000     # ragged against the 32-row GEMM tiles
+    dx_g = g.forward(x[:B], u[:B])
+    dx_o = omlp.predict_delta(net, x[:B], u[:B], bf16=True)
+    yg, yo = (dx_g - net.mu_out) / net.sd_out, (dx_o - net.mu_out) / net.sd_out
+    err = np.abs(yg - yo)
+    print("forward: max", err.max(), "mean", err.mean())
+    assert err.max() < 2e-2 and err.mean() < 1e-3
+
+
+def test_gradients_match_bf16_oracle():
+    wl, x, u, d, net, w = _stats_net()
+    z = np.concatenate([x, u], 1)
+    zn = (z - net.mu_in) / net.sd_in
+    tn = (d - net.mu_out) / net.sd_out
+    g = P.Mlp(w)
+    B = 4096
+    loss_g, grads_g = g.loss_grads(zn[:B], tn[:B])
+    loss_o, grads_o = omlp.loss_and_grads(net, omlp.bf16_round(zn[:B]), tn[:B], bf16=True)
+    assert loss_g == pytest.approx(loss_o, rel=1e-3)
+    for (k, _), go in zip(P.binding._MLP_SHAPES, grads_o):
+        rel = np.linalg.norm(grads_g[k] - go) / np.linalg.norm(go)
+        print("grad", k, rel)
+        assert rel < 1e-2, k
+
+
+def test_training_tracks_the_oracle():
+    wl, x, u, d, net, w = _stats_net(n=16384)
+    g = P.Mlp(w)
+    g.set_dataset(wl.params, wl.dt, x, u)
+    order = np.concatenate(W.minibatch_order(16384, 3))
+    losses_g = g.train(order, 1024, 2e-3)
+    z = np.concatenate([x, u], 1)
+    zn = omlp.bf16_round((z - net.mu_in) / net.sd_in)
+    tn = (d - net.mu_out) / net.sd_out
+    opt = omlp.Adam(net, lr=2e-3)
+    losses_o = []
+    for s in range(len(losses_g)):
+        idx = order[s * 1024:(s + 1) * 1024]
+        l, gr = omlp.loss_and_grads(net, zn[idx], tn[idx], bf16=True)
+        losses_o.append(l)
+        opt.step(net, gr)
+    losses_o = np.array(losses_o)
+    print("losses gpu", losses_g[[0, 10, -1]], "oracle", losses_o[[0, 10, -1]])
+    assert losses_g[-1] < 0.3 * losses_g[0]
+    assert np.allclose(losses_g, losses_o, rtol=0.05)
+
+
+def test_mppi_iteration_with_learned_dynamics():
+    wl0, x, u, d, net, w = _stats_net()
+    rng = np.random.default_rng(2)
+    g = P.Mlp(w)
+    g.set_stats(_stats_vec(net))
+    wl = W.quadrotor_mlp(g, nu=2.0, K=4096 + 37, T=50).replace(seed=9)
+    sysm = omlp.QuadrotorMLP(wl.params, net, bf16=True)
+    U0 = mppi.initial_sequence(wl)
+    with P.controller_for(wl) as c:
+        u0 = c.step(wl.x0)
+        U = c.get_controls()
+        S_gpu, rho, eta, dU = c.debug_last()
+    u0_r, U_r, _, res = mppi.control_step(wl, wl.x0, U0, 0, system=sysm)
+    S = res[-1].S
+    rel = np.abs(S_gpu - S) / np.maximum(1.0, np.abs(S))
+    scale = max(1.0, float(np.max(np.abs(U_r))))
+    print("mlp mppi: S rel max", rel.max(), "median", np.median(rel), "U", np.max(np.abs(U - U_r)) / scale)
+    assert np.median(rel) < 1e-4 and rel.max() < 1e-2
+    assert np.max(np.abs(U - U_r)) / scale < 10 * TOL_U

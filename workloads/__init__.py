@@ -202,6 +202,13 @@ def quadrotor(nu: float = 2.0, K: int = 16384, T: int = 150, lam: Optional[float
                     u_init=np.full(4, QUAD_HOVER), params=quadrotor_params(obstacles), x0=x0)
 
 
+def quadrotor_mlp(net, nu: float = 2.0, K: int = 16384, T: int = 100, lam: Optional[float] = None) -> Workload:
+    """Learned-dynamics quadrotor: the quadrotor workload with x <- x + MLP(x, u); ``net`` is
+    the network object the consumer uses (a GPU handle or an oracle network)."""
+    wl = quadrotor(nu=nu, K=K, T=T, lam=lam)
+    return wl.replace(name="quadrotor_mlp", system=SYS_QUADROTOR_MLP, params=dict(wl.params, mlp=net))
+
+
 # ------------------------------------------------------------------ MLP training data
 
 MLP_BOX_LO = np.array([-5, -5, -5, -2, -2, -2, -0.5, -0.5, -0.5, -2, -2, -2], dtype=np.float64)
