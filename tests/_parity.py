@@ -10,16 +10,18 @@ from oracle import mppi, systems
 #          plus twice the first-order effect of the (in-tolerance) cost differences,
 #          |(1/lambda) sum_k w_k (dS_k - <dS>_w) du_k|_inf / scale, which is only material when
 #          lambda is small against the cost scale on a chaotic system (cart-pole, lambda = 1)
-#   S      |S_gpu - S_orc| / max(1, |S_orc|) <= 1e-4 on every well-conditioned sample: FP32
+#   S      |S_gpu - S_orc| / max(1, |S_orc|) <= 4e-4 on every well-conditioned sample: FP32
 #          rounding (6e-8 per step) amplified by at most exp(4/s * 2 s) ~ 3e3 along the
-#          cart-pole's unstable upright manifold; <= 0.1 on quadrotor samples whose attitude
+#          cart-pole's unstable upright manifold gives ~1.8e-4 in the state and twice that in
+#          the quadratic cost (a correctly rounded FP32 emulation of the oracle reaches
+#          1.9e-4 over the 200-step cart-pole run); <= 0.1 on quadrotor samples whose attitude
 #          passes 1.2 rad (1/cos(pitch) of the Euler-angle rates is ill-conditioned there)
 #   impact sum_k w_k |dS_k - <dS>_w| / lambda: first-order change of the update in du units; must
 #          not exceed what the per-sample cost tolerance allows, 2 TOL_S max_w|S| / lambda
 #          (max over samples with weight >= 1e-9), nor 1e-3 when that is larger
 #   stage  the GPU's costs through the oracle's FP64 weights and update: <= 1e-5 relative
 TOL_U = 1e-4
-TOL_S = 1e-4
+TOL_S = 4e-4
 TOL_S_TUMBLE = 0.1
 TUMBLE_ANGLE = 1.2
 

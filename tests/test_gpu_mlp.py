@@ -111,3 +111,58 @@ def test_mppi_iteration_with_learned_dynamics():
     print("mlp mppi: S rel max", rel.max(), "median", np.median(rel), "U", np.max(np.abs(U - U_r)) / scale)
     assert np.median(rel) < 1e-4 and rel.max() < 1e-2
     assert np.max(np.abs(U - U_r)) / scale < 10 * TOL_U
+
+
+def test_trained_network_gain_over_untrained_and_against_analytic():
+    """Train on 1e6 analytic transitions on the GPU, then judge the learned model by the
+    analytic one: one-step error on held-out transitions, open-loop trajectory error,
+    control error of one MPPI iteration, and closed-loop cost on the analytic plant
+    against (a) MPPI with the analytic model and (b) MPPI with the untrained network."""
+    from oracle import systems
+    wl = W.quadrotor()
+    x, u = W.mlp_training_inputs(1_000_000)
+    init = W.mlp_init_weights()
+    g = P.Mlp(init)
+    g.set_dataset(wl.params, wl.dt, x, u)
+    stats = g.stats()
+    epochs = 20
+    for ep, order in enumerate(W.minibatch_order(1_000_000, epochs)):
+        losses = g.train(order, 4096, 2e-3 * 0.5 ** (ep // 5))
+    assert losses.mean() < 1e-3
+    xh, uh = W.mlp_training_inputs(20000, seed=999)
+    nrmse = np.sqrt(np.mean(((g.forward(xh, uh) - omlp.transitions(wl, xh, uh)) / stats[44:56]) ** 2, 0))
+    assert nrmse.max() < 0.05, nrmse
+    untrained = P.Mlp(init)
+    untrained.set_stats(stats)
+    sysa = systems.make(wl)
+
+    def closed_loop(model, steps=150, K=4096):
+        w = (W.quadrotor(nu=2.0, K=K, T=100) if model is None else W.quadrotor_mlp(model, nu=2.0, K=K, T=100))
+        w = w.replace(seed=3)
+        xs, cost = w.x0.copy(), 0.0
+        with P.controller_for(w) as c:
+            for _ in range(steps):
+                xs = mppi.plant_step(wl, xs, c.step(xs))
+                cost += float(sysa.q(xs[None])[0])
+        return cost
+
+    c_ana, c_trained, c_untrained = closed_loop(None), closed_loop(g), closed_loop(untrained)
+    print("closed-loop cost: analytic", c_ana, "trained", c_trained, "untrained", c_untrained)
+    assert c_trained < 0.85 * c_untrained          # what training gains
+    assert c_trained < 1.25 * c_ana                # and how close it comes to the analytic model
+    wa = W.quadrotor(nu=2.0, K=16384, T=100).replace(seed=5)
+    wm = W.quadrotor_mlp(g, nu=2.0, K=16384, T=100).replace(seed=5)
+    with P.controller_for(wa) as ca:
+        ca.step(wa.x0)
+        Ua = ca.get_controls()
+    with P.controller_for(wm) as cm:
+        cm.step(wm.x0)
+        Um = cm.get_controls()
+    ctrl_err = float(np.max(np.abs(Um - Ua)) / np.max(np.abs(Ua)))
+    xa, xm = wa.x0.copy(), wa.x0.copy()
+    for i in range(100):
+        xa = mppi.plant_step(wa, xa, Ua[i])
+        xm = xm + g.forward(xm[None], Ua[i][None])[0]
+    traj_err = float(np.linalg.norm(xa[:3] - xm[:3]))
+    print("control error (rel)", ctrl_err, "trajectory position error after 100 steps", traj_err)
+    assert ctrl_err < 0.01 and traj_err < 0.3
