@@ -31,6 +31,9 @@ METRIC = "rollout-steps/sec (K*T) and MPPI iters/sec; p50/p99 step latency batch
 # FP32/FP64 arithmetic op, transcendental and Philox integer op = 1).  Derivation in
 # DESIGN.md ("Roofline").
 ALG_OPS_PER_ROLLOUT_STEP = {"cartpole": 87, "bicycle": 164, "quadrotor": 740, "linear": 90}
+# MLP [16 -> 128 -> 128 -> 12]: 2 (16*128 + 128*128 + 128*12) FLOP per rollout-step on BF16 MFMA.
+MLP_FLOP_PER_ROLLOUT_STEP = 2 * (16 * 128 + 128 * 128 + 128 * 12)
+BF16_MFMA_PEAK_TFLOPS = 2500.0
 
 # VALU peak without packed FP32 (the build forbids v_pk_*_f32): 256 CUs x 4 SIMD x 16 lanes
 # x 2 (FMA) x 2.4 GHz.
@@ -46,7 +49,25 @@ def make_workload(name):
         return W.cartpole(nu=2.0).replace(seed=0)
     if name == "quadrotor":
         return W.quadrotor(nu=2.0).replace(seed=0)
+    if name == "quadrotor_mlp":
+        return W.quadrotor_mlp(trained_mlp(), nu=2.0, K=16384, T=100).replace(seed=0)
     raise SystemExit(f"unknown workload {name}")
+
+
+def trained_mlp(n=1_000_000, epochs=20):
+    """The learned-dynamics network, trained on the GPU on n analytic transitions."""
+    import workloads as W
+    import paper_1509_01149_amd as P
+    wl = W.quadrotor()
+    x, u = W.mlp_training_inputs(n)
+    g = P.Mlp(W.mlp_init_weights())
+    g.set_dataset(wl.params, wl.dt, x, u)
+    t0 = time.perf_counter()
+    for ep, order in enumerate(W.minibatch_order(n, epochs)):
+        losses = g.train(order, 4096, 2e-3 * 0.5 ** (ep // 5))
+    g.train_seconds = time.perf_counter() - t0
+    g.final_loss = float(losses.mean())
+    return g
 
 
 def serving_mix_workloads(n_controllers):
@@ -156,8 +177,7 @@ def main():
 
     def run(n):
         for _ in range(n):
-            ctrl.step_async(xp, up, 1)
-            ctrl.plant_step_async(xp, up)
+            ctrl.step_plant_async(xp, up, 1)
 
     run(args.warmup)
     ctrl.sync()
@@ -176,18 +196,29 @@ def main():
     run(args.steps)
     times = ctrl.kernel_times()
     ctrl.set_profiling(False)
-    kind, (k_ms, k_n) = max(times.items(), key=lambda kv: kv[1][0])
     roll_ms = times["rollout"][0]
-    ops = ALG_OPS_PER_ROLLOUT_STEP[wl.name] * rollout_steps
-    achieved = ops / (roll_ms / 1e3) / 1e12
-    roofline = dict(bound="alu", kernel="rollout", achieved=round(achieved, 4), peak=round(ALU_PEAK_TFLOPS, 2),
-                    unit="TFLOP/s", frac=round(achieved / ALU_PEAK_TFLOPS, 5), traffic=None,
-                    peak_published_fp32=PUBLISHED_FP32_TFLOPS,
-                    alg_ops_per_launch=ops, kernel_ms=round(roll_ms, 5),
-                    kernel_ms_all={k: round(v[0], 5) for k, v in times.items()}, launches_timed=times["rollout"][1])
+    if wl.name == "quadrotor_mlp":
+        ops = MLP_FLOP_PER_ROLLOUT_STEP * rollout_steps
+        achieved = ops / (roll_ms / 1e3) / 1e12
+        roofline = dict(bound="mfma", kernel="mlp_rollout", achieved=round(achieved, 3), peak=BF16_MFMA_PEAK_TFLOPS,
+                        unit="TFLOP/s", frac=round(achieved / BF16_MFMA_PEAK_TFLOPS, 5), traffic=None,
+                        alg_flop_per_launch=ops, kernel_ms=round(roll_ms, 5),
+                        kernel_ms_all={k: round(v[0], 5) for k, v in times.items()},
+                        launches_timed=times["rollout"][1],
+                        mlp_train_seconds=round(wl.params["mlp"].train_seconds, 3),
+                        mlp_final_loss=wl.params["mlp"].final_loss)
+    else:
+        ops = ALG_OPS_PER_ROLLOUT_STEP[wl.name] * rollout_steps
+        achieved = ops / (roll_ms / 1e3) / 1e12
+        roofline = dict(bound="alu", kernel="rollout", achieved=round(achieved, 4), peak=round(ALU_PEAK_TFLOPS, 2),
+                        unit="TFLOP/s", frac=round(achieved / ALU_PEAK_TFLOPS, 5), traffic=None,
+                        peak_published_fp32=PUBLISHED_FP32_TFLOPS,
+                        alg_ops_per_launch=ops, kernel_ms=round(roll_ms, 5),
+                        kernel_ms_all={k: round(v[0], 5) for k, v in times.items()},
+                        launches_timed=times["rollout"][1])
 
     parity = None
-    if not args.no_parity:
+    if not args.no_parity and wl.name != "quadrotor_mlp":
         from oracle import mppi
         x = x_dev.cpu().numpy()
         U = ctrl.get_controls()
@@ -210,7 +241,7 @@ def main():
         out["parity"] = parity
     if args.serving_seconds > 0:
         out["serving"] = serving_bench(args.serving_seconds, args.plain_seconds)
-    if not args.no_cpu:
+    if not args.no_cpu and wl.name != "quadrotor_mlp":
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
         out["cpu_baseline"]["value"] = round(out["cpu_baseline"]["value"], 1)
     ctrl.close()

@@ -161,6 +161,11 @@ int mppi_step(mppi_ctx *ctx, const double *x0, int32_t n_iters, double *u0);
  * mppi_sync. */
 int mppi_step_async(mppi_ctx *ctx, const double *x0_dev, int32_t n_iters, double *u0_dev);
 
+/* Closed-loop form of mppi_step_async for simulation on the device: x_dev (n FP64) is the
+ * start state of the step and, once u0 is emitted into u0_dev (m FP64), is advanced by the
+ * harness plant step (as mppi_plant_step_async) inside the same launch sequence. */
+int mppi_step_plant_async(mppi_ctx *ctx, double *x_dev, int32_t n_iters, double *u0_dev);
+
 /* Wait for the context's stream.  Returns MPPI_ENUMERIC if any iteration since the
  * previous mppi_sync / mppi_step had no finite path cost, and clears that flag. */
 int mppi_sync(mppi_ctx *ctx);

@@ -102,6 +102,7 @@ def load() -> C.CDLL:
         "mppi_destroy": [C.c_void_p],
         "mppi_step": [C.c_void_p, _dp, C.c_int32, _dp],
         "mppi_step_async": [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p],
+        "mppi_step_plant_async": [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p],
         "mppi_sync": [C.c_void_p],
         "mppi_plant_step_async": [C.c_void_p, C.c_void_p, C.c_void_p],
         "mppi_get_controls": [C.c_void_p, _dp, C.c_uint64],
@@ -263,6 +264,10 @@ class Controller:
 
     def step_async(self, x0_dev_ptr: int, u0_dev_ptr: int, n_iters: int = 1):
         check(self._lib.mppi_step_async(self.handle, C.c_void_p(x0_dev_ptr), int(n_iters), C.c_void_p(u0_dev_ptr)))
+
+    def step_plant_async(self, x_dev_ptr: int, u0_dev_ptr: int, n_iters: int = 1):
+        """Device closed loop: step from x_dev, emit u0, then advance x_dev by the plant step."""
+        check(self._lib.mppi_step_plant_async(self.handle, C.c_void_p(x_dev_ptr), int(n_iters), C.c_void_p(u0_dev_ptr)))
 
     def sync(self):
         check(self._lib.mppi_sync(self.handle))

@@ -181,8 +181,15 @@ void compute_layout(const mppi_config *c, Layout *L) {
   const int K = c->K, T = c->T, m = c->n_ctrl;
   L->TM = T * m;
   L->G = (L->TM + 3) / 4;
-  // the learned-dynamics rollout runs 64 samples per block (16 per wave), the others 256
-  const int roll_per_block = c->system == MPPI_SYS_QUADROTOR_MLP ? 64 : kBlock;
+  // samples per rollout block: 64 for the learned dynamics (16 per wave), 256 / lanes-per-sample otherwise
+  int roll_per_block = kBlock;
+  switch (c->system) {
+    case MPPI_SYS_QUADROTOR_MLP: roll_per_block = 64; break;
+    case MPPI_SYS_LINEAR: roll_per_block = kBlock / LinearSys<1>::kLPS; break;
+    case MPPI_SYS_CARTPOLE: roll_per_block = kBlock / CartPoleSys::kLPS; break;
+    case MPPI_SYS_BICYCLE: roll_per_block = kBlock / BicycleSys::kLPS; break;
+    case MPPI_SYS_QUADROTOR: roll_per_block = kBlock / QuadrotorSys::kLPS; break;
+  }
   L->n_roll_blocks = (K + roll_per_block - 1) / roll_per_block;
   L->n_kc = (K + kUpdChunk - 1) / kUpdChunk;
   uint64_t o = 0;
@@ -324,7 +331,7 @@ static size_t rollout_lds_bytes(const mppi_ctx *c) {
 template <class Sys>
 static int launch_rollout(mppi_ctx *c, const IterArgs &a, const typename Sys::Params &p, hipStream_t s) {
   const size_t lds = rollout_lds_bytes<Sys>(c);
-  hipLaunchKernelGGL(rollout_kernel<Sys>, dim3(c->L.n_roll_blocks), dim3(kBlock), lds, s, a, p);
+  hipLaunchKernelGGL((rollout_kernel<Sys, Sys::kLPS>), dim3(c->L.n_roll_blocks), dim3(kBlock), lds, s, a, p);
   return MPPI_OK;
 }
 
@@ -332,7 +339,7 @@ template <class Sys>
 static int prepare_rollout(mppi_ctx *c) {
   const size_t lds = rollout_lds_bytes<Sys>(c);
   if (lds > 160 * 1024 - 64) return fail(MPPI_EINVAL, "rollout needs %zu B of LDS (T too large)", lds);
-  HIP_TRY(hipFuncSetAttribute((const void *)rollout_kernel<Sys>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  HIP_TRY(hipFuncSetAttribute((const void *)rollout_kernel<Sys, Sys::kLPS>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   return MPPI_OK;
 }
 
@@ -408,7 +415,32 @@ static void prof_end(mppi_ctx *c, hipStream_t s, int kind, hipEvent_t start) {
 }
 
 // Enqueue n_iters iterations (+ emit/shift) on stream s.
-int enqueue_iterations(mppi_ctx *c, const double *x0_dev, int n_iters, double *u0_dev, hipStream_t s) {
+template <class Sys>
+static void launch_finalize_plant(mppi_ctx *c, const FinalizeArgs &f, double *x, const typename Sys::Params &p,
+                                  hipStream_t s) {
+  hipLaunchKernelGGL(finalize_plant_kernel<Sys>, dim3(1), dim3(kFinBlock), 0, s, f, x, c->cfg.dt, c->cfg.n_state, p);
+}
+
+// Last finalize of a step with the plant step fused (plant_x != NULL).
+static void launch_finalize(mppi_ctx *c, const FinalizeArgs &f, double *plant_x, hipStream_t s) {
+  if (!plant_x) {
+    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kFinBlock), 0, s, f);
+    return;
+  }
+  switch (c->cfg.system) {
+    case MPPI_SYS_LINEAR:
+      if (c->cfg.n_ctrl == 1) launch_finalize_plant<LinearSys<1>>(c, f, plant_x, c->linear, s);
+      else if (c->cfg.n_ctrl == 2) launch_finalize_plant<LinearSys<2>>(c, f, plant_x, c->linear, s);
+      else launch_finalize_plant<LinearSys<4>>(c, f, plant_x, c->linear, s);
+      break;
+    case MPPI_SYS_CARTPOLE: launch_finalize_plant<CartPoleSys>(c, f, plant_x, c->cartpole, s); break;
+    case MPPI_SYS_BICYCLE: launch_finalize_plant<BicycleSys>(c, f, plant_x, c->bicycle, s); break;
+    default: launch_finalize_plant<QuadrotorSys>(c, f, plant_x, c->quad, s); break;
+  }
+}
+
+int enqueue_iterations(mppi_ctx *c, const double *x0_dev, int n_iters, double *u0_dev, hipStream_t s,
+                       double *plant_x) {
   const IterArgs a = make_iter_args(c, x0_dev);
   for (int it = 0; it < n_iters; ++it) {
     int rc = MPPI_OK;
@@ -431,7 +463,7 @@ int enqueue_iterations(mppi_ctx *c, const double *x0_dev, int n_iters, double *u
     prof_end(c, s, 1, t0);
     const FinalizeArgs f = make_fin_args(c, u0_dev, it == n_iters - 1);
     t0 = prof_begin(c, s);
-    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kFinBlock), 0, s, f);
+    launch_finalize(c, f, it == n_iters - 1 ? plant_x : nullptr, s);
     prof_end(c, s, 2, t0);
   }
   HIP_TRY(hipGetLastError());
@@ -439,15 +471,15 @@ int enqueue_iterations(mppi_ctx *c, const double *x0_dev, int n_iters, double *u
 }
 
 // Run n_iters iterations, through a cached hipGraph when enabled.
-int run_iterations(mppi_ctx *c, const double *x0_dev, int n_iters, double *u0_dev) {
-  if (!c->cfg.use_graph || c->profiling) return enqueue_iterations(c, x0_dev, n_iters, u0_dev, c->stream);
-  auto key = std::make_tuple(n_iters, (const void *)x0_dev, (const void *)u0_dev);
+int run_iterations(mppi_ctx *c, const double *x0_dev, int n_iters, double *u0_dev, double *plant_x) {
+  if (!c->cfg.use_graph || c->profiling) return enqueue_iterations(c, x0_dev, n_iters, u0_dev, c->stream, plant_x);
+  auto key = std::make_tuple(n_iters, (const void *)x0_dev, (const void *)u0_dev, (const void *)plant_x);
   auto itg = c->graphs.find(key);
   if (itg == c->graphs.end()) {
     hipGraph_t g;
     hipGraphExec_t ge;
     HIP_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-    int rc = enqueue_iterations(c, x0_dev, n_iters, u0_dev, c->cap_stream);
+    int rc = enqueue_iterations(c, x0_dev, n_iters, u0_dev, c->cap_stream, plant_x);
     hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
     if (rc) return rc;
     if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
@@ -615,7 +647,7 @@ extern "C" int mppi_step(mppi_ctx *c, const double *x0, int32_t n_iters, double 
   double *d_x0 = (double *)(c->base + c->L.off_x0);
   double *d_res = (double *)(c->base + c->L.off_res);
   HIP_TRY(hipMemcpyAsync(d_x0, px, n * sizeof(double), hipMemcpyHostToDevice, c->stream));
-  rc = run_iterations(c, d_x0, n_iters, d_res);
+  rc = run_iterations(c, d_x0, n_iters, d_res, nullptr);
   if (rc) return rc;
   char *pres = c->pinned + 1024;
   HIP_TRY(hipMemcpyAsync(pres, d_res, 8 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
@@ -631,7 +663,15 @@ extern "C" int mppi_step_async(mppi_ctx *c, const double *x0_dev, int32_t n_iter
   if (rc) return rc;
   if (!x0_dev || !u0_dev) return fail(MPPI_EINVAL, "x0_dev and u0_dev must be non-NULL");
   if (n_iters < 1 || n_iters > 1000) return fail(MPPI_EINVAL, "n_iters=%d outside [1, 1000]", n_iters);
-  return run_iterations(c, x0_dev, n_iters, u0_dev);
+  return run_iterations(c, x0_dev, n_iters, u0_dev, nullptr);
+}
+
+extern "C" int mppi_step_plant_async(mppi_ctx *c, double *x_dev, int32_t n_iters, double *u0_dev) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (!x_dev || !u0_dev) return fail(MPPI_EINVAL, "x_dev and u0_dev must be non-NULL");
+  if (n_iters < 1 || n_iters > 1000) return fail(MPPI_EINVAL, "n_iters=%d outside [1, 1000]", n_iters);
+  return run_iterations(c, x_dev, n_iters, u0_dev, x_dev);
 }
 
 extern "C" int mppi_sync(mppi_ctx *c) {

@@ -55,7 +55,7 @@ __global__ __launch_bounds__(kBlock) void rollout_batched(const CtrlDesc *__rest
   const int j = find_item(prefix, n, blockIdx.x);
   const WorkItem &w = items[sel[j]];
   const CtrlDesc &d = descs[w.desc];
-  rollout_body<Sys>(d.it, sys_params<Sys>(d.p), w.x0, blockIdx.x - prefix[j], lds4);
+  rollout_body<Sys, Sys::kLPS>(d.it, sys_params<Sys>(d.p), w.x0, blockIdx.x - prefix[j], lds4);
 }
 
 static __global__ __launch_bounds__(kBlock) void update_batched(const CtrlDesc *__restrict__ descs,
@@ -69,8 +69,9 @@ static __global__ __launch_bounds__(kBlock) void update_batched(const CtrlDesc *
 
 static __global__ __launch_bounds__(kFinBlock) void finalize_batched(const CtrlDesc *__restrict__ descs,
                                                                      const WorkItem *__restrict__ items) {
+  __shared__ double u0_s[4];
   const WorkItem &w = items[blockIdx.x];
-  finalize_body(descs[w.desc].fin, w.out, w.out + 4);
+  finalize_body(descs[w.desc].fin, w.out, w.out + 4, u0_s);
 }
 
 }  // namespace mppi

@@ -17,8 +17,9 @@
 
 namespace mppi {
 
-constexpr int kUpdGroups = 16;                       // noise groups per update block
+constexpr int kUpdGroups = 4;                        // noise groups per update block
 constexpr int kUpdStrips = kBlock / kUpdGroups;      // sample strips per update block
+static_assert(kUpdStrips % 16 == 0 && kUpdGroups * 4 * 16 <= kBlock, "update reduction layout");
 constexpr int kUpdChunk = 256;                       // samples per update block
 constexpr int kUpdPerThread = kUpdChunk / kUpdStrips;
 
@@ -58,10 +59,58 @@ struct FinalizeArgs {
 };
 
 // ------------------------------------------------------------------------ rollout
-// One 256-sample block of one controller (`blk` indexes the controller's blocks).
-// The single-controller kernel and the batched serving kernel both call this body, so a
-// controller's results do not depend on what else shares the launch.
-template <class Sys>
+// One block of one controller (`blk` indexes the controller's blocks): 256 / LPS samples,
+// LPS adjacent lanes per sample.  With LPS = 4 the four lanes of a DPP quad share a
+// sample: lane j generates every fourth noise group (g = 4r + j) and broadcasts it across
+// the quad, a system with a decomposable cost splits it over the quad and sums with two
+// DPP steps, and the dynamics run redundantly, so all four lanes hold the same state and
+// the same path cost.  The single-controller kernel and the batched serving kernel both
+// call this body, so a controller's results do not depend on what else shares a launch.
+template <int J>
+__device__ __forceinline__ float quad_bcast(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), J * 0x55, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float quad_sum(float v) {
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));   // quad_perm(1,0,3,2)
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, false));   // quad_perm(2,3,0,1)
+  return v;
+}
+
+// One horizon step of one sample from the four normals `e` of its noise group.
+template <class Sys, int LPS>
+__device__ __forceinline__ void rollout_step(const IterArgs &a, const typename Sys::Params &p, const StageView &sv,
+                                             const float *sU, const float *sRU, const float *sC, int i, int s,
+                                             int lane_j, const float e[4], float *x, double &S) {
+  constexpr int N = Sys::N, M = Sys::M;
+  float du[M], v[M], xd[N];
+#pragma unroll
+  for (int j = 0; j < M; ++j) {
+    float t = 0.f;
+#pragma unroll
+    for (int l = 0; l <= j; ++l) t += a.Ls[j * M + l] * e[s * M + l];
+    du[j] = t;
+    v[j] = sU[i * M + j] + t;
+  }
+  Sys::xdot(p, x, v, xd);
+#pragma unroll
+  for (int r = 0; r < N; ++r) x[r] += a.dt * xd[r];
+  float quad = 0.f, lin = 0.f;
+#pragma unroll
+  for (int r = 0; r < M; ++r) {
+    float t = 0.f;
+#pragma unroll
+    for (int j = 0; j < M; ++j) t += a.R[r * M + j] * du[j];
+    quad += du[r] * t;
+    lin += sRU[i * M + r] * du[r];
+  }
+  float q;
+  if constexpr (LPS == 4 && Sys::kSplitCost) q = quad_sum(Sys::q_part(p, sv, x, lane_j, 4));
+  else q = Sys::q(p, sv, x);
+  const float qt = q + (a.lr_quad * quad + lin + sC[i]);
+  S += (double)qt;
+}
+
+template <class Sys, int LPS>
 __device__ __forceinline__ void rollout_body(const IterArgs &a, const typename Sys::Params &p, const double *x0,
                                              int blk, float4 *lds4) {
   constexpr int N = Sys::N, M = Sys::M;
@@ -94,56 +143,55 @@ __device__ __forceinline__ void rollout_body(const IterArgs &a, const typename S
   __syncthreads();
   const StageView sv{sSys, ti, tj};
 
-  const int k = blk * kBlock + threadIdx.x;
+  const int lane_j = threadIdx.x % LPS;
+  const int k = blk * (kBlock / LPS) + threadIdx.x / LPS;
   float x[N];
 #pragma unroll
   for (int r = 0; r < N; ++r) x[r] = r < a.n ? (float)x0[r] : 0.f;
   double S = 0.0;
-  for (int g = 0; g < a.G; ++g) {
-    float e[4];
-    normals4((uint32_t)g, (uint32_t)k, it, a.key0, a.key1, e);
+  if constexpr (LPS == 1) {
+    for (int g = 0; g < a.G; ++g) {
+      float e[4];
+      normals4((uint32_t)g, (uint32_t)k, it, a.key0, a.key1, e);
 #pragma unroll
-    for (int s = 0; s < SPG; ++s) {
-      const int i = g * SPG + s;
-      if (i < a.T) {
-        float du[M], v[M], xd[N];
-#pragma unroll
-        for (int j = 0; j < M; ++j) {
-          float t = 0.f;
-#pragma unroll
-          for (int l = 0; l <= j; ++l) t += a.Ls[j * M + l] * e[s * M + l];
-          du[j] = t;
-          v[j] = sU[i * M + j] + t;
-        }
-        Sys::xdot(p, x, v, xd);
-#pragma unroll
-        for (int r = 0; r < N; ++r) x[r] += a.dt * xd[r];
-        float quad = 0.f, lin = 0.f;
-#pragma unroll
-        for (int r = 0; r < M; ++r) {
-          float t = 0.f;
-#pragma unroll
-          for (int j = 0; j < M; ++j) t += a.R[r * M + j] * du[j];
-          quad += du[r] * t;
-          lin += sRU[i * M + r] * du[r];
-        }
-        const float qt = Sys::q(p, sv, x) + (a.lr_quad * quad + lin + sC[i]);
-        S += (double)qt;
+      for (int s = 0; s < SPG; ++s) {
+        const int i = g * SPG + s;
+        if (i < a.T) rollout_step<Sys, LPS>(a, p, sv, sU, sRU, sC, i, s, 0, e, x, S);
       }
+    }
+  } else {
+    static_assert(LPS == 4, "LPS is 1 or 4");
+    for (int g0 = 0; g0 < a.G; g0 += 4) {
+      float mine[4];
+      normals4((uint32_t)(g0 + lane_j), (uint32_t)k, it, a.key0, a.key1, mine);
+#define MPPI_QUAD_GROUP(J)                                                              \
+      if (g0 + J < a.G) {                                                               \
+        float e[4];                                                                     \
+        for (int c = 0; c < 4; ++c) e[c] = quad_bcast<J>(mine[c]);                      \
+        _Pragma("unroll") for (int s = 0; s < SPG; ++s) {                               \
+          const int i = (g0 + J) * SPG + s;                                             \
+          if (i < a.T) rollout_step<Sys, LPS>(a, p, sv, sU, sRU, sC, i, s, lane_j, e, x, S); \
+        }                                                                               \
+      }
+      MPPI_QUAD_GROUP(0)
+      MPPI_QUAD_GROUP(1)
+      MPPI_QUAD_GROUP(2)
+      MPPI_QUAD_GROUP(3)
+#undef MPPI_QUAD_GROUP
     }
   }
   S += (double)Sys::phi(p, x);
   if (!isfinite(S)) S = __builtin_inf();
-  const bool valid = k < a.K;
+  const bool valid = k < a.K && lane_j == 0;
   if (valid) a.S[k] = S;
   const double bm = block_min(valid ? S : __builtin_inf(), red);
   if (threadIdx.x == 0) a.blk_min[blk] = bm;
 }
 
-template <class Sys>
+template <class Sys, int LPS>
 __global__ __launch_bounds__(kBlock) void rollout_kernel(const IterArgs a, const typename Sys::Params p) {
   extern __shared__ float4 lds4[];
-  rollout_body<Sys>(a, p, a.x0, blockIdx.x, lds4);
+  rollout_body<Sys, LPS>(a, p, a.x0, blockIdx.x, lds4);
 }
 
 // Minimum over the rollout blocks' minima (every thread gets it).
@@ -194,11 +242,23 @@ __device__ __forceinline__ void update_body(const IterArgs &a, int kc, int gcb) 
 #pragma unroll
   for (int c = 0; c < 4; ++c) acc_lds[strip][gl][c] = acc[c];
   __syncthreads();
+  // fixed-order two-level sum over the strips: 16 runs of kUpdStrips/16, then the runs
+  __shared__ double runs[16][kUpdGroups * 4];
+  {
+    const int slot = threadIdx.x % (kUpdGroups * 4), run = threadIdx.x / (kUpdGroups * 4);
+    if (run < 16) {
+      const int gg = slot / 4, c = slot % 4;
+      double s = 0.0;
+      for (int st = run * (kUpdStrips / 16); st < (run + 1) * (kUpdStrips / 16); ++st) s += acc_lds[st][gg][c];
+      runs[run][slot] = s;
+    }
+  }
+  __syncthreads();
   if (threadIdx.x < kUpdGroups * 4) {
     const int gg = threadIdx.x / 4, c = threadIdx.x % 4;
     const int gabs = gcb * kUpdGroups + gg;
     double s = 0.0;
-    for (int st = 0; st < kUpdStrips; ++st) s += acc_lds[st][gg][c];
+    for (int r = 0; r < 16; ++r) s += runs[r][threadIdx.x];
     if (gabs < a.G) a.part[(size_t)kc * (a.G * 4) + gabs * 4 + c] = s;
   }
 }
@@ -228,31 +288,48 @@ __device__ __forceinline__ double ordered_sum(const double *p, size_t stride, in
   return s;
 }
 
-// status_out (nullable): 0 when the iteration had a finite cost, -5 otherwise.
-__device__ __forceinline__ void finalize_body(const FinalizeArgs &a, double *u0_out, double *status_out) {
+// status_out (nullable): 0 when the iteration had a finite cost, -5 otherwise.  All global
+// loads (block minima, chunk partials, the previous sequence) are issued before the first
+// barrier; the updated sequence then lives in LDS until the (shifted) write-back.
+// Returns with u0 (the emitted control, when a.emit) in u0_s.
+__device__ __forceinline__ void finalize_body(const FinalizeArgs &a, double *u0_out, double *status_out,
+                                              double *u0_s) {
   __shared__ double N_lds[kMaxTM];
   __shared__ double red[16];
   __shared__ double eta_s;
+  constexpr int kPer = kMaxTM / kFinBlock;
   const int TM = a.T * a.m;
   double v = __builtin_inf();
   for (int b = threadIdx.x; b < a.n_roll_blocks; b += kFinBlock) v = fmin(v, a.blk_min[b]);
-  v = wave_min(v);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x / 64] = v;
+  double Uold[kPer];
+#pragma unroll
+  for (int n = 0; n < kPer; ++n) {
+    const int f = threadIdx.x + n * kFinBlock;
+    Uold[n] = f < TM ? a.U64[f] : 0.0;
+  }
   if (threadIdx.x == 0) eta_s = ordered_sum(a.eta_part, 1, a.n_kc);
   for (int f = threadIdx.x; f < TM; f += kFinBlock) N_lds[f] = ordered_sum(a.part + f, (size_t)a.G * 4, a.n_kc);
+  v = wave_min(v);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x / 64] = v;
   __syncthreads();
   double rho = red[0];
   for (int i = 1; i < kFinBlock / 64; ++i) rho = fmin(rho, red[i]);
   const bool ok = rho < __builtin_inf();
   const double eta = eta_s;
   const double inv_eta = ok ? 1.0 / eta : 0.0;
-  for (int f = threadIdx.x; f < TM; f += kFinBlock) {
-    const int i = f / a.m, j = f - i * a.m;
-    double d = 0.0;
-    for (int l = 0; l <= j; ++l) d += a.Ls[j * a.m + l] * N_lds[i * a.m + l];
-    d = ok ? d * inv_eta : 0.0;
-    a.dbg[2 + f] = d;
-    a.U64[f] += d;
+  double Unew[kPer];
+#pragma unroll
+  for (int n = 0; n < kPer; ++n) {
+    const int f = threadIdx.x + n * kFinBlock;
+    Unew[n] = Uold[n];
+    if (f < TM) {
+      const int i = f / a.m, j = f - i * a.m;
+      double d = 0.0;
+      for (int l = 0; l <= j; ++l) d += a.Ls[j * a.m + l] * N_lds[i * a.m + l];
+      d = ok ? d * inv_eta : 0.0;
+      a.dbg[2 + f] = d;
+      Unew[n] = Uold[n] + d;
+    }
   }
   if (threadIdx.x == 0) {
     a.dbg[0] = rho;
@@ -262,23 +339,52 @@ __device__ __forceinline__ void finalize_body(const FinalizeArgs &a, double *u0_
     a.iter[0] += 1;
   }
   if (a.emit) {
-    __syncthreads();
-    double nxt[kMaxTM / kFinBlock];
-    int n = 0;
-    for (int f = threadIdx.x; f < TM; f += kFinBlock) {
-      if (f < a.m) u0_out[f] = a.U64[f];
-      nxt[n++] = (f + a.m < TM) ? a.U64[f + a.m] : a.u_init[f - (TM - a.m)];
+    __syncthreads();                                   // everyone has read N_lds
+#pragma unroll
+    for (int n = 0; n < kPer; ++n) {
+      const int f = threadIdx.x + n * kFinBlock;
+      if (f < TM) N_lds[f] = Unew[n];
     }
     __syncthreads();
-    n = 0;
-    for (int f = threadIdx.x; f < TM; f += kFinBlock) a.U64[f] = nxt[n++];
+#pragma unroll
+    for (int n = 0; n < kPer; ++n) {
+      const int f = threadIdx.x + n * kFinBlock;
+      if (f < a.m) {
+        u0_out[f] = N_lds[f];
+        u0_s[f] = N_lds[f];
+      }
+      if (f < TM) Unew[n] = (f + a.m < TM) ? N_lds[f + a.m] : a.u_init[f - (TM - a.m)];
+    }
     __syncthreads();
   }
-  for (int f = threadIdx.x; f < TM; f += kFinBlock) a.U32[f] = (float)a.U64[f];
+#pragma unroll
+  for (int n = 0; n < kPer; ++n) {
+    const int f = threadIdx.x + n * kFinBlock;
+    if (f < TM) {
+      a.U64[f] = Unew[n];
+      a.U32[f] = (float)Unew[n];
+    }
+  }
 }
 
 static __global__ __launch_bounds__(kFinBlock) void finalize_kernel(const FinalizeArgs a) {
-  finalize_body(a, a.u0_out, nullptr);
+  __shared__ double u0_s[4];
+  finalize_body(a, a.u0_out, nullptr, u0_s);
+}
+
+// finalize + the harness plant step on the emitted control: x <- x + dt (f + G u0), FP64.
+template <class Sys>
+__global__ __launch_bounds__(kFinBlock) void finalize_plant_kernel(const FinalizeArgs a, double *x, double dt, int n,
+                                                                   const typename Sys::Params p) {
+  __shared__ double u0_s[4];
+  finalize_body(a, a.u0_out, nullptr, u0_s);
+  if (threadIdx.x == 0) {
+    double xl[Sys::N], ul[Sys::M], xd[Sys::N];
+    for (int r = 0; r < Sys::N; ++r) xl[r] = r < n ? x[r] : 0.0;
+    for (int j = 0; j < Sys::M; ++j) ul[j] = u0_s[j];
+    Sys::xdot(p, xl, ul, xd);
+    for (int r = 0; r < n; ++r) x[r] = xl[r] + dt * xd[r];
+  }
 }
 
 // --------------------------------------------------------------------- plant (FP64)

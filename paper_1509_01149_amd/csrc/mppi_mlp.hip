@@ -25,15 +25,11 @@ constexpr int kFrags = 8 + 32 + 4;   // A-operand fragments per lane in the roll
 // ------------------------------------------------------------------ device helpers
 __device__ __forceinline__ __bf16 to_bf16(float x) { return (__bf16)x; }
 
-// tanh in FP32: odd Taylor series below |x| = 0.25 (truncation < 1e-7), else
-// 1 - 2 / (exp(2x) + 1) with the hardware exp2 and reciprocal.
+// tanh in FP32 as sign(x) (1 - 2 / (exp(2|x|) + 1)) with the hardware exp2 and reciprocal:
+// absolute error ~1e-7, below the bfloat16 step of every activation it feeds.
 __device__ __forceinline__ float tanh_f(float x) {
-  const float a = fabsf(x);
-  const float x2 = x * x;
-  const float poly = x * (1.f + x2 * (-0.333333333f + x2 * (0.133333333f + x2 * (-0.0539682540f))));
-  const float e = __builtin_amdgcn_exp2f(2.88539008177792681f * a);   // exp(2|x|)
-  const float t = 1.f - 2.f * __builtin_amdgcn_rcpf(e + 1.f);
-  return a < 0.25f ? poly : copysignf(t, x);
+  const float e = __builtin_amdgcn_exp2f(2.88539008177792681f * fabsf(x));   // exp(2|x|)
+  return copysignf(1.f - 2.f * __builtin_amdgcn_rcpf(e + 1.f), x);
 }
 
 // Layer-1 k slot (8 q + e) -> input feature (4 q + e, e < 4) or -1 (zero padding): each lane
@@ -310,11 +306,16 @@ static __global__ __launch_bounds__(256) void mlp_rollout_kernel(const IterArgs 
   for (int r = 0; r < 4; ++r) v[r] = q < 3 ? (float)a.x0[4 * q + r] : 0.f;
   const __bf16 z = to_bf16(0.f);
   double S = 0.0;
+  float mine[4];
   for (int i = 0; i < a.T; ++i) {
+    // the four lanes of a sample take turns generating its noise: lane q draws the group of
+    // step i + q once every four steps; the control lane (q = 3) fetches each step's four.
+    if ((i & 3) == 0) normals4((uint32_t)(i + q), (uint32_t)k, it, a.key0, a.key1, mine);
+    float e[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) e[c] = __shfl(mine[c], 16 * (i & 3) + nn, 64);
     float du[4] = {0.f, 0.f, 0.f, 0.f};
     if (q == 3) {
-      float e[4];
-      normals4((uint32_t)i, (uint32_t)k, it, a.key0, a.key1, e);
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         float t = 0.f;

@@ -42,7 +42,7 @@ struct mppi_ctx {
   mppi::BicycleSys::Params bicycle;
   mppi::QuadrotorSys::Params quad;
   mppi::MlpState *mlp = nullptr;
-  std::map<std::tuple<int, const void *, const void *>, hipGraphExec_t> graphs;
+  std::map<std::tuple<int, const void *, const void *, const void *>, hipGraphExec_t> graphs;
   // profiling: pending (kind, start, stop) event triples and accumulated totals
   bool profiling = false;
   struct Timed { int kind; hipEvent_t a, b; };
@@ -59,8 +59,9 @@ int fail(int code, const char *fmt, ...);
 int hip_fail(hipError_t e, const char *what);
 int validate_config(const mppi_config *c);
 void compute_layout(const mppi_config *c, Layout *L);
-int enqueue_iterations(mppi_ctx *c, const double *x0_dev, int n_iters, double *u0_dev, hipStream_t s);
-int run_iterations(mppi_ctx *c, const double *x0_dev, int n_iters, double *u0_dev);
+int enqueue_iterations(mppi_ctx *c, const double *x0_dev, int n_iters, double *u0_dev, hipStream_t s,
+                       double *plant_x);
+int run_iterations(mppi_ctx *c, const double *x0_dev, int n_iters, double *u0_dev, double *plant_x);
 size_t ctx_rollout_lds(const mppi_ctx *c);
 void fill_desc(mppi_ctx *c, CtrlDesc *d);
 int set_device(int dev);

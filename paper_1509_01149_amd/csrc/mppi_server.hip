@@ -176,7 +176,7 @@ int launch_plain(mppi_server *s, Batch &b, int slot) {
   double *d_res = (double *)(c->base + c->L.off_res);
   hipError_t e = hipMemcpyAsync(d_x0, hx, 16 * sizeof(double), hipMemcpyHostToDevice, b.stream);
   if (e != hipSuccess) return hip_fail(e, "plain upload");
-  int rc = run_iterations(c, d_x0, 1, d_res);
+  int rc = run_iterations(c, d_x0, 1, d_res, nullptr);
   if (rc) return rc;
   e = hipMemcpyAsync(b.h + b.off_out, d_res, 8 * sizeof(double), hipMemcpyDeviceToHost, b.stream);
   if (e == hipSuccess) e = hipEventRecord(b.done, b.stream);

@@ -5,6 +5,11 @@
 #pragma once
 #include "mppi_device.h"
 
+// Lanes per sample in the rollout (1 or 4); a build-time tuning knob.
+#ifndef MPPI_ROLLOUT_LPS
+#define MPPI_ROLLOUT_LPS 4
+#endif
+
 namespace mppi {
 
 // LDS view handed to a system's cost: its staged data (map tile, obstacles).
@@ -46,7 +51,10 @@ struct LinearSys {
     }
     return s;
   }
+  static constexpr bool kSplitCost = false;
+  static constexpr int kLPS = MPPI_ROLLOUT_LPS;
   __device__ static float q(const Params &p, const StageView &, const float *x) { return quad(p.Q, x); }
+  __device__ static float q_part(const Params &p, const StageView &sv, const float *x, int, int) { return q(p, sv, x); }
   __device__ static float phi(const Params &p, const float *x) { return quad(p.Qf, x); }
   static constexpr int stage_floats(int, int) { return 0; }
   __device__ static void stage(const Params &, float *, const double *, int *, int *) {}
@@ -74,9 +82,12 @@ struct CartPoleSys {
     xd[2] = x[3];
     xd[3] = thdd;
   }
+  static constexpr bool kSplitCost = false;
+  static constexpr int kLPS = MPPI_ROLLOUT_LPS;
   __device__ static float q(const Params &p, const StageView &, const float *x) {
     return p.qd[0] * x[0] * x[0] + p.qd[1] * x[1] * x[1] + p.qd[2] * x[2] * x[2] + p.qd[3] * x[3] * x[3];
   }
+  __device__ static float q_part(const Params &p, const StageView &sv, const float *x, int, int) { return q(p, sv, x); }
   __device__ static float phi(const Params &p, const float *x) {
     return p.qfd[0] * x[0] * x[0] + p.qfd[1] * x[1] * x[1] + p.qfd[2] * x[2] * x[2] + p.qfd[3] * x[3] * x[3];
   }
@@ -128,6 +139,9 @@ struct BicycleSys {
     *i0 = ci;
     *j0 = cj;
   }
+  static constexpr bool kSplitCost = false;
+  static constexpr int kLPS = MPPI_ROLLOUT_LPS;
+  __device__ static float q_part(const Params &p, const StageView &sv, const float *x, int, int) { return q(p, sv, x); }
   __device__ static float q(const Params &p, const StageView &sv, const float *x) {
     float gx = x[0] * p.cell_inv, gy = x[1] * p.cell_inv;
     gx = fminf(fmaxf(gx, 0.f), (float)(p.W - 1));
@@ -200,6 +214,22 @@ struct QuadrotorSys {
   static constexpr int stage_floats(int n_obs, int) { return 4 * n_obs; }
   __device__ static void stage(const Params &p, float *lds, const double *, int *, int *) {
     for (int e = threadIdx.x; e < p.n_obs; e += kBlock) reinterpret_cast<float4 *>(lds)[e] = p.obs[e];
+  }
+  static constexpr bool kSplitCost = true;
+  static constexpr int kLPS = MPPI_ROLLOUT_LPS;
+  // Lane j of nj: the goal term (j = 0) plus the barriers of obstacles j, j + nj, ...
+  __device__ static float q_part(const Params &p, const StageView &sv, const float *x, int j, int nj) {
+    const float dx = x[0] - p.goal[0], dy = x[1] - p.goal[1], dz = x[2] - p.goal[2];
+    const float c = j == 0 ? p.wg * (dx * dx + dy * dy + dz * dz) : 0.f;
+    const float4 *ob = reinterpret_cast<const float4 *>(sv.lds);
+    float barrier = 0.f;
+    for (int o = j; o < p.n_obs; o += nj) {
+      const float4 ov = ob[o];
+      const float ex = x[0] - ov.x, ey = x[1] - ov.y, ez = x[2] - ov.z;
+      const float pen = fmaxf(0.f, ov.w - (ex * ex + ey * ey + ez * ez));
+      barrier += pen * pen;
+    }
+    return c + p.wo * barrier;
   }
   __device__ static float q(const Params &p, const StageView &sv, const float *x) {
     const float dx = x[0] - p.goal[0], dy = x[1] - p.goal[1], dz = x[2] - p.goal[2];

@@ -115,3 +115,28 @@ def test_linear_small_state():
     with controller(wl) as c:
         m = one_step(wl, c, wl.x0, mppi.initial_sequence(wl), 0)
     assert_parity(m)
+
+
+def test_fused_plant_step_equals_step_then_plant():
+    """mppi_step_plant_async == mppi_step_async + mppi_plant_step_async, bitwise; and the
+    device plant agrees with the oracle's FP64 plant step."""
+    import torch
+    for wl in (W.bicycle(K=2048, T=50), W.quadrotor(nu=2.0, K=1024, T=60), W.cartpole(nu=2.0)):
+        wl = wl.replace(seed=13)
+        dev = torch.device("cuda:0")
+        xa = torch.tensor(wl.x0, dtype=torch.float64, device=dev)
+        xb = xa.clone()
+        ua = torch.zeros(wl.m, dtype=torch.float64, device=dev)
+        ub = ua.clone()
+        with controller(wl) as a, controller(wl) as b:
+            for _ in range(5):
+                x_before = xb.cpu().numpy()
+                a.step_plant_async(xa.data_ptr(), ua.data_ptr())
+                b.step_async(xb.data_ptr(), ub.data_ptr())
+                b.plant_step_async(xb.data_ptr(), ub.data_ptr())
+                a.sync()
+                b.sync()
+                x_ref = mppi.plant_step(wl, x_before, ub.cpu().numpy())
+                assert np.allclose(xb.cpu().numpy(), x_ref, rtol=1e-12, atol=1e-12)
+            assert torch.equal(xa, xb) and torch.equal(ua, ub)
+            assert np.array_equal(a.get_controls(), b.get_controls())
