@@ -41,6 +41,33 @@ ALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 PUBLISHED_FP32_TFLOPS = 157.3
 
 
+TRAFFIC_FILES = {"bicycle": "traffic_rollout_bicycle_K4096_T100.md",
+                 "quadrotor": "traffic_rollout_quadrotor_K16384_T150.md"}
+ROLLOUT_SOURCES = ["mppi_device.h", "mppi_systems.h", "mppi_kernels.h"]
+
+
+def measured_traffic(name):
+    """HBM bytes per rollout launch from the committed rocprofv3 counter summary (FETCH_SIZE and
+    WRITE_SIZE, each divided by its factor on a known-size copy), or None when there is none or
+    the rollout kernel's sources have changed since the counters were taken."""
+    import hashlib
+    fn = TRAFFIC_FILES.get(name)
+    path = os.path.join(ROOT, "profiles", fn) if fn else None
+    if not path or not os.path.exists(path):
+        return None
+    rec = {}
+    for line in open(path):
+        if ":" in line and not line.startswith(("|", "#", " ", "`")):
+            k, v = line.split(":", 1)
+            rec[k.strip()] = v.strip()
+    h = hashlib.sha256()
+    for f in ROLLOUT_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_1509_01149_amd", "csrc", f), "rb").read())
+    if rec.get("kernel_source_sha256") != h.hexdigest():
+        return None
+    return int(rec["traffic_bytes_per_launch"])
+
+
 def make_workload(name):
     import workloads as W
     if name == "bicycle":
@@ -153,6 +180,9 @@ def main():
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--serving-seconds", type=float, default=2.0,
                     help="length of the batched serving trace (0 disables the serving leg)")
+    ap.add_argument("--copy-calibration", type=int, default=0,
+                    help="first run one plain device copy of this many bytes (a known-size kernel for "
+                         "calibrating HBM byte counters in a profiler pass)")
     ap.add_argument("--plain-seconds", type=float, default=1.0,
                     help="length of the same trace replayed one controller at a time")
     args = ap.parse_args()
@@ -168,6 +198,13 @@ def main():
     if not torch.cuda.is_available():
         raise SystemExit("no GPU visible: bench.py runs the HIP path only")
     dev = torch.device("cuda:0")
+    if args.copy_calibration > 0:
+        src = torch.ones(args.copy_calibration // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     wl = make_workload(args.workload)
     stream = torch.cuda.current_stream(dev)
     ctrl = P.controller_for(wl, device=0, torch_stream=stream, torch_workspace=True)
@@ -211,7 +248,7 @@ def main():
         ops = ALG_OPS_PER_ROLLOUT_STEP[wl.name] * rollout_steps
         achieved = ops / (roll_ms / 1e3) / 1e12
         roofline = dict(bound="alu", kernel="rollout", achieved=round(achieved, 4), peak=round(ALU_PEAK_TFLOPS, 2),
-                        unit="TFLOP/s", frac=round(achieved / ALU_PEAK_TFLOPS, 5), traffic=None,
+                        unit="TFLOP/s", frac=round(achieved / ALU_PEAK_TFLOPS, 5), traffic=measured_traffic(wl.name),
                         peak_published_fp32=PUBLISHED_FP32_TFLOPS,
                         alg_ops_per_launch=ops, kernel_ms=round(roll_ms, 5),
                         kernel_ms_all={k: round(v[0], 5) for k, v in times.items()},
