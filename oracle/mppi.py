@@ -39,12 +39,18 @@ class IterationResult:
 
 
 def likelihood_ratio_cost(du, U_i, R, nu):
-    """Control part of q-tilde in the special case A = sqrt(nu) I (Section III-C):
-    (1 - 1/nu)/2 du^T R du + u^T R du + 1/2 u^T R u, per sample."""
-    quad = np.einsum("kj,jl,kl->k", du, R, du)
+    """Control part of q-tilde.  Special case A = sqrt(nu) I (Section III-C):
+    (1 - 1/nu)/2 du^T R du + u^T R du + 1/2 u^T R u, per sample.  For per-dimension factors
+    A = diag(sqrt(nu_j)) the same derivation (the theorem of Section III-A with the noise-cost
+    coupling of Section II) gives 1/2 du^T (R - A^-1 R A^-1) du + u^T R du + 1/2 u^T R u."""
     lin = du @ (R @ U_i)
     const = 0.5 * U_i @ R @ U_i
-    return 0.5 * (1.0 - 1.0 / nu) * quad + lin + const
+    if np.ndim(nu) == 0:
+        quad = np.einsum("kj,jl,kl->k", du, R, du)
+        return 0.5 * (1.0 - 1.0 / nu) * quad + lin + const
+    Ai = np.diag(1.0 / np.sqrt(np.asarray(nu, dtype=np.float64)))
+    M = R - Ai @ R @ Ai
+    return 0.5 * np.einsum("kj,jl,kl->k", du, M, du) + lin + const
 
 
 def rollout_costs(system, x0, U, du, dt, R, nu, observer=None):

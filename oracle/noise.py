@@ -45,13 +45,18 @@ def standard_normals(seed: int, iteration: int, K: int, T: int, m: int, k_offset
     return flat.reshape(K, T, m)
 
 
-def control_noise(seed: int, iteration: int, K: int, T: int, sigma, nu: float, k_offset: int = 0):
-    """du[k, i, :] = sqrt(nu) * chol(sigma) @ eps[k, i, :]."""
+def control_noise(seed: int, iteration: int, K: int, T: int, sigma, nu, k_offset: int = 0):
+    """du[k, i, :] = A chol(sigma) eps[k, i, :] with A = sqrt(nu) I for a scalar nu, or
+    A = diag(sqrt(nu_j)) for per-dimension factors (the covariance change A_t of the
+    likelihood-ratio theorem, Section III-A): du ~ N(0, A sigma A)."""
     sigma = np.atleast_2d(np.asarray(sigma, dtype=np.float64))
     m = sigma.shape[0]
     eps = standard_normals(seed, iteration, K, T, m, k_offset)
     L = cholesky_psd(sigma)
-    return np.sqrt(nu) * np.einsum("jl,ktl->ktj", L, eps)
+    if np.ndim(nu) == 0:
+        return np.sqrt(nu) * np.einsum("jl,ktl->ktj", L, eps)
+    A = np.diag(np.sqrt(np.asarray(nu, dtype=np.float64)))
+    return np.einsum("jl,ktl->ktj", A @ L, eps)
 
 
 def cholesky_psd(sigma):

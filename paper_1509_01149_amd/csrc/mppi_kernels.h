@@ -269,22 +269,30 @@ static __global__ __launch_bounds__(kBlock) void update_kernel(const IterArgs a)
 
 // ----------------------------------------------------------------------- finalize
 // One block of 1024 threads; T*m <= 4096 handled in a strided loop.  Sums over the
-// chunk partials run in a fixed order (c = 0, 1, ...) with their loads issued eight at
+// chunk partials run in a fixed order (c = 0, 1, ...) with their loads issued 32 at
 // a time, so the result is independent of timing and of the batch it runs in.
 constexpr int kFinBlock = 1024;
 constexpr int kMaxTM = 4096;
 
 __device__ __forceinline__ double ordered_sum(const double *p, size_t stride, int n) {
+  constexpr int kBatch = 32;                       // loads in flight per round
   double s = 0.0;
   int c = 0;
-  for (; c + 8 <= n; c += 8) {
-    double v[8];
+  for (; c + kBatch <= n; c += kBatch) {
+    double v[kBatch];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) v[j] = p[(size_t)(c + j) * stride];
+    for (int j = 0; j < kBatch; ++j) v[j] = p[(size_t)(c + j) * stride];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) s += v[j];
+    for (int j = 0; j < kBatch; ++j) s += v[j];
   }
-  for (; c < n; ++c) s += p[(size_t)c * stride];
+  if (c < n) {
+    double v[kBatch];
+#pragma unroll
+    for (int j = 0; j < kBatch; ++j) v[j] = c + j < n ? p[(size_t)(c + j) * stride] : 0.0;
+#pragma unroll
+    for (int j = 0; j < kBatch; ++j)
+      if (c + j < n) s += v[j];
+  }
   return s;
 }
 

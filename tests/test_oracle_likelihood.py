@@ -57,3 +57,32 @@ def test_q_tilde_at_nu_one_is_girsanov_only():
     du = rng.standard_normal((10, 2))
     c = mppi.likelihood_ratio_cost(du, U, R, 1.0)
     assert np.allclose(c, du @ R @ U + 0.5 * U @ R @ U, rtol=1e-14)
+
+
+@pytest.mark.parametrize("m,lam", [(2, 1.0), (4, 3.0), (3, 0.5)])
+def test_per_dimension_covariance_change(m, lam):
+    """Diagonal A = diag(sqrt(nu_j)) (the general A_t of Section III-A): the generalised
+    q-tilde control terms are the log ratio of N(0, Sigma) and N(u, A Sigma A), up to
+    log|A|, under the coupling R = lambda Sigma^-1; a scalar nu reduces to Section III-C."""
+    rng = np.random.default_rng(10 + m)
+    Sig = _spd(rng, m) / m
+    R = lam * np.linalg.inv(Sig)
+    nu = rng.uniform(1.0, 20.0, m)
+    A = np.diag(np.sqrt(nu))
+    U = rng.standard_normal(m)
+    du = rng.standard_normal((40, m)) * 2
+    v = U + du
+    log_ratio = mvn.logpdf(v, np.zeros(m), Sig) - mvn.logpdf(v, U, A @ Sig @ A)
+    cost = mppi.likelihood_ratio_cost(du, U, R, nu)
+    assert np.allclose(log_ratio, -cost / lam + np.log(np.linalg.det(A)), rtol=1e-10, atol=1e-10)
+    same = mppi.likelihood_ratio_cost(du, U, R, np.full(m, 3.0))
+    assert np.allclose(same, mppi.likelihood_ratio_cost(du, U, R, 3.0), rtol=1e-13)
+
+
+def test_per_dimension_noise_covariance():
+    from oracle import noise
+    sigma = np.array([[0.5, 0.1], [0.1, 0.3]])
+    nu = np.array([2.0, 9.0])
+    du = noise.control_noise(4, 0, 100_000, 4, sigma, nu).reshape(-1, 2)
+    A = np.diag(np.sqrt(nu))
+    assert np.allclose(np.cov(du.T), A @ sigma @ A, rtol=0.02, atol=0.01)
