@@ -53,18 +53,33 @@ def likelihood_ratio_cost(du, U_i, R, nu):
     return 0.5 * np.einsum("kj,jl,kl->k", du, M, du) + lin + const
 
 
+def transition(system, x, v, dt, crashed):
+    """One Euler transition of all samples and the crash term of the step's cost.  With a
+    crash indicator (Section V-C: C = 1 once the vehicle hits the ground or an obstacle) a
+    crashed sample stops simulating and stays where it is for the rest of the horizon,
+    paying crash_cost at every step from the one that crashed on."""
+    x_new = _systems.euler_step(system, x, v, dt)
+    cc = getattr(system, "crash_cost", 0.0)
+    if not cc:
+        return x_new, crashed, 0.0
+    x_new = np.where(crashed[:, None], x, x_new)
+    crashed = crashed | system.crashed(x_new)
+    return x_new, crashed, np.where(crashed, cc, 0.0)
+
+
 def rollout_costs(system, x0, U, du, dt, R, nu, observer=None):
     """Path costs S-tilde for all samples: the K-loop of Algorithm 1.
     ``observer(i, x)``, if given, sees the states x_{i+1} of all samples (tests only)."""
     K, T, m = du.shape
     x = np.repeat(np.asarray(x0, float)[None, :], K, axis=0)
+    crashed = np.zeros(K, dtype=bool)
     S = np.zeros(K)
     for i in range(T):
         v = U[i][None, :] + du[:, i, :]
-        x = _systems.euler_step(system, x, v, dt)
+        x, crashed, c_cost = transition(system, x, v, dt, crashed)
         if observer is not None:
             observer(i, x)
-        S = S + (system.q(x) + likelihood_ratio_cost(du[:, i, :], U[i], R, nu))
+        S = S + (system.q(x) + c_cost + likelihood_ratio_cost(du[:, i, :], U[i], R, nu))
     S = S + system.phi(x)
     S[~np.isfinite(S)] = np.inf
     return S
@@ -147,19 +162,22 @@ def plain_mppi_iteration(wl, x0, U, iteration_index, system=None):
     return U + np.einsum("k,ktj->tj", e / e.sum(), du), S
 
 
-def iteration_cost_to_go(wl, x0, U, iteration_index, system=None):
+def iteration_cost_to_go(wl, x0, U, iteration_index, system=None, du=None):
     """Per-time-step weighting by the cost-to-go from time i onward (the literal reading of
     the update law's S(tau_{i,k})): u_i += sum_k w_{k,i} du_{k,i} with w_{.,i} the min-shifted
     softmax of the tail sums of q-tilde."""
     system = system or _systems.make(wl)
     R = np.asarray(wl.R, float)
-    du = control_noise(wl.seed, iteration_index, wl.K, wl.T, wl.sigma, wl.nu)
+    U = np.asarray(U, float)
+    if du is None:
+        du = control_noise(wl.seed, iteration_index, wl.K, wl.T, wl.sigma, wl.nu)
     K, T, m = du.shape
     x = np.repeat(np.asarray(x0, float)[None, :], K, axis=0)
+    crashed = np.zeros(K, dtype=bool)
     qt = np.zeros((K, T))
     for i in range(T):
-        x = _systems.euler_step(system, x, U[i][None, :] + du[:, i, :], wl.dt)
-        qt[:, i] = system.q(x) + likelihood_ratio_cost(du[:, i, :], U[i], R, wl.nu)
+        x, crashed, c_cost = transition(system, x, U[i][None, :] + du[:, i, :], wl.dt, crashed)
+        qt[:, i] = system.q(x) + c_cost + likelihood_ratio_cost(du[:, i, :], U[i], R, wl.nu)
     qt[:, -1] += system.phi(x)
     tail = np.cumsum(qt[:, ::-1], axis=1)[:, ::-1]
     dU = np.zeros((T, m))

@@ -156,6 +156,8 @@ class Quadrotor:
       eta' = W(eta)^-1 w            (ZYX Euler-angle rates)
       w' = J^-1 (tau - w x J w),    tau = (l (f2 - f4), l (f3 - f1), kappa (f1 - f2 + f3 - f4))
     q = w_goal |p - goal|^2 + w_obs sum_j max(0, (r_j + margin)^2 - |p - c_j|^2)^2, phi = 0.
+    With crash_cost > 0 a rollout that crashes stops moving and pays crash_cost at every
+    remaining step (``crashed``, applied by the rollout in oracle.mppi).
     """
 
     def __init__(self, params):
@@ -169,6 +171,17 @@ class Quadrotor:
         self.wo = params["w_obs"]
         self.margin = params["obs_margin"]
         self.obs = np.asarray(params["obstacles"], float).reshape(-1, 4)
+        # crash indicator C of Section V-C (0 disables it): cost per step once crashed
+        self.crash_cost = float(params.get("crash_cost", 0.0))
+        self.ground_z = float(params.get("ground_z", 0.0))
+
+    def crashed(self, x):
+        """C = 1: below the ground plane or inside an obstacle (its radius, no margin)."""
+        p = x[:, 0:3]
+        hit = p[:, 2] < self.ground_z
+        for cx, cy, cz, r in self.obs:
+            hit = hit | ((p[:, 0] - cx) ** 2 + (p[:, 1] - cy) ** 2 + (p[:, 2] - cz) ** 2 < r * r)
+        return hit
 
     def xdot(self, x, f):
         vel = x[:, 3:6]
@@ -204,9 +217,46 @@ class Quadrotor:
         return np.zeros(x.shape[0])
 
 
+class CartPoleSwingUp:
+    """The cart-pole of the swing-up experiment (Section V-A): the control is a desired cart
+    velocity, tracked as pddot = gain (u - pdot); the pole is a uniform rod of half-length l
+    on a pivot that the cart accelerates, theta = 0 hanging down and theta = pi upright:
+      thetaddot = -(3 / (4 l)) (g sin theta + pddot cos theta)
+    (rotation about the pivot, inertia (4/3) m l^2, under gravity and the pivot's
+    acceleration).  State (p, pdot, theta, thetadot).
+    q = w_pos p^2 + w_angle (1 + cos theta)^2 + w_rate thetadot^2 + w_vel pdot^2, phi = 0."""
+
+    def __init__(self, params):
+        self.gain = params["gain"]
+        self.l = params["half_length"]
+        self.g = params["gravity"]
+        self.w_pos, self.w_angle = params["w_pos"], params["w_angle"]
+        self.w_vel, self.w_rate = params["w_vel"], params["w_rate"]
+
+    def xdot(self, x, v):
+        pd, th, thd = x[:, 1], x[:, 2], x[:, 3]
+        pdd = self.gain * (v[:, 0] - pd)
+        thdd = -(3.0 / (4.0 * self.l)) * (self.g * np.sin(th) + pdd * np.cos(th))
+        return np.stack([pd, pdd, thd, thdd], axis=1)
+
+    def q(self, x):
+        p, pd, th, thd = x[:, 0], x[:, 1], x[:, 2], x[:, 3]
+        return (self.w_pos * p * p + self.w_angle * (1.0 + np.cos(th)) ** 2
+                + self.w_rate * thd * thd + self.w_vel * pd * pd)
+
+    def phi(self, x):
+        return np.zeros(x.shape[0])
+
+    # invariant used by the tests (not by the method): pole energy per unit mass in the
+    # cart's frame, (2/3) l^2 thetadot^2 - g l cos theta
+    def pole_energy(self, x):
+        return (2.0 / 3.0) * self.l ** 2 * x[..., 3] ** 2 - self.g * self.l * np.cos(x[..., 2])
+
+
 def make(workload):
-    from workloads import SYS_LINEAR, SYS_CARTPOLE, SYS_BICYCLE, SYS_QUADROTOR
-    table = {SYS_LINEAR: Linear, SYS_CARTPOLE: CartPole, SYS_BICYCLE: Bicycle, SYS_QUADROTOR: Quadrotor}
+    from workloads import SYS_LINEAR, SYS_CARTPOLE, SYS_BICYCLE, SYS_QUADROTOR, SYS_CARTPOLE_SWINGUP
+    table = {SYS_LINEAR: Linear, SYS_CARTPOLE: CartPole, SYS_BICYCLE: Bicycle, SYS_QUADROTOR: Quadrotor,
+             SYS_CARTPOLE_SWINGUP: CartPoleSwingUp}
     if workload.system not in table:
         raise ValueError(f"oracle has no analytic system {workload.system}")
     return table[workload.system](workload.params)

@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from oracle import lqr, mppi, noise
+from oracle import lqr, mppi, noise, systems
 
 
 def _se(r):
@@ -189,3 +189,122 @@ def test_closed_loop_cartpole_balances():
         x = mppi.plant_step(wl, x, u0)
     qd = wl.params["q_diag"]
     assert float(qd @ x ** 2) < 0.1 and abs(x[2]) < 0.1 and it == 200
+
+
+def _zero_state_cost(wl):
+    return wl.replace(params=dict(wl.params, Q=np.zeros((2, 2)), Qf=np.zeros((2, 2))))
+
+
+def test_cost_to_go_weights_only_the_future():
+    """S(tau_{i,k}) is the cost of the trajectory from time i on (Section III-C): with no
+    state cost, redrawing the perturbations of steps 0 and 1 leaves the updates of steps
+    2.. unchanged, and changes those of steps 0 and 1."""
+    from oracle.noise import control_noise
+    wl = _zero_state_cost(W.linear_double_integrator(K=64, T=6, nu=2.0))
+    U = np.linspace(-0.5, 0.5, 6)[:, None]
+    du = control_noise(wl.seed, 0, wl.K, wl.T, wl.sigma, wl.nu)
+    du2 = du.copy()
+    du2[:, :2, :] = control_noise(wl.seed + 1, 0, wl.K, 2, wl.sigma, wl.nu)
+    a = mppi.iteration_cost_to_go(wl, wl.x0, U, 0, du=du)
+    b = mppi.iteration_cost_to_go(wl, wl.x0, U, 0, du=du2)
+    assert np.array_equal(a[2:], b[2:])
+    assert np.all(a[:2] != b[:2])
+
+
+def test_cost_to_go_expected_update_cancels_the_nominal():
+    """Zero state cost, R = lambda Sigma^-1 and exploration nu: the weight of step i is
+    exp(-sum_{j>=i} [(1 - 1/nu)/2 du_j^2 + u_j du_j] / lambda) up to a constant, and under
+    du_j ~ N(0, nu) the weighted density of du_i is N(-u_i, 1) (the likelihood-ratio terms
+    of Section III-C undo the exploration), so U + dU -> 0 at every step as K grows."""
+    wl = _zero_state_cost(W.linear_double_integrator(K=200_000, T=4, nu=2.0, lam=1.0, sigma=1.0))
+    U = np.array([[0.3], [-0.2], [0.25], [0.1]])
+    out = mppi.iteration_cost_to_go(wl, wl.x0, U, 0)
+    assert np.abs(out).max() < 0.015, out.ravel()
+
+
+def _swingup_running_cost(nu, steps, K=1000):
+    wl = W.cartpole_swingup(nu=nu, K=K).replace(seed=1)
+    system = systems.make(wl)
+    x, U, it, qs = wl.x0.copy(), mppi.initial_sequence(wl), 0, []
+    for _ in range(steps):
+        u0, U, it, _ = mppi.control_step(wl, x, U, it, system=system)
+        x = mppi.plant_step(wl, x, u0, system=system)
+        qs.append(system.q(x[None])[0])
+    return float(np.mean(qs)), x
+
+
+def test_swingup_exploration_variance_speeds_up_the_swing():
+    """Section V-A: the swing-up gets faster as nu grows.  Over the first 2 s (100 control
+    steps, K = 1000) the natural variance (nu = 1) has not brought the pole up (average
+    running cost near the hanging value 2000), while nu = 500 has it upright within 1 s."""
+    c1, x1 = _swingup_running_cost(1.0, 100)
+    c500, x500 = _swingup_running_cost(500.0, 100)
+    print("average running cost nu=1:", c1, "nu=500:", c500)
+    assert c1 > 1200.0 and c500 < 400.0
+    assert abs(abs(x500[2]) - np.pi) < 0.3
+
+
+# ------------------------------------------------------------- crash indicator
+def _crash_quad(obstacles, **over):
+    wl = W.quadrotor(K=1, T=60, obstacles=obstacles, crash=True)
+    return wl.replace(params=dict(wl.params, **over))
+
+
+def test_crash_indicator_free_fall_freezes_and_charges_every_later_step():
+    """Zero thrust from height h: the Euler recursion gives z_i = h - g dt^2 i (i - 1) / 2.
+    C switches on at the first post-transition state below the ground (Section V-C); from
+    then on the state stays put and each step adds crash_cost on top of the state cost."""
+    h, g, dt, T, cc = 0.3, W.QUAD_GRAVITY, 0.01, 60, W.QUAD_CRASH_COST
+    wl = _crash_quad(np.zeros((0, 4)))
+    system = systems.make(wl)
+    x0 = np.zeros(12)
+    x0[2] = h
+    U = np.zeros((T, 4))
+    du = np.zeros((1, T, 4))
+    seen = []
+    S = mppi.rollout_costs(system, x0, U, du, dt, np.asarray(wl.R), wl.nu,
+                           observer=lambda i, x: seen.append(x[0].copy()))
+    z = h - g * dt * dt * np.arange(1, T + 1) * np.arange(0, T) / 2.0     # z after step i
+    i_star = int(np.argmax(z < 0.0))
+    assert 0 < i_star < T - 1
+    zs = np.array([s[2] for s in seen])
+    assert np.allclose(zs[:i_star + 1], z[:i_star + 1], atol=1e-12)
+    assert np.all(zs[i_star:] == zs[i_star])                            # frozen where it crashed
+    goal = np.asarray(wl.params["goal"])
+    p = np.zeros((T, 3))
+    p[:, 2] = np.where(np.arange(T) < i_star, z, z[i_star])
+    want = np.sum(np.sum((p - goal) ** 2, axis=1)) + cc * (T - i_star)
+    assert abs(S[0] - want) < 1e-9 * want
+
+
+def test_crash_indicator_obstacle_hit_at_constant_velocity():
+    """Hover thrust, level attitude, horizontal speed v: x_i = v dt i.  An obstacle of radius r
+    at (c, 0, z0) is hit at the first step with |x_i - c| < r; with crash_cost = 0 the same
+    rollout flies through, so the difference of the two path costs is crash_cost times the
+    steps from the hit on plus the state-cost difference of the frozen tail."""
+    v, dt, T, c, r = 2.0, 0.01, 60, 0.5, 0.2
+    obs = np.array([[c, 0.0, 1.5, r]])
+    wl = _crash_quad(obs, w_obs=0.0)
+    on, off = systems.make(wl), systems.make(wl.replace(params=dict(wl.params, crash_cost=0.0)))
+    x0 = np.zeros(12)
+    x0[2], x0[3] = 1.5, v
+    U = np.full((T, 4), W.QUAD_HOVER)
+    du = np.zeros((1, T, 4))
+    R = np.asarray(wl.R)
+    S_on = mppi.rollout_costs(on, x0, U, du, dt, R, wl.nu)[0]
+    S_off = mppi.rollout_costs(off, x0, U, du, dt, R, wl.nu)[0]
+    xs = v * dt * np.arange(1, T + 1)
+    i_star = int(np.argmax(np.abs(xs - c) < r))
+    goal = np.asarray(wl.params["goal"])
+    q = lambda px: (px - goal[0]) ** 2 + (0.0 - goal[1]) ** 2 + (1.5 - goal[2]) ** 2
+    frozen = np.where(np.arange(T) < i_star, xs, xs[i_star])
+    want = np.sum(q(frozen) - q(xs)) + W.QUAD_CRASH_COST * (T - i_star)
+    assert abs((S_on - S_off) - want) < 1e-9 * abs(want)
+
+
+def test_crash_indicator_off_changes_nothing():
+    wl = W.quadrotor(K=64, T=30).replace(seed=4)
+    a = mppi.iteration(wl, wl.x0, mppi.initial_sequence(wl), 0)
+    wl0 = wl.replace(params={k: v for k, v in wl.params.items() if k not in ("crash_cost", "ground_z")})
+    b = mppi.iteration(wl0, wl0.x0, mppi.initial_sequence(wl0), 0)
+    assert np.array_equal(a.S, b.S)

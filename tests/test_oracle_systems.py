@@ -152,3 +152,70 @@ def test_quadrotor_barrier():
                                           for o in q.obs), abs=1e-9)
     x[0, :3] = ob[:3]
     assert q.q(x)[0] >= q.wo * ((ob[3] + q.margin) ** 2) ** 2
+
+
+# ------------------------------------------------------------- cart-pole swing-up
+def _swingup():
+    return systems.CartPoleSwingUp(W.cartpole_swingup().params)
+
+
+def test_swingup_cart_tracks_the_commanded_velocity():
+    """pddot = 10 (u - pdot): pdot(t) = u + (pdot0 - u) exp(-10 t), whatever the pole does."""
+    su = _swingup()
+    x0 = np.array([0.3, -0.5, 2.0, 1.0])
+    sol = _flow(su, x0, [1.5], 1.0)
+    t = np.linspace(0, 1, 11)
+    assert np.allclose(sol.sol(t)[1], 1.5 + (-0.5 - 1.5) * np.exp(-10.0 * t), atol=1e-8)
+
+
+def test_swingup_pendulum_period_and_energy_at_constant_cart_velocity():
+    """With pdot = u the pivot moves uniformly, so the pole is a free physical pendulum:
+    its energy per unit mass (2/3) l^2 thetadot^2 - g l cos theta is conserved, and small
+    swings have period 2 pi sqrt(I / (m g l)) = 2 pi sqrt(4 l / (3 g)) for a uniform rod."""
+    su = _swingup()
+    l, g = 0.5, 9.81
+    E = lambda x: (2.0 / 3.0) * l * l * x[3] ** 2 - g * l * np.cos(x[2])
+    rng = np.random.default_rng(4)
+    for _ in range(3):
+        x0 = np.array([0.0, 0.7, rng.uniform(-3, 3), rng.uniform(-4, 4)])
+        sol = _flow(su, x0, [0.7], 2.0)
+        xe = sol.y[:, -1]
+        assert abs(E(xe) - E(x0)) < 1e-8
+        assert abs(xe[0] - 0.7 * 2.0) < 1e-8
+    sol = _flow(su, np.array([0.0, 0.0, 0.01, 0.0]), [0.0], 3.0)
+    t = np.linspace(0, 3, 300001)
+    th = sol.sol(t)[2]
+    up = t[1:][(th[:-1] < 0) & (th[1:] >= 0)]           # upward zero crossings
+    assert np.allclose(np.diff(up), 2 * np.pi * np.sqrt(4 * l / (3 * g)), rtol=1e-4)
+
+
+def test_swingup_pivot_acceleration_drives_the_pole():
+    """Power balance in the cart's frame: the pseudo-force -m pddot on the centre of mass
+    (lever l cos theta) changes the pole's energy at the rate -l pddot thetadot cos theta;
+    and a hanging pole swings backwards (theta < 0) when the cart accelerates forwards."""
+    su = _swingup()
+    l, g = 0.5, 9.81
+
+    def f(t, z):
+        x = z[:4]
+        xd = su.xdot(x[None, :], np.array([[2.0 * np.sin(3 * t)]]))[0]
+        return np.concatenate([xd, [-l * xd[1] * x[3] * np.cos(x[2])]])
+
+    rng = np.random.default_rng(5)
+    for _ in range(3):
+        x0 = rng.uniform(-2, 2, 4)
+        sol = solve_ivp(f, (0, 2), np.concatenate([x0, [0.0]]), rtol=1e-11, atol=1e-12)
+        xe, work = sol.y[:4, -1], sol.y[4, -1]
+        E = lambda x: (2.0 / 3.0) * l * l * x[3] ** 2 - g * l * np.cos(x[2])
+        assert abs(E(xe) - E(x0) - work) < 1e-7
+    sol = _flow(su, np.zeros(4), [1.0], 0.1)
+    assert sol.y[2, -1] < 0 and sol.y[1, -1] > 0
+
+
+def test_swingup_cost_hanging_and_upright():
+    """The pole hanging at rest costs 500 (1 + 1)^2 = 2000 per step (the running cost the
+    paper reports when the pole is never swung up); upright at rest costs 0."""
+    su = _swingup()
+    assert su.q(np.zeros((1, 4)))[0] == 2000.0
+    assert su.q(np.array([[0.0, 0.0, np.pi, 0.0]]))[0] < 1e-20
+    assert np.array_equal(su.q(np.array([[2.0, 0.0, np.pi, 0.0]])), su.q(np.array([[-2.0, 0.0, np.pi, 0.0]])))

@@ -30,8 +30,10 @@ SYS_CARTPOLE = 1
 SYS_BICYCLE = 2
 SYS_QUADROTOR = 3
 SYS_QUADROTOR_MLP = 4
+SYS_CARTPOLE_SWINGUP = 5
 SYSTEM_NAMES = {SYS_LINEAR: "linear", SYS_CARTPOLE: "cartpole", SYS_BICYCLE: "bicycle",
-                SYS_QUADROTOR: "quadrotor", SYS_QUADROTOR_MLP: "quadrotor_mlp"}
+                SYS_QUADROTOR: "quadrotor", SYS_QUADROTOR_MLP: "quadrotor_mlp",
+                SYS_CARTPOLE_SWINGUP: "cartpole_swingup"}
 
 # Seeds of the input streams (builder-choice, frozen).
 SEED_X0 = 100
@@ -147,6 +149,27 @@ def cartpole(nu: float = 1.0, K: int = 1000, T: int = 100, x0_index: int = 0) ->
                     u_init=np.zeros(1), params=params, x0=x0, control_steps=200)
 
 
+SWINGUP_DT = 0.02          # the controller's 50 Hz re-optimisation period (Section V)
+SWINGUP_NOISE = 0.01       # 1/sqrt(rho) of the swing-up experiment (Section V-A)
+
+
+def cartpole_swingup(nu: float = 1.0, K: int = 1000, T: int = 50, control_steps: int = 500) -> Workload:
+    """The cart-pole swing-up of Section V-A: velocity-command cart (pddot = 10 (u - pdot)),
+    q = p^2 + 500 (1 + cos theta)^2 + thetadot^2 + pdot^2, R = 1, 1/sqrt(rho) = 0.01,
+    1 s horizon (T = 50 at dt = 0.02), 10 s run (500 control steps), pole hanging at rest.
+
+    The per-step perturbation is du = (1/sqrt(rho)) eps / sqrt(dt) (Section III-C), so
+    Sigma = 1e-4 / dt = 5e-3; lambda follows the noise-cost coupling Sigma = lambda R^-1,
+    lambda = 5e-3 in the per-step cost units used here (the continuous-time lambda = R / rho
+    = 1e-4 divided by dt).  Pole half-length 0.5 m and g = 9.81 (builder-choice: the paper
+    gives neither the pole's equation nor its length)."""
+    sigma = SWINGUP_NOISE ** 2 / SWINGUP_DT
+    params = dict(gain=10.0, half_length=0.5, gravity=9.81, w_pos=1.0, w_angle=500.0, w_vel=1.0, w_rate=1.0)
+    return Workload(name="cartpole_swingup", system=SYS_CARTPOLE_SWINGUP, n=4, m=1, K=K, T=T, dt=SWINGUP_DT,
+                    sigma=np.array([[sigma]]), nu=nu, lam=sigma * 1.0, R=np.array([[1.0]]),
+                    u_init=np.zeros(1), params=params, x0=np.zeros(4), control_steps=control_steps)
+
+
 # Temperatures not given for these systems: calibrated so that the effective sample size is
 # 5 % of K at iteration 0 from the initial state (tests/golden/calibrate_lambda.py).
 BICYCLE_LAMBDA = 130.0
@@ -176,19 +199,24 @@ QUAD_HOVER = QUAD_MASS * QUAD_GRAVITY / 4.0
 QUADROTOR_LAMBDA = {1.0: 410.0, 2.0: 420.0, 4.0: 460.0}
 
 
-def quadrotor_params(obstacles: Optional[np.ndarray] = None) -> Dict:
+QUAD_CRASH_COST = 1000.0    # the crash indicator's weight in the quadrotor cost (Section V-C)
+
+
+def quadrotor_params(obstacles: Optional[np.ndarray] = None, crash_cost: float = 0.0) -> Dict:
     """'+' rotor layout, arm 0.2 m, yaw-torque coefficient 0.01 m, inertia diag(0.01, 0.01, 0.02).
 
-    q = w_goal * |p - goal|^2 + w_obs * sum_j max(0, (r_j + margin)^2 - |p - c_j|^2)^2."""
+    q = w_goal * |p - goal|^2 + w_obs * sum_j max(0, (r_j + margin)^2 - |p - c_j|^2)^2,
+    plus crash_cost * C (crash indicator, ground at z = 0) when crash_cost > 0."""
     if obstacles is None:
         obstacles = obstacle_field()
     return dict(mass=QUAD_MASS, gravity=QUAD_GRAVITY, arm=0.2, yaw_coef=0.01,
                 inertia=np.array([0.01, 0.01, 0.02]), goal=np.array([8.0, 0.0, 1.5]),
-                w_goal=1.0, w_obs=1000.0, obs_margin=0.1, obstacles=obstacles)
+                w_goal=1.0, w_obs=1000.0, obs_margin=0.1, obstacles=obstacles,
+                crash_cost=crash_cost, ground_z=0.0)
 
 
 def quadrotor(nu: float = 2.0, K: int = 16384, T: int = 150, lam: Optional[float] = None,
-              obstacles: Optional[np.ndarray] = None) -> Workload:
+              obstacles: Optional[np.ndarray] = None, crash: bool = False) -> Workload:
     """Quadrotor rigid body: state (p, v, roll/pitch/yaw, body rates), four rotor thrusts.
 
     Mass 1.0, inertia diag(0.01, 0.01, 0.02), dt = 0.01, R = 0.1 I, Sigma = 0.25 I N^2
@@ -199,7 +227,8 @@ def quadrotor(nu: float = 2.0, K: int = 16384, T: int = 150, lam: Optional[float
     x0[2] = 1.5
     return Workload(name="quadrotor", system=SYS_QUADROTOR, n=12, m=4, K=K, T=T, dt=0.01,
                     sigma=0.25 * np.eye(4), nu=nu, lam=lam, R=0.1 * np.eye(4),
-                    u_init=np.full(4, QUAD_HOVER), params=quadrotor_params(obstacles), x0=x0)
+                    u_init=np.full(4, QUAD_HOVER),
+                    params=quadrotor_params(obstacles, QUAD_CRASH_COST if crash else 0.0), x0=x0)
 
 
 def quadrotor_mlp(net, nu: float = 2.0, K: int = 16384, T: int = 100, lam: Optional[float] = None) -> Workload:
