@@ -30,7 +30,8 @@ METRIC = "rollout-steps/sec (K*T) and MPPI iters/sec; p50/p99 step latency batch
 # Algorithmic operations per rollout-step of the rollout kernel (FMA = 2, every other
 # FP32/FP64 arithmetic op, transcendental and Philox integer op = 1).  Derivation in
 # DESIGN.md ("Roofline").
-ALG_OPS_PER_ROLLOUT_STEP = {"cartpole": 87, "bicycle": 164, "quadrotor": 740, "linear": 90}
+ALG_OPS_PER_ROLLOUT_STEP = {"cartpole": 87, "bicycle": 164, "quadrotor": 740, "linear": 90,
+                            "cartpole_swingup": 77, "quadrotor_crash": 1064}
 # MLP [16 -> 128 -> 128 -> 12]: 2 (16*128 + 128*128 + 128*12) FLOP per rollout-step on BF16 MFMA.
 MLP_FLOP_PER_ROLLOUT_STEP = 2 * (16 * 128 + 128 * 128 + 128 * 12)
 BF16_MFMA_PEAK_TFLOPS = 2500.0
@@ -76,6 +77,10 @@ def make_workload(name):
         return W.cartpole(nu=2.0).replace(seed=0)
     if name == "quadrotor":
         return W.quadrotor(nu=2.0).replace(seed=0)
+    if name == "quadrotor_crash":
+        return W.quadrotor(nu=2.0, crash=True).replace(seed=0, name="quadrotor_crash")
+    if name == "swingup":
+        return W.cartpole_swingup(nu=1000.0, K=4096).replace(seed=0)
     if name == "quadrotor_mlp":
         return W.quadrotor_mlp(trained_mlp(), nu=2.0, K=16384, T=100).replace(seed=0)
     raise SystemExit(f"unknown workload {name}")

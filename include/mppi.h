@@ -55,7 +55,8 @@ typedef enum {
   MPPI_SYS_CARTPOLE = 1,      /* cart with uniform pole, force input             */
   MPPI_SYS_BICYCLE = 2,       /* kinematic bicycle on a bilinear cost map        */
   MPPI_SYS_QUADROTOR = 3,     /* 12-state rigid-body quadrotor, spherical obstacles */
-  MPPI_SYS_QUADROTOR_MLP = 4  /* quadrotor cost, dynamics by a learned MLP (mppi_mlp) */
+  MPPI_SYS_QUADROTOR_MLP = 4, /* quadrotor cost, dynamics by a learned MLP (mppi_mlp) */
+  MPPI_SYS_CARTPOLE_SWINGUP = 5 /* velocity-command cart-pole of the swing-up task    */
 } mppi_system;
 
 /* MPPI_SYS_LINEAR: n_state <= 4, n_ctrl in {1, 2, 4}.  A (n x n), B (n x m), Q (n x n),
@@ -75,6 +76,16 @@ typedef struct {
   double qf_diag[4];
 } mppi_cartpole_params;
 
+/* MPPI_SYS_CARTPOLE_SWINGUP (Section V-A): state (p, pdot, theta, thetadot), theta = 0
+ * hanging down, theta = pi upright, n = 4, m = 1; the control is a desired cart velocity.
+ * pddot = gain (u - pdot); thetaddot = -(3 / (4 l)) (g sin theta + pddot cos theta)
+ * (uniform pole of half-length l on the accelerated pivot).
+ * q = w_pos p^2 + w_angle (1 + cos theta)^2 + w_rate thetadot^2 + w_vel pdot^2, phi = 0. */
+typedef struct {
+  double gain, half_length, gravity;
+  double w_pos, w_angle, w_vel, w_rate;
+} mppi_swingup_params;
+
 /* MPPI_SYS_BICYCLE: state (x, y, yaw, v, delta), controls (accel, steer rate), n = 5, m = 2.
  *   x' = v cos yaw, y' = v sin yaw, yaw' = v tan(clamp(delta, +-steer_limit)) / wheelbase,
  *   v' = a, delta' = omega   (steer_limit <= 0: no clamp)
@@ -93,7 +104,10 @@ typedef struct {
  *   euler' = W(euler)^-1 w,  w' = J^-1 (tau - w x J w),
  *   tau = (arm (f2 - f4), arm (f3 - f1), yaw_coef (f1 - f2 + f3 - f4)),  J = diag(inertia)
  * q = w_goal |p - goal|^2 + w_obs sum_j max(0, (r_j + obs_margin)^2 - |p - c_j|^2)^2,
- * phi = 0.  obstacles: n_obstacles x 4 (cx, cy, cz, r) FP64, copied; n_obstacles <= 256. */
+ * phi = 0.  obstacles: n_obstacles x 4 (cx, cy, cz, r) FP64, copied; n_obstacles <= 256.
+ * crash_cost > 0 adds the crash indicator C (Section V-C): C = 1 once p_z < ground_z or
+ * |p - c_j| < r_j; from then on the rollout stops simulating, the vehicle stays where it
+ * is and every remaining step adds crash_cost (not with MPPI_SYS_QUADROTOR_MLP). */
 typedef struct {
   double mass, gravity, arm, yaw_coef;
   double inertia[3];
@@ -101,6 +115,8 @@ typedef struct {
   double w_goal, w_obs, obs_margin;
   int32_t n_obstacles;
   const double *obstacles;
+  double crash_cost;          /* crash indicator C (Section V-C); 0 disables it          */
+  double ground_z;            /* ground plane height for C                               */
 } mppi_quadrotor_params;
 
 /* MPPI_SYS_QUADROTOR_MLP: the quadrotor's cost with dynamics x <- x + MLP(x, u)
@@ -135,7 +151,20 @@ typedef struct {
   void *stream;               /* hipStream_t to run on; NULL => the library makes its own  */
   void *workspace;            /* optional caller-owned device memory for all device state  */
   uint64_t workspace_bytes;   /* its size; must be >= mppi_workspace_bytes()               */
+  const double *nu_diag;      /* m per-dimension exploration factors (a diagonal covariance */
+                              /* change A = diag(sqrt(nu_j)), Section III-A); NULL => nu.   */
+                              /* The quadratic likelihood-ratio term becomes               */
+                              /* du'(R - A^-1 R A^-1) du / 2; copied                       */
+  int32_t weighting;          /* MPPI_WEIGHT_PATH or MPPI_WEIGHT_COST_TO_GO                */
+  int32_t reserved;           /* must be 0                                                 */
 } mppi_config;
+
+/* Weights of the update law (Section III-C).  PATH: one total path cost per sample weights
+ * every time step (Algorithm 1's forward-accumulated cost).  COST_TO_GO: time step i is
+ * weighted by each sample's cost from step i onward, as the update law's S(tau_{i,k}) reads,
+ * with a per-step minimum and normaliser; it adds T x K FP64 of workspace and is not
+ * available with MPPI_SYS_QUADROTOR_MLP or through the server (MPPI_EINVAL). */
+enum { MPPI_WEIGHT_PATH = 0, MPPI_WEIGHT_COST_TO_GO = 1 };
 
 typedef struct mppi_ctx mppi_ctx;
 

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libmppi.so")
 
 ABI_VERSION = 1
 OK, EINVAL, ENOMEM, EDEVICE, EBUSY, ENUMERIC, ENOTFOUND = 0, -1, -2, -3, -4, -5, -6
-SYS_LINEAR, SYS_CARTPOLE, SYS_BICYCLE, SYS_QUADROTOR, SYS_QUADROTOR_MLP = 0, 1, 2, 3, 4
+SYS_LINEAR, SYS_CARTPOLE, SYS_BICYCLE, SYS_QUADROTOR, SYS_QUADROTOR_MLP, SYS_CARTPOLE_SWINGUP = 0, 1, 2, 3, 4, 5
 
 _dp = C.POINTER(C.c_double)
 _fp = C.POINTER(C.c_float)
@@ -46,6 +46,10 @@ class CartPoleParams(C.Structure):
                 ("gravity", C.c_double), ("q_diag", C.c_double * 4), ("qf_diag", C.c_double * 4)]
 
 
+class SwingUpParams(C.Structure):
+    _fields_ = [(k, C.c_double) for k in ("gain", "half_length", "gravity", "w_pos", "w_angle", "w_vel", "w_rate")]
+
+
 class BicycleParams(C.Structure):
     _fields_ = [("wheelbase", C.c_double), ("v_target", C.c_double), ("w_speed", C.c_double),
                 ("cell_size", C.c_double), ("steer_limit", C.c_double), ("map_w", C.c_int32),
@@ -56,7 +60,7 @@ class QuadrotorParams(C.Structure):
     _fields_ = [("mass", C.c_double), ("gravity", C.c_double), ("arm", C.c_double), ("yaw_coef", C.c_double),
                 ("inertia", C.c_double * 3), ("goal", C.c_double * 3), ("w_goal", C.c_double),
                 ("w_obs", C.c_double), ("obs_margin", C.c_double), ("n_obstacles", C.c_int32),
-                ("obstacles", _dp)]
+                ("obstacles", _dp), ("crash_cost", C.c_double), ("ground_z", C.c_double)]
 
 
 class QuadrotorMlpParams(C.Structure):
@@ -69,7 +73,8 @@ class Config(C.Structure):
                 ("nu", C.c_double), ("sigma", _dp), ("R", _dp), ("u_init", _dp), ("u_nominal0", _dp),
                 ("params", C.c_void_p), ("params_bytes", C.c_uint64), ("seed", C.c_uint64),
                 ("device", C.c_int32), ("use_graph", C.c_int32), ("stream", C.c_void_p),
-                ("workspace", C.c_void_p), ("workspace_bytes", C.c_uint64)]
+                ("workspace", C.c_void_p), ("workspace_bytes", C.c_uint64), ("nu_diag", _dp),
+                ("weighting", C.c_int32), ("reserved", C.c_int32)]
 
 
 class ServerConfig(C.Structure):
@@ -179,6 +184,9 @@ def make_params(system: int, params: Dict, keep: list):
         p.q_diag[:] = list(_f64(params["q_diag"]))
         p.qf_diag[:] = list(_f64(params["qf_diag"]))
         return p
+    if system == SYS_CARTPOLE_SWINGUP:
+        return SwingUpParams(*[float(params[k]) for k in ("gain", "half_length", "gravity", "w_pos", "w_angle",
+                                                           "w_vel", "w_rate")])
     if system == SYS_BICYCLE:
         m = np.ascontiguousarray(np.asarray(params["map"], dtype=np.float32))
         keep.append(m)
@@ -193,6 +201,7 @@ def make_params(system: int, params: Dict, keep: list):
         q.w_goal, q.w_obs, q.obs_margin = params["w_goal"], params["w_obs"], params["obs_margin"]
         q.n_obstacles = ob.shape[0]
         q.obstacles = _ptr(ob) if ob.shape[0] else None
+        q.crash_cost, q.ground_z = float(params.get("crash_cost", 0.0)), float(params.get("ground_z", 0.0))
         if system == SYS_QUADROTOR:
             return q
         mlp = params["mlp"]
@@ -201,16 +210,23 @@ def make_params(system: int, params: Dict, keep: list):
     raise ValueError(f"unknown system {system}")
 
 
-def make_config(*, system: int, n: int, m: int, K: int, T: int, dt: float, lam: float, nu: float,
+WEIGHT_PATH, WEIGHT_COST_TO_GO = 0, 1
+
+
+def make_config(*, system: int, n: int, m: int, K: int, T: int, dt: float, lam: float, nu,
                 sigma, R=None, u_init, params: Dict, u_nominal0=None, seed: int = 0, device: int = 0,
-                use_graph: bool = True):
+                use_graph: bool = True, weighting: int = 0):
     """Fill an mppi_config; returns (config, list of arrays that must stay alive)."""
     keep = []
     sig = _f64(sigma).reshape(m, m)
     Rm = None if R is None else _f64(R).reshape(m, m)
     ui = _f64(u_init).reshape(m)
     un = None if u_nominal0 is None else _f64(u_nominal0).reshape(T, m)
-    keep += [sig, Rm, ui, un]
+    nu_vec = None
+    if np.ndim(nu) > 0:                 # per-dimension exploration factors
+        nu_vec = _f64(nu).reshape(m)
+        nu = float(nu_vec.max())
+    keep += [sig, Rm, ui, un, nu_vec]
     prm = make_params(system, params, keep)
     keep.append(prm)
     cfg = Config()
@@ -223,20 +239,22 @@ def make_config(*, system: int, n: int, m: int, K: int, T: int, dt: float, lam: 
     cfg.seed = seed & 0xFFFFFFFFFFFFFFFF
     cfg.device = device
     cfg.use_graph = 1 if use_graph else 0
+    cfg.nu_diag = _ptr(nu_vec)
+    cfg.weighting = weighting
     return cfg, keep
 
 
 class Controller:
     """One MPPI controller context (mppi_create ... mppi_destroy)."""
 
-    def __init__(self, *, system: int, n: int, m: int, K: int, T: int, dt: float, lam: float, nu: float,
+    def __init__(self, *, system: int, n: int, m: int, K: int, T: int, dt: float, lam: float, nu,
                  sigma, R=None, u_init, params: Dict, u_nominal0=None, seed: int = 0, device: int = 0,
-                 use_graph: bool = True, torch_stream=None, torch_workspace: bool = False):
+                 use_graph: bool = True, weighting: int = 0, torch_stream=None, torch_workspace: bool = False):
         lib = load()
         self.n, self.m, self.K, self.T = n, m, K, T
         cfg, self._keep = make_config(system=system, n=n, m=m, K=K, T=T, dt=dt, lam=lam, nu=nu, sigma=sigma, R=R,
                                       u_init=u_init, params=params, u_nominal0=u_nominal0, seed=seed,
-                                      device=device, use_graph=use_graph)
+                                      device=device, use_graph=use_graph, weighting=weighting)
         self._workspace = None
         if torch_stream is not None:
             cfg.stream = C.c_void_p(torch_stream.cuda_stream)

@@ -99,6 +99,7 @@ static int expected_dims(int sys, int *n, int *m) {
   switch (sys) {
     case MPPI_SYS_LINEAR: return 0;  // checked separately
     case MPPI_SYS_CARTPOLE: *n = 4; *m = 1; return 1;
+    case MPPI_SYS_CARTPOLE_SWINGUP: *n = 4; *m = 1; return 1;
     case MPPI_SYS_BICYCLE: *n = 5; *m = 2; return 1;
     case MPPI_SYS_QUADROTOR: *n = 12; *m = 4; return 1;
     case MPPI_SYS_QUADROTOR_MLP: *n = 12; *m = 4; return 1;
@@ -131,6 +132,14 @@ int validate_config(const mppi_config *c) {
   if (!finite_all(c->sigma, mm * mm)) return fail(MPPI_EINVAL, "sigma has non-finite entries");
   if (c->R && !finite_all(c->R, mm * mm)) return fail(MPPI_EINVAL, "R has non-finite entries");
   if (!finite_all(c->u_init, mm)) return fail(MPPI_EINVAL, "u_init has non-finite entries");
+  if (c->nu_diag)
+    for (int j = 0; j < mm; ++j)
+      if (!(c->nu_diag[j] > 0.0) || !std::isfinite(c->nu_diag[j])) return fail(MPPI_EINVAL, "nu_diag entries must be finite and > 0");
+  if (c->weighting != MPPI_WEIGHT_PATH && c->weighting != MPPI_WEIGHT_COST_TO_GO)
+    return fail(MPPI_EINVAL, "unknown weighting %d", c->weighting);
+  if (c->reserved != 0) return fail(MPPI_EINVAL, "reserved must be 0");
+  if (c->weighting == MPPI_WEIGHT_COST_TO_GO && c->system == MPPI_SYS_QUADROTOR_MLP)
+    return fail(MPPI_EINVAL, "cost-to-go weighting is not available with the learned dynamics");
   if (c->u_nominal0 && !finite_all(c->u_nominal0, c->T * mm)) return fail(MPPI_EINVAL, "u_nominal0 has non-finite entries");
   for (int i = 0; i < mm; ++i)
     for (int j = 0; j < i; ++j)
@@ -145,6 +154,7 @@ int validate_config(const mppi_config *c) {
   switch (c->system) {
     case MPPI_SYS_LINEAR: want = sizeof(mppi_linear_params); break;
     case MPPI_SYS_CARTPOLE: want = sizeof(mppi_cartpole_params); break;
+    case MPPI_SYS_CARTPOLE_SWINGUP: want = sizeof(mppi_swingup_params); break;
     case MPPI_SYS_BICYCLE: want = sizeof(mppi_bicycle_params); break;
     case MPPI_SYS_QUADROTOR: want = sizeof(mppi_quadrotor_params); break;
     case MPPI_SYS_QUADROTOR_MLP: want = sizeof(mppi_quadrotor_mlp_params); break;
@@ -154,6 +164,10 @@ int validate_config(const mppi_config *c) {
   if (c->system == MPPI_SYS_LINEAR) {
     const auto *p = (const mppi_linear_params *)c->params;
     if (!p->A || !p->B || !p->Q || !p->Qf) return fail(MPPI_EINVAL, "linear params: NULL matrix");
+  } else if (c->system == MPPI_SYS_CARTPOLE_SWINGUP) {
+    const auto *p = (const mppi_swingup_params *)c->params;
+    if (!(p->half_length > 0) || !std::isfinite(p->half_length) || !std::isfinite(p->gain) || !std::isfinite(p->gravity))
+      return fail(MPPI_EINVAL, "swing-up params: half_length must be finite and > 0, gain and gravity finite");
   } else if (c->system == MPPI_SYS_BICYCLE) {
     const auto *p = (const mppi_bicycle_params *)c->params;
     if (!p->map || p->map_w < 2 || p->map_h < 2 || p->map_w > 16384 || p->map_h > 16384)
@@ -170,6 +184,10 @@ int validate_config(const mppi_config *c) {
       return fail(MPPI_EINVAL, "quadrotor params: mass and inertia must be > 0");
     if (c->system == MPPI_SYS_QUADROTOR_MLP && !((const mppi_quadrotor_mlp_params *)c->params)->mlp)
       return fail(MPPI_EINVAL, "quadrotor_mlp params: mlp is NULL");
+    if (!(p->crash_cost >= 0) || !std::isfinite(p->crash_cost) || !std::isfinite(p->ground_z))
+      return fail(MPPI_EINVAL, "quadrotor params: crash_cost must be finite and >= 0, ground_z finite");
+    if (c->system == MPPI_SYS_QUADROTOR_MLP && p->crash_cost != 0)
+      return fail(MPPI_EINVAL, "the crash indicator is not available with the learned dynamics");
   }
   return MPPI_OK;
 }
@@ -187,6 +205,7 @@ void compute_layout(const mppi_config *c, Layout *L) {
     case MPPI_SYS_QUADROTOR_MLP: roll_per_block = 64; break;
     case MPPI_SYS_LINEAR: roll_per_block = kBlock / LinearSys<1>::kLPS; break;
     case MPPI_SYS_CARTPOLE: roll_per_block = kBlock / CartPoleSys::kLPS; break;
+    case MPPI_SYS_CARTPOLE_SWINGUP: roll_per_block = kBlock / SwingUpSys::kLPS; break;
     case MPPI_SYS_BICYCLE: roll_per_block = kBlock / BicycleSys::kLPS; break;
     case MPPI_SYS_QUADROTOR: roll_per_block = kBlock / QuadrotorSys::kLPS; break;
   }
@@ -201,9 +220,12 @@ void compute_layout(const mppi_config *c, Layout *L) {
   L->off_U32 = take((uint64_t)L->TM * 4);
   L->off_S = take((uint64_t)K * 8);
   L->off_blk_min = take((uint64_t)L->n_roll_blocks * 8);
-  L->off_eta_part = take((uint64_t)L->n_kc * 8);
+  const bool ctg = c->weighting == MPPI_WEIGHT_COST_TO_GO;
+  L->off_eta_part = take((uint64_t)L->n_kc * (ctg ? T : 1) * 8);
   L->off_part = take((uint64_t)L->n_kc * L->G * 4 * 8);
   L->off_dbg = take((uint64_t)(2 + L->TM) * 8);
+  L->off_pre = ctg ? take((uint64_t)T * K * 8) : 0;
+  L->off_rho_step = ctg ? take((uint64_t)T * 8) : 0;
   uint64_t sys_bytes = 0;
   if (c->system == MPPI_SYS_BICYCLE) {
     const auto *p = (const mppi_bicycle_params *)c->params;
@@ -212,7 +234,7 @@ void compute_layout(const mppi_config *c, Layout *L) {
     const mppi_quadrotor_params *p = c->system == MPPI_SYS_QUADROTOR
                                          ? (const mppi_quadrotor_params *)c->params
                                          : &((const mppi_quadrotor_mlp_params *)c->params)->quad;
-    sys_bytes = (uint64_t)(p->n_obstacles > 0 ? p->n_obstacles : 1) * 16;
+    sys_bytes = (uint64_t)(p->n_obstacles > 0 ? p->n_obstacles : 1) * 20;   // float4 + r^2 each
   }
   L->off_sys = take(sys_bytes > 0 ? sys_bytes : 16);
   L->off_extra = o;
@@ -270,6 +292,16 @@ static int build_params(mppi_ctx *c) {
       c->cartpole = cp;
       break;
     }
+    case MPPI_SYS_CARTPOLE_SWINGUP: {
+      const auto *p = (const mppi_swingup_params *)cfg.params;
+      SwingUpSys::Params sp;
+      const double k = 3.0 / (4.0 * p->half_length);
+      sp.gain = (float)p->gain; sp.k = (float)k; sp.g = (float)p->gravity;
+      sp.dgain = p->gain; sp.dk = k; sp.dg = p->gravity;
+      sp.wp = (float)p->w_pos; sp.wa = (float)p->w_angle; sp.wv = (float)p->w_vel; sp.wr = (float)p->w_rate;
+      c->swingup = sp;
+      break;
+    }
     case MPPI_SYS_BICYCLE: {
       const auto *p = (const mppi_bicycle_params *)cfg.params;
       BicycleSys::Params bp;
@@ -300,12 +332,15 @@ static int build_params(mppi_ctx *c) {
       }
       qp.wg = (float)p->w_goal; qp.wo = (float)p->w_obs; qp.margin = (float)p->obs_margin;
       qp.n_obs = p->n_obstacles;
-      std::vector<float> ob((size_t)(p->n_obstacles > 0 ? p->n_obstacles : 1) * 4, 0.f);
-      for (int j = 0; j < p->n_obstacles; ++j) {
+      qp.crash = (float)p->crash_cost; qp.ground = (float)p->ground_z;
+      const int no = p->n_obstacles;
+      std::vector<float> ob((size_t)(no > 0 ? no : 1) * 5, 0.f);
+      for (int j = 0; j < no; ++j) {
         const double *o = p->obstacles + 4 * j;
         const double rr = o[3] + p->obs_margin;
         ob[4 * j + 0] = (float)o[0]; ob[4 * j + 1] = (float)o[1]; ob[4 * j + 2] = (float)o[2];
         ob[4 * j + 3] = (float)(rr * rr);
+        ob[4 * (size_t)no + j] = (float)(o[3] * o[3]);
       }
       qp.obs = (const float4 *)(c->base + c->L.off_sys);
       HIP_TRY(hipMemcpy((void *)qp.obs, ob.data(), ob.size() * 4, hipMemcpyHostToDevice));
@@ -354,15 +389,18 @@ static IterArgs make_iter_args(mppi_ctx *c, const double *x0) {
   a.iter = (const uint64_t *)(c->base + L.off_iter);
   a.part = (double *)(c->base + L.off_part);
   a.eta_part = (double *)(c->base + L.off_eta_part);
+  if (c->cfg.weighting == MPPI_WEIGHT_COST_TO_GO) {
+    a.pre = (double *)(c->base + L.off_pre);
+    a.rho_step = (double *)(c->base + L.off_rho_step);
+  }
   a.key0 = (uint32_t)c->cfg.seed;
   a.key1 = (uint32_t)(c->cfg.seed >> 32);
   a.n = c->cfg.n_state;
   a.K = c->cfg.K; a.T = c->cfg.T; a.m = c->cfg.n_ctrl; a.G = L.G;
   a.n_roll_blocks = L.n_roll_blocks; a.n_kc = L.n_kc;
   a.dt = (float)c->cfg.dt;
-  a.lr_quad = (float)(0.5 * (1.0 - 1.0 / c->cfg.nu));
   const int m = c->cfg.n_ctrl;
-  for (int i = 0; i < m * m; ++i) { a.Ls[i] = (float)c->Ls[i]; a.R[i] = (float)c->R[i]; }
+  for (int i = 0; i < m * m; ++i) { a.Ls[i] = (float)c->Ls[i]; a.R[i] = (float)c->R[i]; a.Mq[i] = (float)c->Mq[i]; }
   a.inv_lambda = 1.0 / c->cfg.lambda;
   return a;
 }
@@ -382,6 +420,7 @@ static FinalizeArgs make_fin_args(mppi_ctx *c, double *u0_out, int emit) {
   f.u0_out = u0_out;
   f.T = c->cfg.T; f.m = c->cfg.n_ctrl; f.G = L.G; f.n_roll_blocks = L.n_roll_blocks; f.n_kc = L.n_kc;
   f.emit = emit;
+  f.ctg = c->cfg.weighting == MPPI_WEIGHT_COST_TO_GO;
   for (int i = 0; i < 16; ++i) f.Ls[i] = c->Ls[i];
   for (int j = 0; j < c->cfg.n_ctrl; ++j) f.u_init[j] = c->u_init[j];
   return f;
@@ -434,6 +473,7 @@ static void launch_finalize(mppi_ctx *c, const FinalizeArgs &f, double *plant_x,
       else launch_finalize_plant<LinearSys<4>>(c, f, plant_x, c->linear, s);
       break;
     case MPPI_SYS_CARTPOLE: launch_finalize_plant<CartPoleSys>(c, f, plant_x, c->cartpole, s); break;
+    case MPPI_SYS_CARTPOLE_SWINGUP: launch_finalize_plant<SwingUpSys>(c, f, plant_x, c->swingup, s); break;
     case MPPI_SYS_BICYCLE: launch_finalize_plant<BicycleSys>(c, f, plant_x, c->bicycle, s); break;
     default: launch_finalize_plant<QuadrotorSys>(c, f, plant_x, c->quad, s); break;
   }
@@ -452,6 +492,7 @@ int enqueue_iterations(mppi_ctx *c, const double *x0_dev, int n_iters, double *u
         else rc = launch_rollout<LinearSys<4>>(c, a, c->linear_as<4>(), s);
         break;
       case MPPI_SYS_CARTPOLE: rc = launch_rollout<CartPoleSys>(c, a, c->cartpole, s); break;
+      case MPPI_SYS_CARTPOLE_SWINGUP: rc = launch_rollout<SwingUpSys>(c, a, c->swingup, s); break;
       case MPPI_SYS_BICYCLE: rc = launch_rollout<BicycleSys>(c, a, c->bicycle, s); break;
       case MPPI_SYS_QUADROTOR: rc = launch_rollout<QuadrotorSys>(c, a, c->quad, s); break;
       case MPPI_SYS_QUADROTOR_MLP: rc = launch_mlp_rollout(c, a, s); break;
@@ -459,7 +500,12 @@ int enqueue_iterations(mppi_ctx *c, const double *x0_dev, int n_iters, double *u
     if (rc) return rc;
     prof_end(c, s, 0, t0);
     t0 = prof_begin(c, s);
-    hipLaunchKernelGGL(update_kernel, dim3(c->L.n_kc, (c->L.G + kUpdGroups - 1) / kUpdGroups), dim3(kBlock), 0, s, a);
+    if (a.pre) {
+      hipLaunchKernelGGL(stepmin_kernel, dim3(c->cfg.T), dim3(kBlock), 0, s, a);
+      hipLaunchKernelGGL(update_ctg_kernel, dim3(c->L.n_kc, (c->L.G + kUpdGroups - 1) / kUpdGroups), dim3(kBlock), 0, s, a);
+    } else {
+      hipLaunchKernelGGL(update_kernel, dim3(c->L.n_kc, (c->L.G + kUpdGroups - 1) / kUpdGroups), dim3(kBlock), 0, s, a);
+    }
     prof_end(c, s, 1, t0);
     const FinalizeArgs f = make_fin_args(c, u0_dev, it == n_iters - 1);
     t0 = prof_begin(c, s);
@@ -496,6 +542,7 @@ size_t ctx_rollout_lds(const mppi_ctx *c) {
   switch (c->cfg.system) {
     case MPPI_SYS_LINEAR: return rollout_lds_bytes<LinearSys<1>>(c);
     case MPPI_SYS_CARTPOLE: return rollout_lds_bytes<CartPoleSys>(c);
+    case MPPI_SYS_CARTPOLE_SWINGUP: return rollout_lds_bytes<SwingUpSys>(c);
     case MPPI_SYS_BICYCLE: return rollout_lds_bytes<BicycleSys>(c);
     default: return rollout_lds_bytes<QuadrotorSys>(c);
   }
@@ -509,6 +556,7 @@ void fill_desc(mppi_ctx *c, CtrlDesc *d) {
   switch (c->cfg.system) {
     case MPPI_SYS_LINEAR: d->p.lin = c->linear; break;
     case MPPI_SYS_CARTPOLE: d->p.cp = c->cartpole; break;
+    case MPPI_SYS_CARTPOLE_SWINGUP: d->p.su = c->swingup; break;
     case MPPI_SYS_BICYCLE: d->p.bc = c->bicycle; break;
     default: d->p.qd = c->quad; break;
   }
@@ -536,9 +584,12 @@ extern "C" int mppi_create(const mppi_config *cfg, mppi_ctx **out) {
   c->cfg = *cfg;
   const int m = cfg->n_ctrl, T = cfg->T;
   cholesky(cfg->sigma, m, c->L64);
-  const double sq = std::sqrt(cfg->nu);
+  // covariance change A = diag(sqrt(nu_j)) (sqrt(nu) I without per-dimension factors)
+  double sq[4];
+  for (int j = 0; j < m; ++j) sq[j] = std::sqrt(cfg->nu_diag ? cfg->nu_diag[j] : cfg->nu);
   for (int i = 0; i < 16; ++i) c->Ls[i] = 0.0;
-  for (int i = 0; i < m * m; ++i) c->Ls[i] = sq * c->L64[i];
+  for (int r = 0; r < m; ++r)
+    for (int l = 0; l < m; ++l) c->Ls[r * m + l] = sq[r] * c->L64[r * m + l];
   if (cfg->R) {
     for (int i = 0; i < m * m; ++i) c->R[i] = cfg->R[i];
   } else {
@@ -546,8 +597,10 @@ extern "C" int mppi_create(const mppi_config *cfg, mppi_ctx **out) {
     invert(cfg->sigma, m, Si);
     for (int i = 0; i < m * m; ++i) c->R[i] = cfg->lambda * Si[i];
   }
+  for (int r = 0; r < m; ++r)
+    for (int l = 0; l < m; ++l) c->Mq[r * m + l] = 0.5 * c->R[r * m + l] * (1.0 - 1.0 / (sq[r] * sq[l]));
   for (int j = 0; j < m; ++j) c->u_init[j] = cfg->u_init[j];
-  c->cfg.sigma = c->cfg.R = c->cfg.u_init = c->cfg.u_nominal0 = nullptr;  // not kept
+  c->cfg.sigma = c->cfg.R = c->cfg.u_init = c->cfg.u_nominal0 = c->cfg.nu_diag = nullptr;  // not kept
   compute_layout(cfg, &c->L);
   // device memory
   if (cfg->workspace) {
@@ -584,6 +637,7 @@ extern "C" int mppi_create(const mppi_config *cfg, mppi_ctx **out) {
         rc = m == 1 ? prepare_rollout<LinearSys<1>>(c) : (m == 2 ? prepare_rollout<LinearSys<2>>(c) : prepare_rollout<LinearSys<4>>(c));
         break;
       case MPPI_SYS_CARTPOLE: rc = prepare_rollout<CartPoleSys>(c); break;
+      case MPPI_SYS_CARTPOLE_SWINGUP: rc = prepare_rollout<SwingUpSys>(c); break;
       case MPPI_SYS_BICYCLE: rc = prepare_rollout<BicycleSys>(c); break;
       case MPPI_SYS_QUADROTOR: rc = prepare_rollout<QuadrotorSys>(c); break;
       case MPPI_SYS_QUADROTOR_MLP: rc = prepare_mlp_rollout(c); break;
@@ -697,6 +751,7 @@ extern "C" int mppi_plant_step_async(mppi_ctx *c, double *x_dev, const double *u
       else hipLaunchKernelGGL(plant_kernel<LinearSys<4>>, dim3(1), dim3(64), 0, c->stream, x_dev, u_dev, dt, c->cfg.n_state, c->linear_as<4>());
       break;
     case MPPI_SYS_CARTPOLE: hipLaunchKernelGGL(plant_kernel<CartPoleSys>, dim3(1), dim3(64), 0, c->stream, x_dev, u_dev, dt, c->cfg.n_state, c->cartpole); break;
+    case MPPI_SYS_CARTPOLE_SWINGUP: hipLaunchKernelGGL(plant_kernel<SwingUpSys>, dim3(1), dim3(64), 0, c->stream, x_dev, u_dev, dt, c->cfg.n_state, c->swingup); break;
     case MPPI_SYS_BICYCLE: hipLaunchKernelGGL(plant_kernel<BicycleSys>, dim3(1), dim3(64), 0, c->stream, x_dev, u_dev, dt, c->cfg.n_state, c->bicycle); break;
     case MPPI_SYS_QUADROTOR:
     case MPPI_SYS_QUADROTOR_MLP:

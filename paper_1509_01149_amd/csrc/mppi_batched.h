@@ -11,6 +11,7 @@ namespace mppi {
 union SysParams {
   LinearParams lin;
   CartPoleSys::Params cp;
+  SwingUpSys::Params su;
   BicycleSys::Params bc;
   QuadrotorSys::Params qd;
 };
@@ -20,6 +21,7 @@ template <> __device__ __host__ inline const LinearParams &sys_params<LinearSys<
 template <> __device__ __host__ inline const LinearParams &sys_params<LinearSys<2>>(const SysParams &u) { return u.lin; }
 template <> __device__ __host__ inline const LinearParams &sys_params<LinearSys<4>>(const SysParams &u) { return u.lin; }
 template <> __device__ __host__ inline const CartPoleSys::Params &sys_params<CartPoleSys>(const SysParams &u) { return u.cp; }
+template <> __device__ __host__ inline const SwingUpSys::Params &sys_params<SwingUpSys>(const SysParams &u) { return u.su; }
 template <> __device__ __host__ inline const BicycleSys::Params &sys_params<BicycleSys>(const SysParams &u) { return u.bc; }
 template <> __device__ __host__ inline const QuadrotorSys::Params &sys_params<QuadrotorSys>(const SysParams &u) { return u.qd; }
 
@@ -55,7 +57,11 @@ __global__ __launch_bounds__(kBlock) void rollout_batched(const CtrlDesc *__rest
   const int j = find_item(prefix, n, blockIdx.x);
   const WorkItem &w = items[sel[j]];
   const CtrlDesc &d = descs[w.desc];
-  rollout_body<Sys, Sys::kLPS>(d.it, sys_params<Sys>(d.p), w.x0, blockIdx.x - prefix[j], lds4);
+  // block-uniform copies: the per-step constants live in SGPRs instead of being re-read
+  // from the descriptor
+  const IterArgs a = d.it;
+  const typename Sys::Params p = sys_params<Sys>(d.p);
+  rollout_body<Sys, Sys::kLPS>(a, p, w.x0, blockIdx.x - prefix[j], lds4);
 }
 
 static __global__ __launch_bounds__(kBlock) void update_batched(const CtrlDesc *__restrict__ descs,

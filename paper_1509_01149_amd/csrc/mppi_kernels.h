@@ -3,7 +3,8 @@
 //
 //   rollout<Sys>  one lane per sample: draw the perturbations from Philox in registers,
 //                 Euler-step the dynamics over the horizon, accumulate the path cost
-//                 S_k = sum_i [q(x_{i+1}) + (1 - 1/nu)/2 du'R du + u'R du + u'R u/2] + phi
+//                 S_k = sum_i [q(x_{i+1}) + du'Mq du + u'R du + u'R u/2] + phi, where
+//                 Mq = (R - A^-1 R A^-1)/2 and du ~ N(0, A Sigma A) (A = sqrt(nu) I or diagonal)
 //                 (FP32 arithmetic per step, FP64 running sum), write S_k and the block
 //                 minimum.
 //   update        2-D grid over (sample chunk, noise group): rho = min_k S_k,
@@ -30,13 +31,15 @@ struct IterArgs {
   double *blk_min;         // [n_roll_blocks]
   const uint64_t *iter;    // iteration counter (keys the noise)
   double *part;            // [n_kc][G*4] partial sums of w*eps
-  double *eta_part;        // [n_kc]
+  double *eta_part;        // [n_kc] ([n_kc][T] with cost-to-go weights)
+  double *pre;             // cost-to-go weights only: [T][K] sum of the first i step costs, else NULL
+  double *rho_step;        // cost-to-go weights only: [T] min_k of the cost from step i onward
   uint32_t key0, key1;
   int n;                   // state dimension actually present in x0 (<= Sys::N)
   int K, T, m, G;          // G = ceil(T*m/4) noise groups per sample
   int n_roll_blocks, n_kc;
   float dt;
-  float lr_quad;           // (1 - 1/nu)/2
+  float Mq[16];            // 1/2 (R - A^-1 R A^-1): quadratic likelihood-ratio term, m x m
   float Ls[16];            // sqrt(nu) chol(Sigma), row-major m x m (lower)
   float R[16];             // m x m
   double inv_lambda;
@@ -54,7 +57,8 @@ struct FinalizeArgs {
   double *u0_out;          // [m]; written when emit != 0
   int T, m, G, n_roll_blocks, n_kc;
   int emit;                // last iteration of the control step: emit u0 and shift
-  double Ls[16];           // sqrt(nu) chol(Sigma)
+  int ctg;                 // cost-to-go weights: eta_part is [n_kc][T], one normaliser per step
+  double Ls[16];           // A chol(Sigma)
   double u_init[4];
 };
 
@@ -80,7 +84,8 @@ __device__ __forceinline__ float quad_sum(float v) {
 template <class Sys, int LPS>
 __device__ __forceinline__ void rollout_step(const IterArgs &a, const typename Sys::Params &p, const StageView &sv,
                                              const float *sU, const float *sRU, const float *sC, int i, int s,
-                                             int lane_j, const float e[4], float *x, double &S) {
+                                             int lane_j, int k, const float e[4], float *x, double &S, bool &crashed) {
+  if (a.pre && lane_j == 0 && k < a.K) a.pre[(size_t)i * a.K + k] = S;   // cost of steps before i
   constexpr int N = Sys::N, M = Sys::M;
   float du[M], v[M], xd[N];
 #pragma unroll
@@ -92,21 +97,32 @@ __device__ __forceinline__ void rollout_step(const IterArgs &a, const typename S
     v[j] = sU[i * M + j] + t;
   }
   Sys::xdot(p, x, v, xd);
+  if (!crashed) {                                   // a crashed rollout stays where it is
 #pragma unroll
-  for (int r = 0; r < N; ++r) x[r] += a.dt * xd[r];
+    for (int r = 0; r < N; ++r) x[r] += a.dt * xd[r];
+  }
   float quad = 0.f, lin = 0.f;
 #pragma unroll
   for (int r = 0; r < M; ++r) {
     float t = 0.f;
 #pragma unroll
-    for (int j = 0; j < M; ++j) t += a.R[r * M + j] * du[j];
+    for (int j = 0; j < M; ++j) t += a.Mq[r * M + j] * du[j];
     quad += du[r] * t;
     lin += sRU[i * M + r] * du[r];
   }
   float q;
   if constexpr (LPS == 4 && Sys::kSplitCost) q = quad_sum(Sys::q_part(p, sv, x, lane_j, 4));
   else q = Sys::q(p, sv, x);
-  const float qt = q + (a.lr_quad * quad + lin + sC[i]);
+  if constexpr (Sys::kCrash) {
+    if (p.crash > 0.f) {                            // crash indicator: sticky, crash cost per step
+      float hit;
+      if constexpr (LPS == 4) hit = quad_sum(Sys::crash_part(p, sv, x, lane_j, 4));
+      else hit = Sys::crash_part(p, sv, x, 0, 1);
+      crashed = crashed || hit > 0.f;
+      if (crashed) q += p.crash;
+    }
+  }
+  const float qt = q + (quad + lin + sC[i]);
   S += (double)qt;
 }
 
@@ -149,6 +165,7 @@ __device__ __forceinline__ void rollout_body(const IterArgs &a, const typename S
 #pragma unroll
   for (int r = 0; r < N; ++r) x[r] = r < a.n ? (float)x0[r] : 0.f;
   double S = 0.0;
+  bool crashed = false;                             // only a system with a crash indicator sets it
   if constexpr (LPS == 1) {
     for (int g = 0; g < a.G; ++g) {
       float e[4];
@@ -156,7 +173,7 @@ __device__ __forceinline__ void rollout_body(const IterArgs &a, const typename S
 #pragma unroll
       for (int s = 0; s < SPG; ++s) {
         const int i = g * SPG + s;
-        if (i < a.T) rollout_step<Sys, LPS>(a, p, sv, sU, sRU, sC, i, s, 0, e, x, S);
+        if (i < a.T) rollout_step<Sys, LPS>(a, p, sv, sU, sRU, sC, i, s, 0, k, e, x, S, crashed);
       }
     }
   } else {
@@ -170,7 +187,7 @@ __device__ __forceinline__ void rollout_body(const IterArgs &a, const typename S
         for (int c = 0; c < 4; ++c) e[c] = quad_bcast<J>(mine[c]);                      \
         _Pragma("unroll") for (int s = 0; s < SPG; ++s) {                               \
           const int i = (g0 + J) * SPG + s;                                             \
-          if (i < a.T) rollout_step<Sys, LPS>(a, p, sv, sU, sRU, sC, i, s, lane_j, e, x, S); \
+          if (i < a.T) rollout_step<Sys, LPS>(a, p, sv, sU, sRU, sC, i, s, lane_j, k, e, x, S, crashed); \
         }                                                                               \
       }
       MPPI_QUAD_GROUP(0)
@@ -267,6 +284,92 @@ static __global__ __launch_bounds__(kBlock) void update_kernel(const IterArgs a)
   update_body(a, blockIdx.x, blockIdx.y);
 }
 
+// ------------------------------------------------------ cost-to-go weighting (option)
+// Step i of sample k is weighted by its cost from step i onward, S_k - pre[i][k] (the
+// update law's S(tau_{i,k})); rho_i and eta_i are per step.
+static __global__ __launch_bounds__(kBlock) void stepmin_kernel(const IterArgs a) {
+  __shared__ double red[4];
+  const int i = blockIdx.x;
+  double v = __builtin_inf();
+  for (int k = threadIdx.x; k < a.K; k += kBlock) {
+    const double s = a.S[k];
+    if (s < __builtin_inf()) v = fmin(v, s - a.pre[(size_t)i * a.K + k]);
+  }
+  v = block_min(v, red);
+  if (threadIdx.x == 0) a.rho_step[i] = v;
+}
+
+__device__ __forceinline__ double ctg_weight(const IterArgs &a, double s, int i, int k) {
+  return exp(-((s - a.pre[(size_t)i * a.K + k]) - a.rho_step[i]) * a.inv_lambda);
+}
+
+static __global__ __launch_bounds__(kBlock) void update_ctg_kernel(const IterArgs a) {
+  __shared__ double acc_lds[kUpdStrips][kUpdGroups][4];
+  __shared__ double runs[16][kUpdGroups * 4];
+  __shared__ double red[4];
+  const int kc = blockIdx.x, gcb = blockIdx.y;
+  const int TM = a.T * a.m;
+  const uint64_t it = *a.iter;
+  // normalisers of the steps whose first control component lies in this block's groups
+  {
+    const int f_lo = gcb * kUpdGroups * 4, f_hi = min(f_lo + kUpdGroups * 4, TM);
+    const int k = kc * kUpdChunk + threadIdx.x;
+    const double s = k < a.K ? a.S[k] : __builtin_inf();
+    for (int i = (f_lo + a.m - 1) / a.m; i * a.m < f_hi; ++i) {
+      const double w = s < __builtin_inf() ? ctg_weight(a, s, i, k) : 0.0;
+      const double e = block_sum(w, red);
+      if (threadIdx.x == 0) a.eta_part[(size_t)kc * a.T + i] = e;
+    }
+  }
+  const int gl = threadIdx.x % kUpdGroups, strip = threadIdx.x / kUpdGroups;
+  const int g = gcb * kUpdGroups + gl;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  if (g < a.G) {
+    for (int r = 0; r < kUpdPerThread; ++r) {
+      const int k = kc * kUpdChunk + strip * kUpdPerThread + r;
+      const double s = k < a.K ? a.S[k] : __builtin_inf();
+      if (s < __builtin_inf()) {
+        float e[4];
+        normals4((uint32_t)g, (uint32_t)k, it, a.key0, a.key1, e);
+        int last_i = -1;
+        double w = 0.0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int f = 4 * g + c;
+          if (f < TM) {
+            const int i = f / a.m;
+            if (i != last_i) {
+              w = ctg_weight(a, s, i, k);
+              last_i = i;
+            }
+            acc[c] = fma(w, (double)e[c], acc[c]);
+          }
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) acc_lds[strip][gl][c] = acc[c];
+  __syncthreads();
+  {
+    const int slot = threadIdx.x % (kUpdGroups * 4), run = threadIdx.x / (kUpdGroups * 4);
+    if (run < 16) {
+      const int gg = slot / 4, c = slot % 4;
+      double s = 0.0;
+      for (int st = run * (kUpdStrips / 16); st < (run + 1) * (kUpdStrips / 16); ++st) s += acc_lds[st][gg][c];
+      runs[run][slot] = s;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < kUpdGroups * 4) {
+    const int gg = threadIdx.x / 4, c = threadIdx.x % 4;
+    const int gabs = gcb * kUpdGroups + gg;
+    double s = 0.0;
+    for (int r = 0; r < 16; ++r) s += runs[r][threadIdx.x];
+    if (gabs < a.G) a.part[(size_t)kc * (a.G * 4) + gabs * 4 + c] = s;
+  }
+}
+
 // ----------------------------------------------------------------------- finalize
 // One block of 1024 threads; T*m <= 4096 handled in a strided loop.  Sums over the
 // chunk partials run in a fixed order (c = 0, 1, ...) with their loads issued 32 at
@@ -303,6 +406,7 @@ __device__ __forceinline__ double ordered_sum(const double *p, size_t stride, in
 __device__ __forceinline__ void finalize_body(const FinalizeArgs &a, double *u0_out, double *status_out,
                                               double *u0_s) {
   __shared__ double N_lds[kMaxTM];
+  __shared__ double eta_step[1024];                // per-step normalisers (cost-to-go weights)
   __shared__ double red[16];
   __shared__ double eta_s;
   constexpr int kPer = kMaxTM / kFinBlock;
@@ -315,7 +419,11 @@ __device__ __forceinline__ void finalize_body(const FinalizeArgs &a, double *u0_
     const int f = threadIdx.x + n * kFinBlock;
     Uold[n] = f < TM ? a.U64[f] : 0.0;
   }
-  if (threadIdx.x == 0) eta_s = ordered_sum(a.eta_part, 1, a.n_kc);
+  if (a.ctg) {
+    for (int i = threadIdx.x; i < a.T; i += kFinBlock) eta_step[i] = ordered_sum(a.eta_part + i, (size_t)a.T, a.n_kc);
+  } else if (threadIdx.x == 0) {
+    eta_s = ordered_sum(a.eta_part, 1, a.n_kc);
+  }
   for (int f = threadIdx.x; f < TM; f += kFinBlock) N_lds[f] = ordered_sum(a.part + f, (size_t)a.G * 4, a.n_kc);
   v = wave_min(v);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x / 64] = v;
@@ -323,7 +431,7 @@ __device__ __forceinline__ void finalize_body(const FinalizeArgs &a, double *u0_
   double rho = red[0];
   for (int i = 1; i < kFinBlock / 64; ++i) rho = fmin(rho, red[i]);
   const bool ok = rho < __builtin_inf();
-  const double eta = eta_s;
+  const double eta = a.ctg ? eta_step[0] : eta_s;
   const double inv_eta = ok ? 1.0 / eta : 0.0;
   double Unew[kPer];
 #pragma unroll
@@ -334,7 +442,7 @@ __device__ __forceinline__ void finalize_body(const FinalizeArgs &a, double *u0_
       const int i = f / a.m, j = f - i * a.m;
       double d = 0.0;
       for (int l = 0; l <= j; ++l) d += a.Ls[j * a.m + l] * N_lds[i * a.m + l];
-      d = ok ? d * inv_eta : 0.0;
+      d = ok ? d * (a.ctg ? 1.0 / eta_step[i] : inv_eta) : 0.0;
       a.dbg[2 + f] = d;
       Unew[n] = Uold[n] + d;
     }

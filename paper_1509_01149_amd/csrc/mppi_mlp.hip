@@ -387,11 +387,11 @@ static __global__ __launch_bounds__(256) void mlp_rollout_kernel(const IterArgs 
       for (int r = 0; r < 4; ++r) {
         float t = 0.f;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) t += a.R[r * 4 + j] * du[j];
+        for (int j = 0; j < 4; ++j) t += a.Mq[r * 4 + j] * du[j];
         quad += du[r] * t;
         lin += sRU[i * 4 + r] * du[r];
       }
-      lr = a.lr_quad * quad + lin + sC[i];
+      lr = quad + lin + sC[i];
     }
     lr = __shfl(lr, 48 + nn, 64);
     const float dx = px - p.goal[0], dy = py - p.goal[1], dz = pz - p.goal[2];
@@ -812,7 +812,7 @@ size_t mlp_rollout_lds(const mppi_ctx *c) {
   const int T = c->cfg.T;
   size_t fl = (size_t)8 * T + ((T + 3) & ~3);
   fl = (fl + 3) & ~size_t(3);
-  return (fl + 4 * (size_t)c->quad.n_obs) * 4;
+  return (fl + (size_t)QuadrotorSys::stage_floats(c->quad.n_obs, 0)) * 4;
 }
 
 int prepare_mlp_rollout(mppi_ctx *c) {

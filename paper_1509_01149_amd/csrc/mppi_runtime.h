@@ -16,7 +16,7 @@ namespace mppi {
 struct Layout {
   int TM, G, n_roll_blocks, n_kc;
   uint64_t off_x0, off_res, off_iter, off_U64, off_U32, off_S, off_blk_min, off_eta_part, off_part, off_dbg,
-      off_sys, off_extra, extra_bytes, total;
+      off_pre, off_rho_step, off_sys, off_extra, extra_bytes, total;   // off_pre/off_rho_step: cost-to-go only
 };
 
 struct MlpState;  // learned-dynamics extension (mppi_mlp.hip)
@@ -33,12 +33,14 @@ struct mppi_ctx {
   hipStream_t cap_stream = nullptr;
   char *pinned = nullptr;          // 4 KiB pinned staging for x0 / results
   double L64[16] = {0};            // chol(sigma)
-  double Ls[16] = {0};             // sqrt(nu) chol(sigma)
+  double Ls[16] = {0};             // A chol(sigma), A = diag(sqrt(nu_j))
+  double Mq[16] = {0};             // (R - A^-1 R A^-1) / 2
   double R[16] = {0};
   double u_init[4] = {0};
   int seen_numeric = 0;
   mppi::LinearParams linear;
   mppi::CartPoleSys::Params cartpole;
+  mppi::SwingUpSys::Params swingup;
   mppi::BicycleSys::Params bicycle;
   mppi::QuadrotorSys::Params quad;
   mppi::MlpState *mlp = nullptr;

@@ -18,13 +18,14 @@ using namespace mppi;
 
 namespace {
 
-constexpr int kKinds = 6;  // rollout instantiations: linear m=1,2,4, cart-pole, bicycle, quadrotor
+constexpr int kKinds = 7;  // rollout instantiations: linear m=1,2,4, cart-pole, bicycle, quadrotor, swing-up
 
 int kind_of(const mppi_config &c) {
   switch (c.system) {
     case MPPI_SYS_LINEAR: return c.n_ctrl == 1 ? 0 : (c.n_ctrl == 2 ? 1 : 2);
     case MPPI_SYS_CARTPOLE: return 3;
     case MPPI_SYS_BICYCLE: return 4;
+    case MPPI_SYS_CARTPOLE_SWINGUP: return 6;
     default: return 5;
   }
 }
@@ -146,6 +147,7 @@ int launch_batched(mppi_server *s, Batch &b, const std::vector<int> &sl) {
   if (cnt[3]) launch_roll<CartPoleSys>(s, b, 3, cnt[3], proll[3 * (B + 1) + cnt[3]], lds[3]);
   if (cnt[4]) launch_roll<BicycleSys>(s, b, 4, cnt[4], proll[4 * (B + 1) + cnt[4]], lds[4]);
   if (cnt[5]) launch_roll<QuadrotorSys>(s, b, 5, cnt[5], proll[5 * (B + 1) + cnt[5]], lds[5]);
+  if (cnt[6]) launch_roll<SwingUpSys>(s, b, 6, cnt[6], proll[6 * (B + 1) + cnt[6]], lds[6]);
   hipLaunchKernelGGL(update_batched, dim3(pupd[nb]), dim3(kBlock), 0, b.stream, s->d_descs,
                      (const WorkItem *)(b.d + b.off_items), (const int *)(b.d + b.off_pupd), nb);
   hipLaunchKernelGGL(finalize_batched, dim3(nb), dim3(kFinBlock), 0, b.stream, s->d_descs,
@@ -324,6 +326,7 @@ extern "C" int mppi_server_admit(mppi_server *s, const mppi_config *cfg, int32_t
   if (rc) return rc;
   if (!cfg || !slot) return fail(MPPI_EINVAL, "cfg and slot must be non-NULL");
   if (cfg->system == MPPI_SYS_QUADROTOR_MLP) return fail(MPPI_EINVAL, "the server runs the analytic systems");
+  if (cfg->weighting != MPPI_WEIGHT_PATH) return fail(MPPI_EINVAL, "the server runs path-cost weighting only");
   std::lock_guard<std::mutex> lk(s->mu);
   uint64_t bytes = 0;
   rc = mppi_workspace_bytes(cfg, &bytes);

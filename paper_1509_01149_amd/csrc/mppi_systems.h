@@ -51,7 +51,7 @@ struct LinearSys {
     }
     return s;
   }
-  static constexpr bool kSplitCost = false;
+  static constexpr bool kSplitCost = false, kCrash = false;
   static constexpr int kLPS = MPPI_ROLLOUT_LPS;
   __device__ static float q(const Params &p, const StageView &, const float *x) { return quad(p.Q, x); }
   __device__ static float q_part(const Params &p, const StageView &sv, const float *x, int, int) { return q(p, sv, x); }
@@ -82,7 +82,7 @@ struct CartPoleSys {
     xd[2] = x[3];
     xd[3] = thdd;
   }
-  static constexpr bool kSplitCost = false;
+  static constexpr bool kSplitCost = false, kCrash = false;
   static constexpr int kLPS = MPPI_ROLLOUT_LPS;
   __device__ static float q(const Params &p, const StageView &, const float *x) {
     return p.qd[0] * x[0] * x[0] + p.qd[1] * x[1] * x[1] + p.qd[2] * x[2] * x[2] + p.qd[3] * x[3] * x[3];
@@ -91,6 +91,37 @@ struct CartPoleSys {
   __device__ static float phi(const Params &p, const float *x) {
     return p.qfd[0] * x[0] * x[0] + p.qfd[1] * x[1] * x[1] + p.qfd[2] * x[2] * x[2] + p.qfd[3] * x[3] * x[3];
   }
+  static constexpr int stage_floats(int, int) { return 0; }
+  __device__ static void stage(const Params &, float *, const double *, int *, int *) {}
+};
+
+// ------------------------------------------------ cart-pole swing-up (velocity command)
+// The cart tracks the commanded velocity through pddot = gain (u - pdot); the pole turns
+// about the accelerated pivot, theta = 0 hanging down.
+struct SwingUpSys {
+  static constexpr int N = 4, M = 1;
+  struct Params {
+    float gain, k, g, wp, wa, wv, wr;    // k = 3 / (4 l)
+    double dgain, dk, dg;
+  };
+  template <typename F>
+  __device__ static void xdot(const Params &p, const F *x, const F *v, F *xd) {
+    const bool d = sizeof(F) == 8;
+    const F gain = d ? (F)p.dgain : (F)p.gain, k = d ? (F)p.dk : (F)p.k, g = d ? (F)p.dg : (F)p.g;
+    const F pdd = gain * (v[0] - x[1]);
+    xd[0] = x[1];
+    xd[1] = pdd;
+    xd[2] = x[3];
+    xd[3] = -k * (g * fsin(x[2]) + pdd * fcos(x[2]));
+  }
+  static constexpr bool kSplitCost = false, kCrash = false;
+  static constexpr int kLPS = MPPI_ROLLOUT_LPS;
+  __device__ static float q(const Params &p, const StageView &, const float *x) {
+    const float a = 1.f + fcos(x[2]);
+    return p.wp * x[0] * x[0] + p.wa * a * a + p.wr * x[3] * x[3] + p.wv * x[1] * x[1];
+  }
+  __device__ static float q_part(const Params &p, const StageView &sv, const float *x, int, int) { return q(p, sv, x); }
+  __device__ static float phi(const Params &, const float *) { return 0.f; }
   static constexpr int stage_floats(int, int) { return 0; }
   __device__ static void stage(const Params &, float *, const double *, int *, int *) {}
 };
@@ -139,7 +170,7 @@ struct BicycleSys {
     *i0 = ci;
     *j0 = cj;
   }
-  static constexpr bool kSplitCost = false;
+  static constexpr bool kSplitCost = false, kCrash = false;
   static constexpr int kLPS = MPPI_ROLLOUT_LPS;
   __device__ static float q_part(const Params &p, const StageView &sv, const float *x, int, int) { return q(p, sv, x); }
   __device__ static float q(const Params &p, const StageView &sv, const float *x) {
@@ -151,13 +182,20 @@ struct BicycleSys {
     const float fx = gx - (float)i0, fy = gy - (float)j0;
     const int tw = p.W < kTile ? p.W : kTile, th = p.H < kTile ? p.H : kTile;
     const int li = i0 - sv.i0, lj = j0 - sv.j0;
-    float m00, m01, m10, m11;
-    if (li >= 0 && lj >= 0 && li + 1 < tw && lj + 1 < th) {
-      const float *t = sv.lds + lj * tw + li;
-      m00 = t[0]; m01 = t[1]; m10 = t[tw]; m11 = t[tw + 1];
-    } else {
-      const float *t = p.map + (size_t)j0 * p.W + i0;
-      m00 = t[0]; m01 = t[1]; m10 = t[p.W]; m11 = t[p.W + 1];
+    // LDS taps from the index clamped into the tile, always; outside the tile the global
+    // taps replace them.  Loading both ways (rather than selecting a pointer) keeps the
+    // common case on ds_read: a pointer that may be LDS or global compiles to flat loads
+    // on every step.  The global taps are relaxed atomic loads (plain global loads in the
+    // ISA), which the compiler does not merge with the LDS loads into one flat load.
+    const int lic = min(max(li, 0), tw - 2), ljc = min(max(lj, 0), th - 2);
+    const float *t = sv.lds + ljc * tw + lic;
+    float m00 = t[0], m01 = t[1], m10 = t[tw], m11 = t[tw + 1];
+    if (!(li >= 0 && lj >= 0 && li + 1 < tw && lj + 1 < th)) {
+      const float *g = p.map + (size_t)j0 * p.W + i0;
+      m00 = __hip_atomic_load(g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      m01 = __hip_atomic_load(g + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      m10 = __hip_atomic_load(g + p.W, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      m11 = __hip_atomic_load(g + p.W + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     const float top = (1.f - fx) * m00 + fx * m01;
     const float bot = (1.f - fx) * m10 + fx * m11;
@@ -174,7 +212,8 @@ struct QuadrotorSys {
   struct Params {
     float m_inv, g, arm, kap, J[3], Jinv[3], goal[3], wg, wo, margin;
     int n_obs;
-    const float4 *obs;   // device: (cx, cy, cz, (r + margin)^2)
+    const float4 *obs;   // device: n_obs x (cx, cy, cz, (r + margin)^2), then n_obs x r^2
+    float crash, ground; // crash indicator cost (0: off) and ground height
     double dm_inv, dg, darm, dkap, dJ[3], dJinv[3];
   };
   template <typename F>
@@ -211,9 +250,28 @@ struct QuadrotorSys {
     xd[10] = (ty - (wz * hx - wx * hz)) * Ji1;
     xd[11] = (tz - (wx * hy - wy * hx)) * Ji2;
   }
-  static constexpr int stage_floats(int n_obs, int) { return 4 * n_obs; }
+  // LDS: the obstacles' float4s, then (crash indicator on) their squared radii
+  static constexpr int stage_floats(int n_obs, int) { return 5 * n_obs; }
   __device__ static void stage(const Params &p, float *lds, const double *, int *, int *) {
     for (int e = threadIdx.x; e < p.n_obs; e += kBlock) reinterpret_cast<float4 *>(lds)[e] = p.obs[e];
+    if (p.crash > 0.f) {
+      const float *r2 = reinterpret_cast<const float *>(p.obs + p.n_obs);
+      for (int e = threadIdx.x; e < p.n_obs; e += kBlock) lds[4 * p.n_obs + e] = r2[e];
+    }
+  }
+  // Crash indicator, lane j of nj: the ground (j = 0) plus obstacles j, j + nj, ...; the
+  // count of hits (0 = no crash).
+  static constexpr bool kCrash = true;
+  __device__ static float crash_part(const Params &p, const StageView &sv, const float *x, int j, int nj) {
+    float hit = (j == 0 && x[2] < p.ground) ? 1.f : 0.f;
+    const float4 *ob = reinterpret_cast<const float4 *>(sv.lds);
+    const float *r2 = sv.lds + 4 * p.n_obs;
+    for (int o = j; o < p.n_obs; o += nj) {
+      const float4 ov = ob[o];
+      const float ex = x[0] - ov.x, ey = x[1] - ov.y, ez = x[2] - ov.z;
+      hit += (ex * ex + ey * ey + ez * ez) < r2[o] ? 1.f : 0.f;
+    }
+    return hit;
   }
   static constexpr bool kSplitCost = true;
   static constexpr int kLPS = MPPI_ROLLOUT_LPS;

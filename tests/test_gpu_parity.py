@@ -7,8 +7,8 @@ import pytest
 
 import paper_1509_01149_amd as P
 import workloads as W
-from oracle import mppi, noise, philox
-from tests._parity import assert_parity, controller, one_step
+from oracle import mppi, noise, philox, systems
+from tests._parity import _first_order, assert_parity, controller, one_step
 
 pytestmark = pytest.mark.gpu
 
@@ -42,6 +42,12 @@ CASES = {
     "quadrotor_nu2": lambda: W.quadrotor(nu=2.0),
     "quadrotor_nu4": lambda: W.quadrotor(nu=4.0),
     "linear": lambda: W.linear_double_integrator(K=4096, R=0.3),
+    # per-dimension exploration factors, A = diag(sqrt(nu_j))
+    "quadrotor_nu_diag": lambda: W.quadrotor(nu=np.array([1.0, 2.0, 4.0, 8.0]), lam=420.0),
+    "bicycle_nu_diag": lambda: W.bicycle(nu=np.array([1.0, 4.0])),
+    # the swing-up task of Section V-A (velocity-command cart, pole hanging at rest)
+    "swingup_nu1": lambda: W.cartpole_swingup(nu=1.0),
+    "swingup_nu1000": lambda: W.cartpole_swingup(nu=1000.0, K=4096),
 }
 
 
@@ -55,7 +61,7 @@ def test_first_iteration_parity(name):
     assert_parity(m)
 
 
-@pytest.mark.parametrize("name", ["bicycle", "quadrotor_nu2"])
+@pytest.mark.parametrize("name", ["bicycle", "quadrotor_nu2", "swingup_nu1000"])
 def test_warm_started_steps_parity(name):
     """Several control steps; before each the oracle is given the GPU's own nominal
     sequence and state, so only one step's arithmetic is compared at a time."""
@@ -140,3 +146,90 @@ def test_fused_plant_step_equals_step_then_plant():
                 assert np.allclose(xb.cpu().numpy(), x_ref, rtol=1e-12, atol=1e-12)
             assert torch.equal(xa, xb) and torch.equal(ua, ub)
             assert np.array_equal(a.get_controls(), b.get_controls())
+
+
+CTG_CASES = {
+    "linear": lambda: W.linear_double_integrator(K=4096, T=20, R=0.3),
+    "bicycle": lambda: W.bicycle(K=4096, T=100),
+    "bicycle_nu_diag": lambda: W.bicycle(K=3000, T=37, nu=np.array([1.0, 4.0])),
+    "quadrotor": lambda: W.quadrotor(nu=2.0, K=4096, T=60),
+}
+
+
+@pytest.mark.parametrize("name", list(CTG_CASES))
+def test_cost_to_go_parity(name):
+    """Cost-to-go weighting: step i weighted by each sample's cost from step i on, with its
+    own minimum and normaliser, against the oracle's per-step softmax of tail sums."""
+    wl = CTG_CASES[name]().replace(seed=7)
+    U0 = mppi.initial_sequence(wl) + 0.1 * np.sin(np.arange(wl.T))[:, None]
+    with controller(wl, u_nominal0=U0, weighting=P.WEIGHT_COST_TO_GO) as c:
+        u0 = c.step(wl.x0)
+        U_gpu = np.vstack([u0[None, :], c.get_controls()[:-1]])
+        S_gpu = c.debug_last()[0]
+    U_orc = mppi.iteration_cost_to_go(wl, wl.x0, U0, 0)
+    S_orc = mppi.iteration(wl, wl.x0, U0, 0).S
+    scale = max(1.0, np.abs(U_orc).max())
+    err = np.abs(U_gpu - U_orc).max() / scale
+    s_err = (np.abs(S_gpu - S_orc) / np.maximum(1.0, np.abs(S_orc))).max()
+    print(name, "U err", err, "S err", s_err)
+    assert s_err <= 4e-4
+    assert err <= 1e-4, err
+
+
+def test_cost_to_go_first_step_equals_path_weighting():
+    """At step 0 the cost-to-go is the whole path cost: u_0 must be bitwise the same
+    under both weightings; later steps must differ."""
+    wl = W.bicycle(K=2048, T=50).replace(seed=9)
+    with controller(wl) as a, controller(wl, weighting=P.WEIGHT_COST_TO_GO) as b:
+        ua, ub = a.step(wl.x0), b.step(wl.x0)
+        assert np.array_equal(ua, ub)
+        assert not np.array_equal(a.get_controls(), b.get_controls())
+
+
+def test_swingup_closed_loop_exploration_variance():
+    """Section V-A: 10 s of swing-up (500 control steps, K = 1000) on the GPU path, the
+    plant stepped by the oracle's FP64 model.  The average running cost falls as nu grows:
+    the natural variance (nu = 1) brings the pole up late, nu = 1000 within the first second."""
+    avg = {}
+    for nu in (1.0, 1000.0):
+        wl = W.cartpole_swingup(nu=nu).replace(seed=1)
+        sysm = systems.make(wl)
+        x, qs = wl.x0.copy(), []
+        with controller(wl) as c:
+            for _ in range(wl.control_steps):
+                x = mppi.plant_step(wl, x, c.step(x), system=sysm)
+                qs.append(float(sysm.q(x[None])[0]))
+        avg[nu] = float(np.mean(qs))
+        print("nu", nu, "average running cost", avg[nu], "final state", x)
+        if nu == 1000.0:
+            assert np.mean(qs[:50]) < 1000.0 and abs(abs(x[2]) - np.pi) < 0.3
+    assert avg[1.0] > 2.0 * avg[1000.0]
+
+
+@pytest.mark.parametrize("T", [100, 150])
+def test_crash_indicator_parity(T):
+    """Quadrotor with the crash indicator (Section V-C).  The indicator is a threshold on
+    the FP32 state, so a sample grazing the ground or an obstacle may crash one step earlier
+    or later than in the FP64 oracle: such a flip changes its cost by about crash_cost per
+    step.  Flips must be rare (<= 0.5 % of samples); every other sample meets the usual
+    per-sample cost tolerance; the update meets the usual bar plus what the flipped samples'
+    weights can move it (sum of their weights on either side times max |du|)."""
+    wl = W.quadrotor(nu=2.0, K=4096, T=T, crash=True).replace(seed=3)
+    U0 = mppi.initial_sequence(wl)
+    with controller(wl) as c:
+        m = one_step(wl, c, wl.x0, U0, 0)
+    last = m["res"][-1]
+    S_gpu, S_orc = m["S_gpu"], last.S
+    fin = np.isfinite(S_orc) & np.isfinite(S_gpu)
+    flip = fin & (np.abs(S_gpu - S_orc) > 0.5 * W.QUAD_CRASH_COST)
+    rel = np.abs(S_gpu - S_orc) / np.maximum(1.0, np.abs(S_orc))
+    ok = fin & ~flip
+    print("T", T, "flips", int(flip.sum()), "S err (others)", rel[ok].max(), "U err", m["U_err"])
+    assert flip.sum() <= 0.005 * wl.K
+    assert rel[ok].max() <= 4e-4
+    w_gpu, _, _, _, _ = mppi.weights_and_update(np.where(np.isfinite(S_gpu), S_gpu, np.inf), last.du, wl.lam)
+    moved = float(np.sum(last.w[flip]) + np.sum(w_gpu[flip])) * float(np.abs(last.du).max())
+    scale = max(1.0, np.abs(U0).max())
+    first = float(np.max(np.abs(_first_order(last, S_gpu, ok, wl.lam)))) / scale
+    assert m["U_err"] <= 1e-4 + 2.0 * first + moved / scale
+    assert m["stage_err"] <= 1e-5
