@@ -363,10 +363,37 @@ static size_t rollout_lds_bytes(const mppi_ctx *c) {
   return fl * 4;
 }
 
+// The rollout variant a context runs: cost-to-go weighting records prefix costs; the
+// quadrotor's crash indicator when its crash_cost is positive.
+static int rollout_mode(const mppi_ctx *c) {
+  int mode = c->cfg.weighting == MPPI_WEIGHT_COST_TO_GO ? kRecordPrefix : 0;
+  if (c->cfg.system == MPPI_SYS_QUADROTOR && c->quad.crash > 0.f) mode |= kCrashOn;
+  return mode;
+}
+
+template <class Sys, int Mode>
+static const void *rollout_fn() {
+  if constexpr ((Mode & kCrashOn) != 0 && !Sys::kCrash) return nullptr;
+  else return (const void *)rollout_kernel<Sys, Sys::kLPS, Mode>;
+}
+
+template <class Sys>
+static const void *rollout_fn_for(int mode) {
+  switch (mode) {
+    case 0: return rollout_fn<Sys, 0>();
+    case kRecordPrefix: return rollout_fn<Sys, kRecordPrefix>();
+    case kCrashOn: return rollout_fn<Sys, kCrashOn>();
+    default: return rollout_fn<Sys, kRecordPrefix | kCrashOn>();
+  }
+}
+
 template <class Sys>
 static int launch_rollout(mppi_ctx *c, const IterArgs &a, const typename Sys::Params &p, hipStream_t s) {
   const size_t lds = rollout_lds_bytes<Sys>(c);
-  hipLaunchKernelGGL((rollout_kernel<Sys, Sys::kLPS>), dim3(c->L.n_roll_blocks), dim3(kBlock), lds, s, a, p);
+  const void *fn = rollout_fn_for<Sys>(rollout_mode(c));
+  if (!fn) return fail(MPPI_EINVAL, "rollout variant not available for system %d", c->cfg.system);
+  void *args[] = {(void *)&a, (void *)&p};
+  HIP_TRY(hipLaunchKernel(fn, dim3(c->L.n_roll_blocks), dim3(kBlock), args, lds, s));
   return MPPI_OK;
 }
 
@@ -374,7 +401,9 @@ template <class Sys>
 static int prepare_rollout(mppi_ctx *c) {
   const size_t lds = rollout_lds_bytes<Sys>(c);
   if (lds > 160 * 1024 - 64) return fail(MPPI_EINVAL, "rollout needs %zu B of LDS (T too large)", lds);
-  HIP_TRY(hipFuncSetAttribute((const void *)rollout_kernel<Sys, Sys::kLPS>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  const void *fn = rollout_fn_for<Sys>(rollout_mode(c));
+  if (!fn) return fail(MPPI_EINVAL, "rollout variant not available for system %d", c->cfg.system);
+  HIP_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   return MPPI_OK;
 }
 

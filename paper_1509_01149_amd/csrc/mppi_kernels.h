@@ -80,12 +80,18 @@ __device__ __forceinline__ float quad_sum(float v) {
   return v;
 }
 
+// Rollout variants (compile-time, so the default path carries none of their code):
+// kRecordPrefix records each sample's cost before every step (cost-to-go weighting);
+// kCrash applies the system's crash indicator (systems with Sys::kCrash only).
+enum { kRecordPrefix = 1, kCrashOn = 2 };
+
 // One horizon step of one sample from the four normals `e` of its noise group.
-template <class Sys, int LPS>
+template <class Sys, int LPS, int Mode>
 __device__ __forceinline__ void rollout_step(const IterArgs &a, const typename Sys::Params &p, const StageView &sv,
                                              const float *sU, const float *sRU, const float *sC, int i, int s,
                                              int lane_j, int k, const float e[4], float *x, double &S, bool &crashed) {
-  if (a.pre && lane_j == 0 && k < a.K) a.pre[(size_t)i * a.K + k] = S;   // cost of steps before i
+  if constexpr ((Mode & kRecordPrefix) != 0)
+    if (lane_j == 0 && k < a.K) a.pre[(size_t)i * a.K + k] = S;        // cost of steps before i
   constexpr int N = Sys::N, M = Sys::M;
   float du[M], v[M], xd[N];
 #pragma unroll
@@ -97,7 +103,12 @@ __device__ __forceinline__ void rollout_step(const IterArgs &a, const typename S
     v[j] = sU[i * M + j] + t;
   }
   Sys::xdot(p, x, v, xd);
-  if (!crashed) {                                   // a crashed rollout stays where it is
+  if constexpr ((Mode & kCrashOn) != 0) {
+    if (!crashed) {                                 // a crashed rollout stays where it is
+#pragma unroll
+      for (int r = 0; r < N; ++r) x[r] += a.dt * xd[r];
+    }
+  } else {
 #pragma unroll
     for (int r = 0; r < N; ++r) x[r] += a.dt * xd[r];
   }
@@ -111,22 +122,27 @@ __device__ __forceinline__ void rollout_step(const IterArgs &a, const typename S
     lin += sRU[i * M + r] * du[r];
   }
   float q;
-  if constexpr (LPS == 4 && Sys::kSplitCost) q = quad_sum(Sys::q_part(p, sv, x, lane_j, 4));
-  else q = Sys::q(p, sv, x);
-  if constexpr (Sys::kCrash) {
-    if (p.crash > 0.f) {                            // crash indicator: sticky, crash cost per step
-      float hit;
-      if constexpr (LPS == 4) hit = quad_sum(Sys::crash_part(p, sv, x, lane_j, 4));
-      else hit = Sys::crash_part(p, sv, x, 0, 1);
-      crashed = crashed || hit > 0.f;
-      if (crashed) q += p.crash;
+  if constexpr ((Mode & kCrashOn) != 0) {          // crash indicator: sticky, crash cost per step
+    static_assert(Sys::kCrash, "system has no crash indicator");
+    float hit;
+    if constexpr (LPS == 4) {
+      q = quad_sum(Sys::q_part_crash(p, sv, x, lane_j, 4, hit));
+      hit = quad_sum(hit);
+    } else {
+      q = Sys::q_part_crash(p, sv, x, 0, 1, hit);
     }
+    crashed = crashed || hit > 0.f;
+    if (crashed) q += p.crash;
+  } else if constexpr (LPS == 4 && Sys::kSplitCost) {
+    q = quad_sum(Sys::q_part(p, sv, x, lane_j, 4));
+  } else {
+    q = Sys::q(p, sv, x);
   }
   const float qt = q + (quad + lin + sC[i]);
   S += (double)qt;
 }
 
-template <class Sys, int LPS>
+template <class Sys, int LPS, int Mode>
 __device__ __forceinline__ void rollout_body(const IterArgs &a, const typename Sys::Params &p, const double *x0,
                                              int blk, float4 *lds4) {
   constexpr int N = Sys::N, M = Sys::M;
@@ -165,7 +181,7 @@ __device__ __forceinline__ void rollout_body(const IterArgs &a, const typename S
 #pragma unroll
   for (int r = 0; r < N; ++r) x[r] = r < a.n ? (float)x0[r] : 0.f;
   double S = 0.0;
-  bool crashed = false;                             // only a system with a crash indicator sets it
+  bool crashed = false;                             // set only in the kCrashOn variant
   if constexpr (LPS == 1) {
     for (int g = 0; g < a.G; ++g) {
       float e[4];
@@ -173,7 +189,7 @@ __device__ __forceinline__ void rollout_body(const IterArgs &a, const typename S
 #pragma unroll
       for (int s = 0; s < SPG; ++s) {
         const int i = g * SPG + s;
-        if (i < a.T) rollout_step<Sys, LPS>(a, p, sv, sU, sRU, sC, i, s, 0, k, e, x, S, crashed);
+        if (i < a.T) rollout_step<Sys, LPS, Mode>(a, p, sv, sU, sRU, sC, i, s, 0, k, e, x, S, crashed);
       }
     }
   } else {
@@ -187,7 +203,7 @@ __device__ __forceinline__ void rollout_body(const IterArgs &a, const typename S
         for (int c = 0; c < 4; ++c) e[c] = quad_bcast<J>(mine[c]);                      \
         _Pragma("unroll") for (int s = 0; s < SPG; ++s) {                               \
           const int i = (g0 + J) * SPG + s;                                             \
-          if (i < a.T) rollout_step<Sys, LPS>(a, p, sv, sU, sRU, sC, i, s, lane_j, k, e, x, S, crashed); \
+          if (i < a.T) rollout_step<Sys, LPS, Mode>(a, p, sv, sU, sRU, sC, i, s, lane_j, k, e, x, S, crashed); \
         }                                                                               \
       }
       MPPI_QUAD_GROUP(0)
@@ -205,10 +221,10 @@ __device__ __forceinline__ void rollout_body(const IterArgs &a, const typename S
   if (threadIdx.x == 0) a.blk_min[blk] = bm;
 }
 
-template <class Sys, int LPS>
+template <class Sys, int LPS, int Mode>
 __global__ __launch_bounds__(kBlock) void rollout_kernel(const IterArgs a, const typename Sys::Params p) {
   extern __shared__ float4 lds4[];
-  rollout_body<Sys, LPS>(a, p, a.x0, blockIdx.x, lds4);
+  rollout_body<Sys, LPS, Mode>(a, p, a.x0, blockIdx.x, lds4);
 }
 
 // Minimum over the rollout blocks' minima (every thread gets it).

@@ -18,9 +18,12 @@ using namespace mppi;
 
 namespace {
 
-constexpr int kKinds = 7;  // rollout instantiations: linear m=1,2,4, cart-pole, bicycle, quadrotor, swing-up
+// rollout instantiations: linear m=1,2,4, cart-pole, bicycle, quadrotor, swing-up, quadrotor
+// with the crash indicator
+constexpr int kKinds = 8;
 
 int kind_of(const mppi_config &c) {
+  if (c.system == MPPI_SYS_QUADROTOR && ((const mppi_quadrotor_params *)c.params)->crash_cost > 0) return 7;
   switch (c.system) {
     case MPPI_SYS_LINEAR: return c.n_ctrl == 1 ? 0 : (c.n_ctrl == 2 ? 1 : 2);
     case MPPI_SYS_CARTPOLE: return 3;
@@ -96,14 +99,14 @@ struct mppi_server {
 
 namespace {
 
-template <class Sys>
+template <class Sys, int Mode = 0>
 void launch_roll(mppi_server *s, Batch &b, int kind, int count, int total, size_t lds) {
   if (lds > s->lds_set[kind]) {
-    (void)hipFuncSetAttribute((const void *)rollout_batched<Sys>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    (void)hipFuncSetAttribute((const void *)rollout_batched<Sys, Mode>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     s->lds_set[kind] = lds;
   }
   const int B = s->cfg.max_batch;
-  hipLaunchKernelGGL(rollout_batched<Sys>, dim3(total), dim3(kBlock), lds, b.stream, s->d_descs,
+  hipLaunchKernelGGL((rollout_batched<Sys, Mode>), dim3(total), dim3(kBlock), lds, b.stream, s->d_descs,
                      (const WorkItem *)(b.d + b.off_items), (const int *)(b.d + b.off_sel) + kind * B,
                      (const int *)(b.d + b.off_proll) + kind * (B + 1), count);
 }
@@ -148,6 +151,7 @@ int launch_batched(mppi_server *s, Batch &b, const std::vector<int> &sl) {
   if (cnt[4]) launch_roll<BicycleSys>(s, b, 4, cnt[4], proll[4 * (B + 1) + cnt[4]], lds[4]);
   if (cnt[5]) launch_roll<QuadrotorSys>(s, b, 5, cnt[5], proll[5 * (B + 1) + cnt[5]], lds[5]);
   if (cnt[6]) launch_roll<SwingUpSys>(s, b, 6, cnt[6], proll[6 * (B + 1) + cnt[6]], lds[6]);
+  if (cnt[7]) launch_roll<QuadrotorSys, kCrashOn>(s, b, 7, cnt[7], proll[7 * (B + 1) + cnt[7]], lds[7]);
   hipLaunchKernelGGL(update_batched, dim3(pupd[nb]), dim3(kBlock), 0, b.stream, s->d_descs,
                      (const WorkItem *)(b.d + b.off_items), (const int *)(b.d + b.off_pupd), nb);
   hipLaunchKernelGGL(finalize_batched, dim3(nb), dim3(kFinBlock), 0, b.stream, s->d_descs,

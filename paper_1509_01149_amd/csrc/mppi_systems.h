@@ -259,19 +259,27 @@ struct QuadrotorSys {
       for (int e = threadIdx.x; e < p.n_obs; e += kBlock) lds[4 * p.n_obs + e] = r2[e];
     }
   }
-  // Crash indicator, lane j of nj: the ground (j = 0) plus obstacles j, j + nj, ...; the
-  // count of hits (0 = no crash).
+  // Lane j of nj with the crash indicator on: the cost of q_part and, in `hit`, the count
+  // of crash conditions among the same obstacles (plus the ground for j = 0), from the
+  // same distances.
   static constexpr bool kCrash = true;
-  __device__ static float crash_part(const Params &p, const StageView &sv, const float *x, int j, int nj) {
-    float hit = (j == 0 && x[2] < p.ground) ? 1.f : 0.f;
+  __device__ static float q_part_crash(const Params &p, const StageView &sv, const float *x, int j, int nj,
+                                       float &hit) {
+    const float dx = x[0] - p.goal[0], dy = x[1] - p.goal[1], dz = x[2] - p.goal[2];
+    const float c = j == 0 ? p.wg * (dx * dx + dy * dy + dz * dz) : 0.f;
     const float4 *ob = reinterpret_cast<const float4 *>(sv.lds);
     const float *r2 = sv.lds + 4 * p.n_obs;
+    float barrier = 0.f, h = (j == 0 && x[2] < p.ground) ? 1.f : 0.f;
     for (int o = j; o < p.n_obs; o += nj) {
       const float4 ov = ob[o];
       const float ex = x[0] - ov.x, ey = x[1] - ov.y, ez = x[2] - ov.z;
-      hit += (ex * ex + ey * ey + ez * ez) < r2[o] ? 1.f : 0.f;
+      const float d2 = ex * ex + ey * ey + ez * ez;
+      const float pen = fmaxf(0.f, ov.w - d2);
+      barrier += pen * pen;
+      h += d2 < r2[o] ? 1.f : 0.f;
     }
-    return hit;
+    hit = h;
+    return c + p.wo * barrier;
   }
   static constexpr bool kSplitCost = true;
   static constexpr int kLPS = MPPI_ROLLOUT_LPS;
