@@ -528,12 +528,13 @@ int enqueue_iterations(mppi_ctx *c, const double *x0_dev, int n_iters, double *u
     }
     if (rc) return rc;
     prof_end(c, s, 0, t0);
+    const dim3 ugrid(c->L.n_kc, (c->L.G + kUpdGroups - 1) / kUpdGroups);
     t0 = prof_begin(c, s);
     if (a.pre) {
       hipLaunchKernelGGL(stepmin_kernel, dim3(c->cfg.T), dim3(kBlock), 0, s, a);
-      hipLaunchKernelGGL(update_ctg_kernel, dim3(c->L.n_kc, (c->L.G + kUpdGroups - 1) / kUpdGroups), dim3(kBlock), 0, s, a);
+      hipLaunchKernelGGL(update_ctg_kernel, ugrid, dim3(kBlock), 0, s, a);
     } else {
-      hipLaunchKernelGGL(update_kernel, dim3(c->L.n_kc, (c->L.G + kUpdGroups - 1) / kUpdGroups), dim3(kBlock), 0, s, a);
+      hipLaunchKernelGGL(update_kernel, ugrid, dim3(kBlock), 0, s, a);
     }
     prof_end(c, s, 1, t0);
     const FinalizeArgs f = make_fin_args(c, u0_dev, it == n_iters - 1);

@@ -75,6 +75,14 @@ __device__ __forceinline__ double fsin(double x) { return sin(x); }
 __device__ __forceinline__ double fcos(double x) { return cos(x); }
 __device__ __forceinline__ double frcp(double x) { return 1.0 / x; }
 
+// sin and cos of one angle: one shared reduction (FP32: the revolution; FP64: sincos).
+__device__ __forceinline__ void fsincos(float x, float &s, float &c) {
+  const float r = rev(x);
+  s = __builtin_amdgcn_sinf(r);
+  c = __builtin_amdgcn_cosf(r);
+}
+__device__ __forceinline__ void fsincos(double x, double &s, double &c) { sincos(x, &s, &c); }
+
 // ---------------------------------------------------------------------------------
 // Wave64 / block reductions (fixed order: results do not depend on timing).
 // ---------------------------------------------------------------------------------

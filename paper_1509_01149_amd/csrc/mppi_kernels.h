@@ -88,8 +88,9 @@ enum { kRecordPrefix = 1, kCrashOn = 2 };
 // One horizon step of one sample from the four normals `e` of its noise group.
 template <class Sys, int LPS, int Mode>
 __device__ __forceinline__ void rollout_step(const IterArgs &a, const typename Sys::Params &p, const StageView &sv,
-                                             const float *sU, const float *sRU, const float *sC, int i, int s,
-                                             int lane_j, int k, const float e[4], float *x, double &S, bool &crashed) {
+                                             const typename Sys::Regs &rg, const float *sU, const float *sRU,
+                                             const float *sC, int i, int s, int lane_j, int k, const float e[4],
+                                             float *x, double &S, bool &crashed) {
   if constexpr ((Mode & kRecordPrefix) != 0)
     if (lane_j == 0 && k < a.K) a.pre[(size_t)i * a.K + k] = S;        // cost of steps before i
   constexpr int N = Sys::N, M = Sys::M;
@@ -126,15 +127,15 @@ __device__ __forceinline__ void rollout_step(const IterArgs &a, const typename S
     static_assert(Sys::kCrash, "system has no crash indicator");
     float hit;
     if constexpr (LPS == 4) {
-      q = quad_sum(Sys::q_part_crash(p, sv, x, lane_j, 4, hit));
+      q = quad_sum(Sys::q_part_crash(p, sv, rg, x, lane_j, 4, hit));
       hit = quad_sum(hit);
     } else {
-      q = Sys::q_part_crash(p, sv, x, 0, 1, hit);
+      q = Sys::q_part_crash(p, sv, rg, x, 0, 1, hit);
     }
     crashed = crashed || hit > 0.f;
     if (crashed) q += p.crash;
   } else if constexpr (LPS == 4 && Sys::kSplitCost) {
-    q = quad_sum(Sys::q_part(p, sv, x, lane_j, 4));
+    q = quad_sum(Sys::q_part(p, sv, rg, x, lane_j, 4));
   } else {
     q = Sys::q(p, sv, x);
   }
@@ -154,10 +155,20 @@ __device__ __forceinline__ void rollout_body(const IterArgs &a, const typename S
   __shared__ double red[4];
 
   const uint64_t it = *a.iter;
+  // Preamble loads first (start state, this thread's first control, then the system's
+  // staging loads), so their memory latencies overlap instead of following each other.
+  float x[N];
+#pragma unroll
+  for (int r = 0; r < N; ++r) x[r] = r < a.n ? (float)x0[r] : 0.f;
+  float u_first[M];
+#pragma unroll
+  for (int j = 0; j < M; ++j) u_first[j] = threadIdx.x < a.T ? a.U32[threadIdx.x * M + j] : 0.f;
+  int ti = 0, tj = 0;                               // every thread computes the same origin
+  Sys::stage(p, sSys, x0, &ti, &tj);
   for (int i = threadIdx.x; i < a.T; i += kBlock) {
     float u[M];
 #pragma unroll
-    for (int j = 0; j < M; ++j) u[j] = a.U32[i * M + j];
+    for (int j = 0; j < M; ++j) u[j] = i == threadIdx.x ? u_first[j] : a.U32[i * M + j];
     float c = 0.f;
 #pragma unroll
     for (int r = 0; r < M; ++r) {
@@ -170,16 +181,13 @@ __device__ __forceinline__ void rollout_body(const IterArgs &a, const typename S
     }
     sC[i] = 0.5f * c;
   }
-  int ti = 0, tj = 0;                               // every thread computes the same origin
-  Sys::stage(p, sSys, x0, &ti, &tj);
   __syncthreads();
   const StageView sv{sSys, ti, tj};
 
   const int lane_j = threadIdx.x % LPS;
+  typename Sys::Regs rg;                            // per-lane register copy of system data
+  Sys::load_regs(p, sv, lane_j, LPS, rg);
   const int k = blk * (kBlock / LPS) + threadIdx.x / LPS;
-  float x[N];
-#pragma unroll
-  for (int r = 0; r < N; ++r) x[r] = r < a.n ? (float)x0[r] : 0.f;
   double S = 0.0;
   bool crashed = false;                             // set only in the kCrashOn variant
   if constexpr (LPS == 1) {
@@ -189,7 +197,7 @@ __device__ __forceinline__ void rollout_body(const IterArgs &a, const typename S
 #pragma unroll
       for (int s = 0; s < SPG; ++s) {
         const int i = g * SPG + s;
-        if (i < a.T) rollout_step<Sys, LPS, Mode>(a, p, sv, sU, sRU, sC, i, s, 0, k, e, x, S, crashed);
+        if (i < a.T) rollout_step<Sys, LPS, Mode>(a, p, sv, rg, sU, sRU, sC, i, s, 0, k, e, x, S, crashed);
       }
     }
   } else {
@@ -203,7 +211,7 @@ __device__ __forceinline__ void rollout_body(const IterArgs &a, const typename S
         for (int c = 0; c < 4; ++c) e[c] = quad_bcast<J>(mine[c]);                      \
         _Pragma("unroll") for (int s = 0; s < SPG; ++s) {                               \
           const int i = (g0 + J) * SPG + s;                                             \
-          if (i < a.T) rollout_step<Sys, LPS, Mode>(a, p, sv, sU, sRU, sC, i, s, lane_j, k, e, x, S, crashed); \
+          if (i < a.T) rollout_step<Sys, LPS, Mode>(a, p, sv, rg, sU, sRU, sC, i, s, lane_j, k, e, x, S, crashed); \
         }                                                                               \
       }
       MPPI_QUAD_GROUP(0)
@@ -229,8 +237,8 @@ __global__ __launch_bounds__(kBlock) void rollout_kernel(const IterArgs a, const
 
 // Minimum over the rollout blocks' minima (every thread gets it).
 __device__ __forceinline__ double global_min(const double *blk_min, int n, double *red) {
-  double v = __builtin_inf();
-  for (int b = threadIdx.x; b < n; b += kBlock) v = fmin(v, blk_min[b]);
+  double v = threadIdx.x < n ? blk_min[threadIdx.x] : __builtin_inf();
+  for (int b = threadIdx.x + kBlock; b < n; b += kBlock) v = fmin(v, blk_min[b]);
   return block_min(v, red);
 }
 
@@ -241,15 +249,13 @@ __device__ __forceinline__ void update_body(const IterArgs &a, int kc, int gcb) 
   __shared__ double w[kUpdChunk];
   __shared__ double acc_lds[kUpdStrips][kUpdGroups][4];
   __shared__ double red[4];
+  const int k_own = kc * kUpdChunk + threadIdx.x;
+  const double s_own = k_own < a.K ? a.S[k_own] : __builtin_inf();   // in flight with the minima
   const double rho = global_min(a.blk_min, a.n_roll_blocks, red);
   const uint64_t it = *a.iter;
   {
-    const int k = kc * kUpdChunk + threadIdx.x;
     double wk = 0.0;
-    if (k < a.K && rho < __builtin_inf()) {
-      const double s = a.S[k];
-      wk = s < __builtin_inf() ? exp(-(s - rho) * a.inv_lambda) : 0.0;
-    }
+    if (rho < __builtin_inf() && s_own < __builtin_inf()) wk = exp(-(s_own - rho) * a.inv_lambda);
     w[threadIdx.x] = wk;
     if (gcb == 0) {
       const double e = block_sum(wk, red);
@@ -421,38 +427,41 @@ __device__ __forceinline__ double ordered_sum(const double *p, size_t stride, in
 // Returns with u0 (the emitted control, when a.emit) in u0_s.
 __device__ __forceinline__ void finalize_body(const FinalizeArgs &a, double *u0_out, double *status_out,
                                               double *u0_s) {
+  constexpr int NT = kFinBlock;
   __shared__ double N_lds[kMaxTM];
   __shared__ double eta_step[1024];                // per-step normalisers (cost-to-go weights)
-  __shared__ double red[16];
+  __shared__ double red[NT / 64];
   __shared__ double eta_s;
-  constexpr int kPer = kMaxTM / kFinBlock;
+  constexpr int kPer = kMaxTM / NT;
   const int TM = a.T * a.m;
-  double v = __builtin_inf();
-  for (int b = threadIdx.x; b < a.n_roll_blocks; b += kFinBlock) v = fmin(v, a.blk_min[b]);
+  // first block minimum outside the loop, so its load is in flight with all the others
+  double v = threadIdx.x < a.n_roll_blocks ? a.blk_min[threadIdx.x] : __builtin_inf();
+  for (int b = threadIdx.x + NT; b < a.n_roll_blocks; b += NT) v = fmin(v, a.blk_min[b]);
+  const uint64_t it0 = threadIdx.x == 0 ? a.iter[0] : 0;   // loaded with the rest, not after
   double Uold[kPer];
 #pragma unroll
   for (int n = 0; n < kPer; ++n) {
-    const int f = threadIdx.x + n * kFinBlock;
+    const int f = threadIdx.x + n * NT;
     Uold[n] = f < TM ? a.U64[f] : 0.0;
   }
   if (a.ctg) {
-    for (int i = threadIdx.x; i < a.T; i += kFinBlock) eta_step[i] = ordered_sum(a.eta_part + i, (size_t)a.T, a.n_kc);
+    for (int i = threadIdx.x; i < a.T; i += NT) eta_step[i] = ordered_sum(a.eta_part + i, (size_t)a.T, a.n_kc);
   } else if (threadIdx.x == 0) {
     eta_s = ordered_sum(a.eta_part, 1, a.n_kc);
   }
-  for (int f = threadIdx.x; f < TM; f += kFinBlock) N_lds[f] = ordered_sum(a.part + f, (size_t)a.G * 4, a.n_kc);
+  for (int f = threadIdx.x; f < TM; f += NT) N_lds[f] = ordered_sum(a.part + f, (size_t)a.G * 4, a.n_kc);
   v = wave_min(v);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x / 64] = v;
   __syncthreads();
   double rho = red[0];
-  for (int i = 1; i < kFinBlock / 64; ++i) rho = fmin(rho, red[i]);
+  for (int i = 1; i < NT / 64; ++i) rho = fmin(rho, red[i]);
   const bool ok = rho < __builtin_inf();
   const double eta = a.ctg ? eta_step[0] : eta_s;
   const double inv_eta = ok ? 1.0 / eta : 0.0;
   double Unew[kPer];
 #pragma unroll
   for (int n = 0; n < kPer; ++n) {
-    const int f = threadIdx.x + n * kFinBlock;
+    const int f = threadIdx.x + n * NT;
     Unew[n] = Uold[n];
     if (f < TM) {
       const int i = f / a.m, j = f - i * a.m;
@@ -468,19 +477,19 @@ __device__ __forceinline__ void finalize_body(const FinalizeArgs &a, double *u0_
     a.dbg[1] = ok ? eta : 0.0;
     if (!ok) a.flags[0] += 1;
     if (status_out) *status_out = ok ? 0.0 : -5.0;
-    a.iter[0] += 1;
+    a.iter[0] = it0 + 1;
   }
   if (a.emit) {
     __syncthreads();                                   // everyone has read N_lds
 #pragma unroll
     for (int n = 0; n < kPer; ++n) {
-      const int f = threadIdx.x + n * kFinBlock;
+      const int f = threadIdx.x + n * NT;
       if (f < TM) N_lds[f] = Unew[n];
     }
     __syncthreads();
 #pragma unroll
     for (int n = 0; n < kPer; ++n) {
-      const int f = threadIdx.x + n * kFinBlock;
+      const int f = threadIdx.x + n * NT;
       if (f < a.m) {
         u0_out[f] = N_lds[f];
         u0_s[f] = N_lds[f];
@@ -491,7 +500,7 @@ __device__ __forceinline__ void finalize_body(const FinalizeArgs &a, double *u0_
   }
 #pragma unroll
   for (int n = 0; n < kPer; ++n) {
-    const int f = threadIdx.x + n * kFinBlock;
+    const int f = threadIdx.x + n * NT;
     if (f < TM) {
       a.U64[f] = Unew[n];
       a.U32[f] = (float)Unew[n];
@@ -509,10 +518,12 @@ template <class Sys>
 __global__ __launch_bounds__(kFinBlock) void finalize_plant_kernel(const FinalizeArgs a, double *x, double dt, int n,
                                                                    const typename Sys::Params p) {
   __shared__ double u0_s[4];
+  double xl[Sys::N];
+  if (threadIdx.x == 0)                               // the plant state, loaded with the rest
+    for (int r = 0; r < Sys::N; ++r) xl[r] = r < n ? x[r] : 0.0;
   finalize_body(a, a.u0_out, nullptr, u0_s);
   if (threadIdx.x == 0) {
-    double xl[Sys::N], ul[Sys::M], xd[Sys::N];
-    for (int r = 0; r < Sys::N; ++r) xl[r] = r < n ? x[r] : 0.0;
+    double ul[Sys::M], xd[Sys::N];
     for (int j = 0; j < Sys::M; ++j) ul[j] = u0_s[j];
     Sys::xdot(p, xl, ul, xd);
     for (int r = 0; r < n; ++r) x[r] = xl[r] + dt * xd[r];

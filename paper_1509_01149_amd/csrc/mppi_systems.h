@@ -58,6 +58,8 @@ struct LinearSys {
   __device__ static float phi(const Params &p, const float *x) { return quad(p.Qf, x); }
   static constexpr int stage_floats(int, int) { return 0; }
   __device__ static void stage(const Params &, float *, const double *, int *, int *) {}
+  struct Regs {};
+  __device__ static void load_regs(const Params &, const StageView &, int, int, Regs &) {}
 };
 
 // ------------------------------------------------------------------------ cart-pole
@@ -74,7 +76,8 @@ struct CartPoleSys {
     const F l = d ? (F)p.dl : (F)p.l, g = d ? (F)p.dg : (F)p.g;
     const F Mt = mc + mp;
     const F iM = frcp(Mt);
-    const F s = fsin(x[2]), c = fcos(x[2]);
+    F s, c;
+    fsincos(x[2], s, c);
     const F h = (v[0] + mp * l * x[3] * x[3] * s) * iM;
     const F thdd = (g * s - c * h) * frcp(l * ((F)(4.0 / 3.0) - mp * c * c * iM));
     xd[0] = x[1];
@@ -93,6 +96,8 @@ struct CartPoleSys {
   }
   static constexpr int stage_floats(int, int) { return 0; }
   __device__ static void stage(const Params &, float *, const double *, int *, int *) {}
+  struct Regs {};
+  __device__ static void load_regs(const Params &, const StageView &, int, int, Regs &) {}
 };
 
 // ------------------------------------------------ cart-pole swing-up (velocity command)
@@ -112,7 +117,9 @@ struct SwingUpSys {
     xd[0] = x[1];
     xd[1] = pdd;
     xd[2] = x[3];
-    xd[3] = -k * (g * fsin(x[2]) + pdd * fcos(x[2]));
+    F s, c;
+    fsincos(x[2], s, c);
+    xd[3] = -k * (g * s + pdd * c);
   }
   static constexpr bool kSplitCost = false, kCrash = false;
   static constexpr int kLPS = MPPI_ROLLOUT_LPS;
@@ -124,6 +131,8 @@ struct SwingUpSys {
   __device__ static float phi(const Params &, const float *) { return 0.f; }
   static constexpr int stage_floats(int, int) { return 0; }
   __device__ static void stage(const Params &, float *, const double *, int *, int *) {}
+  struct Regs {};
+  __device__ static void load_regs(const Params &, const StageView &, int, int, Regs &) {}
 };
 
 // ------------------------------------------------------------ kinematic bicycle + map
@@ -146,26 +155,52 @@ struct BicycleSys {
     const F lim = d ? (F)p.dlim : (F)p.lim;
     F dl = x[4];
     if (lim > 0) dl = dl < -lim ? -lim : (dl > lim ? lim : dl);
-    const F s = fsin(x[2]), c = fcos(x[2]);
-    const F tn = fsin(dl) * frcp(fcos(dl));
+    F s, c, sd, cd;
+    fsincos(x[2], s, c);
+    fsincos(dl, sd, cd);
+    const F tn = sd * frcp(cd);
     xd[0] = x[3] * c;
     xd[1] = x[3] * s;
     xd[2] = x[3] * tn * (d ? (F)p.dL_inv : (F)p.L_inv);
     xd[3] = v[0];
     xd[4] = v[1];
   }
+  struct Regs {};
+  __device__ static void load_regs(const Params &, const StageView &, int, int, Regs &) {}
   static int tile_w(int W) { return W < kTile ? W : kTile; }
   static constexpr int stage_floats(int W, int H) { return (W < kTile ? W : kTile) * (H < kTile ? H : kTile); }
-  // Stage the window centred on the start position x0 (device, FP64).
+  // Stage the window centred on the start position x0 (device, FP64).  Wave w copies rows
+  // w, w + 4, ...; its lanes cover a row in coalesced 64-float chunks, and 4 rows x 3 chunks
+  // of loads are issued before the first is waited on (one wave per SIMD here, so the
+  // loads must overlap: a load-wait-store loop costs a full memory latency per element).
   __device__ static void stage(const Params &p, float *lds, const double *x0, int *i0, int *j0) {
     const int tw = p.W < kTile ? p.W : kTile, th = p.H < kTile ? p.H : kTile;
     int ci = (int)floor(x0[0] * (double)p.cell_inv) - tw / 2;
     int cj = (int)floor(x0[1] * (double)p.cell_inv) - th / 2;
     ci = ci < 0 ? 0 : (ci > p.W - tw ? p.W - tw : ci);
     cj = cj < 0 ? 0 : (cj > p.H - th ? p.H - th : cj);
-    for (int e = threadIdx.x; e < tw * th; e += kBlock) {
-      const int r = e / tw, c = e - r * tw;
-      lds[e] = p.map[(size_t)(cj + r) * p.W + (ci + c)];
+    constexpr int kRows = 4, kChunks = (kTile + kWave - 1) / kWave, kWaves = kBlock / kWave;
+    const int wv = threadIdx.x / kWave, ln = threadIdx.x % kWave;
+    for (int r0 = wv; r0 < th; r0 += kWaves * kRows) {
+      float v[kRows][kChunks];
+#pragma unroll
+      for (int rr = 0; rr < kRows; ++rr) {
+        const int r = r0 + kWaves * rr;
+#pragma unroll
+        for (int cc = 0; cc < kChunks; ++cc) {
+          const int c = ln + kWave * cc;
+          v[rr][cc] = (r < th && c < tw) ? p.map[(size_t)(cj + r) * p.W + (ci + c)] : 0.f;
+        }
+      }
+#pragma unroll
+      for (int rr = 0; rr < kRows; ++rr) {
+        const int r = r0 + kWaves * rr;
+#pragma unroll
+        for (int cc = 0; cc < kChunks; ++cc) {
+          const int c = ln + kWave * cc;
+          if (r < th && c < tw) lds[r * tw + c] = v[rr][cc];
+        }
+      }
     }
     *i0 = ci;
     *j0 = cj;
@@ -224,9 +259,10 @@ struct QuadrotorSys {
     const F J0 = d ? (F)p.dJ[0] : (F)p.J[0], J1 = d ? (F)p.dJ[1] : (F)p.J[1], J2 = d ? (F)p.dJ[2] : (F)p.J[2];
     const F Ji0 = d ? (F)p.dJinv[0] : (F)p.Jinv[0], Ji1 = d ? (F)p.dJinv[1] : (F)p.Jinv[1],
             Ji2 = d ? (F)p.dJinv[2] : (F)p.Jinv[2];
-    const F sr = fsin(x[6]), cr = fcos(x[6]);
-    const F sp = fsin(x[7]), cp = fcos(x[7]);
-    const F sy = fsin(x[8]), cy = fcos(x[8]);
+    F sr, cr, sp, cp, sy, cy;
+    fsincos(x[6], sr, cr);
+    fsincos(x[7], sp, cp);
+    fsincos(x[8], sy, cy);
     const F a = (f[0] + f[1] + f[2] + f[3]) * m_inv;
     xd[0] = x[3];
     xd[1] = x[4];
@@ -259,43 +295,67 @@ struct QuadrotorSys {
       for (int e = threadIdx.x; e < p.n_obs; e += kBlock) lds[4 * p.n_obs + e] = r2[e];
     }
   }
-  // Lane j of nj with the crash indicator on: the cost of q_part and, in `hit`, the count
-  // of crash conditions among the same obstacles (plus the ground for j = 0), from the
-  // same distances.
-  static constexpr bool kCrash = true;
-  __device__ static float q_part_crash(const Params &p, const StageView &sv, const float *x, int j, int nj,
-                                       float &hit) {
-    const float dx = x[0] - p.goal[0], dy = x[1] - p.goal[1], dz = x[2] - p.goal[2];
-    const float c = j == 0 ? p.wg * (dx * dx + dy * dy + dz * dz) : 0.f;
+  // The obstacles a lane visits first (j, j + nj, ... for kRegObs of them) are held in
+  // registers for the whole rollout, the rest are read from LDS each step: with one wave
+  // per SIMD, an LDS round trip per obstacle per step would dominate the step.  Unused
+  // register slots hold a zero obstacle (no barrier, no hit).
+  static constexpr int kRegObs = 8;
+  struct Regs {
+    float4 o[kRegObs];
+    float r2[kRegObs];
+  };
+  __device__ static void load_regs(const Params &p, const StageView &sv, int j, int nj, Regs &rg) {
     const float4 *ob = reinterpret_cast<const float4 *>(sv.lds);
     const float *r2 = sv.lds + 4 * p.n_obs;
-    float barrier = 0.f, h = (j == 0 && x[2] < p.ground) ? 1.f : 0.f;
-    for (int o = j; o < p.n_obs; o += nj) {
+#pragma unroll
+    for (int t = 0; t < kRegObs; ++t) {
+      const int o = j + nj * t;
+      const bool in = o < p.n_obs;
+      rg.o[t] = in ? ob[o] : make_float4(0.f, 0.f, 0.f, 0.f);
+      rg.r2[t] = in && p.crash > 0.f ? r2[o] : 0.f;
+    }
+  }
+  // Lane j of nj: the goal term (j = 0) plus the barriers of obstacles j, j + nj, ...; with
+  // kHit also the count of crash conditions among the same obstacles (and the ground for
+  // j = 0), from the same distances.
+  template <bool kHit>
+  __device__ static float cost_part(const Params &p, const StageView &sv, const Regs &rg, const float *x, int j,
+                                    int nj, float &hit) {
+    const float dx = x[0] - p.goal[0], dy = x[1] - p.goal[1], dz = x[2] - p.goal[2];
+    const float c = j == 0 ? p.wg * (dx * dx + dy * dy + dz * dz) : 0.f;
+    float barrier = 0.f, h = (kHit && j == 0 && x[2] < p.ground) ? 1.f : 0.f;
+#pragma unroll
+    for (int t = 0; t < kRegObs; ++t) {
+      const float4 ov = rg.o[t];
+      const float ex = x[0] - ov.x, ey = x[1] - ov.y, ez = x[2] - ov.z;
+      const float d2 = ex * ex + ey * ey + ez * ez;
+      const float pen = fmaxf(0.f, ov.w - d2);
+      barrier += pen * pen;
+      if (kHit) h += d2 < rg.r2[t] ? 1.f : 0.f;
+    }
+    const float4 *ob = reinterpret_cast<const float4 *>(sv.lds);
+    const float *r2 = sv.lds + 4 * p.n_obs;
+    for (int o = j + nj * kRegObs; o < p.n_obs; o += nj) {
       const float4 ov = ob[o];
       const float ex = x[0] - ov.x, ey = x[1] - ov.y, ez = x[2] - ov.z;
       const float d2 = ex * ex + ey * ey + ez * ez;
       const float pen = fmaxf(0.f, ov.w - d2);
       barrier += pen * pen;
-      h += d2 < r2[o] ? 1.f : 0.f;
+      if (kHit) h += d2 < r2[o] ? 1.f : 0.f;
     }
     hit = h;
     return c + p.wo * barrier;
   }
+  static constexpr bool kCrash = true;
+  __device__ static float q_part_crash(const Params &p, const StageView &sv, const Regs &rg, const float *x, int j,
+                                       int nj, float &hit) {
+    return cost_part<true>(p, sv, rg, x, j, nj, hit);
+  }
   static constexpr bool kSplitCost = true;
   static constexpr int kLPS = MPPI_ROLLOUT_LPS;
-  // Lane j of nj: the goal term (j = 0) plus the barriers of obstacles j, j + nj, ...
-  __device__ static float q_part(const Params &p, const StageView &sv, const float *x, int j, int nj) {
-    const float dx = x[0] - p.goal[0], dy = x[1] - p.goal[1], dz = x[2] - p.goal[2];
-    const float c = j == 0 ? p.wg * (dx * dx + dy * dy + dz * dz) : 0.f;
-    const float4 *ob = reinterpret_cast<const float4 *>(sv.lds);
-    float barrier = 0.f;
-    for (int o = j; o < p.n_obs; o += nj) {
-      const float4 ov = ob[o];
-      const float ex = x[0] - ov.x, ey = x[1] - ov.y, ez = x[2] - ov.z;
-      const float pen = fmaxf(0.f, ov.w - (ex * ex + ey * ey + ez * ez));
-      barrier += pen * pen;
-    }
-    return c + p.wo * barrier;
+  __device__ static float q_part(const Params &p, const StageView &sv, const Regs &rg, const float *x, int j, int nj) {
+    float unused;
+    return cost_part<false>(p, sv, rg, x, j, nj, unused);
   }
   __device__ static float q(const Params &p, const StageView &sv, const float *x) {
     const float dx = x[0] - p.goal[0], dy = x[1] - p.goal[1], dz = x[2] - p.goal[2];
