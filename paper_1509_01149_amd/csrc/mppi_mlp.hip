@@ -31,6 +31,13 @@ __device__ __forceinline__ float tanh_f(float x) {
   const float e = __builtin_amdgcn_exp2f(2.88539008177792681f * fabsf(x));   // exp(2|x|)
   return copysignf(1.f - 2.f * __builtin_amdgcn_rcpf(e + 1.f), x);
 }
+// tanh(x) from t = 2 log2(e) x, as 1 - 2 / (2^t + 1): valid for either sign (2^t -> 0 gives
+// -1, 2^t -> inf gives 1) and the same accuracy as tanh_f; the rollout forms t with one FMA
+// from the accumulator and the pre-scaled bias.
+constexpr float kTanhScale = 2.88539008177792681f;
+__device__ __forceinline__ float tanh_from_scaled(float t) {
+  return 1.f - 2.f * __builtin_amdgcn_rcpf(__builtin_amdgcn_exp2f(t) + 1.f);
+}
 
 // Layer-1 k slot (8 q + e) -> input feature (4 q + e, e < 4) or -1 (zero padding): each lane
 // of a 16-sample wave owns four consecutive features of its sample.
@@ -287,8 +294,8 @@ static __global__ __launch_bounds__(256) void mlp_rollout_kernel(const IterArgs 
   for (int t = 0; t < 8; ++t)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      b1[4 * t + r] = m.params[kOffB1 + 16 * t + 4 * q + r];
-      b2[4 * t + r] = m.params[kOffB2 + 16 * t + 4 * q + r];
+      b1[4 * t + r] = kTanhScale * m.params[kOffB1 + 16 * t + 4 * q + r];   // pre-scaled biases
+      b2[4 * t + r] = kTanhScale * m.params[kOffB2 + 16 * t + 4 * q + r];
     }
   float mu_in[4], isd_in[4], b3[4], sd_out[4], mu_out[4];
 #pragma unroll
@@ -338,7 +345,7 @@ static __global__ __launch_bounds__(256) void mlp_rollout_kernel(const IterArgs 
       floatx4 c = {0.f, 0.f, 0.f, 0.f};
       c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(W[t], bz, c, 0, 0, 0);
 #pragma unroll
-      for (int r = 0; r < 4; ++r) h1[4 * t + r] = tanh_f(c[r] + b1[4 * t + r]);
+      for (int r = 0; r < 4; ++r) h1[4 * t + r] = tanh_from_scaled(fmaf(c[r], kTanhScale, b1[4 * t + r]));
     }
     bf16x8 b2op[4];
 #pragma unroll
@@ -353,7 +360,7 @@ static __global__ __launch_bounds__(256) void mlp_rollout_kernel(const IterArgs 
 #pragma unroll
       for (int s = 0; s < 4; ++s) c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(W[8 + 4 * t + s], b2op[s], c, 0, 0, 0);
 #pragma unroll
-      for (int r = 0; r < 4; ++r) h2[4 * t + r] = tanh_f(c[r] + b2[4 * t + r]);
+      for (int r = 0; r < 4; ++r) h2[4 * t + r] = tanh_from_scaled(fmaf(c[r], kTanhScale, b2[4 * t + r]));
     }
     bf16x8 b3op[4];
 #pragma unroll
