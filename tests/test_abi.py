@@ -106,6 +106,34 @@ def test_bicycle_map_and_quadrotor_obstacles_are_validated():
     assert _ws(c)[0] == B.EINVAL
 
 
+def test_extension_fields_are_validated():
+    """Per-dimension exploration factors, the weighting, the reserved word, the crash
+    indicator's parameters and the swing-up pole are checked before any device work."""
+    wl = W.bicycle()
+    bad_nu = np.array([1.0, 0.0])
+    c, keep = _cfg(wl, nu_diag=B._ptr(bad_nu))
+    assert _ws(c)[0] == B.EINVAL
+    good_nu = np.array([1.0, 4.0])
+    c, keep = _cfg(wl, nu_diag=B._ptr(good_nu))
+    assert _ws(c)[0] == B.OK
+    for over in (dict(weighting=2), dict(weighting=-1), dict(reserved=1)):
+        c, keep = _cfg(wl, **over)
+        assert _ws(c)[0] == B.EINVAL, over
+    c, keep = _cfg(wl, weighting=B.WEIGHT_COST_TO_GO)
+    rc, n_ctg = _ws(c)
+    assert rc == B.OK and n_ctg >= _ws(_cfg(wl)[0])[1] + wl.T * wl.K * 8   # prefix costs [T][K]
+    q = W.quadrotor(crash=True)
+    c, keep = _cfg(q)
+    assert _ws(c)[0] == B.OK
+    c, keep = _cfg(q.replace(params=dict(q.params, crash_cost=-1.0)))
+    assert _ws(c)[0] == B.EINVAL
+    s = W.cartpole_swingup()
+    c, keep = _cfg(s)
+    assert _ws(c)[0] == B.OK
+    c, keep = _cfg(s.replace(params=dict(s.params, half_length=0.0)))
+    assert _ws(c)[0] == B.EINVAL
+
+
 def test_create_needs_a_device_or_fails_cleanly():
     """Without a GPU, mppi_create reports MPPI_EDEVICE (never a silent CPU fallback)."""
     import torch
