@@ -513,33 +513,50 @@ static __global__ __launch_bounds__(kFinBlock) void finalize_kernel(const Finali
   finalize_body(a, a.u0_out, nullptr, u0_s);
 }
 
-// finalize + the harness plant step on the emitted control: x <- x + dt (f + G u0), FP64.
+// --------------------------------------------------------------------- plant (FP64)
+// The harness plant step x <- x + dt xdot(x, u), FP64.  Every system is affine in its
+// control, so xdot(x, u) = f0 + sum_j u_j (f_{j+1} - f0) with f0 = xdot(x, 0) and
+// f_{j+1} = xdot(x, e_j): M + 1 lanes evaluate these in parallel, before u is known (in
+// the fused finalize, while the other waves wait on their loads), and one lane combines.
+// Both plant kernels use the same two functions, so they agree bit for bit.  x holds
+// n <= Sys::N doubles; components beyond n are treated as zero and not written.
+template <class Sys>
+__device__ __forceinline__ void plant_basis(const typename Sys::Params &p, const double *x, int n, int j,
+                                            double *out) {
+  double xl[Sys::N], ul[Sys::M];
+  for (int r = 0; r < Sys::N; ++r) xl[r] = r < n ? x[r] : 0.0;
+  for (int c = 0; c < Sys::M; ++c) ul[c] = c + 1 == j ? 1.0 : 0.0;
+  Sys::xdot(p, xl, ul, out);
+}
+template <class Sys>
+__device__ __forceinline__ void plant_combine(double *x, int n, double dt, const double (*basis)[Sys::N],
+                                              const double *u) {
+  for (int r = 0; r < n; ++r) {
+    double d = basis[0][r];
+    for (int c = 0; c < Sys::M; ++c) d += u[c] * (basis[c + 1][r] - basis[0][r]);
+    x[r] += dt * d;
+  }
+}
+
+// finalize + the plant step on the emitted control (wave 1 evaluates the plant basis).
 template <class Sys>
 __global__ __launch_bounds__(kFinBlock) void finalize_plant_kernel(const FinalizeArgs a, double *x, double dt, int n,
                                                                    const typename Sys::Params p) {
   __shared__ double u0_s[4];
-  double xl[Sys::N];
-  if (threadIdx.x == 0)                               // the plant state, loaded with the rest
-    for (int r = 0; r < Sys::N; ++r) xl[r] = r < n ? x[r] : 0.0;
-  finalize_body(a, a.u0_out, nullptr, u0_s);
-  if (threadIdx.x == 0) {
-    double ul[Sys::M], xd[Sys::N];
-    for (int j = 0; j < Sys::M; ++j) ul[j] = u0_s[j];
-    Sys::xdot(p, xl, ul, xd);
-    for (int r = 0; r < n; ++r) x[r] = xl[r] + dt * xd[r];
-  }
+  __shared__ double basis[Sys::M + 1][Sys::N];
+  const int j = (int)threadIdx.x - kWave;
+  if (j >= 0 && j <= Sys::M) plant_basis<Sys>(p, x, n, j, basis[j]);
+  finalize_body(a, a.u0_out, nullptr, u0_s);          // its barriers publish the basis
+  if (threadIdx.x == 0) plant_combine<Sys>(x, n, dt, basis, u0_s);
 }
 
-// --------------------------------------------------------------------- plant (FP64)
-// x holds n <= Sys::N doubles; components beyond n are treated as zero and not written.
+// The plant step alone (block of one wave).
 template <class Sys>
 __global__ void plant_kernel(double *x, const double *u, double dt, int n, const typename Sys::Params p) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  double xl[Sys::N], ul[Sys::M], xd[Sys::N];
-  for (int r = 0; r < Sys::N; ++r) xl[r] = r < n ? x[r] : 0.0;
-  for (int j = 0; j < Sys::M; ++j) ul[j] = u[j];
-  Sys::xdot(p, xl, ul, xd);
-  for (int r = 0; r < n; ++r) x[r] = xl[r] + dt * xd[r];
+  __shared__ double basis[Sys::M + 1][Sys::N];
+  if (threadIdx.x <= Sys::M) plant_basis<Sys>(p, x, n, threadIdx.x, basis[threadIdx.x]);
+  __syncthreads();
+  if (threadIdx.x == 0) plant_combine<Sys>(x, n, dt, basis, u);
 }
 
 // ---------------------------------------------------------------------- diagnostics
