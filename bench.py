@@ -116,7 +116,7 @@ def serving_mix_workloads(n_controllers):
     return out
 
 
-def serving_bench(seconds, plain_seconds, n_controllers=256, rate_hz=50.0, inflight=3):
+def serving_bench(seconds, plain_seconds, n_controllers=256, rate_hz=50.0, inflight=3, saturate_requests=8):
     """Replay the same Poisson trace (rate_hz per controller) through the batched server
     and through the plain one-controller-at-a-time policy; report latency percentiles and
     aggregate rollout-steps/s."""
@@ -153,7 +153,41 @@ def serving_bench(seconds, plain_seconds, n_controllers=256, rate_hz=50.0, infli
                          mean_batch=round((st1["batches"] and (st1["requests_done"] - st0["requests_done"]) /
                                            max(1, st1["batches"] - st0["batches"])), 2),
                          numeric_failures=int(np.sum(status != 0)))
+    if saturate_requests > 0:
+        res["saturated"] = saturation_bench(wls, saturate_requests, inflight)
     return res
+
+
+def saturation_bench(wls, per_controller, inflight):
+    """Capacity: every controller's requests arrive at once (per_controller each, served in
+    order, at most one in flight per controller), through both policies; the completion
+    span gives the sustained rate when the queue never empties."""
+    import paper_1509_01149_amd as P
+    n = len(wls)
+    ci = np.tile(np.arange(n), per_controller)
+    t = np.zeros(ci.size)
+    steps = float(sum(wls[c].K * wls[c].T for c in ci))
+    ops = float(sum(ALG_OPS_PER_ROLLOUT_STEP[wls[c].name] * wls[c].K * wls[c].T for c in ci))
+    out = dict(requests_per_controller=per_controller, requests=int(ci.size))
+    for mode in ("batched", "plain"):
+        kw = dict(max_slots=n, max_inflight=inflight, max_batch=n,
+                  mode=P.SERVE_BATCHED if mode == "batched" else P.SERVE_PLAIN, hbm_budget_bytes=64 << 30)
+        with P.Server(**kw) as srv:
+            slots = np.array([srv.admit(**P.controller_args(wl)) for wl in wls])
+            srv.replay(np.zeros(n), slots, [np.pad(w.x0, (0, 16 - w.n)) for w in wls])
+            st0 = srv.stats()
+            td, _, status = srv.replay(t, slots[ci], [np.pad(wls[c].x0, (0, 16 - wls[c].n)) for c in ci])
+            st1 = srv.stats()
+        span = float(td.max())
+        out[mode] = dict(completion_span_s=round(span, 4), requests_per_s=round(ci.size / span, 1),
+                         rollout_steps_per_s=round(steps / span, 1),
+                         rollout_alg_tflops=round(ops / span / 1e12, 3),
+                         frac_of_alu_peak=round(ops / span / 1e12 / ALU_PEAK_TFLOPS, 4),
+                         mean_batch=round((st1["requests_done"] - st0["requests_done"]) /
+                                          max(1, st1["batches"] - st0["batches"]), 2),
+                         numeric_failures=int(np.sum(status != 0)))
+    out["batched_over_plain"] = round(out["plain"]["completion_span_s"] / out["batched"]["completion_span_s"], 2)
+    return out
 
 
 def cpu_baseline(wl, seconds):
