@@ -7,9 +7,12 @@
  *   - problem statement (control-affine dynamics, state cost q, terminal cost phi,
  *     control cost R): Section II;
  *   - likelihood-ratio running cost for the special case A = sqrt(nu) I and the
- *     Monte-Carlo update law: Section III-C;
+ *     Monte-Carlo update law: Section III-C; a diagonal covariance change
+ *     A = diag(sqrt(nu_j)) from the theorem of Section III-A (mppi_config.nu_diag);
  *   - the control loop (sample, roll out, weight, update, send u0, shift, u_init):
- *     Algorithm 1, Section IV.
+ *     Algorithm 1, Section IV;
+ *   - the experiments' swing-up cart-pole and the quadrotor's crash indicator:
+ *     Section V.
  *
  * Conventions for every function below:
  *   - Every call returns an mppi_status; nothing throws across the ABI.  On failure

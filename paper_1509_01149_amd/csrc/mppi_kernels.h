@@ -1,8 +1,9 @@
 // The MPPI iteration as three kernels (paper: Algorithm 1 with the likelihood-ratio
 // running cost and update law of Section III-C):
 //
-//   rollout<Sys>  one lane per sample: draw the perturbations from Philox in registers,
-//                 Euler-step the dynamics over the horizon, accumulate the path cost
+//   rollout<Sys>  four lanes per sample (a DPP quad; one with the LPS = 1 build): draw the
+//                 perturbations from Philox in registers, Euler-step the dynamics over
+//                 the horizon, accumulate the path cost
 //                 S_k = sum_i [q(x_{i+1}) + du'Mq du + u'R du + u'R u/2] + phi, where
 //                 Mq = (R - A^-1 R A^-1)/2 and du ~ N(0, A Sigma A) (A = sqrt(nu) I or diagonal)
 //                 (FP32 arithmetic per step, FP64 running sum), write S_k and the block
@@ -10,7 +11,7 @@
 //   update        2-D grid over (sample chunk, noise group): rho = min_k S_k,
 //                 w_k = exp(-(S_k - rho)/lambda) in FP64, regenerate the same normals and
 //                 accumulate sum_k w_k eps_k in FP64; fixed-order reductions, no atomics.
-//   finalize      one block: eta = sum_k w_k, dU = sqrt(nu) L (sum_k w_k eps_k) / eta,
+//   finalize      one block: eta = sum_k w_k, dU = A L (sum_k w_k eps_k) / eta,
 //                 U += dU (FP64 master, FP32 copy for the next rollout); on the last
 //                 iteration of a control step emit u0 and apply the warm shift.
 #pragma once
@@ -40,7 +41,7 @@ struct IterArgs {
   int n_roll_blocks, n_kc;
   float dt;
   float Mq[16];            // 1/2 (R - A^-1 R A^-1): quadratic likelihood-ratio term, m x m
-  float Ls[16];            // sqrt(nu) chol(Sigma), row-major m x m (lower)
+  float Ls[16];            // A chol(Sigma), row-major m x m (lower)
   float R[16];             // m x m
   double inv_lambda;
 };
@@ -243,8 +244,9 @@ __device__ __forceinline__ double global_min(const double *blk_min, int n, doubl
 }
 
 // ------------------------------------------------------------------------- update
-// grid (n_kc, ceil(G / kUpdGroups)).  Thread t handles noise group gc*16 + t%16 for the
-// samples of strip t/16 of this block's 256-sample chunk.
+// grid (n_kc, ceil(G / kUpdGroups)).  Thread t handles noise group gcb*kUpdGroups +
+// t % kUpdGroups for the kUpdPerThread samples of strip t / kUpdGroups of this block's
+// 256-sample chunk.
 __device__ __forceinline__ void update_body(const IterArgs &a, int kc, int gcb) {
   __shared__ double w[kUpdChunk];
   __shared__ double acc_lds[kUpdStrips][kUpdGroups][4];
