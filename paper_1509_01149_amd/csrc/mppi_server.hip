@@ -59,8 +59,15 @@ struct Entry {
 };
 
 // Per-stream batch buffers: plan + staged start states (uploaded), results (downloaded).
+// A batch that mixes system types runs each type's rollout on its own stream (the batch
+// stream and kSide side streams forked from it), so the types' kernels fill the device
+// together instead of one after the other; the update and finalize join on the batch
+// stream.
+constexpr int kSide = 2;
 struct Batch {
   hipStream_t stream = nullptr;
+  hipStream_t side[kSide] = {nullptr, nullptr};
+  hipEvent_t fork = nullptr, join[kSide] = {nullptr, nullptr};
   hipEvent_t done = nullptr;
   bool active = false;
   char *h = nullptr, *d = nullptr;
@@ -100,13 +107,13 @@ struct mppi_server {
 namespace {
 
 template <class Sys, int Mode = 0>
-void launch_roll(mppi_server *s, Batch &b, int kind, int count, int total, size_t lds) {
+void launch_roll(mppi_server *s, Batch &b, int kind, int count, int total, size_t lds, hipStream_t st) {
   if (lds > s->lds_set[kind]) {
     (void)hipFuncSetAttribute((const void *)rollout_batched<Sys, Mode>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     s->lds_set[kind] = lds;
   }
   const int B = s->cfg.max_batch;
-  hipLaunchKernelGGL((rollout_batched<Sys, Mode>), dim3(total), dim3(kBlock), lds, b.stream, s->d_descs,
+  hipLaunchKernelGGL((rollout_batched<Sys, Mode>), dim3(total), dim3(kBlock), lds, st, s->d_descs,
                      (const WorkItem *)(b.d + b.off_items), (const int *)(b.d + b.off_sel) + kind * B,
                      (const int *)(b.d + b.off_proll) + kind * (B + 1), count);
 }
@@ -144,14 +151,36 @@ int launch_batched(mppi_server *s, Batch &b, const std::vector<int> &sl) {
   }
   hipError_t e = hipMemcpyAsync(b.d, b.h, b.off_out, hipMemcpyHostToDevice, b.stream);
   if (e != hipSuccess) return hip_fail(e, "batch upload");
-  if (cnt[0]) launch_roll<LinearSys<1>>(s, b, 0, cnt[0], proll[0 * (B + 1) + cnt[0]], lds[0]);
-  if (cnt[1]) launch_roll<LinearSys<2>>(s, b, 1, cnt[1], proll[1 * (B + 1) + cnt[1]], lds[1]);
-  if (cnt[2]) launch_roll<LinearSys<4>>(s, b, 2, cnt[2], proll[2 * (B + 1) + cnt[2]], lds[2]);
-  if (cnt[3]) launch_roll<CartPoleSys>(s, b, 3, cnt[3], proll[3 * (B + 1) + cnt[3]], lds[3]);
-  if (cnt[4]) launch_roll<BicycleSys>(s, b, 4, cnt[4], proll[4 * (B + 1) + cnt[4]], lds[4]);
-  if (cnt[5]) launch_roll<QuadrotorSys>(s, b, 5, cnt[5], proll[5 * (B + 1) + cnt[5]], lds[5]);
-  if (cnt[6]) launch_roll<SwingUpSys>(s, b, 6, cnt[6], proll[6 * (B + 1) + cnt[6]], lds[6]);
-  if (cnt[7]) launch_roll<QuadrotorSys, kCrashOn>(s, b, 7, cnt[7], proll[7 * (B + 1) + cnt[7]], lds[7]);
+  // one stream per system type present (the batch stream first, then the side streams)
+  int kinds[kKinds], nk = 0;
+  for (int k = 0; k < kKinds; ++k)
+    if (cnt[k]) kinds[nk++] = k;
+  const int n_side = std::min(nk - 1, kSide);
+  if (n_side > 0) {
+    e = hipEventRecord(b.fork, b.stream);
+    for (int i = 0; i < n_side && e == hipSuccess; ++i) e = hipStreamWaitEvent(b.side[i], b.fork, 0);
+    if (e != hipSuccess) return hip_fail(e, "batch fork");
+  }
+  for (int i = 0; i < nk; ++i) {
+    const int k = kinds[i];
+    const hipStream_t st = i == 0 ? b.stream : b.side[(i - 1) % kSide];
+    const int total = proll[k * (B + 1) + cnt[k]];
+    switch (k) {
+      case 0: launch_roll<LinearSys<1>>(s, b, k, cnt[k], total, lds[k], st); break;
+      case 1: launch_roll<LinearSys<2>>(s, b, k, cnt[k], total, lds[k], st); break;
+      case 2: launch_roll<LinearSys<4>>(s, b, k, cnt[k], total, lds[k], st); break;
+      case 3: launch_roll<CartPoleSys>(s, b, k, cnt[k], total, lds[k], st); break;
+      case 4: launch_roll<BicycleSys>(s, b, k, cnt[k], total, lds[k], st); break;
+      case 5: launch_roll<QuadrotorSys>(s, b, k, cnt[k], total, lds[k], st); break;
+      case 6: launch_roll<SwingUpSys>(s, b, k, cnt[k], total, lds[k], st); break;
+      default: launch_roll<QuadrotorSys, kCrashOn>(s, b, k, cnt[k], total, lds[k], st); break;
+    }
+  }
+  for (int i = 0; i < n_side; ++i) {
+    e = hipEventRecord(b.join[i], b.side[i]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(b.stream, b.join[i], 0);
+    if (e != hipSuccess) return hip_fail(e, "batch join");
+  }
   hipLaunchKernelGGL(update_batched, dim3(pupd[nb]), dim3(kBlock), 0, b.stream, s->d_descs,
                      (const WorkItem *)(b.d + b.off_items), (const int *)(b.d + b.off_pupd), nb);
   hipLaunchKernelGGL(finalize_batched, dim3(nb), dim3(kFinBlock), 0, b.stream, s->d_descs,
@@ -299,6 +328,11 @@ extern "C" int mppi_server_create(const mppi_server_config *cfg, mppi_server **o
     b.off_out = al(b.off_x0 + sizeof(double) * 16 * B);
     b.bytes = al(b.off_out + sizeof(double) * 8 * B);
     e = hipStreamCreateWithFlags(&b.stream, hipStreamNonBlocking);
+    for (int i = 0; i < kSide && e == hipSuccess; ++i) {
+      e = hipStreamCreateWithFlags(&b.side[i], hipStreamNonBlocking);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&b.join[i], hipEventDisableTiming);
+    }
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b.fork, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&b.done, hipEventDisableTiming);
     if (e == hipSuccess) e = hipHostMalloc((void **)&b.h, b.bytes, hipHostMallocDefault);
     if (e == hipSuccess) e = hipMalloc((void **)&b.d, b.bytes);
@@ -312,12 +346,20 @@ extern "C" int mppi_server_create(const mppi_server_config *cfg, mppi_server **o
 extern "C" int mppi_server_destroy(mppi_server *s) {
   if (!s) return MPPI_OK;
   (void)hipSetDevice(s->cfg.device);
-  for (auto &b : s->batches) if (b.stream) (void)hipStreamSynchronize(b.stream);
+  for (auto &b : s->batches) {
+    if (b.stream) (void)hipStreamSynchronize(b.stream);
+    for (auto st : b.side) if (st) (void)hipStreamSynchronize(st);
+  }
   for (auto &S : s->slots) if (S.ctx) mppi_destroy(S.ctx);
   for (auto &b : s->batches) {
     if (b.h) (void)hipHostFree(b.h);
     if (b.d) (void)hipFree(b.d);
     if (b.done) (void)hipEventDestroy(b.done);
+    if (b.fork) (void)hipEventDestroy(b.fork);
+    for (int i = 0; i < kSide; ++i) {
+      if (b.join[i]) (void)hipEventDestroy(b.join[i]);
+      if (b.side[i]) (void)hipStreamDestroy(b.side[i]);
+    }
     if (b.stream) (void)hipStreamDestroy(b.stream);
   }
   if (s->d_descs) (void)hipFree(s->d_descs);
