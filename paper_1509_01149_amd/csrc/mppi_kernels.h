@@ -89,9 +89,9 @@ enum { kRecordPrefix = 1, kCrashOn = 2 };
 // One horizon step of one sample from the four normals `e` of its noise group.
 template <class Sys, int LPS, int Mode>
 __device__ __forceinline__ void rollout_step(const IterArgs &a, const typename Sys::Params &p, const StageView &sv,
-                                             const typename Sys::Regs &rg, const float *sU, const float *sRU,
-                                             const float *sC, int i, int s, int lane_j, int k, const float e[4],
-                                             float *x, double &S, bool &crashed) {
+                                             const typename Sys::Regs &rg, const float *mrow, const float *sU,
+                                             const float *sRU, const float *sC, int i, int s, int lane_j, int k,
+                                             const float e[4], float *x, double &S, bool &crashed) {
   if constexpr ((Mode & kRecordPrefix) != 0)
     if (lane_j == 0 && k < a.K) a.pre[(size_t)i * a.K + k] = S;        // cost of steps before i
   constexpr int N = Sys::N, M = Sys::M;
@@ -114,21 +114,34 @@ __device__ __forceinline__ void rollout_step(const IterArgs &a, const typename S
 #pragma unroll
     for (int r = 0; r < N; ++r) x[r] += a.dt * xd[r];
   }
-  float quad = 0.f, lin = 0.f;
-#pragma unroll
-  for (int r = 0; r < M; ++r) {
+  // likelihood-ratio control terms du'Mq du + (R u_i)'du + u_i'R u_i / 2: with a split
+  // cost and one control per lane (m = 4), lane j takes row j (mrow = row j of Mq) and
+  // the terms join the state cost in the same quad sum
+  constexpr bool kSplitLR = LPS == 4 && Sys::kSplitCost && M == 4;
+  float quad = 0.f, lin = 0.f, lr_in = 0.f;         // lr_in: this lane's share (split form)
+  if constexpr (kSplitLR) {
+    const float duj = lane_j == 0 ? du[0] : (lane_j == 1 ? du[1] : (lane_j == 2 ? du[2] : du[3]));
     float t = 0.f;
 #pragma unroll
-    for (int j = 0; j < M; ++j) t += a.Mq[r * M + j] * du[j];
-    quad += du[r] * t;
-    lin += sRU[i * M + r] * du[r];
+    for (int j = 0; j < M; ++j) t += mrow[j] * du[j];
+    const float c0 = sC[i];                          // every lane reads it; lane 0 adds it
+    lr_in = duj * t + sRU[i * M + lane_j] * duj + (lane_j == 0 ? c0 : 0.f);
+  } else {
+#pragma unroll
+    for (int r = 0; r < M; ++r) {
+      float t = 0.f;
+#pragma unroll
+      for (int j = 0; j < M; ++j) t += a.Mq[r * M + j] * du[j];
+      quad += du[r] * t;
+      lin += sRU[i * M + r] * du[r];
+    }
   }
   float q;
   if constexpr ((Mode & kCrashOn) != 0) {          // crash indicator: sticky, crash cost per step
     static_assert(Sys::kCrash, "system has no crash indicator");
     float hit;
     if constexpr (LPS == 4) {
-      q = quad_sum(Sys::q_part_crash(p, sv, rg, x, lane_j, 4, hit));
+      q = quad_sum(Sys::q_part_crash(p, sv, rg, x, lane_j, 4, hit) + lr_in);
       hit = quad_sum(hit);
     } else {
       q = Sys::q_part_crash(p, sv, rg, x, 0, 1, hit);
@@ -136,11 +149,11 @@ __device__ __forceinline__ void rollout_step(const IterArgs &a, const typename S
     crashed = crashed || hit > 0.f;
     if (crashed) q += p.crash;
   } else if constexpr (LPS == 4 && Sys::kSplitCost) {
-    q = quad_sum(Sys::q_part(p, sv, rg, x, lane_j, 4));
+    q = quad_sum(Sys::q_part(p, sv, rg, x, lane_j, 4) + lr_in);
   } else {
     q = Sys::q(p, sv, x);
   }
-  const float qt = q + (quad + lin + sC[i]);
+  const float qt = kSplitLR ? q : q + (quad + lin + sC[i]);
   S += (double)qt;
 }
 
@@ -188,6 +201,12 @@ __device__ __forceinline__ void rollout_body(const IterArgs &a, const typename S
   const int lane_j = threadIdx.x % LPS;
   typename Sys::Regs rg;                            // per-lane register copy of system data
   Sys::load_regs(p, sv, lane_j, LPS, rg);
+  float mrow[4] = {0.f, 0.f, 0.f, 0.f};             // row lane_j of Mq (split control terms)
+  if constexpr (LPS == 4 && M == 4) {
+#pragma unroll
+    for (int l = 0; l < 4; ++l)
+      mrow[l] = lane_j == 0 ? a.Mq[l] : (lane_j == 1 ? a.Mq[4 + l] : (lane_j == 2 ? a.Mq[8 + l] : a.Mq[12 + l]));
+  }
   const int k = blk * (kBlock / LPS) + threadIdx.x / LPS;
   double S = 0.0;
   bool crashed = false;                             // set only in the kCrashOn variant
@@ -198,7 +217,7 @@ __device__ __forceinline__ void rollout_body(const IterArgs &a, const typename S
 #pragma unroll
       for (int s = 0; s < SPG; ++s) {
         const int i = g * SPG + s;
-        if (i < a.T) rollout_step<Sys, LPS, Mode>(a, p, sv, rg, sU, sRU, sC, i, s, 0, k, e, x, S, crashed);
+        if (i < a.T) rollout_step<Sys, LPS, Mode>(a, p, sv, rg, mrow, sU, sRU, sC, i, s, 0, k, e, x, S, crashed);
       }
     }
   } else {
@@ -212,7 +231,7 @@ __device__ __forceinline__ void rollout_body(const IterArgs &a, const typename S
         for (int c = 0; c < 4; ++c) e[c] = quad_bcast<J>(mine[c]);                      \
         _Pragma("unroll") for (int s = 0; s < SPG; ++s) {                               \
           const int i = (g0 + J) * SPG + s;                                             \
-          if (i < a.T) rollout_step<Sys, LPS, Mode>(a, p, sv, rg, sU, sRU, sC, i, s, lane_j, k, e, x, S, crashed); \
+          if (i < a.T) rollout_step<Sys, LPS, Mode>(a, p, sv, rg, mrow, sU, sRU, sC, i, s, lane_j, k, e, x, S, crashed); \
         }                                                                               \
       }
       MPPI_QUAD_GROUP(0)

@@ -335,6 +335,7 @@ struct QuadrotorSys {
     }
     const float4 *ob = reinterpret_cast<const float4 *>(sv.lds);
     const float *r2 = sv.lds + 4 * p.n_obs;
+    if (p.n_obs > nj * kRegObs)                     // block-uniform: skipped when all fit in registers
     for (int o = j + nj * kRegObs; o < p.n_obs; o += nj) {
       const float4 ov = ob[o];
       const float ex = x[0] - ov.x, ey = x[1] - ov.y, ez = x[2] - ov.z;
