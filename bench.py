@@ -31,8 +31,11 @@ sys.path.insert(0, ROOT)
 METRIC = "rollout-steps/sec (K*T) and MPPI iters/sec; p50/p99 step latency batched vs plain"
 
 # Algorithmic operations per rollout-step of the rollout kernel (FMA = 2, every other
-# FP32/FP64 arithmetic op, transcendental and Philox integer op = 1).  Derivation in
-# DESIGN.md ("Roofline").
+# FP32/FP64 arithmetic op, transcendental and Philox integer op = 1), counted per part:
+# noise (a quarter of a Philox4x32-10 call with its uniforms and Box-Muller per control,
+# about 130 ops per call), du = A L eps and v = u + du, the dynamics, the Euler update,
+# the state cost and the likelihood-ratio control terms; for example the quadrotor:
+# 130 + 24 + 80 + 24 + 428 (32 obstacles x 13 + goal) + 54 = 740.
 ALG_OPS_PER_ROLLOUT_STEP = {"cartpole": 87, "bicycle": 164, "quadrotor": 740, "linear": 90,
                             "cartpole_swingup": 77, "quadrotor_crash": 1064}
 # MLP [16 -> 128 -> 128 -> 12]: 2 (16*128 + 128*128 + 128*12) FLOP per rollout-step on BF16 MFMA.

@@ -5,7 +5,7 @@ import numpy as np
 import paper_1509_01149_amd as P
 from oracle import mppi, systems
 
-# Tolerances (derivation in DESIGN.md, "Parity tolerances"):
+# Tolerances and where they come from:
 #   U      max |U_gpu - U_orc| / max(1, |U_orc|_inf) <= 1e-4 (the stated bar for FP32 rollouts),
 #          plus twice the first-order effect of the (in-tolerance) cost differences,
 #          |(1/lambda) sum_k w_k (dS_k - <dS>_w) du_k|_inf / scale, which is only material when

@@ -114,8 +114,8 @@ def test_mppi_iteration_with_learned_dynamics():
 
 
 def test_trained_network_gain_over_untrained_and_against_analytic():
-    """Train on 1e6 analytic transitions on the GPU, then judge the learned model by the
-    analytic one: one-step error on held-out transitions, open-loop trajectory error,
+    """Train on 1e6 analytic transitions on the GPU, then assess the learned model against
+    the analytic one: one-step error on held-out transitions, open-loop trajectory error,
     control error of one MPPI iteration, and closed-loop cost on the analytic plant
     against (a) MPPI with the analytic model and (b) MPPI with the untrained network."""
     from oracle import systems
