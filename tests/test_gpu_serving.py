@@ -27,6 +27,9 @@ def mix():
         W.bicycle().replace(seed=26),
         W.cartpole(nu=1.0, K=257, T=7).replace(seed=27),
         W.quadrotor(nu=2.0, K=16384, T=50).replace(seed=28),
+        W.quadrotor(nu=2.0, K=2048, T=120, crash=True).replace(seed=29),      # own rollout type
+        W.cartpole_swingup(nu=100.0, K=1000).replace(seed=30),
+        W.bicycle(K=1024, T=30, nu=np.array([1.0, 4.0])).replace(seed=31),    # per-dimension nu
     ]
 
 
