@@ -54,31 +54,67 @@ __host__ __device__ __forceinline__ int hidden_of(int k) {
 
 // ------------------------------------------------------------------ generic GEMM
 // C[m][n] = sum_k A(m, k) B(k, n) over bf16 operands addressed by strides, FP32 result.
-// Block = 4 waves, each wave one 16 x 16 tile of C; K advances 32 per MFMA.
+// Block = 4 waves, each wave one 16 x 16 tile of C; K advances 32 per MFMA.  Split K:
+// block z covers k in [z k_chunk, (z + 1) k_chunk) and, when P is given, writes its
+// partial tile to P[z] (dense M x N); reduce_splits_kernel then sums the splits in order.
+// An operand whose k stride is 1 is read eight elements (16 bytes) at a time.
 static __global__ __launch_bounds__(256) void gemm_bf16_kernel(const __bf16 *__restrict__ A, long sam, long sak,
                                                                const __bf16 *__restrict__ B, long sbk, long sbn,
                                                                float *__restrict__ C, long scm, long scn, int M,
-                                                               int N, int K) {
+                                                               int N, int K, int k_chunk, float *__restrict__ P) {
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int m0 = blockIdx.y * 32 + (w >> 1) * 16, n0 = blockIdx.x * 32 + (w & 1) * 16;
   const int row = l & 15, kg = l >> 4;
+  const int kb = blockIdx.z * k_chunk, ke = min(K, kb + k_chunk);
   floatx4 acc = {0.f, 0.f, 0.f, 0.f};
   const __bf16 z = to_bf16(0.f);
-  for (int k0 = 0; k0 < K; k0 += 32) {
+  const bool a_row = m0 + row < M, b_row = n0 + row < N;
+  // 16-byte vector reads need k contiguous and every row start 16-byte aligned
+  const bool a_vec = sak == 1 && (sam & 7) == 0 && (reinterpret_cast<uintptr_t>(A) & 15) == 0;
+  const bool b_vec = sbk == 1 && (sbn & 7) == 0 && (reinterpret_cast<uintptr_t>(B) & 15) == 0;
+  for (int k0 = kb; k0 < ke; k0 += 32) {
+    const int k8 = k0 + 8 * kg;
     bf16x8 a, b;
+    if (a_vec && a_row && k8 + 8 <= ke) {
+      a = *reinterpret_cast<const bf16x8 *>(A + (long)(m0 + row) * sam + k8);
+    } else {
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int k = k0 + 8 * kg + e;
-      a[e] = (m0 + row < M && k < K) ? A[(long)(m0 + row) * sam + (long)k * sak] : z;
-      b[e] = (n0 + row < N && k < K) ? B[(long)k * sbk + (long)(n0 + row) * sbn] : z;
+      for (int e = 0; e < 8; ++e) a[e] = (a_row && k8 + e < ke) ? A[(long)(m0 + row) * sam + (long)(k8 + e) * sak] : z;
+    }
+    if (b_vec && b_row && k8 + 8 <= ke) {
+      b = *reinterpret_cast<const bf16x8 *>(B + (long)(n0 + row) * sbn + k8);
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) b[e] = (b_row && k8 + e < ke) ? B[(long)(k8 + e) * sbk + (long)(n0 + row) * sbn] : z;
     }
     acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
   }
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int m = m0 + 4 * kg + r, n = n0 + row;
-    if (m < M && n < N) C[(long)m * scm + (long)n * scn] = acc[r];
+    if (m < M && n < N) {
+      if (P) P[((long)blockIdx.z * M + m) * N + n] = acc[r];
+      else C[(long)m * scm + (long)n * scn] = acc[r];
+    }
   }
+}
+
+// C[m][n] = sum over the splits z = 0, 1, ... of P[z][m][n], in that order.
+static __global__ void reduce_splits_kernel(const float *__restrict__ P, int splits, int M, int N, float *C, long scm,
+                                            long scn) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= M * N) return;
+  float s = 0.f;
+  constexpr int kBatch = 16;                        // loads in flight per thread
+  for (int z0 = 0; z0 < splits; z0 += kBatch) {
+    float v[kBatch];
+#pragma unroll
+    for (int j = 0; j < kBatch; ++j) v[j] = z0 + j < splits ? P[(long)(z0 + j) * M * N + i] : 0.f;
+#pragma unroll
+    for (int j = 0; j < kBatch; ++j)
+      if (z0 + j < splits) s += v[j];
+  }
+  C[(long)(i / N) * scm + (long)(i % N) * scn] = s;
 }
 
 // ------------------------------------------------------------ elementwise kernels
@@ -122,9 +158,7 @@ static __global__ __launch_bounds__(256) void loss_grad_kernel(const float *Yc, 
 
 static __global__ void loss_finish_kernel(const double *loss_part, int nparts, int B, double *out) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  double s = 0.0;
-  for (int i = 0; i < nparts; ++i) s += loss_part[i];
-  *out = s / (double)(B * kOut);
+  *out = ordered_sum(loss_part, 1, nparts) / (double)(B * kOut);   // in order, loads batched
 }
 
 // dZ = dH (1 - H^2) (FP32 and bf16).
@@ -142,7 +176,15 @@ static __global__ __launch_bounds__(256) void colsum_kernel(const float *X, int 
   __shared__ double red[4];
   const int c = blockIdx.x;
   double s = 0.0;
-  for (int r = threadIdx.x; r < B; r += 256) s += (double)X[(long)r * ncol + c];
+  constexpr int kBatch = 8;                         // loads in flight per thread
+  for (int r0 = threadIdx.x; r0 < B; r0 += 256 * kBatch) {
+    float v[kBatch];
+#pragma unroll
+    for (int j = 0; j < kBatch; ++j) v[j] = r0 + 256 * j < B ? X[(long)(r0 + 256 * j) * ncol + c] : 0.f;
+#pragma unroll
+    for (int j = 0; j < kBatch; ++j)
+      if (r0 + 256 * j < B) s += (double)v[j];
+  }
   const double t = block_sum(s, red);
   if (threadIdx.x == 0) out[c] = (float)t;
 }
@@ -439,9 +481,13 @@ struct mppi_mlp {
 
 namespace {
 
+constexpr int kMaxSplits = 64;     // split-K partial tiles for the weight gradients
+constexpr int kSplitChunk = 128;   // samples per split (a multiple of the MFMA's 32)
+
 struct BatchBufs {
   __bf16 *Xh, *H1h, *H2h, *dYh, *dZ1h, *dZ2h;
   float *Tn, *Z1, *H1, *Z2, *H2, *Y, *dY, *dH2, *dZ2, *dH1, *dZ1;
+  float *part;                     // [kMaxSplits][kH][kH]
   double *loss_part, *loss;
   int *order;
 };
@@ -463,6 +509,7 @@ size_t batch_bytes(int B) {
   take((size_t)((B * kOut + 255) / 256 + 1) * 8);  // loss_part
   take(8);                                        // loss
   take((size_t)B * 4);                            // order
+  take((size_t)kMaxSplits * kH * kH * 4);         // part
   return o;
 }
 
@@ -490,6 +537,7 @@ BatchBufs carve(char *base, int B) {
   b.loss_part = (double *)take((size_t)((B * kOut + 255) / 256 + 1) * 8);
   b.loss = (double *)take(8);
   b.order = (int *)take((size_t)B * 4);
+  b.part = (float *)take((size_t)kMaxSplits * kH * kH * 4);
   return b;
 }
 
@@ -503,10 +551,24 @@ int ensure_cap(mppi_mlp *m, int B) {
   return MPPI_OK;
 }
 
+// part: split-K scratch of kMaxSplits * M * N floats, or NULL for no split.  A long K
+// (the weight gradients sum over the minibatch) is cut into kSplitChunk pieces so the
+// 16 output tiles become hundreds of blocks.
 void gemm(hipStream_t s, const __bf16 *A, long sam, long sak, const __bf16 *B, long sbk, long sbn, float *C, long scm,
-          long scn, int M, int N, int K) {
-  hipLaunchKernelGGL(gemm_bf16_kernel, dim3((N + 31) / 32, (M + 31) / 32), dim3(256), 0, s, A, sam, sak, B, sbk, sbn,
-                     C, scm, scn, M, N, K);
+          long scn, int M, int N, int K, float *part = nullptr) {
+  const dim3 grid((N + 31) / 32, (M + 31) / 32);
+  int splits = part ? (K + kSplitChunk - 1) / kSplitChunk : 1;
+  if (splits > kMaxSplits) splits = kMaxSplits;
+  if (splits <= 1) {
+    hipLaunchKernelGGL(gemm_bf16_kernel, grid, dim3(256), 0, s, A, sam, sak, B, sbk, sbn, C, scm, scn, M, N, K, K,
+                       (float *)nullptr);
+    return;
+  }
+  const int chunk = ((K + splits - 1) / splits + 31) / 32 * 32;
+  splits = (K + chunk - 1) / chunk;
+  hipLaunchKernelGGL(gemm_bf16_kernel, dim3(grid.x, grid.y, splits), dim3(256), 0, s, A, sam, sak, B, sbk, sbn, C, scm,
+                     scn, M, N, K, chunk, part);
+  hipLaunchKernelGGL(reduce_splits_kernel, dim3((M * N + 255) / 256), dim3(256), 0, s, part, splits, M, N, C, scm, scn);
 }
 
 inline int nb(long n, int t = 256) { return (int)((n + t - 1) / t); }
@@ -533,9 +595,9 @@ void bwd(mppi_mlp *m, const BatchBufs &b, int B) {
   gemm(s, b.dZ2h, kH, 1, m->W2h, kH, 1, b.dH1, kH, 1, B, kH, kH);
   hipLaunchKernelGGL(tanh_bwd_kernel, dim3(nb((long)B * kH)), dim3(256), 0, s, b.dH1, b.H1, b.dZ1, b.dZ1h, B * kH);
   // weight gradients: sum over the batch (k = sample)
-  gemm(s, b.dYh, 1, kOut, b.H2h, kH, 1, m->g + kOffW3, kH, 1, kOut, kH, B);
-  gemm(s, b.dZ2h, 1, kH, b.H1h, kH, 1, m->g + kOffW2, kH, 1, kH, kH, B);
-  gemm(s, b.dZ1h, 1, kH, b.Xh, 16, 1, m->g + kOffW1, kIn, 1, kH, kIn, B);
+  gemm(s, b.dYh, 1, kOut, b.H2h, kH, 1, m->g + kOffW3, kH, 1, kOut, kH, B, b.part);
+  gemm(s, b.dZ2h, 1, kH, b.H1h, kH, 1, m->g + kOffW2, kH, 1, kH, kH, B, b.part);
+  gemm(s, b.dZ1h, 1, kH, b.Xh, 16, 1, m->g + kOffW1, kIn, 1, kH, kIn, B, b.part);
   hipLaunchKernelGGL(colsum_kernel, dim3(kOut), dim3(256), 0, s, b.dY, B, kOut, m->g + kOffB3);
   hipLaunchKernelGGL(colsum_kernel, dim3(kH), dim3(256), 0, s, b.dZ2, B, kH, m->g + kOffB2);
   hipLaunchKernelGGL(colsum_kernel, dim3(kH), dim3(256), 0, s, b.dZ1, B, kH, m->g + kOffB1);
