@@ -233,3 +233,22 @@ def test_crash_indicator_parity(T):
     first = float(np.max(np.abs(_first_order(last, S_gpu, ok, wl.lam)))) / scale
     assert m["U_err"] <= 1e-4 + 2.0 * first + moved / scale
     assert m["stage_err"] <= 1e-5
+
+
+def test_all_costs_non_finite_leaves_the_sequence_and_reports():
+    """Every sample's path cost overflows FP32 (state cost ~1e60): the iteration leaves U
+    unchanged, the step still emits u0 and shifts, MPPI_ENUMERIC is reported, and the
+    controller recovers on the next finite step."""
+    wl = W.linear_double_integrator(K=1000, T=10, R=0.3).replace(seed=31)
+    U = np.linspace(-0.5, 0.5, wl.T)[:, None]
+    with controller(wl, u_nominal0=U) as c:
+        with pytest.raises(P.NumericError):
+            c.step(np.array([1e30, 0.0]))
+        assert np.array_equal(c.get_controls(), np.vstack([U[1:], [[0.0]]]))
+        assert c.iteration() == 1
+        S, rho, eta, dU = c.debug_last()
+        assert np.all(np.isinf(S)) and np.all(dU == 0.0)
+        U1 = c.get_controls()
+        c.step(wl.x0)                                          # finite again
+        m_res = mppi.control_step(wl, wl.x0, U1, 1)
+        assert np.abs(c.get_controls() - m_res[1]).max() < 1e-4
