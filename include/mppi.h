@@ -150,7 +150,8 @@ typedef struct {
   uint64_t params_bytes;      /* sizeof that block                                         */
   uint64_t seed;              /* Philox4x32-10 key of the rollout noise                    */
   int32_t device;             /* HIP device ordinal                                        */
-  int32_t use_graph;          /* nonzero: replay each step as a captured hipGraph          */
+  int32_t use_graph;          /* nonzero: replay each step as a captured hipGraph, one per */
+                              /* (n_iters, device pointers) combination, at most 16 kept  */
   void *stream;               /* hipStream_t to run on; NULL => the library makes its own  */
   void *workspace;            /* optional caller-owned device memory for all device state  */
   uint64_t workspace_bytes;   /* its size; must be >= mppi_workspace_bytes()               */

@@ -547,17 +547,27 @@ int enqueue_iterations(mppi_ctx *c, const double *x0_dev, int n_iters, double *u
 }
 
 // Run n_iters iterations, through a cached hipGraph when enabled.
+constexpr size_t kMaxGraphs = 16;   // captured step graphs kept per context
+
 int run_iterations(mppi_ctx *c, const double *x0_dev, int n_iters, double *u0_dev, double *plant_x) {
   if (!c->cfg.use_graph || c->profiling) return enqueue_iterations(c, x0_dev, n_iters, u0_dev, c->stream, plant_x);
   auto key = std::make_tuple(n_iters, (const void *)x0_dev, (const void *)u0_dev, (const void *)plant_x);
   auto itg = c->graphs.find(key);
   if (itg == c->graphs.end()) {
-    hipGraph_t g;
+    if (c->graphs.size() >= kMaxGraphs) {           // bounded cache: start over (none in flight)
+      HIP_TRY(hipStreamSynchronize(c->stream));
+      for (auto &kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+      c->graphs.clear();
+    }
+    hipGraph_t g = nullptr;
     hipGraphExec_t ge;
     HIP_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
     int rc = enqueue_iterations(c, x0_dev, n_iters, u0_dev, c->cap_stream, plant_x);
     hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
-    if (rc) return rc;
+    if (rc) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
     if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
     e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);

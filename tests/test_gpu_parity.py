@@ -252,3 +252,23 @@ def test_all_costs_non_finite_leaves_the_sequence_and_reports():
         c.step(wl.x0)                                          # finite again
         m_res = mppi.control_step(wl, wl.x0, U1, 1)
         assert np.abs(c.get_controls() - m_res[1]).max() < 1e-4
+
+
+def test_graph_cache_stays_bounded_and_correct():
+    """Steps with many different device buffers (one captured graph each) past the cache
+    bound give the same controls as one buffer reused."""
+    import torch
+    wl = W.bicycle(K=1024, T=20).replace(seed=33)
+    dev = torch.device("cuda:0")
+    with controller(wl) as a, controller(wl) as b:
+        xs = [torch.tensor(wl.x0, dtype=torch.float64, device=dev) for _ in range(20)]
+        us = [torch.zeros(wl.m, dtype=torch.float64, device=dev) for _ in range(20)]
+        x_one = torch.tensor(wl.x0, dtype=torch.float64, device=dev)
+        u_one = torch.zeros(wl.m, dtype=torch.float64, device=dev)
+        for j in range(20):
+            a.step_async(xs[j].data_ptr(), us[j].data_ptr())
+            b.step_async(x_one.data_ptr(), u_one.data_ptr())
+            a.sync()
+            b.sync()
+            assert torch.equal(us[j], u_one)
+        assert np.array_equal(a.get_controls(), b.get_controls())
