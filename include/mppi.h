@@ -199,6 +199,13 @@ int mppi_step_async(mppi_ctx *ctx, const double *x0_dev, int32_t n_iters, double
  * harness plant step (as mppi_plant_step_async) inside the same launch sequence. */
 int mppi_step_plant_async(mppi_ctx *ctx, double *x_dev, int32_t n_iters, double *u0_dev);
 
+/* n_steps consecutive closed-loop steps on the device in one launch sequence (one
+ * captured graph when use_graph is set): exactly n_steps calls of mppi_step_plant_async
+ * with u0_dev = u_log_dev + j m for step j (the same results bit for bit), without the
+ * per-launch gap between steps.  u_log_dev holds n_steps x m FP64 (device).
+ * 1 <= n_steps, n_iters and n_steps * n_iters <= 1000; status collected by mppi_sync. */
+int mppi_run_closed_loop_async(mppi_ctx *ctx, double *x_dev, int32_t n_steps, int32_t n_iters, double *u_log_dev);
+
 /* Wait for the context's stream.  Returns MPPI_ENUMERIC if any iteration since the
  * previous mppi_sync / mppi_step had no finite path cost, and clears that flag. */
 int mppi_sync(mppi_ctx *ctx);

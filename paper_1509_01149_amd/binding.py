@@ -108,6 +108,7 @@ def load() -> C.CDLL:
         "mppi_step": [C.c_void_p, _dp, C.c_int32, _dp],
         "mppi_step_async": [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p],
         "mppi_step_plant_async": [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p],
+        "mppi_run_closed_loop_async": [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p],
         "mppi_sync": [C.c_void_p],
         "mppi_plant_step_async": [C.c_void_p, C.c_void_p, C.c_void_p],
         "mppi_get_controls": [C.c_void_p, _dp, C.c_uint64],
@@ -286,6 +287,12 @@ class Controller:
     def step_plant_async(self, x_dev_ptr: int, u0_dev_ptr: int, n_iters: int = 1):
         """Device closed loop: step from x_dev, emit u0, then advance x_dev by the plant step."""
         check(self._lib.mppi_step_plant_async(self.handle, C.c_void_p(x_dev_ptr), int(n_iters), C.c_void_p(u0_dev_ptr)))
+
+    def run_closed_loop_async(self, x_dev_ptr: int, n_steps: int, u_log_dev_ptr: int, n_iters: int = 1):
+        """n_steps device closed-loop steps in one launch sequence; step j's u0 goes to
+        u_log (device, n_steps x m FP64) row j."""
+        check(self._lib.mppi_run_closed_loop_async(self.handle, C.c_void_p(x_dev_ptr), int(n_steps), int(n_iters),
+                                                   C.c_void_p(u_log_dev_ptr)))
 
     def sync(self):
         check(self._lib.mppi_sync(self.handle))

@@ -549,9 +549,20 @@ int enqueue_iterations(mppi_ctx *c, const double *x0_dev, int n_iters, double *u
 // Run n_iters iterations, through a cached hipGraph when enabled.
 constexpr size_t kMaxGraphs = 16;   // captured step graphs kept per context
 
-int run_iterations(mppi_ctx *c, const double *x0_dev, int n_iters, double *u0_dev, double *plant_x) {
-  if (!c->cfg.use_graph || c->profiling) return enqueue_iterations(c, x0_dev, n_iters, u0_dev, c->stream, plant_x);
-  auto key = std::make_tuple(n_iters, (const void *)x0_dev, (const void *)u0_dev, (const void *)plant_x);
+// n_steps control steps (closed loop: n_steps > 1 needs plant_x, and step j emits into
+// u0_dev + j m), through a cached hipGraph when enabled.
+static int enqueue_steps(mppi_ctx *c, const double *x0_dev, int n_iters, double *u0_dev, hipStream_t s,
+                         double *plant_x, int n_steps) {
+  for (int j = 0; j < n_steps; ++j) {
+    const int rc = enqueue_iterations(c, x0_dev, n_iters, u0_dev + (size_t)j * c->cfg.n_ctrl, s, plant_x);
+    if (rc) return rc;
+  }
+  return MPPI_OK;
+}
+
+int run_iterations(mppi_ctx *c, const double *x0_dev, int n_iters, double *u0_dev, double *plant_x, int n_steps) {
+  if (!c->cfg.use_graph || c->profiling) return enqueue_steps(c, x0_dev, n_iters, u0_dev, c->stream, plant_x, n_steps);
+  auto key = std::make_tuple(n_steps, n_iters, (const void *)x0_dev, (const void *)u0_dev, (const void *)plant_x);
   auto itg = c->graphs.find(key);
   if (itg == c->graphs.end()) {
     if (c->graphs.size() >= kMaxGraphs) {           // bounded cache: start over (none in flight)
@@ -562,7 +573,7 @@ int run_iterations(mppi_ctx *c, const double *x0_dev, int n_iters, double *u0_de
     hipGraph_t g = nullptr;
     hipGraphExec_t ge;
     HIP_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-    int rc = enqueue_iterations(c, x0_dev, n_iters, u0_dev, c->cap_stream, plant_x);
+    int rc = enqueue_steps(c, x0_dev, n_iters, u0_dev, c->cap_stream, plant_x, n_steps);
     hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
     if (rc) {
       if (g) (void)hipGraphDestroy(g);
@@ -766,6 +777,17 @@ extern "C" int mppi_step_plant_async(mppi_ctx *c, double *x_dev, int32_t n_iters
   if (!x_dev || !u0_dev) return fail(MPPI_EINVAL, "x_dev and u0_dev must be non-NULL");
   if (n_iters < 1 || n_iters > 1000) return fail(MPPI_EINVAL, "n_iters=%d outside [1, 1000]", n_iters);
   return run_iterations(c, x_dev, n_iters, u0_dev, x_dev);
+}
+
+extern "C" int mppi_run_closed_loop_async(mppi_ctx *c, double *x_dev, int32_t n_steps, int32_t n_iters,
+                                          double *u_log_dev) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (!x_dev || !u_log_dev) return fail(MPPI_EINVAL, "x_dev and u_log_dev must be non-NULL");
+  if (n_steps < 1 || n_steps > 1000) return fail(MPPI_EINVAL, "n_steps=%d outside [1, 1000]", n_steps);
+  if (n_iters < 1 || n_iters > 1000) return fail(MPPI_EINVAL, "n_iters=%d outside [1, 1000]", n_iters);
+  if ((int64_t)n_steps * n_iters > 1000) return fail(MPPI_EINVAL, "n_steps * n_iters exceeds 1000");
+  return run_iterations(c, x_dev, n_iters, u_log_dev, x_dev, n_steps);
 }
 
 extern "C" int mppi_sync(mppi_ctx *c) {

@@ -44,7 +44,8 @@ struct mppi_ctx {
   mppi::BicycleSys::Params bicycle;
   mppi::QuadrotorSys::Params quad;
   mppi::MlpState *mlp = nullptr;
-  std::map<std::tuple<int, const void *, const void *, const void *>, hipGraphExec_t> graphs;
+  // captured graphs keyed by (n_steps, n_iters, x0, u0, plant state)
+  std::map<std::tuple<int, int, const void *, const void *, const void *>, hipGraphExec_t> graphs;
   // profiling: pending (kind, start, stop) event triples and accumulated totals
   bool profiling = false;
   struct Timed { int kind; hipEvent_t a, b; };
@@ -63,7 +64,8 @@ int validate_config(const mppi_config *c);
 void compute_layout(const mppi_config *c, Layout *L);
 int enqueue_iterations(mppi_ctx *c, const double *x0_dev, int n_iters, double *u0_dev, hipStream_t s,
                        double *plant_x);
-int run_iterations(mppi_ctx *c, const double *x0_dev, int n_iters, double *u0_dev, double *plant_x);
+int run_iterations(mppi_ctx *c, const double *x0_dev, int n_iters, double *u0_dev, double *plant_x,
+                   int n_steps = 1);
 size_t ctx_rollout_lds(const mppi_ctx *c);
 void fill_desc(mppi_ctx *c, CtrlDesc *d);
 int set_device(int dev);

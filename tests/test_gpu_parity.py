@@ -272,3 +272,23 @@ def test_graph_cache_stays_bounded_and_correct():
             b.sync()
             assert torch.equal(us[j], u_one)
         assert np.array_equal(a.get_controls(), b.get_controls())
+
+
+def test_closed_loop_run_equals_single_steps():
+    """mppi_run_closed_loop_async over n steps == n calls of mppi_step_plant_async, bitwise."""
+    import torch
+    dev = torch.device("cuda:0")
+    for wl in (W.bicycle(K=2048, T=50), W.quadrotor(nu=2.0, K=1024, T=40), W.cartpole(nu=2.0)):
+        wl = wl.replace(seed=37)
+        xa = torch.tensor(wl.x0, dtype=torch.float64, device=dev)
+        xb = xa.clone()
+        log = torch.zeros((7, wl.m), dtype=torch.float64, device=dev)
+        ub = torch.zeros((7, wl.m), dtype=torch.float64, device=dev)
+        with controller(wl) as a, controller(wl) as b:
+            a.run_closed_loop_async(xa.data_ptr(), 7, log.data_ptr())
+            for j in range(7):
+                b.step_plant_async(xb.data_ptr(), ub[j].data_ptr())
+            a.sync()
+            b.sync()
+            assert torch.equal(xa, xb) and torch.equal(log, ub)
+            assert np.array_equal(a.get_controls(), b.get_controls()) and a.iteration() == b.iteration() == 7
