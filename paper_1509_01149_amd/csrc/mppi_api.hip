@@ -1,5 +1,6 @@
 // Host runtime and C ABI of libmppi (declarations and contracts: include/mppi.h).
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <cmath>
 #include <cstdarg>
@@ -387,14 +388,36 @@ static const void *rollout_fn_for(int mode) {
   }
 }
 
+static hipEvent_t take_event(mppi_ctx *c) {
+  if (!c->event_pool.empty()) {
+    hipEvent_t e = c->event_pool.back();
+    c->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Launch fn on s. In profiling mode the start and stop events are taken by the launch
+// itself, so the interval they bound holds this kernel alone (kind: 0 rollout).
+int timed_launch(mppi_ctx *c, int kind, const void *fn, dim3 grid, dim3 block, void **args, size_t lds,
+                 hipStream_t s) {
+  hipEvent_t e0 = c->profiling ? take_event(c) : nullptr;
+  hipEvent_t e1 = e0 ? take_event(c) : nullptr;
+  if (e0 && !e1) { c->event_pool.push_back(e0); e0 = nullptr; }
+  HIP_TRY(hipExtLaunchKernel(fn, grid, block, args, lds, s, e0, e1, 0));
+  if (e0) c->pending.push_back({kind, e0, e1});
+  return MPPI_OK;
+}
+
 template <class Sys>
 static int launch_rollout(mppi_ctx *c, const IterArgs &a, const typename Sys::Params &p, hipStream_t s) {
   const size_t lds = rollout_lds_bytes<Sys>(c);
   const void *fn = rollout_fn_for<Sys>(rollout_mode(c));
   if (!fn) return fail(MPPI_EINVAL, "rollout variant not available for system %d", c->cfg.system);
   void *args[] = {(void *)&a, (void *)&p};
-  HIP_TRY(hipLaunchKernel(fn, dim3(c->L.n_roll_blocks), dim3(kBlock), args, lds, s));
-  return MPPI_OK;
+  return timed_launch(c, 0, fn, dim3(c->L.n_roll_blocks), dim3(kBlock), args, lds, s);
 }
 
 template <class Sys>
@@ -455,17 +478,6 @@ static FinalizeArgs make_fin_args(mppi_ctx *c, double *u0_out, int emit) {
   return f;
 }
 
-static hipEvent_t take_event(mppi_ctx *c) {
-  if (!c->event_pool.empty()) {
-    hipEvent_t e = c->event_pool.back();
-    c->event_pool.pop_back();
-    return e;
-  }
-  hipEvent_t e = nullptr;
-  if (hipEventCreate(&e) != hipSuccess) return nullptr;
-  return e;
-}
-
 // Record the start event of a timed kernel (profiling mode only).
 static hipEvent_t prof_begin(mppi_ctx *c, hipStream_t s) {
   if (!c->profiling) return nullptr;
@@ -513,7 +525,6 @@ int enqueue_iterations(mppi_ctx *c, const double *x0_dev, int n_iters, double *u
   const IterArgs a = make_iter_args(c, x0_dev);
   for (int it = 0; it < n_iters; ++it) {
     int rc = MPPI_OK;
-    hipEvent_t t0 = prof_begin(c, s);
     switch (c->cfg.system) {
       case MPPI_SYS_LINEAR:
         if (c->cfg.n_ctrl == 1) rc = launch_rollout<LinearSys<1>>(c, a, c->linear_as<1>(), s);
@@ -527,9 +538,8 @@ int enqueue_iterations(mppi_ctx *c, const double *x0_dev, int n_iters, double *u
       case MPPI_SYS_QUADROTOR_MLP: rc = launch_mlp_rollout(c, a, s); break;
     }
     if (rc) return rc;
-    prof_end(c, s, 0, t0);
     const dim3 ugrid(c->L.n_kc, (c->L.G + kUpdGroups - 1) / kUpdGroups);
-    t0 = prof_begin(c, s);
+    hipEvent_t t0 = prof_begin(c, s);
     if (a.pre) {
       hipLaunchKernelGGL(stepmin_kernel, dim3(c->cfg.T), dim3(kBlock), 0, s, a);
       hipLaunchKernelGGL(update_ctg_kernel, ugrid, dim3(kBlock), 0, s, a);

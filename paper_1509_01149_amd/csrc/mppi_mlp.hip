@@ -893,8 +893,11 @@ int prepare_mlp_rollout(mppi_ctx *c) {
 
 int launch_mlp_rollout(mppi_ctx *c, const IterArgs &a, hipStream_t s) {
   MlpRollArgs m{c->mlp->frag, c->mlp->params, c->mlp->stats};
-  hipLaunchKernelGGL(mlp_rollout_kernel, dim3(c->L.n_roll_blocks), dim3(kBlock), mlp_rollout_lds(c), s, a, c->quad, m);
-  return MPPI_OK;
+  IterArgs a_arg = a;
+  QuadrotorSys::Params p_arg = c->quad;
+  void *args[] = {(void *)&a_arg, (void *)&p_arg, (void *)&m};
+  return timed_launch(c, 0, (const void *)mlp_rollout_kernel, dim3(c->L.n_roll_blocks), dim3(kBlock), args,
+                      mlp_rollout_lds(c), s);
 }
 
 }  // namespace mppi

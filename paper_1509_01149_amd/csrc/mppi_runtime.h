@@ -75,6 +75,8 @@ uint64_t extra_workspace_bytes(const mppi_config *c);
 int init_extra(mppi_ctx *c, const mppi_config *cfg);
 void destroy_extra(mppi_ctx *c);
 int launch_mlp_rollout(mppi_ctx *c, const IterArgs &a, hipStream_t s);
+int timed_launch(mppi_ctx *c, int kind, const void *fn, dim3 grid, dim3 block, void **args, size_t lds,
+                 hipStream_t s);
 int prepare_mlp_rollout(mppi_ctx *c);
 size_t mlp_rollout_lds(const mppi_ctx *c);
 }  // namespace mppi
