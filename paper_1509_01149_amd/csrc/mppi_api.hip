@@ -196,20 +196,27 @@ int validate_config(const mppi_config *c) {
 // ------------------------------------------------------------ workspace layout
 static uint64_t align256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
 
+// The step-split rollout serves the systems whose cost does not act on the state.
+bool rollout_split(const mppi_config *c) {
+  return c->system == MPPI_SYS_LINEAR || c->system == MPPI_SYS_CARTPOLE ||
+         c->system == MPPI_SYS_CARTPOLE_SWINGUP || c->system == MPPI_SYS_BICYCLE;
+}
+
+// Lanes per sample of the rollout.  Step-split: 16 while K x 16 lanes stay within two
+// waves per SIMD (K <= 8192), which trades redundant dynamics for a shorter chain per
+// wave on a device the controller cannot fill; 4 for larger K, where the device is full
+// and the redundancy would cost throughput.  Otherwise the four-lane body's build value.
+int rollout_lps(const mppi_config *c) {
+  if (rollout_split(c)) return c->K <= 8192 ? 16 : 4;
+  return MPPI_ROLLOUT_LPS;
+}
+
 void compute_layout(const mppi_config *c, Layout *L) {
   const int K = c->K, T = c->T, m = c->n_ctrl;
   L->TM = T * m;
   L->G = (L->TM + 3) / 4;
   // samples per rollout block: 64 for the learned dynamics (16 per wave), 256 / lanes-per-sample otherwise
-  int roll_per_block = kBlock;
-  switch (c->system) {
-    case MPPI_SYS_QUADROTOR_MLP: roll_per_block = 64; break;
-    case MPPI_SYS_LINEAR: roll_per_block = kBlock / LinearSys<1>::kLPS; break;
-    case MPPI_SYS_CARTPOLE: roll_per_block = kBlock / CartPoleSys::kLPS; break;
-    case MPPI_SYS_CARTPOLE_SWINGUP: roll_per_block = kBlock / SwingUpSys::kLPS; break;
-    case MPPI_SYS_BICYCLE: roll_per_block = kBlock / BicycleSys::kLPS; break;
-    case MPPI_SYS_QUADROTOR: roll_per_block = kBlock / QuadrotorSys::kLPS; break;
-  }
+  const int roll_per_block = c->system == MPPI_SYS_QUADROTOR_MLP ? 64 : kBlock / rollout_lps(c);
   L->n_roll_blocks = (K + roll_per_block - 1) / roll_per_block;
   L->n_kc = (K + kUpdChunk - 1) / kUpdChunk;
   uint64_t o = 0;
@@ -360,14 +367,16 @@ static size_t rollout_lds_bytes(const mppi_ctx *c) {
   int a = 0, b = 0;
   if (c->cfg.system == MPPI_SYS_BICYCLE) { a = c->bicycle.W; b = c->bicycle.H; }
   if (c->cfg.system == MPPI_SYS_QUADROTOR || c->cfg.system == MPPI_SYS_QUADROTOR_MLP) a = c->quad.n_obs;
-  fl += Sys::stage_floats(a, b);
+  if (!rollout_split(&c->cfg)) fl += Sys::stage_floats(a, b);   // the step-split body stages nothing
   return fl * 4;
 }
 
-// The rollout variant a context runs: cost-to-go weighting records prefix costs; the
+// The rollout variant a context runs: step-split where the system allows it, else the
+// four-lane body; recording prefix costs under cost-to-go weighting, and with the
 // quadrotor's crash indicator when its crash_cost is positive.
 static int rollout_mode(const mppi_ctx *c) {
   int mode = c->cfg.weighting == MPPI_WEIGHT_COST_TO_GO ? kRecordPrefix : 0;
+  if (rollout_split(&c->cfg)) return mode | kStepSplit;
   if (c->cfg.system == MPPI_SYS_QUADROTOR && c->quad.crash > 0.f) mode |= kCrashOn;
   return mode;
 }
@@ -375,11 +384,23 @@ static int rollout_mode(const mppi_ctx *c) {
 template <class Sys, int Mode>
 static const void *rollout_fn() {
   if constexpr ((Mode & kCrashOn) != 0 && !Sys::kCrash) return nullptr;
+  else if constexpr (Sys::kStepSplit) return nullptr;                // these run step-split
   else return (const void *)rollout_kernel<Sys, Sys::kLPS, Mode>;
 }
 
+template <class Sys, int Mode>
+static const void *rollout_split_fn(int lps) {
+  if constexpr (Sys::kStepSplit) {
+    if (lps == 16) return (const void *)rollout_kernel<Sys, 16, Mode>;
+    if (lps == 4) return (const void *)rollout_kernel<Sys, 4, Mode>;
+  }
+  return nullptr;
+}
+
 template <class Sys>
-static const void *rollout_fn_for(int mode) {
+static const void *rollout_fn_for(int mode, int lps) {
+  if (mode == kStepSplit) return rollout_split_fn<Sys, kStepSplit>(lps);
+  if (mode == (kStepSplit | kRecordPrefix)) return rollout_split_fn<Sys, kStepSplit | kRecordPrefix>(lps);
   switch (mode) {
     case 0: return rollout_fn<Sys, 0>();
     case kRecordPrefix: return rollout_fn<Sys, kRecordPrefix>();
@@ -414,7 +435,7 @@ int timed_launch(mppi_ctx *c, int kind, const void *fn, dim3 grid, dim3 block, v
 template <class Sys>
 static int launch_rollout(mppi_ctx *c, const IterArgs &a, const typename Sys::Params &p, hipStream_t s) {
   const size_t lds = rollout_lds_bytes<Sys>(c);
-  const void *fn = rollout_fn_for<Sys>(rollout_mode(c));
+  const void *fn = rollout_fn_for<Sys>(rollout_mode(c), rollout_lps(&c->cfg));
   if (!fn) return fail(MPPI_EINVAL, "rollout variant not available for system %d", c->cfg.system);
   void *args[] = {(void *)&a, (void *)&p};
   return timed_launch(c, 0, fn, dim3(c->L.n_roll_blocks), dim3(kBlock), args, lds, s);
@@ -424,7 +445,7 @@ template <class Sys>
 static int prepare_rollout(mppi_ctx *c) {
   const size_t lds = rollout_lds_bytes<Sys>(c);
   if (lds > 160 * 1024 - 64) return fail(MPPI_EINVAL, "rollout needs %zu B of LDS (T too large)", lds);
-  const void *fn = rollout_fn_for<Sys>(rollout_mode(c));
+  const void *fn = rollout_fn_for<Sys>(rollout_mode(c), rollout_lps(&c->cfg));
   if (!fn) return fail(MPPI_EINVAL, "rollout variant not available for system %d", c->cfg.system);
   HIP_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   return MPPI_OK;

@@ -48,7 +48,7 @@ __device__ __forceinline__ int find_item(const int *__restrict__ prefix, int n, 
   return lo;
 }
 
-template <class Sys, int Mode>
+template <class Sys, int LPS, int Mode>
 __global__ __launch_bounds__(kBlock) void rollout_batched(const CtrlDesc *__restrict__ descs,
                                                           const WorkItem *__restrict__ items,
                                                           const int *__restrict__ sel,
@@ -61,7 +61,7 @@ __global__ __launch_bounds__(kBlock) void rollout_batched(const CtrlDesc *__rest
   // from the descriptor
   const IterArgs a = d.it;
   const typename Sys::Params p = sys_params<Sys>(d.p);
-  rollout_body<Sys, Sys::kLPS, Mode>(a, p, w.x0, blockIdx.x - prefix[j], lds4);
+  rollout_any<Sys, LPS, Mode>(a, p, w.x0, blockIdx.x - prefix[j], lds4);
 }
 
 static __global__ __launch_bounds__(kBlock) void update_batched(const CtrlDesc *__restrict__ descs,

@@ -1,7 +1,9 @@
 // The MPPI iteration as three kernels (paper: Algorithm 1 with the likelihood-ratio
 // running cost and update law of Section III-C):
 //
-//   rollout<Sys>  four lanes per sample (a DPP quad; one with the LPS = 1 build): draw the
+//   rollout<Sys>  four lanes per sample (a DPP quad; one with the LPS = 1 build), or the
+//                 step-split variant (4 or 16 lanes sharing a sample's horizon) for
+//                 systems whose cost does not act on the state: draw the
 //                 perturbations from Philox in registers, Euler-step the dynamics over
 //                 the horizon, accumulate the path cost
 //                 S_k = sum_i [q(x_{i+1}) + du'Mq du + u'R du + u'R u/2] + phi, where
@@ -15,6 +17,8 @@
 //                 U += dU (FP64 master, FP32 copy for the next rollout); on the last
 //                 iteration of a control step emit u0 and apply the warm shift.
 #pragma once
+#include <type_traits>
+
 #include "mppi_systems.h"
 
 namespace mppi {
@@ -83,8 +87,10 @@ __device__ __forceinline__ float quad_sum(float v) {
 
 // Rollout variants (compile-time, so the default path carries none of their code):
 // kRecordPrefix records each sample's cost before every step (cost-to-go weighting);
-// kCrash applies the system's crash indicator (systems with Sys::kCrash only).
-enum { kRecordPrefix = 1, kCrashOn = 2 };
+// kCrash applies the system's crash indicator (systems with Sys::kCrash only);
+// kStepSplit selects the step-split body below (systems with Sys::kStepSplit; with
+// kRecordPrefix or alone).
+enum { kRecordPrefix = 1, kCrashOn = 2, kStepSplit = 4 };
 
 // One horizon step of one sample from the four normals `e` of its noise group.
 template <class Sys, int LPS, int Mode>
@@ -249,10 +255,213 @@ __device__ __forceinline__ void rollout_body(const IterArgs &a, const typename S
   if (threadIdx.x == 0) a.blk_min[blk] = bm;
 }
 
+// ------------------------------------------------------------- step-split rollout
+// For a system whose cost does not act back on its state (path weighting, no crash
+// indicator) the LPS lanes of a sample (4 or 16) share its horizon by noise group.  Per
+// chunk of LPS groups, lane j draws group g0 + j and forms the perturbations of that
+// group's steps and their likelihood-ratio terms; then every lane steps the dynamics
+// through the whole chunk, taking group g0 + jj's perturbations from lane jj by a DPP
+// broadcast, and lane j keeps the (cost-relevant) state after each of its own steps;
+// after the chunk lane j evaluates the state cost at those states.  So the noise and the
+// cost are computed once per step (not once per lane), and only the short dynamics
+// chain is redundant.  The per-step cost is the FP32 expression of the four-lane body;
+// each lane sums its steps in FP64 and the lanes' sums are added in a fixed tree.  Under
+// cost-to-go weighting (kRecordPrefix) the running cost before every step is recorded
+// from an in-order scan of the chunk's step costs; the path cost is the same tree sum in
+// both variants, so the two weightings see bitwise the same S.
+template <int LPS, int J>
+__device__ __forceinline__ float group_bcast(float v) {
+  if constexpr (LPS == 4) {
+    return quad_bcast<J>(v);
+  } else {
+    static_assert(LPS == 16, "step-split LPS is 4 or 16");
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x150 + J, 0xF, 0xF, false));  // row_newbcast:J
+  }
+}
+
+template <int Ctrl>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), Ctrl, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), Ctrl, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over a sample's LPS lanes; lane 0 of the group holds the fixed-order total.
+template <int LPS>
+__device__ __forceinline__ double group_sum(double v) {
+  v += dpp_f64<0xB1>(v);                            // quad_perm(1,0,3,2)
+  v += dpp_f64<0x4E>(v);                            // quad_perm(2,3,0,1)
+  if constexpr (LPS == 16) {
+    v += dpp_f64<0x124>(v);                         // row_ror:4
+    v += dpp_f64<0x128>(v);                         // row_ror:8
+  }
+  return v;
+}
+
+// Compile-time loop: f(std::integral_constant<int, J>) for J = B .. E-1.
+template <int B, int E>
+struct StaticFor {
+  template <class F>
+  __device__ __forceinline__ static void run(F &&f) {
+    if constexpr (B < E) {
+      f(std::integral_constant<int, B>{});
+      StaticFor<B + 1, E>::run(f);
+    }
+  }
+};
+
+template <class Sys, int LPS, int Mode>
+__device__ __forceinline__ void rollout_body_split(const IterArgs &a, const typename Sys::Params &p,
+                                                   const double *x0, int blk, float4 *lds4) {
+  static_assert((Mode & kCrashOn) == 0, "the step-split body has no crash indicator");
+  static_assert(Sys::kStepSplit, "system cost acts on the state");
+  constexpr int N = Sys::N, M = Sys::M, NQ = Sys::NQ;
+  constexpr int SPG = 4 / M;                        // steps per noise group
+  float *sU = reinterpret_cast<float *>(lds4);      // [T*M]
+  float *sRU = sU + a.T * M;                        // [T*M]  R u_i
+  float *sC = sRU + a.T * M;                        // [T]    u_i'R u_i / 2
+  __shared__ double red[4];
+
+  const uint64_t it = *a.iter;
+  float x[N];
+#pragma unroll
+  for (int r = 0; r < N; ++r) x[r] = r < a.n ? (float)x0[r] : 0.f;
+  for (int i = threadIdx.x; i < a.T; i += kBlock) {
+    float u[M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) u[j] = a.U32[i * M + j];
+    float c = 0.f;
+#pragma unroll
+    for (int r = 0; r < M; ++r) {
+      float s = 0.f;
+#pragma unroll
+      for (int j = 0; j < M; ++j) s += a.R[r * M + j] * u[j];
+      sU[i * M + r] = u[r];
+      sRU[i * M + r] = s;
+      c += u[r] * s;
+    }
+    sC[i] = 0.5f * c;
+  }
+  __syncthreads();
+
+  const int lane_j = threadIdx.x % LPS;
+  const int k = blk * (kBlock / LPS) + threadIdx.x / LPS;
+  double Sp = 0.0;                                  // this lane's steps
+  double P = 0.0;                                   // running cost (kRecordPrefix only)
+  for (int g0 = 0; g0 < a.G; g0 += LPS) {
+    // this lane's group: perturbations du = A L eps and likelihood-ratio terms of its steps
+    const int g = g0 + lane_j;
+    float e[4];
+    normals4((uint32_t)g, (uint32_t)k, it, a.key0, a.key1, e);
+    float du[4], lr[SPG];
+#pragma unroll
+    for (int s = 0; s < SPG; ++s) {
+      const int ic = min(g * SPG + s, a.T - 1);    // steps past the horizon are never used
+#pragma unroll
+      for (int j = 0; j < M; ++j) {
+        float t = 0.f;
+#pragma unroll
+        for (int l = 0; l <= j; ++l) t += a.Ls[j * M + l] * e[s * M + l];
+        du[s * M + j] = t;
+      }
+      float quad = 0.f, lin = 0.f;
+#pragma unroll
+      for (int r = 0; r < M; ++r) {
+        float t = 0.f;
+#pragma unroll
+        for (int j = 0; j < M; ++j) t += a.Mq[r * M + j] * du[s * M + j];
+        quad += du[s * M + r] * t;
+        lin += sRU[ic * M + r] * du[s * M + r];
+      }
+      lr[s] = quad + lin + sC[ic];
+    }
+    // every lane: the dynamics through the chunk; lane jj keeps the states after group jj's steps
+    float xq[SPG][NQ];
+#pragma unroll
+    for (int s = 0; s < SPG; ++s)
+#pragma unroll
+      for (int c = 0; c < NQ; ++c) xq[s][c] = 0.f;
+    // a full chunk runs without horizon checks (one basic block, so the control loads
+    // are scheduled ahead of the steps that use them); only the last chunk checks
+    auto chunk = [&](auto checked) {
+      constexpr bool kChecked = decltype(checked)::value;
+      StaticFor<0, LPS>::run([&](auto jc) {
+        constexpr int JJ = decltype(jc)::value;
+        const int i0 = (g0 + JJ) * SPG;
+        if (!kChecked || i0 < a.T) {
+          float db[4];
+#pragma unroll
+          for (int c = 0; c < 4; ++c) db[c] = group_bcast<LPS, JJ>(du[c]);
+          const bool mine = lane_j == JJ;
+#pragma unroll
+          for (int s = 0; s < SPG; ++s) {
+            const int i = i0 + s;
+            if (!kChecked || i < a.T) {
+              float v[M], xd[N], t[NQ];
+#pragma unroll
+              for (int j = 0; j < M; ++j) v[j] = sU[i * M + j] + db[s * M + j];
+              Sys::xdot(p, x, v, xd);
+#pragma unroll
+              for (int r = 0; r < N; ++r) x[r] += a.dt * xd[r];
+              Sys::cost_state(x, t);
+#pragma unroll
+              for (int c = 0; c < NQ; ++c) xq[s][c] = mine ? t[c] : xq[s][c];
+            }
+          }
+        }
+      });
+    };
+    if ((g0 + LPS) * SPG <= a.T) chunk(std::false_type{});
+    else chunk(std::true_type{});
+    // this lane's steps: state cost + likelihood-ratio terms
+    float qt[SPG];
+#pragma unroll
+    for (int s = 0; s < SPG; ++s) {
+      qt[s] = 0.f;
+      if (g * SPG + s < a.T) {
+        qt[s] = Sys::q_step(p, xq[s]) + lr[s];
+        Sp += (double)qt[s];
+      }
+    }
+    if constexpr ((Mode & kRecordPrefix) != 0) {
+      // cost-to-go weighting: the running cost before each step of the chunk, in step order
+      StaticFor<0, LPS>::run([&](auto jc) {
+        constexpr int JJ = decltype(jc)::value;
+#pragma unroll
+        for (int s = 0; s < SPG; ++s) {
+          const int i = (g0 + JJ) * SPG + s;
+          const float c = group_bcast<LPS, JJ>(qt[s]);
+          if (i < a.T) {
+            if (lane_j == 0 && k < a.K) a.pre[(size_t)i * a.K + k] = P;
+            P += (double)c;
+          }
+        }
+      });
+    }
+  }
+  double S = group_sum<LPS>(Sp) + (double)Sys::phi(p, x);
+  if (!isfinite(S)) S = __builtin_inf();
+  const bool valid = k < a.K && lane_j == 0;
+  if (valid) a.S[k] = S;
+  const double bm = block_min(valid ? S : __builtin_inf(), red);
+  if (threadIdx.x == 0) a.blk_min[blk] = bm;
+}
+
+// The body a rollout variant runs (the single-controller and the batched kernels alike).
+template <class Sys, int LPS, int Mode>
+__device__ __forceinline__ void rollout_any(const IterArgs &a, const typename Sys::Params &p, const double *x0,
+                                            int blk, float4 *lds4) {
+  if constexpr ((Mode & kStepSplit) != 0) {
+    rollout_body_split<Sys, LPS, Mode>(a, p, x0, blk, lds4);
+  } else {
+    rollout_body<Sys, LPS, Mode>(a, p, x0, blk, lds4);
+  }
+}
+
 template <class Sys, int LPS, int Mode>
 __global__ __launch_bounds__(kBlock) void rollout_kernel(const IterArgs a, const typename Sys::Params p) {
   extern __shared__ float4 lds4[];
-  rollout_body<Sys, LPS, Mode>(a, p, a.x0, blockIdx.x, lds4);
+  rollout_any<Sys, LPS, Mode>(a, p, a.x0, blockIdx.x, lds4);
 }
 
 // Minimum over the rollout blocks' minima (every thread gets it).

@@ -62,6 +62,8 @@ int fail(int code, const char *fmt, ...);
 int hip_fail(hipError_t e, const char *what);
 int validate_config(const mppi_config *c);
 void compute_layout(const mppi_config *c, Layout *L);
+bool rollout_split(const mppi_config *c);
+int rollout_lps(const mppi_config *c);
 int enqueue_iterations(mppi_ctx *c, const double *x0_dev, int n_iters, double *u0_dev, hipStream_t s,
                        double *plant_x);
 int run_iterations(mppi_ctx *c, const double *x0_dev, int n_iters, double *u0_dev, double *plant_x,

@@ -19,16 +19,19 @@ using namespace mppi;
 namespace {
 
 // rollout instantiations: linear m=1,2,4, cart-pole, bicycle, quadrotor, swing-up, quadrotor
-// with the crash indicator
-constexpr int kKinds = 8;
+// with the crash indicator; kinds 8 + (0, 1, 2, 3, 4, 6) are the step-split systems at 16
+// lanes per sample (at 4 below that)
+constexpr int kKinds = 16;
+constexpr int kWide = 8;
 
 int kind_of(const mppi_config &c) {
   if (c.system == MPPI_SYS_QUADROTOR && ((const mppi_quadrotor_params *)c.params)->crash_cost > 0) return 7;
+  const int wide = rollout_split(&c) && rollout_lps(&c) == 16 ? kWide : 0;
   switch (c.system) {
-    case MPPI_SYS_LINEAR: return c.n_ctrl == 1 ? 0 : (c.n_ctrl == 2 ? 1 : 2);
-    case MPPI_SYS_CARTPOLE: return 3;
-    case MPPI_SYS_BICYCLE: return 4;
-    case MPPI_SYS_CARTPOLE_SWINGUP: return 6;
+    case MPPI_SYS_LINEAR: return wide + (c.n_ctrl == 1 ? 0 : (c.n_ctrl == 2 ? 1 : 2));
+    case MPPI_SYS_CARTPOLE: return wide + 3;
+    case MPPI_SYS_BICYCLE: return wide + 4;
+    case MPPI_SYS_CARTPOLE_SWINGUP: return wide + 6;
     default: return 5;
   }
 }
@@ -106,14 +109,15 @@ struct mppi_server {
 
 namespace {
 
-template <class Sys, int Mode = 0>
+template <class Sys, int LPS, int Mode>
 void launch_roll(mppi_server *s, Batch &b, int kind, int count, int total, size_t lds, hipStream_t st) {
   if (lds > s->lds_set[kind]) {
-    (void)hipFuncSetAttribute((const void *)rollout_batched<Sys, Mode>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    (void)hipFuncSetAttribute((const void *)rollout_batched<Sys, LPS, Mode>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds);
     s->lds_set[kind] = lds;
   }
   const int B = s->cfg.max_batch;
-  hipLaunchKernelGGL((rollout_batched<Sys, Mode>), dim3(total), dim3(kBlock), lds, st, s->d_descs,
+  hipLaunchKernelGGL((rollout_batched<Sys, LPS, Mode>), dim3(total), dim3(kBlock), lds, st, s->d_descs,
                      (const WorkItem *)(b.d + b.off_items), (const int *)(b.d + b.off_sel) + kind * B,
                      (const int *)(b.d + b.off_proll) + kind * (B + 1), count);
 }
@@ -166,14 +170,20 @@ int launch_batched(mppi_server *s, Batch &b, const std::vector<int> &sl) {
     const hipStream_t st = i == 0 ? b.stream : b.side[(i - 1) % kSide];
     const int total = proll[k * (B + 1) + cnt[k]];
     switch (k) {
-      case 0: launch_roll<LinearSys<1>>(s, b, k, cnt[k], total, lds[k], st); break;
-      case 1: launch_roll<LinearSys<2>>(s, b, k, cnt[k], total, lds[k], st); break;
-      case 2: launch_roll<LinearSys<4>>(s, b, k, cnt[k], total, lds[k], st); break;
-      case 3: launch_roll<CartPoleSys>(s, b, k, cnt[k], total, lds[k], st); break;
-      case 4: launch_roll<BicycleSys>(s, b, k, cnt[k], total, lds[k], st); break;
-      case 5: launch_roll<QuadrotorSys>(s, b, k, cnt[k], total, lds[k], st); break;
-      case 6: launch_roll<SwingUpSys>(s, b, k, cnt[k], total, lds[k], st); break;
-      default: launch_roll<QuadrotorSys, kCrashOn>(s, b, k, cnt[k], total, lds[k], st); break;
+      case 0: launch_roll<LinearSys<1>, 4, kStepSplit>(s, b, k, cnt[k], total, lds[k], st); break;
+      case 1: launch_roll<LinearSys<2>, 4, kStepSplit>(s, b, k, cnt[k], total, lds[k], st); break;
+      case 2: launch_roll<LinearSys<4>, 4, kStepSplit>(s, b, k, cnt[k], total, lds[k], st); break;
+      case 3: launch_roll<CartPoleSys, 4, kStepSplit>(s, b, k, cnt[k], total, lds[k], st); break;
+      case 4: launch_roll<BicycleSys, 4, kStepSplit>(s, b, k, cnt[k], total, lds[k], st); break;
+      case 5: launch_roll<QuadrotorSys, QuadrotorSys::kLPS, 0>(s, b, k, cnt[k], total, lds[k], st); break;
+      case 6: launch_roll<SwingUpSys, 4, kStepSplit>(s, b, k, cnt[k], total, lds[k], st); break;
+      case 7: launch_roll<QuadrotorSys, QuadrotorSys::kLPS, kCrashOn>(s, b, k, cnt[k], total, lds[k], st); break;
+      case kWide + 0: launch_roll<LinearSys<1>, 16, kStepSplit>(s, b, k, cnt[k], total, lds[k], st); break;
+      case kWide + 1: launch_roll<LinearSys<2>, 16, kStepSplit>(s, b, k, cnt[k], total, lds[k], st); break;
+      case kWide + 2: launch_roll<LinearSys<4>, 16, kStepSplit>(s, b, k, cnt[k], total, lds[k], st); break;
+      case kWide + 3: launch_roll<CartPoleSys, 16, kStepSplit>(s, b, k, cnt[k], total, lds[k], st); break;
+      case kWide + 4: launch_roll<BicycleSys, 16, kStepSplit>(s, b, k, cnt[k], total, lds[k], st); break;
+      default: launch_roll<SwingUpSys, 16, kStepSplit>(s, b, k, cnt[k], total, lds[k], st); break;
     }
   }
   for (int i = 0; i < n_side; ++i) {

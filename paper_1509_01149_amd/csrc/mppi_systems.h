@@ -53,6 +53,14 @@ struct LinearSys {
   }
   static constexpr bool kSplitCost = false, kCrash = false;
   static constexpr int kLPS = MPPI_ROLLOUT_LPS;
+  // step-split rollout: the cost reads the whole state
+  static constexpr bool kStepSplit = true;
+  static constexpr int NQ = N;
+  __device__ static void cost_state(const float *x, float *xq) {
+#pragma unroll
+    for (int r = 0; r < N; ++r) xq[r] = x[r];
+  }
+  __device__ static float q_step(const Params &p, const float *xq) { return quad(p.Q, xq); }
   __device__ static float q(const Params &p, const StageView &, const float *x) { return quad(p.Q, x); }
   __device__ static float q_part(const Params &p, const StageView &sv, const float *x, int, int) { return q(p, sv, x); }
   __device__ static float phi(const Params &p, const float *x) { return quad(p.Qf, x); }
@@ -90,6 +98,13 @@ struct CartPoleSys {
   __device__ static float q(const Params &p, const StageView &, const float *x) {
     return p.qd[0] * x[0] * x[0] + p.qd[1] * x[1] * x[1] + p.qd[2] * x[2] * x[2] + p.qd[3] * x[3] * x[3];
   }
+  static constexpr bool kStepSplit = true;
+  static constexpr int NQ = N;
+  __device__ static void cost_state(const float *x, float *xq) {
+#pragma unroll
+    for (int r = 0; r < N; ++r) xq[r] = x[r];
+  }
+  __device__ static float q_step(const Params &p, const float *xq) { return q(p, StageView{}, xq); }
   __device__ static float q_part(const Params &p, const StageView &sv, const float *x, int, int) { return q(p, sv, x); }
   __device__ static float phi(const Params &p, const float *x) {
     return p.qfd[0] * x[0] * x[0] + p.qfd[1] * x[1] * x[1] + p.qfd[2] * x[2] * x[2] + p.qfd[3] * x[3] * x[3];
@@ -127,6 +142,13 @@ struct SwingUpSys {
     const float a = 1.f + fcos(x[2]);
     return p.wp * x[0] * x[0] + p.wa * a * a + p.wr * x[3] * x[3] + p.wv * x[1] * x[1];
   }
+  static constexpr bool kStepSplit = true;
+  static constexpr int NQ = N;
+  __device__ static void cost_state(const float *x, float *xq) {
+#pragma unroll
+    for (int r = 0; r < N; ++r) xq[r] = x[r];
+  }
+  __device__ static float q_step(const Params &p, const float *xq) { return q(p, StageView{}, xq); }
   __device__ static float q_part(const Params &p, const StageView &sv, const float *x, int, int) { return q(p, sv, x); }
   __device__ static float phi(const Params &, const float *) { return 0.f; }
   static constexpr int stage_floats(int, int) { return 0; }
@@ -136,10 +158,12 @@ struct SwingUpSys {
 };
 
 // ------------------------------------------------------------ kinematic bicycle + map
-// The cost map (FP32, [y][x]) stays in HBM; each block stages the kTile x kTile window
-// around the current start position into LDS (the horizon's reachable region at the
-// configured speeds) and reads the bilinear taps from LDS whenever all four lie inside
-// the window, from global memory (L2) otherwise.  Both paths read identical values.
+// The cost map (FP32, [y][x]) stays in HBM.  The four-lane rollout (cost-to-go weighting)
+// stages the kTile x kTile window around the current start position into LDS (the
+// horizon's reachable region at the configured speeds) and reads the bilinear taps from
+// LDS whenever all four lie inside the window, from global memory (L2) otherwise; the
+// step-split rollout evaluates each step's cost a chunk after the state is known and
+// reads the taps from global memory.  All paths read identical values.
 struct BicycleSys {
   static constexpr int N = 5, M = 2;
   static constexpr int kTile = 160;   // 160 x 160 x 4 B = 100 KiB of LDS
@@ -237,6 +261,27 @@ struct BicycleSys {
     const float dv = x[3] - p.vt;
     return (1.f - fy) * top + fy * bot + p.ws * dv * dv;
   }
+  // Step-split rollout: the cost needs position and speed only, and reads the bilinear
+  // taps straight from the map in global memory (L2-resident; no LDS window, so no
+  // fallback).  Same arithmetic and tap values as q().
+  static constexpr bool kStepSplit = true;
+  static constexpr int NQ = 3;
+  __device__ static void cost_state(const float *x, float *xq) { xq[0] = x[0]; xq[1] = x[1]; xq[2] = x[3]; }
+  __device__ static float q_step(const Params &p, const float *xq) {
+    float gx = xq[0] * p.cell_inv, gy = xq[1] * p.cell_inv;
+    gx = fminf(fmaxf(gx, 0.f), (float)(p.W - 1));
+    gy = fminf(fmaxf(gy, 0.f), (float)(p.H - 1));
+    const int i0 = min((int)floorf(gx), p.W - 2);
+    const int j0 = min((int)floorf(gy), p.H - 2);
+    const float fx = gx - (float)i0, fy = gy - (float)j0;
+    const __attribute__((address_space(1))) float *g =
+        (const __attribute__((address_space(1))) float *)p.map + ((size_t)j0 * p.W + i0);
+    const float m00 = g[0], m01 = g[1], m10 = g[p.W], m11 = g[p.W + 1];
+    const float top = (1.f - fx) * m00 + fx * m01;
+    const float bot = (1.f - fx) * m10 + fx * m11;
+    const float dv = xq[2] - p.vt;
+    return (1.f - fy) * top + fy * bot + p.ws * dv * dv;
+  }
   __device__ static float phi(const Params &, const float *) { return 0.f; }
 };
 
@@ -244,6 +289,7 @@ struct BicycleSys {
 struct QuadrotorSys {
   static constexpr int N = 12, M = 4;
   static constexpr int kMaxObstacles = 256;
+  static constexpr bool kStepSplit = false;   // obstacles split over the quad instead
   struct Params {
     float m_inv, g, arm, kap, J[3], Jinv[3], goal[3], wg, wo, margin;
     int n_obs;
