@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace mppi {
 
 constexpr int kBlock = 256;       // threads per block in every kernel (4 wave64s)
@@ -82,6 +84,36 @@ __device__ __forceinline__ void fsincos(float x, float &s, float &c) {
   c = __builtin_amdgcn_cosf(r);
 }
 __device__ __forceinline__ void fsincos(double x, double &s, double &c) { sincos(x, &s, &c); }
+
+// ---------------------------------------------------------------------------------
+// Lane groups of a wave: broadcast lane J of each aligned group of G lanes to the group
+// (DPP: quad_perm for 4, row_newbcast for a 16-lane row).
+// ---------------------------------------------------------------------------------
+template <int J>
+__device__ __forceinline__ float quad_bcast(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), J * 0x55, 0xF, 0xF, false));
+}
+template <int G, int J>
+__device__ __forceinline__ float group_bcast(float v) {
+  if constexpr (G == 4) {
+    return quad_bcast<J>(v);
+  } else {
+    static_assert(G == 16, "lane groups of 4 or 16");
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x150 + J, 0xF, 0xF, false));  // row_newbcast:J
+  }
+}
+
+// Compile-time loop: f(std::integral_constant<int, J>) for J = B .. E-1.
+template <int B, int E>
+struct StaticFor {
+  template <class F>
+  __device__ __forceinline__ static void run(F &&f) {
+    if constexpr (B < E) {
+      f(std::integral_constant<int, B>{});
+      StaticFor<B + 1, E>::run(f);
+    }
+  }
+};
 
 // ---------------------------------------------------------------------------------
 // Wave64 / block reductions (fixed order: results do not depend on timing).

@@ -17,8 +17,6 @@
 //                 U += dU (FP64 master, FP32 copy for the next rollout); on the last
 //                 iteration of a control step emit u0 and apply the warm shift.
 #pragma once
-#include <type_traits>
-
 #include "mppi_systems.h"
 
 namespace mppi {
@@ -75,10 +73,6 @@ struct FinalizeArgs {
 // DPP steps, and the dynamics run redundantly, so all four lanes hold the same state and
 // the same path cost.  The single-controller kernel and the batched serving kernel both
 // call this body, so a controller's results do not depend on what else shares a launch.
-template <int J>
-__device__ __forceinline__ float quad_bcast(float v) {
-  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), J * 0x55, 0xF, 0xF, false));
-}
 __device__ __forceinline__ float quad_sum(float v) {
   v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));   // quad_perm(1,0,3,2)
   v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, false));   // quad_perm(2,3,0,1)
@@ -269,16 +263,6 @@ __device__ __forceinline__ void rollout_body(const IterArgs &a, const typename S
 // cost-to-go weighting (kRecordPrefix) the running cost before every step is recorded
 // from an in-order scan of the chunk's step costs; the path cost is the same tree sum in
 // both variants, so the two weightings see bitwise the same S.
-template <int LPS, int J>
-__device__ __forceinline__ float group_bcast(float v) {
-  if constexpr (LPS == 4) {
-    return quad_bcast<J>(v);
-  } else {
-    static_assert(LPS == 16, "step-split LPS is 4 or 16");
-    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x150 + J, 0xF, 0xF, false));  // row_newbcast:J
-  }
-}
-
 template <int Ctrl>
 __device__ __forceinline__ double dpp_f64(double v) {
   const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), Ctrl, 0xF, 0xF, false);
@@ -297,18 +281,6 @@ __device__ __forceinline__ double group_sum(double v) {
   }
   return v;
 }
-
-// Compile-time loop: f(std::integral_constant<int, J>) for J = B .. E-1.
-template <int B, int E>
-struct StaticFor {
-  template <class F>
-  __device__ __forceinline__ static void run(F &&f) {
-    if constexpr (B < E) {
-      f(std::integral_constant<int, B>{});
-      StaticFor<B + 1, E>::run(f);
-    }
-  }
-};
 
 template <class Sys, int LPS, int Mode>
 __device__ __forceinline__ void rollout_body_split(const IterArgs &a, const typename Sys::Params &p,
@@ -385,31 +357,35 @@ __device__ __forceinline__ void rollout_body_split(const IterArgs &a, const type
     // are scheduled ahead of the steps that use them); only the last chunk checks
     auto chunk = [&](auto checked) {
       constexpr bool kChecked = decltype(checked)::value;
-      StaticFor<0, LPS>::run([&](auto jc) {
-        constexpr int JJ = decltype(jc)::value;
-        const int i0 = (g0 + JJ) * SPG;
-        if (!kChecked || i0 < a.T) {
-          float db[4];
+      if constexpr (Sys::kOwnChunk) {
+        Sys::template chunk<LPS, SPG, kChecked>(p, a.T, a.dt, sU, du, g0, lane_j, x, xq);
+      } else {
+        StaticFor<0, LPS>::run([&](auto jc) {
+          constexpr int JJ = decltype(jc)::value;
+          const int i0 = (g0 + JJ) * SPG;
+          if (!kChecked || i0 < a.T) {
+            float db[4];
 #pragma unroll
-          for (int c = 0; c < 4; ++c) db[c] = group_bcast<LPS, JJ>(du[c]);
-          const bool mine = lane_j == JJ;
+            for (int c = 0; c < 4; ++c) db[c] = group_bcast<LPS, JJ>(du[c]);
+            const bool mine = lane_j == JJ;
 #pragma unroll
-          for (int s = 0; s < SPG; ++s) {
-            const int i = i0 + s;
-            if (!kChecked || i < a.T) {
-              float v[M], xd[N], t[NQ];
+            for (int s = 0; s < SPG; ++s) {
+              const int i = i0 + s;
+              if (!kChecked || i < a.T) {
+                float v[M], xd[N], t[NQ];
 #pragma unroll
-              for (int j = 0; j < M; ++j) v[j] = sU[i * M + j] + db[s * M + j];
-              Sys::xdot(p, x, v, xd);
+                for (int j = 0; j < M; ++j) v[j] = sU[i * M + j] + db[s * M + j];
+                Sys::xdot(p, x, v, xd);
 #pragma unroll
-              for (int r = 0; r < N; ++r) x[r] += a.dt * xd[r];
-              Sys::cost_state(x, t);
+                for (int r = 0; r < N; ++r) x[r] += a.dt * xd[r];
+                Sys::cost_state(x, t);
 #pragma unroll
-              for (int c = 0; c < NQ; ++c) xq[s][c] = mine ? t[c] : xq[s][c];
+                for (int c = 0; c < NQ; ++c) xq[s][c] = mine ? t[c] : xq[s][c];
+              }
             }
           }
-        }
-      });
+        });
+      }
     };
     if ((g0 + LPS) * SPG <= a.T) chunk(std::false_type{});
     else chunk(std::true_type{});

@@ -54,7 +54,7 @@ struct LinearSys {
   static constexpr bool kSplitCost = false, kCrash = false;
   static constexpr int kLPS = MPPI_ROLLOUT_LPS;
   // step-split rollout: the cost reads the whole state
-  static constexpr bool kStepSplit = true;
+  static constexpr bool kStepSplit = true, kOwnChunk = false;
   static constexpr int NQ = N;
   __device__ static void cost_state(const float *x, float *xq) {
 #pragma unroll
@@ -98,7 +98,7 @@ struct CartPoleSys {
   __device__ static float q(const Params &p, const StageView &, const float *x) {
     return p.qd[0] * x[0] * x[0] + p.qd[1] * x[1] * x[1] + p.qd[2] * x[2] * x[2] + p.qd[3] * x[3] * x[3];
   }
-  static constexpr bool kStepSplit = true;
+  static constexpr bool kStepSplit = true, kOwnChunk = false;
   static constexpr int NQ = N;
   __device__ static void cost_state(const float *x, float *xq) {
 #pragma unroll
@@ -142,7 +142,7 @@ struct SwingUpSys {
     const float a = 1.f + fcos(x[2]);
     return p.wp * x[0] * x[0] + p.wa * a * a + p.wr * x[3] * x[3] + p.wv * x[1] * x[1];
   }
-  static constexpr bool kStepSplit = true;
+  static constexpr bool kStepSplit = true, kOwnChunk = false;
   static constexpr int NQ = N;
   __device__ static void cost_state(const float *x, float *xq) {
 #pragma unroll
@@ -264,9 +264,96 @@ struct BicycleSys {
   // Step-split rollout: the cost needs position and speed only, and reads the bilinear
   // taps straight from the map in global memory (L2-resident; no LDS window, so no
   // fallback).  Same arithmetic and tap values as q().
-  static constexpr bool kStepSplit = true;
+  static constexpr bool kStepSplit = true, kOwnChunk = true;
   static constexpr int NQ = 3;
   __device__ static void cost_state(const float *x, float *xq) { xq[0] = x[0]; xq[1] = x[1]; xq[2] = x[3]; }
+  // One chunk of the step-split rollout.  Every state update of the bicycle is a running
+  // sum once its increment is known: speed and steering add the controls, heading adds
+  // dt x3 tan(d)/L, position adds dt x3 (cos, sin)(heading).  So the chunk runs three
+  // passes over its steps, each a chain of one FMA per step and state in every lane, and
+  // between the passes each lane computes the increments of its own steps (the only
+  // transcendentals, once per step instead of once per lane), which the next pass
+  // broadcasts from their owners.  Per step the operations and operands are those of
+  // xdot + the Euler update, in the same order, so the result is bitwise the same.
+  // du: this lane's group perturbations (SPG steps x M); xq: cost state after its steps.
+  template <int LPS, int SPG, bool kChecked>
+  __device__ static void chunk(const Params &p, int T, float dt, const float *sU, const float *du, int g0,
+                               int lane_j, float *x, float (*xq)[NQ]) {
+    // each pass: for every step i of the chunk (owner lane JJ, slot s), f(JJ, s, i)
+    auto pass = [&](auto f) {
+      StaticFor<0, LPS>::run([&](auto jc) {
+        constexpr int JJ = decltype(jc)::value;
+        const int i0 = (g0 + JJ) * SPG;
+        if (!kChecked || i0 < T) {
+#pragma unroll
+          for (int s = 0; s < SPG; ++s)
+            if (!kChecked || i0 + s < T) f(jc, s, lane_j == JJ);
+        }
+      });
+    };
+    // own steps: controls (clamped index past the horizon: never used)
+    float u0[SPG], u1[SPG];
+#pragma unroll
+    for (int s = 0; s < SPG; ++s) {
+      const int ic = min((g0 + lane_j) * SPG + s, T - 1);
+      u0[s] = sU[ic * M] + du[s * M];
+      u1[s] = sU[ic * M + 1] + du[s * M + 1];
+    }
+    // pass 1: speed and steering; own steps keep both from before the step
+    float vb[SPG], db[SPG];
+#pragma unroll
+    for (int s = 0; s < SPG; ++s) vb[s] = db[s] = 0.f;
+    pass([&](auto jc, int s, bool mine) {
+      constexpr int JJ = decltype(jc)::value;
+      const float v0 = group_bcast<LPS, JJ>(u0[s]), v1 = group_bcast<LPS, JJ>(u1[s]);
+      vb[s] = mine ? x[3] : vb[s];
+      db[s] = mine ? x[4] : db[s];
+      x[3] += dt * v0;
+      x[4] += dt * v1;
+    });
+    // own steps: heading increment x3 tan(d) / L
+    float w[SPG];
+#pragma unroll
+    for (int s = 0; s < SPG; ++s) {
+      float dl = db[s];
+      if (p.lim > 0) dl = dl < -p.lim ? -p.lim : (dl > p.lim ? p.lim : dl);
+      float sd, cd;
+      fsincos(dl, sd, cd);
+      const float tn = sd * frcp(cd);
+      w[s] = vb[s] * tn * p.L_inv;
+    }
+    // pass 2: heading; own steps keep it from before the step
+    float hb[SPG];
+#pragma unroll
+    for (int s = 0; s < SPG; ++s) hb[s] = 0.f;
+    pass([&](auto jc, int s, bool mine) {
+      constexpr int JJ = decltype(jc)::value;
+      const float wj = group_bcast<LPS, JJ>(w[s]);
+      hb[s] = mine ? x[2] : hb[s];
+      x[2] += dt * wj;
+    });
+    // own steps: position increments x3 (cos, sin)(heading)
+    float c0[SPG], c1[SPG];
+#pragma unroll
+    for (int s = 0; s < SPG; ++s) {
+      float sn, cs;
+      fsincos(hb[s], sn, cs);
+      c0[s] = vb[s] * cs;
+      c1[s] = vb[s] * sn;
+    }
+    // pass 3: position; own steps keep it from after the step
+    pass([&](auto jc, int s, bool mine) {
+      constexpr int JJ = decltype(jc)::value;
+      const float a0 = group_bcast<LPS, JJ>(c0[s]), a1 = group_bcast<LPS, JJ>(c1[s]);
+      x[0] += dt * a0;
+      x[1] += dt * a1;
+      xq[s][0] = mine ? x[0] : xq[s][0];
+      xq[s][1] = mine ? x[1] : xq[s][1];
+    });
+    // own steps: speed after the step, as pass 1 formed it
+#pragma unroll
+    for (int s = 0; s < SPG; ++s) xq[s][2] = vb[s] + dt * u0[s];
+  }
   __device__ static float q_step(const Params &p, const float *xq) {
     float gx = xq[0] * p.cell_inv, gy = xq[1] * p.cell_inv;
     gx = fminf(fmaxf(gx, 0.f), (float)(p.W - 1));
