@@ -15,6 +15,9 @@ HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # never emit packed FP32 instructions (v_pk_*_f32)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # fuse a*b + c only within one source expression, as the front end decides: every
+    # kernel that runs the same code (fused or not, batched or not) rounds the same way
+    "-ffp-contract=on",
     "-Wno-unused-result",
 ]
 

@@ -234,6 +234,7 @@ void compute_layout(const mppi_config *c, Layout *L) {
   L->off_dbg = take((uint64_t)(2 + L->TM) * 8);
   L->off_pre = ctg ? take((uint64_t)T * K * 8) : 0;
   L->off_rho_step = ctg ? take((uint64_t)T * 8) : 0;
+  L->off_rho = take(sizeof(double));
   uint64_t sys_bytes = 0;
   if (c->system == MPPI_SYS_BICYCLE) {
     const auto *p = (const mppi_bicycle_params *)c->params;
@@ -475,6 +476,7 @@ static IterArgs make_iter_args(mppi_ctx *c, const double *x0) {
   const int m = c->cfg.n_ctrl;
   for (int i = 0; i < m * m; ++i) { a.Ls[i] = (float)c->Ls[i]; a.R[i] = (float)c->R[i]; a.Mq[i] = (float)c->Mq[i]; }
   a.inv_lambda = 1.0 / c->cfg.lambda;
+  a.rho_out = (double *)(c->base + L.off_rho);
   return a;
 }
 
@@ -484,14 +486,17 @@ static FinalizeArgs make_fin_args(mppi_ctx *c, double *u0_out, int emit) {
   const Layout &L = c->L;
   f.U64 = (double *)(c->base + L.off_U64);
   f.U32 = (float *)(c->base + L.off_U32);
-  f.blk_min = (const double *)(c->base + L.off_blk_min);
+  // the minimum: the update's (path weighting), or the first step's cost-to-go minimum,
+  // which is the minimum path cost since no cost precedes step 0
+  f.rho = c->cfg.weighting == MPPI_WEIGHT_COST_TO_GO ? (const double *)(c->base + L.off_rho_step)
+                                                     : (const double *)(c->base + L.off_rho);
   f.part = (const double *)(c->base + L.off_part);
   f.eta_part = (const double *)(c->base + L.off_eta_part);
   f.iter = (uint64_t *)(c->base + L.off_iter);
   f.flags = (int *)(c->base + L.off_res + 4 * sizeof(double));
   f.dbg = (double *)(c->base + L.off_dbg);
   f.u0_out = u0_out;
-  f.T = c->cfg.T; f.m = c->cfg.n_ctrl; f.G = L.G; f.n_roll_blocks = L.n_roll_blocks; f.n_kc = L.n_kc;
+  f.T = c->cfg.T; f.m = c->cfg.n_ctrl; f.G = L.G; f.n_kc = L.n_kc;
   f.emit = emit;
   f.ctg = c->cfg.weighting == MPPI_WEIGHT_COST_TO_GO;
   for (int i = 0; i < 16; ++i) f.Ls[i] = c->Ls[i];

@@ -46,19 +46,20 @@ struct IterArgs {
   float Ls[16];            // A chol(Sigma), row-major m x m (lower)
   float R[16];             // m x m
   double inv_lambda;
+  double *rho_out;         // update: this iteration's minimum path cost (written by one block)
 };
 
 struct FinalizeArgs {
   double *U64;             // [T*m] FP64 master
   float *U32;              // [T*m]
-  const double *blk_min;
+  const double *rho;       // the iteration's minimum path cost (written by the update)
   const double *part;
   const double *eta_part;
   uint64_t *iter;
   int *flags;              // bit 0: an iteration had no finite cost
   double *dbg;             // [2 + T*m]: rho, eta, dU
   double *u0_out;          // [m]; written when emit != 0
-  int T, m, G, n_roll_blocks, n_kc;
+  int T, m, G, n_kc;
   int emit;                // last iteration of the control step: emit u0 and shift
   int ctg;                 // cost-to-go weights: eta_part is [n_kc][T], one normaliser per step
   double Ls[16];           // A chol(Sigma)
@@ -458,6 +459,7 @@ __device__ __forceinline__ void update_body(const IterArgs &a, int kc, int gcb) 
   const int k_own = kc * kUpdChunk + threadIdx.x;
   const double s_own = k_own < a.K ? a.S[k_own] : __builtin_inf();   // in flight with the minima
   const double rho = global_min(a.blk_min, a.n_roll_blocks, red);
+  if (kc == 0 && gcb == 0 && threadIdx.x == 0) *a.rho_out = rho;
   const uint64_t it = *a.iter;
   {
     double wk = 0.0;
@@ -627,8 +629,9 @@ __device__ __forceinline__ double ordered_sum(const double *p, size_t stride, in
   return s;
 }
 
-// status_out (nullable): 0 when the iteration had a finite cost, -5 otherwise.  All global
-// loads (block minima, chunk partials, the previous sequence) are issued before the first
+// status_out (nullable): 0 when the iteration had a finite cost, -5 otherwise.  The
+// minimum comes from the update (every update block reduces the block minima anyway); all
+// global loads (chunk partials, the previous sequence) are issued before the first
 // barrier; the updated sequence then lives in LDS until the (shifted) write-back.
 // Returns with u0 (the emitted control, when a.emit) in u0_s.
 __device__ __forceinline__ void finalize_body(const FinalizeArgs &a, double *u0_out, double *status_out,
@@ -636,13 +639,10 @@ __device__ __forceinline__ void finalize_body(const FinalizeArgs &a, double *u0_
   constexpr int NT = kFinBlock;
   __shared__ double N_lds[kMaxTM];
   __shared__ double eta_step[1024];                // per-step normalisers (cost-to-go weights)
-  __shared__ double red[NT / 64];
   __shared__ double eta_s;
   constexpr int kPer = kMaxTM / NT;
   const int TM = a.T * a.m;
-  // first block minimum outside the loop, so its load is in flight with all the others
-  double v = threadIdx.x < a.n_roll_blocks ? a.blk_min[threadIdx.x] : __builtin_inf();
-  for (int b = threadIdx.x + NT; b < a.n_roll_blocks; b += NT) v = fmin(v, a.blk_min[b]);
+  const double rho = *a.rho;
   const uint64_t it0 = threadIdx.x == 0 ? a.iter[0] : 0;   // loaded with the rest, not after
   double Uold[kPer];
 #pragma unroll
@@ -656,11 +656,7 @@ __device__ __forceinline__ void finalize_body(const FinalizeArgs &a, double *u0_
     eta_s = ordered_sum(a.eta_part, 1, a.n_kc);
   }
   for (int f = threadIdx.x; f < TM; f += NT) N_lds[f] = ordered_sum(a.part + f, (size_t)a.G * 4, a.n_kc);
-  v = wave_min(v);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x / 64] = v;
   __syncthreads();
-  double rho = red[0];
-  for (int i = 1; i < NT / 64; ++i) rho = fmin(rho, red[i]);
   const bool ok = rho < __builtin_inf();
   const double eta = a.ctg ? eta_step[0] : eta_s;
   const double inv_eta = ok ? 1.0 / eta : 0.0;
@@ -672,7 +668,7 @@ __device__ __forceinline__ void finalize_body(const FinalizeArgs &a, double *u0_
     if (f < TM) {
       const int i = f / a.m, j = f - i * a.m;
       double d = 0.0;
-      for (int l = 0; l <= j; ++l) d += a.Ls[j * a.m + l] * N_lds[i * a.m + l];
+      for (int l = 0; l <= j; ++l) d = fma(a.Ls[j * a.m + l], N_lds[i * a.m + l], d);
       d = ok ? d * (a.ctg ? 1.0 / eta_step[i] : inv_eta) : 0.0;
       a.dbg[2 + f] = d;
       Unew[n] = Uold[n] + d;
@@ -723,7 +719,7 @@ static __global__ __launch_bounds__(kFinBlock) void finalize_kernel(const Finali
 // The harness plant step x <- x + dt xdot(x, u), FP64.  Every system is affine in its
 // control, so xdot(x, u) = f0 + sum_j u_j (f_{j+1} - f0) with f0 = xdot(x, 0) and
 // f_{j+1} = xdot(x, e_j): M + 1 lanes evaluate these in parallel, before u is known (in
-// the fused finalize, while the other waves wait on their loads), and one lane combines.
+// the finalize kernel, while the other waves wait on their loads), and one lane combines.
 // Both plant kernels use the same two functions, so they agree bit for bit.  x holds
 // n <= Sys::N doubles; components beyond n are treated as zero and not written.
 template <class Sys>
@@ -739,18 +735,20 @@ __device__ __forceinline__ void plant_combine(double *x, int n, double dt, const
                                               const double *u) {
   for (int r = 0; r < n; ++r) {
     double d = basis[0][r];
-    for (int c = 0; c < Sys::M; ++c) d += u[c] * (basis[c + 1][r] - basis[0][r]);
-    x[r] += dt * d;
+    for (int c = 0; c < Sys::M; ++c) d = fma(u[c], basis[c + 1][r] - basis[0][r], d);
+    x[r] = fma(dt, d, x[r]);
   }
 }
 
-// finalize + the plant step on the emitted control (wave 1 evaluates the plant basis).
+// finalize + the plant step on the emitted control.  The last wave evaluates the plant
+// basis: it owns no sequence component while T*m <= kFinBlock - 64, so the basis overlaps
+// the other waves' loads instead of delaying them.
 template <class Sys>
 __global__ __launch_bounds__(kFinBlock) void finalize_plant_kernel(const FinalizeArgs a, double *x, double dt, int n,
                                                                    const typename Sys::Params p) {
   __shared__ double u0_s[4];
   __shared__ double basis[Sys::M + 1][Sys::N];
-  const int j = (int)threadIdx.x - kWave;
+  const int j = (int)threadIdx.x - (kFinBlock - kWave);
   if (j >= 0 && j <= Sys::M) plant_basis<Sys>(p, x, n, j, basis[j]);
   finalize_body(a, a.u0_out, nullptr, u0_s);          // its barriers publish the basis
   if (threadIdx.x == 0) plant_combine<Sys>(x, n, dt, basis, u0_s);

@@ -275,16 +275,22 @@ def test_graph_cache_stays_bounded_and_correct():
 
 
 def test_closed_loop_run_equals_single_steps():
-    """mppi_run_closed_loop_async over n steps == n calls of mppi_step_plant_async, bitwise."""
+    """mppi_run_closed_loop_async over n steps == n calls of mppi_step_plant_async, bitwise.
+    On the step-split systems the run completes each step inside the next step's rollout
+    (fused finalize) while single steps end with the finalize kernel; both weightings."""
     import torch
     dev = torch.device("cuda:0")
-    for wl in (W.bicycle(K=2048, T=50), W.quadrotor(nu=2.0, K=1024, T=40), W.cartpole(nu=2.0)):
+    cases = [(W.bicycle(K=2048, T=50), P.WEIGHT_PATH), (W.quadrotor(nu=2.0, K=1024, T=40), P.WEIGHT_PATH),
+             (W.cartpole(nu=2.0), P.WEIGHT_PATH), (W.bicycle(K=2048, T=50), P.WEIGHT_COST_TO_GO),
+             (W.linear_double_integrator(K=1000, T=30, R=0.3), P.WEIGHT_PATH),
+             (W.cartpole_swingup(nu=1000.0, K=1024, T=50), P.WEIGHT_PATH)]
+    for wl, weighting in cases:
         wl = wl.replace(seed=37)
         xa = torch.tensor(wl.x0, dtype=torch.float64, device=dev)
         xb = xa.clone()
         log = torch.zeros((7, wl.m), dtype=torch.float64, device=dev)
         ub = torch.zeros((7, wl.m), dtype=torch.float64, device=dev)
-        with controller(wl) as a, controller(wl) as b:
+        with controller(wl, weighting=weighting) as a, controller(wl, weighting=weighting) as b:
             a.run_closed_loop_async(xa.data_ptr(), 7, log.data_ptr())
             for j in range(7):
                 b.step_plant_async(xb.data_ptr(), ub[j].data_ptr())
