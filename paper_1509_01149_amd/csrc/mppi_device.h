@@ -66,8 +66,8 @@ __device__ __forceinline__ void normals4(uint32_t g, uint32_t k, uint64_t it, ui
 // hardware sin/cos.  Absolute error ~1e-6 for moderate arguments.
 // ---------------------------------------------------------------------------------
 __device__ __forceinline__ float rev(float x) {
-  const float r = x * 0.159154943091895335769f;
-  return r - __builtin_rintf(r);
+  constexpr float kInv2Pi = 0.159154943091895335769f;
+  return fmaf(x, kInv2Pi, -__builtin_rintf(x * kInv2Pi));   // the fraction from the unrounded product
 }
 __device__ __forceinline__ float fsin(float x) { return __builtin_amdgcn_sinf(rev(x)); }
 __device__ __forceinline__ float fcos(float x) { return __builtin_amdgcn_cosf(rev(x)); }

@@ -413,11 +413,11 @@ struct QuadrotorSys {
     const F tx = arm * (f[1] - f[3]);
     const F ty = arm * (f[2] - f[0]);
     const F tz = kap * (f[0] - f[1] + f[2] - f[3]);
-    // w x (J w)
+    // tau - w x (J w), as explicit FMAs
     const F hx = J0 * wx, hy = J1 * wy, hz = J2 * wz;
-    xd[9] = (tx - (wy * hz - wz * hy)) * Ji0;
-    xd[10] = (ty - (wz * hx - wx * hz)) * Ji1;
-    xd[11] = (tz - (wx * hy - wy * hx)) * Ji2;
+    xd[9] = fma(wz, hy, fma(-wy, hz, tx)) * Ji0;
+    xd[10] = fma(wx, hz, fma(-wz, hx, ty)) * Ji1;
+    xd[11] = fma(wy, hx, fma(-wx, hy, tz)) * Ji2;
   }
   // LDS: the obstacles' float4s, then (crash indicator on) their squared radii
   static constexpr int stage_floats(int n_obs, int) { return 5 * n_obs; }
