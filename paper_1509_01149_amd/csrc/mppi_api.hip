@@ -365,10 +365,9 @@ static size_t rollout_lds_bytes(const mppi_ctx *c) {
   const int T = c->cfg.T, m = c->cfg.n_ctrl;
   size_t fl = (size_t)2 * T * m + ((T + 3) & ~3);
   fl = (fl + 3) & ~size_t(3);
-  int a = 0, b = 0;
-  if (c->cfg.system == MPPI_SYS_BICYCLE) { a = c->bicycle.W; b = c->bicycle.H; }
-  if (c->cfg.system == MPPI_SYS_QUADROTOR || c->cfg.system == MPPI_SYS_QUADROTOR_MLP) a = c->quad.n_obs;
-  if (!rollout_split(&c->cfg)) fl += Sys::stage_floats(a, b);   // the step-split body stages nothing
+  // the step-split body stages nothing beyond the controls; the quadrotor its obstacles
+  if (c->cfg.system == MPPI_SYS_QUADROTOR || c->cfg.system == MPPI_SYS_QUADROTOR_MLP)
+    fl += Sys::stage_floats(c->quad.n_obs, 0);
   return fl * 4;
 }
 
@@ -384,8 +383,8 @@ static int rollout_mode(const mppi_ctx *c) {
 
 template <class Sys, int Mode>
 static const void *rollout_fn() {
-  if constexpr ((Mode & kCrashOn) != 0 && !Sys::kCrash) return nullptr;
-  else if constexpr (Sys::kStepSplit) return nullptr;                // these run step-split
+  if constexpr (Sys::kStepSplit) return nullptr;                     // these run step-split
+  else if constexpr ((Mode & kCrashOn) != 0 && !Sys::kCrash) return nullptr;
   else return (const void *)rollout_kernel<Sys, Sys::kLPS, Mode>;
 }
 

@@ -158,15 +158,11 @@ struct SwingUpSys {
 };
 
 // ------------------------------------------------------------ kinematic bicycle + map
-// The cost map (FP32, [y][x]) stays in HBM.  The four-lane rollout (cost-to-go weighting)
-// stages the kTile x kTile window around the current start position into LDS (the
-// horizon's reachable region at the configured speeds) and reads the bilinear taps from
-// LDS whenever all four lie inside the window, from global memory (L2) otherwise; the
-// step-split rollout evaluates each step's cost a chunk after the state is known and
-// reads the taps from global memory.  All paths read identical values.
+// The cost map (FP32, [y][x]) stays in HBM; the step-split rollout evaluates each step's
+// cost a chunk after the state is known and reads the bilinear taps from global memory
+// (the map stays resident in L2).
 struct BicycleSys {
   static constexpr int N = 5, M = 2;
-  static constexpr int kTile = 160;   // 160 x 160 x 4 B = 100 KiB of LDS
   struct Params {
     float L_inv, vt, ws, cell_inv, lim;
     int W, H;
@@ -189,78 +185,7 @@ struct BicycleSys {
     xd[3] = v[0];
     xd[4] = v[1];
   }
-  struct Regs {};
-  __device__ static void load_regs(const Params &, const StageView &, int, int, Regs &) {}
-  static int tile_w(int W) { return W < kTile ? W : kTile; }
-  static constexpr int stage_floats(int W, int H) { return (W < kTile ? W : kTile) * (H < kTile ? H : kTile); }
-  // Stage the window centred on the start position x0 (device, FP64).  Wave w copies rows
-  // w, w + 4, ...; its lanes cover a row in coalesced 64-float chunks, and 4 rows x 3 chunks
-  // of loads are issued before the first is waited on (one wave per SIMD here, so the
-  // loads must overlap: a load-wait-store loop costs a full memory latency per element).
-  __device__ static void stage(const Params &p, float *lds, const double *x0, int *i0, int *j0) {
-    const int tw = p.W < kTile ? p.W : kTile, th = p.H < kTile ? p.H : kTile;
-    int ci = (int)floor(x0[0] * (double)p.cell_inv) - tw / 2;
-    int cj = (int)floor(x0[1] * (double)p.cell_inv) - th / 2;
-    ci = ci < 0 ? 0 : (ci > p.W - tw ? p.W - tw : ci);
-    cj = cj < 0 ? 0 : (cj > p.H - th ? p.H - th : cj);
-    constexpr int kRows = 4, kChunks = (kTile + kWave - 1) / kWave, kWaves = kBlock / kWave;
-    const int wv = threadIdx.x / kWave, ln = threadIdx.x % kWave;
-    for (int r0 = wv; r0 < th; r0 += kWaves * kRows) {
-      float v[kRows][kChunks];
-#pragma unroll
-      for (int rr = 0; rr < kRows; ++rr) {
-        const int r = r0 + kWaves * rr;
-#pragma unroll
-        for (int cc = 0; cc < kChunks; ++cc) {
-          const int c = ln + kWave * cc;
-          v[rr][cc] = (r < th && c < tw) ? p.map[(size_t)(cj + r) * p.W + (ci + c)] : 0.f;
-        }
-      }
-#pragma unroll
-      for (int rr = 0; rr < kRows; ++rr) {
-        const int r = r0 + kWaves * rr;
-#pragma unroll
-        for (int cc = 0; cc < kChunks; ++cc) {
-          const int c = ln + kWave * cc;
-          if (r < th && c < tw) lds[r * tw + c] = v[rr][cc];
-        }
-      }
-    }
-    *i0 = ci;
-    *j0 = cj;
-  }
-  static constexpr bool kSplitCost = false, kCrash = false;
-  static constexpr int kLPS = MPPI_ROLLOUT_LPS;
-  __device__ static float q_part(const Params &p, const StageView &sv, const float *x, int, int) { return q(p, sv, x); }
-  __device__ static float q(const Params &p, const StageView &sv, const float *x) {
-    float gx = x[0] * p.cell_inv, gy = x[1] * p.cell_inv;
-    gx = fminf(fmaxf(gx, 0.f), (float)(p.W - 1));
-    gy = fminf(fmaxf(gy, 0.f), (float)(p.H - 1));
-    const int i0 = min((int)floorf(gx), p.W - 2);
-    const int j0 = min((int)floorf(gy), p.H - 2);
-    const float fx = gx - (float)i0, fy = gy - (float)j0;
-    const int tw = p.W < kTile ? p.W : kTile, th = p.H < kTile ? p.H : kTile;
-    const int li = i0 - sv.i0, lj = j0 - sv.j0;
-    // LDS taps from the index clamped into the tile, always; outside the tile the global
-    // taps replace them.  Loading both ways (rather than selecting a pointer) keeps the
-    // common case on ds_read: a pointer that may be LDS or global compiles to flat loads
-    // on every step.  The global taps are relaxed atomic loads (plain global loads in the
-    // ISA), which the compiler does not merge with the LDS loads into one flat load.
-    const int lic = min(max(li, 0), tw - 2), ljc = min(max(lj, 0), th - 2);
-    const float *t = sv.lds + ljc * tw + lic;
-    float m00 = t[0], m01 = t[1], m10 = t[tw], m11 = t[tw + 1];
-    if (!(li >= 0 && lj >= 0 && li + 1 < tw && lj + 1 < th)) {
-      const float *g = p.map + (size_t)j0 * p.W + i0;
-      m00 = __hip_atomic_load(g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      m01 = __hip_atomic_load(g + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      m10 = __hip_atomic_load(g + p.W, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      m11 = __hip_atomic_load(g + p.W + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    const float top = (1.f - fx) * m00 + fx * m01;
-    const float bot = (1.f - fx) * m10 + fx * m11;
-    const float dv = x[3] - p.vt;
-    return (1.f - fy) * top + fy * bot + p.ws * dv * dv;
-  }
+  static constexpr int stage_floats(int, int) { return 0; }   // nothing staged in LDS
   // Step-split rollout: the cost needs position and speed only, and reads the bilinear
   // taps straight from the map in global memory (L2-resident; no LDS window, so no
   // fallback).  Same arithmetic and tap values as q().
