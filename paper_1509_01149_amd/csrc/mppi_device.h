@@ -118,15 +118,35 @@ struct StaticFor {
 // ---------------------------------------------------------------------------------
 // Wave64 / block reductions (fixed order: results do not depend on timing).
 // ---------------------------------------------------------------------------------
+// DPP move of a double (two 32-bit halves); Ctrl is the DPP control word.
+template <int Ctrl>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), Ctrl, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), Ctrl, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), lane),
+                          __builtin_amdgcn_readlane(__double2loint(v), lane));
+}
+
+// Wave reductions with every lane active: a DPP butterfly inside each 16-lane row
+// (quad_perm swaps, then row rotations by 4 and 8), after which lane 0 of each row holds
+// the row's result; the four rows are then combined from lanes 0, 16, 32, 48 in a fixed
+// order.  No LDS traffic (a __shfl would go through the LDS crossbar at every step).
+template <class Op>
+__device__ __forceinline__ double wave_reduce(double v, Op op) {
+  v = op(v, dpp_f64<0xB1>(v));                     // quad_perm(1,0,3,2)
+  v = op(v, dpp_f64<0x4E>(v));                     // quad_perm(2,3,0,1)
+  v = op(v, dpp_f64<0x124>(v));                    // row_ror:4
+  v = op(v, dpp_f64<0x128>(v));                    // row_ror:8
+  return op(op(readlane_f64(v, 0), readlane_f64(v, 16)), op(readlane_f64(v, 32), readlane_f64(v, 48)));
+}
 __device__ __forceinline__ double wave_min(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, kWave));
-  return v;
+  return wave_reduce(v, [](double a, double b) { return fmin(a, b); });
 }
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-  return v;
+  return wave_reduce(v, [](double a, double b) { return a + b; });
 }
 
 // Min over a 256-thread block; every thread gets the result.

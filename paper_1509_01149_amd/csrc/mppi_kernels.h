@@ -264,13 +264,6 @@ __device__ __forceinline__ void rollout_body(const IterArgs &a, const typename S
 // cost-to-go weighting (kRecordPrefix) the running cost before every step is recorded
 // from an in-order scan of the chunk's step costs; the path cost is the same tree sum in
 // both variants, so the two weightings see bitwise the same S.
-template <int Ctrl>
-__device__ __forceinline__ double dpp_f64(double v) {
-  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), Ctrl, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), Ctrl, 0xF, 0xF, false);
-  return __hiloint2double(hi, lo);
-}
-
 // Sum over a sample's LPS lanes; lane 0 of the group holds the fixed-order total.
 template <int LPS>
 __device__ __forceinline__ double group_sum(double v) {
