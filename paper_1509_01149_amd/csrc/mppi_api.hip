@@ -218,7 +218,11 @@ void compute_layout(const mppi_config *c, Layout *L) {
   // samples per rollout block: 64 for the learned dynamics (16 per wave), 256 / lanes-per-sample otherwise
   const int roll_per_block = c->system == MPPI_SYS_QUADROTOR_MLP ? 64 : kBlock / rollout_lps(c);
   L->n_roll_blocks = (K + roll_per_block - 1) / roll_per_block;
-  L->n_kc = (K + kUpdChunk - 1) / kUpdChunk;
+  // update chunk: 128 samples while that keeps the update grid within ~500 blocks (the
+  // shorter per-thread chain wins while the device has room), else 256
+  const int upd_blocks_128 = ((K + 127) / 128) * ((L->G + kUpdGroups - 1) / kUpdGroups);
+  L->upd_chunk = upd_blocks_128 <= 500 ? 128 : 256;
+  L->n_kc = (K + L->upd_chunk - 1) / L->upd_chunk;
   uint64_t o = 0;
   auto take = [&](uint64_t bytes) { uint64_t r = o; o = align256(o + bytes); return r; };
   L->off_x0 = take(16 * sizeof(double));
@@ -476,6 +480,7 @@ static IterArgs make_iter_args(mppi_ctx *c, const double *x0) {
   for (int i = 0; i < m * m; ++i) { a.Ls[i] = (float)c->Ls[i]; a.R[i] = (float)c->R[i]; a.Mq[i] = (float)c->Mq[i]; }
   a.inv_lambda = 1.0 / c->cfg.lambda;
   a.rho_out = (double *)(c->base + L.off_rho);
+  a.upd_chunk = L.upd_chunk;
   return a;
 }
 

@@ -24,8 +24,7 @@ namespace mppi {
 constexpr int kUpdGroups = 4;                        // noise groups per update block
 constexpr int kUpdStrips = kBlock / kUpdGroups;      // sample strips per update block
 static_assert(kUpdStrips % 16 == 0 && kUpdGroups * 4 * 16 <= kBlock, "update reduction layout");
-constexpr int kUpdChunk = 256;                       // samples per update block
-constexpr int kUpdPerThread = kUpdChunk / kUpdStrips;
+constexpr int kUpdChunkMax = kBlock;                 // samples per update block: 128 or 256 (IterArgs)
 
 struct IterArgs {
   const double *x0;        // [n]
@@ -47,6 +46,7 @@ struct IterArgs {
   float R[16];             // m x m
   double inv_lambda;
   double *rho_out;         // update: this iteration's minimum path cost (written by one block)
+  int upd_chunk;           // samples per update block (128 or 256)
 };
 
 struct FinalizeArgs {
@@ -443,14 +443,15 @@ __device__ __forceinline__ double global_min(const double *blk_min, int n, doubl
 
 // ------------------------------------------------------------------------- update
 // grid (n_kc, ceil(G / kUpdGroups)).  Thread t handles noise group gcb*kUpdGroups +
-// t % kUpdGroups for the kUpdPerThread samples of strip t / kUpdGroups of this block's
-// 256-sample chunk.
+// t % kUpdGroups for the upd_chunk / kUpdStrips samples of strip t / kUpdGroups of this
+// block's chunk of upd_chunk samples.
 __device__ __forceinline__ void update_body(const IterArgs &a, int kc, int gcb) {
-  __shared__ double w[kUpdChunk];
+  __shared__ double w[kUpdChunkMax];
   __shared__ double acc_lds[kUpdStrips][kUpdGroups][4];
   __shared__ double red[4];
-  const int k_own = kc * kUpdChunk + threadIdx.x;
-  const double s_own = k_own < a.K ? a.S[k_own] : __builtin_inf();   // in flight with the minima
+  const int chunk = a.upd_chunk, ppt = chunk / kUpdStrips;
+  const int k_own = kc * chunk + threadIdx.x;
+  const double s_own = (int)threadIdx.x < chunk && k_own < a.K ? a.S[k_own] : __builtin_inf();   // in flight with the minima
   const double rho = global_min(a.blk_min, a.n_roll_blocks, red);
   if (kc == 0 && gcb == 0 && threadIdx.x == 0) *a.rho_out = rho;
   const uint64_t it = *a.iter;
@@ -468,12 +469,12 @@ __device__ __forceinline__ void update_body(const IterArgs &a, int kc, int gcb) 
   const int g = gcb * kUpdGroups + gl;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   if (g < a.G) {
-    for (int r = 0; r < kUpdPerThread; ++r) {
-      const int kl = strip * kUpdPerThread + r;
+    for (int r = 0; r < ppt; ++r) {
+      const int kl = strip * ppt + r;
       const double wk = w[kl];
       if (wk != 0.0) {
         float e[4];
-        normals4((uint32_t)g, (uint32_t)(kc * kUpdChunk + kl), it, a.key0, a.key1, e);
+        normals4((uint32_t)g, (uint32_t)(kc * chunk + kl), it, a.key0, a.key1, e);
 #pragma unroll
         for (int c = 0; c < 4; ++c) acc[c] = fma(wk, (double)e[c], acc[c]);
       }
@@ -532,12 +533,13 @@ static __global__ __launch_bounds__(kBlock) void update_ctg_kernel(const IterArg
   __shared__ double red[4];
   const int kc = blockIdx.x, gcb = blockIdx.y;
   const int TM = a.T * a.m;
+  const int chunk = a.upd_chunk, ppt = chunk / kUpdStrips;
   const uint64_t it = *a.iter;
   // normalisers of the steps whose first control component lies in this block's groups
   {
     const int f_lo = gcb * kUpdGroups * 4, f_hi = min(f_lo + kUpdGroups * 4, TM);
-    const int k = kc * kUpdChunk + threadIdx.x;
-    const double s = k < a.K ? a.S[k] : __builtin_inf();
+    const int k = kc * chunk + threadIdx.x;
+    const double s = (int)threadIdx.x < chunk && k < a.K ? a.S[k] : __builtin_inf();
     for (int i = (f_lo + a.m - 1) / a.m; i * a.m < f_hi; ++i) {
       const double w = s < __builtin_inf() ? ctg_weight(a, s, i, k) : 0.0;
       const double e = block_sum(w, red);
@@ -548,8 +550,8 @@ static __global__ __launch_bounds__(kBlock) void update_ctg_kernel(const IterArg
   const int g = gcb * kUpdGroups + gl;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   if (g < a.G) {
-    for (int r = 0; r < kUpdPerThread; ++r) {
-      const int k = kc * kUpdChunk + strip * kUpdPerThread + r;
+    for (int r = 0; r < ppt; ++r) {
+      const int k = kc * chunk + strip * ppt + r;
       const double s = k < a.K ? a.S[k] : __builtin_inf();
       if (s < __builtin_inf()) {
         float e[4];

@@ -14,7 +14,7 @@ namespace mppi {
 
 // Offsets (bytes) of every device buffer inside one workspace allocation.
 struct Layout {
-  int TM, G, n_roll_blocks, n_kc;
+  int TM, G, n_roll_blocks, n_kc, upd_chunk;
   uint64_t off_x0, off_res, off_iter, off_U64, off_U32, off_S, off_blk_min, off_eta_part, off_part, off_dbg,
       off_pre, off_rho_step, off_sys, off_extra, extra_bytes, total;   // off_pre/off_rho_step: cost-to-go only
   uint64_t off_rho;                                  // the iteration's minimum path cost
