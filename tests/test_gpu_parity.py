@@ -48,6 +48,10 @@ CASES = {
     # the swing-up task of Section V-A (velocity-command cart, pole hanging at rest)
     "swingup_nu1": lambda: W.cartpole_swingup(nu=1.0),
     "swingup_nu1000": lambda: W.cartpole_swingup(nu=1000.0, K=4096),
+    # step-split lane counts: K above 8192 takes 4 lanes per sample (ragged horizon, last
+    # chunk partial); K = 8192 is the largest with 16
+    "bicycle_4lanes": lambda: W.bicycle(K=9000, T=37),
+    "bicycle_16lanes_k8192": lambda: W.bicycle(K=8192, T=100),
 }
 
 
@@ -152,6 +156,7 @@ CTG_CASES = {
     "linear": lambda: W.linear_double_integrator(K=4096, T=20, R=0.3),
     "bicycle": lambda: W.bicycle(K=4096, T=100),
     "bicycle_nu_diag": lambda: W.bicycle(K=3000, T=37, nu=np.array([1.0, 4.0])),
+    "bicycle_4lanes": lambda: W.bicycle(K=9000, T=37),
     "quadrotor": lambda: W.quadrotor(nu=2.0, K=4096, T=60),
 }
 
