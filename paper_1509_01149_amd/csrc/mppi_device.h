@@ -103,6 +103,37 @@ __device__ __forceinline__ float group_bcast(float v) {
   }
 }
 
+// Prefix sums over each aligned group of G lanes (G = 4 or 16; lj = lane % G), in a fixed
+// tree order.  Inclusive: DPP row shifts by 1, 2, 4, 8 (lanes with no source add 0);
+// groups of 4 mask the shifts that would cross a quad.  Exclusive: the inclusive sum of
+// the lane before (0 in the group's first lane).
+template <int Ctrl>
+__device__ __forceinline__ float dpp_or_zero(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), Ctrl, 0xF, 0xF, false));
+}
+template <int G>
+__device__ __forceinline__ float group_scan_incl(float v, int lj) {
+  if constexpr (G == 16) {
+    v += dpp_or_zero<0x111>(v);                    // row_shr:1
+    v += dpp_or_zero<0x112>(v);                    // row_shr:2
+    v += dpp_or_zero<0x114>(v);                    // row_shr:4
+    v += dpp_or_zero<0x118>(v);                    // row_shr:8
+  } else {
+    static_assert(G == 4, "lane groups of 4 or 16");
+    const float t1 = dpp_or_zero<0x111>(v);
+    v += lj >= 1 ? t1 : 0.f;
+    const float t2 = dpp_or_zero<0x112>(v);
+    v += lj >= 2 ? t2 : 0.f;
+  }
+  return v;
+}
+template <int G>
+__device__ __forceinline__ float group_excl_of_incl(float incl, int lj) {
+  const float t = dpp_or_zero<0x111>(incl);        // row_shr:1
+  if constexpr (G == 16) return t;
+  else return lj >= 1 ? t : 0.f;
+}
+
 // Compile-time loop: f(std::integral_constant<int, J>) for J = B .. E-1.
 template <int B, int E>
 struct StaticFor {

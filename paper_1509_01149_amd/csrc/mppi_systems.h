@@ -193,51 +193,46 @@ struct BicycleSys {
   static constexpr int NQ = 3;
   __device__ static void cost_state(const float *x, float *xq) { xq[0] = x[0]; xq[1] = x[1]; xq[2] = x[3]; }
   // One chunk of the step-split rollout.  Every state update of the bicycle is a running
-  // sum once its increment is known: speed and steering add the controls, heading adds
-  // dt x3 tan(d)/L, position adds dt x3 (cos, sin)(heading).  So the chunk runs three
-  // passes over its steps, each a chain of one FMA per step and state in every lane, and
-  // between the passes each lane computes the increments of its own steps (the only
-  // transcendentals, once per step instead of once per lane), which the next pass
-  // broadcasts from their owners.  Per step the operations and operands are those of
-  // xdot + the Euler update, in the same order, so the result is bitwise the same.
+  // sum once its increment is known: speed and steering add dt times the controls, heading
+  // adds dt x3 tan(d)/L, position adds dt x3 (cos, sin)(heading).  So each is a prefix sum
+  // over the chunk's steps: a lane adds the increments of its own steps, a DPP scan over
+  // the lane group gives every lane the value at the start of its steps, and the group's
+  // last lane holds the value at the end of the chunk.  Three rounds (speed and steering,
+  // heading, position), each preceded by the increments of the lane's own steps (the only
+  // transcendentals: once per step).  Steps past the horizon add nothing.
   // du: this lane's group perturbations (SPG steps x M); xq: cost state after its steps.
   template <int LPS, int SPG, bool kChecked>
   __device__ static void chunk(const Params &p, int T, float dt, const float *sU, const float *du, int g0,
                                int lane_j, float *x, float (*xq)[NQ]) {
-    // each pass: for every step i of the chunk (owner lane JJ, slot s), f(JJ, s, i)
-    auto pass = [&](auto f) {
-      StaticFor<0, LPS>::run([&](auto jc) {
-        constexpr int JJ = decltype(jc)::value;
-        const int i0 = (g0 + JJ) * SPG;
-        if (!kChecked || i0 < T) {
-#pragma unroll
-          for (int s = 0; s < SPG; ++s)
-            if (!kChecked || i0 + s < T) f(jc, s, lane_j == JJ);
-        }
-      });
-    };
-    // own steps: controls (clamped index past the horizon: never used)
-    float u0[SPG], u1[SPG];
+    const int i_first = (g0 + lane_j) * SPG;
+    bool ok[SPG];
+    float a3[SPG], a4[SPG];                        // own steps: speed and steering increments
 #pragma unroll
     for (int s = 0; s < SPG; ++s) {
-      const int ic = min((g0 + lane_j) * SPG + s, T - 1);
-      u0[s] = sU[ic * M] + du[s * M];
-      u1[s] = sU[ic * M + 1] + du[s * M + 1];
+      const int i = i_first + s;
+      ok[s] = !kChecked || i < T;
+      const int ic = min(i, T - 1);
+      a3[s] = ok[s] ? dt * (sU[ic * M] + du[s * M]) : 0.f;
+      a4[s] = ok[s] ? dt * (sU[ic * M + 1] + du[s * M + 1]) : 0.f;
     }
-    // pass 1: speed and steering; own steps keep both from before the step
-    float vb[SPG], db[SPG];
+    // running sums of this lane's increments, then the scan across the group
+    auto scan = [&](const float *inc, float start, float *before, float *after) {
+      float own = inc[0];
 #pragma unroll
-    for (int s = 0; s < SPG; ++s) vb[s] = db[s] = 0.f;
-    pass([&](auto jc, int s, bool mine) {
-      constexpr int JJ = decltype(jc)::value;
-      const float v0 = group_bcast<LPS, JJ>(u0[s]), v1 = group_bcast<LPS, JJ>(u1[s]);
-      vb[s] = mine ? x[3] : vb[s];
-      db[s] = mine ? x[4] : db[s];
-      x[3] += dt * v0;
-      x[4] += dt * v1;
-    });
-    // own steps: heading increment x3 tan(d) / L
-    float w[SPG];
+      for (int s = 1; s < SPG; ++s) own += inc[s];
+      float r = start + group_excl_of_incl<LPS>(group_scan_incl<LPS>(own, lane_j), lane_j);
+#pragma unroll
+      for (int s = 0; s < SPG; ++s) {
+        if (before) before[s] = r;
+        r += inc[s];
+        if (after) after[s] = r;
+      }
+      return group_bcast<LPS, LPS - 1>(r);         // the value after the chunk
+    };
+    float vb[SPG], db[SPG], va[SPG];
+    x[3] = scan(a3, x[3], vb, va);
+    x[4] = scan(a4, x[4], db, nullptr);
+    float a2[SPG];                                 // own steps: heading increments
 #pragma unroll
     for (int s = 0; s < SPG; ++s) {
       float dl = db[s];
@@ -245,39 +240,27 @@ struct BicycleSys {
       float sd, cd;
       fsincos(dl, sd, cd);
       const float tn = sd * frcp(cd);
-      w[s] = vb[s] * tn * p.L_inv;
+      a2[s] = ok[s] ? dt * (vb[s] * tn * p.L_inv) : 0.f;
     }
-    // pass 2: heading; own steps keep it from before the step
     float hb[SPG];
-#pragma unroll
-    for (int s = 0; s < SPG; ++s) hb[s] = 0.f;
-    pass([&](auto jc, int s, bool mine) {
-      constexpr int JJ = decltype(jc)::value;
-      const float wj = group_bcast<LPS, JJ>(w[s]);
-      hb[s] = mine ? x[2] : hb[s];
-      x[2] += dt * wj;
-    });
-    // own steps: position increments x3 (cos, sin)(heading)
-    float c0[SPG], c1[SPG];
+    x[2] = scan(a2, x[2], hb, nullptr);
+    float a0[SPG], a1[SPG];                        // own steps: position increments
 #pragma unroll
     for (int s = 0; s < SPG; ++s) {
       float sn, cs;
       fsincos(hb[s], sn, cs);
-      c0[s] = vb[s] * cs;
-      c1[s] = vb[s] * sn;
+      a0[s] = ok[s] ? dt * (vb[s] * cs) : 0.f;
+      a1[s] = ok[s] ? dt * (vb[s] * sn) : 0.f;
     }
-    // pass 3: position; own steps keep it from after the step
-    pass([&](auto jc, int s, bool mine) {
-      constexpr int JJ = decltype(jc)::value;
-      const float a0 = group_bcast<LPS, JJ>(c0[s]), a1 = group_bcast<LPS, JJ>(c1[s]);
-      x[0] += dt * a0;
-      x[1] += dt * a1;
-      xq[s][0] = mine ? x[0] : xq[s][0];
-      xq[s][1] = mine ? x[1] : xq[s][1];
-    });
-    // own steps: speed after the step, as pass 1 formed it
+    float pa0[SPG], pa1[SPG];
+    x[0] = scan(a0, x[0], nullptr, pa0);
+    x[1] = scan(a1, x[1], nullptr, pa1);
 #pragma unroll
-    for (int s = 0; s < SPG; ++s) xq[s][2] = vb[s] + dt * u0[s];
+    for (int s = 0; s < SPG; ++s) {
+      xq[s][0] = pa0[s];
+      xq[s][1] = pa1[s];
+      xq[s][2] = va[s];
+    }
   }
   __device__ static float q_step(const Params &p, const float *xq) {
     float gx = xq[0] * p.cell_inv, gy = xq[1] * p.cell_inv;
