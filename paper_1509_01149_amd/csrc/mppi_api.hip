@@ -218,10 +218,14 @@ void compute_layout(const mppi_config *c, Layout *L) {
   // samples per rollout block: 64 for the learned dynamics (16 per wave), 256 / lanes-per-sample otherwise
   const int roll_per_block = c->system == MPPI_SYS_QUADROTOR_MLP ? 64 : kBlock / rollout_lps(c);
   L->n_roll_blocks = (K + roll_per_block - 1) / roll_per_block;
-  // update chunk: 128 samples while that keeps the update grid within ~500 blocks (the
-  // shorter per-thread chain wins while the device has room), else 256
-  const int upd_blocks_128 = ((K + 127) / 128) * ((L->G + kUpdGroups - 1) / kUpdGroups);
-  L->upd_chunk = upd_blocks_128 <= 500 ? 128 : 256;
+  // update chunk: the smallest of 128, 256, 512 samples that keeps the update grid within
+  // ~500 (128) or ~1200 (256) blocks: a shorter per-thread chain wins while the device has
+  // room, fewer blocks win once it is full (512 with path weighting only)
+  const int gblk = (L->G + kUpdGroups - 1) / kUpdGroups;
+  const bool ctg_w = c->weighting == MPPI_WEIGHT_COST_TO_GO;
+  if (((K + 127) / 128) * gblk <= 500) L->upd_chunk = 128;
+  else if (ctg_w || ((K + 255) / 256) * gblk <= 1200) L->upd_chunk = 256;
+  else L->upd_chunk = 512;
   L->n_kc = (K + L->upd_chunk - 1) / L->upd_chunk;
   uint64_t o = 0;
   auto take = [&](uint64_t bytes) { uint64_t r = o; o = align256(o + bytes); return r; };

@@ -24,7 +24,7 @@ namespace mppi {
 constexpr int kUpdGroups = 4;                        // noise groups per update block
 constexpr int kUpdStrips = kBlock / kUpdGroups;      // sample strips per update block
 static_assert(kUpdStrips % 16 == 0 && kUpdGroups * 4 * 16 <= kBlock, "update reduction layout");
-constexpr int kUpdChunkMax = kBlock;                 // samples per update block: 128 or 256 (IterArgs)
+constexpr int kUpdChunkMax = 2 * kBlock;             // samples per update block: 128, 256 or 512 (IterArgs)
 
 struct IterArgs {
   const double *x0;        // [n]
@@ -46,7 +46,7 @@ struct IterArgs {
   float R[16];             // m x m
   double inv_lambda;
   double *rho_out;         // update: this iteration's minimum path cost (written by one block)
-  int upd_chunk;           // samples per update block (128 or 256)
+  int upd_chunk;           // samples per update block (128, 256, or 512 with path weighting)
 };
 
 struct FinalizeArgs {
@@ -450,17 +450,29 @@ __device__ __forceinline__ void update_body(const IterArgs &a, int kc, int gcb) 
   __shared__ double acc_lds[kUpdStrips][kUpdGroups][4];
   __shared__ double red[4];
   const int chunk = a.upd_chunk, ppt = chunk / kUpdStrips;
-  const int k_own = kc * chunk + threadIdx.x;
-  const double s_own = (int)threadIdx.x < chunk && k_own < a.K ? a.S[k_own] : __builtin_inf();   // in flight with the minima
+  // this thread's samples of the chunk (tid, tid + 256): costs in flight with the minima
+  constexpr int kOwn = kUpdChunkMax / kBlock;
+  double s_own[kOwn];
+#pragma unroll
+  for (int o = 0; o < kOwn; ++o) {
+    const int kk = threadIdx.x + o * kBlock, k = kc * chunk + kk;
+    s_own[o] = kk < chunk && k < a.K ? a.S[k] : __builtin_inf();
+  }
   const double rho = global_min(a.blk_min, a.n_roll_blocks, red);
   if (kc == 0 && gcb == 0 && threadIdx.x == 0) *a.rho_out = rho;
   const uint64_t it = *a.iter;
   {
-    double wk = 0.0;
-    if (rho < __builtin_inf() && s_own < __builtin_inf()) wk = exp(-(s_own - rho) * a.inv_lambda);
-    w[threadIdx.x] = wk;
+    double wsum = 0.0;                              // this thread's weights, in order
+#pragma unroll
+    for (int o = 0; o < kOwn; ++o) {
+      const int kk = threadIdx.x + o * kBlock;
+      double wk = 0.0;
+      if (rho < __builtin_inf() && s_own[o] < __builtin_inf()) wk = exp(-(s_own[o] - rho) * a.inv_lambda);
+      if (kk < chunk) w[kk] = wk;
+      wsum += wk;
+    }
     if (gcb == 0) {
-      const double e = block_sum(wk, red);
+      const double e = block_sum(wsum, red);
       if (threadIdx.x == 0) a.eta_part[kc] = e;
     }
   }
