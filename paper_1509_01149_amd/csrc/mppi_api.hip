@@ -374,8 +374,7 @@ static size_t rollout_lds_bytes(const mppi_ctx *c) {
   size_t fl = (size_t)2 * T * m + ((T + 3) & ~3);
   fl = (fl + 3) & ~size_t(3);
   // the step-split body stages nothing beyond the controls; the quadrotor its obstacles
-  if (c->cfg.system == MPPI_SYS_QUADROTOR || c->cfg.system == MPPI_SYS_QUADROTOR_MLP)
-    fl += Sys::stage_floats(c->quad.n_obs, 0);
+  if constexpr (!Sys::kStepSplit) fl += Sys::stage_floats(c->quad.n_obs, 0);
   return fl * 4;
 }
 

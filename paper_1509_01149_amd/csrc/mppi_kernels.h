@@ -1,9 +1,10 @@
 // The MPPI iteration as three kernels (paper: Algorithm 1 with the likelihood-ratio
 // running cost and update law of Section III-C):
 //
-//   rollout<Sys>  four lanes per sample (a DPP quad; one with the LPS = 1 build), or the
-//                 step-split variant (4 or 16 lanes sharing a sample's horizon) for
-//                 systems whose cost does not act on the state: draw the
+//   rollout<Sys>  the step-split body (4 or 16 lanes sharing a sample's horizon) for
+//                 systems whose cost does not act on the state, or the four-lane body
+//                 (a DPP quad per sample; one lane with the LPS = 1 build) for the
+//                 quadrotor, whose cost is split over the quad: draw the
 //                 perturbations from Philox in registers, Euler-step the dynamics over
 //                 the horizon, accumulate the path cost
 //                 S_k = sum_i [q(x_{i+1}) + du'Mq du + u'R du + u'R u/2] + phi, where

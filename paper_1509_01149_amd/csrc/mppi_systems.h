@@ -5,7 +5,8 @@
 #pragma once
 #include "mppi_device.h"
 
-// Lanes per sample in the rollout (1 or 4); a build-time tuning knob.
+// Lanes per sample of the four-lane rollout body (1 or 4; the quadrotor's); a build-time
+// tuning knob.  The step-split systems choose theirs per controller.
 #ifndef MPPI_ROLLOUT_LPS
 #define MPPI_ROLLOUT_LPS 4
 #endif
@@ -51,8 +52,6 @@ struct LinearSys {
     }
     return s;
   }
-  static constexpr bool kSplitCost = false, kCrash = false;
-  static constexpr int kLPS = MPPI_ROLLOUT_LPS;
   // step-split rollout: the cost reads the whole state
   static constexpr bool kStepSplit = true, kOwnChunk = false;
   static constexpr int NQ = N;
@@ -62,12 +61,7 @@ struct LinearSys {
   }
   __device__ static float q_step(const Params &p, const float *xq) { return quad(p.Q, xq); }
   __device__ static float q(const Params &p, const StageView &, const float *x) { return quad(p.Q, x); }
-  __device__ static float q_part(const Params &p, const StageView &sv, const float *x, int, int) { return q(p, sv, x); }
   __device__ static float phi(const Params &p, const float *x) { return quad(p.Qf, x); }
-  static constexpr int stage_floats(int, int) { return 0; }
-  __device__ static void stage(const Params &, float *, const double *, int *, int *) {}
-  struct Regs {};
-  __device__ static void load_regs(const Params &, const StageView &, int, int, Regs &) {}
 };
 
 // ------------------------------------------------------------------------ cart-pole
@@ -93,8 +87,6 @@ struct CartPoleSys {
     xd[2] = x[3];
     xd[3] = thdd;
   }
-  static constexpr bool kSplitCost = false, kCrash = false;
-  static constexpr int kLPS = MPPI_ROLLOUT_LPS;
   __device__ static float q(const Params &p, const StageView &, const float *x) {
     return p.qd[0] * x[0] * x[0] + p.qd[1] * x[1] * x[1] + p.qd[2] * x[2] * x[2] + p.qd[3] * x[3] * x[3];
   }
@@ -105,14 +97,9 @@ struct CartPoleSys {
     for (int r = 0; r < N; ++r) xq[r] = x[r];
   }
   __device__ static float q_step(const Params &p, const float *xq) { return q(p, StageView{}, xq); }
-  __device__ static float q_part(const Params &p, const StageView &sv, const float *x, int, int) { return q(p, sv, x); }
   __device__ static float phi(const Params &p, const float *x) {
     return p.qfd[0] * x[0] * x[0] + p.qfd[1] * x[1] * x[1] + p.qfd[2] * x[2] * x[2] + p.qfd[3] * x[3] * x[3];
   }
-  static constexpr int stage_floats(int, int) { return 0; }
-  __device__ static void stage(const Params &, float *, const double *, int *, int *) {}
-  struct Regs {};
-  __device__ static void load_regs(const Params &, const StageView &, int, int, Regs &) {}
 };
 
 // ------------------------------------------------ cart-pole swing-up (velocity command)
@@ -136,8 +123,6 @@ struct SwingUpSys {
     fsincos(x[2], s, c);
     xd[3] = -k * (g * s + pdd * c);
   }
-  static constexpr bool kSplitCost = false, kCrash = false;
-  static constexpr int kLPS = MPPI_ROLLOUT_LPS;
   __device__ static float q(const Params &p, const StageView &, const float *x) {
     const float a = 1.f + fcos(x[2]);
     return p.wp * x[0] * x[0] + p.wa * a * a + p.wr * x[3] * x[3] + p.wv * x[1] * x[1];
@@ -149,12 +134,7 @@ struct SwingUpSys {
     for (int r = 0; r < N; ++r) xq[r] = x[r];
   }
   __device__ static float q_step(const Params &p, const float *xq) { return q(p, StageView{}, xq); }
-  __device__ static float q_part(const Params &p, const StageView &sv, const float *x, int, int) { return q(p, sv, x); }
   __device__ static float phi(const Params &, const float *) { return 0.f; }
-  static constexpr int stage_floats(int, int) { return 0; }
-  __device__ static void stage(const Params &, float *, const double *, int *, int *) {}
-  struct Regs {};
-  __device__ static void load_regs(const Params &, const StageView &, int, int, Regs &) {}
 };
 
 // ------------------------------------------------------------ kinematic bicycle + map
@@ -185,7 +165,6 @@ struct BicycleSys {
     xd[3] = v[0];
     xd[4] = v[1];
   }
-  static constexpr int stage_floats(int, int) { return 0; }   // nothing staged in LDS
   // Step-split rollout: the cost needs position and speed only, and reads the bilinear
   // taps straight from the map in global memory (L2-resident; no LDS window, so no
   // fallback).  Same arithmetic and tap values as q().
