@@ -134,6 +134,42 @@ __device__ __forceinline__ float group_excl_of_incl(float incl, int lj) {
   else return lj >= 1 ? t : 0.f;
 }
 
+// Scan of affine maps x -> A x + B over each aligned group of G lanes, composed in lane
+// order (a lane's map applies after those of the lanes before it): inclusive result in
+// (A, B); lanes with no source take the identity (1, 0).
+template <int Ctrl>
+__device__ __forceinline__ float dpp_or(float v, float fill) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(fill), __float_as_int(v), Ctrl, 0xF, 0xF, false));
+}
+template <int G, int Ctrl, int D>
+__device__ __forceinline__ void affine_step(float &A, float &B, int lj) {
+  float Ap = dpp_or<Ctrl>(A, 1.f), Bp = dpp_or<Ctrl>(B, 0.f);
+  if constexpr (G == 4) {
+    if (lj < D) { Ap = 1.f; Bp = 0.f; }            // no crossing into the previous quad
+  }
+  B = fmaf(A, Bp, B);                              // x -> A (Ap x + Bp) + B
+  A = A * Ap;
+}
+template <int G>
+__device__ __forceinline__ void group_affine_scan_incl(float &A, float &B, int lj) {
+  affine_step<G, 0x111, 1>(A, B, lj);              // row_shr:1
+  affine_step<G, 0x112, 2>(A, B, lj);              // row_shr:2
+  if constexpr (G == 16) {
+    affine_step<G, 0x114, 4>(A, B, lj);            // row_shr:4
+    affine_step<G, 0x118, 8>(A, B, lj);            // row_shr:8
+  }
+}
+// The inclusive map of the lane before (the identity in the group's first lane).
+template <int G>
+__device__ __forceinline__ void group_affine_excl_of_incl(float &A, float &B, int lj) {
+  float Ap = dpp_or<0x111>(A, 1.f), Bp = dpp_or<0x111>(B, 0.f);
+  if constexpr (G == 4) {
+    if (lj < 1) { Ap = 1.f; Bp = 0.f; }
+  }
+  A = Ap;
+  B = Bp;
+}
+
 // Compile-time loop: f(std::integral_constant<int, J>) for J = B .. E-1.
 template <int B, int E>
 struct StaticFor {

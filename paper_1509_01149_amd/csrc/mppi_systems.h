@@ -127,7 +127,7 @@ struct SwingUpSys {
     const float a = 1.f + fcos(x[2]);
     return p.wp * x[0] * x[0] + p.wa * a * a + p.wr * x[3] * x[3] + p.wv * x[1] * x[1];
   }
-  static constexpr bool kStepSplit = true, kOwnChunk = false;
+  static constexpr bool kStepSplit = true, kOwnChunk = true;
   static constexpr int NQ = N;
   __device__ static void cost_state(const float *x, float *xq) {
 #pragma unroll
@@ -135,6 +135,96 @@ struct SwingUpSys {
   }
   __device__ static float q_step(const Params &p, const float *xq) { return q(p, StageView{}, xq); }
   __device__ static float phi(const Params &, const float *) { return 0.f; }
+  // One chunk of the step-split rollout.  The cart is driven by the command alone: its
+  // velocity follows the affine map pdot -> (1 - dt gain) pdot + dt gain u and its
+  // position adds dt pdot, so both are prefix scans over the chunk (the velocity's a scan
+  // of affine maps); each lane then forms the cart acceleration of its own steps, and the
+  // pole's angle and rate, the only part with a per-step chain, are stepped in every lane
+  // with those accelerations broadcast from their owners.  Steps past the horizon leave
+  // the state unchanged.  du: this lane's perturbations (SPG steps); xq: state after its
+  // steps.
+  template <int LPS, int SPG, bool kChecked>
+  __device__ static void chunk(const Params &p, int T, float dt, const float *sU, const float *du, int g0,
+                               int lane_j, float *x, float (*xq)[NQ]) {
+    const int i_first = (g0 + lane_j) * SPG;
+    const float ca = 1.f - dt * p.gain, cb = dt * p.gain;
+    bool ok[SPG];
+    float v[SPG];
+#pragma unroll
+    for (int s = 0; s < SPG; ++s) {
+      const int i = i_first + s;
+      ok[s] = !kChecked || i < T;
+      v[s] = sU[min(i, T - 1)] + du[s];
+    }
+    // cart velocity: this lane's composed map, the maps before it, then its own steps
+    float A = 1.f, B = 0.f;
+#pragma unroll
+    for (int s = 0; s < SPG; ++s)
+      if (ok[s]) {
+        B = fmaf(ca, B, cb * v[s]);
+        A = ca * A;
+      }
+    group_affine_scan_incl<LPS>(A, B, lane_j);
+    group_affine_excl_of_incl<LPS>(A, B, lane_j);
+    float w = fmaf(A, x[1], B);                     // cart velocity before this lane's steps
+    float vb[SPG], va[SPG], pdd[SPG];
+#pragma unroll
+    for (int s = 0; s < SPG; ++s) {
+      vb[s] = w;
+      pdd[s] = p.gain * (v[s] - w);
+      if (ok[s]) w = fmaf(ca, w, cb * v[s]);
+      va[s] = w;
+    }
+    x[1] = group_bcast<LPS, LPS - 1>(w);
+    // cart position: running sum of dt pdot
+    float own = 0.f, inc[SPG];
+#pragma unroll
+    for (int s = 0; s < SPG; ++s) {
+      inc[s] = ok[s] ? dt * vb[s] : 0.f;
+      own += inc[s];
+    }
+    float r = x[0] + group_excl_of_incl<LPS>(group_scan_incl<LPS>(own, lane_j), lane_j);
+    float pa[SPG];
+#pragma unroll
+    for (int s = 0; s < SPG; ++s) {
+      r += inc[s];
+      pa[s] = r;
+    }
+    x[0] = group_bcast<LPS, LPS - 1>(r);
+    // pole: every lane steps angle and rate through the chunk
+    float th[SPG], om[SPG];
+#pragma unroll
+    for (int s = 0; s < SPG; ++s) th[s] = om[s] = 0.f;
+    StaticFor<0, LPS>::run([&](auto jc) {
+      constexpr int JJ = decltype(jc)::value;
+      const int i0 = (g0 + JJ) * SPG;
+      if (!kChecked || i0 < T) {
+        float a_c[SPG];
+#pragma unroll
+        for (int s = 0; s < SPG; ++s) a_c[s] = group_bcast<LPS, JJ>(pdd[s]);
+        const bool mine = lane_j == JJ;
+#pragma unroll
+        for (int s = 0; s < SPG; ++s) {
+          if (!kChecked || i0 + s < T) {
+            float sn, cs;
+            fsincos(x[2], sn, cs);
+            const float al = -p.k * (p.g * sn + a_c[s] * cs);
+            x[2] += dt * x[3];
+            x[3] += dt * al;
+            th[s] = mine ? x[2] : th[s];
+            om[s] = mine ? x[3] : om[s];
+          }
+        }
+      }
+    });
+#pragma unroll
+    for (int s = 0; s < SPG; ++s) {
+      xq[s][0] = pa[s];
+      xq[s][1] = va[s];
+      xq[s][2] = th[s];
+      xq[s][3] = om[s];
+    }
+  }
 };
 
 // ------------------------------------------------------------ kinematic bicycle + map
