@@ -205,10 +205,13 @@ bool rollout_split(const mppi_config *c) {
 // Lanes per sample of the rollout.  Step-split: 16 while K x 16 lanes stay within two
 // waves per SIMD (K <= 8192), which trades redundant dynamics for a shorter chain per
 // wave on a device the controller cannot fill; 4 for larger K, where the device is full
-// and the redundancy would cost throughput.  Otherwise the four-lane body's build value.
+// and the redundancy would cost throughput.  The bicycle, whose chunk is all prefix
+// scans (so a lane's chain shrinks with the group), takes 32 while K <= 4096: two waves
+// per SIMD, each with half the chunks.  Otherwise the four-lane body's build value.
 int rollout_lps(const mppi_config *c) {
-  if (rollout_split(c)) return c->K <= 8192 ? 16 : 4;
-  return MPPI_ROLLOUT_LPS;
+  if (!rollout_split(c)) return MPPI_ROLLOUT_LPS;
+  if (c->system == MPPI_SYS_BICYCLE && c->K <= 4096) return 32;
+  return c->K <= 8192 ? 16 : 4;
 }
 
 void compute_layout(const mppi_config *c, Layout *L) {
@@ -398,6 +401,8 @@ static const void *rollout_fn() {
 template <class Sys, int Mode>
 static const void *rollout_split_fn(int lps) {
   if constexpr (Sys::kStepSplit) {
+    if constexpr (Sys::kLanes32)
+      if (lps == 32) return (const void *)rollout_kernel<Sys, 32, Mode>;
     if (lps == 16) return (const void *)rollout_kernel<Sys, 16, Mode>;
     if (lps == 4) return (const void *)rollout_kernel<Sys, 4, Mode>;
   }

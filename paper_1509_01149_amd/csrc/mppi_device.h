@@ -87,7 +87,8 @@ __device__ __forceinline__ void fsincos(double x, double &s, double &c) { sincos
 
 // ---------------------------------------------------------------------------------
 // Lane groups of a wave: broadcast lane J of each aligned group of G lanes to the group
-// (DPP: quad_perm for 4, row_newbcast for a 16-lane row).
+// (DPP quad_perm for 4, DPP row_newbcast for a 16-lane row, ds_swizzle in bit-mask
+// mode for a half wave of 32: source lane (lane & 0) | J within each 32-lane half).
 // ---------------------------------------------------------------------------------
 template <int J>
 __device__ __forceinline__ float quad_bcast(float v) {
@@ -97,29 +98,36 @@ template <int G, int J>
 __device__ __forceinline__ float group_bcast(float v) {
   if constexpr (G == 4) {
     return quad_bcast<J>(v);
-  } else {
-    static_assert(G == 16, "lane groups of 4 or 16");
+  } else if constexpr (G == 16) {
     return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x150 + J, 0xF, 0xF, false));  // row_newbcast:J
+  } else {
+    static_assert(G == 32, "lane groups of 4, 16 or 32");
+    return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), J << 5));  // and 0, or J, xor 0
   }
 }
 
-// Prefix sums over each aligned group of G lanes (G = 4 or 16; lj = lane % G), in a fixed
-// tree order.  Inclusive: DPP row shifts by 1, 2, 4, 8 (lanes with no source add 0);
-// groups of 4 mask the shifts that would cross a quad.  Exclusive: the inclusive sum of
-// the lane before (0 in the group's first lane).
+// Prefix sums over each aligned group of G lanes (G = 4, 16 or 32; lj = lane % G), in a
+// fixed tree order.  Inclusive: DPP row shifts by 1, 2, 4, 8 (lanes with no source add
+// 0); groups of 4 mask the shifts that would cross a quad; groups of 32 then add the
+// first row's total (its lane 15, DPP row_bcast:15) into the second row.  Exclusive: the
+// inclusive sum of the lane before (0 in the group's first lane; across the row boundary
+// of a 32-lane group by a whole-wave shift).
 template <int Ctrl>
 __device__ __forceinline__ float dpp_or_zero(float v) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), Ctrl, 0xF, 0xF, false));
 }
 template <int G>
 __device__ __forceinline__ float group_scan_incl(float v, int lj) {
-  if constexpr (G == 16) {
+  if constexpr (G >= 16) {
+    static_assert(G == 16 || G == 32, "lane groups of 4, 16 or 32");
     v += dpp_or_zero<0x111>(v);                    // row_shr:1
     v += dpp_or_zero<0x112>(v);                    // row_shr:2
     v += dpp_or_zero<0x114>(v);                    // row_shr:4
     v += dpp_or_zero<0x118>(v);                    // row_shr:8
+    if constexpr (G == 32)                         // rows 1 and 3 add lane 15 of rows 0 and 2
+      v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x142, 0xA, 0xF, false));
   } else {
-    static_assert(G == 4, "lane groups of 4 or 16");
+    static_assert(G == 4, "lane groups of 4, 16 or 32");
     const float t1 = dpp_or_zero<0x111>(v);
     v += lj >= 1 ? t1 : 0.f;
     const float t2 = dpp_or_zero<0x112>(v);
@@ -129,9 +137,14 @@ __device__ __forceinline__ float group_scan_incl(float v, int lj) {
 }
 template <int G>
 __device__ __forceinline__ float group_excl_of_incl(float incl, int lj) {
-  const float t = dpp_or_zero<0x111>(incl);        // row_shr:1
-  if constexpr (G == 16) return t;
-  else return lj >= 1 ? t : 0.f;
+  if constexpr (G == 32) {
+    const float t = dpp_or_zero<0x138>(incl);      // wave_shr:1
+    return lj >= 1 ? t : 0.f;
+  } else {
+    const float t = dpp_or_zero<0x111>(incl);      // row_shr:1
+    if constexpr (G == 16) return t;
+    else return lj >= 1 ? t : 0.f;
+  }
 }
 
 // Scan of affine maps x -> A x + B over each aligned group of G lanes, composed in lane

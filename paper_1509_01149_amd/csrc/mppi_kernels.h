@@ -270,9 +270,14 @@ template <int LPS>
 __device__ __forceinline__ double group_sum(double v) {
   v += dpp_f64<0xB1>(v);                            // quad_perm(1,0,3,2)
   v += dpp_f64<0x4E>(v);                            // quad_perm(2,3,0,1)
-  if constexpr (LPS == 16) {
+  if constexpr (LPS >= 16) {
     v += dpp_f64<0x124>(v);                         // row_ror:4
     v += dpp_f64<0x128>(v);                         // row_ror:8
+  }
+  if constexpr (LPS == 32) {                        // lane 0 adds lane 16's row total
+    const int lo = __builtin_amdgcn_ds_swizzle(__double2loint(v), (16 << 10) | 0x1F);   // lane ^ 16
+    const int hi = __builtin_amdgcn_ds_swizzle(__double2hiint(v), (16 << 10) | 0x1F);
+    v += __hiloint2double(hi, lo);
   }
   return v;
 }

@@ -20,13 +20,14 @@ namespace {
 
 // rollout instantiations: linear m=1,2,4, cart-pole, bicycle, quadrotor, swing-up, quadrotor
 // with the crash indicator; kinds 8 + (0, 1, 2, 3, 4, 6) are the step-split systems at 16
-// lanes per sample (at 4 below that)
-constexpr int kKinds = 16;
+// lanes per sample (at 4 below that), kind 16 + 4 the bicycle at 32
+constexpr int kKinds = 24;
 constexpr int kWide = 8;
 
 int kind_of(const mppi_config &c) {
   if (c.system == MPPI_SYS_QUADROTOR && ((const mppi_quadrotor_params *)c.params)->crash_cost > 0) return 7;
-  const int wide = rollout_split(&c) && rollout_lps(&c) == 16 ? kWide : 0;
+  const int lps = rollout_split(&c) ? rollout_lps(&c) : 0;
+  const int wide = lps == 32 ? 2 * kWide : (lps == 16 ? kWide : 0);
   switch (c.system) {
     case MPPI_SYS_LINEAR: return wide + (c.n_ctrl == 1 ? 0 : (c.n_ctrl == 2 ? 1 : 2));
     case MPPI_SYS_CARTPOLE: return wide + 3;
@@ -183,6 +184,7 @@ int launch_batched(mppi_server *s, Batch &b, const std::vector<int> &sl) {
       case kWide + 2: launch_roll<LinearSys<4>, 16, kStepSplit>(s, b, k, cnt[k], total, lds[k], st); break;
       case kWide + 3: launch_roll<CartPoleSys, 16, kStepSplit>(s, b, k, cnt[k], total, lds[k], st); break;
       case kWide + 4: launch_roll<BicycleSys, 16, kStepSplit>(s, b, k, cnt[k], total, lds[k], st); break;
+      case 2 * kWide + 4: launch_roll<BicycleSys, 32, kStepSplit>(s, b, k, cnt[k], total, lds[k], st); break;
       default: launch_roll<SwingUpSys, 16, kStepSplit>(s, b, k, cnt[k], total, lds[k], st); break;
     }
   }

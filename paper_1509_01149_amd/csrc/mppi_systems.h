@@ -53,7 +53,7 @@ struct LinearSys {
     return s;
   }
   // step-split rollout: the cost reads the whole state
-  static constexpr bool kStepSplit = true, kOwnChunk = false;
+  static constexpr bool kStepSplit = true, kOwnChunk = false, kLanes32 = false;
   static constexpr int NQ = N;
   __device__ static void cost_state(const float *x, float *xq) {
 #pragma unroll
@@ -90,7 +90,7 @@ struct CartPoleSys {
   __device__ static float q(const Params &p, const StageView &, const float *x) {
     return p.qd[0] * x[0] * x[0] + p.qd[1] * x[1] * x[1] + p.qd[2] * x[2] * x[2] + p.qd[3] * x[3] * x[3];
   }
-  static constexpr bool kStepSplit = true, kOwnChunk = false;
+  static constexpr bool kStepSplit = true, kOwnChunk = false, kLanes32 = false;
   static constexpr int NQ = N;
   __device__ static void cost_state(const float *x, float *xq) {
 #pragma unroll
@@ -127,7 +127,7 @@ struct SwingUpSys {
     const float a = 1.f + fcos(x[2]);
     return p.wp * x[0] * x[0] + p.wa * a * a + p.wr * x[3] * x[3] + p.wv * x[1] * x[1];
   }
-  static constexpr bool kStepSplit = true, kOwnChunk = true;
+  static constexpr bool kStepSplit = true, kOwnChunk = true, kLanes32 = false;   // affine scans: 4 or 16
   static constexpr int NQ = N;
   __device__ static void cost_state(const float *x, float *xq) {
 #pragma unroll
@@ -258,7 +258,7 @@ struct BicycleSys {
   // Step-split rollout: the cost needs position and speed only, and reads the bilinear
   // taps straight from the map in global memory (L2-resident; no LDS window, so no
   // fallback).  Same arithmetic and tap values as q().
-  static constexpr bool kStepSplit = true, kOwnChunk = true;
+  static constexpr bool kStepSplit = true, kOwnChunk = true, kLanes32 = true;
   static constexpr int NQ = 3;
   __device__ static void cost_state(const float *x, float *xq) { xq[0] = x[0]; xq[1] = x[1]; xq[2] = x[3]; }
   // One chunk of the step-split rollout.  Every state update of the bicycle is a running

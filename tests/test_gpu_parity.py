@@ -49,9 +49,11 @@ CASES = {
     "swingup_nu1": lambda: W.cartpole_swingup(nu=1.0),
     "swingup_nu1000": lambda: W.cartpole_swingup(nu=1000.0, K=4096),
     # step-split lane counts: K above 8192 takes 4 lanes per sample (ragged horizon, last
-    # chunk partial); K = 8192 is the largest with 16
+    # chunk partial); K = 8192 is the largest with 16; the bicycle takes 32 up to K = 4096
+    # (the default cases; here also a partial last block and a single ragged chunk)
     "bicycle_4lanes": lambda: W.bicycle(K=9000, T=37),
     "bicycle_16lanes_k8192": lambda: W.bicycle(K=8192, T=100),
+    "bicycle_32lanes_ragged": lambda: W.bicycle(K=4000, T=37),
 }
 
 
