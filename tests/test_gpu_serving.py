@@ -30,6 +30,7 @@ def mix():
         W.quadrotor(nu=2.0, K=2048, T=120, crash=True).replace(seed=29),      # own rollout type
         W.cartpole_swingup(nu=100.0, K=1000).replace(seed=30),
         W.bicycle(K=1024, T=30, nu=np.array([1.0, 4.0])).replace(seed=31),    # per-dimension nu
+        W.bicycle(K=8192, T=40).replace(seed=32),                             # 16 lanes (the others 32)
     ]
 
 
