@@ -90,7 +90,7 @@ struct CartPoleSys {
   __device__ static float q(const Params &p, const StageView &, const float *x) {
     return p.qd[0] * x[0] * x[0] + p.qd[1] * x[1] * x[1] + p.qd[2] * x[2] * x[2] + p.qd[3] * x[3] * x[3];
   }
-  static constexpr bool kStepSplit = true, kOwnChunk = false, kLanes32 = false;
+  static constexpr bool kStepSplit = true, kOwnChunk = true, kLanes32 = false;
   static constexpr int NQ = N;
   __device__ static void cost_state(const float *x, float *xq) {
 #pragma unroll
@@ -99,6 +99,92 @@ struct CartPoleSys {
   __device__ static float q_step(const Params &p, const float *xq) { return q(p, StageView{}, xq); }
   __device__ static float phi(const Params &p, const float *x) {
     return p.qfd[0] * x[0] * x[0] + p.qfd[1] * x[1] * x[1] + p.qfd[2] * x[2] * x[2] + p.qfd[3] * x[3] * x[3];
+  }
+  // One chunk of the step-split rollout.  The pole's angle and rate do not depend on the
+  // cart's position or velocity, so every lane steps only the pole through the chunk (the
+  // FP32 expressions of xdot), with the owners' forces broadcast, and keeps the cart
+  // acceleration of its own steps and the pole state after them; the cart's velocity
+  // (adding dt xddot) and position (adding dt times the velocity before the step) are
+  // then prefix sums over the chunk.  Steps past the horizon leave the state unchanged.
+  // du: this lane's perturbations (SPG steps); xq: state after its steps.
+  template <int LPS, int SPG, bool kChecked>
+  __device__ static void chunk(const Params &p, int T, float dt, const float *sU, const float *du, int g0,
+                               int lane_j, float *x, float (*xq)[NQ]) {
+    const int i_first = (g0 + lane_j) * SPG;
+    bool ok[SPG];
+    float f[SPG];                                  // own steps: applied force
+#pragma unroll
+    for (int s = 0; s < SPG; ++s) {
+      const int i = i_first + s;
+      ok[s] = !kChecked || i < T;
+      f[s] = sU[min(i, T - 1)] + du[s];
+    }
+    const float mc = p.mc, mp = p.mp, l = p.l, g = p.g;
+    const float Mt = mc + mp;
+    const float iM = frcp(Mt);
+    float xa[SPG], th[SPG], om[SPG];               // own steps: cart acceleration, pole after
+#pragma unroll
+    for (int s = 0; s < SPG; ++s) xa[s] = th[s] = om[s] = 0.f;
+    StaticFor<0, LPS>::run([&](auto jc) {
+      constexpr int JJ = decltype(jc)::value;
+      const int i0 = (g0 + JJ) * SPG;
+      if (!kChecked || i0 < T) {
+        float fj[SPG];
+#pragma unroll
+        for (int s = 0; s < SPG; ++s) fj[s] = group_bcast<LPS, JJ>(f[s]);
+        const bool mine = lane_j == JJ;
+#pragma unroll
+        for (int s = 0; s < SPG; ++s) {
+          if (!kChecked || i0 + s < T) {
+            float sn, cs;
+            fsincos(x[2], sn, cs);
+            const float h = (fj[s] + mp * l * x[3] * x[3] * sn) * iM;
+            const float thdd = (g * sn - cs * h) * frcp(l * ((float)(4.0 / 3.0) - mp * cs * cs * iM));
+            const float xdd = h - mp * l * thdd * cs * iM;
+            x[2] += dt * x[3];
+            x[3] += dt * thdd;
+            xa[s] = mine ? xdd : xa[s];
+            th[s] = mine ? x[2] : th[s];
+            om[s] = mine ? x[3] : om[s];
+            // keep each capture at its step: sunk to the chunk's end, the selects would hold
+            // every step's candidates live (about three times the registers)
+            asm volatile("" : "+v"(xa[s]), "+v"(th[s]), "+v"(om[s]));
+          }
+        }
+      }
+    });
+    // cart velocity, then position: running sums across the group
+    float inc[SPG], own = 0.f;
+#pragma unroll
+    for (int s = 0; s < SPG; ++s) {
+      inc[s] = ok[s] ? dt * xa[s] : 0.f;
+      own += inc[s];
+    }
+    float w = x[1] + group_excl_of_incl<LPS>(group_scan_incl<LPS>(own, lane_j), lane_j);
+    float vb[SPG], va[SPG];
+#pragma unroll
+    for (int s = 0; s < SPG; ++s) {
+      vb[s] = w;
+      w += inc[s];
+      va[s] = w;
+    }
+    x[1] = group_bcast<LPS, LPS - 1>(w);
+    float pinc[SPG], pown = 0.f;
+#pragma unroll
+    for (int s = 0; s < SPG; ++s) {
+      pinc[s] = ok[s] ? dt * vb[s] : 0.f;
+      pown += pinc[s];
+    }
+    float r = x[0] + group_excl_of_incl<LPS>(group_scan_incl<LPS>(pown, lane_j), lane_j);
+#pragma unroll
+    for (int s = 0; s < SPG; ++s) {
+      r += pinc[s];
+      xq[s][0] = r;
+      xq[s][1] = va[s];
+      xq[s][2] = th[s];
+      xq[s][3] = om[s];
+    }
+    x[0] = group_bcast<LPS, LPS - 1>(r);
   }
 };
 
