@@ -239,6 +239,17 @@ int mppi_debug_normals(mppi_ctx *ctx, uint64_t iteration, int32_t k0, int32_t nk
  * counters and out are host arrays of 4n uint32. */
 int mppi_debug_philox(int32_t device, uint64_t seed, const uint32_t *counters, int32_t n, uint32_t *out);
 
+/* The rollouts' lane-group primitives (aligned groups of `group` = 4, 16 or 32 lanes of a
+ * 64-lane wave) on `device`, over n_waves (1..4096) full waves.  a and b are host arrays
+ * of 64 n_waves floats; out (host, 6 floats per lane) receives, for lane t with j = t mod
+ * group: the inclusive prefix sum of a over lanes 0..j of its group, the exclusive one,
+ * a of the group's last lane, the group's sum of a (computed in FP64, returned in the
+ * group's first lane; other lanes unspecified), and the composition, in lane order, of
+ * the maps x -> a x + b of lanes 0..j as (slope, offset) (group <= 16; NaN for 32).
+ * EINVAL on a bad group, size or pointer. */
+int mppi_debug_lane_groups(int32_t device, int32_t group, const float *a, const float *b, int32_t n_waves,
+                           float *out);
+
 /* Kernel timing.  While profiling is on, every kernel of mppi_step / mppi_step_async is
  * launched directly (no graph) between two hipEvents recorded on the context's stream.
  * mppi_kernel_times waits for the stream and returns, per kernel kind (0 = rollout,

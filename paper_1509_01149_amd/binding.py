@@ -119,6 +119,7 @@ def load() -> C.CDLL:
         "mppi_debug_last": [C.c_void_p, _dp, _dp, _dp, _dp],
         "mppi_debug_normals": [C.c_void_p, C.c_uint64, C.c_int32, C.c_int32, _fp],
         "mppi_debug_philox": [C.c_int32, C.c_uint64, _u32p, C.c_int32, _u32p],
+        "mppi_debug_lane_groups": [C.c_int32, C.c_int32, _fp, _fp, C.c_int32, _fp],
         "mppi_set_profiling": [C.c_void_p, C.c_int32],
         "mppi_kernel_times": [C.c_void_p, _dp, C.POINTER(C.c_int64)],
         "mppi_server_create": [C.POINTER(ServerConfig), C.POINTER(C.c_void_p)],
@@ -558,6 +559,20 @@ def philox(counters: np.ndarray, seed: int, device: int = 0) -> np.ndarray:
     c = np.ascontiguousarray(np.asarray(counters, dtype=np.uint32).reshape(-1, 4))
     out = np.zeros_like(c)
     check(lib.mppi_debug_philox(device, seed & 0xFFFFFFFFFFFFFFFF, _ptr(c, _u32p), c.shape[0], _ptr(out, _u32p)))
+    return out
+
+
+def lane_groups(a: np.ndarray, b: np.ndarray, group: int, device: int = 0) -> np.ndarray:
+    """The rollouts' lane-group primitives on the GPU: a, b (64 n,) float32 -> (64 n, 6) float32
+    (inclusive scan, exclusive scan, last-lane broadcast, group sum in the first lane,
+    affine-scan slope and offset)."""
+    lib = load()
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float32).ravel())
+    b = np.ascontiguousarray(np.asarray(b, dtype=np.float32).ravel())
+    if a.size != b.size or a.size % 64:
+        raise ValueError("a and b must hold the same whole number of 64-lane waves")
+    out = np.zeros((a.size, 6), dtype=np.float32)
+    check(lib.mppi_debug_lane_groups(device, int(group), _ptr(a, _fp), _ptr(b, _fp), a.size // 64, _ptr(out, _fp)))
     return out
 
 

@@ -980,6 +980,32 @@ extern "C" int mppi_debug_philox(int32_t device, uint64_t seed, const uint32_t *
   return MPPI_OK;
 }
 
+extern "C" int mppi_debug_lane_groups(int32_t device, int32_t group, const float *a, const float *b, int32_t n_waves,
+                                      float *out) {
+  if (!a || !b || !out || n_waves < 1 || n_waves > 4096) return fail(MPPI_EINVAL, "bad a/b/out/n_waves");
+  if (group != 4 && group != 16 && group != 32) return fail(MPPI_EINVAL, "group must be 4, 16 or 32");
+  int rc = set_device(device);
+  if (rc) return rc;
+  const size_t n = (size_t)n_waves * kWave;
+  float *d = nullptr;                                   // a | b | out (6 per lane)
+  HIP_TRY(hipMalloc((void **)&d, n * 8 * sizeof(float)));
+  hipError_t e = hipMemcpy(d, a, n * sizeof(float), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(d + n, b, n * sizeof(float), hipMemcpyHostToDevice);
+  if (e == hipSuccess) {
+    const void *fn = group == 4 ? (const void *)lane_groups_kernel<4>
+                     : group == 16 ? (const void *)lane_groups_kernel<16> : (const void *)lane_groups_kernel<32>;
+    const float *da = d, *db = d + n;
+    float *dout = d + 2 * n;
+    void *args[] = {(void *)&da, (void *)&db, (void *)&dout};
+    e = hipLaunchKernel(fn, dim3(n_waves), dim3(kWave), args, 0, 0);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+  }
+  if (e == hipSuccess) e = hipMemcpy(out, d + 2 * n, n * 6 * sizeof(float), hipMemcpyDeviceToHost);
+  (void)hipFree(d);
+  if (e != hipSuccess) return hip_fail(e, "debug_lane_groups");
+  return MPPI_OK;
+}
+
 extern "C" int mppi_set_profiling(mppi_ctx *c, int32_t on) {
   int rc = check_ctx(c);
   if (rc) return rc;

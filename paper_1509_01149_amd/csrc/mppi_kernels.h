@@ -795,4 +795,28 @@ static __global__ void philox_kernel(const uint4 *ctr, uint4 *out, int n, uint32
   if (i < n) out[i] = philox4x32_10(ctr[i], key0, key1);
 }
 
+// The lane-group helpers of the rollouts on one full wave per block (every lane active,
+// as in the rollouts): per lane, the inclusive and exclusive scans of a, the broadcast
+// of the group's last lane, the FP64 group sum (meaningful in the group's first lane)
+// and, for G <= 16, the inclusive scan of the affine maps x -> a x + b.
+template <int G>
+static __global__ __launch_bounds__(kWave) void lane_groups_kernel(const float *a_in, const float *b_in, float *out) {
+  const int t = blockIdx.x * kWave + threadIdx.x;
+  const int lj = threadIdx.x % G;
+  const float a = a_in[t], b = b_in[t];
+  const float incl = group_scan_incl<G>(a, lj);
+  out[6 * t + 0] = incl;
+  out[6 * t + 1] = group_excl_of_incl<G>(incl, lj);
+  out[6 * t + 2] = group_bcast<G, G - 1>(a);
+  out[6 * t + 3] = (float)group_sum<G>((double)a);
+  float A = a, B = b;
+  if constexpr (G <= 16) {
+    group_affine_scan_incl<G>(A, B, lj);
+  } else {
+    A = B = __builtin_nanf("");
+  }
+  out[6 * t + 4] = A;
+  out[6 * t + 5] = B;
+}
+
 }  // namespace mppi

@@ -23,6 +23,36 @@ def test_philox_bits_match_oracle():
         assert np.array_equal(out, ref)
 
 
+@pytest.mark.parametrize("G", [4, 16, 32])
+def test_lane_group_primitives(G):
+    """The DPP and swizzle scans, broadcasts and sums the step-split rollouts are built on,
+    against their definitions.  Small integers (and slopes in {1, -1, 2}) keep every sum
+    and product exact in FP32, so the comparison is bitwise."""
+    rng = np.random.default_rng(G)
+    n = 3 * 64
+    a = rng.integers(-8, 9, size=n).astype(np.float32)
+    b = rng.integers(-8, 9, size=n).astype(np.float32)
+    out = P.binding.lane_groups(a, b, G)
+    ag = a.reshape(-1, G)
+    incl = np.cumsum(ag, axis=1)
+    assert np.array_equal(out[:, 0], incl.ravel())
+    assert np.array_equal(out[:, 1], (incl - ag).ravel())
+    assert np.array_equal(out[:, 2], np.repeat(ag[:, -1], G))
+    assert np.array_equal(out[::G, 3], ag.sum(axis=1))
+    slope = rng.choice(np.array([1.0, -1.0, 2.0], dtype=np.float32), size=n)
+    out = P.binding.lane_groups(slope, b, G)
+    if G > 16:
+        assert np.all(np.isnan(out[:, 4:]))
+        return
+    ref = np.zeros((n, 2), dtype=np.float64)
+    for g0 in range(0, n, G):
+        A, B = 1.0, 0.0
+        for t in range(g0, g0 + G):                  # lane t's map after those before it
+            A, B = slope[t] * A, slope[t] * B + b[t]
+            ref[t] = A, B
+    assert np.array_equal(out[:, 4:].astype(np.float64), ref)
+
+
 @pytest.mark.parametrize("T,m", [(100, 1), (7, 2), (150, 4)])
 def test_normals_match_oracle(T, m):
     wl = {1: W.cartpole(K=64, T=T), 2: W.bicycle(K=64, T=T), 4: W.quadrotor(K=64, T=T)}[m].replace(seed=77)
