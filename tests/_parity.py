@@ -20,7 +20,15 @@ from oracle import mppi, systems
 #          not exceed what the per-sample cost tolerance allows, 2 TOL_S max_w|S| / lambda
 #          (max over samples with weight >= 1e-9), nor 1e-3 when that is larger
 #   stage  the GPU's costs through the oracle's FP64 weights and update: <= 1e-5 relative
+#   finite the same samples are finite on both sides, except quadrotor samples whose attitude
+#          passes 1.2 rad: near pitch = +-pi/2 the Euler-angle rates divide by cos(pitch),
+#          which the FP32 path can round to zero where FP64 stays finite.  Such samples may
+#          differ in finiteness if they are at most 0.1 % of K and carry at most 1e-6 of the
+#          normalised weight on either side (the update cannot move by more than that
+#          fraction of max |du|); the cost and update metrics then use the samples finite
+#          on both sides.
 TOL_U = 1e-4
+TOL_W_INF_FLIP = 1e-6
 TOL_S = 4e-4
 TOL_S_TUMBLE = 0.1
 TUMBLE_ANGLE = 1.2
@@ -68,23 +76,30 @@ def one_step(wl, ctrl, x0, U_before, iteration, n_iters=1):
     last = res[-1]
     scale_U = max(1.0, np.max(np.abs(U_orc)), np.max(np.abs(u0_orc)))
     fin = np.isfinite(last.S)
+    fin_gpu = np.isfinite(S_gpu)
+    both = fin & fin_gpu
     rel = np.zeros(wl.K)
-    rel[fin] = np.abs(S_gpu[fin] - last.S[fin]) / np.maximum(1.0, np.abs(last.S[fin]))
+    rel[both] = np.abs(S_gpu[both] - last.S[both]) / np.maximum(1.0, np.abs(last.S[both]))
     tumble = att["max"] >= TUMBLE_ANGLE
-    dS = rel[fin & ~tumble]
+    dS = rel[both & ~tumble]
     # stage isolation: the GPU's own costs through the oracle's FP64 weights and update
-    w_i, eta_i, rho_i, dU_i, _ = mppi.weights_and_update(np.where(np.isfinite(S_gpu), S_gpu, np.inf), last.du, wl.lam)
+    w_i, eta_i, rho_i, dU_i, _ = mppi.weights_and_update(np.where(fin_gpu, S_gpu, np.inf), last.du, wl.lam)
+    # finiteness flips: tumbling samples only, few, and weightless on both sides
+    flip = fin != fin_gpu
+    w_flip = float(np.sum(np.asarray(last.w)[flip & fin])) + float(np.sum(np.asarray(w_i)[flip & fin_gpu]))
+    finite_ok = (not np.any(flip & ~tumble)) and int(np.sum(flip)) <= max(1, wl.K // 1000) \
+        and w_flip <= TOL_W_INF_FLIP
     return dict(
         u0_err=float(np.max(np.abs(u0_gpu - u0_orc)) / scale_U),
         U_err=float(np.max(np.abs(U_gpu - U_orc)) / scale_U),
         S_err=float(dS.max()) if dS.size else 0.0,
-        S_err_tumble=float(rel[fin & tumble].max()) if np.any(fin & tumble) else 0.0,
+        S_err_tumble=float(rel[both & tumble].max()) if np.any(both & tumble) else 0.0,
         n_tumble=int(np.sum(tumble)),
-        impact=_impact(last, S_gpu, fin, wl.lam),
-        first_order=float(np.max(np.abs(_first_order(last, S_gpu, fin, wl.lam)))) / scale_U,
+        impact=_impact(last, S_gpu, both, wl.lam),
+        first_order=float(np.max(np.abs(_first_order(last, S_gpu, both, wl.lam)))) / scale_U,
         impact_bound=max(1e-3, 2 * TOL_S * float(np.max(np.abs(last.S[fin & (last.w >= 1e-9)]), initial=0.0)) / wl.lam)
         if last.status == 0 else 1e-3,
-        S_inf_match=bool(np.array_equal(np.isfinite(S_gpu), fin)),
+        S_inf_match=bool(finite_ok), n_inf_flips=int(np.sum(flip)), w_inf_flips=w_flip,
         rho_err=float(abs(rho_gpu - last.rho) / max(1.0, abs(last.rho))),
         eta_rel=float(abs(eta_gpu - last.eta) / last.eta) if last.eta else 0.0,
         dU_rel=float(np.max(np.abs(dU_gpu - last.dU)) / max(1e-300, np.max(np.abs(last.dU)))),
@@ -97,7 +112,7 @@ def one_step(wl, ctrl, x0, U_before, iteration, n_iters=1):
 
 def assert_parity(m, tol_u=TOL_U, tol_s=TOL_S):
     assert m["iteration"] == m["it_next"]
-    assert m["S_inf_match"]
+    assert m["S_inf_match"], (m["n_inf_flips"], m["w_inf_flips"])
     assert m["S_err"] <= tol_s, m["S_err"]
     assert m["S_err_tumble"] <= TOL_S_TUMBLE, m["S_err_tumble"]
     assert m["impact"] <= m["impact_bound"], (m["impact"], m["impact_bound"])
