@@ -456,6 +456,8 @@ __device__ __forceinline__ void update_body(const IterArgs &a, int kc, int gcb) 
   __shared__ double acc_lds[kUpdStrips][kUpdGroups][4];
   __shared__ double red[4];
   const int chunk = a.upd_chunk, ppt = chunk / kUpdStrips;
+  // the iteration counter before the minimum's barriers (a load after a barrier waits for it)
+  const uint64_t it = *a.iter;
   // this thread's samples of the chunk (tid, tid + 256): costs in flight with the minima
   constexpr int kOwn = kUpdChunkMax / kBlock;
   double s_own[kOwn];
@@ -466,7 +468,6 @@ __device__ __forceinline__ void update_body(const IterArgs &a, int kc, int gcb) 
   }
   const double rho = global_min(a.blk_min, a.n_roll_blocks, red);
   if (kc == 0 && gcb == 0 && threadIdx.x == 0) *a.rho_out = rho;
-  const uint64_t it = *a.iter;
   {
     double wsum = 0.0;                              // this thread's weights, in order
 #pragma unroll
