@@ -40,7 +40,8 @@ METRIC = "rollout-steps/sec (K*T) and MPPI iters/sec; p50/p99 step latency batch
 # the state cost and the likelihood-ratio control terms; for example the quadrotor:
 # 130 + 24 + 80 + 24 + 428 (32 obstacles x 13 + goal) + 54 = 740.
 ALG_OPS_PER_ROLLOUT_STEP = {"cartpole": 87, "bicycle": 164, "quadrotor": 740, "linear": 90,
-                            "cartpole_swingup": 77, "quadrotor_crash": 1064}
+                            "cartpole_swingup": 77, "quadrotor_crash": 1064,
+                            "bicycle_ctg": 164}     # same arithmetic; the prefix costs are stores
 # MLP [16 -> 128 -> 128 -> 12]: 2 (16*128 + 128*128 + 128*12) FLOP per rollout-step on BF16 MFMA.
 MLP_FLOP_PER_ROLLOUT_STEP = 2 * (16 * 128 + 128 * 128 + 128 * 12)
 BF16_MFMA_PEAK_TFLOPS = 2500.0
@@ -88,6 +89,8 @@ def make_workload(name):
         return W.quadrotor(nu=2.0).replace(seed=0)
     if name == "quadrotor_crash":
         return W.quadrotor(nu=2.0, crash=True).replace(seed=0, name="quadrotor_crash")
+    if name == "bicycle_ctg":               # the bicycle under cost-to-go weighting
+        return W.bicycle().replace(seed=0, name="bicycle_ctg")
     if name == "swingup":
         return W.cartpole_swingup(nu=1000.0, K=4096).replace(seed=0)
     if name == "quadrotor_mlp":
@@ -271,7 +274,9 @@ def main():
         del src, dst
     wl = make_workload(args.workload)
     stream = torch.cuda.current_stream(dev)
-    ctrl = P.controller_for(wl, device=0, torch_stream=stream, torch_workspace=True)
+    ctg = wl.name.endswith("_ctg")
+    ctrl = P.controller_for(wl, device=0, torch_stream=stream, torch_workspace=True,
+                            **(dict(weighting=P.WEIGHT_COST_TO_GO) if ctg else {}))
     x_dev = torch.tensor(np.asarray(wl.x0, float), dtype=torch.float64, device=dev)
     spl = max(1, args.steps_per_launch)
     u_log = torch.zeros((spl, wl.m), dtype=torch.float64, device=dev)
@@ -335,7 +340,8 @@ def main():
     out = dict(metric=METRIC, value=round(value, 1), unit="rollout-steps/s", n_gpus=1, steps=args.steps,
                warmup=args.warmup, ms_per_step=round(ms_per_step, 5), higher_is_better=True, scaling="weak",
                vs_baseline=None, dtype="f32", data="synthetic",
-               config=dict(workload=f"{wl.name} K={wl.K} T={wl.T} nu={wl.nu} (1 iteration per control step)",
+               config=dict(workload=f"{wl.name} K={wl.K} T={wl.T} nu={wl.nu} (1 iteration per control step"
+                                    f"{', cost-to-go weighting' if ctg else ''})",
                            K=wl.K, T=wl.T, n=wl.n, m=wl.m, nu=wl.nu, lam=wl.lam, n_iters=1,
                            precision="FP32 rollouts, FP64 weights/normaliser/update", parallelism="single GPU"),
                mppi_iters_per_s=round(1e3 / ms_per_step, 1), roofline=roofline,
@@ -343,7 +349,8 @@ def main():
                            rollout_steps_per_s_one_launch_per_step=round(rollout_steps / (ms_per_step_single / 1e3), 1)))
     if args.serving_seconds > 0:
         out["serving"] = serving_bench(args.serving_seconds, args.plain_seconds)
-    if not args.no_cpu and wl.name != "quadrotor_mlp":
+    # (the oracle leg runs path weighting: the cost-to-go parity is in the tests)
+    if not args.no_cpu and wl.name != "quadrotor_mlp" and not ctg:
         # the CPU leg: the oracle timed on a bounded sample, and one more control step of the
         # timed controller checked against it from the same state, sequence and iteration
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)

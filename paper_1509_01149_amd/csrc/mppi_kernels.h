@@ -529,40 +529,68 @@ static __global__ __launch_bounds__(kBlock) void update_kernel(const IterArgs a)
 
 // ------------------------------------------------------ cost-to-go weighting (option)
 // Step i of sample k is weighted by its cost from step i onward, S_k - pre[i][k] (the
-// update law's S(tau_{i,k})); rho_i and eta_i are per step.
+// update law's S(tau_{i,k})): w = exp(-((S_k - pre[i][k]) - rho_i) / lambda), with rho_i
+// and eta_i per step.
 static __global__ __launch_bounds__(kBlock) void stepmin_kernel(const IterArgs a) {
   __shared__ double red[4];
   const int i = blockIdx.x;
+  const double *pre_i = a.pre + (size_t)i * a.K;
   double v = __builtin_inf();
-  for (int k = threadIdx.x; k < a.K; k += kBlock) {
-    const double s = a.S[k];
-    if (s < __builtin_inf()) v = fmin(v, s - a.pre[(size_t)i * a.K + k]);
+  // loads issued kB samples at a time, ahead of their use (one memory round trip per batch)
+  constexpr int kB = 8;
+  for (int k0 = threadIdx.x; k0 < a.K; k0 += kB * kBlock) {
+    double sv[kB], pv[kB];
+#pragma unroll
+    for (int j = 0; j < kB; ++j) {
+      const int k = k0 + j * kBlock;
+      sv[j] = k < a.K ? a.S[k] : __builtin_inf();
+      pv[j] = k < a.K ? pre_i[k] : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < kB; ++j) v = fmin(v, sv[j] < __builtin_inf() ? sv[j] - pv[j] : __builtin_inf());
   }
   v = block_min(v, red);
   if (threadIdx.x == 0) a.rho_step[i] = v;
 }
 
-__device__ __forceinline__ double ctg_weight(const IterArgs &a, double s, int i, int k) {
-  return exp(-((s - a.pre[(size_t)i * a.K + k]) - a.rho_step[i]) * a.inv_lambda);
-}
-
 static __global__ __launch_bounds__(kBlock) void update_ctg_kernel(const IterArgs a) {
   __shared__ double acc_lds[kUpdStrips][kUpdGroups][4];
   __shared__ double runs[16][kUpdGroups * 4];
-  __shared__ double red[4];
   const int kc = blockIdx.x, gcb = blockIdx.y;
   const int TM = a.T * a.m;
   const int chunk = a.upd_chunk, ppt = chunk / kUpdStrips;
   const uint64_t it = *a.iter;
   // normalisers of the steps whose first control component lies in this block's groups
+  // (at most kUpdGroups * 4 steps; their prefix costs and minima are loaded up front)
   {
+    constexpr int kMaxSteps = kUpdGroups * 4;
     const int f_lo = gcb * kUpdGroups * 4, f_hi = min(f_lo + kUpdGroups * 4, TM);
+    const int i_lo = (f_lo + a.m - 1) / a.m, n_i = (f_hi + a.m - 1) / a.m - i_lo;
     const int k = kc * chunk + threadIdx.x;
-    const double s = (int)threadIdx.x < chunk && k < a.K ? a.S[k] : __builtin_inf();
-    for (int i = (f_lo + a.m - 1) / a.m; i * a.m < f_hi; ++i) {
-      const double w = s < __builtin_inf() ? ctg_weight(a, s, i, k) : 0.0;
-      const double e = block_sum(w, red);
-      if (threadIdx.x == 0) a.eta_part[(size_t)kc * a.T + i] = e;
+    const bool in = (int)threadIdx.x < chunk && k < a.K;
+    const double s = in ? a.S[k] : __builtin_inf();
+    double tail[kMaxSteps], rho_i[kMaxSteps];
+#pragma unroll
+    for (int j = 0; j < kMaxSteps; ++j) {
+      tail[j] = in && j < n_i ? a.pre[(size_t)(i_lo + j) * a.K + k] : 0.0;
+      rho_i[j] = j < n_i ? a.rho_step[i_lo + j] : 0.0;
+    }
+    // the steps' block sums (each in block_sum's order) share one barrier; thread j
+    // writes step i_lo + j
+    __shared__ double wsum[4][kMaxSteps];
+    const int wv = threadIdx.x / kWave;
+#pragma unroll
+    for (int j = 0; j < kMaxSteps; ++j) {
+      if (j < n_i) {
+        const double w = s < __builtin_inf() ? exp(-((s - tail[j]) - rho_i[j]) * a.inv_lambda) : 0.0;
+        const double ws = wave_sum(w);
+        if ((threadIdx.x & (kWave - 1)) == 0) wsum[wv][j] = ws;
+      }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < n_i) {
+      const int j = threadIdx.x;
+      a.eta_part[(size_t)kc * a.T + i_lo + j] = (wsum[0][j] + wsum[1][j]) + (wsum[2][j] + wsum[3][j]);
     }
   }
   const int gl = threadIdx.x % kUpdGroups, strip = threadIdx.x / kUpdGroups;
@@ -571,7 +599,16 @@ static __global__ __launch_bounds__(kBlock) void update_ctg_kernel(const IterArg
   if (g < a.G) {
     for (int r = 0; r < ppt; ++r) {
       const int k = kc * chunk + strip * ppt + r;
-      const double s = k < a.K ? a.S[k] : __builtin_inf();
+      const bool in = k < a.K;
+      // the cost, and the prefix costs and minima of the group's steps, in one round trip
+      const double s = in ? a.S[k] : __builtin_inf();
+      double pc[4], rc[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int f = 4 * g + c;
+        pc[c] = in && f < TM ? a.pre[(size_t)(f / a.m) * a.K + k] : 0.0;
+        rc[c] = f < TM ? a.rho_step[f / a.m] : 0.0;
+      }
       if (s < __builtin_inf()) {
         float e[4];
         normals4((uint32_t)g, (uint32_t)k, it, a.key0, a.key1, e);
@@ -583,7 +620,7 @@ static __global__ __launch_bounds__(kBlock) void update_ctg_kernel(const IterArg
           if (f < TM) {
             const int i = f / a.m;
             if (i != last_i) {
-              w = ctg_weight(a, s, i, k);
+              w = exp(-((s - pc[c]) - rc[c]) * a.inv_lambda);
               last_i = i;
             }
             acc[c] = fma(w, (double)e[c], acc[c]);
