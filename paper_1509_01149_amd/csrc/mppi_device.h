@@ -147,6 +147,49 @@ __device__ __forceinline__ float group_excl_of_incl(float incl, int lj) {
   }
 }
 
+// FP64 forms of the group scan, exclusive scan and broadcast (each 32-bit half moved
+// with the same DPP or swizzle control; the same tree order as the FP32 forms).
+template <int Ctrl, int RowMask = 0xF>
+__device__ __forceinline__ double dpp_f64_or_zero(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), Ctrl, RowMask, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), Ctrl, RowMask, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+template <int G>
+__device__ __forceinline__ double group_scan_incl_f64(double v, int lj) {
+  if constexpr (G >= 16) {
+    static_assert(G == 16 || G == 32, "lane groups of 4, 16 or 32");
+    v += dpp_f64_or_zero<0x111>(v);                // row_shr:1
+    v += dpp_f64_or_zero<0x112>(v);                // row_shr:2
+    v += dpp_f64_or_zero<0x114>(v);                // row_shr:4
+    v += dpp_f64_or_zero<0x118>(v);                // row_shr:8
+    if constexpr (G == 32) v += dpp_f64_or_zero<0x142, 0xA>(v);   // row_bcast:15 into rows 1, 3
+  } else {
+    static_assert(G == 4, "lane groups of 4, 16 or 32");
+    const double t1 = dpp_f64_or_zero<0x111>(v);
+    v += lj >= 1 ? t1 : 0.0;
+    const double t2 = dpp_f64_or_zero<0x112>(v);
+    v += lj >= 2 ? t2 : 0.0;
+  }
+  return v;
+}
+template <int G>
+__device__ __forceinline__ double group_excl_of_incl_f64(double incl, int lj) {
+  if constexpr (G == 32) {
+    const double t = dpp_f64_or_zero<0x138>(incl);   // wave_shr:1
+    return lj >= 1 ? t : 0.0;
+  } else {
+    const double t = dpp_f64_or_zero<0x111>(incl);   // row_shr:1
+    if constexpr (G == 16) return t;
+    else return lj >= 1 ? t : 0.0;
+  }
+}
+template <int G, int J>
+__device__ __forceinline__ double group_bcast_f64(double v) {
+  return __hiloint2double(__float_as_int(group_bcast<G, J>(__int_as_float(__double2hiint(v)))),
+                          __float_as_int(group_bcast<G, J>(__int_as_float(__double2loint(v)))));
+}
+
 // Scan of affine maps x -> A x + B over each aligned group of G lanes, composed in lane
 // order (a lane's map applies after those of the lanes before it): inclusive result in
 // (A, B); lanes with no source take the identity (1, 0).

@@ -263,8 +263,9 @@ __device__ __forceinline__ void rollout_body(const IterArgs &a, const typename S
 // chain is redundant.  The per-step cost is the FP32 expression of the four-lane body;
 // each lane sums its steps in FP64 and the lanes' sums are added in a fixed tree.  Under
 // cost-to-go weighting (kRecordPrefix) the running cost before every step is recorded
-// from an in-order scan of the chunk's step costs; the path cost is the same tree sum in
-// both variants, so the two weightings see bitwise the same S.
+// by the lane owning the step, from an FP64 scan of the lanes' step costs across the
+// group; the path cost is the same tree sum in both variants, so the two weightings see
+// bitwise the same S.
 // Sum over a sample's LPS lanes; lane 0 of the group holds the fixed-order total.
 template <int LPS>
 __device__ __forceinline__ double group_sum(double v) {
@@ -400,19 +401,21 @@ __device__ __forceinline__ void rollout_body_split(const IterArgs &a, const type
       }
     }
     if constexpr ((Mode & kRecordPrefix) != 0) {
-      // cost-to-go weighting: the running cost before each step of the chunk, in step order
-      StaticFor<0, LPS>::run([&](auto jc) {
-        constexpr int JJ = decltype(jc)::value;
+      // cost-to-go weighting: the running cost before each of this lane's steps (the
+      // running total, the lanes before this one by an FP64 scan across the group, this
+      // lane's earlier steps), written by the lane that owns the step
+      double own = 0.0;
 #pragma unroll
-        for (int s = 0; s < SPG; ++s) {
-          const int i = (g0 + JJ) * SPG + s;
-          const float c = group_bcast<LPS, JJ>(qt[s]);
-          if (i < a.T) {
-            if (lane_j == 0 && k < a.K) a.pre[(size_t)i * a.K + k] = P;
-            P += (double)c;
-          }
-        }
-      });
+      for (int s = 0; s < SPG; ++s) own += (double)qt[s];   // 0 past the horizon
+      const double incl = group_scan_incl_f64<LPS>(own, lane_j);
+      double r = P + group_excl_of_incl_f64<LPS>(incl, lane_j);
+#pragma unroll
+      for (int s = 0; s < SPG; ++s) {
+        const int i = g * SPG + s;
+        if (i < a.T && k < a.K) a.pre[(size_t)i * a.K + k] = r;
+        r += (double)qt[s];
+      }
+      P += group_bcast_f64<LPS, LPS - 1>(incl);
     }
   }
   double S = group_sum<LPS>(Sp) + (double)Sys::phi(p, x);
