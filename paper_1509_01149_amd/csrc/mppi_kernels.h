@@ -557,18 +557,24 @@ static __global__ __launch_bounds__(kBlock) void stepmin_kernel(const IterArgs a
 }
 
 static __global__ __launch_bounds__(kBlock) void update_ctg_kernel(const IterArgs a) {
+  // The chunk has at most kBlock samples under cost-to-go weighting (one per thread), and
+  // m is 1, 2 or 4, so the steps of this block's groups are exactly the steps whose first
+  // component lies in them: their weights are computed once, for the normalisers, and
+  // kept in LDS for the accumulation.
+  constexpr int kMaxSteps = kUpdGroups * 4;
   __shared__ double acc_lds[kUpdStrips][kUpdGroups][4];
   __shared__ double runs[16][kUpdGroups * 4];
+  __shared__ double w_lds[kBlock][kMaxSteps + 1];
+  __shared__ double s_lds[kBlock];
+  __shared__ double wsum[4][kMaxSteps];
   const int kc = blockIdx.x, gcb = blockIdx.y;
   const int TM = a.T * a.m;
   const int chunk = a.upd_chunk, ppt = chunk / kUpdStrips;
   const uint64_t it = *a.iter;
-  // normalisers of the steps whose first control component lies in this block's groups
-  // (at most kUpdGroups * 4 steps; their prefix costs and minima are loaded up front)
+  const int f_lo = gcb * kUpdGroups * 4, f_hi = min(f_lo + kUpdGroups * 4, TM);
+  const int i_lo = (f_lo + a.m - 1) / a.m, n_i = (f_hi + a.m - 1) / a.m - i_lo;
+  // weights and normalisers of those steps (prefix costs and minima loaded up front)
   {
-    constexpr int kMaxSteps = kUpdGroups * 4;
-    const int f_lo = gcb * kUpdGroups * 4, f_hi = min(f_lo + kUpdGroups * 4, TM);
-    const int i_lo = (f_lo + a.m - 1) / a.m, n_i = (f_hi + a.m - 1) / a.m - i_lo;
     const int k = kc * chunk + threadIdx.x;
     const bool in = (int)threadIdx.x < chunk && k < a.K;
     const double s = in ? a.S[k] : __builtin_inf();
@@ -578,14 +584,15 @@ static __global__ __launch_bounds__(kBlock) void update_ctg_kernel(const IterArg
       tail[j] = in && j < n_i ? a.pre[(size_t)(i_lo + j) * a.K + k] : 0.0;
       rho_i[j] = j < n_i ? a.rho_step[i_lo + j] : 0.0;
     }
+    s_lds[threadIdx.x] = s;
     // the steps' block sums (each in block_sum's order) share one barrier; thread j
     // writes step i_lo + j
-    __shared__ double wsum[4][kMaxSteps];
     const int wv = threadIdx.x / kWave;
 #pragma unroll
     for (int j = 0; j < kMaxSteps; ++j) {
       if (j < n_i) {
         const double w = s < __builtin_inf() ? exp(-((s - tail[j]) - rho_i[j]) * a.inv_lambda) : 0.0;
+        w_lds[threadIdx.x][j] = w;
         const double ws = wave_sum(w);
         if ((threadIdx.x & (kWave - 1)) == 0) wsum[wv][j] = ws;
       }
@@ -601,33 +608,14 @@ static __global__ __launch_bounds__(kBlock) void update_ctg_kernel(const IterArg
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   if (g < a.G) {
     for (int r = 0; r < ppt; ++r) {
-      const int k = kc * chunk + strip * ppt + r;
-      const bool in = k < a.K;
-      // the cost, and the prefix costs and minima of the group's steps, in one round trip
-      const double s = in ? a.S[k] : __builtin_inf();
-      double pc[4], rc[4];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const int f = 4 * g + c;
-        pc[c] = in && f < TM ? a.pre[(size_t)(f / a.m) * a.K + k] : 0.0;
-        rc[c] = f < TM ? a.rho_step[f / a.m] : 0.0;
-      }
-      if (s < __builtin_inf()) {
+      const int kl = strip * ppt + r;
+      if (s_lds[kl] < __builtin_inf()) {
         float e[4];
-        normals4((uint32_t)g, (uint32_t)k, it, a.key0, a.key1, e);
-        int last_i = -1;
-        double w = 0.0;
+        normals4((uint32_t)g, (uint32_t)(kc * chunk + kl), it, a.key0, a.key1, e);
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
           const int f = 4 * g + c;
-          if (f < TM) {
-            const int i = f / a.m;
-            if (i != last_i) {
-              w = exp(-((s - pc[c]) - rc[c]) * a.inv_lambda);
-              last_i = i;
-            }
-            acc[c] = fma(w, (double)e[c], acc[c]);
-          }
+          if (f < TM) acc[c] = fma(w_lds[kl][f / a.m - i_lo], (double)e[c], acc[c]);
         }
       }
     }
