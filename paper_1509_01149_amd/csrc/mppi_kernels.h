@@ -540,7 +540,7 @@ static __global__ __launch_bounds__(kBlock) void stepmin_kernel(const IterArgs a
   const double *pre_i = a.pre + (size_t)i * a.K;
   double v = __builtin_inf();
   // loads issued kB samples at a time, ahead of their use (one memory round trip per batch)
-  constexpr int kB = 8;
+  constexpr int kB = 16;
   for (int k0 = threadIdx.x; k0 < a.K; k0 += kB * kBlock) {
     double sv[kB], pv[kB];
 #pragma unroll
