@@ -26,10 +26,11 @@ constexpr uint32_t kPhiloxW1 = 0xBB67AE85u;
 __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
-    const uint32_t lo0 = c.x * kPhiloxM0;
-    const uint32_t hi0 = __umulhi(c.x, kPhiloxM0);
-    const uint32_t lo1 = c.z * kPhiloxM1;
-    const uint32_t hi1 = __umulhi(c.z, kPhiloxM1);
+    // each 32 x 32 -> 64-bit product as one v_mad_u64_u32 (a mul_lo / mul_hi pair otherwise)
+    const uint64_t p0 = (uint64_t)c.x * kPhiloxM0;
+    const uint64_t p1 = (uint64_t)c.z * kPhiloxM1;
+    const uint32_t lo0 = (uint32_t)p0, hi0 = (uint32_t)(p0 >> 32);
+    const uint32_t lo1 = (uint32_t)p1, hi1 = (uint32_t)(p1 >> 32);
     c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
     k0 += kPhiloxW0;
     k1 += kPhiloxW1;
