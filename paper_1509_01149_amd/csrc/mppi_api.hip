@@ -386,6 +386,12 @@ static size_t rollout_lds_bytes(const mppi_ctx *c) {
 // quadrotor's crash indicator when its crash_cost is positive.
 static int rollout_mode(const mppi_ctx *c) {
   int mode = c->cfg.weighting == MPPI_WEIGHT_COST_TO_GO ? kRecordPrefix : 0;
+  const int m = c->cfg.n_ctrl;
+  bool diag = true;                                 // the FP32 copies the kernels use
+  for (int r = 0; r < m; ++r)
+    for (int j = 0; j < m; ++j)
+      if (r != j && ((float)c->Ls[r * m + j] != 0.f || (float)c->Mq[r * m + j] != 0.f)) diag = false;
+  if (diag) mode |= kDiagLR;
   if (rollout_split(&c->cfg)) return mode | kStepSplit;
   if (c->cfg.system == MPPI_SYS_QUADROTOR && c->quad.crash > 0.f) mode |= kCrashOn;
   return mode;
@@ -409,16 +415,24 @@ static const void *rollout_split_fn(int lps) {
   return nullptr;
 }
 
+// kDiagL: 0 or kDiagLR, the same for every variant the mode maps to
+template <class Sys, int kDiagL>
+static const void *rollout_fn_for_base(int mode, int lps) {
+  if (mode == (kStepSplit | kDiagL)) return rollout_split_fn<Sys, kStepSplit | kDiagL>(lps);
+  if (mode == (kStepSplit | kRecordPrefix | kDiagL)) return rollout_split_fn<Sys, kStepSplit | kRecordPrefix | kDiagL>(lps);
+  switch (mode) {
+    case kDiagL: return rollout_fn<Sys, kDiagL>();
+    case kRecordPrefix | kDiagL: return rollout_fn<Sys, kRecordPrefix | kDiagL>();
+    case kCrashOn | kDiagL: return rollout_fn<Sys, kCrashOn | kDiagL>();
+    case kRecordPrefix | kCrashOn | kDiagL: return rollout_fn<Sys, kRecordPrefix | kCrashOn | kDiagL>();
+    default: return nullptr;
+  }
+}
+
 template <class Sys>
 static const void *rollout_fn_for(int mode, int lps) {
-  if (mode == kStepSplit) return rollout_split_fn<Sys, kStepSplit>(lps);
-  if (mode == (kStepSplit | kRecordPrefix)) return rollout_split_fn<Sys, kStepSplit | kRecordPrefix>(lps);
-  switch (mode) {
-    case 0: return rollout_fn<Sys, 0>();
-    case kRecordPrefix: return rollout_fn<Sys, kRecordPrefix>();
-    case kCrashOn: return rollout_fn<Sys, kCrashOn>();
-    default: return rollout_fn<Sys, kRecordPrefix | kCrashOn>();
-  }
+  if (mode & kDiagLR) return rollout_fn_for_base<Sys, kDiagLR>(mode, lps);
+  return rollout_fn_for_base<Sys, 0>(mode, lps);
 }
 
 static hipEvent_t take_event(mppi_ctx *c) {

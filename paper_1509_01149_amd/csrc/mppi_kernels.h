@@ -86,7 +86,10 @@ __device__ __forceinline__ float quad_sum(float v) {
 // kCrash applies the system's crash indicator (systems with Sys::kCrash only);
 // kStepSplit selects the step-split body below (systems with Sys::kStepSplit; with
 // kRecordPrefix or alone).
-enum { kRecordPrefix = 1, kCrashOn = 2, kStepSplit = 4 };
+// kDiagLR: Ls and Mq are diagonal, so the noise and likelihood-ratio products keep their
+// diagonal terms only -- the general FMA chains add exact zeros to them, so both forms give
+// the same values bit for bit.
+enum { kRecordPrefix = 1, kCrashOn = 2, kStepSplit = 4, kDiagLR = 8 };
 
 // One horizon step of one sample from the four normals `e` of its noise group.
 template <class Sys, int LPS, int Mode>
@@ -101,8 +104,12 @@ __device__ __forceinline__ void rollout_step(const IterArgs &a, const typename S
 #pragma unroll
   for (int j = 0; j < M; ++j) {
     float t = 0.f;
+    if constexpr ((Mode & kDiagLR) != 0) {
+      t = fmaf(a.Ls[j * M + j], e[s * M + j], 0.f);
+    } else {
 #pragma unroll
-    for (int l = 0; l <= j; ++l) t += a.Ls[j * M + l] * e[s * M + l];
+      for (int l = 0; l <= j; ++l) t += a.Ls[j * M + l] * e[s * M + l];
+    }
     du[j] = t;
     v[j] = sU[i * M + j] + t;
   }
@@ -124,16 +131,24 @@ __device__ __forceinline__ void rollout_step(const IterArgs &a, const typename S
   if constexpr (kSplitLR) {
     const float duj = lane_j == 0 ? du[0] : (lane_j == 1 ? du[1] : (lane_j == 2 ? du[2] : du[3]));
     float t = 0.f;
+    if constexpr ((Mode & kDiagLR) != 0) {
+      t = fmaf(mrow[4], duj, 0.f);                   // mrow[4]: this lane's diagonal entry
+    } else {
 #pragma unroll
-    for (int j = 0; j < M; ++j) t += mrow[j] * du[j];
+      for (int j = 0; j < M; ++j) t += mrow[j] * du[j];
+    }
     const float c0 = sC[i];                          // every lane reads it; lane 0 adds it
     lr_in = duj * t + sRU[i * M + lane_j] * duj + (lane_j == 0 ? c0 : 0.f);
   } else {
 #pragma unroll
     for (int r = 0; r < M; ++r) {
       float t = 0.f;
+      if constexpr ((Mode & kDiagLR) != 0) {
+        t = fmaf(a.Mq[r * M + r], du[r], 0.f);
+      } else {
 #pragma unroll
-      for (int j = 0; j < M; ++j) t += a.Mq[r * M + j] * du[j];
+        for (int j = 0; j < M; ++j) t += a.Mq[r * M + j] * du[j];
+      }
       quad += du[r] * t;
       lin += sRU[i * M + r] * du[r];
     }
@@ -203,11 +218,12 @@ __device__ __forceinline__ void rollout_body(const IterArgs &a, const typename S
   const int lane_j = threadIdx.x % LPS;
   typename Sys::Regs rg;                            // per-lane register copy of system data
   Sys::load_regs(p, sv, lane_j, LPS, rg);
-  float mrow[4] = {0.f, 0.f, 0.f, 0.f};             // row lane_j of Mq (split control terms)
+  float mrow[5] = {0.f, 0.f, 0.f, 0.f, 0.f};        // row lane_j of Mq, then its diagonal entry
   if constexpr (LPS == 4 && M == 4) {
 #pragma unroll
     for (int l = 0; l < 4; ++l)
       mrow[l] = lane_j == 0 ? a.Mq[l] : (lane_j == 1 ? a.Mq[4 + l] : (lane_j == 2 ? a.Mq[8 + l] : a.Mq[12 + l]));
+    mrow[4] = lane_j == 0 ? mrow[0] : (lane_j == 1 ? mrow[1] : (lane_j == 2 ? mrow[2] : mrow[3]));
   }
   const int k = blk * (kBlock / LPS) + threadIdx.x / LPS;
   double S = 0.0;
@@ -333,16 +349,24 @@ __device__ __forceinline__ void rollout_body_split(const IterArgs &a, const type
 #pragma unroll
       for (int j = 0; j < M; ++j) {
         float t = 0.f;
+        if constexpr ((Mode & kDiagLR) != 0) {
+          t = fmaf(a.Ls[j * M + j], e[s * M + j], 0.f);
+        } else {
 #pragma unroll
-        for (int l = 0; l <= j; ++l) t += a.Ls[j * M + l] * e[s * M + l];
+          for (int l = 0; l <= j; ++l) t += a.Ls[j * M + l] * e[s * M + l];
+        }
         du[s * M + j] = t;
       }
       float quad = 0.f, lin = 0.f;
 #pragma unroll
       for (int r = 0; r < M; ++r) {
         float t = 0.f;
+        if constexpr ((Mode & kDiagLR) != 0) {
+          t = fmaf(a.Mq[r * M + r], du[s * M + r], 0.f);
+        } else {
 #pragma unroll
-        for (int j = 0; j < M; ++j) t += a.Mq[r * M + j] * du[s * M + j];
+          for (int j = 0; j < M; ++j) t += a.Mq[r * M + j] * du[s * M + j];
+        }
         quad += du[s * M + r] * t;
         lin += sRU[ic * M + r] * du[s * M + r];
       }
