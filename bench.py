@@ -9,15 +9,19 @@ launch sequence (one captured graph; --steps-per-launch), which removes the gap 
 runtime leaves between consecutive graph launches; `value` is rollout-steps per second
 (K * T * iterations / wall time).  The rate with one launch per control step (what a
 loop that waits for each external state measurement sees) is reported beside it.
+Every graph shape the timed region launches is captured during the warm-up.
 
-Default workload: the kinematic bicycle on a 256 x 256 cost map, K = 4096, T = 100,
-nu = 2.  Other single-GPU workloads can be chosen with --workload.
+Default workload: the quadrotor with 32 spherical obstacles, K = 16384, T = 150, nu = 2
+(the largest single-GPU configuration).  Other workloads can be chosen with --workload;
+the bicycle (K = 4096, T = 100) is also timed as a secondary line (`bicycle`).
 
-The JSON line also carries the dominant kernel's roofline (its mean duration from
-HIP events recorded on the library's own stream during a profiled pass of the same
-length), the serving legs (a Poisson trace at 50 Hz per controller and a saturated
-burst, batched against one controller at a time) and the CPU leg: the oracle's
-throughput on a bounded sample of the same workload, plus one control step of the
+The JSON line also carries the dominant kernel's roofline (algorithmic FLOP per launch
+over its mean duration from HIP events recorded on the library's own stream during a
+profiled pass of the same length), the learned-dynamics training rate, the serving legs
+(a Poisson trace at 50 Hz per controller and a saturated burst, batched against one
+controller at a time) and the CPU leg: the oracle's throughput on a bounded sample of the
+same workload on one host core and with the samples sharded over the host's cores (the
+shards' partial sums combined by the oracle's exact merge), plus one control step of the
 timed controller checked against the oracle.  Only the CPU leg touches the oracle.
 """
 import argparse
@@ -33,36 +37,55 @@ sys.path.insert(0, ROOT)
 
 METRIC = "rollout-steps/sec (K*T) and MPPI iters/sec; p50/p99 step latency batched vs plain"
 
-# Algorithmic operations per rollout-step of the rollout kernel (FMA = 2, every other
-# FP32/FP64 arithmetic op, transcendental and Philox integer op = 1), counted per part:
-# noise (a quarter of a Philox4x32-10 call with its uniforms and Box-Muller per control,
-# about 130 ops per call), du = A L eps and v = u + du, the dynamics, the Euler update,
-# the state cost and the likelihood-ratio control terms; for example the quadrotor:
-# 130 + 24 + 80 + 24 + 428 (32 obstacles x 13 + goal) + 54 = 740.
-ALG_OPS_PER_ROLLOUT_STEP = {"cartpole": 87, "bicycle": 164, "quadrotor": 740, "linear": 90,
-                            "cartpole_swingup": 77, "quadrotor_crash": 1064,
-                            "bicycle_ctg": 164}     # same arithmetic; the prefix costs are stores
-# MLP [16 -> 128 -> 128 -> 12]: 2 (16*128 + 128*128 + 128*12) FLOP per rollout-step on BF16 MFMA.
+# Algorithmic FLOP per rollout-step (FMA = 2; the transcendentals and the noise
+# generator's integer work are not counted): the dynamics and state cost of one Euler
+# step plus 5 m for the likelihood-ratio control terms of q-tilde, as in the survey's
+# hand counts.  Quadrotor: about 480 for dynamics and cost, of which the 32 obstacle
+# barriers take about 350, plus 20 -> 500.  Bicycle 45 + 10, cart-pole 40 + 5.  The
+# swing-up cart-pole: 27 + 5.  The crash indicator adds one comparison per obstacle and
+# the ground test and crash cost (500 + 34).
+ALG_FLOP_PER_ROLLOUT_STEP = {"quadrotor": 500, "quadrotor_crash": 534, "bicycle": 55, "bicycle_ctg": 55,
+                             "cartpole": 45, "cartpole_swingup": 32, "linear": 25}
+# Operations per rollout-step including the noise generator (a Philox4x32-10 call with its
+# uniforms and Box-Muller is about 130 integer and FP32 ops per four normals), du = A L eps
+# and v = u + du: what the kernel must issue whatever the arithmetic counts as FLOP.
+# Quadrotor: 130 + 24 + 80 + 24 + 428 (32 obstacles x 13 + goal) + 54 = 740.
+ISSUE_OPS_PER_ROLLOUT_STEP = {"cartpole": 87, "bicycle": 164, "quadrotor": 740, "linear": 90,
+                              "cartpole_swingup": 77, "quadrotor_crash": 1064, "bicycle_ctg": 164}
+# MLP [16 -> 128 -> 128 -> 12]: 2 (16*128 + 128*128 + 128*12) FLOP per rollout-step on BF16 MFMA;
+# training: forward + two backward products per sample, three times that.
 MLP_FLOP_PER_ROLLOUT_STEP = 2 * (16 * 128 + 128 * 128 + 128 * 12)
+MLP_TRAIN_FLOP_PER_SAMPLE = 3 * MLP_FLOP_PER_ROLLOUT_STEP
 BF16_MFMA_PEAK_TFLOPS = 2500.0
 
-# VALU peak without packed FP32 (the build forbids v_pk_*_f32): 256 CUs x 4 SIMD x 16 lanes
-# x 2 (FMA) x 2.4 GHz.
+# Published FP32 vector peak (counts packed FP32, two FMAs per lane per cycle); the build
+# forbids packed FP32 (v_pk_*_f32), so its own issue ceiling is half of it:
+# 256 CUs x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz.
+FP32_PEAK_TFLOPS = 157.3
 ALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
-PUBLISHED_FP32_TFLOPS = 157.3
 
 
+# Committed rocprofv3 counter summaries: HBM traffic (FETCH_SIZE / WRITE_SIZE) and the SQ
+# instruction mix of the rollout kernel, keyed by workload.
 TRAFFIC_FILES = {"bicycle": "traffic_rollout_bicycle_K4096_T100.md",
                  "quadrotor": "traffic_rollout_quadrotor_K16384_T150.md"}
+SQ_FILES = {"bicycle": "sq_rollout_bicycle_K4096_T100.md",
+            "quadrotor": "sq_rollout_quadrotor_K16384_T150.md"}
 ROLLOUT_SOURCES = ["mppi_device.h", "mppi_systems.h", "mppi_kernels.h"]
 
 
-def measured_traffic(name):
-    """HBM bytes per rollout launch from the committed rocprofv3 counter summary (FETCH_SIZE and
-    WRITE_SIZE, each divided by its factor on a known-size copy), or None when there is none or
-    the rollout kernel's sources have changed since the counters were taken."""
+def rollout_source_hash():
     import hashlib
-    fn = TRAFFIC_FILES.get(name)
+    h = hashlib.sha256()
+    for f in ROLLOUT_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_1509_01149_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
+
+
+def profile_record(files, name):
+    """The machine-readable "key: value" lines of a committed counter summary, or None when
+    there is none or the rollout kernel's sources have changed since the counters were taken."""
+    fn = files.get(name)
     path = os.path.join(ROOT, "profiles", fn) if fn else None
     if not path or not os.path.exists(path):
         return None
@@ -71,12 +94,23 @@ def measured_traffic(name):
         if ":" in line and not line.startswith(("|", "#", " ", "`")):
             k, v = line.split(":", 1)
             rec[k.strip()] = v.strip()
-    h = hashlib.sha256()
-    for f in ROLLOUT_SOURCES:
-        h.update(open(os.path.join(ROOT, "paper_1509_01149_amd", "csrc", f), "rb").read())
-    if rec.get("kernel_source_sha256") != h.hexdigest():
+    if rec.get("kernel_source_sha256") != rollout_source_hash():
         return None
-    return int(rec["traffic_bytes_per_launch"])
+    return rec
+
+
+def measured_traffic(name):
+    """HBM bytes per rollout launch (FETCH_SIZE and WRITE_SIZE, each divided by its factor on a
+    known-size copy), or None."""
+    rec = profile_record(TRAFFIC_FILES, name)
+    return int(rec["traffic_bytes_per_launch"]) if rec else None
+
+
+def valu_issue_share(name):
+    """Share of the rollout waves' lifetime their SIMD spends issuing their VALU instructions
+    (SQ_INSTS_VALU / SQ_WAVE_CYCLES per wave, both in quad-cycles), or None."""
+    rec = profile_record(SQ_FILES, name)
+    return float(rec["valu_issue_share"]) if rec and "valu_issue_share" in rec else None
 
 
 def make_workload(name):
@@ -93,8 +127,6 @@ def make_workload(name):
         return W.bicycle().replace(seed=0, name="bicycle_ctg")
     if name == "swingup":
         return W.cartpole_swingup(nu=1000.0, K=4096).replace(seed=0)
-    if name == "quadrotor_mlp":
-        return W.quadrotor_mlp(trained_mlp(), nu=2.0, K=16384, T=100).replace(seed=0)
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -110,6 +142,8 @@ def trained_mlp(n=1_000_000, epochs=20):
     for ep, order in enumerate(W.minibatch_order(n, epochs)):
         losses = g.train(order, 4096, 2e-3 * 0.5 ** (ep // 5))
     g.train_seconds = time.perf_counter() - t0
+    g.train_samples = n * epochs
+    g.train_epochs = epochs
     g.final_loss = float(losses.mean())
     return g
 
@@ -128,42 +162,43 @@ def serving_mix_workloads(n_controllers):
     return out
 
 
-def serving_bench(seconds, plain_seconds, n_controllers=256, rate_hz=50.0, inflight=3, saturate_requests=8):
+def serving_bench(seconds, plain_seconds, n_controllers=256, rate_hz=50.0, inflight=3, saturate_requests=8,
+                  warm_seconds=1.0):
     """Replay the same Poisson trace (rate_hz per controller) through the batched server
-    and through the plain one-controller-at-a-time policy; report latency percentiles and
-    aggregate rollout-steps/s."""
+    and through the plain one-controller-at-a-time policy: the first warm_seconds of the
+    trace warm the server up and are not measured; report latency percentiles and the
+    aggregate rollout-steps/s of the requests that arrive in the measured window."""
     import workloads as W
     import paper_1509_01149_amd as P
     wls = serving_mix_workloads(n_controllers)
-    trace = W.poisson_arrivals(n_controllers, rate_hz, max(seconds, plain_seconds))
+    trace = W.poisson_arrivals(n_controllers, rate_hz, warm_seconds + max(seconds, plain_seconds))
     res = dict(controllers=n_controllers, rate_hz_per_controller=rate_hz,
                offered_requests_per_s=n_controllers * rate_hz,
-               offered_rollout_steps_per_s=rate_hz * sum(w.K * w.T for w in wls))
+               offered_rollout_steps_per_s=rate_hz * sum(w.K * w.T for w in wls), warmup_seconds=warm_seconds)
     for mode, dur in (("batched", seconds), ("plain", plain_seconds)):
         if dur <= 0:
             continue
-        ev = [(t, c) for t, c in trace if t < dur]
+        ev = [(t, c) for t, c in trace if t < warm_seconds + dur]
         t = np.array([a for a, _ in ev])
         ci = np.array([c for _, c in ev])
         kw = dict(max_slots=n_controllers, max_inflight=inflight, max_batch=n_controllers,
                   mode=P.SERVE_BATCHED if mode == "batched" else P.SERVE_PLAIN, hbm_budget_bytes=64 << 30)
         with P.Server(**kw) as srv:
             slots = np.array([srv.admit(**P.controller_args(wl)) for wl in wls])
-            # warm up: one request per controller, not timed
-            srv.replay(np.zeros(n_controllers), slots, [np.pad(w.x0, (0, 16 - w.n)) for w in wls])
             st0 = srv.stats()
             x0s = [np.pad(wls[c].x0, (0, 16 - wls[c].n)) for c in ci]
             td, u0, status = srv.replay(t, slots[ci], x0s)
             st1 = srv.stats()
-        lat = (td - t) * 1e3
-        span = float(td.max())
-        steps = float(sum(wls[c].K * wls[c].T for c in ci))
-        res[mode] = dict(trace_seconds=dur, requests=int(t.size), p50_ms=round(float(np.percentile(lat, 50)), 3),
+        meas = t >= warm_seconds
+        lat = (td[meas] - t[meas]) * 1e3
+        span = float(td[meas].max()) - warm_seconds
+        steps = float(sum(wls[c].K * wls[c].T for c in ci[meas]))
+        res[mode] = dict(trace_seconds=dur, requests=int(meas.sum()), p50_ms=round(float(np.percentile(lat, 50)), 3),
                          p99_ms=round(float(np.percentile(lat, 99)), 3), max_ms=round(float(lat.max()), 3),
                          mean_ms=round(float(lat.mean()), 3), completion_span_s=round(span, 3),
-                         rollout_steps_per_s=round(steps / span, 1), requests_per_s=round(t.size / span, 1),
-                         mean_batch=round((st1["batches"] and (st1["requests_done"] - st0["requests_done"]) /
-                                           max(1, st1["batches"] - st0["batches"])), 2),
+                         rollout_steps_per_s=round(steps / span, 1), requests_per_s=round(meas.sum() / span, 1),
+                         mean_batch=round((st1["requests_done"] - st0["requests_done"]) /
+                                          max(1, st1["batches"] - st0["batches"]), 2),
                          numeric_failures=int(np.sum(status != 0)))
     if saturate_requests > 0:
         res["saturated"] = saturation_bench(wls, saturate_requests, inflight)
@@ -179,7 +214,7 @@ def saturation_bench(wls, per_controller, inflight):
     ci = np.tile(np.arange(n), per_controller)
     t = np.zeros(ci.size)
     steps = float(sum(wls[c].K * wls[c].T for c in ci))
-    ops = float(sum(ALG_OPS_PER_ROLLOUT_STEP[wls[c].name] * wls[c].K * wls[c].T for c in ci))
+    flop = float(sum(ALG_FLOP_PER_ROLLOUT_STEP[wls[c].name] * wls[c].K * wls[c].T for c in ci))
     out = dict(requests_per_controller=per_controller, requests=int(ci.size))
     for mode in ("batched", "plain"):
         kw = dict(max_slots=n, max_inflight=inflight, max_batch=n,
@@ -193,8 +228,8 @@ def saturation_bench(wls, per_controller, inflight):
         span = float(td.max())
         out[mode] = dict(completion_span_s=round(span, 4), requests_per_s=round(ci.size / span, 1),
                          rollout_steps_per_s=round(steps / span, 1),
-                         rollout_alg_tflops=round(ops / span / 1e12, 3),
-                         frac_of_alu_peak=round(ops / span / 1e12 / ALU_PEAK_TFLOPS, 4),
+                         rollout_alg_tflops=round(flop / span / 1e12, 3),
+                         frac_of_fp32_peak=round(flop / span / 1e12 / FP32_PEAK_TFLOPS, 4),
                          mean_batch=round((st1["requests_done"] - st0["requests_done"]) /
                                           max(1, st1["batches"] - st0["batches"]), 2),
                          numeric_failures=int(np.sum(status != 0)))
@@ -203,21 +238,93 @@ def saturation_bench(wls, per_controller, inflight):
 
 
 def cpu_baseline(wl, seconds):
-    """The FP64 oracle, as it stands, on a bounded closed-loop sample of the workload."""
+    """The FP64 oracle, as it stands, on a bounded closed-loop sample of the workload, on one
+    host thread (BLAS pools limited to one thread)."""
+    from threadpoolctl import threadpool_limits
     from oracle import mppi
+    x = np.asarray(wl.x0, float).copy()
+    U = mppi.initial_sequence(wl)
+    it = 0
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        while True:
+            u0, U, it, _ = mppi.control_step(wl, x, U, it)
+            x = mppi.plant_step(wl, x, u0)
+            el = time.perf_counter() - t0
+            if el >= seconds:
+                break
+    return dict(value=wl.K * wl.T * it / el, unit="rollout-steps/s", cores=1, kind="oracle",
+                sample=f"{it} closed-loop control steps of the same workload (K={wl.K}, T={wl.T}), "
+                       f"{el:.1f} s, NumPy FP64 on one host thread")
+
+
+# Sharded oracle (the CPU leg on all host cores).  Each worker process holds the workload
+# and, per control step, rolls out its contiguous range of samples (their noise keyed by the
+# global sample index, as the one-process oracle draws it) and returns its shard's partial
+# sums (rho_g, eta_g, N_g); the parent combines them with the oracle's exact merge.
+_SHARD_WL = None
+
+
+def _shard_init(wl):
+    global _SHARD_WL
+    _SHARD_WL = wl
+    from threadpoolctl import threadpool_limits
+    threadpool_limits(1)
+
+
+def _shard_partials(args):
+    from oracle import mppi, systems
+    from oracle.noise import control_noise
+    x, U, it, k0, k1 = args
+    wl = _SHARD_WL
+    du = control_noise(wl.seed, it, k1 - k0, wl.T, wl.sigma, wl.nu, k_offset=k0)
+    S = mppi.rollout_costs(systems.make(wl), x, U, du, wl.dt, np.asarray(wl.R, float), wl.nu)
+    rho = float(np.min(S))
+    if not np.isfinite(rho):
+        return rho, 0.0, np.zeros((wl.T, wl.m))
+    e = np.exp(-(S - rho) / wl.lam)
+    return rho, float(np.sum(e)), np.einsum("k,ktj->tj", e, du)
+
+
+def host_cores():
+    """Cores this process may use, at most 16 (the host share of one GPU)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
+
+
+def start_shard_pool(wl, cores):
+    """Worker processes for the sharded oracle, forked before this process touches the GPU."""
+    import multiprocessing as mp
+    return mp.get_context("fork").Pool(cores, initializer=_shard_init, initargs=(wl,))
+
+
+def cpu_baseline_sharded(pool, wl, cores, seconds):
+    """The oracle on `cores` processes: the K samples split into one contiguous range per
+    process, merged exactly (the sample-independent factors of the update law cancel, so each
+    shard's sums are rescaled by exp(-(rho_g - rho) / lambda)); closed loop as on one core."""
+    from oracle import mppi
+    bounds = np.linspace(0, wl.K, cores + 1).astype(int)
     x = np.asarray(wl.x0, float).copy()
     U = mppi.initial_sequence(wl)
     it = 0
     t0 = time.perf_counter()
     while True:
-        u0, U, it, _ = mppi.control_step(wl, x, U, it)
+        parts = pool.map(_shard_partials, [(x, U, it, int(bounds[g]), int(bounds[g + 1])) for g in range(cores)])
+        U = U + mppi.merge_shards(parts, wl.lam)
+        u0 = U[0].copy()
+        U = mppi.shift(U, wl.u_init)
+        it += 1
         x = mppi.plant_step(wl, x, u0)
         el = time.perf_counter() - t0
         if el >= seconds:
             break
-    return dict(value=wl.K * wl.T * it / el, unit="rollout-steps/s", cores=1, kind="oracle",
+    return dict(value=wl.K * wl.T * it / el, unit="rollout-steps/s", cores=cores, kind="oracle",
                 sample=f"{it} closed-loop control steps of the same workload (K={wl.K}, T={wl.T}), "
-                       f"{el:.1f} s, NumPy FP64 on one host thread")
+                       f"{el:.1f} s, NumPy FP64, samples sharded over {cores} processes, partial sums "
+                       f"merged exactly")
 
 
 def parity_spot_check(wl, ctrl, x):
@@ -234,51 +341,15 @@ def parity_spot_check(wl, ctrl, x):
                 tolerance=1e-4, at_iteration=it)
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=300)
-    ap.add_argument("--steps-per-launch", type=int, default=10,
-                    help="closed-loop steps per launch sequence (captured graph); 1 = one launch per step")
-    ap.add_argument("--warmup", type=int, default=30)
-    ap.add_argument("--workload", default="bicycle")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-parity", action="store_true")
-    ap.add_argument("--serving-seconds", type=float, default=2.0,
-                    help="length of the batched serving trace (0 disables the serving leg)")
-    ap.add_argument("--copy-calibration", type=int, default=0,
-                    help="first run one plain device copy of this many bytes (a known-size kernel for "
-                         "calibrating HBM byte counters in a profiler pass)")
-    ap.add_argument("--plain-seconds", type=float, default=1.0,
-                    help="length of the same trace replayed one controller at a time")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU only: the MPPI path shards over samples with one small "
-              f"exchange per iteration, which is designed but not built; --gpus {args.gpus} is not supported.",
-              file=sys.stderr)
-        sys.exit(2)
-
-    import torch
-    import paper_1509_01149_amd as P
-    P.load()
-    if not torch.cuda.is_available():
-        raise SystemExit("no GPU visible: bench.py runs the HIP path only")
+def time_controller(P, torch, wl, steps, warmup, spl, weighting=0):
+    """Time `steps` closed-loop control steps of workload wl on the device, `spl` per launch
+    sequence, then the same with one launch per step, then one profiled pass of the same
+    length (per-kernel HIP events on the library's stream).  Every graph shape the timed
+    passes launch is captured during the warm-up."""
     dev = torch.device("cuda:0")
-    if args.copy_calibration > 0:
-        src = torch.ones(args.copy_calibration // 4, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-    wl = make_workload(args.workload)
     stream = torch.cuda.current_stream(dev)
-    ctg = wl.name.endswith("_ctg")
-    ctrl = P.controller_for(wl, device=0, torch_stream=stream, torch_workspace=True,
-                            **(dict(weighting=P.WEIGHT_COST_TO_GO) if ctg else {}))
+    ctrl = P.controller_for(wl, device=0, torch_stream=stream, torch_workspace=True, weighting=weighting)
     x_dev = torch.tensor(np.asarray(wl.x0, float), dtype=torch.float64, device=dev)
-    spl = max(1, args.steps_per_launch)
     u_log = torch.zeros((spl, wl.m), dtype=torch.float64, device=dev)
     xp, up = x_dev.data_ptr(), u_log.data_ptr()
 
@@ -304,38 +375,115 @@ def main():
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) * 1e3 / n
 
-    run(args.warmup)
-    run(min(args.warmup, 10), 1)
-    ms_per_step = timed(args.steps, spl)
-    ms_per_step_single = timed(args.steps, 1) if spl > 1 else ms_per_step
-    rollout_steps = wl.K * wl.T
-    value = rollout_steps / (ms_per_step / 1e3)
-
-    # profiled pass of the same length: per-kernel HIP events on the library's stream
+    for k in sorted({min(spl, steps), steps % spl, 1} - {0}):   # capture every shape once
+        run(k, k)
+    run(warmup)
+    run(min(warmup, 10), 1)
+    ms = timed(steps, spl)
+    ms_single = timed(steps, 1) if spl > 1 else ms
     ctrl.set_profiling(True)
-    run(args.steps)
+    run(steps)
     times = ctrl.kernel_times()
     ctrl.set_profiling(False)
+    return ctrl, x_dev, ms, ms_single, times
+
+
+def alu_roofline(wl, times):
+    """Roofline of the rollout kernel of an analytic system: algorithmic FP32 FLOP per launch
+    (FLOP per rollout-step x K T) over its mean event-timed duration, against the published
+    FP32 peak; with the same rate against this build's unpacked-FP32 issue ceiling, the ops
+    including the noise generator, and the SQ VALU issue share of the committed profile."""
     roll_ms = times["rollout"][0]
-    if wl.name == "quadrotor_mlp":
-        ops = MLP_FLOP_PER_ROLLOUT_STEP * rollout_steps
-        achieved = ops / (roll_ms / 1e3) / 1e12
-        roofline = dict(bound="mfma", kernel="mlp_rollout", achieved=round(achieved, 3), peak=BF16_MFMA_PEAK_TFLOPS,
-                        unit="TFLOP/s", frac=round(achieved / BF16_MFMA_PEAK_TFLOPS, 5), traffic=None,
-                        alg_flop_per_launch=ops, kernel_ms=round(roll_ms, 5),
-                        kernel_ms_all={k: round(v[0], 5) for k, v in times.items()},
-                        launches_timed=times["rollout"][1],
-                        mlp_train_seconds=round(wl.params["mlp"].train_seconds, 3),
-                        mlp_final_loss=wl.params["mlp"].final_loss)
-    else:
-        ops = ALG_OPS_PER_ROLLOUT_STEP[wl.name] * rollout_steps
-        achieved = ops / (roll_ms / 1e3) / 1e12
-        roofline = dict(bound="alu", kernel="rollout", achieved=round(achieved, 4), peak=round(ALU_PEAK_TFLOPS, 2),
-                        unit="TFLOP/s", frac=round(achieved / ALU_PEAK_TFLOPS, 5), traffic=measured_traffic(wl.name),
-                        peak_published_fp32=PUBLISHED_FP32_TFLOPS,
-                        alg_ops_per_launch=ops, kernel_ms=round(roll_ms, 5),
-                        kernel_ms_all={k: round(v[0], 5) for k, v in times.items()},
-                        launches_timed=times["rollout"][1])
+    rs = wl.K * wl.T
+    flop = ALG_FLOP_PER_ROLLOUT_STEP[wl.name] * rs
+    achieved = flop / (roll_ms / 1e3) / 1e12
+    ops = ISSUE_OPS_PER_ROLLOUT_STEP[wl.name] * rs
+    ops_rate = ops / (roll_ms / 1e3) / 1e12
+    return dict(bound="alu", kernel="rollout", achieved=round(achieved, 4), peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
+                frac=round(achieved / FP32_PEAK_TFLOPS, 5), traffic=measured_traffic(wl.name),
+                flop_per_rollout_step=ALG_FLOP_PER_ROLLOUT_STEP[wl.name], rollout_steps_per_launch=rs,
+                alg_flop_per_launch=flop, kernel_ms=round(roll_ms, 5),
+                frac_of_unpacked_fp32=round(achieved / ALU_PEAK_TFLOPS, 5),
+                ops_incl_noise_per_rollout_step=ISSUE_OPS_PER_ROLLOUT_STEP[wl.name],
+                ops_incl_noise_frac_of_unpacked_fp32=round(ops_rate / ALU_PEAK_TFLOPS, 5),
+                valu_issue_share=valu_issue_share(wl.name),
+                kernel_ms_all={k: round(v[0], 5) for k, v in times.items()},
+                launches_timed=times["rollout"][1])
+
+
+def mlp_roofline(wl, times):
+    roll_ms = times["rollout"][0]
+    flop = MLP_FLOP_PER_ROLLOUT_STEP * wl.K * wl.T
+    achieved = flop / (roll_ms / 1e3) / 1e12
+    return dict(bound="mfma", kernel="mlp_rollout", achieved=round(achieved, 3), peak=BF16_MFMA_PEAK_TFLOPS,
+                unit="TFLOP/s", frac=round(achieved / BF16_MFMA_PEAK_TFLOPS, 5), traffic=None,
+                alg_flop_per_launch=flop, kernel_ms=round(roll_ms, 5),
+                kernel_ms_all={k: round(v[0], 5) for k, v in times.items()},
+                launches_timed=times["rollout"][1])
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--steps-per-launch", type=int, default=10,
+                    help="closed-loop steps per launch sequence (captured graph); 1 = one launch per step")
+    ap.add_argument("--warmup", type=int, default=30)
+    ap.add_argument("--workload", default="quadrotor")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="time the chosen workload only (no bicycle line, no learned-dynamics leg)")
+    ap.add_argument("--serving-seconds", type=float, default=10.0,
+                    help="length of the measured serving trace, after a one-second warm-up (0 disables "
+                         "the serving leg)")
+    ap.add_argument("--plain-seconds", type=float, default=10.0,
+                    help="length of the same trace replayed one controller at a time")
+    ap.add_argument("--copy-calibration", type=int, default=0,
+                    help="first run one plain device copy of this many bytes (a known-size kernel for "
+                         "calibrating HBM byte counters in a profiler pass)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only: the MPPI path shards over samples with one small "
+              f"exchange per iteration, which is designed but not built; --gpus {args.gpus} is not supported.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    ctg = args.workload.endswith("_ctg")
+    wl = make_workload(args.workload) if args.workload != "quadrotor_mlp" else None
+    cpu_leg = not args.no_cpu and args.workload != "quadrotor_mlp" and not ctg
+    cores = host_cores()
+    pool = start_shard_pool(wl, cores) if cpu_leg and cores > 1 else None
+
+    import torch
+    import paper_1509_01149_amd as P
+    P.load()
+    if not torch.cuda.is_available():
+        raise SystemExit("no GPU visible: bench.py runs the HIP path only")
+    dev = torch.device("cuda:0")
+    if args.copy_calibration > 0:
+        src = torch.ones(args.copy_calibration // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    learned = None
+    if wl is None or not args.no_extra:
+        g = trained_mlp()
+        learned = dict(train=dict(samples=g.train_samples, epochs=g.train_epochs, batch=4096,
+                                  seconds=round(g.train_seconds, 3), final_loss=g.final_loss,
+                                  tflops=round(g.train_samples * MLP_TRAIN_FLOP_PER_SAMPLE / g.train_seconds / 1e12, 3)))
+        learned["train"]["frac"] = round(learned["train"]["tflops"] / BF16_MFMA_PEAK_TFLOPS, 6)
+        if wl is None:
+            wl = W_quadrotor_mlp(g)
+    spl = max(1, args.steps_per_launch)
+    ctrl, x_dev, ms_per_step, ms_per_step_single, times = time_controller(
+        P, torch, wl, args.steps, args.warmup, spl, weighting=P.WEIGHT_COST_TO_GO if ctg else P.WEIGHT_PATH)
+    rollout_steps = wl.K * wl.T
+    value = rollout_steps / (ms_per_step / 1e3)
+    roofline = mlp_roofline(wl, times) if wl.name == "quadrotor_mlp" else alu_roofline(wl, times)
 
     out = dict(metric=METRIC, value=round(value, 1), unit="rollout-steps/s", n_gpus=1, steps=args.steps,
                warmup=args.warmup, ms_per_step=round(ms_per_step, 5), higher_is_better=True, scaling="weak",
@@ -347,18 +495,49 @@ def main():
                mppi_iters_per_s=round(1e3 / ms_per_step, 1), roofline=roofline,
                launch=dict(steps_per_launch=spl, ms_per_step_one_launch_per_step=round(ms_per_step_single, 5),
                            rollout_steps_per_s_one_launch_per_step=round(rollout_steps / (ms_per_step_single / 1e3), 1)))
+    if not args.no_extra and wl.name != "bicycle":
+        wb = make_workload("bicycle")
+        cb, _, ms_b, ms_b1, times_b = time_controller(P, torch, wb, args.steps, args.warmup, spl)
+        cb.close()
+        out["bicycle"] = dict(workload=f"bicycle K={wb.K} T={wb.T} nu={wb.nu}", ms_per_step=round(ms_b, 5),
+                              rollout_steps_per_s=round(wb.K * wb.T / (ms_b / 1e3), 1),
+                              ms_per_step_one_launch_per_step=round(ms_b1, 5), roofline=alu_roofline(wb, times_b))
+    if learned is not None and wl.name != "quadrotor_mlp":
+        wm = W_quadrotor_mlp(g)
+        cm, _, ms_m, _, times_m = time_controller(P, torch, wm, min(args.steps, 100), args.warmup, spl)
+        cm.close()
+        learned["rollout"] = dict(workload=f"quadrotor_mlp K={wm.K} T={wm.T}", ms_per_step=round(ms_m, 5),
+                                  rollout_steps_per_s=round(wm.K * wm.T / (ms_m / 1e3), 1),
+                                  roofline=mlp_roofline(wm, times_m))
+    if learned is not None:
+        out["learned"] = learned
     if args.serving_seconds > 0:
         out["serving"] = serving_bench(args.serving_seconds, args.plain_seconds)
     # (the oracle leg runs path weighting: the cost-to-go parity is in the tests)
-    if not args.no_cpu and wl.name != "quadrotor_mlp" and not ctg:
-        # the CPU leg: the oracle timed on a bounded sample, and one more control step of the
-        # timed controller checked against it from the same state, sequence and iteration
-        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
-        out["cpu_baseline"]["value"] = round(out["cpu_baseline"]["value"], 1)
+    if cpu_leg:
+        # the CPU leg: the oracle timed on a bounded sample, sharded over the host's cores and on
+        # one core, and one more control step of the timed controller checked against it from
+        # the same state, sequence and iteration
+        one = cpu_baseline(wl, args.cpu_seconds)
+        one["value"] = round(one["value"], 1)
+        if pool is not None:
+            cb = cpu_baseline_sharded(pool, wl, cores, args.cpu_seconds)
+            cb["value"] = round(cb["value"], 1)
+            cb["one_core"] = one
+            pool.close()
+            pool.join()
+        else:
+            cb = one
+        out["cpu_baseline"] = cb
         if not args.no_parity:
             out["cpu_baseline"]["parity"] = parity_spot_check(wl, ctrl, x_dev.cpu().numpy())
     ctrl.close()
     print(json.dumps(out), flush=True)
+
+
+def W_quadrotor_mlp(g):
+    import workloads as W
+    return W.quadrotor_mlp(g, nu=2.0, K=16384, T=100).replace(seed=0)
 
 
 if __name__ == "__main__":

@@ -250,6 +250,24 @@ int mppi_debug_philox(int32_t device, uint64_t seed, const uint32_t *counters, i
 int mppi_debug_lane_groups(int32_t device, int32_t group, const float *a, const float *b, int32_t n_waves,
                            float *out);
 
+/* The launch configuration a context chose (host output).  rollout_mode bits name the
+ * compiled rollout variant: MPPI_ROLLOUT_COST_TO_GO (prefix costs recorded), _CRASH (crash
+ * indicator), _STEP_SPLIT (the lanes of a sample share its horizon), _DIAGONAL (A chol(Sigma)
+ * and the likelihood-ratio matrix are diagonal, so only their diagonal products are formed);
+ * rollout_lanes is the lanes per sample (the learned dynamics: 4, sixteen samples per wave). */
+enum { MPPI_ROLLOUT_COST_TO_GO = 1, MPPI_ROLLOUT_CRASH = 2, MPPI_ROLLOUT_STEP_SPLIT = 4,
+       MPPI_ROLLOUT_DIAGONAL = 8 };
+typedef struct {
+  int32_t rollout_lanes;
+  int32_t rollout_mode;
+  int32_t rollout_blocks;     /* rollout blocks per iteration                               */
+  int32_t update_chunk;       /* samples per update block                                  */
+  int32_t update_blocks;      /* update blocks per iteration                               */
+  int32_t noise_groups;       /* Philox4x32-10 blocks per sample and iteration, ceil(T m/4) */
+  uint64_t workspace_bytes;   /* device bytes of the context's state                       */
+} mppi_info;
+int mppi_get_info(mppi_ctx *ctx, mppi_info *out);
+
 /* Kernel timing.  While profiling is on, every kernel of mppi_step / mppi_step_async is
  * launched directly (no graph) between two hipEvents recorded on the context's stream.
  * mppi_kernel_times waits for the stream and returns, per kernel kind (0 = rollout,

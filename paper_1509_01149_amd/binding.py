@@ -88,6 +88,14 @@ class ServerStats(C.Structure):
                 ("mean_batch", C.c_double), ("rollout_steps_done", C.c_int64)]
 
 
+class Info(C.Structure):
+    _fields_ = [("rollout_lanes", C.c_int32), ("rollout_mode", C.c_int32), ("rollout_blocks", C.c_int32),
+                ("update_chunk", C.c_int32), ("update_blocks", C.c_int32), ("noise_groups", C.c_int32),
+                ("workspace_bytes", C.c_uint64)]
+
+
+ROLLOUT_COST_TO_GO, ROLLOUT_CRASH, ROLLOUT_STEP_SPLIT, ROLLOUT_DIAGONAL = 1, 2, 4, 8
+
 SERVE_BATCHED, SERVE_PLAIN = 0, 1
 
 _lib = None
@@ -122,6 +130,7 @@ def load() -> C.CDLL:
         "mppi_debug_lane_groups": [C.c_int32, C.c_int32, _fp, _fp, C.c_int32, _fp],
         "mppi_set_profiling": [C.c_void_p, C.c_int32],
         "mppi_kernel_times": [C.c_void_p, _dp, C.POINTER(C.c_int64)],
+        "mppi_get_info": [C.c_void_p, C.POINTER(Info)],
         "mppi_server_create": [C.POINTER(ServerConfig), C.POINTER(C.c_void_p)],
         "mppi_server_destroy": [C.c_void_p],
         "mppi_server_admit": [C.c_void_p, C.POINTER(Config), C.POINTER(C.c_int32)],
@@ -338,6 +347,12 @@ class Controller:
         out = np.zeros((nk, self.T, self.m), dtype=np.float32)
         check(self._lib.mppi_debug_normals(self.handle, int(iteration), int(k0), int(nk), _ptr(out, _fp)))
         return out
+
+    def info(self) -> Dict:
+        """The launch configuration this context chose (mppi_get_info)."""
+        s = Info()
+        check(self._lib.mppi_get_info(self.handle, C.byref(s)))
+        return {f: getattr(s, f) for f, _ in Info._fields_}
 
     def set_profiling(self, on: bool):
         check(self._lib.mppi_set_profiling(self.handle, 1 if on else 0))

@@ -384,6 +384,9 @@ static size_t rollout_lds_bytes(const mppi_ctx *c) {
 // The rollout variant a context runs: step-split where the system allows it, else the
 // four-lane body; recording prefix costs under cost-to-go weighting, and with the
 // quadrotor's crash indicator when its crash_cost is positive.
+static_assert(MPPI_ROLLOUT_COST_TO_GO == kRecordPrefix && MPPI_ROLLOUT_CRASH == kCrashOn &&
+                  MPPI_ROLLOUT_STEP_SPLIT == kStepSplit && MPPI_ROLLOUT_DIAGONAL == kDiagLR,
+              "mppi_info.rollout_mode bits");
 static int rollout_mode(const mppi_ctx *c) {
   int mode = c->cfg.weighting == MPPI_WEIGHT_COST_TO_GO ? kRecordPrefix : 0;
   const int m = c->cfg.n_ctrl;
@@ -1017,6 +1020,21 @@ extern "C" int mppi_debug_lane_groups(int32_t device, int32_t group, const float
   if (e == hipSuccess) e = hipMemcpy(out, d + 2 * n, n * 6 * sizeof(float), hipMemcpyDeviceToHost);
   (void)hipFree(d);
   if (e != hipSuccess) return hip_fail(e, "debug_lane_groups");
+  return MPPI_OK;
+}
+
+extern "C" int mppi_get_info(mppi_ctx *c, mppi_info *out) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (!out) return fail(MPPI_EINVAL, "out is NULL");
+  const bool mlp = c->cfg.system == MPPI_SYS_QUADROTOR_MLP;
+  out->rollout_lanes = mlp ? 4 : rollout_lps(&c->cfg);
+  out->rollout_mode = mlp ? 0 : rollout_mode(c);
+  out->rollout_blocks = c->L.n_roll_blocks;
+  out->update_chunk = c->L.upd_chunk;
+  out->update_blocks = c->L.n_kc * ((c->L.G + kUpdGroups - 1) / kUpdGroups);
+  out->noise_groups = c->L.G;
+  out->workspace_bytes = c->L.total;
   return MPPI_OK;
 }
 

@@ -8,8 +8,10 @@ from oracle import mppi, systems
 # Tolerances and where they come from:
 #   U      max |U_gpu - U_orc| / max(1, |U_orc|_inf) <= 1e-4 (the stated bar for FP32 rollouts),
 #          plus twice the first-order effect of the (in-tolerance) cost differences,
-#          |(1/lambda) sum_k w_k (dS_k - <dS>_w) du_k|_inf / scale, which is only material when
-#          lambda is small against the cost scale on a chaotic system (cart-pole, lambda = 1)
+#          |(1/lambda) sum_k w_k (dS_k - <dS>_w) du_k|_inf / scale, capped at 1e-3; the term is
+#          only material when lambda is small against the cost scale on a chaotic system
+#          (cart-pole, lambda = 1), where an FP32 emulation of the oracle misses 1e-4 as well;
+#          every check reports which form of the bar it met
 #   S      |S_gpu - S_orc| / max(1, |S_orc|) <= 4e-4 on every well-conditioned sample: FP32
 #          rounding (6e-8 per step) amplified by at most exp(4/s * 2 s) ~ 3e3 along the
 #          cart-pole's unstable upright manifold gives ~1.8e-4 in the state and twice that in
@@ -28,6 +30,11 @@ from oracle import mppi, systems
 #          fraction of max |du|); the cost and update metrics then use the samples finite
 #          on both sides.
 TOL_U = 1e-4
+# Cap of the first-order allowance on U.  An FP32 rollout emulated on the CPU (correctly
+# rounded float32, tests/test_fp32_emulation.py) misses 1e-4 by itself on the cart-pole
+# closed loop, by at most 2.1e-4 with a first-order term of at most 2.1e-4; the allowance
+# (twice the first-order term) is never allowed above 1e-3, whatever the cost errors are.
+TOL_U_FIRST_ORDER_CAP = 1e-3
 TOL_W_INF_FLIP = 1e-6
 TOL_S = 4e-4
 TOL_S_TUMBLE = 0.1
@@ -110,13 +117,24 @@ def one_step(wl, ctrl, x0, U_before, iteration, n_iters=1):
     )
 
 
-def assert_parity(m, tol_u=TOL_U, tol_s=TOL_S):
+def u_tolerance(m, tol_u=TOL_U):
+    """The U bar a step is held to and which form of it the step met: the raw bar, or the raw
+    bar plus twice the first-order effect of its cost differences (capped)."""
+    u_err = max(m["u0_err"], m["U_err"])
+    allowance = min(2.0 * m["first_order"], TOL_U_FIRST_ORDER_CAP)
+    return tol_u + allowance, ("raw 1e-4" if u_err <= tol_u else "1e-4 + first-order")
+
+
+def assert_parity(m, tol_u=TOL_U, tol_s=TOL_S, label=""):
     assert m["iteration"] == m["it_next"]
     assert m["S_inf_match"], (m["n_inf_flips"], m["w_inf_flips"])
     assert m["S_err"] <= tol_s, m["S_err"]
     assert m["S_err_tumble"] <= TOL_S_TUMBLE, m["S_err_tumble"]
     assert m["impact"] <= m["impact_bound"], (m["impact"], m["impact_bound"])
-    tol = tol_u + 2.0 * m["first_order"]
+    tol, met = u_tolerance(m, tol_u)
+    m["U_bar_met"] = met
+    print(f"parity {label}: U_err {max(m['u0_err'], m['U_err']):.3e} ({met}; first-order "
+          f"{m['first_order']:.2e}), S_err {m['S_err']:.2e}, stage {m['stage_err']:.2e}")
     assert m["u0_err"] <= tol, (m["u0_err"], m["first_order"])
     assert m["U_err"] <= tol, (m["U_err"], m["first_order"])
     assert m["stage_err"] <= 1e-5, m["stage_err"]

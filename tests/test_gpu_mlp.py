@@ -8,9 +8,31 @@ import paper_1509_01149_amd as P
 import workloads as W
 from oracle import mlp as omlp
 from oracle import mppi
-from tests._parity import TOL_U
+from tests._parity import _first_order, u_tolerance
 
 pytestmark = pytest.mark.gpu
+
+# Element-wise bars of the BF16 network against the BF16-emulating FP64 oracle:
+#   |x_gpu - x_orc| <= A_REL |x_orc| + B_RMS rms(x_orc), per element of each gradient tensor
+# and of the forward outputs.  The operands of every product are the same BF16 values on
+# both sides unless the FP32 value of an activation or gradient falls on the other side of
+# a BF16 rounding boundary than the FP64 one (a "flip": one BF16 ulp, 2^-8 relative, of
+# one operand); A_REL = 2^-8 covers a flip of the element's own operand.  The rest is FP32
+# accumulation over the B = 4096 samples of a batch (about log2(B) 2^-24 of the sum of the
+# terms' magnitudes, which cancellation makes up to sqrt(B) times the result) and flips in
+# the layer feeding a product, each moving one of B terms by 2^-8 of itself: B_RMS = 2^-10
+# of the tensor's rms.  A CPU emulation of the FP32 arithmetic (float32 products of the same
+# BF16 operands) stays below 2.8e-4 rms on every tensor, a quarter of B_RMS.
+A_REL = 2.0 ** -8
+B_RMS = 2.0 ** -10
+
+
+def assert_elementwise(got, ref, what):
+    ref = np.asarray(ref, dtype=np.float64)
+    bound = A_REL * np.abs(ref) + B_RMS * np.sqrt(np.mean(ref * ref))
+    excess = np.abs(np.asarray(got, dtype=np.float64) - ref) / bound
+    print(what, "worst |d| / bound", float(excess.max()))
+    assert np.all(excess <= 1.0), (what, float(excess.max()))
 
 
 def _stats_net(seed=5, n=20000):
@@ -51,7 +73,7 @@ def test_forward_matches_bf16_oracle():
     yg, yo = (dx_g - net.mu_out) / net.sd_out, (dx_o - net.mu_out) / net.sd_out
     err = np.abs(yg - yo)
     print("forward: max", err.max(), "mean", err.mean())
-    assert err.max() < 2e-2 and err.mean() < 1e-3
+    assert_elementwise(yg, yo, "forward (standardised outputs)")
 
 
 def test_gradients_match_bf16_oracle():
@@ -63,11 +85,9 @@ def test_gradients_match_bf16_oracle():
     B = 4096
     loss_g, grads_g = g.loss_grads(zn[:B], tn[:B])
     loss_o, grads_o = omlp.loss_and_grads(net, omlp.bf16_round(zn[:B]), tn[:B], bf16=True)
-    assert loss_g == pytest.approx(loss_o, rel=1e-3)
+    assert loss_g == pytest.approx(loss_o, rel=1e-4)
     for (k, _), go in zip(P.binding._MLP_SHAPES, grads_o):
-        rel = np.linalg.norm(grads_g[k] - go) / np.linalg.norm(go)
-        print("grad", k, rel)
-        assert rel < 1e-2, k
+        assert_elementwise(grads_g[k], go, "gradient " + k)
 
 
 def test_training_tracks_the_oracle():
@@ -107,10 +127,14 @@ def test_mppi_iteration_with_learned_dynamics():
     u0_r, U_r, _, res = mppi.control_step(wl, wl.x0, U0, 0, system=sysm)
     S = res[-1].S
     rel = np.abs(S_gpu - S) / np.maximum(1.0, np.abs(S))
-    scale = max(1.0, float(np.max(np.abs(U_r))))
-    print("mlp mppi: S rel max", rel.max(), "median", np.median(rel), "U", np.max(np.abs(U - U_r)) / scale)
+    scale = max(1.0, float(np.max(np.abs(U_r))), float(np.max(np.abs(u0_r))))
+    fin = np.isfinite(S) & np.isfinite(S_gpu)
+    m = dict(u0_err=float(np.max(np.abs(u0[:wl.m] - u0_r))) / scale, U_err=float(np.max(np.abs(U - U_r))) / scale,
+             first_order=float(np.max(np.abs(_first_order(res[-1], S_gpu, fin, wl.lam)))) / scale)
+    tol, met = u_tolerance(m)
+    print("mlp mppi: S rel max", rel.max(), "median", np.median(rel), "U", m["U_err"], met)
     assert np.median(rel) < 1e-4 and rel.max() < 1e-2
-    assert np.max(np.abs(U - U_r)) / scale < 10 * TOL_U
+    assert m["U_err"] <= tol and m["u0_err"] <= tol
 
 
 def test_trained_network_gain_over_untrained_and_against_analytic():

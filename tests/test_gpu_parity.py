@@ -92,9 +92,40 @@ def test_first_iteration_parity(name):
     wl = CASES[name]().replace(seed=3)
     U0 = mppi.initial_sequence(wl)
     with controller(wl) as c:
+        assert c.info()["rollout_mode"] & P.binding.ROLLOUT_DIAGONAL    # diagonal Sigma and R here
         m = one_step(wl, c, wl.x0, U0, 0)
     print(name, {k: v for k, v in m.items() if isinstance(v, (float, int, bool))})
-    assert_parity(m)
+    assert_parity(m, label=name)
+
+
+def full_sigma_cases():
+    """Full (non-diagonal) SPD covariances, so the rollouts take the general products: a
+    lower-triangular A chol(Sigma) for the perturbations and a full likelihood-ratio matrix.
+    `coupled` passes R = NULL to the library (R = lambda Sigma^-1 formed there) and the same
+    matrix explicitly to the oracle."""
+    sb = np.array([[0.5, 0.1], [0.1, 0.3]])
+    sq = 0.2 * np.eye(4) + 0.05 * np.ones((4, 4))
+    return {
+        "bicycle_coupled": (W.bicycle().replace(sigma=sb, R=130.0 * np.linalg.inv(sb)), True),
+        "bicycle_coupled_nu_diag": (W.bicycle(nu=np.array([1.0, 4.0])).replace(sigma=sb, R=130.0 * np.linalg.inv(sb)),
+                                    True),
+        "bicycle_decoupled_16lanes": (W.bicycle(K=8000, T=50).replace(sigma=sb), False),
+        "quadrotor_decoupled": (W.quadrotor(nu=2.0, K=4096, T=150).replace(sigma=sq), False),
+        "quadrotor_coupled": (W.quadrotor(nu=2.0, K=4096, T=100).replace(sigma=sq, R=420.0 * np.linalg.inv(sq)), True),
+        "quadrotor_nu_diag": (W.quadrotor(nu=np.array([1.0, 2.0, 4.0, 8.0]), lam=420.0, K=2048, T=150)
+                              .replace(sigma=sq), False),
+    }
+
+
+@pytest.mark.parametrize("name", list(full_sigma_cases()))
+def test_full_covariance_parity(name):
+    wl, coupled = full_sigma_cases()[name]
+    wl = wl.replace(seed=19)
+    with controller(wl, **(dict(R=None) if coupled else {})) as c:
+        info = c.info()
+        assert not info["rollout_mode"] & P.binding.ROLLOUT_DIAGONAL, info
+        m = one_step(wl, c, wl.x0, mppi.initial_sequence(wl), 0)
+    assert_parity(m, label=name)
 
 
 @pytest.mark.parametrize("name", ["bicycle", "quadrotor_nu2", "swingup_nu1000"])

@@ -31,6 +31,9 @@ def mix():
         W.cartpole_swingup(nu=100.0, K=1000).replace(seed=30),
         W.bicycle(K=1024, T=30, nu=np.array([1.0, 4.0])).replace(seed=31),    # per-dimension nu
         W.bicycle(K=8192, T=40).replace(seed=32),                             # 16 lanes (the others 32)
+        # full covariances: the general (non-diagonal) noise and likelihood-ratio products
+        W.bicycle(K=2048, T=60).replace(sigma=np.array([[0.5, 0.1], [0.1, 0.3]]), seed=33),
+        W.quadrotor(nu=2.0, K=1024, T=80).replace(sigma=0.2 * np.eye(4) + 0.05 * np.ones((4, 4)), seed=34),
     ]
 
 
@@ -78,8 +81,10 @@ def test_alone_equals_mix_and_plain():
 
 def test_served_steps_match_oracle():
     wls = [W.bicycle(K=4096, T=100).replace(seed=31), W.cartpole(nu=2.0).replace(seed=32),
-           W.quadrotor(nu=2.0, K=4096, T=100).replace(seed=33)]
-    with P.Server(max_slots=4) as srv:
+           W.quadrotor(nu=2.0, K=4096, T=100).replace(seed=33),
+           W.quadrotor(nu=2.0, K=4096, T=100).replace(sigma=0.2 * np.eye(4) + 0.05 * np.ones((4, 4)), seed=35),
+           W.bicycle(K=4096, T=100).replace(sigma=np.array([[0.5, 0.1], [0.1, 0.3]]), seed=36)]
+    with P.Server(max_slots=8) as srv:
         u, U = serve_rounds(srv, wls, 1)
     for j, wl in enumerate(wls):
         u0_r, U_r, _, _ = mppi.control_step(wl, wl.x0, mppi.initial_sequence(wl), 0)

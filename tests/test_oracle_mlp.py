@@ -69,6 +69,50 @@ def test_gradients_match_autograd_and_finite_differences():
             assert (lp - lm) / (2 * h) == pytest.approx(g[pi].reshape(-1)[idx], rel=1e-5, abs=1e-10)
 
 
+class _RoundGrad(torch.autograd.Function):
+    """Identity forward; the gradient passing back through it is rounded to bfloat16."""
+
+    @staticmethod
+    def forward(ctx, x):
+        return x.view_as(x)
+
+    @staticmethod
+    def backward(ctx, g):
+        return g.to(torch.float32).to(torch.bfloat16).to(torch.float64)
+
+
+def test_bf16_backward_matches_autograd_with_the_same_rounding_points():
+    """The BF16-emulating backward: every matrix-product operand rounded to bfloat16 -- the
+    forward's inputs and weights (rounded values, gradient passed straight through) and the
+    gradients entering the weight and input products (dy, dz2, dz1) -- while the bias
+    gradients sum the unrounded ones.  Torch autograd with the roundings placed at those
+    points by hand computes the same loss and gradients to 1e-12."""
+    net = _net(7)
+    rng = np.random.default_rng(4)
+    zn, tn = rng.standard_normal((48, 16)), rng.standard_normal((48, 12))
+    loss, g = mlp.loss_and_grads(net, zn, tn, bf16=True)
+
+    t = lambda a: torch.tensor(a, dtype=torch.float64)
+    rnd = lambda a: a.to(torch.float32).to(torch.bfloat16).to(torch.float64)
+    st = lambda a: a + (rnd(a) - a).detach()                     # rounded value, identity gradient
+    W1, b1, W2, b2, W3, b3 = (t(p).requires_grad_(True) for p in net.params())
+    a0 = st(t(zn))
+    z1 = _RoundGrad.apply(a0 @ st(W1).T) + b1
+    a1 = st(torch.tanh(z1))
+    z2 = _RoundGrad.apply(a1 @ st(W2).T) + b2
+    a2 = st(torch.tanh(z2))
+    y = _RoundGrad.apply(a2 @ st(W3).T) + b3
+    lt = torch.mean((y - t(tn)) ** 2)
+    lt.backward()
+    assert loss == pytest.approx(lt.item(), rel=1e-13)
+    for gi, p in zip(g, (W1, b1, W2, b2, W3, b3)):
+        ref = p.grad.numpy()
+        assert np.max(np.abs(gi - ref)) <= 1e-12 * max(1e-30, np.max(np.abs(ref)))
+    # and the roundings matter: the FP64 backward differs from both by far more than that
+    _, g64 = mlp.loss_and_grads(net, zn, tn, bf16=False)
+    assert max(np.max(np.abs(a - b)) / np.max(np.abs(b)) for a, b in zip(g64, g)) > 1e-4
+
+
 def test_adam_matches_torch():
     net = _net()
     rng = np.random.default_rng(3)
