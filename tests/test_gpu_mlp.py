@@ -12,25 +12,16 @@ from tests._parity import _first_order, u_tolerance
 
 pytestmark = pytest.mark.gpu
 
-# Element-wise bars of the BF16 network against the BF16-emulating FP64 oracle:
-#   |x_gpu - x_orc| <= A_REL |x_orc| + B_RMS rms(x_orc), per element of each gradient tensor
-# and of the forward outputs.  The operands of every product are the same BF16 values on
-# both sides unless the FP32 value of an activation or gradient falls on the other side of
-# a BF16 rounding boundary than the FP64 one (a "flip": one BF16 ulp, 2^-8 relative, of
-# one operand); A_REL = 2^-8 covers a flip of the element's own operand.  The rest is FP32
-# accumulation over the B = 4096 samples of a batch (about log2(B) 2^-24 of the sum of the
-# terms' magnitudes, which cancellation makes up to sqrt(B) times the result) and flips in
-# the layer feeding a product, each moving one of B terms by 2^-8 of itself: B_RMS = 2^-10
-# of the tensor's rms.  A CPU emulation of the FP32 arithmetic (float32 products of the same
-# BF16 operands) stays below 2.8e-4 rms on every tensor, a quarter of B_RMS.
-A_REL = 2.0 ** -8
-B_RMS = 2.0 ** -10
+# Element-wise bars of the BF16 network against the BF16-emulating FP64 oracle: per element, the
+# worst-case FP32 summation error of its own product plus the propagation of every bfloat16
+# operand whose FP32 value can round the other way than its FP64 value (tests/_mlp_bounds.py,
+# derived from the arithmetic and pinned on the CPU against an FP32 realisation and planted
+# mistakes in tests/test_oracle_mlp.py).
+from tests import _mlp_bounds as MB  # noqa: E402
 
 
-def assert_elementwise(got, ref, what):
-    ref = np.asarray(ref, dtype=np.float64)
-    bound = A_REL * np.abs(ref) + B_RMS * np.sqrt(np.mean(ref * ref))
-    excess = np.abs(np.asarray(got, dtype=np.float64) - ref) / bound
+def assert_elementwise(got, ref, bound, what):
+    excess = np.abs(np.asarray(got, dtype=np.float64) - np.asarray(ref, dtype=np.float64)) / bound
     print(what, "worst |d| / bound", float(excess.max()))
     assert np.all(excess <= 1.0), (what, float(excess.max()))
 
@@ -73,21 +64,26 @@ def test_forward_matches_bf16_oracle():
     yg, yo = (dx_g - net.mu_out) / net.sd_out, (dx_o - net.mu_out) / net.sd_out
     err = np.abs(yg - yo)
     print("forward: max", err.max(), "mean", err.mean())
-    assert_elementwise(yg, yo, "forward (standardised outputs)")
+    z = np.concatenate([x[:B], u[:B]], 1)
+    bound, _ = MB.forward_bounds(net, (z - net.mu_in) / net.sd_in)
+    assert_elementwise(yg, yo, bound, "forward (standardised outputs)")
 
 
-def test_gradients_match_bf16_oracle():
+@pytest.mark.parametrize("B", [48, 4096])
+def test_gradients_match_bf16_oracle(B):
+    """Every element of every gradient, at a small ragged batch (one product per tile, tight
+    summation bounds) and at a full minibatch (the split-K path over the batch)."""
     wl, x, u, d, net, w = _stats_net()
     z = np.concatenate([x, u], 1)
     zn = (z - net.mu_in) / net.sd_in
     tn = (d - net.mu_out) / net.sd_out
     g = P.Mlp(w)
-    B = 4096
     loss_g, grads_g = g.loss_grads(zn[:B], tn[:B])
     loss_o, grads_o = omlp.loss_and_grads(net, omlp.bf16_round(zn[:B]), tn[:B], bf16=True)
     assert loss_g == pytest.approx(loss_o, rel=1e-4)
-    for (k, _), go in zip(P.binding._MLP_SHAPES, grads_o):
-        assert_elementwise(grads_g[k], go, "gradient " + k)
+    bounds = MB.gradient_bounds(net, zn[:B], tn[:B])
+    for (k, _), go, bd in zip(P.binding._MLP_SHAPES, grads_o, bounds):
+        assert_elementwise(grads_g[k], go, bd, "gradient " + k)
 
 
 def test_training_tracks_the_oracle():

@@ -256,21 +256,24 @@ def test_cost_to_go_first_step_equals_path_weighting():
 
 def test_swingup_closed_loop_exploration_variance():
     """Section V-A: 10 s of swing-up (500 control steps, K = 1000) on the GPU path, the
-    plant stepped by the oracle's FP64 model.  The average running cost falls as nu grows:
-    the natural variance (nu = 1) brings the pole up late, nu = 1000 within the first second."""
-    avg = {}
+    plant stepped by the oracle's FP64 model.  The natural variance (nu = 1) never brings the
+    pole up and its average running cost stays near the hanging value 2000; nu = 1000 brings
+    it up within 4 s and keeps it balanced through the last second."""
+    avg, th = {}, {}
     for nu in (1.0, 1000.0):
         wl = W.cartpole_swingup(nu=nu).replace(seed=1)
         sysm = systems.make(wl)
-        x, qs = wl.x0.copy(), []
+        x, qs, ths = wl.x0.copy(), [], []
         with controller(wl) as c:
             for _ in range(wl.control_steps):
                 x = mppi.plant_step(wl, x, c.step(x), system=sysm)
                 qs.append(float(sysm.q(x[None])[0]))
-        avg[nu] = float(np.mean(qs))
+                ths.append(x[2])
+        avg[nu], th[nu] = float(np.mean(qs)), np.array(ths)
         print("nu", nu, "average running cost", avg[nu], "final state", x)
-        if nu == 1000.0:
-            assert np.mean(qs[:50]) < 1000.0 and abs(abs(x[2]) - np.pi) < 0.3
+    assert np.all(np.cos(th[1.0]) > -0.9) and avg[1.0] > 1500.0
+    up = np.where(np.cos(th[1000.0]) < -0.9)[0]
+    assert up.size and up[0] * wl.dt < 4.0 and np.all(np.cos(th[1000.0][-50:]) < -0.99)
     assert avg[1.0] > 2.0 * avg[1000.0]
 
 

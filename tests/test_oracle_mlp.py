@@ -163,3 +163,98 @@ def test_learned_step_replaces_euler():
     x, u = W.mlp_training_inputs(10)
     from oracle import systems
     assert np.allclose(systems.euler_step(sysm, x, u, wl.dt), x + mlp.predict_delta(net, x, u), rtol=1e-14)
+
+
+# ------------------------------------------------- element-wise bars of the GPU tests
+from tests import _mlp_bounds as MB   # noqa: E402
+
+F32 = np.float32
+
+
+def _tanh_f32(x):
+    e = np.exp(F32(2.0) * np.abs(x), dtype=F32)
+    return np.copysign(F32(1.0) - F32(2.0) / (e + F32(1.0)), x).astype(F32)
+
+
+def _fp32_network(net, zn, tn, mistake=None):
+    """An FP32 realisation of the network's forward and backward with bfloat16 operands (what
+    the GPU kernels compute, written independently with NumPy float32 products and sums):
+    returns the standardised outputs and the six gradients.  `mistake` plants one error."""
+    b16 = lambda a: MB.omlp.bf16_round(a).astype(F32)
+    W1, W2, W3 = b16(net.W1), b16(net.W2), b16(net.W3)
+    if mistake == "transposed_W2":
+        W2 = W2.T.copy()
+    b1, b2, b3 = (np.asarray(b, dtype=F32) for b in (net.b1, net.b2, net.b3))
+    if mistake == "dropped_b2":
+        b2 = np.zeros_like(b2)
+    a0 = b16(zn)
+    h1 = _tanh_f32(a0 @ W1.T + b1)
+    a1 = b16(h1)
+    h2 = _tanh_f32(a1 @ W2.T + b2)
+    a2 = b16(h2)
+    y = a2 @ W3.T + b3
+    B = zn.shape[0]
+    g = ((F32(1.0) if mistake == "loss_gradient_without_2" else F32(2.0)) * (y - tn.astype(F32))
+         / F32(B * 12)).astype(F32)
+    gr = b16(g)
+    s2 = F32(1.0) + h2 * h2 if mistake == "tanh_derivative_sign" else F32(1.0) - h2 * h2
+    dz2 = (gr @ W3) * s2
+    dz2r = b16(dz2)
+    dz1 = (dz2r @ W2) * (F32(1.0) - h1 * h1)
+    dz1r = b16(dz1)
+    col = lambda v: v.astype(np.float64).sum(axis=0).astype(F32)
+    gW2 = dz2r.T @ (a2 if mistake == "wrong_layer_in_weight_gradient" else a1)
+    grads = [dz1r.T @ a0, col(dz1), gW2, col(dz2), gr.T @ a2, col(g)]
+    return y.astype(np.float64), [np.asarray(x, dtype=np.float64) for x in grads]
+
+
+def _bounds_case(n=4096):
+    wl = W.quadrotor()
+    x, u = W.mlp_training_inputs(n)
+    d = mlp.transitions(wl, x, u)
+    z = np.concatenate([x, u], 1)
+    mi, si, mo, so = mlp.standardisation(z, d)
+    w = W.mlp_init_weights(5)
+    rng = np.random.default_rng(1)
+    net = mlp.Net(w["W1"], w["b1"] + 0.1 * rng.standard_normal(128), w["W2"], w["b2"] + 0.1 * rng.standard_normal(128),
+                  w["W3"], w["b3"] + 0.1 * rng.standard_normal(12), mi, si, mo, so)
+    return net, (z - mi) / si, (d - mo) / so
+
+
+def _worst(got, ref, bound):
+    return float(np.max(np.abs(got - ref) / bound))
+
+
+@pytest.mark.parametrize("n", [48, 4096])
+def test_elementwise_bounds_hold_for_an_fp32_realisation(n):
+    """The per-element bounds of the GPU MLP tests (tests/_mlp_bounds.py) hold for an
+    independent FP32 realisation of the same bfloat16 arithmetic, on every output of the
+    forward and every element of every gradient, including the elements whose bfloat16
+    operands flip between FP32 and FP64 (a small batch and a full minibatch)."""
+    net, zn, tn = _bounds_case(n)
+    y_ref, _ = mlp.forward_normalised(net, zn, bf16=True)
+    _, g_ref = mlp.loss_and_grads(net, zn, tn, bf16=True)
+    y32, g32 = _fp32_network(net, zn, tn)
+    yb, _ = MB.forward_bounds(net, zn)
+    assert np.any(y32 != y_ref)                         # the realisations differ ...
+    assert _worst(y32, y_ref, yb) <= 1.0                # ... within the bound
+    for k, (a, b, bd) in enumerate(zip(g32, g_ref, MB.gradient_bounds(net, zn, tn))):
+        assert _worst(a, b, bd) <= 1.0, (k, _worst(a, b, bd))
+
+
+@pytest.mark.parametrize("mistake", ["dropped_b2", "transposed_W2", "tanh_derivative_sign",
+                                     "loss_gradient_without_2", "wrong_layer_in_weight_gradient"])
+@pytest.mark.parametrize("n", [48, 4096])
+def test_elementwise_bounds_catch_planted_mistakes(mistake, n):
+    """Each planted mistake in the FP32 realisation (a dropped term, a transposed operand, a
+    wrong sign, factor or operand) breaks the bound on some element by far.  A mistake of one
+    bfloat16 step (a rounding placed at another point) stays inside the flip allowance; the
+    oracle's own rounding points are pinned against torch autograd above."""
+    net, zn, tn = _bounds_case(n)
+    y_ref, _ = mlp.forward_normalised(net, zn, bf16=True)
+    _, g_ref = mlp.loss_and_grads(net, zn, tn, bf16=True)
+    y32, g32 = _fp32_network(net, zn, tn, mistake=mistake)
+    yb, _ = MB.forward_bounds(net, zn)
+    worst = max([_worst(y32, y_ref, yb)] + [_worst(a, b, bd) for a, b, bd in
+                                           zip(g32, g_ref, MB.gradient_bounds(net, zn, tn))])
+    assert worst > 10.0, worst

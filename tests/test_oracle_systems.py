@@ -173,7 +173,7 @@ def test_swingup_pendulum_period_and_energy_at_constant_cart_velocity():
     its energy per unit mass (2/3) l^2 thetadot^2 - g l cos theta is conserved, and small
     swings have period 2 pi sqrt(I / (m g l)) = 2 pi sqrt(4 l / (3 g)) for a uniform rod."""
     su = _swingup()
-    l, g = 0.5, 9.81
+    l, g = W.SWINGUP_HALF_LENGTH, 9.81
     E = lambda x: (2.0 / 3.0) * l * l * x[3] ** 2 - g * l * np.cos(x[2])
     rng = np.random.default_rng(4)
     for _ in range(3):
@@ -194,7 +194,7 @@ def test_swingup_pivot_acceleration_drives_the_pole():
     (lever l cos theta) changes the pole's energy at the rate -l pddot thetadot cos theta;
     and a hanging pole swings backwards (theta < 0) when the cart accelerates forwards."""
     su = _swingup()
-    l, g = 0.5, 9.81
+    l, g = W.SWINGUP_HALF_LENGTH, 9.81
 
     def f(t, z):
         x = z[:4]
