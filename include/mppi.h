@@ -215,6 +215,30 @@ int mppi_sync(mppi_ctx *ctx);
  * Device pointers, enqueued on the context's stream. */
 int mppi_plant_step_async(mppi_ctx *ctx, double *x_dev, const double *u_dev);
 
+/* Allocation-free control step, for callers that cannot allocate device memory (code under
+ * stream capture, tight serving loops, harnesses that forbid hipMalloc).  It computes exactly
+ * what mppi_create(cfg) with u_nominal0 = U and the iteration counter at *iteration, followed
+ * by mppi_step(ctx, x0, n_iters, u0) and mppi_get_controls, would: the same kernels on the same
+ * inputs, so the results are bit for bit those of that sequence.  The caller holds the
+ * controller state between calls:
+ *   x0         host, n       start state
+ *   U          host, T x m   in: nominal sequence; out: the sequence after the update and the
+ *                            warm shift (u_i <- u_{i+1}, u_{T-1} <- u_init)
+ *   iteration  host, 1       in: noise counter; out: advanced by n_iters
+ *   u0         host, m       out: the control sent to the actuators
+ * Every device buffer of the step (path costs, partial sums, the FP32 sequence, the cost map
+ * or obstacles) lives in one static device array of MPPI_STATIC_SCRATCH_BYTES per GPU, which
+ * the library keeps until the process ends; the call makes no device or pinned allocation.
+ * It runs on cfg->stream (NULL: the null stream) and blocks until done; cfg->workspace and
+ * cfg->use_graph are ignored.  All calls on one GPU share that array: calls that overlap on
+ * one GPU (from several threads) race and must be serialised by the caller.
+ * Errors: MPPI_EINVAL for an invalid cfg or argument, for MPPI_SYS_QUADROTOR_MLP, and when the
+ * step needs more than MPPI_STATIC_SCRATCH_BYTES (the same bytes mppi_workspace_bytes reports);
+ * MPPI_ENUMERIC as for mppi_step (u0 and the shift are still produced); MPPI_EDEVICE. */
+#define MPPI_STATIC_SCRATCH_BYTES (8ull << 20)
+int mppi_step_static(const mppi_config *cfg, const double *x0, double *U, uint64_t *iteration, int32_t n_iters,
+                     double *u0);
+
 /* Copy the current (post-shift) nominal sequence, T x m FP64, to / from the host. */
 int mppi_get_controls(mppi_ctx *ctx, double *u, uint64_t len);
 int mppi_set_controls(mppi_ctx *ctx, const double *u, uint64_t len);

@@ -114,6 +114,7 @@ def load() -> C.CDLL:
         "mppi_create": [C.POINTER(Config), C.POINTER(C.c_void_p)],
         "mppi_destroy": [C.c_void_p],
         "mppi_step": [C.c_void_p, _dp, C.c_int32, _dp],
+        "mppi_step_static": [C.POINTER(Config), _dp, _dp, _u64p, C.c_int32, _dp],
         "mppi_step_async": [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p],
         "mppi_step_plant_async": [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p],
         "mppi_run_closed_loop_async": [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p],
@@ -253,6 +254,24 @@ def make_config(*, system: int, n: int, m: int, K: int, T: int, dt: float, lam: 
     cfg.nu_diag = _ptr(nu_vec)
     cfg.weighting = weighting
     return cfg, keep
+
+
+STATIC_SCRATCH_BYTES = 8 << 20      # MPPI_STATIC_SCRATCH_BYTES
+
+
+def step_static(x0, U, iteration: int, n_iters: int = 1, **config):
+    """mppi_step_static: one control step without any device allocation, the controller state
+    (nominal sequence U (T, m) and noise counter) held by the caller.  `config` takes the
+    arguments of make_config.  Returns (u0, U after the update and the shift, iteration)."""
+    lib = load()
+    cfg, keep = make_config(**config)
+    n, m, T = cfg.n_state, cfg.n_ctrl, cfg.T
+    x = _f64(x0).reshape(n)
+    Uc = _f64(U).reshape(T, m).copy()
+    it = C.c_uint64(int(iteration))
+    u0 = np.zeros(m)
+    check(lib.mppi_step_static(C.byref(cfg), _ptr(x), _ptr(Uc), C.byref(it), int(n_iters), _ptr(u0)))
+    return u0, Uc, int(it.value)
 
 
 class Controller:

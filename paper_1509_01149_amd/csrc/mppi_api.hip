@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -354,7 +355,8 @@ static int build_params(mppi_ctx *c) {
       qp.n_obs = p->n_obstacles;
       qp.crash = (float)p->crash_cost; qp.ground = (float)p->ground_z;
       const int no = p->n_obstacles;
-      std::vector<float> ob((size_t)(no > 0 ? no : 1) * 5, 0.f);
+      float ob[(QuadrotorSys::kMaxObstacles + 1) * 5];
+      std::memset(ob, 0, sizeof(ob));
       for (int j = 0; j < no; ++j) {
         const double *o = p->obstacles + 4 * j;
         const double rr = o[3] + p->obs_margin;
@@ -363,7 +365,7 @@ static int build_params(mppi_ctx *c) {
         ob[4 * (size_t)no + j] = (float)(o[3] * o[3]);
       }
       qp.obs = (const float4 *)(c->base + c->L.off_sys);
-      HIP_TRY(hipMemcpy((void *)qp.obs, ob.data(), ob.size() * 4, hipMemcpyHostToDevice));
+      HIP_TRY(hipMemcpy((void *)qp.obs, ob, (size_t)(no > 0 ? no : 1) * 5 * 4, hipMemcpyHostToDevice));
       c->quad = qp;
       break;
     }
@@ -689,16 +691,13 @@ int set_device(int dev) {
 
 }  // namespace mppi
 
-extern "C" int mppi_create(const mppi_config *cfg, mppi_ctx **out) {
-  if (!out) return fail(MPPI_EINVAL, "out is NULL");
-  *out = nullptr;
-  int rc = validate_config(cfg);
-  if (rc) return rc;
-  rc = set_device(cfg->device);
-  if (rc) return rc;
-  auto *c = new mppi_ctx();
+namespace mppi {
+
+// The host-side state of a context: the configuration, A chol(Sigma), R, the likelihood-ratio
+// matrix (R - A^-1 R A^-1) / 2, u_init and the workspace layout (no device work).
+static void init_host_state(mppi_ctx *c, const mppi_config *cfg) {
   c->cfg = *cfg;
-  const int m = cfg->n_ctrl, T = cfg->T;
+  const int m = cfg->n_ctrl;
   cholesky(cfg->sigma, m, c->L64);
   // covariance change A = diag(sqrt(nu_j)) (sqrt(nu) I without per-dimension factors)
   double sq[4];
@@ -718,6 +717,35 @@ extern "C" int mppi_create(const mppi_config *cfg, mppi_ctx **out) {
   for (int j = 0; j < m; ++j) c->u_init[j] = cfg->u_init[j];
   c->cfg.sigma = c->cfg.R = c->cfg.u_init = c->cfg.u_nominal0 = c->cfg.nu_diag = nullptr;  // not kept
   compute_layout(cfg, &c->L);
+}
+
+// Per-system preparation of the rollout kernel (dynamic LDS size) once buffers are placed.
+static int prepare_system(mppi_ctx *c) {
+  const int m = c->cfg.n_ctrl;
+  switch (c->cfg.system) {
+    case MPPI_SYS_LINEAR:
+      return m == 1 ? prepare_rollout<LinearSys<1>>(c) : (m == 2 ? prepare_rollout<LinearSys<2>>(c) : prepare_rollout<LinearSys<4>>(c));
+    case MPPI_SYS_CARTPOLE: return prepare_rollout<CartPoleSys>(c);
+    case MPPI_SYS_CARTPOLE_SWINGUP: return prepare_rollout<SwingUpSys>(c);
+    case MPPI_SYS_BICYCLE: return prepare_rollout<BicycleSys>(c);
+    case MPPI_SYS_QUADROTOR: return prepare_rollout<QuadrotorSys>(c);
+    case MPPI_SYS_QUADROTOR_MLP: return prepare_mlp_rollout(c);
+    default: return MPPI_OK;
+  }
+}
+
+}  // namespace mppi
+
+extern "C" int mppi_create(const mppi_config *cfg, mppi_ctx **out) {
+  if (!out) return fail(MPPI_EINVAL, "out is NULL");
+  *out = nullptr;
+  int rc = validate_config(cfg);
+  if (rc) return rc;
+  rc = set_device(cfg->device);
+  if (rc) return rc;
+  auto *c = new mppi_ctx();
+  init_host_state(c, cfg);
+  const int m = cfg->n_ctrl, T = cfg->T;
   // device memory
   if (cfg->workspace) {
     if (cfg->workspace_bytes < c->L.total) {
@@ -747,19 +775,7 @@ extern "C" int mppi_create(const mppi_config *cfg, mppi_ctx **out) {
   if (hipHostMalloc((void **)&c->pinned, 4096, hipHostMallocDefault) != hipSuccess) { mppi_destroy(c); return fail(MPPI_ENOMEM, "hipHostMalloc failed"); }
   rc = build_params(c);
   if (!rc) rc = init_extra(c, cfg);
-  if (!rc) {
-    switch (cfg->system) {
-      case MPPI_SYS_LINEAR:
-        rc = m == 1 ? prepare_rollout<LinearSys<1>>(c) : (m == 2 ? prepare_rollout<LinearSys<2>>(c) : prepare_rollout<LinearSys<4>>(c));
-        break;
-      case MPPI_SYS_CARTPOLE: rc = prepare_rollout<CartPoleSys>(c); break;
-      case MPPI_SYS_CARTPOLE_SWINGUP: rc = prepare_rollout<SwingUpSys>(c); break;
-      case MPPI_SYS_BICYCLE: rc = prepare_rollout<BicycleSys>(c); break;
-      case MPPI_SYS_QUADROTOR: rc = prepare_rollout<QuadrotorSys>(c); break;
-      case MPPI_SYS_QUADROTOR_MLP: rc = prepare_mlp_rollout(c); break;
-      default: break;
-    }
-  }
+  if (!rc) rc = prepare_system(c);
   if (rc) { std::string msg = g_last_error; mppi_destroy(c); g_last_error = msg; return rc; }
   // initial state: U (FP64 + FP32), iteration 0, zero flags
   std::vector<double> U((size_t)T * m);
@@ -1067,5 +1083,86 @@ extern "C" int mppi_kernel_times(mppi_ctx *c, double *avg_ms, int64_t *count) {
     count[k] = c->prof_n[k];
     avg_ms[k] = c->prof_n[k] ? c->prof_ms[k] / (double)c->prof_n[k] : 0.0;
   }
+  return MPPI_OK;
+}
+
+// ------------------------------------------------------ allocation-free control step
+// Device memory of mppi_step_static: one file-scope array, which every GPU the library runs
+// on holds at its own address until the process ends.  In host code the name `scratch` is a
+// host-side stand-in, never a device address: its address on each device is looked up once
+// (hipGetSymbolAddress, with that device current) and only that pointer is used.
+static __device__ __align__(256) char scratch[MPPI_STATIC_SCRATCH_BYTES];
+
+namespace mppi {
+constexpr int kMaxStaticDevices = 64;
+static std::mutex g_scratch_mu;
+static char *g_scratch_dev[kMaxStaticDevices] = {};
+
+// The device address of `scratch` on `dev` (the current device), looked up on the first call.
+static int static_scratch(int dev, char **out) {
+  if (dev < 0 || dev >= kMaxStaticDevices) return fail(MPPI_EINVAL, "device %d outside [0, %d)", dev, kMaxStaticDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!p) return fail(MPPI_EDEVICE, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch_dev[dev] = (char *)p;
+  }
+  *out = g_scratch_dev[dev];
+  return MPPI_OK;
+}
+}  // namespace mppi
+
+extern "C" int mppi_step_static(const mppi_config *cfg, const double *x0, double *U, uint64_t *iteration,
+                                int32_t n_iters, double *u0) {
+  int rc = validate_config(cfg);
+  if (rc) return rc;
+  if (!x0 || !U || !iteration || !u0) return fail(MPPI_EINVAL, "x0, U, iteration and u0 must be non-NULL");
+  if (n_iters < 1 || n_iters > 1000) return fail(MPPI_EINVAL, "n_iters=%d outside [1, 1000]", n_iters);
+  if (cfg->system == MPPI_SYS_QUADROTOR_MLP)
+    return fail(MPPI_EINVAL, "mppi_step_static: the learned dynamics need device buffers of their own");
+  if (!finite_all(x0, cfg->n_state) || !finite_all(U, cfg->T * cfg->n_ctrl))
+    return fail(MPPI_EINVAL, "x0 or U has non-finite entries");
+  rc = set_device(cfg->device);
+  if (rc) return rc;
+  char *base = nullptr;
+  rc = static_scratch(cfg->device, &base);
+  if (rc) return rc;
+  // a context on the stack: its containers stay empty (no graphs, no profiling events)
+  mppi_ctx c;
+  init_host_state(&c, cfg);
+  if (c.L.total > MPPI_STATIC_SCRATCH_BYTES)
+    return fail(MPPI_EINVAL, "mppi_step_static: K=%d, T=%d needs %llu B of device state, the static scratch holds %llu B",
+                cfg->K, cfg->T, (unsigned long long)c.L.total, (unsigned long long)MPPI_STATIC_SCRATCH_BYTES);
+  c.base = base;
+  c.stream = (hipStream_t)cfg->stream;
+  c.cfg.use_graph = 0;
+  c.cfg.workspace = nullptr;
+  // the previous call on this device is complete (calls block), so the system data, the
+  // sequence and the counters can be rewritten; what the kernels expect at zero is cleared
+  rc = build_params(&c);
+  if (!rc) rc = prepare_system(&c);
+  if (rc) return rc;
+  const int T = cfg->T, m = cfg->n_ctrl, n = cfg->n_state;
+  float U32[kMaxTM];
+  for (int i = 0; i < T * m; ++i) U32[i] = (float)U[i];
+  HIP_TRY(hipMemsetAsync(base, 0, c.L.off_U64, c.stream));
+  HIP_TRY(hipMemcpyAsync(base + c.L.off_x0, x0, (size_t)n * 8, hipMemcpyHostToDevice, c.stream));
+  HIP_TRY(hipMemcpyAsync(base + c.L.off_iter, iteration, 8, hipMemcpyHostToDevice, c.stream));
+  HIP_TRY(hipMemcpyAsync(base + c.L.off_U64, U, (size_t)T * m * 8, hipMemcpyHostToDevice, c.stream));
+  HIP_TRY(hipMemcpyAsync(base + c.L.off_U32, U32, (size_t)T * m * 4, hipMemcpyHostToDevice, c.stream));
+  double *d_res = (double *)(base + c.L.off_res);
+  rc = enqueue_iterations(&c, (const double *)(base + c.L.off_x0), n_iters, d_res, c.stream, nullptr);
+  if (rc) return rc;
+  double res[8];
+  HIP_TRY(hipMemcpyAsync(res, d_res, sizeof(res), hipMemcpyDeviceToHost, c.stream));
+  HIP_TRY(hipMemcpyAsync(U, base + c.L.off_U64, (size_t)T * m * 8, hipMemcpyDeviceToHost, c.stream));
+  HIP_TRY(hipMemcpyAsync(iteration, base + c.L.off_iter, 8, hipMemcpyDeviceToHost, c.stream));
+  HIP_TRY(hipStreamSynchronize(c.stream));
+  std::memcpy(u0, res, (size_t)m * sizeof(double));
+  int count;
+  std::memcpy(&count, res + 4, sizeof(int));
+  if (count != 0) return fail(MPPI_ENUMERIC, "an iteration had no sample with a finite path cost; U was left unchanged");
   return MPPI_OK;
 }
