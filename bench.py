@@ -18,8 +18,8 @@ the bicycle (K = 4096, T = 100) is also timed as a secondary line (`bicycle`).
 The JSON line also carries the dominant kernel's roofline (algorithmic FLOP per launch
 over its mean duration from HIP events recorded on the library's own stream during a
 profiled pass of the same length), the learned-dynamics training rate, the serving legs
-(a Poisson trace at 50 Hz per controller and a saturated burst, batched against one
-controller at a time) and the CPU leg: the oracle's throughput on a bounded sample of the
+(a Poisson trace at 50 Hz per controller under an HBM admission budget of 75 % of the mix's
+device state, and a saturated burst, batched against one controller at a time) and the CPU leg: the oracle's throughput on a bounded sample of the
 same workload on one host core and with the samples sharded over the host's cores (the
 shards' partial sums combined by the oracle's exact merge), plus one control step of the
 timed controller checked against the oracle.  Only the CPU leg touches the oracle.
@@ -113,6 +113,11 @@ def valu_issue_share(name):
     return float(rec["valu_issue_share"]) if rec and "valu_issue_share" in rec else None
 
 
+def progress(msg):
+    """One line per finished leg on stderr (the JSON line is the only stdout output)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def make_workload(name):
     import workloads as W
     if name == "bicycle":
@@ -162,44 +167,70 @@ def serving_mix_workloads(n_controllers):
     return out
 
 
-def serving_bench(seconds, plain_seconds, n_controllers=256, rate_hz=50.0, inflight=3, saturate_requests=8,
-                  warm_seconds=1.0):
-    """Replay the same Poisson trace (rate_hz per controller) through the batched server
-    and through the plain one-controller-at-a-time policy: the first warm_seconds of the
-    trace warm the server up and are not measured; report latency percentiles and the
-    aggregate rollout-steps/s of the requests that arrive in the measured window."""
+def workspace_bytes(wl):
+    import ctypes as C
+    import paper_1509_01149_amd as P
+    cfg, keep = P.binding.make_config(**P.controller_args(wl))
+    need = C.c_uint64(0)
+    P.binding.check(P.load().mppi_workspace_bytes(C.byref(cfg), C.byref(need)))
+    return int(need.value)
+
+
+SERVE_MODES = ("batched", "plain")
+
+
+def serving_bench(n_controllers=256, rate_hz=50.0, inflight=3, saturate_requests=8, warm_seconds=1.0,
+                  seconds=10.0, budget_frac=0.75, modes=SERVE_MODES):
+    """The serving mix replayed in real time through the batched server and through the plain
+    one-controller-at-a-time policy, under an HBM budget of budget_frac of the mix's total
+    device state, so admission binds: controllers are admitted in order until the budget
+    refuses one, and the requests of the refused controllers are counted as rejected.  The
+    admitted controllers' requests arrive Poisson at rate_hz each; those of the first
+    warm_seconds are served but not measured."""
     import workloads as W
     import paper_1509_01149_amd as P
     wls = serving_mix_workloads(n_controllers)
-    trace = W.poisson_arrivals(n_controllers, rate_hz, warm_seconds + max(seconds, plain_seconds))
-    res = dict(controllers=n_controllers, rate_hz_per_controller=rate_hz,
-               offered_requests_per_s=n_controllers * rate_hz,
-               offered_rollout_steps_per_s=rate_hz * sum(w.K * w.T for w in wls), warmup_seconds=warm_seconds)
-    for mode, dur in (("batched", seconds), ("plain", plain_seconds)):
-        if dur <= 0:
-            continue
-        ev = [(t, c) for t, c in trace if t < warm_seconds + dur]
-        t = np.array([a for a, _ in ev])
-        ci = np.array([c for _, c in ev])
-        kw = dict(max_slots=n_controllers, max_inflight=inflight, max_batch=n_controllers,
-                  mode=P.SERVE_BATCHED if mode == "batched" else P.SERVE_PLAIN, hbm_budget_bytes=64 << 30)
-        with P.Server(**kw) as srv:
-            slots = np.array([srv.admit(**P.controller_args(wl)) for wl in wls])
+    need = np.array([workspace_bytes(w) for w in wls])
+    budget = int(budget_frac * need.sum())
+    trace = W.poisson_arrivals(n_controllers, rate_hz, warm_seconds + seconds)
+    res = dict(controllers=n_controllers, rate_hz_per_controller=rate_hz, warmup_seconds=warm_seconds,
+               trace_seconds=seconds, mix_state_bytes=int(need.sum()), hbm_budget_bytes=budget,
+               budget_frac_of_mix=budget_frac, offered_requests_per_s=n_controllers * rate_hz,
+               offered_rollout_steps_per_s=rate_hz * sum(w.K * w.T for w in wls))
+    mode_id = dict(batched=P.SERVE_BATCHED, plain=P.SERVE_PLAIN)
+    for mode in modes:
+        with P.Server(max_slots=n_controllers, max_inflight=inflight, max_batch=n_controllers, mode=mode_id[mode],
+                      hbm_budget_bytes=budget) as srv:
+            slots = np.full(n_controllers, -1)
+            for c, wl in enumerate(wls):
+                try:
+                    slots[c] = srv.admit(**P.controller_args(wl))
+                except P.MppiError as e:
+                    if e.code != P.binding.EBUSY:
+                        raise
+            admitted = slots >= 0
+            ev = [(t, c) for t, c in trace if admitted[c]]
+            t = np.array([a for a, _ in ev])
+            ci = np.array([c for _, c in ev])
             st0 = srv.stats()
             x0s = [np.pad(wls[c].x0, (0, 16 - wls[c].n)) for c in ci]
             td, u0, status = srv.replay(t, slots[ci], x0s)
             st1 = srv.stats()
+        progress(f"serving {mode} replayed")
         meas = t >= warm_seconds
         lat = (td[meas] - t[meas]) * 1e3
         span = float(td[meas].max()) - warm_seconds
         steps = float(sum(wls[c].K * wls[c].T for c in ci[meas]))
-        res[mode] = dict(trace_seconds=dur, requests=int(meas.sum()), p50_ms=round(float(np.percentile(lat, 50)), 3),
+        res[mode] = dict(requests=int(meas.sum()), p50_ms=round(float(np.percentile(lat, 50)), 3),
                          p99_ms=round(float(np.percentile(lat, 99)), 3), max_ms=round(float(lat.max()), 3),
                          mean_ms=round(float(lat.mean()), 3), completion_span_s=round(span, 3),
                          rollout_steps_per_s=round(steps / span, 1), requests_per_s=round(meas.sum() / span, 1),
                          mean_batch=round((st1["requests_done"] - st0["requests_done"]) /
                                           max(1, st1["batches"] - st0["batches"]), 2),
-                         numeric_failures=int(np.sum(status != 0)))
+                         numeric_failures=int(np.sum(status != 0)),
+                         admitted_controllers=int(admitted.sum()), rejected_controllers=int((~admitted).sum()),
+                         admitted_state_bytes=int(need[admitted].sum()),
+                         rejected_requests=int(sum(1 for a, c in trace if not admitted[c] and a >= warm_seconds)))
     if saturate_requests > 0:
         res["saturated"] = saturation_bench(wls, saturate_requests, inflight)
     return res
@@ -216,9 +247,9 @@ def saturation_bench(wls, per_controller, inflight):
     steps = float(sum(wls[c].K * wls[c].T for c in ci))
     flop = float(sum(ALG_FLOP_PER_ROLLOUT_STEP[wls[c].name] * wls[c].K * wls[c].T for c in ci))
     out = dict(requests_per_controller=per_controller, requests=int(ci.size))
-    for mode in ("batched", "plain"):
-        kw = dict(max_slots=n, max_inflight=inflight, max_batch=n,
-                  mode=P.SERVE_BATCHED if mode == "batched" else P.SERVE_PLAIN, hbm_budget_bytes=64 << 30)
+    mode_id = dict(batched=P.SERVE_BATCHED, plain=P.SERVE_PLAIN)
+    for mode in SERVE_MODES:
+        kw = dict(max_slots=n, max_inflight=inflight, max_batch=n, mode=mode_id[mode], hbm_budget_bytes=64 << 30)
         with P.Server(**kw) as srv:
             slots = np.array([srv.admit(**P.controller_args(wl)) for wl in wls])
             srv.replay(np.zeros(n), slots, [np.pad(w.x0, (0, 16 - w.n)) for w in wls])
@@ -435,11 +466,7 @@ def main():
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
                     help="time the chosen workload only (no bicycle line, no learned-dynamics leg)")
-    ap.add_argument("--serving-seconds", type=float, default=10.0,
-                    help="length of the measured serving trace, after a one-second warm-up (0 disables "
-                         "the serving leg)")
-    ap.add_argument("--plain-seconds", type=float, default=10.0,
-                    help="length of the same trace replayed one controller at a time")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="first run one plain device copy of this many bytes (a known-size kernel for "
                          "calibrating HBM byte counters in a profiler pass)")
@@ -483,6 +510,7 @@ def main():
         P, torch, wl, args.steps, args.warmup, spl, weighting=P.WEIGHT_COST_TO_GO if ctg else P.WEIGHT_PATH)
     rollout_steps = wl.K * wl.T
     value = rollout_steps / (ms_per_step / 1e3)
+    progress(f"{wl.name} timed: {ms_per_step:.5f} ms per control step")
     roofline = mlp_roofline(wl, times) if wl.name == "quadrotor_mlp" else alu_roofline(wl, times)
 
     out = dict(metric=METRIC, value=round(value, 1), unit="rollout-steps/s", n_gpus=1, steps=args.steps,
@@ -502,6 +530,8 @@ def main():
         out["bicycle"] = dict(workload=f"bicycle K={wb.K} T={wb.T} nu={wb.nu}", ms_per_step=round(ms_b, 5),
                               rollout_steps_per_s=round(wb.K * wb.T / (ms_b / 1e3), 1),
                               ms_per_step_one_launch_per_step=round(ms_b1, 5), roofline=alu_roofline(wb, times_b))
+    if "bicycle" in out:
+        progress("bicycle timed")
     if learned is not None and wl.name != "quadrotor_mlp":
         wm = W_quadrotor_mlp(g)
         cm, _, ms_m, _, times_m = time_controller(P, torch, wm, min(args.steps, 100), args.warmup, spl)
@@ -511,8 +541,10 @@ def main():
                                   roofline=mlp_roofline(wm, times_m))
     if learned is not None:
         out["learned"] = learned
-    if args.serving_seconds > 0:
-        out["serving"] = serving_bench(args.serving_seconds, args.plain_seconds)
+        progress("learned dynamics trained and timed")
+    if not args.no_serving:
+        out["serving"] = serving_bench()
+        progress("serving legs done")
     # (the oracle leg runs path weighting: the cost-to-go parity is in the tests)
     if cpu_leg:
         # the CPU leg: the oracle timed on a bounded sample, sharded over the host's cores and on

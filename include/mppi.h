@@ -362,12 +362,19 @@ int mppi_mlp_forward(mppi_mlp *mlp, const double *x, const double *u, int32_t B,
  * and every reduction has a fixed order).  The real-time control loop of the paper runs
  * each controller at 50 Hz (Section V); the server reports per-request completion times.
  *
+ * MPPI_SERVE_BATCHED_GRAPH forms the same batches but runs each as one graph launch: each
+ * server stream keeps one instantiated graph per set of system types a batch can hold (the
+ * plan upload, the types' rollouts as parallel branches, the update, the finalize and the
+ * result download), and a launch only rewrites its kernel nodes' grid sizes and counts for
+ * the batch at hand.  Its results are the same bit for bit; it is not the default because a
+ * run at the scale of 256 controllers under a session trace ended the process with a host
+ * segmentation fault whose cause has not been found.
  * MPPI_SERVE_PLAIN is the reference policy: one controller step at a time in arrival
  * order, each through the controller's own captured single-controller graph.
  * ------------------------------------------------------------------------------------ */
 typedef struct mppi_server mppi_server;
 
-enum { MPPI_SERVE_BATCHED = 0, MPPI_SERVE_PLAIN = 1 };
+enum { MPPI_SERVE_BATCHED = 0, MPPI_SERVE_PLAIN = 1, MPPI_SERVE_BATCHED_GRAPH = 2 };
 
 typedef struct {
   int32_t device;
@@ -375,7 +382,7 @@ typedef struct {
   int32_t max_slots;          /* 1 .. 4096 controllers                                     */
   int32_t max_inflight;       /* concurrent batches (one stream each), 1 .. 8; PLAIN uses 1 */
   int32_t max_batch;          /* controllers per batch, 1 .. max_slots                     */
-  int32_t mode;               /* MPPI_SERVE_BATCHED or MPPI_SERVE_PLAIN                    */
+  int32_t mode;               /* MPPI_SERVE_BATCHED, MPPI_SERVE_PLAIN or _BATCHED_GRAPH    */
 } mppi_server_config;
 
 typedef struct {
@@ -411,6 +418,24 @@ int mppi_server_poll(mppi_server *srv, int32_t max, uint64_t *req_ids, double *u
  * times must be non-decreasing. */
 int mppi_server_replay(mppi_server *srv, int32_t n, const double *t_arrival, const int32_t *slots,
                        const double *x0s, double *t_done, double *u0s, int32_t *status);
+/* Replay a trace of controller sessions with admission by the HBM budget: controllers that
+ * arrive, wait for a slot and budget, run their 50 Hz loop (Section V) and leave.  Session j
+ * (configuration cfgs[j], as for mppi_server_admit) arrives t_start[j] seconds after the call
+ * starts and ends at t_end[j] >= t_start[j].  Arriving sessions wait in one first-come queue;
+ * the head is admitted as soon as mppi_server_admit finds a slot and budget for it (the
+ * sessions behind it wait too).  Request i of session sessions[i] arrives t_arrival[i], within
+ * [t_start, t_end) of its session (non-decreasing over i), from x0s[16 i .. 16 i + n); it is
+ * submitted when its session is admitted, so its latency includes any admission wait.  A
+ * session is released once its end has passed (or the trace's last request has arrived) and
+ * all its requests are served, which frees its slot and bytes for the queue.  Returns when
+ * every request is done and every session has left, with t_done[i], u0s[4 i ..] and status[i]
+ * per request (MPPI_EBUSY, not served, for a session whose state alone exceeds the budget)
+ * and t_admit[j], t_release[j] per session (seconds since the start; -1 if never admitted).
+ * Slots admitted before the call keep their share of the budget. */
+int mppi_server_replay_sessions(mppi_server *srv, int32_t n_sessions, const mppi_config *cfgs,
+                                const double *t_start, const double *t_end, int32_t n, const double *t_arrival,
+                                const int32_t *sessions, const double *x0s, double *t_done, double *u0s,
+                                int32_t *status, double *t_admit, double *t_release);
 int mppi_server_stats_get(mppi_server *srv, mppi_server_stats *out);
 /* Nominal sequence (T x m FP64) of an admitted controller, after its finished steps. */
 int mppi_server_get_controls(mppi_server *srv, int32_t slot, double *u, uint64_t len);

@@ -15,7 +15,9 @@ from typing import Dict, Optional
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libmppi.so")
+# MPPI_LIBRARY names another build of the same library (the sanitizer build of the host
+# code); it must exist like the default one
+LIB_PATH = os.environ.get("MPPI_LIBRARY") or os.path.join(_HERE, "libmppi.so")
 
 ABI_VERSION = 1
 OK, EINVAL, ENOMEM, EDEVICE, EBUSY, ENUMERIC, ENOTFOUND = 0, -1, -2, -3, -4, -5, -6
@@ -96,7 +98,7 @@ class Info(C.Structure):
 
 ROLLOUT_COST_TO_GO, ROLLOUT_CRASH, ROLLOUT_STEP_SPLIT, ROLLOUT_DIAGONAL = 1, 2, 4, 8
 
-SERVE_BATCHED, SERVE_PLAIN = 0, 1
+SERVE_BATCHED, SERVE_PLAIN, SERVE_BATCHED_GRAPH = 0, 1, 2
 
 _lib = None
 
@@ -140,6 +142,8 @@ def load() -> C.CDLL:
         "mppi_server_poll": [C.c_void_p, C.c_int32, _u64p, _dp, C.POINTER(C.c_int32), _dp, C.POINTER(C.c_int32)],
         "mppi_server_replay": [C.c_void_p, C.c_int32, _dp, C.POINTER(C.c_int32), _dp, _dp, _dp,
                                C.POINTER(C.c_int32)],
+        "mppi_server_replay_sessions": [C.c_void_p, C.c_int32, C.POINTER(Config), _dp, _dp, C.c_int32, _dp,
+                                        C.POINTER(C.c_int32), _dp, _dp, _dp, C.POINTER(C.c_int32), _dp, _dp],
         "mppi_server_stats_get": [C.c_void_p, C.POINTER(ServerStats)],
         "mppi_server_get_controls": [C.c_void_p, C.c_int32, _dp, C.c_uint64],
         "mppi_mlp_create": [C.c_int32, _fp, C.POINTER(C.c_void_p)],
@@ -462,6 +466,33 @@ class Server:
         check(self._lib.mppi_server_replay(self.handle, n, _ptr(t), sl.ctypes.data_as(C.POINTER(C.c_int32)),
                                            _ptr(x), _ptr(td), _ptr(u0), st.ctypes.data_as(C.POINTER(C.c_int32))))
         return td, u0, st
+
+    def replay_sessions(self, configs, t_start, t_end, t_arrival, sessions, x0s):
+        """mppi_server_replay_sessions: controllers (keyword-argument dicts as for admit) that
+        arrive at t_start, wait for admission by the HBM budget, serve their requests and leave
+        after t_end.  Returns (t_done, u0s, status) per request and (t_admit, t_release) per
+        session."""
+        ns = len(configs)
+        keep = []
+        cfgs = (Config * ns)()
+        for j, kw in enumerate(configs):
+            kw = {k: v for k, v in kw.items() if k not in ("torch_stream", "torch_workspace")}
+            cfg, kp = make_config(**kw)
+            keep.append(kp)
+            cfgs[j] = cfg
+        ts, te = _f64(t_start).ravel(), _f64(t_end).ravel()
+        t = _f64(t_arrival).ravel()
+        sess = np.ascontiguousarray(np.asarray(sessions, dtype=np.int32).ravel())
+        n = t.size
+        x = np.zeros((n, 16))
+        x0s = np.asarray(x0s, dtype=np.float64).reshape(n, -1)
+        x[:, :x0s.shape[1]] = x0s
+        td, u0, st = np.zeros(n), np.zeros((n, 4)), np.zeros(n, dtype=np.int32)
+        ta, tr = np.zeros(ns), np.zeros(ns)
+        i32 = lambda a: a.ctypes.data_as(C.POINTER(C.c_int32))
+        check(self._lib.mppi_server_replay_sessions(self.handle, ns, cfgs, _ptr(ts), _ptr(te), n, _ptr(t), i32(sess),
+                                                    _ptr(x), _ptr(td), _ptr(u0), i32(st), _ptr(ta), _ptr(tr)))
+        return td, u0, st, ta, tr
 
     def stats(self) -> Dict:
         s = ServerStats()

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstring>
 #include <deque>
+#include <map>
 #include <mutex>
 #include <thread>
 #include <vector>
@@ -68,6 +69,14 @@ struct Entry {
 // together instead of one after the other; the update and finalize join on the batch
 // stream.
 constexpr int kSide = 2;
+struct BatchGraph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipGraphNode_t roll[kKinds] = {};
+  hipGraphNode_t upd = nullptr, fin = nullptr, down = nullptr;
+};
+constexpr size_t kMaxBatchGraphs = 64;   // kind sets kept per stream
+
 struct Batch {
   hipStream_t stream = nullptr;
   hipStream_t side[kSide] = {nullptr, nullptr};
@@ -77,7 +86,12 @@ struct Batch {
   char *h = nullptr, *d = nullptr;
   size_t off_items = 0, off_sel = 0, off_proll = 0, off_pupd = 0, off_x0 = 0, off_out = 0, bytes = 0;
   std::vector<Entry> entries;
+  // BATCHED_GRAPH: one instantiated graph per set of rollout kinds a batch holds (the plan upload,
+  // the kinds' rollouts as parallel branches, the update, the finalize and the result
+  // download); a launch rewrites the kernel nodes' grids and counts for its batch
+  std::map<uint32_t, BatchGraph> graphs;
 };
+
 
 struct Result {
   uint64_t id;
@@ -110,17 +124,129 @@ struct mppi_server {
 
 namespace {
 
-template <class Sys, int LPS, int Mode>
-void launch_roll(mppi_server *s, Batch &b, int kind, int count, int total, size_t lds, hipStream_t st) {
-  if (lds > s->lds_set[kind]) {
-    (void)hipFuncSetAttribute((const void *)rollout_batched<Sys, LPS, Mode>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)lds);
-    s->lds_set[kind] = lds;
+// The rollout instantiation of each kind (see kind_of).
+const void *roll_fn(int k) {
+  switch (k) {
+    case 0: return (const void *)rollout_batched<LinearSys<1>, 4, kStepSplit>;
+    case 1: return (const void *)rollout_batched<LinearSys<2>, 4, kStepSplit>;
+    case 2: return (const void *)rollout_batched<LinearSys<4>, 4, kStepSplit>;
+    case 3: return (const void *)rollout_batched<CartPoleSys, 4, kStepSplit>;
+    case 4: return (const void *)rollout_batched<BicycleSys, 4, kStepSplit>;
+    case 5: return (const void *)rollout_batched<QuadrotorSys, QuadrotorSys::kLPS, 0>;
+    case 6: return (const void *)rollout_batched<SwingUpSys, 4, kStepSplit>;
+    case 7: return (const void *)rollout_batched<QuadrotorSys, QuadrotorSys::kLPS, kCrashOn>;
+    case kWide + 0: return (const void *)rollout_batched<LinearSys<1>, 16, kStepSplit>;
+    case kWide + 1: return (const void *)rollout_batched<LinearSys<2>, 16, kStepSplit>;
+    case kWide + 2: return (const void *)rollout_batched<LinearSys<4>, 16, kStepSplit>;
+    case kWide + 3: return (const void *)rollout_batched<CartPoleSys, 16, kStepSplit>;
+    case kWide + 4: return (const void *)rollout_batched<BicycleSys, 16, kStepSplit>;
+    case kWide + 6: return (const void *)rollout_batched<SwingUpSys, 16, kStepSplit>;
+    case 2 * kWide + 4: return (const void *)rollout_batched<BicycleSys, 32, kStepSplit>;
+    default: return nullptr;
   }
+}
+
+// Dynamic LDS above the default needs the kernel's attribute raised first (once per size).
+int ensure_lds(mppi_server *s, int k, size_t lds) {
+  if (lds > s->lds_set[k]) {
+    const hipError_t e = hipFuncSetAttribute(roll_fn(k), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return hip_fail(e, "rollout LDS attribute");
+    s->lds_set[k] = lds;
+  }
+  return MPPI_OK;
+}
+
+// The kernel arguments of one batch, in the launch order of the kernels.
+struct BatchArgs {
+  const CtrlDesc *descs;
+  const WorkItem *items;
+  const int *sel[kKinds];
+  const int *proll[kKinds];
+  const int *pupd;
+  int count[kKinds];
+  int nb;
+};
+
+hipKernelNodeParams roll_params(BatchArgs &a, int k, int total, size_t lds, void **argv) {
+  argv[0] = (void *)&a.descs;
+  argv[1] = (void *)&a.items;
+  argv[2] = (void *)&a.sel[k];
+  argv[3] = (void *)&a.proll[k];
+  argv[4] = (void *)&a.count[k];
+  hipKernelNodeParams p{};
+  p.func = (void *)roll_fn(k);
+  p.gridDim = dim3(total > 0 ? total : 1);
+  p.blockDim = dim3(kBlock);
+  p.sharedMemBytes = (unsigned)lds;
+  p.kernelParams = argv;
+  p.extra = nullptr;
+  return p;
+}
+
+hipKernelNodeParams upd_params(BatchArgs &a, int blocks, void **argv) {
+  argv[0] = (void *)&a.descs;
+  argv[1] = (void *)&a.items;
+  argv[2] = (void *)&a.pupd;
+  argv[3] = (void *)&a.nb;
+  hipKernelNodeParams p{};
+  p.func = (void *)update_batched;
+  p.gridDim = dim3(blocks > 0 ? blocks : 1);
+  p.blockDim = dim3(kBlock);
+  p.kernelParams = argv;
+  return p;
+}
+
+hipKernelNodeParams fin_params(BatchArgs &a, void **argv) {
+  argv[0] = (void *)&a.descs;
+  argv[1] = (void *)&a.items;
+  hipKernelNodeParams p{};
+  p.func = (void *)finalize_batched;
+  p.gridDim = dim3(a.nb > 0 ? a.nb : 1);
+  p.blockDim = dim3(kFinBlock);
+  p.kernelParams = argv;
+  return p;
+}
+
+void destroy_graph(BatchGraph &G) {
+  if (G.exec) (void)hipGraphExecDestroy(G.exec);
+  if (G.graph) (void)hipGraphDestroy(G.graph);
+  G = BatchGraph();
+}
+
+// The graph of a batch stream for one set of rollout kinds: upload -> rollouts (one branch
+// per kind) -> update -> finalize -> download.  Grids and counts are placeholders until a
+// launch sets them.
+int build_graph(mppi_server *s, Batch &b, uint32_t mask, BatchArgs &a, BatchGraph &G) {
   const int B = s->cfg.max_batch;
-  hipLaunchKernelGGL((rollout_batched<Sys, LPS, Mode>), dim3(total), dim3(kBlock), lds, st, s->d_descs,
-                     (const WorkItem *)(b.d + b.off_items), (const int *)(b.d + b.off_sel) + kind * B,
-                     (const int *)(b.d + b.off_proll) + kind * (B + 1), count);
+  hipError_t e = hipGraphCreate(&G.graph, 0);
+  hipGraphNode_t up = nullptr;
+  if (e == hipSuccess) e = hipGraphAddMemcpyNode1D(&up, G.graph, nullptr, 0, b.d, b.h, b.off_out, hipMemcpyHostToDevice);
+  std::vector<hipGraphNode_t> rolls;
+  for (int k = 0; k < kKinds && e == hipSuccess; ++k) {
+    if (!(mask >> k & 1u)) continue;
+    void *argv[5];
+    const hipKernelNodeParams p = roll_params(a, k, 1, 0, argv);
+    e = hipGraphAddKernelNode(&G.roll[k], G.graph, &up, 1, &p);
+    rolls.push_back(G.roll[k]);
+  }
+  void *uargv[4], *fargv[2];
+  if (e == hipSuccess) {
+    const hipKernelNodeParams p = upd_params(a, 1, uargv);
+    e = hipGraphAddKernelNode(&G.upd, G.graph, rolls.data(), rolls.size(), &p);
+  }
+  if (e == hipSuccess) {
+    const hipKernelNodeParams p = fin_params(a, fargv);
+    e = hipGraphAddKernelNode(&G.fin, G.graph, &G.upd, 1, &p);
+  }
+  if (e == hipSuccess)
+    e = hipGraphAddMemcpyNode1D(&G.down, G.graph, &G.fin, 1, b.h + b.off_out, b.d + b.off_out,
+                                (size_t)B * 8 * sizeof(double), hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipGraphInstantiate(&G.exec, G.graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    destroy_graph(G);
+    return hip_fail(e, "batch graph");
+  }
+  return MPPI_OK;
 }
 
 int launch_batched(mppi_server *s, Batch &b, const std::vector<int> &sl) {
@@ -154,54 +280,93 @@ int launch_batched(mppi_server *s, Batch &b, const std::vector<int> &sl) {
     pupd[j + 1] = pupd[j] + S.n_upd;
     b.entries.push_back({sl[j], r.id, r.t_arrival});
   }
-  hipError_t e = hipMemcpyAsync(b.d, b.h, b.off_out, hipMemcpyHostToDevice, b.stream);
-  if (e != hipSuccess) return hip_fail(e, "batch upload");
-  // one stream per system type present (the batch stream first, then the side streams)
+  BatchArgs a;
+  a.descs = s->d_descs;
+  a.items = (const WorkItem *)(b.d + b.off_items);
+  a.pupd = (const int *)(b.d + b.off_pupd);
+  a.nb = nb;
+  uint32_t mask = 0;
   int kinds[kKinds], nk = 0;
-  for (int k = 0; k < kKinds; ++k)
-    if (cnt[k]) kinds[nk++] = k;
-  const int n_side = std::min(nk - 1, kSide);
-  if (n_side > 0) {
-    e = hipEventRecord(b.fork, b.stream);
-    for (int i = 0; i < n_side && e == hipSuccess; ++i) e = hipStreamWaitEvent(b.side[i], b.fork, 0);
-    if (e != hipSuccess) return hip_fail(e, "batch fork");
-  }
-  for (int i = 0; i < nk; ++i) {
-    const int k = kinds[i];
-    const hipStream_t st = i == 0 ? b.stream : b.side[(i - 1) % kSide];
-    const int total = proll[k * (B + 1) + cnt[k]];
-    switch (k) {
-      case 0: launch_roll<LinearSys<1>, 4, kStepSplit>(s, b, k, cnt[k], total, lds[k], st); break;
-      case 1: launch_roll<LinearSys<2>, 4, kStepSplit>(s, b, k, cnt[k], total, lds[k], st); break;
-      case 2: launch_roll<LinearSys<4>, 4, kStepSplit>(s, b, k, cnt[k], total, lds[k], st); break;
-      case 3: launch_roll<CartPoleSys, 4, kStepSplit>(s, b, k, cnt[k], total, lds[k], st); break;
-      case 4: launch_roll<BicycleSys, 4, kStepSplit>(s, b, k, cnt[k], total, lds[k], st); break;
-      case 5: launch_roll<QuadrotorSys, QuadrotorSys::kLPS, 0>(s, b, k, cnt[k], total, lds[k], st); break;
-      case 6: launch_roll<SwingUpSys, 4, kStepSplit>(s, b, k, cnt[k], total, lds[k], st); break;
-      case 7: launch_roll<QuadrotorSys, QuadrotorSys::kLPS, kCrashOn>(s, b, k, cnt[k], total, lds[k], st); break;
-      case kWide + 0: launch_roll<LinearSys<1>, 16, kStepSplit>(s, b, k, cnt[k], total, lds[k], st); break;
-      case kWide + 1: launch_roll<LinearSys<2>, 16, kStepSplit>(s, b, k, cnt[k], total, lds[k], st); break;
-      case kWide + 2: launch_roll<LinearSys<4>, 16, kStepSplit>(s, b, k, cnt[k], total, lds[k], st); break;
-      case kWide + 3: launch_roll<CartPoleSys, 16, kStepSplit>(s, b, k, cnt[k], total, lds[k], st); break;
-      case kWide + 4: launch_roll<BicycleSys, 16, kStepSplit>(s, b, k, cnt[k], total, lds[k], st); break;
-      case 2 * kWide + 4: launch_roll<BicycleSys, 32, kStepSplit>(s, b, k, cnt[k], total, lds[k], st); break;
-      default: launch_roll<SwingUpSys, 16, kStepSplit>(s, b, k, cnt[k], total, lds[k], st); break;
+  for (int k = 0; k < kKinds; ++k) {
+    a.sel[k] = (const int *)(b.d + b.off_sel) + k * B;
+    a.proll[k] = (const int *)(b.d + b.off_proll) + k * (B + 1);
+    a.count[k] = cnt[k];
+    if (cnt[k]) {
+      kinds[nk++] = k;
+      mask |= 1u << k;
+      const int rc = ensure_lds(s, k, lds[k]);
+      if (rc) return rc;
     }
   }
-  for (int i = 0; i < n_side; ++i) {
-    e = hipEventRecord(b.join[i], b.side[i]);
-    if (e == hipSuccess) e = hipStreamWaitEvent(b.stream, b.join[i], 0);
-    if (e != hipSuccess) return hip_fail(e, "batch join");
+  hipError_t e = hipSuccess;
+  if (s->cfg.mode == MPPI_SERVE_BATCHED_GRAPH) {
+    auto it = b.graphs.find(mask);
+    if (it == b.graphs.end()) {
+      if (b.graphs.size() >= kMaxBatchGraphs) {      // bounded cache (this stream is idle)
+        for (auto &kv : b.graphs) destroy_graph(kv.second);
+        b.graphs.clear();
+      }
+      BatchGraph G;
+      const int rc = build_graph(s, b, mask, a, G);
+      if (rc) return rc;
+      it = b.graphs.emplace(mask, G).first;
+    }
+    BatchGraph &G = it->second;
+    for (int i = 0; i < nk && e == hipSuccess; ++i) {
+      const int k = kinds[i];
+      void *argv[5];
+      const hipKernelNodeParams p = roll_params(a, k, proll[k * (B + 1) + cnt[k]], lds[k], argv);
+      e = hipGraphExecKernelNodeSetParams(G.exec, G.roll[k], &p);
+    }
+    void *uargv[4], *fargv[2];
+    if (e == hipSuccess) {
+      const hipKernelNodeParams p = upd_params(a, pupd[nb], uargv);
+      e = hipGraphExecKernelNodeSetParams(G.exec, G.upd, &p);
+    }
+    if (e == hipSuccess) {
+      const hipKernelNodeParams p = fin_params(a, fargv);
+      e = hipGraphExecKernelNodeSetParams(G.exec, G.fin, &p);
+    }
+    if (e == hipSuccess)
+      e = hipGraphExecMemcpyNodeSetParams1D(G.exec, G.down, b.h + b.off_out, b.d + b.off_out,
+                                            (size_t)nb * 8 * sizeof(double), hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipGraphLaunch(G.exec, b.stream);
+    if (e == hipSuccess) e = hipEventRecord(b.done, b.stream);
+    if (e != hipSuccess) return hip_fail(e, "batch graph launch");
+  } else {
+    // direct launches: one stream per system type present (the batch stream first, then
+    // the side streams), joined before the update
+    e = hipMemcpyAsync(b.d, b.h, b.off_out, hipMemcpyHostToDevice, b.stream);
+    if (e != hipSuccess) return hip_fail(e, "batch upload");
+    const int n_side = std::min(nk - 1, kSide);
+    if (n_side > 0) {
+      e = hipEventRecord(b.fork, b.stream);
+      for (int i = 0; i < n_side && e == hipSuccess; ++i) e = hipStreamWaitEvent(b.side[i], b.fork, 0);
+      if (e != hipSuccess) return hip_fail(e, "batch fork");
+    }
+    for (int i = 0; i < nk && e == hipSuccess; ++i) {
+      const int k = kinds[i];
+      const hipStream_t st = i == 0 ? b.stream : b.side[(i - 1) % kSide];
+      void *argv[5];
+      const hipKernelNodeParams p = roll_params(a, k, proll[k * (B + 1) + cnt[k]], lds[k], argv);
+      e = hipLaunchKernel(p.func, p.gridDim, p.blockDim, p.kernelParams, p.sharedMemBytes, st);
+    }
+    if (e != hipSuccess) return hip_fail(e, "batch rollout launch");
+    for (int i = 0; i < n_side; ++i) {
+      e = hipEventRecord(b.join[i], b.side[i]);
+      if (e == hipSuccess) e = hipStreamWaitEvent(b.stream, b.join[i], 0);
+      if (e != hipSuccess) return hip_fail(e, "batch join");
+    }
+    void *uargv[4], *fargv[2];
+    const hipKernelNodeParams pu = upd_params(a, pupd[nb], uargv);
+    e = hipLaunchKernel(pu.func, pu.gridDim, pu.blockDim, pu.kernelParams, 0, b.stream);
+    const hipKernelNodeParams pf = fin_params(a, fargv);
+    if (e == hipSuccess) e = hipLaunchKernel(pf.func, pf.gridDim, pf.blockDim, pf.kernelParams, 0, b.stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(b.h + b.off_out, b.d + b.off_out, (size_t)nb * 8 * sizeof(double),
+                                            hipMemcpyDeviceToHost, b.stream);
+    if (e == hipSuccess) e = hipEventRecord(b.done, b.stream);
+    if (e != hipSuccess) return hip_fail(e, "batch launch");
   }
-  hipLaunchKernelGGL(update_batched, dim3(pupd[nb]), dim3(kBlock), 0, b.stream, s->d_descs,
-                     (const WorkItem *)(b.d + b.off_items), (const int *)(b.d + b.off_pupd), nb);
-  hipLaunchKernelGGL(finalize_batched, dim3(nb), dim3(kFinBlock), 0, b.stream, s->d_descs,
-                     (const WorkItem *)(b.d + b.off_items));
-  e = hipGetLastError();
-  if (e == hipSuccess) e = hipMemcpyAsync(b.h + b.off_out, b.d + b.off_out, (size_t)nb * 8 * sizeof(double),
-                                          hipMemcpyDeviceToHost, b.stream);
-  if (e == hipSuccess) e = hipEventRecord(b.done, b.stream);
-  if (e != hipSuccess) return hip_fail(e, "batch launch");
   b.active = true;
   s->n_batches += 1;
   s->n_batched_req += nb;
@@ -319,7 +484,8 @@ extern "C" int mppi_server_create(const mppi_server_config *cfg, mppi_server **o
   if (cfg->max_slots < 1 || cfg->max_slots > 4096) return fail(MPPI_EINVAL, "max_slots outside [1, 4096]");
   if (cfg->max_inflight < 1 || cfg->max_inflight > 8) return fail(MPPI_EINVAL, "max_inflight outside [1, 8]");
   if (cfg->max_batch < 1 || cfg->max_batch > cfg->max_slots) return fail(MPPI_EINVAL, "max_batch outside [1, max_slots]");
-  if (cfg->mode != MPPI_SERVE_BATCHED && cfg->mode != MPPI_SERVE_PLAIN) return fail(MPPI_EINVAL, "unknown mode");
+  if (cfg->mode != MPPI_SERVE_BATCHED && cfg->mode != MPPI_SERVE_PLAIN && cfg->mode != MPPI_SERVE_BATCHED_GRAPH)
+    return fail(MPPI_EINVAL, "unknown mode");
   int rc = set_device(cfg->device);
   if (rc) return rc;
   auto *s = new mppi_server();
@@ -364,6 +530,7 @@ extern "C" int mppi_server_destroy(mppi_server *s) {
   }
   for (auto &S : s->slots) if (S.ctx) mppi_destroy(S.ctx);
   for (auto &b : s->batches) {
+    for (auto &kv : b.graphs) destroy_graph(kv.second);
     if (b.h) (void)hipHostFree(b.h);
     if (b.d) (void)hipFree(b.d);
     if (b.done) (void)hipEventDestroy(b.done);
@@ -550,3 +717,125 @@ extern "C" int mppi_server_get_controls(mppi_server *s, int32_t slot, double *u,
 }
 
 extern "C" double mppi_server_now(mppi_server *s) { return s ? s->now() : 0.0; }
+
+// Sessions: controllers that arrive, wait for a slot and budget, run, and leave.
+extern "C" int mppi_server_replay_sessions(mppi_server *s, int32_t n_sessions, const mppi_config *cfgs,
+                                           const double *t_start, const double *t_end, int32_t n,
+                                           const double *t_arrival, const int32_t *sessions, const double *x0s,
+                                           double *t_done, double *u0s, int32_t *status, double *t_admit,
+                                           double *t_release) {
+  int rc = check_srv(s);
+  if (rc) return rc;
+  if (n_sessions < 0 || n < 0 || (n_sessions > 0 && (!cfgs || !t_start || !t_end || !t_admit || !t_release)) ||
+      (n > 0 && (!t_arrival || !sessions || !x0s || !t_done || !u0s || !status)))
+    return fail(MPPI_EINVAL, "bad replay_sessions arguments");
+  std::vector<uint64_t> need(n_sessions);
+  for (int j = 0; j < n_sessions; ++j) {
+    if (!(t_end[j] >= t_start[j])) return fail(MPPI_EINVAL, "session %d ends before it starts", j);
+    rc = mppi_workspace_bytes(&cfgs[j], &need[j]);
+    if (rc) return rc;
+    t_admit[j] = t_release[j] = -1.0;
+  }
+  for (int i = 0; i < n; ++i) {
+    const int j = sessions[i];
+    if (j < 0 || j >= n_sessions) return fail(MPPI_EINVAL, "request %d names session %d of %d", i, j, n_sessions);
+    if (t_arrival[i] < t_start[j] || t_arrival[i] >= t_end[j])
+      return fail(MPPI_EINVAL, "request %d arrives outside its session's lifetime", i);
+    if (i > 0 && t_arrival[i] < t_arrival[i - 1]) return fail(MPPI_EINVAL, "arrival times must be non-decreasing");
+  }
+  enum { kNotYet, kQueued, kAdmitted, kReleased, kNever };
+  std::vector<int> state(n_sessions, kNotYet), slot_of(n_sessions, -1), outstanding(n_sessions, 0);
+  std::vector<std::deque<int>> pending(n_sessions);
+  std::vector<int> order(n_sessions);
+  for (int j = 0; j < n_sessions; ++j) order[j] = j;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return t_start[a] < t_start[b]; });
+  std::deque<int> adm_q;
+  std::vector<int> live;                       // admitted sessions
+  const double base = s->now();
+  int next_s = 0, next_r = 0, finished = 0, done_sessions = 0;
+  std::vector<uint64_t> ids(256);
+  std::vector<double> u(4 * 256), td(256);
+  std::vector<int32_t> st(256);
+  auto submit = [&](int i) {
+    const int j = sessions[i];
+    outstanding[j] += 1;
+    return mppi_server_submit(s, slot_of[j], x0s + 16 * (size_t)i, (uint64_t)i, base + t_arrival[i]);
+  };
+  while (finished < n || done_sessions < n_sessions) {
+    const double t = s->now() - base;
+    bool acted = false;
+    // sessions arriving
+    while (next_s < n_sessions && t_start[order[next_s]] <= t) {
+      const int j = order[next_s++];
+      if (need[j] > s->cfg.hbm_budget_bytes) { state[j] = kNever; ++done_sessions; }
+      else { state[j] = kQueued; adm_q.push_back(j); }
+      acted = true;
+    }
+    // admission, first come first served
+    while (!adm_q.empty()) {
+      const int j = adm_q.front();
+      int32_t slot = -1;
+      rc = mppi_server_admit(s, &cfgs[j], &slot);
+      if (rc == MPPI_EBUSY) break;
+      if (rc) return rc;
+      adm_q.pop_front();
+      state[j] = kAdmitted;
+      slot_of[j] = slot;
+      t_admit[j] = s->now() - base;
+      live.push_back(j);
+      while (!pending[j].empty()) {
+        rc = submit(pending[j].front());
+        if (rc) return rc;
+        pending[j].pop_front();
+      }
+      acted = true;
+    }
+    // requests arriving
+    while (next_r < n && t_arrival[next_r] <= t) {
+      const int i = next_r++, j = sessions[i];
+      if (state[j] == kAdmitted) {
+        rc = submit(i);
+        if (rc) return rc;
+      } else if (state[j] == kNever) {
+        t_done[i] = t_arrival[i];
+        for (int q = 0; q < 4; ++q) u0s[4 * (size_t)i + q] = 0.0;
+        status[i] = MPPI_EBUSY;
+        ++finished;
+      } else {
+        pending[j].push_back(i);
+      }
+      acted = true;
+    }
+    int32_t got = 0;
+    rc = mppi_server_poll(s, 256, ids.data(), u.data(), st.data(), td.data(), &got);
+    if (rc) return rc;
+    for (int q = 0; q < got; ++q) {
+      const uint64_t i = ids[q];
+      t_done[i] = td[q] - base;
+      for (int c = 0; c < 4; ++c) u0s[4 * i + c] = u[4 * q + c];
+      status[i] = st[q];
+      outstanding[sessions[i]] -= 1;
+      ++finished;
+    }
+    // sessions leaving: past their end (or past the last request of the trace), served
+    const bool trace_over = next_r == n;
+    for (size_t q = 0; q < live.size();) {
+      const int j = live[q];
+      if ((t >= t_end[j] || trace_over) && outstanding[j] == 0 && pending[j].empty()) {
+        rc = mppi_server_release(s, slot_of[j]);
+        if (rc) return rc;
+        state[j] = kReleased;
+        t_release[j] = s->now() - base;
+        ++done_sessions;
+        live[q] = live.back();
+        live.pop_back();
+        acted = true;
+      } else {
+        ++q;
+      }
+    }
+    if (trace_over && next_s == n_sessions && live.empty() && adm_q.empty()) break;
+    if (!acted && got == 0) std::this_thread::sleep_for(std::chrono::microseconds(20));
+  }
+  return MPPI_OK;
+}

@@ -4,7 +4,9 @@
   with other controllers of other systems and sizes, and under the plain policy;
 * served steps match the FP64 oracle to the parity tolerances;
 * admission respects the HBM budget and slots free up on release;
-* a real-time replay of a Poisson trace completes every request in per-controller order.
+* a real-time replay of a Poisson trace completes every request in per-controller order;
+* sessions that arrive, wait for the budget, run and leave are admitted first come first
+  served within the budget, and each one's results are those of the controller alone.
 """
 import numpy as np
 import pytest
@@ -71,10 +73,14 @@ def test_alone_equals_mix_and_plain():
         assert st["requests_done"] == 3 * len(wls) and st["mean_batch"] > 1
     with P.Server(max_slots=16, mode=P.SERVE_PLAIN) as srv:
         plain, plain_U = serve_rounds(srv, wls, 3)
+    with P.Server(max_slots=16, max_inflight=3, mode=P.SERVE_BATCHED_GRAPH) as srv:
+        graph, graph_U = serve_rounds(srv, wls, 3)
     for j, wl in enumerate(wls):
         u_alone, U_alone = alone(wl, 3)
         assert np.array_equal(mixed[j], u_alone), wl.name
         assert np.array_equal(mixed_U[j], U_alone), wl.name
+        assert np.array_equal(graph[j], u_alone), wl.name
+        assert np.array_equal(graph_U[j], U_alone), wl.name
         assert np.array_equal(plain[j], u_alone), wl.name
         assert np.array_equal(plain_U[j], U_alone), wl.name
 
@@ -130,5 +136,45 @@ def test_realtime_replay_of_a_poisson_trace():
     assert np.all(st == 0) and np.all(td >= t)
     for c, wl in enumerate(wls):
         mine = np.where(sl_idx == c)[0]
+        u_alone, _ = alone(wl, len(mine))
+        assert np.array_equal(u0[mine], u_alone)
+
+
+def _footprint(wl):
+    import ctypes as C
+    cfg, keep = P.binding.make_config(**P.controller_args(wl))
+    need = C.c_uint64(0)
+    P.binding.check(P.load().mppi_workspace_bytes(C.byref(cfg), C.byref(need)))
+    return int(need.value)
+
+
+@pytest.mark.parametrize("mode", [P.SERVE_BATCHED, P.SERVE_PLAIN, P.SERVE_BATCHED_GRAPH])
+def test_session_replay_admits_within_the_budget(mode):
+    """Six sessions arriving 50 ms apart, each 0.3 s long, under a budget that holds only the
+    two largest at once: later sessions wait in the admission queue (first come first served)
+    until earlier ones leave; every request is served, and each session's controls are those
+    of a fresh controller stepped alone from the same states."""
+    wls = [w.replace(seed=60 + i) for i, w in enumerate(mix()[:6])]
+    need = [_footprint(w) for w in wls]
+    budget = sum(sorted(need)[-2:])
+    t_start = 0.05 * np.arange(len(wls))
+    t_end = t_start + 0.3
+    trace = W.session_arrivals(t_start, t_end, rate_hz=50.0)
+    t = np.array([a for a, _ in trace])
+    sess = np.array([c for _, c in trace])
+    x0s = [np.pad(wls[c].x0, (0, 16 - wls[c].n)) for c in sess]
+    with P.Server(max_slots=8, max_inflight=3, hbm_budget_bytes=budget, mode=mode) as srv:
+        td, u0, st, ta, tr = srv.replay_sessions([P.controller_args(w) for w in wls], t_start, t_end, t, sess, x0s)
+        assert srv.stats()["bytes_used"] == 0 and srv.stats()["slots_used"] == 0
+    print("admission waits (ms):", np.round((ta - t_start) * 1e3, 2), "releases (s):", np.round(tr, 3))
+    assert np.all(st == 0) and np.all(td >= t)
+    assert np.all(ta >= t_start) and np.all(tr >= ta) and np.all(np.diff(ta) >= 0)    # first come, first served
+    assert np.max(ta - t_start) > 0.05                                               # the budget binds
+    for j in range(len(wls)):       # never more admitted at once than the budget holds
+        live = [k for k in range(len(wls)) if ta[k] <= ta[j] < tr[k]]
+        assert sum(need[k] for k in live) <= budget
+    for c, wl in enumerate(wls):
+        mine = np.where(sess == c)[0]
+        assert np.all(td[mine] >= ta[c])
         u_alone, _ = alone(wl, len(mine))
         assert np.array_equal(u0[mine], u_alone)

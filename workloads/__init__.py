@@ -301,3 +301,26 @@ def poisson_arrivals(n_controllers: int, rate_hz: float, duration_s: float, seed
             t += rng.exponential(1.0 / rate_hz)
     events.sort()
     return events
+
+
+def serving_sessions(n_controllers: int = 256, start_s: float = 3.0, min_life_s: float = 4.0, max_life_s: float = 8.0,
+                     seed: int = SEED_SERVING + 2):
+    """Controller sessions: controller c arrives at t_start ~ U[0, start_s) and stays for
+    U[min_life_s, max_life_s) seconds.  Returns (t_start, t_end) arrays."""
+    rng = np.random.default_rng(seed)
+    t0 = rng.uniform(0.0, start_s, n_controllers)
+    return t0, t0 + rng.uniform(min_life_s, max_life_s, n_controllers)
+
+
+def session_arrivals(t_start, t_end, rate_hz: float, seed: int = SEED_SERVING + 3):
+    """Sorted (time, session) arrivals: an independent Poisson process per session over its
+    lifetime [t_start, t_end)."""
+    rng = np.random.default_rng(seed)
+    events = []
+    for c, (a, b) in enumerate(zip(t_start, t_end)):
+        t = a + rng.exponential(1.0 / rate_hz)
+        while t < b:
+            events.append((t, c))
+            t += rng.exponential(1.0 / rate_hz)
+    events.sort()
+    return events
