@@ -467,6 +467,8 @@ def main():
     ap.add_argument("--no-extra", action="store_true",
                     help="time the chosen workload only (no bicycle line, no learned-dynamics leg)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
+    ap.add_argument("--serving-seconds", type=float, default=10.0,
+                    help="length of the measured serving trace after its one-second warm-up (0: no serving leg)")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="first run one plain device copy of this many bytes (a known-size kernel for "
                          "calibrating HBM byte counters in a profiler pass)")
@@ -542,8 +544,8 @@ def main():
     if learned is not None:
         out["learned"] = learned
         progress("learned dynamics trained and timed")
-    if not args.no_serving:
-        out["serving"] = serving_bench()
+    if not args.no_serving and args.serving_seconds > 0:
+        out["serving"] = serving_bench(seconds=args.serving_seconds)
         progress("serving legs done")
     # (the oracle leg runs path weighting: the cost-to-go parity is in the tests)
     if cpu_leg:
