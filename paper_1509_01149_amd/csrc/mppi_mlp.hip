@@ -1,11 +1,14 @@
-// Learned dynamics on BF16 MFMA (gfx950 v_mfma_f32_16x16x32_bf16): training kernels
-// (generic strided GEMM, bias + tanh, loss, tanh backward, bias gradients, Adam) and the
-// fused MPPI rollout whose network weights stay in registers for the whole horizon.
+// Learned dynamics on BF16 MFMA (gfx950 v_mfma_f32_16x16x32_bf16): a fused training step
+// (forward, loss, backward and the weight-gradient products of 64 samples per block, their
+// partial sums reduced with the Adam update in a second kernel) and the fused MPPI rollout
+// whose network weights stay in registers for the whole horizon.
 // Contract: include/mppi.h, "Learned dynamics".
 #include <hip/hip_runtime.h>
 
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <utility>
 #include <vector>
 
 #include "../../include/mppi.h"
@@ -50,168 +53,6 @@ __host__ __device__ __forceinline__ int feature_of(int k) {
 __host__ __device__ __forceinline__ int hidden_of(int k) {
   const int s = k >> 5, q = (k >> 3) & 3, e = k & 7;
   return 16 * (2 * s + (e >> 2)) + 4 * q + (e & 3);
-}
-
-// ------------------------------------------------------------------ generic GEMM
-// C[m][n] = sum_k A(m, k) B(k, n) over bf16 operands addressed by strides, FP32 result.
-// Block = 4 waves, each wave one 16 x 16 tile of C; K advances 32 per MFMA.  Split K:
-// block z covers k in [z k_chunk, (z + 1) k_chunk) and, when P is given, writes its
-// partial tile to P[z] (dense M x N); reduce_splits_kernel then sums the splits in order.
-// An operand whose k stride is 1 is read eight elements (16 bytes) at a time.
-static __global__ __launch_bounds__(256) void gemm_bf16_kernel(const __bf16 *__restrict__ A, long sam, long sak,
-                                                               const __bf16 *__restrict__ B, long sbk, long sbn,
-                                                               float *__restrict__ C, long scm, long scn, int M,
-                                                               int N, int K, int k_chunk, float *__restrict__ P) {
-  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  const int m0 = blockIdx.y * 32 + (w >> 1) * 16, n0 = blockIdx.x * 32 + (w & 1) * 16;
-  const int row = l & 15, kg = l >> 4;
-  const int kb = blockIdx.z * k_chunk, ke = min(K, kb + k_chunk);
-  floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-  const __bf16 z = to_bf16(0.f);
-  const bool a_row = m0 + row < M, b_row = n0 + row < N;
-  // 16-byte vector reads need k contiguous and every row start 16-byte aligned
-  const bool a_vec = sak == 1 && (sam & 7) == 0 && (reinterpret_cast<uintptr_t>(A) & 15) == 0;
-  const bool b_vec = sbk == 1 && (sbn & 7) == 0 && (reinterpret_cast<uintptr_t>(B) & 15) == 0;
-  for (int k0 = kb; k0 < ke; k0 += 32) {
-    const int k8 = k0 + 8 * kg;
-    bf16x8 a, b;
-    if (a_vec && a_row && k8 + 8 <= ke) {
-      a = *reinterpret_cast<const bf16x8 *>(A + (long)(m0 + row) * sam + k8);
-    } else {
-#pragma unroll
-      for (int e = 0; e < 8; ++e) a[e] = (a_row && k8 + e < ke) ? A[(long)(m0 + row) * sam + (long)(k8 + e) * sak] : z;
-    }
-    if (b_vec && b_row && k8 + 8 <= ke) {
-      b = *reinterpret_cast<const bf16x8 *>(B + (long)(n0 + row) * sbn + k8);
-    } else {
-#pragma unroll
-      for (int e = 0; e < 8; ++e) b[e] = (b_row && k8 + e < ke) ? B[(long)(k8 + e) * sbk + (long)(n0 + row) * sbn] : z;
-    }
-    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
-  }
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int m = m0 + 4 * kg + r, n = n0 + row;
-    if (m < M && n < N) {
-      if (P) P[((long)blockIdx.z * M + m) * N + n] = acc[r];
-      else C[(long)m * scm + (long)n * scn] = acc[r];
-    }
-  }
-}
-
-// C[m][n] = sum over the splits z = 0, 1, ... of P[z][m][n], in that order.
-static __global__ void reduce_splits_kernel(const float *__restrict__ P, int splits, int M, int N, float *C, long scm,
-                                            long scn) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= M * N) return;
-  float s = 0.f;
-  constexpr int kBatch = 16;                        // loads in flight per thread
-  for (int z0 = 0; z0 < splits; z0 += kBatch) {
-    float v[kBatch];
-#pragma unroll
-    for (int j = 0; j < kBatch; ++j) v[j] = z0 + j < splits ? P[(long)(z0 + j) * M * N + i] : 0.f;
-#pragma unroll
-    for (int j = 0; j < kBatch; ++j)
-      if (z0 + j < splits) s += v[j];
-  }
-  C[(long)(i / N) * scm + (long)(i % N) * scn] = s;
-}
-
-// ------------------------------------------------------------ elementwise kernels
-// Standardised minibatch: X = (Z[idx] - mu) / sd -> bf16 [B][16]; T = (D[idx] - mu) / sd [B][12].
-static __global__ void gather_kernel(const float *Z, const float *D, const int *order, const double *stats, int B,
-                                     __bf16 *Xh, float *Tn) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= B * 28) return;
-  const int r = i / 28, c = i - r * 28;
-  const long s = order[r];
-  if (c < 16) Xh[r * 16 + c] = to_bf16((float)(((double)Z[s * 16 + c] - stats[c]) / stats[16 + c]));
-  else Tn[r * 12 + (c - 16)] = (float)(((double)D[s * 12 + (c - 16)] - stats[32 + c - 16]) / stats[44 + c - 16]);
-}
-
-// H = tanh(Zc + b) (FP32 and bf16 copies), Zc [B][128].
-static __global__ void bias_tanh_kernel(const float *Zc, const float *b, float *Hf, __bf16 *Hh, int total) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= total) return;
-  const float h = tanh_f(Zc[i] + b[i & (kH - 1)]);
-  Hf[i] = h;
-  Hh[i] = to_bf16(h);
-}
-
-// Y = Yc + b3; dY = 2 (Y - T) / (B 12) (FP32 for the bias gradient, bf16 for the products);
-// per-block FP64 partial sums of (Y - T)^2 in a fixed order.
-static __global__ __launch_bounds__(256) void loss_grad_kernel(const float *Yc, const float *b3, const float *Tn,
-                                                               int B, float *dY, __bf16 *dYh, double *loss_part) {
-  __shared__ double red[4];
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  double sq = 0.0;
-  if (i < B * kOut) {
-    const float d = Yc[i] + b3[i % kOut] - Tn[i];
-    const float g = 2.f * d / (float)(B * kOut);
-    dY[i] = g;
-    dYh[i] = to_bf16(g);
-    sq = (double)d * (double)d;
-  }
-  const double s = block_sum(sq, red);
-  if (threadIdx.x == 0) loss_part[blockIdx.x] = s;
-}
-
-static __global__ void loss_finish_kernel(const double *loss_part, int nparts, int B, double *out) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  *out = ordered_sum(loss_part, 1, nparts) / (double)(B * kOut);   // in order, loads batched
-}
-
-// dZ = dH (1 - H^2) (FP32 and bf16).
-static __global__ void tanh_bwd_kernel(const float *dH, const float *Hf, float *dZ, __bf16 *dZh, int total) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= total) return;
-  const float h = Hf[i];
-  const float g = dH[i] * (1.f - h * h);
-  dZ[i] = g;
-  dZh[i] = to_bf16(g);
-}
-
-// out[c] = sum_r X[r][c] over B rows, fixed order (strided partials, then a block tree).
-static __global__ __launch_bounds__(256) void colsum_kernel(const float *X, int B, int ncol, float *out) {
-  __shared__ double red[4];
-  const int c = blockIdx.x;
-  double s = 0.0;
-  constexpr int kBatch = 8;                         // loads in flight per thread
-  for (int r0 = threadIdx.x; r0 < B; r0 += 256 * kBatch) {
-    float v[kBatch];
-#pragma unroll
-    for (int j = 0; j < kBatch; ++j) v[j] = r0 + 256 * j < B ? X[(long)(r0 + 256 * j) * ncol + c] : 0.f;
-#pragma unroll
-    for (int j = 0; j < kBatch; ++j)
-      if (r0 + 256 * j < B) s += (double)v[j];
-  }
-  const double t = block_sum(s, red);
-  if (threadIdx.x == 0) out[c] = (float)t;
-}
-
-// Adam on the FP32 parameters; refresh the bf16 copies of the weights.
-static __global__ void adam_kernel(float *p, const float *g, float *m, float *v, int n, float lr, float c1,
-                                   float c2, __bf16 *W1h, __bf16 *W2h, __bf16 *W3h) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const float gi = g[i];
-  const float mi = 0.9f * m[i] + 0.1f * gi;
-  const float vi = 0.999f * v[i] + 0.001f * gi * gi;
-  m[i] = mi;
-  v[i] = vi;
-  const float pi = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + 1e-8f);
-  p[i] = pi;
-  if (i < kOffB1) W1h[i - kOffW1] = to_bf16(pi);
-  else if (i >= kOffW2 && i < kOffB2) W2h[i - kOffW2] = to_bf16(pi);
-  else if (i >= kOffW3 && i < kOffB3) W3h[i - kOffW3] = to_bf16(pi);
-}
-
-static __global__ void to_bf16_kernel(const float *p, __bf16 *W1h, __bf16 *W2h, __bf16 *W3h) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= kNParams) return;
-  if (i < kOffB1) W1h[i - kOffW1] = to_bf16(p[i]);
-  else if (i >= kOffW2 && i < kOffB2) W2h[i - kOffW2] = to_bf16(p[i]);
-  else if (i >= kOffW3 && i < kOffB3) W3h[i - kOffW3] = to_bf16(p[i]);
 }
 
 // Dataset: z = (x, u) -> Z [n][16] FP32; dx = dt f(x, u) with the analytic model in FP64 -> D [n][12].
@@ -289,6 +130,359 @@ static __global__ void pack_rollout_kernel(const float *p, __bf16 *frag) {
     v = i < kOut ? p[kOffW3 + i * kH + hidden_of(32 * s + k)] : 0.f;
   }
   frag[idx] = to_bf16(v);
+}
+
+// ---------------------------------------------------------------- fused training step
+// One block = 64 samples (16 per wave).  Each wave runs its samples' forward and backward with
+// the weights as the MFMA A operand and the samples as the N dimension, so activations and
+// their gradients stay in registers in the accumulator layout (lane (q, n) holds rows 4q..4q+3
+// of sample n of every 16-row tile).  The weight gradients are sums over samples: each wave
+// writes its operands transposed ([row][sample], bfloat16) into LDS, and the block multiplies
+// them with the samples as the K dimension, giving its partial gradient; the bias gradients
+// are FP64 sums of the FP32 values over the block's samples.  A second kernel sums the blocks'
+// partials in block order and applies Adam.
+//
+// Fragments ([kTrainFrags][64 lanes] bf16x8, A operands; lane l holds row l % 16 and k slots
+// 8 (l / 16) .. + 7):
+//   [0, 44):  the forward's, as in the rollout (W1 tiles, W2 tiles x k-steps, W3 k-steps)
+//   [44, 52): W3^T tile t: A[i][k] = W3[out_of(k)][16 t + i] (out_of: layer 3's accumulator rows
+//             as the B operand delivers them; zero for the padding)
+//   [52, 84): W2^T tile t, k-step s (52 + 4 t + s): A[i][k] = W2[hidden_of(32 s + k)][16 t + i]
+constexpr int kFwdFrags = 44, kTrainFrags = 84;
+constexpr int kTrainSamples = 64;
+constexpr int kTS = 72;                    // LDS row stride (bf16) of the transposed operands
+constexpr int kNBias = 2 * kH + kOut;      // per-block bias partials: b1 [128], b2 [128], b3 [12]
+constexpr int kTrRows = kIn + kH + kH + 16 + kH + kH;   // a0, a1, a2, dY (16 rows), dZ2, dZ1
+constexpr int kFBS = kTrainSamples + 1;    // LDS row stride (floats) of the FP32 bias operands
+constexpr size_t kTrainLds = (size_t)kTrRows * kTS * 2 + (size_t)kNBias * kFBS * 4;
+static_assert((size_t)kTrainFrags * 64 * 16 <= kTrainLds, "fragments fit the operands' LDS");
+
+// Layer 3's accumulator row of B-operand k slot k in a one-k-step product (outputs 4 q .. 4 q + 3
+// of lane group q in slots 8 q .. 8 q + 3), or -1 for the zero padding.
+__host__ __device__ __forceinline__ int out_of(int k) {
+  const int o = feature_of(k);
+  return o >= 0 && o < kOut ? o : -1;
+}
+
+static __global__ void pack_train_kernel(const float *p, __bf16 *frag) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;   // over kTrainFrags * 64 * 8
+  if (idx >= kTrainFrags * 64 * 8) return;
+  const int e = idx & 7, l = (idx >> 3) & 63, f = idx >> 9;
+  const int i = l & 15, k = 8 * (l >> 4) + e;
+  float v = 0.f;
+  if (f < 8) {
+    const int c = feature_of(k);
+    v = c >= 0 ? p[kOffW1 + (16 * f + i) * kIn + c] : 0.f;
+  } else if (f < 40) {
+    const int t = (f - 8) >> 2, s = (f - 8) & 3;
+    v = p[kOffW2 + (16 * t + i) * kH + hidden_of(32 * s + k)];
+  } else if (f < 44) {
+    const int s = f - 40;
+    v = i < kOut ? p[kOffW3 + i * kH + hidden_of(32 * s + k)] : 0.f;
+  } else if (f < 52) {
+    const int t = f - 44, o = out_of(k);
+    v = o >= 0 ? p[kOffW3 + o * kH + 16 * t + i] : 0.f;
+  } else {
+    const int t = (f - 52) >> 2, s = (f - 52) & 3;
+    v = p[kOffW2 + hidden_of(32 * s + k) * kH + 16 * t + i];
+  }
+  frag[idx] = to_bf16(v);
+}
+
+struct TrainArgs {
+  const float *Z, *D;      // dataset [n][16], [n][12] FP32, with order: the minibatch's rows
+  const int *order;        // [B] dataset rows, or NULL: inputs from Xh / Tn
+  const __bf16 *Xh;        // [B][16] standardised inputs (bfloat16) when order is NULL
+  const float *Tn;         // [B][12] standardised targets when order is NULL (backward only)
+  const double *stats;     // mu_in, sd_in, mu_out, sd_out
+  const float *p;          // FP32 parameters (the biases are read from here)
+  const bf16x8 *frag;      // [kTrainFrags][64]
+  int B;
+  int backward;            // 0: forward only (Yc out), 1: forward, loss and gradient partials
+  float *Yc;               // [B][12] W3 a2 without the bias (forward only)
+  float *P;                // [blocks][kNParams] weight-gradient partials (bias slots unused)
+  double *Pb;              // [blocks][kNBias] bias-gradient partials
+  double *Pl;              // [blocks] sums of squared errors
+};
+
+static __global__ __launch_bounds__(256) void train_step_kernel(const TrainArgs a) {
+  extern __shared__ float4 lds4[];
+  __shared__ double red[4];
+  bf16x8 *sF = reinterpret_cast<bf16x8 *>(lds4);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63, q = l >> 4, nn = l & 15;
+  const int col = 16 * w + nn;                          // the sample's column in the block
+  const int smp = blockIdx.x * kTrainSamples + col;     // its index in the minibatch
+  const bool valid = smp < a.B;
+  for (int i = threadIdx.x; i < kTrainFrags * 64; i += 256) sF[i] = a.frag[i];
+  // inputs: features 4q..4q+3 of this lane's sample in k slots 8q..8q+3; targets 4q..4q+3
+  bf16x8 bz;
+  float tgt[4] = {0.f, 0.f, 0.f, 0.f};
+  const __bf16 zb = to_bf16(0.f);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    bz[r] = zb;
+    bz[4 + r] = zb;
+  }
+  if (valid) {
+    if (a.order) {
+      const long row = a.order[smp];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int c = 4 * q + r;
+        bz[r] = to_bf16((float)(((double)a.Z[row * 16 + c] - a.stats[c]) / a.stats[16 + c]));
+        if (q < 3) tgt[r] = (float)(((double)a.D[row * 12 + c] - a.stats[32 + c]) / a.stats[44 + c]);
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        bz[r] = a.Xh[(long)smp * 16 + 4 * q + r];
+        if (q < 3 && a.backward) tgt[r] = a.Tn[(long)smp * 12 + 4 * q + r];
+      }
+    }
+  }
+  __syncthreads();
+  // forward: H1 = tanh(W1 a0 + b1), H2 = tanh(W2 a1 + b2), Yc = W3 a2
+  float h1[32], h2[32];
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+    floatx4 c = {0.f, 0.f, 0.f, 0.f};
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(sF[t * 64 + l], bz, c, 0, 0, 0);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) h1[4 * t + r] = tanh_f(c[r] + a.p[kOffB1 + 16 * t + 4 * q + r]);
+  }
+  bf16x8 a1op[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+#pragma unroll
+    for (int e = 0; e < 8; ++e) a1op[s][e] = to_bf16(h1[4 * (2 * s + (e >> 2)) + (e & 3)]);
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+    floatx4 c = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < 4; ++s) c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(sF[(8 + 4 * t + s) * 64 + l], a1op[s], c, 0, 0, 0);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) h2[4 * t + r] = tanh_f(c[r] + a.p[kOffB2 + 16 * t + 4 * q + r]);
+  }
+  bf16x8 a2op[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+#pragma unroll
+    for (int e = 0; e < 8; ++e) a2op[s][e] = to_bf16(h2[4 * (2 * s + (e >> 2)) + (e & 3)]);
+  floatx4 y = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int s = 0; s < 4; ++s) y = __builtin_amdgcn_mfma_f32_16x16x32_bf16(sF[(40 + s) * 64 + l], a2op[s], y, 0, 0, 0);
+  if (!a.backward) {
+    if (valid && q < 3)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) a.Yc[(long)smp * kOut + 4 * q + r] = y[r];
+    return;
+  }
+  // loss and its gradient dY = 2 (Y - T) / (12 B); zero for the padding samples and rows
+  float g[4];
+  double sq = 0.0;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int o = 4 * q + r;
+    g[r] = 0.f;
+    if (valid && q < 3) {
+      const float d = y[r] + a.p[kOffB3 + o] - tgt[r];
+      g[r] = 2.f * d / (float)(a.B * kOut);
+      sq = fma((double)d, (double)d, sq);
+    }
+  }
+  bf16x8 gop;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    gop[r] = to_bf16(g[r]);
+    gop[4 + r] = zb;
+  }
+  // dZ2 = (W3^T dY) (1 - H2^2), dZ1 = (W2^T dZ2) (1 - H1^2)
+  float dz2[32], dz1[32];
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+    floatx4 c = {0.f, 0.f, 0.f, 0.f};
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(sF[(44 + t) * 64 + l], gop, c, 0, 0, 0);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const float h = h2[4 * t + r];
+      dz2[4 * t + r] = c[r] * (1.f - h * h);
+    }
+  }
+  bf16x8 dz2op[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+#pragma unroll
+    for (int e = 0; e < 8; ++e) dz2op[s][e] = to_bf16(dz2[4 * (2 * s + (e >> 2)) + (e & 3)]);
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+    floatx4 c = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < 4; ++s) c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(sF[(52 + 4 * t + s) * 64 + l], dz2op[s], c, 0, 0, 0);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const float h = h1[4 * t + r];
+      dz1[4 * t + r] = c[r] * (1.f - h * h);
+    }
+  }
+  __syncthreads();   // every wave is done with the fragments: their LDS now takes the operands
+  __bf16 *T0 = reinterpret_cast<__bf16 *>(lds4);          // a0  [16][kTS]
+  __bf16 *T1 = T0 + kIn * kTS;                               // a1  [128][kTS]
+  __bf16 *T2 = T1 + kH * kTS;                                // a2  [128][kTS]
+  __bf16 *TY = T2 + kH * kTS;                                // dY  [16][kTS]
+  __bf16 *TZ2 = TY + 16 * kTS;                               // dZ2 [128][kTS]
+  __bf16 *TZ1 = TZ2 + kH * kTS;                              // dZ1 [128][kTS]
+  float *FB = reinterpret_cast<float *>(TZ1 + kH * kTS);     // [kNBias][kFBS]: dZ1, dZ2, dY (FP32)
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    T0[(4 * q + r) * kTS + col] = valid ? bz[r] : zb;
+    TY[(4 * q + r) * kTS + col] = gop[r];
+  }
+#pragma unroll
+  for (int t = 0; t < 8; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * t + 4 * q + r;
+      T1[row * kTS + col] = valid ? a1op[t >> 1][4 * (t & 1) + r] : zb;
+      T2[row * kTS + col] = valid ? a2op[t >> 1][4 * (t & 1) + r] : zb;
+      TZ2[row * kTS + col] = dz2op[t >> 1][4 * (t & 1) + r];
+      TZ1[row * kTS + col] = to_bf16(dz1[4 * t + r]);
+      FB[row * kFBS + col] = dz1[4 * t + r];
+      FB[(kH + row) * kFBS + col] = dz2[4 * t + r];
+    }
+  if (q < 3)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) FB[(2 * kH + 4 * q + r) * kFBS + col] = g[r];
+  const double loss = block_sum(sq, red);      // its barriers also order the LDS writes above
+  if (threadIdx.x == 0) a.Pl[blockIdx.x] = loss;
+  // bias partials: FP64 sums over the block's samples, in sample order
+  for (int r = threadIdx.x; r < kNBias; r += 256) {
+    double acc = 0.0;
+    for (int c = 0; c < kTrainSamples; ++c) acc += (double)FB[r * kFBS + c];
+    a.Pb[(long)blockIdx.x * kNBias + r] = acc;
+  }
+  // weight-gradient partials: sum over the block's 64 samples (two k-steps of 32)
+  float *P = a.P + (long)blockIdx.x * kNParams;
+  const int ar = l & 15, ak = 8 * (l >> 4);
+  // dW2 = dZ2 a1^T: this wave's row tiles 2w, 2w+1 against the eight column tiles
+#pragma unroll
+  for (int ti = 2 * w; ti < 2 * w + 2; ++ti) {
+    floatx4 acc[8];
+#pragma unroll
+    for (int tj = 0; tj < 8; ++tj) acc[tj] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) {
+      const bf16x8 A = *reinterpret_cast<const bf16x8 *>(TZ2 + (16 * ti + ar) * kTS + 32 * ks + ak);
+#pragma unroll
+      for (int tj = 0; tj < 8; ++tj) {
+        const bf16x8 Bv = *reinterpret_cast<const bf16x8 *>(T1 + (16 * tj + ar) * kTS + 32 * ks + ak);
+        acc[tj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, Bv, acc[tj], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int tj = 0; tj < 8; ++tj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) P[kOffW2 + (16 * ti + 4 * q + r) * kH + 16 * tj + nn] = acc[tj][r];
+  }
+  // dW3 = dY a2^T (rows 12..15 of the tile are padding) and dW1 = dZ1 a0^T: tiles 2w, 2w+1
+#pragma unroll
+  for (int tt = 2 * w; tt < 2 * w + 2; ++tt) {
+    floatx4 c3 = {0.f, 0.f, 0.f, 0.f}, c1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) {
+      const bf16x8 A3 = *reinterpret_cast<const bf16x8 *>(TY + ar * kTS + 32 * ks + ak);
+      const bf16x8 B3 = *reinterpret_cast<const bf16x8 *>(T2 + (16 * tt + ar) * kTS + 32 * ks + ak);
+      c3 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A3, B3, c3, 0, 0, 0);
+      const bf16x8 A1 = *reinterpret_cast<const bf16x8 *>(TZ1 + (16 * tt + ar) * kTS + 32 * ks + ak);
+      const bf16x8 B1 = *reinterpret_cast<const bf16x8 *>(T0 + ar * kTS + 32 * ks + ak);
+      c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A1, B1, c1, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      if (q < 3) P[kOffW3 + (4 * q + r) * kH + 16 * tt + nn] = c3[r];
+      P[kOffW1 + (16 * tt + 4 * q + r) * kIn + nn] = c1[r];
+    }
+  }
+}
+
+// k slot of the B operand that carries hidden unit h in a k-step product over a hidden layer
+// (the inverse of hidden_of): h = 16 (2 s + e / 4) + 4 q + e % 4 at k = 32 s + 8 q + e.
+__device__ __forceinline__ int kslot_of_hidden(int h) {
+  const int a = h >> 4, rem = h & 15;
+  return 32 * (a >> 1) + 8 * (rem >> 2) + 4 * (a & 1) + (rem & 3);
+}
+// Index of A-operand element (row i, k slot k) of fragment f in the packed array.
+__device__ __forceinline__ int frag_slot(int f, int i, int k) { return (f * 64 + 16 * (k >> 3) + i) * 8 + (k & 7); }
+
+// The new value of parameter i into every training fragment that holds it (the inverse of
+// pack_train_kernel's mapping; padding slots keep their zeros).
+__device__ __forceinline__ void scatter_frag(__bf16 *frag, int i, float v) {
+  const __bf16 b = to_bf16(v);
+  if (i < kOffB1) {                                   // W1 [128][16]
+    const int row = i / kIn, c = i % kIn;
+    frag[frag_slot(row >> 4, row & 15, 8 * (c >> 2) + (c & 3))] = b;
+  } else if (i >= kOffW2 && i < kOffB2) {             // W2 [128][128]
+    const int row = (i - kOffW2) / kH, cj = (i - kOffW2) % kH;
+    const int k = kslot_of_hidden(cj), kb = kslot_of_hidden(row);
+    frag[frag_slot(8 + 4 * (row >> 4) + (k >> 5), row & 15, k & 31)] = b;
+    frag[frag_slot(52 + 4 * (cj >> 4) + (kb >> 5), cj & 15, kb & 31)] = b;
+  } else if (i >= kOffW3 && i < kOffB3) {             // W3 [12][128]
+    const int o = (i - kOffW3) / kH, h = (i - kOffW3) % kH;
+    const int k = kslot_of_hidden(h);
+    frag[frag_slot(40 + (k >> 5), o, k & 31)] = b;
+    frag[frag_slot(44 + (h >> 4), h & 15, 8 * (o >> 2) + (o & 3))] = b;
+  }
+}
+
+// Gradient = the blocks' partials summed in a fixed order (weights in FP32: each of the four
+// lanes of a quad sums every fourth block in block order, then the quad adds its four sums as
+// (l0 + l1) + (l2 + l3); biases in FP64 in block order, then rounded once); with update, Adam on
+// the FP32 parameters, step number *adam_t + step + 1 and step size *lr (device memory, so a
+// captured sequence of steps can be replayed), and the new weights scattered into the training
+// fragments.  One quad of lanes per parameter; lane 0 of the grid also writes the loss.
+static __global__ void train_reduce_kernel(const float *__restrict__ P, const double *__restrict__ Pb,
+                                           const double *__restrict__ Pl, int nblk, int B, float *g, float *p,
+                                           float *m, float *v, int update, const int64_t *adam_t, int step,
+                                           const float *lr, __bf16 *frag, double *loss_out) {
+  const int gt = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = gt >> 2, sub = gt & 3;
+  if (gt == 0 && loss_out) *loss_out = ordered_sum(Pl, 1, nblk) / (double)(B * kOut);
+  if (i >= kNParams) return;                          // whole quads leave together (kNParams quads)
+  int bias = -1;
+  if (i >= kOffB1 && i < kOffB1 + kH) bias = i - kOffB1;
+  else if (i >= kOffB2 && i < kOffB2 + kH) bias = kH + (i - kOffB2);
+  else if (i >= kOffB3) bias = 2 * kH + (i - kOffB3);
+  float gi;
+  if (bias >= 0) {
+    gi = sub == 0 ? (float)ordered_sum(Pb + bias, kNBias, nblk) : 0.f;
+    gi = __shfl(gi, threadIdx.x & ~3, 64);
+  } else {
+    float s = 0.f;
+    constexpr int kBatch = 16;                      // loads in flight per lane
+    for (int b0 = sub; b0 < nblk; b0 += 4 * kBatch) {
+      float t[kBatch];
+#pragma unroll
+      for (int j = 0; j < kBatch; ++j) t[j] = b0 + 4 * j < nblk ? P[(long)(b0 + 4 * j) * kNParams + i] : 0.f;
+#pragma unroll
+      for (int j = 0; j < kBatch; ++j)
+        if (b0 + 4 * j < nblk) s += t[j];
+    }
+    const float s1 = __shfl_xor(s, 1, 64);            // the partner's sum (l0 <-> l1, l2 <-> l3)
+    const float pair = (sub & 1) ? s1 + s : s + s1;   // l0 + l1 (or l2 + l3) on both lanes
+    const float other = __shfl_xor(pair, 2, 64);
+    gi = (sub & 2) ? other + pair : pair + other;
+  }
+  if (sub != 0) return;
+  g[i] = gi;
+  if (!update) return;
+  const double t = (double)(*adam_t + step + 1);
+  const float c1 = (float)(1.0 - pow(0.9, t)), c2 = (float)(1.0 - pow(0.999, t));
+  const float mi = 0.9f * m[i] + 0.1f * gi;
+  const float vi = 0.999f * v[i] + 0.001f * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  const float pi = p[i] - *lr * (mi / c1) / (sqrtf(vi / c2) + 1e-8f);
+  p[i] = pi;
+  scatter_frag(frag, i, pi);
 }
 
 // ---------------------------------------------------------------- fused rollout
@@ -468,7 +662,7 @@ using namespace mppi;
 struct mppi_mlp {
   int device = 0;
   float *p = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;   // FP32 params, grads, Adam moments
-  __bf16 *W1h = nullptr, *W2h = nullptr, *W3h = nullptr;
+  __bf16 *frag = nullptr;             // training fragments, packed from p after every update
   double *stats = nullptr;
   int64_t adam_t = 0;
   float *Z = nullptr, *D = nullptr;   // dataset
@@ -477,130 +671,100 @@ struct mppi_mlp {
   int cap = 0;
   char *scratch = nullptr;
   hipStream_t stream = nullptr;
+  // training: the Adam step count and step size the captured steps read (device), the
+  // minibatch order and per-step losses (device, capacities in elements), and one captured
+  // graph of a whole call per (steps, batch), valid while these buffers stay in place
+  int64_t *d_adam_t = nullptr;
+  float *d_lr = nullptr;
+  int32_t *d_order = nullptr;
+  int64_t order_cap = 0;
+  double *d_losses = nullptr;
+  int64_t loss_cap = 0;
+  int64_t h_adam_t = 0;
+  float h_lr = 0.f;
+  std::map<std::pair<int64_t, int>, hipGraphExec_t> graphs;
 };
 
 namespace {
 
-constexpr int kMaxSplits = 64;     // split-K partial tiles for the weight gradients
-constexpr int kSplitChunk = 128;   // samples per split (a multiple of the MFMA's 32)
-
+// Per-minibatch buffers (capacity B): direct inputs, forward outputs, the blocks' partials.
 struct BatchBufs {
-  __bf16 *Xh, *H1h, *H2h, *dYh, *dZ1h, *dZ2h;
-  float *Tn, *Z1, *H1, *Z2, *H2, *Y, *dY, *dH2, *dZ2, *dH1, *dZ1;
-  float *part;                     // [kMaxSplits][kH][kH]
-  double *loss_part, *loss;
-  int *order;
+  __bf16 *Xh;                      // [B][16]
+  float *Tn, *Yc;                  // [B][12]
+  float *P;                        // [blocks][kNParams]
+  double *Pb, *Pl, *loss;          // [blocks][kNBias], [blocks], [1]
 };
 
 size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
+inline int train_blocks(int B) { return (B + kTrainSamples - 1) / kTrainSamples; }
 
-size_t batch_bytes(int B) {
-  size_t o = 0;
-  auto take = [&](size_t b) { o = al256(o + b); };
-  take((size_t)B * 16 * 2);                       // Xh
-  for (int i = 0; i < 2; ++i) take((size_t)B * kH * 2);   // H1h H2h
-  take((size_t)B * kOut * 2);                     // dYh
-  for (int i = 0; i < 2; ++i) take((size_t)B * kH * 2);   // dZ1h dZ2h
-  take((size_t)B * kOut * 4);                     // Tn
-  for (int i = 0; i < 4; ++i) take((size_t)B * kH * 4);   // Z1 H1 Z2 H2
-  take((size_t)B * kOut * 4);                     // Y
-  take((size_t)B * kOut * 4);                     // dY
-  for (int i = 0; i < 4; ++i) take((size_t)B * kH * 4);   // dH2 dZ2 dH1 dZ1
-  take((size_t)((B * kOut + 255) / 256 + 1) * 8);  // loss_part
-  take(8);                                        // loss
-  take((size_t)B * 4);                            // order
-  take((size_t)kMaxSplits * kH * kH * 4);         // part
-  return o;
-}
-
-BatchBufs carve(char *base, int B) {
+BatchBufs carve(char *base, int B, size_t *total = nullptr) {
   BatchBufs b;
   size_t o = 0;
   auto take = [&](size_t bytes) { char *r = base + o; o = al256(o + bytes); return r; };
+  const int nbk = train_blocks(B);
   b.Xh = (__bf16 *)take((size_t)B * 16 * 2);
-  b.H1h = (__bf16 *)take((size_t)B * kH * 2);
-  b.H2h = (__bf16 *)take((size_t)B * kH * 2);
-  b.dYh = (__bf16 *)take((size_t)B * kOut * 2);
-  b.dZ1h = (__bf16 *)take((size_t)B * kH * 2);
-  b.dZ2h = (__bf16 *)take((size_t)B * kH * 2);
   b.Tn = (float *)take((size_t)B * kOut * 4);
-  b.Z1 = (float *)take((size_t)B * kH * 4);
-  b.H1 = (float *)take((size_t)B * kH * 4);
-  b.Z2 = (float *)take((size_t)B * kH * 4);
-  b.H2 = (float *)take((size_t)B * kH * 4);
-  b.Y = (float *)take((size_t)B * kOut * 4);
-  b.dY = (float *)take((size_t)B * kOut * 4);
-  b.dH2 = (float *)take((size_t)B * kH * 4);
-  b.dZ2 = (float *)take((size_t)B * kH * 4);
-  b.dH1 = (float *)take((size_t)B * kH * 4);
-  b.dZ1 = (float *)take((size_t)B * kH * 4);
-  b.loss_part = (double *)take((size_t)((B * kOut + 255) / 256 + 1) * 8);
+  b.Yc = (float *)take((size_t)B * kOut * 4);
+  b.P = (float *)take((size_t)nbk * kNParams * 4);
+  b.Pb = (double *)take((size_t)nbk * kNBias * 8);
+  b.Pl = (double *)take((size_t)nbk * 8);
   b.loss = (double *)take(8);
-  b.order = (int *)take((size_t)B * 4);
-  b.part = (float *)take((size_t)kMaxSplits * kH * kH * 4);
+  if (total) *total = o;
   return b;
+}
+
+void clear_graphs(mppi_mlp *m) {
+  for (auto &kv : m->graphs) (void)hipGraphExecDestroy(kv.second);
+  m->graphs.clear();
 }
 
 int ensure_cap(mppi_mlp *m, int B) {
   if (B <= m->cap) return MPPI_OK;
+  (void)hipStreamSynchronize(m->stream);
+  clear_graphs(m);
   if (m->scratch) (void)hipFree(m->scratch);
   m->scratch = nullptr;
   m->cap = 0;
-  HIP_TRY(hipMalloc((void **)&m->scratch, batch_bytes(B)));
+  size_t bytes = 0;
+  (void)carve(nullptr, B, &bytes);
+  HIP_TRY(hipMalloc((void **)&m->scratch, bytes));
   m->cap = B;
   return MPPI_OK;
 }
 
-// part: split-K scratch of kMaxSplits * M * N floats, or NULL for no split.  A long K
-// (the weight gradients sum over the minibatch) is cut into kSplitChunk pieces so the
-// 16 output tiles become hundreds of blocks.
-void gemm(hipStream_t s, const __bf16 *A, long sam, long sak, const __bf16 *B, long sbk, long sbn, float *C, long scm,
-          long scn, int M, int N, int K, float *part = nullptr) {
-  const dim3 grid((N + 31) / 32, (M + 31) / 32);
-  int splits = part ? (K + kSplitChunk - 1) / kSplitChunk : 1;
-  if (splits > kMaxSplits) splits = kMaxSplits;
-  if (splits <= 1) {
-    hipLaunchKernelGGL(gemm_bf16_kernel, grid, dim3(256), 0, s, A, sam, sak, B, sbk, sbn, C, scm, scn, M, N, K, K,
-                       (float *)nullptr);
-    return;
-  }
-  const int chunk = ((K + splits - 1) / splits + 31) / 32 * 32;
-  splits = (K + chunk - 1) / chunk;
-  hipLaunchKernelGGL(gemm_bf16_kernel, dim3(grid.x, grid.y, splits), dim3(256), 0, s, A, sam, sak, B, sbk, sbn, C, scm,
-                     scn, M, N, K, chunk, part);
-  hipLaunchKernelGGL(reduce_splits_kernel, dim3((M * N + 255) / 256), dim3(256), 0, s, part, splits, M, N, C, scm, scn);
-}
-
 inline int nb(long n, int t = 256) { return (int)((n + t - 1) / t); }
 
-// Forward (and optionally backward) of one minibatch already standardised into b.Xh / b.Tn.
-void fwd(mppi_mlp *m, const BatchBufs &b, int B) {
-  hipStream_t s = m->stream;
-  gemm(s, b.Xh, 16, 1, m->W1h, 1, 16, b.Z1, kH, 1, B, kH, kIn);
-  hipLaunchKernelGGL(bias_tanh_kernel, dim3(nb((long)B * kH)), dim3(256), 0, s, b.Z1, m->p + kOffB1, b.H1, b.H1h, B * kH);
-  gemm(s, b.H1h, kH, 1, m->W2h, 1, kH, b.Z2, kH, 1, B, kH, kH);
-  hipLaunchKernelGGL(bias_tanh_kernel, dim3(nb((long)B * kH)), dim3(256), 0, s, b.Z2, m->p + kOffB2, b.H2, b.H2h, B * kH);
-  gemm(s, b.H2h, kH, 1, m->W3h, 1, kH, b.Y, kOut, 1, B, kOut, kH);
+int prepare_train_kernel() {
+  static bool done = false;
+  if (!done) {
+    HIP_TRY(hipFuncSetAttribute((const void *)train_step_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)kTrainLds));
+    done = true;
+  }
+  return MPPI_OK;
 }
 
-void bwd(mppi_mlp *m, const BatchBufs &b, int B) {
-  hipStream_t s = m->stream;
-  const int nparts = nb((long)B * kOut);
-  hipLaunchKernelGGL(loss_grad_kernel, dim3(nparts), dim3(256), 0, s, b.Y, m->p + kOffB3, b.Tn, B, b.dY, b.dYh,
-                     b.loss_part);
-  hipLaunchKernelGGL(loss_finish_kernel, dim3(1), dim3(64), 0, s, b.loss_part, nparts, B, b.loss);
-  // data gradients
-  gemm(s, b.dYh, kOut, 1, m->W3h, kH, 1, b.dH2, kH, 1, B, kH, kOut);
-  hipLaunchKernelGGL(tanh_bwd_kernel, dim3(nb((long)B * kH)), dim3(256), 0, s, b.dH2, b.H2, b.dZ2, b.dZ2h, B * kH);
-  gemm(s, b.dZ2h, kH, 1, m->W2h, kH, 1, b.dH1, kH, 1, B, kH, kH);
-  hipLaunchKernelGGL(tanh_bwd_kernel, dim3(nb((long)B * kH)), dim3(256), 0, s, b.dH1, b.H1, b.dZ1, b.dZ1h, B * kH);
-  // weight gradients: sum over the batch (k = sample)
-  gemm(s, b.dYh, 1, kOut, b.H2h, kH, 1, m->g + kOffW3, kH, 1, kOut, kH, B, b.part);
-  gemm(s, b.dZ2h, 1, kH, b.H1h, kH, 1, m->g + kOffW2, kH, 1, kH, kH, B, b.part);
-  gemm(s, b.dZ1h, 1, kH, b.Xh, 16, 1, m->g + kOffW1, kIn, 1, kH, kIn, B, b.part);
-  hipLaunchKernelGGL(colsum_kernel, dim3(kOut), dim3(256), 0, s, b.dY, B, kOut, m->g + kOffB3);
-  hipLaunchKernelGGL(colsum_kernel, dim3(kH), dim3(256), 0, s, b.dZ2, B, kH, m->g + kOffB2);
-  hipLaunchKernelGGL(colsum_kernel, dim3(kH), dim3(256), 0, s, b.dZ1, B, kH, m->g + kOffB1);
+void repack(mppi_mlp *m) {
+  hipLaunchKernelGGL(pack_train_kernel, dim3(nb(kTrainFrags * 64 * 8)), dim3(256), 0, m->stream, m->p, m->frag);
+}
+
+TrainArgs train_args(mppi_mlp *m, const BatchBufs &b, int B, const int *order, int backward) {
+  TrainArgs t;
+  std::memset(&t, 0, sizeof(t));
+  t.Z = m->Z; t.D = m->D; t.order = order; t.Xh = b.Xh; t.Tn = b.Tn; t.stats = m->stats; t.p = m->p;
+  t.frag = (const bf16x8 *)m->frag; t.B = B; t.backward = backward; t.Yc = b.Yc; t.P = b.P; t.Pb = b.Pb; t.Pl = b.Pl;
+  return t;
+}
+
+// One minibatch on stream st: the fused forward/backward, then the reduction (with update,
+// Adam at step *d_adam_t + step + 1 and the new weights into the fragments).
+void step(mppi_mlp *m, const BatchBufs &b, int B, const int *order, bool update, int step_no, hipStream_t st,
+          double *loss_out) {
+  const TrainArgs t = train_args(m, b, B, order, 1);
+  hipLaunchKernelGGL(train_step_kernel, dim3(train_blocks(B)), dim3(256), kTrainLds, st, t);
+  hipLaunchKernelGGL(train_reduce_kernel, dim3(nb(4L * kNParams)), dim3(256), 0, st, b.P, b.Pb, b.Pl, train_blocks(B),
+                     B, m->g, m->p, m->m, m->v, update ? 1 : 0, m->d_adam_t, step_no, m->d_lr, m->frag, loss_out);
 }
 
 int check_mlp(mppi_mlp *m) {
@@ -634,16 +798,18 @@ extern "C" int mppi_mlp_create(int32_t device, const float *params, mppi_mlp **o
   if (rc) return rc;
   auto *m = new mppi_mlp();
   m->device = device;
+  int rc2 = prepare_train_kernel();
+  if (rc2) { delete m; return rc2; }
   hipError_t e = hipMalloc((void **)&m->p, kNParams * 4 * 4);
-  if (e == hipSuccess) e = hipMalloc((void **)&m->W1h, (size_t)(kH * kIn + kH * kH + kOut * kH) * 2);
-  if (e == hipSuccess) e = hipMalloc((void **)&m->stats, MPPI_MLP_STATS * 8);
+  if (e == hipSuccess) e = hipMalloc((void **)&m->frag, (size_t)kTrainFrags * 64 * 16);
+  if (e == hipSuccess) e = hipMalloc((void **)&m->stats, MPPI_MLP_STATS * 8 + 256);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&m->stream, hipStreamNonBlocking);
   if (e != hipSuccess) { mppi_mlp_destroy(m); return fail(MPPI_ENOMEM, "mlp allocation: %s", hipGetErrorString(e)); }
   m->g = m->p + kNParams;
   m->m = m->g + kNParams;
   m->v = m->m + kNParams;
-  m->W2h = m->W1h + kH * kIn;
-  m->W3h = m->W2h + kH * kH;
+  m->d_adam_t = (int64_t *)(m->stats + MPPI_MLP_STATS);
+  m->d_lr = (float *)(m->d_adam_t + 1);
   std::vector<float> zeros(3 * kNParams, 0.f);
   std::vector<double> st(MPPI_MLP_STATS, 0.0);
   for (int i = 16; i < 32; ++i) st[i] = 1.0;
@@ -652,7 +818,7 @@ extern "C" int mppi_mlp_create(int32_t device, const float *params, mppi_mlp **o
   if (e == hipSuccess) e = hipMemcpy(m->g, zeros.data(), zeros.size() * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(m->stats, st.data(), st.size() * 8, hipMemcpyHostToDevice);
   if (e != hipSuccess) { mppi_mlp_destroy(m); return hip_fail(e, "mlp upload"); }
-  hipLaunchKernelGGL(to_bf16_kernel, dim3(nb(kNParams)), dim3(256), 0, m->stream, m->p, m->W1h, m->W2h, m->W3h);
+  repack(m);
   e = hipStreamSynchronize(m->stream);
   if (e != hipSuccess) { mppi_mlp_destroy(m); return hip_fail(e, "mlp init"); }
   *out = m;
@@ -664,7 +830,10 @@ extern "C" int mppi_mlp_destroy(mppi_mlp *m) {
   (void)hipSetDevice(m->device);
   if (m->stream) (void)hipStreamSynchronize(m->stream);
   if (m->p) (void)hipFree(m->p);
-  if (m->W1h) (void)hipFree(m->W1h);
+  clear_graphs(m);
+  if (m->frag) (void)hipFree(m->frag);
+  if (m->d_order) (void)hipFree(m->d_order);
+  if (m->d_losses) (void)hipFree(m->d_losses);
   if (m->stats) (void)hipFree(m->stats);
   if (m->Z) (void)hipFree(m->Z);
   if (m->scratch) (void)hipFree(m->scratch);
@@ -680,6 +849,8 @@ extern "C" int mppi_mlp_set_dataset(mppi_mlp *m, const mppi_quadrotor_params *qu
   if (!quad || !x || !u || n < 1 || n > (int64_t)1 << 26 || !(dt > 0)) return fail(MPPI_EINVAL, "bad dataset arguments");
   if (!(quad->mass > 0) || !(quad->inertia[0] > 0) || !(quad->inertia[1] > 0) || !(quad->inertia[2] > 0))
     return fail(MPPI_EINVAL, "quadrotor mass and inertia must be > 0");
+  HIP_TRY(hipStreamSynchronize(m->stream));
+  clear_graphs(m);                         // captured training steps hold the old dataset's address
   if (m->Z) (void)hipFree(m->Z);
   m->Z = nullptr;
   m->n = 0;
@@ -747,7 +918,7 @@ extern "C" int mppi_mlp_set_params(mppi_mlp *m, const float *params) {
   if (!params) return fail(MPPI_EINVAL, "params is NULL");
   HIP_TRY(hipStreamSynchronize(m->stream));
   HIP_TRY(hipMemcpy(m->p, params, kNParams * 4, hipMemcpyHostToDevice));
-  hipLaunchKernelGGL(to_bf16_kernel, dim3(nb(kNParams)), dim3(256), 0, m->stream, m->p, m->W1h, m->W2h, m->W3h);
+  repack(m);
   HIP_TRY(hipStreamSynchronize(m->stream));
   return MPPI_OK;
 }
@@ -764,29 +935,55 @@ extern "C" int mppi_mlp_train(mppi_mlp *m, const int32_t *order, int64_t n_order
   if (rc) return rc;
   const BatchBufs b = carve(m->scratch, batch);
   const int64_t steps = n_order / batch;
-  int32_t *d_order = nullptr;
-  double *d_losses = nullptr;
-  HIP_TRY(hipMalloc((void **)&d_order, (size_t)steps * batch * 4));
-  hipError_t e = hipMalloc((void **)&d_losses, (size_t)steps * 8);
-  if (e == hipSuccess) e = hipMemcpyAsync(d_order, order, (size_t)steps * batch * 4, hipMemcpyHostToDevice, m->stream);
-  for (int64_t s = 0; s < steps && e == hipSuccess; ++s) {
-    hipLaunchKernelGGL(gather_kernel, dim3(nb((long)batch * 28)), dim3(256), 0, m->stream, m->Z, m->D,
-                       d_order + s * batch, m->stats, batch, b.Xh, b.Tn);
-    fwd(m, b, batch);
-    bwd(m, b, batch);
-    m->adam_t += 1;
-    const float c1 = (float)(1.0 - std::pow(0.9, (double)m->adam_t));
-    const float c2 = (float)(1.0 - std::pow(0.999, (double)m->adam_t));
-    hipLaunchKernelGGL(adam_kernel, dim3(nb(kNParams)), dim3(256), 0, m->stream, m->p, m->g, m->m, m->v, kNParams,
-                       (float)lr, c1, c2, m->W1h, m->W2h, m->W3h);
-    e = hipMemcpyAsync(d_losses + s, b.loss, 8, hipMemcpyDeviceToDevice, m->stream);
+  if (steps * batch > m->order_cap || steps > m->loss_cap) {
+    HIP_TRY(hipStreamSynchronize(m->stream));
+    clear_graphs(m);
+    if (steps * batch > m->order_cap) {
+      if (m->d_order) (void)hipFree(m->d_order);
+      m->d_order = nullptr;
+      m->order_cap = 0;
+      HIP_TRY(hipMalloc((void **)&m->d_order, (size_t)steps * batch * 4));
+      m->order_cap = steps * batch;
+    }
+    if (steps > m->loss_cap) {
+      if (m->d_losses) (void)hipFree(m->d_losses);
+      m->d_losses = nullptr;
+      m->loss_cap = 0;
+      HIP_TRY(hipMalloc((void **)&m->d_losses, (size_t)steps * 8));
+      m->loss_cap = steps;
+    }
   }
-  if (e == hipSuccess) e = hipGetLastError();
+  // the call's inputs on the stream ahead of its steps: the order, the Adam count, the step size
+  m->h_adam_t = m->adam_t;
+  m->h_lr = (float)lr;
+  HIP_TRY(hipMemcpyAsync(m->d_order, order, (size_t)steps * batch * 4, hipMemcpyHostToDevice, m->stream));
+  HIP_TRY(hipMemcpyAsync(m->d_adam_t, &m->h_adam_t, 8, hipMemcpyHostToDevice, m->stream));
+  HIP_TRY(hipMemcpyAsync(m->d_lr, &m->h_lr, 4, hipMemcpyHostToDevice, m->stream));
+  // all steps of the call as one captured graph, kept for the next call of the same shape
+  auto key = std::make_pair(steps, (int)batch);
+  auto it = m->graphs.find(key);
+  if (it == m->graphs.end()) {
+    hipGraph_t gr = nullptr;
+    hipGraphExec_t ge = nullptr;
+    HIP_TRY(hipStreamBeginCapture(m->stream, hipStreamCaptureModeThreadLocal));
+    hipError_t ce = hipSuccess;
+    for (int64_t s = 0; s < steps; ++s) step(m, b, batch, m->d_order + s * batch, true, (int)s, m->stream, m->d_losses + s);
+    ce = hipGetLastError();
+    hipError_t e = hipStreamEndCapture(m->stream, &gr);
+    if (ce != hipSuccess || e != hipSuccess) {
+      if (gr) (void)hipGraphDestroy(gr);
+      return hip_fail(ce != hipSuccess ? ce : e, "training capture");
+    }
+    e = hipGraphInstantiate(&ge, gr, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(gr);
+    if (e != hipSuccess) return hip_fail(e, "training graph");
+    it = m->graphs.emplace(key, ge).first;
+  }
+  hipError_t e = hipGraphLaunch(it->second, m->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
-  if (e == hipSuccess && losses) e = hipMemcpy(losses, d_losses, (size_t)steps * 8, hipMemcpyDeviceToHost);
-  (void)hipFree(d_order);
-  if (d_losses) (void)hipFree(d_losses);
+  if (e == hipSuccess && losses) e = hipMemcpy(losses, m->d_losses, (size_t)steps * 8, hipMemcpyDeviceToHost);
   if (e != hipSuccess) return hip_fail(e, "training");
+  m->adam_t += steps;
   return MPPI_OK;
 }
 
@@ -803,8 +1000,7 @@ extern "C" int mppi_mlp_loss_grads(mppi_mlp *m, const double *zn, const double *
   for (size_t i = 0; i < t.size(); ++i) t[i] = (float)tn[i];
   HIP_TRY(hipMemcpyAsync(b.Xh, xh.data(), xh.size() * 2, hipMemcpyHostToDevice, m->stream));
   HIP_TRY(hipMemcpyAsync(b.Tn, t.data(), t.size() * 4, hipMemcpyHostToDevice, m->stream));
-  fwd(m, b, B);
-  bwd(m, b, B);
+  step(m, b, B, nullptr, false, 0, m->stream, b.loss);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(m->stream));
   if (loss) HIP_TRY(hipMemcpy(loss, b.loss, 8, hipMemcpyDeviceToHost));
@@ -827,8 +1023,9 @@ extern "C" int mppi_mlp_forward(mppi_mlp *m, const double *x, const double *u, i
   if (e == hipSuccess) {
     hipLaunchKernelGGL(std_inputs_kernel, dim3(nb((long)B * 16)), dim3(256), 0, m->stream, dev, dev + (size_t)B * 12,
                        m->stats, B, b.Xh);
-    fwd(m, b, B);
-    hipLaunchKernelGGL(dx_out_kernel, dim3(nb((long)B * kOut)), dim3(256), 0, m->stream, b.Y, m->p + kOffB3, m->stats, B, dxd);
+    const TrainArgs t = train_args(m, b, B, nullptr, 0);
+    hipLaunchKernelGGL(train_step_kernel, dim3(train_blocks(B)), dim3(256), kTrainLds, m->stream, t);
+    hipLaunchKernelGGL(dx_out_kernel, dim3(nb((long)B * kOut)), dim3(256), 0, m->stream, b.Yc, m->p + kOffB3, m->stats, B, dxd);
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
