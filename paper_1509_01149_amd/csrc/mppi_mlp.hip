@@ -213,7 +213,16 @@ static __global__ __launch_bounds__(256) void train_step_kernel(const TrainArgs 
   const int col = 16 * w + nn;                          // the sample's column in the block
   const int smp = blockIdx.x * kTrainSamples + col;     // its index in the minibatch
   const bool valid = smp < a.B;
-  for (int i = threadIdx.x; i < kTrainFrags * 64; i += 256) sF[i] = a.frag[i];
+  // the fragments into LDS: every load of this thread issued before the first store
+  static_assert(kTrainFrags * 64 % 256 == 0, "whole rounds of fragment loads");
+  {
+    constexpr int kRounds = kTrainFrags * 64 / 256;
+    bf16x8 fr[kRounds];
+#pragma unroll
+    for (int j = 0; j < kRounds; ++j) fr[j] = a.frag[threadIdx.x + 256 * j];
+#pragma unroll
+    for (int j = 0; j < kRounds; ++j) sF[threadIdx.x + 256 * j] = fr[j];
+  }
   // inputs: features 4q..4q+3 of this lane's sample in k slots 8q..8q+3; targets 4q..4q+3
   bf16x8 bz;
   float tgt[4] = {0.f, 0.f, 0.f, 0.f};
@@ -356,8 +365,12 @@ static __global__ __launch_bounds__(256) void train_step_kernel(const TrainArgs 
   if (threadIdx.x == 0) a.Pl[blockIdx.x] = loss;
   // bias partials: FP64 sums over the block's samples, in sample order
   for (int r = threadIdx.x; r < kNBias; r += 256) {
+    float fv[kTrainSamples];
+#pragma unroll
+    for (int c = 0; c < kTrainSamples; ++c) fv[c] = FB[r * kFBS + c];
     double acc = 0.0;
-    for (int c = 0; c < kTrainSamples; ++c) acc += (double)FB[r * kFBS + c];
+#pragma unroll
+    for (int c = 0; c < kTrainSamples; ++c) acc += (double)fv[c];
     a.Pb[(long)blockIdx.x * kNBias + r] = acc;
   }
   // weight-gradient partials: sum over the block's 64 samples (two k-steps of 32)
@@ -433,19 +446,30 @@ __device__ __forceinline__ void scatter_frag(__bf16 *frag, int i, float v) {
   }
 }
 
-// Gradient = the blocks' partials summed in a fixed order (weights in FP32: each of the four
-// lanes of a quad sums every fourth block in block order, then the quad adds its four sums as
-// (l0 + l1) + (l2 + l3); biases in FP64 in block order, then rounded once); with update, Adam on
-// the FP32 parameters, step number *adam_t + step + 1 and step size *lr (device memory, so a
-// captured sequence of steps can be replayed), and the new weights scattered into the training
-// fragments.  One quad of lanes per parameter; lane 0 of the grid also writes the loss.
+// Gradient = the blocks' partials summed in a fixed order (each of the four lanes of a quad sums
+// every fourth block in block order, then the quad adds its four sums as (l0 + l1) + (l2 + l3);
+// weights in FP32, biases in FP64 and then rounded once); with update, Adam on the FP32
+// parameters with the bias corrections bias_corr[2 step], bias_corr[2 step + 1] and step size
+// *lr (device memory, written before each call, so a captured sequence of steps can be
+// replayed), and the new weights scattered into the training fragments.  One quad of lanes per
+// parameter; the first wave also sums the loss.
 static __global__ void train_reduce_kernel(const float *__restrict__ P, const double *__restrict__ Pb,
                                            const double *__restrict__ Pl, int nblk, int B, float *g, float *p,
-                                           float *m, float *v, int update, const int64_t *adam_t, int step,
+                                           float *m, float *v, int update, const float *bias_corr, int step,
                                            const float *lr, __bf16 *frag, double *loss_out) {
   const int gt = blockIdx.x * blockDim.x + threadIdx.x;
   const int i = gt >> 2, sub = gt & 3;
-  if (gt == 0 && loss_out) *loss_out = ordered_sum(Pl, 1, nblk) / (double)(B * kOut);
+  if (blockIdx.x == 0 && threadIdx.x < 64 && loss_out) {
+    // the loss: lane j sums blocks j, j + 64, ... in order, then a fixed butterfly over the wave
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += 64) s += Pl[b];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+      const double o = __shfl_xor(s, off, 64);
+      s = (threadIdx.x & off) ? o + s : s + o;
+    }
+    if (threadIdx.x == 0) *loss_out = s / (double)(B * kOut);
+  }
   if (i >= kNParams) return;                          // whole quads leave together (kNParams quads)
   int bias = -1;
   if (i >= kOffB1 && i < kOffB1 + kH) bias = i - kOffB1;
@@ -453,8 +477,13 @@ static __global__ void train_reduce_kernel(const float *__restrict__ P, const do
   else if (i >= kOffB3) bias = 2 * kH + (i - kOffB3);
   float gi;
   if (bias >= 0) {
-    gi = sub == 0 ? (float)ordered_sum(Pb + bias, kNBias, nblk) : 0.f;
-    gi = __shfl(gi, threadIdx.x & ~3, 64);
+    // FP64: lane sub sums every fourth block in order, the quad adds (l0 + l1) + (l2 + l3)
+    double s = 0.0;
+    for (int b = sub; b < nblk; b += 4) s += Pb[(long)b * kNBias + bias];
+    const double s1 = __shfl_xor(s, 1, 64);
+    const double pair = (sub & 1) ? s1 + s : s + s1;
+    const double other = __shfl_xor(pair, 2, 64);
+    gi = (float)((sub & 2) ? other + pair : pair + other);
   } else {
     float s = 0.f;
     constexpr int kBatch = 16;                      // loads in flight per lane
@@ -474,8 +503,7 @@ static __global__ void train_reduce_kernel(const float *__restrict__ P, const do
   if (sub != 0) return;
   g[i] = gi;
   if (!update) return;
-  const double t = (double)(*adam_t + step + 1);
-  const float c1 = (float)(1.0 - pow(0.9, t)), c2 = (float)(1.0 - pow(0.999, t));
+  const float c1 = bias_corr[2 * step], c2 = bias_corr[2 * step + 1];
   const float mi = 0.9f * m[i] + 0.1f * gi;
   const float vi = 0.999f * v[i] + 0.001f * gi * gi;
   m[i] = mi;
@@ -674,14 +702,14 @@ struct mppi_mlp {
   // training: the Adam step count and step size the captured steps read (device), the
   // minibatch order and per-step losses (device, capacities in elements), and one captured
   // graph of a whole call per (steps, batch), valid while these buffers stay in place
-  int64_t *d_adam_t = nullptr;
   float *d_lr = nullptr;
+  float *d_corr = nullptr;            // [2 steps] Adam bias corrections 1 - beta^t of the call
   int32_t *d_order = nullptr;
   int64_t order_cap = 0;
   double *d_losses = nullptr;
   int64_t loss_cap = 0;
-  int64_t h_adam_t = 0;
   float h_lr = 0.f;
+  std::vector<float> h_corr;
   std::map<std::pair<int64_t, int>, hipGraphExec_t> graphs;
 };
 
@@ -758,13 +786,13 @@ TrainArgs train_args(mppi_mlp *m, const BatchBufs &b, int B, const int *order, i
 }
 
 // One minibatch on stream st: the fused forward/backward, then the reduction (with update,
-// Adam at step *d_adam_t + step + 1 and the new weights into the fragments).
+// Adam with the call's bias corrections and the new weights into the fragments).
 void step(mppi_mlp *m, const BatchBufs &b, int B, const int *order, bool update, int step_no, hipStream_t st,
           double *loss_out) {
   const TrainArgs t = train_args(m, b, B, order, 1);
   hipLaunchKernelGGL(train_step_kernel, dim3(train_blocks(B)), dim3(256), kTrainLds, st, t);
   hipLaunchKernelGGL(train_reduce_kernel, dim3(nb(4L * kNParams)), dim3(256), 0, st, b.P, b.Pb, b.Pl, train_blocks(B),
-                     B, m->g, m->p, m->m, m->v, update ? 1 : 0, m->d_adam_t, step_no, m->d_lr, m->frag, loss_out);
+                     B, m->g, m->p, m->m, m->v, update ? 1 : 0, m->d_corr, step_no, m->d_lr, m->frag, loss_out);
 }
 
 int check_mlp(mppi_mlp *m) {
@@ -808,8 +836,7 @@ extern "C" int mppi_mlp_create(int32_t device, const float *params, mppi_mlp **o
   m->g = m->p + kNParams;
   m->m = m->g + kNParams;
   m->v = m->m + kNParams;
-  m->d_adam_t = (int64_t *)(m->stats + MPPI_MLP_STATS);
-  m->d_lr = (float *)(m->d_adam_t + 1);
+  m->d_lr = (float *)(m->stats + MPPI_MLP_STATS);
   std::vector<float> zeros(3 * kNParams, 0.f);
   std::vector<double> st(MPPI_MLP_STATS, 0.0);
   for (int i = 16; i < 32; ++i) st[i] = 1.0;
@@ -948,16 +975,23 @@ extern "C" int mppi_mlp_train(mppi_mlp *m, const int32_t *order, int64_t n_order
     if (steps > m->loss_cap) {
       if (m->d_losses) (void)hipFree(m->d_losses);
       m->d_losses = nullptr;
+      m->d_corr = nullptr;
       m->loss_cap = 0;
-      HIP_TRY(hipMalloc((void **)&m->d_losses, (size_t)steps * 8));
+      HIP_TRY(hipMalloc((void **)&m->d_losses, (size_t)steps * 16));   // losses, then the corrections
+      m->d_corr = (float *)(m->d_losses + steps);
       m->loss_cap = steps;
     }
   }
   // the call's inputs on the stream ahead of its steps: the order, the Adam count, the step size
-  m->h_adam_t = m->adam_t;
   m->h_lr = (float)lr;
+  m->h_corr.resize((size_t)2 * steps);
+  for (int64_t s = 0; s < steps; ++s) {
+    const double t = (double)(m->adam_t + s + 1);
+    m->h_corr[2 * s] = (float)(1.0 - std::pow(0.9, t));
+    m->h_corr[2 * s + 1] = (float)(1.0 - std::pow(0.999, t));
+  }
   HIP_TRY(hipMemcpyAsync(m->d_order, order, (size_t)steps * batch * 4, hipMemcpyHostToDevice, m->stream));
-  HIP_TRY(hipMemcpyAsync(m->d_adam_t, &m->h_adam_t, 8, hipMemcpyHostToDevice, m->stream));
+  HIP_TRY(hipMemcpyAsync(m->d_corr, m->h_corr.data(), (size_t)steps * 8, hipMemcpyHostToDevice, m->stream));
   HIP_TRY(hipMemcpyAsync(m->d_lr, &m->h_lr, 4, hipMemcpyHostToDevice, m->stream));
   // all steps of the call as one captured graph, kept for the next call of the same shape
   auto key = std::make_pair(steps, (int)batch);
