@@ -72,19 +72,21 @@ TRAFFIC_FILES = {"bicycle": "traffic_rollout_bicycle_K4096_T100.md",
 SQ_FILES = {"bicycle": "sq_rollout_bicycle_K4096_T100.md",
             "quadrotor": "sq_rollout_quadrotor_K16384_T150.md"}
 ROLLOUT_SOURCES = ["mppi_device.h", "mppi_systems.h", "mppi_kernels.h"]
+MLP_SOURCES = ROLLOUT_SOURCES + ["mppi_mlp.hip"]
+MLP_PROFILE = "mlp_quadrotor_rollout_K16384_T100_and_training_B4096.md"
 
 
-def rollout_source_hash():
+def rollout_source_hash(sources=ROLLOUT_SOURCES):
     import hashlib
     h = hashlib.sha256()
-    for f in ROLLOUT_SOURCES:
+    for f in sources:
         h.update(open(os.path.join(ROOT, "paper_1509_01149_amd", "csrc", f), "rb").read())
     return h.hexdigest()
 
 
-def profile_record(files, name):
+def profile_record(files, name, sources=ROLLOUT_SOURCES):
     """The machine-readable "key: value" lines of a committed counter summary, or None when
-    there is none or the rollout kernel's sources have changed since the counters were taken."""
+    there is none or the kernel's sources have changed since the counters were taken."""
     fn = files.get(name)
     path = os.path.join(ROOT, "profiles", fn) if fn else None
     if not path or not os.path.exists(path):
@@ -94,9 +96,15 @@ def profile_record(files, name):
         if ":" in line and not line.startswith(("|", "#", " ", "`")):
             k, v = line.split(":", 1)
             rec[k.strip()] = v.strip()
-    if rec.get("kernel_source_sha256") != rollout_source_hash():
+    if rec.get("kernel_source_sha256") != rollout_source_hash(sources):
         return None
     return rec
+
+
+def mfma_util(key):
+    """MFMA utilisation of an MLP kernel from the committed counter summary (None if stale)."""
+    rec = profile_record({"mlp": MLP_PROFILE}, "mlp", MLP_SOURCES)
+    return float(rec[key]) if rec and key in rec else None
 
 
 def measured_traffic(name):
@@ -450,6 +458,7 @@ def mlp_roofline(wl, times):
     achieved = flop / (roll_ms / 1e3) / 1e12
     return dict(bound="mfma", kernel="mlp_rollout", achieved=round(achieved, 3), peak=BF16_MFMA_PEAK_TFLOPS,
                 unit="TFLOP/s", frac=round(achieved / BF16_MFMA_PEAK_TFLOPS, 5), traffic=None,
+                mfma_busy=mfma_util("mlp_rollout_mfma_util"), valu_issue_share=mfma_util("mlp_rollout_valu_issue_share"),
                 alg_flop_per_launch=flop, kernel_ms=round(roll_ms, 5),
                 kernel_ms_all={k: round(v[0], 5) for k, v in times.items()},
                 launches_timed=times["rollout"][1])
@@ -509,6 +518,7 @@ def main():
                                   seconds=round(g.train_seconds, 3), final_loss=g.final_loss,
                                   tflops=round(g.train_samples * MLP_TRAIN_FLOP_PER_SAMPLE / g.train_seconds / 1e12, 3)))
         learned["train"]["frac"] = round(learned["train"]["tflops"] / BF16_MFMA_PEAK_TFLOPS, 6)
+        learned["train"]["train_step_mfma_busy"] = mfma_util("train_step_mfma_util")
         if wl is None:
             wl = W_quadrotor_mlp(g)
     spl = max(1, args.steps_per_launch)
