@@ -357,12 +357,12 @@ static int build_params(mppi_ctx *c) {
       const int no = p->n_obstacles;
       float ob[(QuadrotorSys::kMaxObstacles + 1) * 5];
       std::memset(ob, 0, sizeof(ob));
-      for (int j = 0; j < no; ++j) {
+      for (int j = 0; j < no; ++j) {   // (2 c, (r + margin)^2 - |c|^2), then (r + margin)^2 - r^2
         const double *o = p->obstacles + 4 * j;
         const double rr = o[3] + p->obs_margin;
-        ob[4 * j + 0] = (float)o[0]; ob[4 * j + 1] = (float)o[1]; ob[4 * j + 2] = (float)o[2];
-        ob[4 * j + 3] = (float)(rr * rr);
-        ob[4 * (size_t)no + j] = (float)(o[3] * o[3]);
+        ob[4 * j + 0] = (float)(2.0 * o[0]); ob[4 * j + 1] = (float)(2.0 * o[1]); ob[4 * j + 2] = (float)(2.0 * o[2]);
+        ob[4 * j + 3] = (float)(rr * rr - (o[0] * o[0] + o[1] * o[1] + o[2] * o[2]));
+        ob[4 * (size_t)no + j] = (float)(rr * rr - o[3] * o[3]);
       }
       qp.obs = (const float4 *)(c->base + c->L.off_sys);
       HIP_TRY(hipMemcpy((void *)qp.obs, ob, (size_t)(no > 0 ? no : 1) * 5 * 4, hipMemcpyHostToDevice));

@@ -642,12 +642,12 @@ static __global__ __launch_bounds__(256) void mlp_rollout_kernel(const IterArgs 
     // cost of x_{i+1}: position from lane q = 0 of this sample; obstacles split over the 4 lanes
     const float px = __shfl(v[0], nn, 64), py = __shfl(v[1], nn, 64), pz = __shfl(v[2], nn, 64);
     const float4 *ob = reinterpret_cast<const float4 *>(sObs);
+    const float pos[3] = {px, py, pz};
+    const float xx = fmaf(px, px, fmaf(py, py, pz * pz));
     float bar = 0.f;
     for (int j = q; j < p.n_obs; j += 4) {
-      const float4 o = ob[j];
-      const float ex = px - o.x, ey = py - o.y, ez = pz - o.z;
-      const float pen = fmaxf(0.f, o.w - (ex * ex + ey * ey + ez * ez));
-      bar += pen * pen;
+      const float pen = fmaxf(0.f, QuadrotorSys::barrier_arg(ob[j], pos, xx));
+      bar = fmaf(pen, pen, bar);
     }
     bar += __shfl_xor(bar, 16, 64);
     bar += __shfl_xor(bar, 32, 64);

@@ -443,7 +443,10 @@ struct QuadrotorSys {
   struct Params {
     float m_inv, g, arm, kap, J[3], Jinv[3], goal[3], wg, wo, margin;
     int n_obs;
-    const float4 *obs;   // device: n_obs x (cx, cy, cz, (r + margin)^2), then n_obs x r^2
+    // device: n_obs x (2 c, (r + margin)^2 - |c|^2), then n_obs x ((r + margin)^2 - r^2): the
+    // barrier's argument (r + margin)^2 - |p - c|^2 = w + 2 c . p - |p|^2 is three FMAs from
+    // |p|^2, and the crash test |p - c| < r is that argument above the second value
+    const float4 *obs;
     float crash, ground; // crash indicator cost (0: off) and ground height
     double dm_inv, dg, darm, dkap, dJ[3], dJinv[3];
   };
@@ -482,63 +485,64 @@ struct QuadrotorSys {
     xd[10] = fma(wx, hz, fma(-wz, hx, ty)) * Ji1;
     xd[11] = fma(wy, hx, fma(-wx, hy, tz)) * Ji2;
   }
-  // LDS: the obstacles' float4s, then (crash indicator on) their squared radii
+  // LDS: the obstacles' float4s, then (crash indicator on) their crash thresholds
   static constexpr int stage_floats(int n_obs, int) { return 5 * n_obs; }
   __device__ static void stage(const Params &p, float *lds, const double *, int *, int *) {
     for (int e = threadIdx.x; e < p.n_obs; e += kBlock) reinterpret_cast<float4 *>(lds)[e] = p.obs[e];
     if (p.crash > 0.f) {
-      const float *r2 = reinterpret_cast<const float *>(p.obs + p.n_obs);
-      for (int e = threadIdx.x; e < p.n_obs; e += kBlock) lds[4 * p.n_obs + e] = r2[e];
+      const float *th = reinterpret_cast<const float *>(p.obs + p.n_obs);
+      for (int e = threadIdx.x; e < p.n_obs; e += kBlock) lds[4 * p.n_obs + e] = th[e];
     }
+  }
+  // (r + margin)^2 - |p - c|^2 of obstacle o at position x with xx = |x|^2
+  __device__ __forceinline__ static float barrier_arg(const float4 &o, const float *x, float xx) {
+    return fmaf(x[0], o.x, fmaf(x[1], o.y, fmaf(x[2], o.z, o.w))) - xx;
   }
   // The obstacles a lane visits first (j, j + nj, ... for kRegObs of them) are held in
   // registers for the whole rollout, the rest are read from LDS each step: with one wave
   // per SIMD, an LDS round trip per obstacle per step would dominate the step.  Unused
-  // register slots hold a zero obstacle (no barrier, no hit).
+  // register slots hold a zero obstacle (argument -|p|^2 <= 0: no barrier, no hit).
   static constexpr int kRegObs = 8;
   struct Regs {
     float4 o[kRegObs];
-    float r2[kRegObs];
+    float th[kRegObs];
   };
   __device__ static void load_regs(const Params &p, const StageView &sv, int j, int nj, Regs &rg) {
     const float4 *ob = reinterpret_cast<const float4 *>(sv.lds);
-    const float *r2 = sv.lds + 4 * p.n_obs;
+    const float *th = sv.lds + 4 * p.n_obs;
 #pragma unroll
     for (int t = 0; t < kRegObs; ++t) {
       const int o = j + nj * t;
       const bool in = o < p.n_obs;
       rg.o[t] = in ? ob[o] : make_float4(0.f, 0.f, 0.f, 0.f);
-      rg.r2[t] = in && p.crash > 0.f ? r2[o] : 0.f;
+      rg.th[t] = in && p.crash > 0.f ? th[o] : 0.f;
     }
   }
   // Lane j of nj: the goal term (j = 0) plus the barriers of obstacles j, j + nj, ...; with
   // kHit also the count of crash conditions among the same obstacles (and the ground for
-  // j = 0), from the same distances.
+  // j = 0), from the same barrier arguments.
   template <bool kHit>
   __device__ static float cost_part(const Params &p, const StageView &sv, const Regs &rg, const float *x, int j,
                                     int nj, float &hit) {
     const float dx = x[0] - p.goal[0], dy = x[1] - p.goal[1], dz = x[2] - p.goal[2];
     const float c = j == 0 ? p.wg * (dx * dx + dy * dy + dz * dz) : 0.f;
+    const float xx = fmaf(x[0], x[0], fmaf(x[1], x[1], x[2] * x[2]));
     float barrier = 0.f, h = (kHit && j == 0 && x[2] < p.ground) ? 1.f : 0.f;
 #pragma unroll
     for (int t = 0; t < kRegObs; ++t) {
-      const float4 ov = rg.o[t];
-      const float ex = x[0] - ov.x, ey = x[1] - ov.y, ez = x[2] - ov.z;
-      const float d2 = ex * ex + ey * ey + ez * ez;
-      const float pen = fmaxf(0.f, ov.w - d2);
-      barrier += pen * pen;
-      if (kHit) h += d2 < rg.r2[t] ? 1.f : 0.f;
+      const float arg = barrier_arg(rg.o[t], x, xx);
+      const float pen = fmaxf(0.f, arg);
+      barrier = fmaf(pen, pen, barrier);
+      if (kHit) h += arg > rg.th[t] ? 1.f : 0.f;
     }
     const float4 *ob = reinterpret_cast<const float4 *>(sv.lds);
-    const float *r2 = sv.lds + 4 * p.n_obs;
+    const float *th = sv.lds + 4 * p.n_obs;
     if (p.n_obs > nj * kRegObs)                     // block-uniform: skipped when all fit in registers
     for (int o = j + nj * kRegObs; o < p.n_obs; o += nj) {
-      const float4 ov = ob[o];
-      const float ex = x[0] - ov.x, ey = x[1] - ov.y, ez = x[2] - ov.z;
-      const float d2 = ex * ex + ey * ey + ez * ez;
-      const float pen = fmaxf(0.f, ov.w - d2);
-      barrier += pen * pen;
-      if (kHit) h += d2 < r2[o] ? 1.f : 0.f;
+      const float arg = barrier_arg(ob[o], x, xx);
+      const float pen = fmaxf(0.f, arg);
+      barrier = fmaf(pen, pen, barrier);
+      if (kHit) h += arg > th[o] ? 1.f : 0.f;
     }
     hit = h;
     return c + p.wo * barrier;
@@ -556,14 +560,13 @@ struct QuadrotorSys {
   }
   __device__ static float q(const Params &p, const StageView &sv, const float *x) {
     const float dx = x[0] - p.goal[0], dy = x[1] - p.goal[1], dz = x[2] - p.goal[2];
-    float c = p.wg * (dx * dx + dy * dy + dz * dz);
+    const float c = p.wg * (dx * dx + dy * dy + dz * dz);
+    const float xx = fmaf(x[0], x[0], fmaf(x[1], x[1], x[2] * x[2]));
     const float4 *ob = reinterpret_cast<const float4 *>(sv.lds);
     float barrier = 0.f;
     for (int j = 0; j < p.n_obs; ++j) {
-      const float4 o = ob[j];
-      const float ex = x[0] - o.x, ey = x[1] - o.y, ez = x[2] - o.z;
-      const float pen = fmaxf(0.f, o.w - (ex * ex + ey * ey + ez * ez));
-      barrier += pen * pen;
+      const float pen = fmaxf(0.f, barrier_arg(ob[j], x, xx));
+      barrier = fmaf(pen, pen, barrier);
     }
     return c + p.wo * barrier;
   }
