@@ -382,14 +382,15 @@ def parity_spot_check(wl, ctrl, x):
                 tolerance=1e-4, at_iteration=it)
 
 
-def time_controller(P, torch, wl, steps, warmup, spl, weighting=0):
+def time_controller(P, torch, wl, steps, warmup, spl, weighting=0, kernels=0):
     """Time `steps` closed-loop control steps of workload wl on the device, `spl` per launch
     sequence, then the same with one launch per step, then one profiled pass of the same
     length (per-kernel HIP events on the library's stream).  Every graph shape the timed
     passes launch is captured during the warm-up."""
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
-    ctrl = P.controller_for(wl, device=0, torch_stream=stream, torch_workspace=True, weighting=weighting)
+    ctrl = P.controller_for(wl, device=0, torch_stream=stream, torch_workspace=True, weighting=weighting,
+                            kernels=kernels)
     x_dev = torch.tensor(np.asarray(wl.x0, float), dtype=torch.float64, device=dev)
     u_log = torch.zeros((spl, wl.m), dtype=torch.float64, device=dev)
     xp, up = x_dev.data_ptr(), u_log.data_ptr()
@@ -448,7 +449,7 @@ def alu_roofline(wl, times):
                 ops_incl_noise_per_rollout_step=ISSUE_OPS_PER_ROLLOUT_STEP[wl.name],
                 ops_incl_noise_frac_of_unpacked_fp32=round(ops_rate / ALU_PEAK_TFLOPS, 5),
                 valu_issue_share=valu_issue_share(wl.name),
-                kernel_ms_all={k: round(v[0], 5) for k, v in times.items()},
+                kernel_ms_all={k: round(v[0], 5) for k, v in times.items() if v[1] > 0},
                 launches_timed=times["rollout"][1])
 
 
@@ -482,6 +483,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
     ap.add_argument("--serving-seconds", type=float, default=10.0,
                     help="length of the measured serving trace after its one-second warm-up (0: no serving leg)")
+    ap.add_argument("--kernels", choices=("auto", "fused", "three"), default="auto",
+                    help="kernels per iteration of the chosen workload (auto: the library's choice)")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="first run one plain device copy of this many bytes (a known-size kernel for "
                          "calibrating HBM byte counters in a profiler pass)")
@@ -522,8 +525,10 @@ def main():
         if wl is None:
             wl = W_quadrotor_mlp(g)
     spl = max(1, args.steps_per_launch)
+    kernels = {"auto": P.KERNELS_AUTO, "fused": P.KERNELS_FUSED, "three": P.KERNELS_THREE}[args.kernels]
     ctrl, x_dev, ms_per_step, ms_per_step_single, times = time_controller(
-        P, torch, wl, args.steps, args.warmup, spl, weighting=P.WEIGHT_COST_TO_GO if ctg else P.WEIGHT_PATH)
+        P, torch, wl, args.steps, args.warmup, spl, weighting=P.WEIGHT_COST_TO_GO if ctg else P.WEIGHT_PATH,
+        kernels=kernels)
     rollout_steps = wl.K * wl.T
     value = rollout_steps / (ms_per_step / 1e3)
     progress(f"{wl.name} timed: {ms_per_step:.5f} ms per control step")
@@ -542,10 +547,19 @@ def main():
     if not args.no_extra and wl.name != "bicycle":
         wb = make_workload("bicycle")
         cb, _, ms_b, ms_b1, times_b = time_controller(P, torch, wb, args.steps, args.warmup, spl)
+        fused = bool(cb.info()["rollout_mode"] & P.binding.ROLLOUT_FUSED)
         cb.close()
+        # the same workload through the three-kernel iteration (rollout, update, finalize)
+        c3, _, ms_3, ms_31, times_3 = time_controller(P, torch, wb, args.steps, args.warmup, spl,
+                                                      kernels=P.KERNELS_THREE)
+        c3.close()
         out["bicycle"] = dict(workload=f"bicycle K={wb.K} T={wb.T} nu={wb.nu}", ms_per_step=round(ms_b, 5),
                               rollout_steps_per_s=round(wb.K * wb.T / (ms_b / 1e3), 1),
-                              ms_per_step_one_launch_per_step=round(ms_b1, 5), roofline=alu_roofline(wb, times_b))
+                              kernels_per_iteration=2 if fused else 3,
+                              ms_per_step_one_launch_per_step=round(ms_b1, 5), roofline=alu_roofline(wb, times_b),
+                              three_kernels=dict(ms_per_step=round(ms_3, 5),
+                                                 ms_per_step_one_launch_per_step=round(ms_31, 5),
+                                                 kernel_ms_all={k: round(v[0], 5) for k, v in times_3.items()}))
     if "bicycle" in out:
         progress("bicycle timed")
     if learned is not None and wl.name != "quadrotor_mlp":

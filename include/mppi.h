@@ -160,8 +160,15 @@ typedef struct {
                               /* The quadratic likelihood-ratio term becomes               */
                               /* du'(R - A^-1 R A^-1) du / 2; copied                       */
   int32_t weighting;          /* MPPI_WEIGHT_PATH or MPPI_WEIGHT_COST_TO_GO                */
-  int32_t reserved;           /* must be 0                                                 */
+  int32_t kernels;            /* MPPI_KERNELS_AUTO (0), _FUSED or _THREE                   */
 } mppi_config;
+
+/* Kernels per iteration.  THREE: rollout, update (regenerates the noise to form the weighted
+ * sums), finalize.  FUSED: the rollout also forms the weighted sums of its block's samples,
+ * and the finalize merges them (MPPI_ROLLOUT_FUSED; step-split systems under path weighting
+ * only, else MPPI_EINVAL).  AUTO takes FUSED wherever it is available.  Both compute the
+ * update law of Section III-C; their results differ by FP64 summation order only. */
+enum { MPPI_KERNELS_AUTO = 0, MPPI_KERNELS_FUSED = 2, MPPI_KERNELS_THREE = 3 };
 
 /* Weights of the update law (Section III-C).  PATH: one total path cost per sample weights
  * every time step (Algorithm 1's forward-accumulated cost).  COST_TO_GO: time step i is
@@ -277,10 +284,15 @@ int mppi_debug_lane_groups(int32_t device, int32_t group, const float *a, const 
 /* The launch configuration a context chose (host output).  rollout_mode bits name the
  * compiled rollout variant: MPPI_ROLLOUT_COST_TO_GO (prefix costs recorded), _CRASH (crash
  * indicator), _STEP_SPLIT (the lanes of a sample share its horizon), _DIAGONAL (A chol(Sigma)
- * and the likelihood-ratio matrix are diagonal, so only their diagonal products are formed);
+ * and the likelihood-ratio matrix are diagonal, so only their diagonal products are formed),
+ * _FUSED (two kernels per iteration: each rollout block also writes its samples' weighted
+ * noise sums against its own minimum, and the finalize, one block per 4 sequence
+ * components, rescales and merges them; update_blocks is then 0.  Chosen for the step-split
+ * systems under path weighting when at most 1024 rollout blocks run and a block's normals
+ * fit 32 KiB of LDS);
  * rollout_lanes is the lanes per sample (the learned dynamics: 4, sixteen samples per wave). */
 enum { MPPI_ROLLOUT_COST_TO_GO = 1, MPPI_ROLLOUT_CRASH = 2, MPPI_ROLLOUT_STEP_SPLIT = 4,
-       MPPI_ROLLOUT_DIAGONAL = 8 };
+       MPPI_ROLLOUT_DIAGONAL = 8, MPPI_ROLLOUT_FUSED = 16 };
 typedef struct {
   int32_t rollout_lanes;
   int32_t rollout_mode;
@@ -296,7 +308,8 @@ int mppi_get_info(mppi_ctx *ctx, mppi_info *out);
  * launched directly (no graph) between two hipEvents recorded on the context's stream.
  * mppi_kernel_times waits for the stream and returns, per kernel kind (0 = rollout,
  * 1 = update, 2 = finalize), the mean duration in milliseconds and the number of
- * launches timed since profiling was switched on (avg_ms[3], count[3], host). */
+ * launches timed since profiling was switched on (avg_ms[3], count[3], host); a fused
+ * context (MPPI_ROLLOUT_FUSED) launches no update, so its count stays 0. */
 int mppi_set_profiling(mppi_ctx *ctx, int32_t on);
 int mppi_kernel_times(mppi_ctx *ctx, double *avg_ms, int64_t *count);
 

@@ -7,6 +7,7 @@ shift) runs in the HIP kernels of libmppi.so behind the C ABI in include/mppi.h;
 from .binding import (  # noqa: F401
     ABI_VERSION, Controller, Mlp, MppiError, NumericError, Server, load, philox, step_static, version,
     SERVE_BATCHED, SERVE_PLAIN, SERVE_BATCHED_GRAPH, WEIGHT_PATH, WEIGHT_COST_TO_GO,
+    KERNELS_AUTO, KERNELS_FUSED, KERNELS_THREE,
     SYS_LINEAR, SYS_CARTPOLE, SYS_BICYCLE, SYS_QUADROTOR, SYS_QUADROTOR_MLP, SYS_CARTPOLE_SWINGUP,
 )
 

@@ -76,7 +76,7 @@ class Config(C.Structure):
                 ("params", C.c_void_p), ("params_bytes", C.c_uint64), ("seed", C.c_uint64),
                 ("device", C.c_int32), ("use_graph", C.c_int32), ("stream", C.c_void_p),
                 ("workspace", C.c_void_p), ("workspace_bytes", C.c_uint64), ("nu_diag", _dp),
-                ("weighting", C.c_int32), ("reserved", C.c_int32)]
+                ("weighting", C.c_int32), ("kernels", C.c_int32)]
 
 
 class ServerConfig(C.Structure):
@@ -96,7 +96,7 @@ class Info(C.Structure):
                 ("workspace_bytes", C.c_uint64)]
 
 
-ROLLOUT_COST_TO_GO, ROLLOUT_CRASH, ROLLOUT_STEP_SPLIT, ROLLOUT_DIAGONAL = 1, 2, 4, 8
+ROLLOUT_COST_TO_GO, ROLLOUT_CRASH, ROLLOUT_STEP_SPLIT, ROLLOUT_DIAGONAL, ROLLOUT_FUSED = 1, 2, 4, 8, 16
 
 SERVE_BATCHED, SERVE_PLAIN, SERVE_BATCHED_GRAPH = 0, 1, 2
 
@@ -227,11 +227,12 @@ def make_params(system: int, params: Dict, keep: list):
 
 
 WEIGHT_PATH, WEIGHT_COST_TO_GO = 0, 1
+KERNELS_AUTO, KERNELS_FUSED, KERNELS_THREE = 0, 2, 3
 
 
 def make_config(*, system: int, n: int, m: int, K: int, T: int, dt: float, lam: float, nu,
                 sigma, R=None, u_init, params: Dict, u_nominal0=None, seed: int = 0, device: int = 0,
-                use_graph: bool = True, weighting: int = 0):
+                use_graph: bool = True, weighting: int = 0, kernels: int = 0):
     """Fill an mppi_config; returns (config, list of arrays that must stay alive)."""
     keep = []
     sig = _f64(sigma).reshape(m, m)
@@ -257,6 +258,7 @@ def make_config(*, system: int, n: int, m: int, K: int, T: int, dt: float, lam: 
     cfg.use_graph = 1 if use_graph else 0
     cfg.nu_diag = _ptr(nu_vec)
     cfg.weighting = weighting
+    cfg.kernels = kernels
     return cfg, keep
 
 
@@ -283,12 +285,13 @@ class Controller:
 
     def __init__(self, *, system: int, n: int, m: int, K: int, T: int, dt: float, lam: float, nu,
                  sigma, R=None, u_init, params: Dict, u_nominal0=None, seed: int = 0, device: int = 0,
-                 use_graph: bool = True, weighting: int = 0, torch_stream=None, torch_workspace: bool = False):
+                 use_graph: bool = True, weighting: int = 0, kernels: int = 0, torch_stream=None,
+                 torch_workspace: bool = False):
         lib = load()
         self.n, self.m, self.K, self.T = n, m, K, T
         cfg, self._keep = make_config(system=system, n=n, m=m, K=K, T=T, dt=dt, lam=lam, nu=nu, sigma=sigma, R=R,
                                       u_init=u_init, params=params, u_nominal0=u_nominal0, seed=seed,
-                                      device=device, use_graph=use_graph, weighting=weighting)
+                                      device=device, use_graph=use_graph, weighting=weighting, kernels=kernels)
         self._workspace = None
         if torch_stream is not None:
             cfg.stream = C.c_void_p(torch_stream.cuda_stream)

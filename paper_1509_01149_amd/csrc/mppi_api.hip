@@ -139,7 +139,11 @@ int validate_config(const mppi_config *c) {
       if (!(c->nu_diag[j] > 0.0) || !std::isfinite(c->nu_diag[j])) return fail(MPPI_EINVAL, "nu_diag entries must be finite and > 0");
   if (c->weighting != MPPI_WEIGHT_PATH && c->weighting != MPPI_WEIGHT_COST_TO_GO)
     return fail(MPPI_EINVAL, "unknown weighting %d", c->weighting);
-  if (c->reserved != 0) return fail(MPPI_EINVAL, "reserved must be 0");
+  if (c->kernels != MPPI_KERNELS_AUTO && c->kernels != MPPI_KERNELS_FUSED && c->kernels != MPPI_KERNELS_THREE)
+    return fail(MPPI_EINVAL, "unknown kernels value %d", c->kernels);
+  if (c->kernels == MPPI_KERNELS_FUSED && !fused_available(c))
+    return fail(MPPI_EINVAL, "the fused iteration needs a step-split system, path weighting, at most %d rollout "
+                "blocks and a block's normals within %d bytes of LDS", kMaxFusedParts, kMaxFusedNormalsBytes);
   if (c->weighting == MPPI_WEIGHT_COST_TO_GO && c->system == MPPI_SYS_QUADROTOR_MLP)
     return fail(MPPI_EINVAL, "cost-to-go weighting is not available with the learned dynamics");
   if (c->u_nominal0 && !finite_all(c->u_nominal0, c->T * mm)) return fail(MPPI_EINVAL, "u_nominal0 has non-finite entries");
@@ -215,6 +219,15 @@ int rollout_lps(const mppi_config *c) {
   return c->K <= 8192 ? 16 : 4;
 }
 
+// The fused iteration: a step-split system under path weighting, every rollout block's
+// partials mergeable by one finalize block, and a rollout block's normals within its LDS share.
+bool fused_available(const mppi_config *c) {
+  if (!rollout_split(c) || c->weighting != MPPI_WEIGHT_PATH) return false;
+  const int lps = rollout_lps(c), spb = kBlock / lps;
+  const int64_t n_roll = ((int64_t)c->K + spb - 1) / spb, G = ((int64_t)c->T * c->n_ctrl + 3) / 4;
+  return n_roll <= kMaxFusedParts && spb * G * 16 <= kMaxFusedNormalsBytes;
+}
+
 void compute_layout(const mppi_config *c, Layout *L) {
   const int K = c->K, T = c->T, m = c->n_ctrl;
   L->TM = T * m;
@@ -231,6 +244,9 @@ void compute_layout(const mppi_config *c, Layout *L) {
   else if (ctg_w || ((K + 255) / 256) * gblk <= 1200) L->upd_chunk = 256;
   else L->upd_chunk = 512;
   L->n_kc = (K + L->upd_chunk - 1) / L->upd_chunk;
+  L->fused = c->kernels != MPPI_KERNELS_THREE && fused_available(c);
+  L->n_fin_blocks = L->fused ? (L->TM + kFusedOut - 1) / kFusedOut : 1;
+  const int n_parts = L->fused ? L->n_roll_blocks : L->n_kc;
   uint64_t o = 0;
   auto take = [&](uint64_t bytes) { uint64_t r = o; o = align256(o + bytes); return r; };
   L->off_x0 = take(16 * sizeof(double));
@@ -241,8 +257,10 @@ void compute_layout(const mppi_config *c, Layout *L) {
   L->off_S = take((uint64_t)K * 8);
   L->off_blk_min = take((uint64_t)L->n_roll_blocks * 8);
   const bool ctg = c->weighting == MPPI_WEIGHT_COST_TO_GO;
-  L->off_eta_part = take((uint64_t)L->n_kc * (ctg ? T : 1) * 8);
-  L->off_part = take((uint64_t)L->n_kc * L->G * 4 * 8);
+  L->off_eta_part = take((uint64_t)n_parts * (ctg ? T : 1) * 8);
+  L->off_part = take((uint64_t)n_parts * L->G * 4 * 8);
+  L->off_shadow = L->fused ? take((uint64_t)L->TM * 8) : 0;
+  L->off_basis = L->fused ? take((uint64_t)5 * 16 * 8) : 0;
   L->off_dbg = take((uint64_t)(2 + L->TM) * 8);
   L->off_pre = ctg ? take((uint64_t)T * K * 8) : 0;
   L->off_rho_step = ctg ? take((uint64_t)T * 8) : 0;
@@ -378,8 +396,10 @@ static size_t rollout_lds_bytes(const mppi_ctx *c) {
   const int T = c->cfg.T, m = c->cfg.n_ctrl;
   size_t fl = (size_t)2 * T * m + ((T + 3) & ~3);
   fl = (fl + 3) & ~size_t(3);
-  // the step-split body stages nothing beyond the controls; the quadrotor its obstacles
+  // the step-split body stages nothing beyond the controls (fused: and the block's normals
+  // and weights); the quadrotor its obstacles
   if constexpr (!Sys::kStepSplit) fl += Sys::stage_floats(c->quad.n_obs, 0);
+  else if (c->L.fused) fl += (size_t)(kBlock / rollout_lps(&c->cfg)) * (c->L.G * 4 + 2);
   return fl * 4;
 }
 
@@ -387,7 +407,8 @@ static size_t rollout_lds_bytes(const mppi_ctx *c) {
 // four-lane body; recording prefix costs under cost-to-go weighting, and with the
 // quadrotor's crash indicator when its crash_cost is positive.
 static_assert(MPPI_ROLLOUT_COST_TO_GO == kRecordPrefix && MPPI_ROLLOUT_CRASH == kCrashOn &&
-                  MPPI_ROLLOUT_STEP_SPLIT == kStepSplit && MPPI_ROLLOUT_DIAGONAL == kDiagLR,
+                  MPPI_ROLLOUT_STEP_SPLIT == kStepSplit && MPPI_ROLLOUT_DIAGONAL == kDiagLR &&
+                  MPPI_ROLLOUT_FUSED == kFused,
               "mppi_info.rollout_mode bits");
 static int rollout_mode(const mppi_ctx *c) {
   int mode = c->cfg.weighting == MPPI_WEIGHT_COST_TO_GO ? kRecordPrefix : 0;
@@ -397,6 +418,7 @@ static int rollout_mode(const mppi_ctx *c) {
     for (int j = 0; j < m; ++j)
       if (r != j && ((float)c->Ls[r * m + j] != 0.f || (float)c->Mq[r * m + j] != 0.f)) diag = false;
   if (diag) mode |= kDiagLR;
+  if (c->L.fused) mode |= kFused;
   if (rollout_split(&c->cfg)) return mode | kStepSplit;
   if (c->cfg.system == MPPI_SYS_QUADROTOR && c->quad.crash > 0.f) mode |= kCrashOn;
   return mode;
@@ -424,6 +446,7 @@ static const void *rollout_split_fn(int lps) {
 template <class Sys, int kDiagL>
 static const void *rollout_fn_for_base(int mode, int lps) {
   if (mode == (kStepSplit | kDiagL)) return rollout_split_fn<Sys, kStepSplit | kDiagL>(lps);
+  if (mode == (kStepSplit | kFused | kDiagL)) return rollout_split_fn<Sys, kStepSplit | kFused | kDiagL>(lps);
   if (mode == (kStepSplit | kRecordPrefix | kDiagL)) return rollout_split_fn<Sys, kStepSplit | kRecordPrefix | kDiagL>(lps);
   switch (mode) {
     case kDiagL: return rollout_fn<Sys, kDiagL>();
@@ -469,7 +492,8 @@ static int launch_rollout(mppi_ctx *c, const IterArgs &a, const typename Sys::Pa
   const void *fn = rollout_fn_for<Sys>(rollout_mode(c), rollout_lps(&c->cfg));
   if (!fn) return fail(MPPI_EINVAL, "rollout variant not available for system %d", c->cfg.system);
   void *args[] = {(void *)&a, (void *)&p};
-  return timed_launch(c, 0, fn, dim3(c->L.n_roll_blocks), dim3(kBlock), args, lds, s);
+  const int extra = c->L.fused ? 1 : 0;              // fused: the shadow / plant-basis block
+  return timed_launch(c, 0, fn, dim3(c->L.n_roll_blocks + extra), dim3(kBlock), args, lds, s);
 }
 
 template <class Sys>
@@ -487,6 +511,8 @@ static IterArgs make_iter_args(mppi_ctx *c, const double *x0) {
   std::memset(&a, 0, sizeof(a));
   const Layout &L = c->L;
   a.x0 = x0;
+  a.U64 = (const double *)(c->base + L.off_U64);
+  if (L.fused) a.Ushadow = (double *)(c->base + L.off_shadow);
   a.U32 = (const float *)(c->base + L.off_U32);
   a.S = (double *)(c->base + L.off_S);
   a.blk_min = (double *)(c->base + L.off_blk_min);
@@ -530,6 +556,13 @@ static FinalizeArgs make_fin_args(mppi_ctx *c, double *u0_out, int emit) {
   f.T = c->cfg.T; f.m = c->cfg.n_ctrl; f.G = L.G; f.n_kc = L.n_kc;
   f.emit = emit;
   f.ctg = c->cfg.weighting == MPPI_WEIGHT_COST_TO_GO;
+  if (L.fused) {
+    f.fused = 1;
+    f.n_parts = L.n_roll_blocks;
+    f.blk_min = (const double *)(c->base + L.off_blk_min);
+    f.Ushadow = (const double *)(c->base + L.off_shadow);
+  }
+  f.inv_lambda = 1.0 / c->cfg.lambda;
   for (int i = 0; i < 16; ++i) f.Ls[i] = c->Ls[i];
   for (int j = 0; j < c->cfg.n_ctrl; ++j) f.u_init[j] = c->u_init[j];
   return f;
@@ -555,13 +588,18 @@ static void prof_end(mppi_ctx *c, hipStream_t s, int kind, hipEvent_t start) {
 template <class Sys>
 static void launch_finalize_plant(mppi_ctx *c, const FinalizeArgs &f, double *x, const typename Sys::Params &p,
                                   hipStream_t s) {
-  hipLaunchKernelGGL(finalize_plant_kernel<Sys>, dim3(1), dim3(kFinBlock), 0, s, f, x, c->cfg.dt, c->cfg.n_state, p);
+  if (c->L.fused)
+    hipLaunchKernelGGL(finalize_fused_plant_kernel<Sys>, dim3(c->L.n_fin_blocks), dim3(kFinBlock), 0, s, f, x,
+                       c->cfg.dt, c->cfg.n_state, (const double *)(c->base + c->L.off_basis));
+  else
+    hipLaunchKernelGGL(finalize_plant_kernel<Sys>, dim3(1), dim3(kFinBlock), 0, s, f, x, c->cfg.dt, c->cfg.n_state, p);
 }
 
 // Last finalize of a step with the plant step fused (plant_x != NULL).
 static void launch_finalize(mppi_ctx *c, const FinalizeArgs &f, double *plant_x, hipStream_t s) {
   if (!plant_x) {
-    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kFinBlock), 0, s, f);
+    if (c->L.fused) hipLaunchKernelGGL(finalize_fused_kernel, dim3(c->L.n_fin_blocks), dim3(kFinBlock), 0, s, f);
+    else hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kFinBlock), 0, s, f);
     return;
   }
   switch (c->cfg.system) {
@@ -579,9 +617,14 @@ static void launch_finalize(mppi_ctx *c, const FinalizeArgs &f, double *plant_x,
 
 int enqueue_iterations(mppi_ctx *c, const double *x0_dev, int n_iters, double *u0_dev, hipStream_t s,
                        double *plant_x) {
-  const IterArgs a = make_iter_args(c, x0_dev);
+  const IterArgs a0 = make_iter_args(c, x0_dev);
   for (int it = 0; it < n_iters; ++it) {
     int rc = MPPI_OK;
+    IterArgs a = a0;
+    if (c->L.fused && plant_x && it == n_iters - 1) {   // the rollout evaluates the plant basis
+      a.plant_basis = (double *)(c->base + c->L.off_basis);
+      a.plant_x = plant_x;
+    }
     switch (c->cfg.system) {
       case MPPI_SYS_LINEAR:
         if (c->cfg.n_ctrl == 1) rc = launch_rollout<LinearSys<1>>(c, a, c->linear_as<1>(), s);
@@ -596,14 +639,17 @@ int enqueue_iterations(mppi_ctx *c, const double *x0_dev, int n_iters, double *u
     }
     if (rc) return rc;
     const dim3 ugrid(c->L.n_kc, (c->L.G + kUpdGroups - 1) / kUpdGroups);
-    hipEvent_t t0 = prof_begin(c, s);
-    if (a.pre) {
-      hipLaunchKernelGGL(stepmin_kernel, dim3(c->cfg.T), dim3(kBlock), 0, s, a);
-      hipLaunchKernelGGL(update_ctg_kernel, ugrid, dim3(kBlock), 0, s, a);
-    } else {
-      hipLaunchKernelGGL(update_kernel, ugrid, dim3(kBlock), 0, s, a);
+    hipEvent_t t0 = nullptr;
+    if (!c->L.fused) {                              // fused: the rollout wrote the partials
+      t0 = prof_begin(c, s);
+      if (a.pre) {
+        hipLaunchKernelGGL(stepmin_kernel, dim3(c->cfg.T), dim3(kBlock), 0, s, a);
+        hipLaunchKernelGGL(update_ctg_kernel, ugrid, dim3(kBlock), 0, s, a);
+      } else {
+        hipLaunchKernelGGL(update_kernel, ugrid, dim3(kBlock), 0, s, a);
+      }
+      prof_end(c, s, 1, t0);
     }
-    prof_end(c, s, 1, t0);
     const FinalizeArgs f = make_fin_args(c, u0_dev, it == n_iters - 1);
     t0 = prof_begin(c, s);
     launch_finalize(c, f, it == n_iters - 1 ? plant_x : nullptr, s);
@@ -1048,7 +1094,7 @@ extern "C" int mppi_get_info(mppi_ctx *c, mppi_info *out) {
   out->rollout_mode = mlp ? 0 : rollout_mode(c);
   out->rollout_blocks = c->L.n_roll_blocks;
   out->update_chunk = c->L.upd_chunk;
-  out->update_blocks = c->L.n_kc * ((c->L.G + kUpdGroups - 1) / kUpdGroups);
+  out->update_blocks = c->L.fused ? 0 : c->L.n_kc * ((c->L.G + kUpdGroups - 1) / kUpdGroups);
   out->noise_groups = c->L.G;
   out->workspace_bytes = c->L.total;
   return MPPI_OK;

@@ -61,23 +61,36 @@ __global__ __launch_bounds__(kBlock) void rollout_batched(const CtrlDesc *__rest
   // from the descriptor
   const IterArgs a = d.it;
   const typename Sys::Params p = sys_params<Sys>(d.p);
-  rollout_any<Sys, LPS, Mode>(a, p, w.x0, blockIdx.x - prefix[j], lds4);
+  const int lb = blockIdx.x - prefix[j];
+  if constexpr ((Mode & kFused) != 0) {
+    if (lb == a.n_roll_blocks) {                      // the controller's shadow block
+      fused_extra_block<Sys>(a, p);
+      return;
+    }
+  }
+  rollout_any<Sys, LPS, Mode>(a, p, w.x0, lb, lds4);
 }
 
 static __global__ __launch_bounds__(kBlock) void update_batched(const CtrlDesc *__restrict__ descs,
                                                                 const WorkItem *__restrict__ items,
                                                                 const int *__restrict__ prefix, int n) {
+  if ((int)blockIdx.x >= prefix[n]) return;           // the one-block grid of a batch with no update
   const int j = find_item(prefix, n, blockIdx.x);
   const CtrlDesc &d = descs[items[j].desc];
   const int l = blockIdx.x - prefix[j];
   update_body(d.it, l % d.it.n_kc, l / d.it.n_kc);
 }
 
+// One block per controller, or ceil(T*m / kFusedOut) for a fused one (prefix over the items).
 static __global__ __launch_bounds__(kFinBlock) void finalize_batched(const CtrlDesc *__restrict__ descs,
-                                                                     const WorkItem *__restrict__ items) {
+                                                                     const WorkItem *__restrict__ items,
+                                                                     const int *__restrict__ prefix, int n) {
   __shared__ double u0_s[4];
-  const WorkItem &w = items[blockIdx.x];
-  finalize_body(descs[w.desc].fin, w.out, w.out + 4, u0_s);
+  const int j = find_item(prefix, n, blockIdx.x);
+  const WorkItem &w = items[j];
+  const FinalizeArgs &f = descs[w.desc].fin;
+  if (f.fused) finalize_fused_body(f, blockIdx.x - prefix[j], w.out, w.out + 4, u0_s, [] {});
+  else finalize_body(f, w.out, w.out + 4, u0_s);
 }
 
 }  // namespace mppi

@@ -17,6 +17,14 @@
 //   finalize      one block: eta = sum_k w_k, dU = A L (sum_k w_k eps_k) / eta,
 //                 U += dU (FP64 master, FP32 copy for the next rollout); on the last
 //                 iteration of a control step emit u0 and apply the warm shift.
+//
+// The step-split systems also run the iteration as two kernels (kFused): each rollout
+// block weights its own samples against its own minimum rho_b and writes
+// (rho_b, eta_b, N_b = sum_k exp(-(S_k - rho_b)/lambda) eps_k) from the normals it drew;
+// the finalize, one block per four sequence components, rescales every block's
+// partials by exp(-(rho_b - rho)/lambda), which turns them into the weights of the
+// global minimum exactly (the sample-independent factor of the weights cancels in the
+// normalised update, Section III-B).
 #pragma once
 #include "mppi_systems.h"
 
@@ -29,6 +37,8 @@ constexpr int kUpdChunkMax = 2 * kBlock;             // samples per update block
 
 struct IterArgs {
   const double *x0;        // [n]
+  const double *U64;       // [T*m] FP64 master (kFused: copied to Ushadow by the extra rollout block)
+  double *Ushadow;         // [T*m] kFused only: the master as the finalize reads it
   const float *U32;        // [T*m] FP32 copy of the nominal sequence
   double *S;               // [K] path costs
   double *blk_min;         // [n_roll_blocks]
@@ -48,7 +58,15 @@ struct IterArgs {
   double inv_lambda;
   double *rho_out;         // update: this iteration's minimum path cost (written by one block)
   int upd_chunk;           // samples per update block (128, 256, or 512 with path weighting)
+  double *plant_basis;     // kFused, last iteration of a plant step: the extra rollout block
+  const double *plant_x;   // writes the plant basis of plant_x here ([Sys::M + 1][Sys::N]), else NULL
 };
+
+// The fused variant's limits: rollout blocks whose partials one finalize block merges (one
+// per thread), sequence components per finalize block, and LDS for a rollout block's normals.
+constexpr int kMaxFusedParts = 1024;
+constexpr int kFusedOut = 4;
+constexpr int kMaxFusedNormalsBytes = 32 * 1024;
 
 struct FinalizeArgs {
   double *U64;             // [T*m] FP64 master
@@ -63,9 +81,39 @@ struct FinalizeArgs {
   int T, m, G, n_kc;
   int emit;                // last iteration of the control step: emit u0 and shift
   int ctg;                 // cost-to-go weights: eta_part is [n_kc][T], one normaliser per step
+  int fused;               // kFused: partials of the n_parts rollout blocks, merged by
+  int n_parts;             //   ceil(T*m / kFusedOut) blocks
+  const double *blk_min;   // kFused: [n_parts] the rollout blocks' minima
+  const double *Ushadow;   // kFused: the master before this iteration
+  double inv_lambda;
   double Ls[16];           // A chol(Sigma)
   double u_init[4];
 };
+
+// --------------------------------------------------------------------- plant (FP64)
+// The harness plant step x <- x + dt xdot(x, u), FP64.  Every system is affine in its
+// control, so xdot(x, u) = f0 + sum_j u_j (f_{j+1} - f0) with f0 = xdot(x, 0) and
+// f_{j+1} = xdot(x, e_j): M + 1 lanes evaluate these in parallel, before u is known (in
+// the finalize kernel, while the other waves wait on their loads), and one lane combines.
+// Both plant kernels use the same two functions, so they agree bit for bit.  x holds
+// n <= Sys::N doubles; components beyond n are treated as zero and not written.
+template <class Sys>
+__device__ __forceinline__ void plant_basis(const typename Sys::Params &p, const double *x, int n, int j,
+                                            double *out) {
+  double xl[Sys::N], ul[Sys::M];
+  for (int r = 0; r < Sys::N; ++r) xl[r] = r < n ? x[r] : 0.0;
+  for (int c = 0; c < Sys::M; ++c) ul[c] = c + 1 == j ? 1.0 : 0.0;
+  Sys::xdot(p, xl, ul, out);
+}
+template <class Sys>
+__device__ __forceinline__ void plant_combine(double *x, int n, double dt, const double (*basis)[Sys::N],
+                                              const double *u) {
+  for (int r = 0; r < n; ++r) {
+    double d = basis[0][r];
+    for (int c = 0; c < Sys::M; ++c) d = fma(u[c], basis[c + 1][r] - basis[0][r], d);
+    x[r] = fma(dt, d, x[r]);
+  }
+}
 
 // ------------------------------------------------------------------------ rollout
 // One block of one controller (`blk` indexes the controller's blocks): 256 / LPS samples,
@@ -89,7 +137,9 @@ __device__ __forceinline__ float quad_sum(float v) {
 // kDiagLR: Ls and Mq are diagonal, so the noise and likelihood-ratio products keep their
 // diagonal terms only -- the general FMA chains add exact zeros to them, so both forms give
 // the same values bit for bit.
-enum { kRecordPrefix = 1, kCrashOn = 2, kStepSplit = 4, kDiagLR = 8 };
+// kFused (step-split only, path weighting): the rollout block also writes its weighted
+// partial sums, so no update kernel runs and the finalize merges the blocks' partials.
+enum { kRecordPrefix = 1, kCrashOn = 2, kStepSplit = 4, kDiagLR = 8, kFused = 16 };
 
 // One horizon step of one sample from the four normals `e` of its noise group.
 template <class Sys, int LPS, int Mode>
@@ -304,11 +354,16 @@ __device__ __forceinline__ void rollout_body_split(const IterArgs &a, const type
                                                    const double *x0, int blk, float4 *lds4) {
   static_assert((Mode & kCrashOn) == 0, "the step-split body has no crash indicator");
   static_assert(Sys::kStepSplit, "system cost acts on the state");
+  static_assert((Mode & kFused) == 0 || (Mode & kRecordPrefix) == 0, "fused: path weighting only");
   constexpr int N = Sys::N, M = Sys::M, NQ = Sys::NQ;
   constexpr int SPG = 4 / M;                        // steps per noise group
+  constexpr int SPB = kBlock / LPS;                 // samples per block
   float *sU = reinterpret_cast<float *>(lds4);      // [T*M]
   float *sRU = sU + a.T * M;                        // [T*M]  R u_i
   float *sC = sRU + a.T * M;                        // [T]    u_i'R u_i / 2
+  // kFused: the block's normals [SPB][G*4] and its samples' weights [SPB] (FP64)
+  float *sE = sU + ((2 * a.T * M + ((a.T + 3) & ~3) + 3) & ~3);
+  double *sW = reinterpret_cast<double *>(sE + SPB * a.G * 4);
   __shared__ double red[4];
 
   const uint64_t it = *a.iter;
@@ -342,6 +397,9 @@ __device__ __forceinline__ void rollout_body_split(const IterArgs &a, const type
     const int g = g0 + lane_j;
     float e[4];
     normals4((uint32_t)g, (uint32_t)k, it, a.key0, a.key1, e);
+    if constexpr ((Mode & kFused) != 0)
+      if (g < a.G)
+        *reinterpret_cast<float4 *>(sE + ((threadIdx.x / LPS) * a.G + g) * 4) = make_float4(e[0], e[1], e[2], e[3]);
     float du[4], lr[SPG];
 #pragma unroll
     for (int s = 0; s < SPG; ++s) {
@@ -448,6 +506,37 @@ __device__ __forceinline__ void rollout_body_split(const IterArgs &a, const type
   if (valid) a.S[k] = S;
   const double bm = block_min(valid ? S : __builtin_inf(), red);
   if (threadIdx.x == 0) a.blk_min[blk] = bm;
+  if constexpr ((Mode & kFused) != 0) {
+    // the block's weights against its own minimum, then its partial sums in sample order
+    // (the normals were published by block_min's barriers)
+    if (lane_j == 0)
+      sW[threadIdx.x / LPS] = valid && S < __builtin_inf() ? exp(-(S - bm) * a.inv_lambda) : 0.0;
+    __syncthreads();
+    const int TM = a.T * M, F = a.G * 4;
+    for (int f = threadIdx.x; f < TM; f += kBlock) {
+      double acc = 0.0;
+#pragma unroll
+      for (int sb = 0; sb < SPB; ++sb) acc = fma(sW[sb], (double)sE[sb * F + f], acc);
+      a.part[(size_t)blk * F + f] = acc;
+    }
+    if (threadIdx.x == 0) {
+      double e = 0.0;
+#pragma unroll
+      for (int sb = 0; sb < SPB; ++sb) e += sW[sb];
+      a.eta_part[blk] = e;
+    }
+  }
+}
+
+// kFused: the block past a controller's rollout blocks, off the critical paths: the master as
+// this iteration's finalize reads it (its blocks write the shifted sequence into U64 while
+// others still read the old one) and, before a plant step, the plant basis of the plant state
+// (the finalize combines it with the emitted control).
+template <class Sys>
+__device__ __forceinline__ void fused_extra_block(const IterArgs &a, const typename Sys::Params &p) {
+  for (int f = threadIdx.x; f < a.T * a.m; f += kBlock) a.Ushadow[f] = a.U64[f];
+  if (a.plant_basis && (int)threadIdx.x <= Sys::M)
+    plant_basis<Sys>(p, a.plant_x, a.n, threadIdx.x, a.plant_basis + threadIdx.x * Sys::N);
 }
 
 // The body a rollout variant runs (the single-controller and the batched kernels alike).
@@ -464,6 +553,12 @@ __device__ __forceinline__ void rollout_any(const IterArgs &a, const typename Sy
 template <class Sys, int LPS, int Mode>
 __global__ __launch_bounds__(kBlock) void rollout_kernel(const IterArgs a, const typename Sys::Params p) {
   extern __shared__ float4 lds4[];
+  if constexpr ((Mode & kFused) != 0) {
+    if ((int)blockIdx.x == a.n_roll_blocks) {
+      fused_extra_block<Sys>(a, p);
+      return;
+    }
+  }
   rollout_any<Sys, LPS, Mode>(a, p, a.x0, blockIdx.x, lds4);
 }
 
@@ -781,29 +876,131 @@ static __global__ __launch_bounds__(kFinBlock) void finalize_kernel(const Finali
   finalize_body(a, a.u0_out, nullptr, u0_s);
 }
 
-// --------------------------------------------------------------------- plant (FP64)
-// The harness plant step x <- x + dt xdot(x, u), FP64.  Every system is affine in its
-// control, so xdot(x, u) = f0 + sum_j u_j (f_{j+1} - f0) with f0 = xdot(x, 0) and
-// f_{j+1} = xdot(x, e_j): M + 1 lanes evaluate these in parallel, before u is known (in
-// the finalize kernel, while the other waves wait on their loads), and one lane combines.
-// Both plant kernels use the same two functions, so they agree bit for bit.  x holds
-// n <= Sys::N doubles; components beyond n are treated as zero and not written.
-template <class Sys>
-__device__ __forceinline__ void plant_basis(const typename Sys::Params &p, const double *x, int n, int j,
-                                            double *out) {
-  double xl[Sys::N], ul[Sys::M];
-  for (int r = 0; r < Sys::N; ++r) xl[r] = r < n ? x[r] : 0.0;
-  for (int c = 0; c < Sys::M; ++c) ul[c] = c + 1 == j ? 1.0 : 0.0;
-  Sys::xdot(p, xl, ul, out);
+// Min and fixed-order sum over a kFinBlock-thread block (16 waves); every thread gets the result.
+__device__ __forceinline__ double fin_block_min(double v, double *scratch16) {
+  constexpr int NW = kFinBlock / kWave;
+  v = wave_min(v);
+  __syncthreads();
+  if ((threadIdx.x & (kWave - 1)) == 0) scratch16[threadIdx.x / kWave] = v;
+  __syncthreads();
+  double r = scratch16[0];
+#pragma unroll
+  for (int w = 1; w < NW; ++w) r = fmin(r, scratch16[w]);
+  return r;
 }
-template <class Sys>
-__device__ __forceinline__ void plant_combine(double *x, int n, double dt, const double (*basis)[Sys::N],
-                                              const double *u) {
-  for (int r = 0; r < n; ++r) {
-    double d = basis[0][r];
-    for (int c = 0; c < Sys::M; ++c) d = fma(u[c], basis[c + 1][r] - basis[0][r], d);
-    x[r] = fma(dt, d, x[r]);
+__device__ __forceinline__ double fin_block_sum(double v, double *scratch16) {
+  constexpr int NW = kFinBlock / kWave;
+  v = wave_sum(v);
+  __syncthreads();
+  if ((threadIdx.x & (kWave - 1)) == 0) scratch16[threadIdx.x / kWave] = v;
+  __syncthreads();
+  double r = 0.0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) r += scratch16[w];
+  return r;
+}
+
+// Fused finalize, block fb of ceil(T*m / kFusedOut): components [4 fb, 4 fb + 4), whole
+// time steps since m divides 4.  Every block forms rho = min_b rho_b, the factors
+// alpha_b = exp(-(rho_b - rho)/lambda) and eta = sum_b alpha_b eta_b from the same loads in
+// the same order, so all agree bit for bit.  Thread (r, c) = (t / 4, t % 4) sums
+// alpha_b N_b,c over the rollout blocks b = r + 256 j in order of j; the sixteen runs of a
+// wave that share c are added by a butterfly, then the sixteen waves' sums in order.  The old
+// sequence comes from the shadow the rollout wrote, so the shifted write-back into U64 cannot
+// race with another block's read.  Block 0 emits u0, counts the iteration and writes the
+// diagnostics.  `after_loads` runs once the loads are issued, before the first barrier.
+// Returns with u0 in u0_s (block 0, when a.emit).
+template <class Hook>
+__device__ __forceinline__ void finalize_fused_body(const FinalizeArgs &a, int fb, double *u0_out,
+                                                    double *status_out, double *u0_s, Hook after_loads) {
+  constexpr int NT = kFinBlock, NR = NT / kFusedOut, NW = NT / kWave, kPerRun = kMaxFusedParts / NR;
+  static_assert(kFusedOut % 4 == 0 && kWave % kFusedOut == 0 && kPerRun >= 1, "fused finalize layout");
+  __shared__ double alpha[kMaxFusedParts];
+  __shared__ double wsum[NW][kFusedOut];
+  __shared__ double N_s[kFusedOut];
+  __shared__ double red[NW];
+  const int TM = a.T * a.m, P = a.n_parts, F = a.G * 4;
+  const int c = threadIdx.x % kFusedOut, r = threadIdx.x / kFusedOut;
+  const int f = fb * kFusedOut + c;
+  // every load up front: block minima and normalisers (one each per thread), this thread's
+  // partials, the old sequence and its row of A chol(Sigma), the counter
+  const double mb = (int)threadIdx.x < P ? a.blk_min[threadIdx.x] : __builtin_inf();
+  const double eb = (int)threadIdx.x < P ? a.eta_part[threadIdx.x] : 0.0;
+  double pv[kPerRun];
+#pragma unroll
+  for (int j = 0; j < kPerRun; ++j) {
+    const int b = r + NR * j;
+    pv[j] = b < P && f < TM ? a.part[(size_t)b * F + f] : 0.0;
   }
+  const bool owner = r == 0 && f < TM;
+  const int i = f / a.m, jc = f - i * a.m;
+  const double Uold = owner ? a.Ushadow[f] : 0.0;
+  double Lrow[4];
+#pragma unroll
+  for (int l = 0; l < 4; ++l) Lrow[l] = owner && l <= jc ? a.Ls[jc * a.m + l] : 0.0;
+  const uint64_t it0 = fb == 0 && threadIdx.x == 0 ? a.iter[0] : 0;
+  after_loads();
+  const double rho = fin_block_min(mb, red);
+  const bool ok = rho < __builtin_inf();
+  const double al = ok && mb < __builtin_inf() ? exp(-(mb - rho) * a.inv_lambda) : 0.0;
+  alpha[threadIdx.x] = al;                            // 0 past the last block
+  const double eta = fin_block_sum(al * eb, red);     // its barriers publish alpha
+  double acc = 0.0;
+#pragma unroll
+  for (int j = 0; j < kPerRun; ++j) acc = fma(alpha[r + NR * j], pv[j], acc);
+  // the wave's runs of component c (lanes c + kFusedOut q) by an xor butterfly: partners
+  // add the same two values, so every lane ends with the same bits
+#pragma unroll
+  for (int st = kFusedOut; st < kWave; st *= 2) acc += __shfl_xor(acc, st);
+  if ((threadIdx.x & (kWave - 1)) < kFusedOut) wsum[threadIdx.x / kWave][c] = acc;
+  __syncthreads();
+  if ((int)threadIdx.x < kFusedOut) {
+    double sum = 0.0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) sum += wsum[w][threadIdx.x];
+    N_s[threadIdx.x] = sum;
+  }
+  __syncthreads();
+  if (owner) {
+    const int base = i * a.m - fb * kFusedOut;
+    const double inv_eta = ok ? 1.0 / eta : 0.0;
+    double d = 0.0;
+#pragma unroll
+    for (int l = 0; l < 4; ++l)
+      if (l <= jc) d = fma(Lrow[l], N_s[base + l], d);
+    d = ok ? d * inv_eta : 0.0;
+    a.dbg[2 + f] = d;
+    const double Unew = Uold + d;
+    if (!a.emit) {
+      a.U64[f] = Unew;
+      a.U32[f] = (float)Unew;
+    } else {
+      if (f < a.m) {
+        u0_out[f] = Unew;
+        u0_s[f] = Unew;
+      } else {
+        a.U64[f - a.m] = Unew;
+        a.U32[f - a.m] = (float)Unew;
+      }
+      if (f >= TM - a.m) {
+        a.U64[f] = a.u_init[f - (TM - a.m)];
+        a.U32[f] = (float)a.u_init[f - (TM - a.m)];
+      }
+    }
+  }
+  if (fb == 0 && threadIdx.x == 0) {
+    a.dbg[0] = rho;
+    a.dbg[1] = ok ? eta : 0.0;
+    if (!ok) a.flags[0] += 1;
+    if (status_out) *status_out = ok ? 0.0 : -5.0;
+    a.iter[0] = it0 + 1;
+  }
+  if (a.emit) __syncthreads();                        // u0_s for the plant step
+}
+
+static __global__ __launch_bounds__(kFinBlock) void finalize_fused_kernel(const FinalizeArgs a) {
+  __shared__ double u0_s[4];
+  finalize_fused_body(a, blockIdx.x, a.u0_out, nullptr, u0_s, [] {});
 }
 
 // finalize + the plant step on the emitted control.  The last wave evaluates the plant
@@ -818,6 +1015,17 @@ __global__ __launch_bounds__(kFinBlock) void finalize_plant_kernel(const Finaliz
   if (j >= 0 && j <= Sys::M) plant_basis<Sys>(p, x, n, j, basis[j]);
   finalize_body(a, a.u0_out, nullptr, u0_s);          // its barriers publish the basis
   if (threadIdx.x == 0) plant_combine<Sys>(x, n, dt, basis, u0_s);
+}
+
+// The fused finalize + the plant step: block 0, which emits u0, combines it with the plant
+// basis the rollout's extra block wrote; no other block touches x.
+template <class Sys>
+__global__ __launch_bounds__(kFinBlock) void finalize_fused_plant_kernel(const FinalizeArgs a, double *x, double dt,
+                                                                         int n, const double *basis) {
+  __shared__ double u0_s[4];
+  finalize_fused_body(a, blockIdx.x, a.u0_out, nullptr, u0_s, [] {});
+  if (blockIdx.x == 0 && threadIdx.x == 0)
+    plant_combine<Sys>(x, n, dt, reinterpret_cast<const double (*)[Sys::N]>(basis), u0_s);
 }
 
 // The plant step alone (block of one wave).

@@ -15,6 +15,10 @@ namespace mppi {
 // Offsets (bytes) of every device buffer inside one workspace allocation.
 struct Layout {
   int TM, G, n_roll_blocks, n_kc, upd_chunk;
+  bool fused;                                        // two kernels per iteration (kFused)
+  int n_fin_blocks;                                  // finalize blocks: 1, or ceil(TM / kFusedOut) fused
+  uint64_t off_shadow;                               // fused only: the master as the finalize reads it
+  uint64_t off_basis;                                // fused only: the plant basis [M + 1][N] of a plant step
   uint64_t off_x0, off_res, off_iter, off_U64, off_U32, off_S, off_blk_min, off_eta_part, off_part, off_dbg,
       off_pre, off_rho_step, off_sys, off_extra, extra_bytes, total;   // off_pre/off_rho_step: cost-to-go only
   uint64_t off_rho;                                  // the iteration's minimum path cost
@@ -64,6 +68,7 @@ int hip_fail(hipError_t e, const char *what);
 int validate_config(const mppi_config *c);
 void compute_layout(const mppi_config *c, Layout *L);
 bool rollout_split(const mppi_config *c);
+bool fused_available(const mppi_config *c);
 int rollout_lps(const mppi_config *c);
 int enqueue_iterations(mppi_ctx *c, const double *x0_dev, int n_iters, double *u0_dev, hipStream_t s,
                        double *plant_x);

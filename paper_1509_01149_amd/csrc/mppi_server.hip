@@ -21,9 +21,13 @@ namespace {
 
 // rollout instantiations: linear m=1,2,4, cart-pole, bicycle, quadrotor, swing-up, quadrotor
 // with the crash indicator; kinds 8 + (0, 1, 2, 3, 4, 6) are the step-split systems at 16
-// lanes per sample (at 4 below that), kind 16 + 4 the bicycle at 32
-constexpr int kKinds = 24;
+// lanes per sample (at 4 below that), kind 16 + 4 the bicycle at 32; kFusedKind + k is the
+// fused variant of step-split kind k
 constexpr int kWide = 8;
+constexpr int kFusedKind = 24;
+constexpr int kKinds = 48;
+using KindMask = uint64_t;
+static_assert(kKinds <= 64, "kind sets are 64-bit masks");
 
 int kind_of(const mppi_config &c) {
   if (c.system == MPPI_SYS_QUADROTOR && ((const mppi_quadrotor_params *)c.params)->crash_cost > 0) return 7;
@@ -52,7 +56,7 @@ struct Slot {
   uint64_t bytes = 0;
   int kind = 0;
   int m = 0;
-  int n_roll = 0, n_upd = 0;
+  int n_roll = 0, n_upd = 0, n_fin = 1;
   size_t lds = 0;
   int64_t rollout_steps = 0;
 };
@@ -84,12 +88,12 @@ struct Batch {
   hipEvent_t done = nullptr;
   bool active = false;
   char *h = nullptr, *d = nullptr;
-  size_t off_items = 0, off_sel = 0, off_proll = 0, off_pupd = 0, off_x0 = 0, off_out = 0, bytes = 0;
+  size_t off_items = 0, off_sel = 0, off_proll = 0, off_pupd = 0, off_pfin = 0, off_x0 = 0, off_out = 0, bytes = 0;
   std::vector<Entry> entries;
   // BATCHED_GRAPH: one instantiated graph per set of rollout kinds a batch holds (the plan upload,
   // the kinds' rollouts as parallel branches, the update, the finalize and the result
   // download); a launch rewrites the kernel nodes' grids and counts for its batch
-  std::map<uint32_t, BatchGraph> graphs;
+  std::map<KindMask, BatchGraph> graphs;
 };
 
 
@@ -127,6 +131,19 @@ namespace {
 // The rollout instantiation of each kind (see kind_of).
 const void *roll_fn(int k) {
   switch (k) {
+    case kFusedKind + 0: return (const void *)rollout_batched<LinearSys<1>, 4, kStepSplit | kFused>;
+    case kFusedKind + 1: return (const void *)rollout_batched<LinearSys<2>, 4, kStepSplit | kFused>;
+    case kFusedKind + 2: return (const void *)rollout_batched<LinearSys<4>, 4, kStepSplit | kFused>;
+    case kFusedKind + 3: return (const void *)rollout_batched<CartPoleSys, 4, kStepSplit | kFused>;
+    case kFusedKind + 4: return (const void *)rollout_batched<BicycleSys, 4, kStepSplit | kFused>;
+    case kFusedKind + 6: return (const void *)rollout_batched<SwingUpSys, 4, kStepSplit | kFused>;
+    case kFusedKind + kWide + 0: return (const void *)rollout_batched<LinearSys<1>, 16, kStepSplit | kFused>;
+    case kFusedKind + kWide + 1: return (const void *)rollout_batched<LinearSys<2>, 16, kStepSplit | kFused>;
+    case kFusedKind + kWide + 2: return (const void *)rollout_batched<LinearSys<4>, 16, kStepSplit | kFused>;
+    case kFusedKind + kWide + 3: return (const void *)rollout_batched<CartPoleSys, 16, kStepSplit | kFused>;
+    case kFusedKind + kWide + 4: return (const void *)rollout_batched<BicycleSys, 16, kStepSplit | kFused>;
+    case kFusedKind + kWide + 6: return (const void *)rollout_batched<SwingUpSys, 16, kStepSplit | kFused>;
+    case kFusedKind + 2 * kWide + 4: return (const void *)rollout_batched<BicycleSys, 32, kStepSplit | kFused>;
     case 0: return (const void *)rollout_batched<LinearSys<1>, 4, kStepSplit>;
     case 1: return (const void *)rollout_batched<LinearSys<2>, 4, kStepSplit>;
     case 2: return (const void *)rollout_batched<LinearSys<4>, 4, kStepSplit>;
@@ -163,6 +180,7 @@ struct BatchArgs {
   const int *sel[kKinds];
   const int *proll[kKinds];
   const int *pupd;
+  const int *pfin;
   int count[kKinds];
   int nb;
 };
@@ -196,12 +214,14 @@ hipKernelNodeParams upd_params(BatchArgs &a, int blocks, void **argv) {
   return p;
 }
 
-hipKernelNodeParams fin_params(BatchArgs &a, void **argv) {
+hipKernelNodeParams fin_params(BatchArgs &a, int blocks, void **argv) {
   argv[0] = (void *)&a.descs;
   argv[1] = (void *)&a.items;
+  argv[2] = (void *)&a.pfin;
+  argv[3] = (void *)&a.nb;
   hipKernelNodeParams p{};
   p.func = (void *)finalize_batched;
-  p.gridDim = dim3(a.nb > 0 ? a.nb : 1);
+  p.gridDim = dim3(blocks > 0 ? blocks : 1);
   p.blockDim = dim3(kFinBlock);
   p.kernelParams = argv;
   return p;
@@ -216,26 +236,26 @@ void destroy_graph(BatchGraph &G) {
 // The graph of a batch stream for one set of rollout kinds: upload -> rollouts (one branch
 // per kind) -> update -> finalize -> download.  Grids and counts are placeholders until a
 // launch sets them.
-int build_graph(mppi_server *s, Batch &b, uint32_t mask, BatchArgs &a, BatchGraph &G) {
+int build_graph(mppi_server *s, Batch &b, KindMask mask, BatchArgs &a, BatchGraph &G) {
   const int B = s->cfg.max_batch;
   hipError_t e = hipGraphCreate(&G.graph, 0);
   hipGraphNode_t up = nullptr;
   if (e == hipSuccess) e = hipGraphAddMemcpyNode1D(&up, G.graph, nullptr, 0, b.d, b.h, b.off_out, hipMemcpyHostToDevice);
   std::vector<hipGraphNode_t> rolls;
   for (int k = 0; k < kKinds && e == hipSuccess; ++k) {
-    if (!(mask >> k & 1u)) continue;
+    if (!(mask >> k & 1ull)) continue;
     void *argv[5];
     const hipKernelNodeParams p = roll_params(a, k, 1, 0, argv);
     e = hipGraphAddKernelNode(&G.roll[k], G.graph, &up, 1, &p);
     rolls.push_back(G.roll[k]);
   }
-  void *uargv[4], *fargv[2];
+  void *uargv[4], *fargv[4];
   if (e == hipSuccess) {
     const hipKernelNodeParams p = upd_params(a, 1, uargv);
     e = hipGraphAddKernelNode(&G.upd, G.graph, rolls.data(), rolls.size(), &p);
   }
   if (e == hipSuccess) {
-    const hipKernelNodeParams p = fin_params(a, fargv);
+    const hipKernelNodeParams p = fin_params(a, 1, fargv);
     e = hipGraphAddKernelNode(&G.fin, G.graph, &G.upd, 1, &p);
   }
   if (e == hipSuccess)
@@ -256,11 +276,13 @@ int launch_batched(mppi_server *s, Batch &b, const std::vector<int> &sl) {
   auto *sel = (int *)(b.h + b.off_sel);
   auto *proll = (int *)(b.h + b.off_proll);
   auto *pupd = (int *)(b.h + b.off_pupd);
+  auto *pfin = (int *)(b.h + b.off_pfin);
   auto *x0 = (double *)(b.h + b.off_x0);
   int cnt[kKinds] = {0};
   size_t lds[kKinds] = {0};
   for (int k = 0; k < kKinds; ++k) proll[k * (B + 1)] = 0;
   pupd[0] = 0;
+  pfin[0] = 0;
   b.entries.clear();
   for (int j = 0; j < nb; ++j) {
     Slot &S = s->slots[sl[j]];
@@ -278,14 +300,16 @@ int launch_batched(mppi_server *s, Batch &b, const std::vector<int> &sl) {
     cnt[k] += 1;
     lds[k] = std::max(lds[k], S.lds);
     pupd[j + 1] = pupd[j] + S.n_upd;
+    pfin[j + 1] = pfin[j] + S.n_fin;
     b.entries.push_back({sl[j], r.id, r.t_arrival});
   }
   BatchArgs a;
   a.descs = s->d_descs;
   a.items = (const WorkItem *)(b.d + b.off_items);
   a.pupd = (const int *)(b.d + b.off_pupd);
+  a.pfin = (const int *)(b.d + b.off_pfin);
   a.nb = nb;
-  uint32_t mask = 0;
+  KindMask mask = 0;
   int kinds[kKinds], nk = 0;
   for (int k = 0; k < kKinds; ++k) {
     a.sel[k] = (const int *)(b.d + b.off_sel) + k * B;
@@ -293,7 +317,7 @@ int launch_batched(mppi_server *s, Batch &b, const std::vector<int> &sl) {
     a.count[k] = cnt[k];
     if (cnt[k]) {
       kinds[nk++] = k;
-      mask |= 1u << k;
+      mask |= 1ull << k;
       const int rc = ensure_lds(s, k, lds[k]);
       if (rc) return rc;
     }
@@ -318,13 +342,13 @@ int launch_batched(mppi_server *s, Batch &b, const std::vector<int> &sl) {
       const hipKernelNodeParams p = roll_params(a, k, proll[k * (B + 1) + cnt[k]], lds[k], argv);
       e = hipGraphExecKernelNodeSetParams(G.exec, G.roll[k], &p);
     }
-    void *uargv[4], *fargv[2];
+    void *uargv[4], *fargv[4];
     if (e == hipSuccess) {
       const hipKernelNodeParams p = upd_params(a, pupd[nb], uargv);
       e = hipGraphExecKernelNodeSetParams(G.exec, G.upd, &p);
     }
     if (e == hipSuccess) {
-      const hipKernelNodeParams p = fin_params(a, fargv);
+      const hipKernelNodeParams p = fin_params(a, pfin[nb], fargv);
       e = hipGraphExecKernelNodeSetParams(G.exec, G.fin, &p);
     }
     if (e == hipSuccess)
@@ -357,10 +381,12 @@ int launch_batched(mppi_server *s, Batch &b, const std::vector<int> &sl) {
       if (e == hipSuccess) e = hipStreamWaitEvent(b.stream, b.join[i], 0);
       if (e != hipSuccess) return hip_fail(e, "batch join");
     }
-    void *uargv[4], *fargv[2];
-    const hipKernelNodeParams pu = upd_params(a, pupd[nb], uargv);
-    e = hipLaunchKernel(pu.func, pu.gridDim, pu.blockDim, pu.kernelParams, 0, b.stream);
-    const hipKernelNodeParams pf = fin_params(a, fargv);
+    void *uargv[4], *fargv[4];
+    if (pupd[nb] > 0) {                             // fused controllers have no update blocks
+      const hipKernelNodeParams pu = upd_params(a, pupd[nb], uargv);
+      e = hipLaunchKernel(pu.func, pu.gridDim, pu.blockDim, pu.kernelParams, 0, b.stream);
+    }
+    const hipKernelNodeParams pf = fin_params(a, pfin[nb], fargv);
     if (e == hipSuccess) e = hipLaunchKernel(pf.func, pf.gridDim, pf.blockDim, pf.kernelParams, 0, b.stream);
     if (e == hipSuccess) e = hipMemcpyAsync(b.h + b.off_out, b.d + b.off_out, (size_t)nb * 8 * sizeof(double),
                                             hipMemcpyDeviceToHost, b.stream);
@@ -502,7 +528,8 @@ extern "C" int mppi_server_create(const mppi_server_config *cfg, mppi_server **o
     b.off_sel = al(b.off_items + sizeof(WorkItem) * B);
     b.off_proll = al(b.off_sel + sizeof(int) * kKinds * B);
     b.off_pupd = al(b.off_proll + sizeof(int) * kKinds * (B + 1));
-    b.off_x0 = al(b.off_pupd + sizeof(int) * (B + 1));
+    b.off_pfin = al(b.off_pupd + sizeof(int) * (B + 1));
+    b.off_x0 = al(b.off_pfin + sizeof(int) * (B + 1));
     b.off_out = al(b.off_x0 + sizeof(double) * 16 * B);
     b.bytes = al(b.off_out + sizeof(double) * 8 * B);
     e = hipStreamCreateWithFlags(&b.stream, hipStreamNonBlocking);
@@ -581,10 +608,11 @@ extern "C" int mppi_server_admit(mppi_server *s, const mppi_config *cfg, int32_t
   S.used = true;
   S.ctx = ctx;
   S.bytes = bytes;
-  S.kind = kind_of(c);
+  S.kind = kind_of(c) + (ctx->L.fused ? kFusedKind : 0);
   S.m = c.n_ctrl;
-  S.n_roll = ctx->L.n_roll_blocks;
-  S.n_upd = ctx->L.n_kc * ((ctx->L.G + kUpdGroups - 1) / kUpdGroups);
+  S.n_roll = ctx->L.n_roll_blocks + (ctx->L.fused ? 1 : 0);   // fused: the shadow block
+  S.n_upd = ctx->L.fused ? 0 : ctx->L.n_kc * ((ctx->L.G + kUpdGroups - 1) / kUpdGroups);
+  S.n_fin = ctx->L.n_fin_blocks;
   S.lds = ctx_rollout_lds(ctx);
   S.rollout_steps = (int64_t)c.K * c.T;
   s->used += bytes;

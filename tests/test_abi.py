@@ -107,7 +107,7 @@ def test_bicycle_map_and_quadrotor_obstacles_are_validated():
 
 
 def test_extension_fields_are_validated():
-    """Per-dimension exploration factors, the weighting, the reserved word, the crash
+    """Per-dimension exploration factors, the weighting, the kernels choice, the crash
     indicator's parameters and the swing-up pole are checked before any device work."""
     wl = W.bicycle()
     bad_nu = np.array([1.0, 0.0])
@@ -116,12 +116,23 @@ def test_extension_fields_are_validated():
     good_nu = np.array([1.0, 4.0])
     c, keep = _cfg(wl, nu_diag=B._ptr(good_nu))
     assert _ws(c)[0] == B.OK
-    for over in (dict(weighting=2), dict(weighting=-1), dict(reserved=1)):
+    for over in (dict(weighting=2), dict(weighting=-1), dict(kernels=1), dict(kernels=4)):
         c, keep = _cfg(wl, **over)
         assert _ws(c)[0] == B.EINVAL, over
+    # the fused iteration: step-split systems under path weighting only
+    for w, kernels, rc in ((wl, B.KERNELS_FUSED, B.OK), (wl, B.KERNELS_THREE, B.OK),
+                           (W.quadrotor(), B.KERNELS_FUSED, B.EINVAL), (W.quadrotor(), B.KERNELS_THREE, B.OK),
+                           (W.cartpole(), B.KERNELS_FUSED, B.OK)):
+        c, keep = _cfg(w, kernels=kernels)
+        assert _ws(c)[0] == rc, (w.name, kernels)
+    c, keep = _cfg(wl, kernels=B.KERNELS_FUSED, weighting=B.WEIGHT_COST_TO_GO)
+    assert _ws(c)[0] == B.EINVAL
+    c, keep = _cfg(wl.replace(K=1 << 20), kernels=B.KERNELS_FUSED)       # 16384 rollout blocks
+    assert _ws(c)[0] == B.EINVAL
     c, keep = _cfg(wl, weighting=B.WEIGHT_COST_TO_GO)
     rc, n_ctg = _ws(c)
-    assert rc == B.OK and n_ctg >= _ws(_cfg(wl)[0])[1] + wl.T * wl.K * 8   # prefix costs [T][K]
+    n_three = _ws(_cfg(wl, kernels=B.KERNELS_THREE)[0])[1]
+    assert rc == B.OK and n_ctg >= n_three + wl.T * wl.K * 8              # prefix costs [T][K]
     q = W.quadrotor(crash=True)
     c, keep = _cfg(q)
     assert _ws(c)[0] == B.OK

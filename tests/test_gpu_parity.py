@@ -245,12 +245,16 @@ def test_cost_to_go_parity(name):
 
 
 def test_cost_to_go_first_step_equals_path_weighting():
-    """At step 0 the cost-to-go is the whole path cost: u_0 must be bitwise the same
-    under both weightings; later steps must differ."""
+    """At step 0 the cost-to-go is the whole path cost: u_0 must be bitwise the same under
+    both weightings through the same kernels (the three-kernel iteration; cost-to-go has no
+    fused one), and the same to FP64 reassociation through the fused path iteration; later
+    steps must differ."""
     wl = W.bicycle(K=2048, T=50).replace(seed=9)
-    with controller(wl) as a, controller(wl, weighting=P.WEIGHT_COST_TO_GO) as b:
-        ua, ub = a.step(wl.x0), b.step(wl.x0)
+    with controller(wl, kernels=P.KERNELS_THREE) as a, controller(wl, weighting=P.WEIGHT_COST_TO_GO) as b, \
+            controller(wl) as f:
+        ua, ub, uf = a.step(wl.x0), b.step(wl.x0), f.step(wl.x0)
         assert np.array_equal(ua, ub)
+        assert np.max(np.abs(uf - ub)) <= 1e-9 * max(1.0, np.max(np.abs(ub)))
         assert not np.array_equal(a.get_controls(), b.get_controls())
 
 
@@ -346,9 +350,9 @@ def test_graph_cache_stays_bounded_and_correct():
 
 
 def test_closed_loop_run_equals_single_steps():
-    """mppi_run_closed_loop_async over n steps == n calls of mppi_step_plant_async, bitwise.
-    On the step-split systems the run completes each step inside the next step's rollout
-    (fused finalize) while single steps end with the finalize kernel; both weightings."""
+    """mppi_run_closed_loop_async over n steps == n calls of mppi_step_plant_async, bitwise:
+    the captured run and the single steps launch the same kernels (the finalize with the
+    plant step fused); both weightings, so both the two- and the three-kernel iteration."""
     import torch
     dev = torch.device("cuda:0")
     cases = [(W.bicycle(K=2048, T=50), P.WEIGHT_PATH), (W.quadrotor(nu=2.0, K=1024, T=40), P.WEIGHT_PATH),

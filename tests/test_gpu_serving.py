@@ -39,8 +39,17 @@ def mix():
     ]
 
 
-def serve_rounds(srv, wls, rounds):
-    slots = [srv.admit(**P.controller_args(wl)) for wl in wls]
+def mix_kernels():
+    """The mix plus two bicycles that differ only in their kernels per iteration, so one batch
+    holds fused and three-kernel controllers of the same system (keyword arguments per entry)."""
+    wls = mix()
+    extra = W.bicycle(K=2048, T=50).replace(seed=38)
+    return (wls + [extra, extra], [{}] * len(wls) + [dict(kernels=P.KERNELS_THREE), dict(kernels=P.KERNELS_FUSED)])
+
+
+def serve_rounds(srv, wls, rounds, kws=None):
+    kws = kws or [{}] * len(wls)
+    slots = [srv.admit(**P.controller_args(wl, **kw)) for wl, kw in zip(wls, kws)]
     out = {s: [] for s in slots}
     rid = 0
     for r in range(rounds):
@@ -59,24 +68,24 @@ def serve_rounds(srv, wls, rounds):
     return [np.array(out[s]) for s in slots], finals
 
 
-def alone(wl, rounds):
-    with P.controller_for(wl) as c:
+def alone(wl, rounds, **kw):
+    with P.controller_for(wl, **kw) as c:
         us = [np.pad(c.step(wl.x0), (0, 4 - wl.m)) for _ in range(rounds)]
         return np.array(us), c.get_controls()
 
 
 def test_alone_equals_mix_and_plain():
-    wls = mix()
+    wls, kws = mix_kernels()
     with P.Server(max_slots=16, max_inflight=3) as srv:
-        mixed, mixed_U = serve_rounds(srv, wls, 3)
+        mixed, mixed_U = serve_rounds(srv, wls, 3, kws)
         st = srv.stats()
         assert st["requests_done"] == 3 * len(wls) and st["mean_batch"] > 1
     with P.Server(max_slots=16, mode=P.SERVE_PLAIN) as srv:
-        plain, plain_U = serve_rounds(srv, wls, 3)
+        plain, plain_U = serve_rounds(srv, wls, 3, kws)
     with P.Server(max_slots=16, max_inflight=3, mode=P.SERVE_BATCHED_GRAPH) as srv:
-        graph, graph_U = serve_rounds(srv, wls, 3)
-    for j, wl in enumerate(wls):
-        u_alone, U_alone = alone(wl, 3)
+        graph, graph_U = serve_rounds(srv, wls, 3, kws)
+    for j, (wl, kw) in enumerate(zip(wls, kws)):
+        u_alone, U_alone = alone(wl, 3, **kw)
         assert np.array_equal(mixed[j], u_alone), wl.name
         assert np.array_equal(mixed_U[j], U_alone), wl.name
         assert np.array_equal(graph[j], u_alone), wl.name
