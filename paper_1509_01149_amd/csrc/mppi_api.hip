@@ -143,7 +143,7 @@ int validate_config(const mppi_config *c) {
     return fail(MPPI_EINVAL, "unknown kernels value %d", c->kernels);
   if (c->kernels == MPPI_KERNELS_FUSED && !fused_available(c))
     return fail(MPPI_EINVAL, "the fused iteration needs a step-split system, path weighting, at most %d rollout "
-                "blocks and a block's normals within %d bytes of LDS", kMaxFusedParts, kMaxFusedNormalsBytes);
+                "blocks and a block's normals within %d bytes of LDS", kMaxMergedParts, kMaxFusedNormalsBytes);
   if (c->weighting == MPPI_WEIGHT_COST_TO_GO && c->system == MPPI_SYS_QUADROTOR_MLP)
     return fail(MPPI_EINVAL, "cost-to-go weighting is not available with the learned dynamics");
   if (c->u_nominal0 && !finite_all(c->u_nominal0, c->T * mm)) return fail(MPPI_EINVAL, "u_nominal0 has non-finite entries");
@@ -225,7 +225,7 @@ bool fused_available(const mppi_config *c) {
   if (!rollout_split(c) || c->weighting != MPPI_WEIGHT_PATH) return false;
   const int lps = rollout_lps(c), spb = kBlock / lps;
   const int64_t n_roll = ((int64_t)c->K + spb - 1) / spb, G = ((int64_t)c->T * c->n_ctrl + 3) / 4;
-  return n_roll <= kMaxFusedParts && spb * G * 16 <= kMaxFusedNormalsBytes;
+  return n_roll <= kMaxMergedParts && spb * G * 16 <= kMaxFusedNormalsBytes;
 }
 
 void compute_layout(const mppi_config *c, Layout *L) {
@@ -245,7 +245,10 @@ void compute_layout(const mppi_config *c, Layout *L) {
   else L->upd_chunk = 512;
   L->n_kc = (K + L->upd_chunk - 1) / L->upd_chunk;
   L->fused = c->kernels != MPPI_KERNELS_THREE && fused_available(c);
-  L->n_fin_blocks = L->fused ? (L->TM + kFusedOut - 1) / kFusedOut : 1;
+  // the multi-block finalize with the fused rollout (its P rollout partials are too many for
+  // one block); the update's few chunk partials merge faster in one block
+  L->multi = L->fused;
+  L->n_fin_blocks = L->multi ? (L->TM + kFinOut - 1) / kFinOut : 1;
   const int n_parts = L->fused ? L->n_roll_blocks : L->n_kc;
   uint64_t o = 0;
   auto take = [&](uint64_t bytes) { uint64_t r = o; o = align256(o + bytes); return r; };
@@ -259,8 +262,8 @@ void compute_layout(const mppi_config *c, Layout *L) {
   const bool ctg = c->weighting == MPPI_WEIGHT_COST_TO_GO;
   L->off_eta_part = take((uint64_t)n_parts * (ctg ? T : 1) * 8);
   L->off_part = take((uint64_t)n_parts * L->G * 4 * 8);
-  L->off_shadow = L->fused ? take((uint64_t)L->TM * 8) : 0;
-  L->off_basis = L->fused ? take((uint64_t)5 * 16 * 8) : 0;
+  L->off_shadow = L->multi ? take((uint64_t)L->TM * 8) : 0;
+  L->off_basis = L->multi ? take((uint64_t)5 * 16 * 8) : 0;
   L->off_dbg = take((uint64_t)(2 + L->TM) * 8);
   L->off_pre = ctg ? take((uint64_t)T * K * 8) : 0;
   L->off_rho_step = ctg ? take((uint64_t)T * 8) : 0;
@@ -492,7 +495,7 @@ static int launch_rollout(mppi_ctx *c, const IterArgs &a, const typename Sys::Pa
   const void *fn = rollout_fn_for<Sys>(rollout_mode(c), rollout_lps(&c->cfg));
   if (!fn) return fail(MPPI_EINVAL, "rollout variant not available for system %d", c->cfg.system);
   void *args[] = {(void *)&a, (void *)&p};
-  const int extra = c->L.fused ? 1 : 0;              // fused: the shadow / plant-basis block
+  const int extra = c->L.multi ? 1 : 0;              // the shadow / plant-basis block
   return timed_launch(c, 0, fn, dim3(c->L.n_roll_blocks + extra), dim3(kBlock), args, lds, s);
 }
 
@@ -512,7 +515,7 @@ static IterArgs make_iter_args(mppi_ctx *c, const double *x0) {
   const Layout &L = c->L;
   a.x0 = x0;
   a.U64 = (const double *)(c->base + L.off_U64);
-  if (L.fused) a.Ushadow = (double *)(c->base + L.off_shadow);
+  if (L.multi) a.Ushadow = (double *)(c->base + L.off_shadow);
   a.U32 = (const float *)(c->base + L.off_U32);
   a.S = (double *)(c->base + L.off_S);
   a.blk_min = (double *)(c->base + L.off_blk_min);
@@ -556,8 +559,8 @@ static FinalizeArgs make_fin_args(mppi_ctx *c, double *u0_out, int emit) {
   f.T = c->cfg.T; f.m = c->cfg.n_ctrl; f.G = L.G; f.n_kc = L.n_kc;
   f.emit = emit;
   f.ctg = c->cfg.weighting == MPPI_WEIGHT_COST_TO_GO;
-  if (L.fused) {
-    f.fused = 1;
+  if (L.multi) {
+    f.multi = 1;
     f.n_parts = L.n_roll_blocks;
     f.blk_min = (const double *)(c->base + L.off_blk_min);
     f.Ushadow = (const double *)(c->base + L.off_shadow);
@@ -588,8 +591,8 @@ static void prof_end(mppi_ctx *c, hipStream_t s, int kind, hipEvent_t start) {
 template <class Sys>
 static void launch_finalize_plant(mppi_ctx *c, const FinalizeArgs &f, double *x, const typename Sys::Params &p,
                                   hipStream_t s) {
-  if (c->L.fused)
-    hipLaunchKernelGGL(finalize_fused_plant_kernel<Sys>, dim3(c->L.n_fin_blocks), dim3(kFinBlock), 0, s, f, x,
+  if (c->L.multi)
+    hipLaunchKernelGGL(finalize_multi_plant_kernel<Sys>, dim3(c->L.n_fin_blocks), dim3(kFinBlock), 0, s, f, x,
                        c->cfg.dt, c->cfg.n_state, (const double *)(c->base + c->L.off_basis));
   else
     hipLaunchKernelGGL(finalize_plant_kernel<Sys>, dim3(1), dim3(kFinBlock), 0, s, f, x, c->cfg.dt, c->cfg.n_state, p);
@@ -598,7 +601,7 @@ static void launch_finalize_plant(mppi_ctx *c, const FinalizeArgs &f, double *x,
 // Last finalize of a step with the plant step fused (plant_x != NULL).
 static void launch_finalize(mppi_ctx *c, const FinalizeArgs &f, double *plant_x, hipStream_t s) {
   if (!plant_x) {
-    if (c->L.fused) hipLaunchKernelGGL(finalize_fused_kernel, dim3(c->L.n_fin_blocks), dim3(kFinBlock), 0, s, f);
+    if (c->L.multi) hipLaunchKernelGGL(finalize_multi_kernel, dim3(c->L.n_fin_blocks), dim3(kFinBlock), 0, s, f);
     else hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kFinBlock), 0, s, f);
     return;
   }
@@ -621,7 +624,7 @@ int enqueue_iterations(mppi_ctx *c, const double *x0_dev, int n_iters, double *u
   for (int it = 0; it < n_iters; ++it) {
     int rc = MPPI_OK;
     IterArgs a = a0;
-    if (c->L.fused && plant_x && it == n_iters - 1) {   // the rollout evaluates the plant basis
+    if (c->L.multi && plant_x && it == n_iters - 1) {   // the rollout evaluates the plant basis
       a.plant_basis = (double *)(c->base + c->L.off_basis);
       a.plant_x = plant_x;
     }

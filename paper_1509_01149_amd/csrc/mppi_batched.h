@@ -62,11 +62,9 @@ __global__ __launch_bounds__(kBlock) void rollout_batched(const CtrlDesc *__rest
   const IterArgs a = d.it;
   const typename Sys::Params p = sys_params<Sys>(d.p);
   const int lb = blockIdx.x - prefix[j];
-  if constexpr ((Mode & kFused) != 0) {
-    if (lb == a.n_roll_blocks) {                      // the controller's shadow block
-      fused_extra_block<Sys>(a, p);
-      return;
-    }
+  if (a.Ushadow && lb == a.n_roll_blocks) {           // the controller's shadow block
+    shadow_block<Sys>(a, p);
+    return;
   }
   rollout_any<Sys, LPS, Mode>(a, p, w.x0, lb, lds4);
 }
@@ -81,7 +79,8 @@ static __global__ __launch_bounds__(kBlock) void update_batched(const CtrlDesc *
   update_body(d.it, l % d.it.n_kc, l / d.it.n_kc);
 }
 
-// One block per controller, or ceil(T*m / kFusedOut) for a fused one (prefix over the items).
+// One block per controller, or ceil(T*m / kFinOut) with the multi-block finalize (prefix over
+// the items).
 static __global__ __launch_bounds__(kFinBlock) void finalize_batched(const CtrlDesc *__restrict__ descs,
                                                                      const WorkItem *__restrict__ items,
                                                                      const int *__restrict__ prefix, int n) {
@@ -89,7 +88,7 @@ static __global__ __launch_bounds__(kFinBlock) void finalize_batched(const CtrlD
   const int j = find_item(prefix, n, blockIdx.x);
   const WorkItem &w = items[j];
   const FinalizeArgs &f = descs[w.desc].fin;
-  if (f.fused) finalize_fused_body(f, blockIdx.x - prefix[j], w.out, w.out + 4, u0_s, [] {});
+  if (f.multi) finalize_multi_body(f, blockIdx.x - prefix[j], w.out, w.out + 4, u0_s, [] {});
   else finalize_body(f, w.out, w.out + 4, u0_s);
 }
 

@@ -21,10 +21,14 @@
 // The step-split systems also run the iteration as two kernels (kFused): each rollout
 // block weights its own samples against its own minimum rho_b and writes
 // (rho_b, eta_b, N_b = sum_k exp(-(S_k - rho_b)/lambda) eps_k) from the normals it drew;
-// the finalize, one block per four sequence components, rescales every block's
-// partials by exp(-(rho_b - rho)/lambda), which turns them into the weights of the
-// global minimum exactly (the sample-independent factor of the weights cancels in the
-// normalised update, Section III-B).
+// the finalize rescales every block's partials by exp(-(rho_b - rho)/lambda), which turns
+// them into the weights of the global minimum exactly (the sample-independent factor of the
+// weights cancels in the normalised update, Section III-B).
+//
+// The fused iteration's finalize runs as one block per four sequence components (the
+// multi-block finalize): it reads the old sequence from a shadow that an extra rollout block
+// copies, so its blocks can write the shifted sequence back without racing each other's
+// reads.
 #pragma once
 #include "mppi_systems.h"
 
@@ -37,8 +41,9 @@ constexpr int kUpdChunkMax = 2 * kBlock;             // samples per update block
 
 struct IterArgs {
   const double *x0;        // [n]
-  const double *U64;       // [T*m] FP64 master (kFused: copied to Ushadow by the extra rollout block)
-  double *Ushadow;         // [T*m] kFused only: the master as the finalize reads it
+  const double *U64;       // [T*m] FP64 master
+  double *Ushadow;         // [T*m] fused: the master as the multi-block finalize reads it
+                           // (copied by the extra rollout block, index n_roll_blocks), else NULL
   const float *U32;        // [T*m] FP32 copy of the nominal sequence
   double *S;               // [K] path costs
   double *blk_min;         // [n_roll_blocks]
@@ -58,14 +63,16 @@ struct IterArgs {
   double inv_lambda;
   double *rho_out;         // update: this iteration's minimum path cost (written by one block)
   int upd_chunk;           // samples per update block (128, 256, or 512 with path weighting)
-  double *plant_basis;     // kFused, last iteration of a plant step: the extra rollout block
-  const double *plant_x;   // writes the plant basis of plant_x here ([Sys::M + 1][Sys::N]), else NULL
+  double *plant_basis;     // multi-block finalize, last iteration of a plant step: the extra
+  const double *plant_x;   // rollout block writes the plant basis of plant_x here
+                           // ([Sys::M + 1][Sys::N]), else NULL
 };
 
-// The fused variant's limits: rollout blocks whose partials one finalize block merges (one
-// per thread), sequence components per finalize block, and LDS for a rollout block's normals.
-constexpr int kMaxFusedParts = 1024;
-constexpr int kFusedOut = 4;
+// Limits of the multi-block finalize and the fused variant: partial sums one finalize block
+// merges (one per thread), sequence components per finalize block, and LDS for a fused
+// rollout block's normals.
+constexpr int kMaxMergedParts = 1024;
+constexpr int kFinOut = 4;
 constexpr int kMaxFusedNormalsBytes = 32 * 1024;
 
 struct FinalizeArgs {
@@ -81,10 +88,10 @@ struct FinalizeArgs {
   int T, m, G, n_kc;
   int emit;                // last iteration of the control step: emit u0 and shift
   int ctg;                 // cost-to-go weights: eta_part is [n_kc][T], one normaliser per step
-  int fused;               // kFused: partials of the n_parts rollout blocks, merged by
-  int n_parts;             //   ceil(T*m / kFusedOut) blocks
-  const double *blk_min;   // kFused: [n_parts] the rollout blocks' minima
-  const double *Ushadow;   // kFused: the master before this iteration
+  int multi;               // multi-block finalize (fused): ceil(T*m / kFinOut) blocks merge
+  int n_parts;             //   the partials of n_parts rollout blocks
+  const double *blk_min;   // multi-block: [n_parts] the rollout blocks' minima
+  const double *Ushadow;   // multi-block: the master before this iteration
   double inv_lambda;
   double Ls[16];           // A chol(Sigma)
   double u_init[4];
@@ -528,12 +535,12 @@ __device__ __forceinline__ void rollout_body_split(const IterArgs &a, const type
   }
 }
 
-// kFused: the block past a controller's rollout blocks, off the critical paths: the master as
-// this iteration's finalize reads it (its blocks write the shifted sequence into U64 while
-// others still read the old one) and, before a plant step, the plant basis of the plant state
-// (the finalize combines it with the emitted control).
+// Multi-block finalize: the block past a controller's rollout blocks, off the critical paths:
+// the master as this iteration's finalize reads it (its blocks write the shifted sequence into
+// U64 while others still read the old one) and, before a plant step, the plant basis of the
+// plant state (the finalize combines it with the emitted control).
 template <class Sys>
-__device__ __forceinline__ void fused_extra_block(const IterArgs &a, const typename Sys::Params &p) {
+__device__ __forceinline__ void shadow_block(const IterArgs &a, const typename Sys::Params &p) {
   for (int f = threadIdx.x; f < a.T * a.m; f += kBlock) a.Ushadow[f] = a.U64[f];
   if (a.plant_basis && (int)threadIdx.x <= Sys::M)
     plant_basis<Sys>(p, a.plant_x, a.n, threadIdx.x, a.plant_basis + threadIdx.x * Sys::N);
@@ -553,11 +560,9 @@ __device__ __forceinline__ void rollout_any(const IterArgs &a, const typename Sy
 template <class Sys, int LPS, int Mode>
 __global__ __launch_bounds__(kBlock) void rollout_kernel(const IterArgs a, const typename Sys::Params p) {
   extern __shared__ float4 lds4[];
-  if constexpr ((Mode & kFused) != 0) {
-    if ((int)blockIdx.x == a.n_roll_blocks) {
-      fused_extra_block<Sys>(a, p);
-      return;
-    }
+  if (a.Ushadow && (int)blockIdx.x == a.n_roll_blocks) {
+    shadow_block<Sys>(a, p);
+    return;
   }
   rollout_any<Sys, LPS, Mode>(a, p, a.x0, blockIdx.x, lds4);
 }
@@ -900,7 +905,7 @@ __device__ __forceinline__ double fin_block_sum(double v, double *scratch16) {
   return r;
 }
 
-// Fused finalize, block fb of ceil(T*m / kFusedOut): components [4 fb, 4 fb + 4), whole
+// Multi-block finalize, block fb of ceil(T*m / kFinOut): components [4 fb, 4 fb + 4), whole
 // time steps since m divides 4.  Every block forms rho = min_b rho_b, the factors
 // alpha_b = exp(-(rho_b - rho)/lambda) and eta = sum_b alpha_b eta_b from the same loads in
 // the same order, so all agree bit for bit.  Thread (r, c) = (t / 4, t % 4) sums
@@ -911,17 +916,17 @@ __device__ __forceinline__ double fin_block_sum(double v, double *scratch16) {
 // diagnostics.  `after_loads` runs once the loads are issued, before the first barrier.
 // Returns with u0 in u0_s (block 0, when a.emit).
 template <class Hook>
-__device__ __forceinline__ void finalize_fused_body(const FinalizeArgs &a, int fb, double *u0_out,
+__device__ __forceinline__ void finalize_multi_body(const FinalizeArgs &a, int fb, double *u0_out,
                                                     double *status_out, double *u0_s, Hook after_loads) {
-  constexpr int NT = kFinBlock, NR = NT / kFusedOut, NW = NT / kWave, kPerRun = kMaxFusedParts / NR;
-  static_assert(kFusedOut % 4 == 0 && kWave % kFusedOut == 0 && kPerRun >= 1, "fused finalize layout");
-  __shared__ double alpha[kMaxFusedParts];
-  __shared__ double wsum[NW][kFusedOut];
-  __shared__ double N_s[kFusedOut];
+  constexpr int NT = kFinBlock, NR = NT / kFinOut, NW = NT / kWave, kPerRun = kMaxMergedParts / NR;
+  static_assert(kFinOut % 4 == 0 && kWave % kFinOut == 0 && kPerRun >= 1, "multi-block finalize layout");
+  __shared__ double alpha[kMaxMergedParts];
+  __shared__ double wsum[NW][kFinOut];
+  __shared__ double N_s[kFinOut];
   __shared__ double red[NW];
   const int TM = a.T * a.m, P = a.n_parts, F = a.G * 4;
-  const int c = threadIdx.x % kFusedOut, r = threadIdx.x / kFusedOut;
-  const int f = fb * kFusedOut + c;
+  const int c = threadIdx.x % kFinOut, r = threadIdx.x / kFinOut;
+  const int f = fb * kFinOut + c;
   // every load up front: block minima and normalisers (one each per thread), this thread's
   // partials, the old sequence and its row of A chol(Sigma), the counter
   const double mb = (int)threadIdx.x < P ? a.blk_min[threadIdx.x] : __builtin_inf();
@@ -948,13 +953,13 @@ __device__ __forceinline__ void finalize_fused_body(const FinalizeArgs &a, int f
   double acc = 0.0;
 #pragma unroll
   for (int j = 0; j < kPerRun; ++j) acc = fma(alpha[r + NR * j], pv[j], acc);
-  // the wave's runs of component c (lanes c + kFusedOut q) by an xor butterfly: partners
+  // the wave's runs of component c (lanes c + kFinOut q) by an xor butterfly: partners
   // add the same two values, so every lane ends with the same bits
 #pragma unroll
-  for (int st = kFusedOut; st < kWave; st *= 2) acc += __shfl_xor(acc, st);
-  if ((threadIdx.x & (kWave - 1)) < kFusedOut) wsum[threadIdx.x / kWave][c] = acc;
+  for (int st = kFinOut; st < kWave; st *= 2) acc += __shfl_xor(acc, st);
+  if ((threadIdx.x & (kWave - 1)) < kFinOut) wsum[threadIdx.x / kWave][c] = acc;
   __syncthreads();
-  if ((int)threadIdx.x < kFusedOut) {
+  if ((int)threadIdx.x < kFinOut) {
     double sum = 0.0;
 #pragma unroll
     for (int w = 0; w < NW; ++w) sum += wsum[w][threadIdx.x];
@@ -962,7 +967,7 @@ __device__ __forceinline__ void finalize_fused_body(const FinalizeArgs &a, int f
   }
   __syncthreads();
   if (owner) {
-    const int base = i * a.m - fb * kFusedOut;
+    const int base = i * a.m - fb * kFinOut;
     const double inv_eta = ok ? 1.0 / eta : 0.0;
     double d = 0.0;
 #pragma unroll
@@ -998,9 +1003,9 @@ __device__ __forceinline__ void finalize_fused_body(const FinalizeArgs &a, int f
   if (a.emit) __syncthreads();                        // u0_s for the plant step
 }
 
-static __global__ __launch_bounds__(kFinBlock) void finalize_fused_kernel(const FinalizeArgs a) {
+static __global__ __launch_bounds__(kFinBlock) void finalize_multi_kernel(const FinalizeArgs a) {
   __shared__ double u0_s[4];
-  finalize_fused_body(a, blockIdx.x, a.u0_out, nullptr, u0_s, [] {});
+  finalize_multi_body(a, blockIdx.x, a.u0_out, nullptr, u0_s, [] {});
 }
 
 // finalize + the plant step on the emitted control.  The last wave evaluates the plant
@@ -1017,13 +1022,13 @@ __global__ __launch_bounds__(kFinBlock) void finalize_plant_kernel(const Finaliz
   if (threadIdx.x == 0) plant_combine<Sys>(x, n, dt, basis, u0_s);
 }
 
-// The fused finalize + the plant step: block 0, which emits u0, combines it with the plant
-// basis the rollout's extra block wrote; no other block touches x.
+// The multi-block finalize + the plant step: block 0, which emits u0, combines it with the
+// plant basis the rollout's extra block wrote; no other block touches x.
 template <class Sys>
-__global__ __launch_bounds__(kFinBlock) void finalize_fused_plant_kernel(const FinalizeArgs a, double *x, double dt,
+__global__ __launch_bounds__(kFinBlock) void finalize_multi_plant_kernel(const FinalizeArgs a, double *x, double dt,
                                                                          int n, const double *basis) {
   __shared__ double u0_s[4];
-  finalize_fused_body(a, blockIdx.x, a.u0_out, nullptr, u0_s, [] {});
+  finalize_multi_body(a, blockIdx.x, a.u0_out, nullptr, u0_s, [] {});
   if (blockIdx.x == 0 && threadIdx.x == 0)
     plant_combine<Sys>(x, n, dt, reinterpret_cast<const double (*)[Sys::N]>(basis), u0_s);
 }

@@ -16,9 +16,10 @@ namespace mppi {
 struct Layout {
   int TM, G, n_roll_blocks, n_kc, upd_chunk;
   bool fused;                                        // two kernels per iteration (kFused)
-  int n_fin_blocks;                                  // finalize blocks: 1, or ceil(TM / kFusedOut) fused
-  uint64_t off_shadow;                               // fused only: the master as the finalize reads it
-  uint64_t off_basis;                                // fused only: the plant basis [M + 1][N] of a plant step
+  bool multi;                                        // multi-block finalize (always when fused)
+  int n_fin_blocks;                                  // finalize blocks: 1, or ceil(TM / kFinOut) multi
+  uint64_t off_shadow;                               // multi only: the master as the finalize reads it
+  uint64_t off_basis;                                // multi only: the plant basis [M + 1][N] of a plant step
   uint64_t off_x0, off_res, off_iter, off_U64, off_U32, off_S, off_blk_min, off_eta_part, off_part, off_dbg,
       off_pre, off_rho_step, off_sys, off_extra, extra_bytes, total;   // off_pre/off_rho_step: cost-to-go only
   uint64_t off_rho;                                  // the iteration's minimum path cost

@@ -610,7 +610,7 @@ extern "C" int mppi_server_admit(mppi_server *s, const mppi_config *cfg, int32_t
   S.bytes = bytes;
   S.kind = kind_of(c) + (ctx->L.fused ? kFusedKind : 0);
   S.m = c.n_ctrl;
-  S.n_roll = ctx->L.n_roll_blocks + (ctx->L.fused ? 1 : 0);   // fused: the shadow block
+  S.n_roll = ctx->L.n_roll_blocks + (ctx->L.multi ? 1 : 0);   // the shadow block
   S.n_upd = ctx->L.fused ? 0 : ctx->L.n_kc * ((ctx->L.G + kUpdGroups - 1) / kUpdGroups);
   S.n_fin = ctx->L.n_fin_blocks;
   S.lds = ctx_rollout_lds(ctx);
