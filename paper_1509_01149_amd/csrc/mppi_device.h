@@ -16,7 +16,8 @@ constexpr int kWave = 64;
 // round forms the two 32x32->64 products of counter words 0 and 2 with the round
 // multipliers, XORs their high halves into the other two words together with the
 // key, and permutes; the key advances by the two Weyl increments between rounds.
-// Integer work only: v_mul_lo_u32 / v_mul_hi_u32 / v_xor on the VALU.
+// Integer work only: one v_mad_u64_u32 per product and one v_bitop3_b32 per three-way
+// XOR on the VALU; the key schedule is uniform (scalar unit).
 // ---------------------------------------------------------------------------------
 constexpr uint32_t kPhiloxM0 = 0xD2511F53u;
 constexpr uint32_t kPhiloxM1 = 0xCD9E8D57u;
@@ -31,7 +32,9 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
     const uint64_t p1 = (uint64_t)c.z * kPhiloxM1;
     const uint32_t lo0 = (uint32_t)p0, hi0 = (uint32_t)(p0 >> 32);
     const uint32_t lo1 = (uint32_t)p1, hi1 = (uint32_t)(p1 >> 32);
-    c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+    // each three-way XOR as one v_bitop3_b32 (truth table 0x96: the parity of the inputs)
+    c = make_uint4(__builtin_amdgcn_bitop3_b32(hi1, c.y, k0, 0x96), lo1,
+                   __builtin_amdgcn_bitop3_b32(hi0, c.w, k1, 0x96), lo0);
     k0 += kPhiloxW0;
     k1 += kPhiloxW1;
   }
