@@ -375,6 +375,9 @@ static int build_params(mppi_ctx *c) {
       qp.wg = (float)p->w_goal; qp.wo = (float)p->w_obs; qp.margin = (float)p->obs_margin;
       qp.n_obs = p->n_obstacles;
       qp.crash = (float)p->crash_cost; qp.ground = (float)p->ground_z;
+      qp.dt_m_inv = (float)(cfg.dt / p->mass);
+      qp.dt_g = (float)(cfg.dt * p->gravity);
+      for (int i = 0; i < 3; ++i) qp.dt_Jinv[i] = (float)(cfg.dt / p->inertia[i]);
       const int no = p->n_obstacles;
       float ob[(QuadrotorSys::kMaxObstacles + 1) * 5];
       std::memset(ob, 0, sizeof(ob));

@@ -148,6 +148,12 @@ __device__ __forceinline__ float quad_sum(float v) {
 // partial sums, so no update kernel runs and the finalize merges the blocks' partials.
 enum { kRecordPrefix = 1, kCrashOn = 2, kStepSplit = 4, kDiagLR = 8, kFused = 16 };
 
+// Systems with their own FP32 Euler step for the rollout (Sys::euler).
+template <class Sys, class = void>
+struct has_folded_euler : std::false_type {};
+template <class Sys>
+struct has_folded_euler<Sys, std::void_t<decltype(Sys::kFoldedEuler)>> : std::bool_constant<Sys::kFoldedEuler> {};
+
 // One horizon step of one sample from the four normals `e` of its noise group.
 template <class Sys, int LPS, int Mode>
 __device__ __forceinline__ void rollout_step(const IterArgs &a, const typename Sys::Params &p, const StageView &sv,
@@ -170,13 +176,16 @@ __device__ __forceinline__ void rollout_step(const IterArgs &a, const typename S
     du[j] = t;
     v[j] = sU[i * M + j] + t;
   }
-  Sys::xdot(p, x, v, xd);
   if constexpr ((Mode & kCrashOn) != 0) {
+    Sys::xdot(p, x, v, xd);
     if (!crashed) {                                 // a crashed rollout stays where it is
 #pragma unroll
       for (int r = 0; r < N; ++r) x[r] += a.dt * xd[r];
     }
+  } else if constexpr (has_folded_euler<Sys>::value) {
+    Sys::euler(p, x, v, a.dt);
   } else {
+    Sys::xdot(p, x, v, xd);
 #pragma unroll
     for (int r = 0; r < N; ++r) x[r] += a.dt * xd[r];
   }

@@ -448,6 +448,7 @@ struct QuadrotorSys {
     // |p|^2, and the crash test |p - c| < r is that argument above the second value
     const float4 *obs;
     float crash, ground; // crash indicator cost (0: off) and ground height
+    float dt_m_inv, dt_g, dt_Jinv[3];   // dt / m, dt g, dt / J_i (the folded Euler step)
     double dm_inv, dg, darm, dkap, dJ[3], dJinv[3];
   };
   template <typename F>
@@ -484,6 +485,46 @@ struct QuadrotorSys {
     xd[9] = fma(wz, hy, fma(-wy, hz, tx)) * Ji0;
     xd[10] = fma(wx, hz, fma(-wz, hx, ty)) * Ji1;
     xd[11] = fma(wy, hx, fma(-wx, hy, tz)) * Ji2;
+  }
+  // One FP32 Euler step x <- x + dt xdot(x, f) of the rollout, with dt folded into the
+  // constants (dt / m, dt g, dt / J_i) so the products by dt merge into the update FMAs.
+  // The attitude's sines and cosines take the revolution x / 2 pi straight to the hardware
+  // sin / cos, which reduce it themselves (|x| up to 1608 rad; for |x| < pi the argument
+  // is the one `rev` forms, bit for bit).  The crash indicator's rollout keeps xdot and a
+  // separate update (a crashed sample does not move).
+  static constexpr bool kFoldedEuler = true;
+  __device__ static void sincos_rev(float x, float &s, float &c) {
+    const float r = x * 0.159154943091895335769f;
+    s = __builtin_amdgcn_sinf(r);
+    c = __builtin_amdgcn_cosf(r);
+  }
+  __device__ static void euler(const Params &p, float *x, const float *f, float dt) {
+    float sr, cr, sp, cp, sy, cy;
+    sincos_rev(x[6], sr, cr);
+    sincos_rev(x[7], sp, cp);
+    sincos_rev(x[8], sy, cy);
+    const float icp = frcp(cp);
+    const float ad = (f[0] + f[1] + f[2] + f[3]) * p.dt_m_inv;
+    const float wx = x[9], wy = x[10], wz = x[11];
+    const float tx = p.arm * (f[1] - f[3]);
+    const float ty = p.arm * (f[2] - f[0]);
+    const float tz = p.kap * (f[0] - f[1] + f[2] - f[3]);
+    const float hx = p.J[0] * wx, hy = p.J[1] * wy, hz = p.J[2] * wz;
+    const float tp = sp * icp;
+    // position with the old velocity, velocity with the old attitude, attitude with the old
+    // body rates, body rates last
+    x[0] = fmaf(dt, x[3], x[0]);
+    x[1] = fmaf(dt, x[4], x[1]);
+    x[2] = fmaf(dt, x[5], x[2]);
+    x[3] = fmaf(ad, cy * sp * cr + sy * sr, x[3]);
+    x[4] = fmaf(ad, sy * sp * cr - cy * sr, x[4]);
+    x[5] = fmaf(ad, cp * cr, x[5]) - p.dt_g;
+    x[6] = fmaf(dt, wx + sr * tp * wy + cr * tp * wz, x[6]);
+    x[7] = fmaf(dt, cr * wy - sr * wz, x[7]);
+    x[8] = fmaf(dt, (sr * wy + cr * wz) * icp, x[8]);
+    x[9] = fmaf(fmaf(wz, hy, fmaf(-wy, hz, tx)), p.dt_Jinv[0], x[9]);
+    x[10] = fmaf(fmaf(wx, hz, fmaf(-wz, hx, ty)), p.dt_Jinv[1], x[10]);
+    x[11] = fmaf(fmaf(wy, hx, fmaf(-wx, hy, tz)), p.dt_Jinv[2], x[11]);
   }
   // LDS: the obstacles' float4s, then (crash indicator on) their crash thresholds
   static constexpr int stage_floats(int n_obs, int) { return 5 * n_obs; }
