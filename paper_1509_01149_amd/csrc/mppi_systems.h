@@ -578,12 +578,15 @@ struct QuadrotorSys {
     }
     const float4 *ob = reinterpret_cast<const float4 *>(sv.lds);
     const float *th = sv.lds + 4 * p.n_obs;
-    if (p.n_obs > nj * kRegObs)                     // block-uniform: skipped when all fit in registers
-    for (int o = j + nj * kRegObs; o < p.n_obs; o += nj) {
-      const float arg = barrier_arg(ob[o], x, xx);
-      const float pen = fmaxf(0.f, arg);
-      barrier = fmaf(pen, pen, barrier);
-      if (kHit) h += arg > th[o] ? 1.f : 0.f;
+    // block-uniform: skipped when all fit in registers (the per-lane bounds are formed
+    // inside the branch only)
+    if (__builtin_expect(p.n_obs > nj * kRegObs, 0)) {
+      for (int o = j + nj * kRegObs; o < p.n_obs; o += nj) {
+        const float arg = barrier_arg(ob[o], x, xx);
+        const float pen = fmaxf(0.f, arg);
+        barrier = fmaf(pen, pen, barrier);
+        if (kHit) h += arg > th[o] ? 1.f : 0.f;
+      }
     }
     hit = h;
     return c + p.wo * barrier;
