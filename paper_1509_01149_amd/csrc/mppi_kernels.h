@@ -1,7 +1,7 @@
 // The MPPI iteration as three kernels (paper: Algorithm 1 with the likelihood-ratio
-// running cost and update law of Section III-C):
+// running cost and update law of Section III-C), or two (below):
 //
-//   rollout<Sys>  the step-split body (4 or 16 lanes sharing a sample's horizon) for
+//   rollout<Sys>  the step-split body (4, 16 or 32 lanes sharing a sample's horizon) for
 //                 systems whose cost does not act on the state, or the four-lane body
 //                 (a DPP quad per sample; one lane with the LPS = 1 build) for the
 //                 quadrotor, whose cost is split over the quad: draw the
