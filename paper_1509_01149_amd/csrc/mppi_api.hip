@@ -691,6 +691,9 @@ int run_iterations(mppi_ctx *c, const double *x0_dev, int n_iters, double *u0_de
     }
     hipGraph_t g = nullptr;
     hipGraphExec_t ge;
+    // the capture stream is made on the first capture: contexts that never replay their own
+    // graphs (the batched server's) hold none
+    if (!c->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
     HIP_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
     int rc = enqueue_steps(c, x0_dev, n_iters, u0_dev, c->cap_stream, plant_x, n_steps);
     hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
@@ -823,7 +826,6 @@ extern "C" int mppi_create(const mppi_config *cfg, mppi_ctx **out) {
     if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) { mppi_destroy(c); return fail(MPPI_EDEVICE, "stream create failed"); }
     c->owns_stream = true;
   }
-  if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) { mppi_destroy(c); return fail(MPPI_EDEVICE, "stream create failed"); }
   if (hipHostMalloc((void **)&c->pinned, 4096, hipHostMallocDefault) != hipSuccess) { mppi_destroy(c); return fail(MPPI_ENOMEM, "hipHostMalloc failed"); }
   rc = build_params(c);
   if (!rc) rc = init_extra(c, cfg);
