@@ -34,6 +34,7 @@ CASES = [
     W.bicycle(K=1000, T=37),                                           # ragged K and T*m
     W.bicycle(K=2048, T=60).replace(sigma=np.array([[0.5, 0.1], [0.1, 0.3]])),   # full covariance
     W.bicycle(K=1024, T=30, nu=np.array([1.0, 4.0])),                  # per-dimension nu
+    W.bicycle(K=4096, T=512),                                          # normals at the 32 KiB LDS limit
     W.cartpole(nu=2.0),
     W.cartpole(K=257, T=7),                                            # one finalize block
     W.cartpole(K=65536, T=16),                                         # 4 lanes, 1024 blocks
