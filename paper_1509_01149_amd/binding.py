@@ -110,6 +110,15 @@ def load() -> C.CDLL:
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run paper_1509_01149_amd.build.build() first")
+    # One HIP runtime per process: PyTorch's ROCm wheel brings its own copy of the runtime,
+    # so when torch is installed it is imported first and the library binds to that copy
+    # (loaded the other way round, torch's later start-up finds no GPU).
+    # MPPI_HIP_FROM_TORCH=0 skips it (processes that must not load torch).
+    if os.environ.get("MPPI_HIP_FROM_TORCH", "1") != "0":
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
     lib = C.CDLL(LIB_PATH)
     sig = {
         "mppi_workspace_bytes": [C.POINTER(Config), _u64p],

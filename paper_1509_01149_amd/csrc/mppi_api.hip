@@ -264,6 +264,11 @@ void compute_layout(const mppi_config *c, Layout *L) {
   L->off_part = take((uint64_t)n_parts * L->G * 4 * 8);
   L->off_shadow = L->multi ? take((uint64_t)L->TM * 8) : 0;
   L->off_basis = L->multi ? take((uint64_t)5 * 16 * 8) : 0;
+  // cost-to-go on the step-split body: the rollout blocks form each step's minimum over their
+  // samples from running costs kept in LDS (at most 32 KiB of them), the update reduces those
+  const int lps_c = rollout_split(c) ? rollout_lps(c) : 0;
+  L->ctg_fold = ctg_w && lps_c > 0 && (uint64_t)(kBlock / lps_c) * (T + 1) * 8 <= 32768;
+  L->off_blk_tail = L->ctg_fold ? take((uint64_t)L->n_roll_blocks * T * 8) : 0;
   L->off_dbg = take((uint64_t)(2 + L->TM) * 8);
   L->off_pre = ctg ? take((uint64_t)T * K * 8) : 0;
   L->off_rho_step = ctg ? take((uint64_t)T * 8) : 0;
@@ -406,6 +411,7 @@ static size_t rollout_lds_bytes(const mppi_ctx *c) {
   // and weights); the quadrotor its obstacles
   if constexpr (!Sys::kStepSplit) fl += Sys::stage_floats(c->quad.n_obs, 0);
   else if (c->L.fused) fl += (size_t)(kBlock / rollout_lps(&c->cfg)) * (c->L.G * 4 + 2);
+  else if (c->L.ctg_fold) fl += (size_t)(kBlock / rollout_lps(&c->cfg)) * (c->cfg.T + 1) * 2;
   return fl * 4;
 }
 
@@ -528,6 +534,7 @@ static IterArgs make_iter_args(mppi_ctx *c, const double *x0) {
   if (c->cfg.weighting == MPPI_WEIGHT_COST_TO_GO) {
     a.pre = (double *)(c->base + L.off_pre);
     a.rho_step = (double *)(c->base + L.off_rho_step);
+    if (L.ctg_fold) a.blk_tail = (double *)(c->base + L.off_blk_tail);
   }
   a.key0 = (uint32_t)c->cfg.seed;
   a.key1 = (uint32_t)(c->cfg.seed >> 32);
@@ -649,7 +656,7 @@ int enqueue_iterations(mppi_ctx *c, const double *x0_dev, int n_iters, double *u
     if (!c->L.fused) {                              // fused: the rollout wrote the partials
       t0 = prof_begin(c, s);
       if (a.pre) {
-        hipLaunchKernelGGL(stepmin_kernel, dim3(c->cfg.T), dim3(kBlock), 0, s, a);
+        if (!a.blk_tail) hipLaunchKernelGGL(stepmin_kernel, dim3(c->cfg.T), dim3(kBlock), 0, s, a);
         hipLaunchKernelGGL(update_ctg_kernel, ugrid, dim3(kBlock), 0, s, a);
       } else {
         hipLaunchKernelGGL(update_kernel, ugrid, dim3(kBlock), 0, s, a);

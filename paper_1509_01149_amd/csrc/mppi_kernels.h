@@ -52,6 +52,8 @@ struct IterArgs {
   double *eta_part;        // [n_kc] ([n_kc][T] with cost-to-go weights)
   double *pre;             // cost-to-go weights only: [T][K] sum of the first i step costs, else NULL
   double *rho_step;        // cost-to-go weights only: [T] min_k of the cost from step i onward
+  double *blk_tail;        // cost-to-go, step-split body: [T][n_roll_blocks] each rollout block's
+                           // min of the cost from step i onward (the update reduces them); else NULL
   uint32_t key0, key1;
   int n;                   // state dimension actually present in x0 (<= Sys::N)
   int K, T, m, G;          // G = ceil(T*m/4) noise groups per sample
@@ -377,9 +379,11 @@ __device__ __forceinline__ void rollout_body_split(const IterArgs &a, const type
   float *sU = reinterpret_cast<float *>(lds4);      // [T*M]
   float *sRU = sU + a.T * M;                        // [T*M]  R u_i
   float *sC = sRU + a.T * M;                        // [T]    u_i'R u_i / 2
-  // kFused: the block's normals [SPB][G*4] and its samples' weights [SPB] (FP64)
+  // kFused: the block's normals [SPB][G*4] and its samples' weights [SPB] (FP64); cost-to-go
+  // with blk_tail: the running cost before each step [SPB][T] and the path costs [SPB] (FP64)
   float *sE = sU + ((2 * a.T * M + ((a.T + 3) & ~3) + 3) & ~3);
   double *sW = reinterpret_cast<double *>(sE + SPB * a.G * 4);
+  double *sPre = reinterpret_cast<double *>(sE);
   __shared__ double red[4];
 
   const uint64_t it = *a.iter;
@@ -511,6 +515,7 @@ __device__ __forceinline__ void rollout_body_split(const IterArgs &a, const type
       for (int s = 0; s < SPG; ++s) {
         const int i = g * SPG + s;
         if (i < a.T && k < a.K) a.pre[(size_t)i * a.K + k] = r;
+        if (a.blk_tail && i < a.T) sPre[(threadIdx.x / LPS) * a.T + i] = r;
         r += (double)qt[s];
       }
       P += group_bcast_f64<LPS, LPS - 1>(incl);
@@ -522,6 +527,24 @@ __device__ __forceinline__ void rollout_body_split(const IterArgs &a, const type
   if (valid) a.S[k] = S;
   const double bm = block_min(valid ? S : __builtin_inf(), red);
   if (threadIdx.x == 0) a.blk_min[blk] = bm;
+  if constexpr ((Mode & kRecordPrefix) != 0) {
+    // the block's minimum of each step's cost from that step onward, S - (cost before it), from
+    // the running costs its lanes kept in LDS (published by block_min's barriers): the update
+    // reduces these instead of a separate pass over the [T][K] prefix costs
+    if (a.blk_tail) {
+      double *sS = sPre + SPB * a.T;
+      if (lane_j == 0) sS[threadIdx.x / LPS] = valid ? S : __builtin_inf();
+      __syncthreads();
+      for (int i = threadIdx.x; i < a.T; i += kBlock) {
+        double m = __builtin_inf();
+        for (int sb = 0; sb < SPB; ++sb) {
+          const double sv = sS[sb];
+          m = fmin(m, sv < __builtin_inf() ? sv - sPre[sb * a.T + i] : __builtin_inf());
+        }
+        a.blk_tail[(size_t)i * a.n_roll_blocks + blk] = m;
+      }
+    }
+  }
   if constexpr ((Mode & kFused) != 0) {
     // the block's weights against its own minimum, then its partial sums in sample order
     // (the normals were published by block_min's barriers)
@@ -700,6 +723,7 @@ static __global__ __launch_bounds__(kBlock) void update_ctg_kernel(const IterArg
   __shared__ double w_lds[kBlock][kMaxSteps + 1];
   __shared__ double s_lds[kBlock];
   __shared__ double wsum[4][kMaxSteps];
+  __shared__ double rmin[kBlock / kMaxSteps][kMaxSteps];
   const int kc = blockIdx.x, gcb = blockIdx.y;
   const int TM = a.T * a.m;
   const int chunk = a.upd_chunk, ppt = chunk / kUpdStrips;
@@ -713,9 +737,43 @@ static __global__ __launch_bounds__(kBlock) void update_ctg_kernel(const IterArg
     const double s = in ? a.S[k] : __builtin_inf();
     double tail[kMaxSteps], rho_i[kMaxSteps];
 #pragma unroll
-    for (int j = 0; j < kMaxSteps; ++j) {
-      tail[j] = in && j < n_i ? a.pre[(size_t)(i_lo + j) * a.K + k] : 0.0;
-      rho_i[j] = j < n_i ? a.rho_step[i_lo + j] : 0.0;
+    for (int j = 0; j < kMaxSteps; ++j) tail[j] = in && j < n_i ? a.pre[(size_t)(i_lo + j) * a.K + k] : 0.0;
+    if (a.blk_tail) {
+      // the per-step minima from the rollout blocks' own: thread (q, j) reduces blocks
+      // q, q + 16, ... of step i_lo + j, then the sixteen partial minima (min is exact, so the
+      // order does not matter); kc = 0 stores them for the finalize
+      constexpr int NQ = kBlock / kMaxSteps;
+      const int q = threadIdx.x % NQ, j = threadIdx.x / NQ;      // sixteen threads per step: coalesced
+      static_assert(kBlock / NQ == kMaxSteps, "one thread row per step");
+      double m = __builtin_inf();
+      if (j < n_i) {
+        const double *row = a.blk_tail + (size_t)(i_lo + j) * a.n_roll_blocks;
+        constexpr int kB = 16;                      // loads in flight per round
+        for (int b0 = q; b0 < a.n_roll_blocks; b0 += NQ * kB) {
+          double v[kB];
+#pragma unroll
+          for (int u = 0; u < kB; ++u) {
+            const int b = b0 + NQ * u;
+            v[u] = b < a.n_roll_blocks ? row[b] : __builtin_inf();
+          }
+#pragma unroll
+          for (int u = 0; u < kB; ++u) m = fmin(m, v[u]);
+        }
+      }
+      rmin[q][j] = m;
+      __syncthreads();
+      if ((int)threadIdx.x < n_i) {
+        double r = rmin[0][threadIdx.x];
+        for (int qq = 1; qq < NQ; ++qq) r = fmin(r, rmin[qq][threadIdx.x]);
+        rmin[0][threadIdx.x] = r;
+        if (kc == 0) a.rho_step[i_lo + threadIdx.x] = r;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int jj = 0; jj < kMaxSteps; ++jj) rho_i[jj] = jj < n_i ? rmin[0][jj] : 0.0;
+    } else {
+#pragma unroll
+      for (int jj = 0; jj < kMaxSteps; ++jj) rho_i[jj] = jj < n_i ? a.rho_step[i_lo + jj] : 0.0;
     }
     s_lds[threadIdx.x] = s;
     // the steps' block sums (each in block_sum's order) share one barrier; thread j

@@ -20,6 +20,8 @@ struct Layout {
   int n_fin_blocks;                                  // finalize blocks: 1, or ceil(TM / kFinOut) multi
   uint64_t off_shadow;                               // multi only: the master as the finalize reads it
   uint64_t off_basis;                                // multi only: the plant basis [M + 1][N] of a plant step
+  bool ctg_fold;                                     // cost-to-go, step-split: rollout blocks' step minima
+  uint64_t off_blk_tail;                             //   [n_roll_blocks][T] (no per-step minimum pass)
   uint64_t off_x0, off_res, off_iter, off_U64, off_U32, off_S, off_blk_min, off_eta_part, off_part, off_dbg,
       off_pre, off_rho_step, off_sys, off_extra, extra_bytes, total;   // off_pre/off_rho_step: cost-to-go only
   uint64_t off_rho;                                  // the iteration's minimum path cost

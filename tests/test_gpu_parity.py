@@ -220,6 +220,8 @@ CTG_CASES = {
     "bicycle": lambda: W.bicycle(K=4096, T=100),
     "bicycle_nu_diag": lambda: W.bicycle(K=3000, T=37, nu=np.array([1.0, 4.0])),
     "bicycle_4lanes": lambda: W.bicycle(K=9000, T=37),
+    # running costs beyond the rollout block's 32 KiB: the separate per-step minimum pass
+    "bicycle_long_horizon": lambda: W.bicycle(K=4096, T=600),
     "quadrotor": lambda: W.quadrotor(nu=2.0, K=4096, T=60),
 }
 

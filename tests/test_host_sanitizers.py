@@ -21,7 +21,7 @@ def san_lib():
 
 
 def test_abi_tests_pass_under_address_and_undefined_behaviour_sanitizers(san_lib):
-    env = dict(os.environ, LD_PRELOAD=S.asan_runtime(), MPPI_LIBRARY=san_lib,
+    env = dict(os.environ, LD_PRELOAD=S.asan_runtime(), MPPI_LIBRARY=san_lib, MPPI_HIP_FROM_TORCH="0",
                ASAN_OPTIONS="detect_leaks=0:halt_on_error=1:abort_on_error=0",
                UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1")
     # the library must not be loaded from the default path in the child
@@ -54,7 +54,7 @@ def test_serving_host_logic_at_bench_scale_under_address_sanitizer(san_lib):
     error, no host dereference of device memory, every request served, every session admitted
     and released."""
     lib = _mock_library()
-    env = dict(os.environ, LD_PRELOAD=S.asan_runtime(), MPPI_LIBRARY=lib,
+    env = dict(os.environ, LD_PRELOAD=S.asan_runtime(), MPPI_LIBRARY=lib, MPPI_HIP_FROM_TORCH="0",
                ASAN_OPTIONS="detect_leaks=0:halt_on_error=1", OMP_NUM_THREADS="1")
     res = subprocess.run([sys.executable, os.path.join(ROOT, "tests", "host_mock", "serve_at_scale.py"), ROOT, "1.5"],
                          cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
