@@ -41,9 +41,10 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
   return c;
 }
 
-// Uniform in (0, 1]: the top 24 bits plus one, times 2^-24 -- exact in FP32.
+// Uniform in (0, 1]: the top 24 bits plus one, times 2^-24 -- exact in FP32 (the 24-bit
+// integer converts exactly and n 2^-24 + 2^-24 is representable, so the FMA rounds nothing).
 __device__ __forceinline__ float uniform01(uint32_t x) {
-  return (float)((x >> 8) + 1u) * 0x1p-24f;
+  return fmaf((float)(x >> 8), 0x1p-24f, 0x1p-24f);
 }
 
 // Box-Muller (1958) on one pair: r = sqrt(-2 ln ua), angle 2 pi ub.  v_log_f32 is log2,
