@@ -550,6 +550,17 @@ def main():
                mppi_iters_per_s=round(1e3 / ms_per_step, 1), roofline=roofline,
                launch=dict(steps_per_launch=spl, ms_per_step_one_launch_per_step=round(ms_per_step_single, 5),
                            rollout_steps_per_s_one_launch_per_step=round(rollout_steps / (ms_per_step_single / 1e3), 1)))
+    fused_main = bool(ctrl.info()["rollout_mode"] & P.binding.ROLLOUT_FUSED)
+    out["kernels_per_iteration"] = 2 if fused_main else 3
+    if not args.no_extra and fused_main:
+        # the same workload through the three-kernel iteration (rollout, update, finalize)
+        c3, _, ms_3, ms_31, times_3 = time_controller(
+            P, torch, wl, args.steps, args.warmup, spl, weighting=P.WEIGHT_COST_TO_GO if ctg else P.WEIGHT_PATH,
+            kernels=P.KERNELS_THREE)
+        c3.close()
+        out["three_kernels"] = dict(ms_per_step=round(ms_3, 5), ms_per_step_one_launch_per_step=round(ms_31, 5),
+                                    kernel_ms_all={k: round(v[0], 5) for k, v in times_3.items()})
+        progress(f"{wl.name} timed with three kernels per iteration: {ms_3:.5f} ms per control step")
     if not args.no_extra and wl.name != "bicycle":
         wb = make_workload("bicycle")
         cb, _, ms_b, ms_b1, times_b = time_controller(P, torch, wb, args.steps, args.warmup, spl)

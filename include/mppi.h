@@ -164,10 +164,13 @@ typedef struct {
 } mppi_config;
 
 /* Kernels per iteration.  THREE: rollout, update (regenerates the noise to form the weighted
- * sums), finalize.  FUSED: the rollout also forms the weighted sums of its block's samples,
- * and the finalize merges them (MPPI_ROLLOUT_FUSED; step-split systems under path weighting
- * only, else MPPI_EINVAL).  AUTO takes FUSED wherever it is available.  Both compute the
- * update law of Section III-C; their results differ by FP64 summation order only. */
+ * sums), finalize.  FUSED: the rollout keeps its block's normals in LDS and also forms the
+ * weighted sums of its samples, and the finalize merges them (MPPI_ROLLOUT_FUSED; path
+ * weighting only, with at most 1024 rollout blocks and a block's normals within its LDS:
+ * 32 KiB on the step-split systems; on the quadrotor, without the crash indicator, the rest
+ * of a 160 KiB CU, 64 samples x T*4 floats, so T <= 153 with 32 obstacles; else
+ * MPPI_EINVAL).  AUTO takes FUSED wherever it is available.  Both compute the update law of
+ * Section III-C; their results differ by FP64 summation order only. */
 enum { MPPI_KERNELS_AUTO = 0, MPPI_KERNELS_FUSED = 2, MPPI_KERNELS_THREE = 3 };
 
 /* Weights of the update law (Section III-C).  PATH: one total path cost per sample weights
@@ -287,9 +290,8 @@ int mppi_debug_lane_groups(int32_t device, int32_t group, const float *a, const 
  * and the likelihood-ratio matrix are diagonal, so only their diagonal products are formed),
  * _FUSED (two kernels per iteration: each rollout block also writes its samples' weighted
  * noise sums against its own minimum, and the finalize, one block per 4 sequence
- * components, rescales and merges them; update_blocks is then 0.  Chosen for the step-split
- * systems under path weighting when at most 1024 rollout blocks run and a block's normals
- * fit 32 KiB of LDS);
+ * components, rescales and merges them; update_blocks is then 0.  Chosen wherever
+ * MPPI_KERNELS_FUSED is available, see mppi_config.kernels);
  * rollout_lanes is the lanes per sample (the learned dynamics: 4, sixteen samples per wave). */
 enum { MPPI_ROLLOUT_COST_TO_GO = 1, MPPI_ROLLOUT_CRASH = 2, MPPI_ROLLOUT_STEP_SPLIT = 4,
        MPPI_ROLLOUT_DIAGONAL = 8, MPPI_ROLLOUT_FUSED = 16 };

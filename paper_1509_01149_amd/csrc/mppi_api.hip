@@ -142,8 +142,9 @@ int validate_config(const mppi_config *c) {
   if (c->kernels != MPPI_KERNELS_AUTO && c->kernels != MPPI_KERNELS_FUSED && c->kernels != MPPI_KERNELS_THREE)
     return fail(MPPI_EINVAL, "unknown kernels value %d", c->kernels);
   if (c->kernels == MPPI_KERNELS_FUSED && !fused_available(c))
-    return fail(MPPI_EINVAL, "the fused iteration needs a step-split system, path weighting, at most %d rollout "
-                "blocks and a block's normals within %d bytes of LDS", kMaxMergedParts, kMaxFusedNormalsBytes);
+    return fail(MPPI_EINVAL, "the fused iteration needs path weighting, at most %d rollout blocks and a block's "
+                "normals within its LDS (%d bytes on the step-split systems, the rest of %d on the quadrotor, "
+                "whose crash indicator it does not run)", kMaxMergedParts, kMaxFusedNormalsBytes, kMaxBlockLdsBytes);
   if (c->weighting == MPPI_WEIGHT_COST_TO_GO && c->system == MPPI_SYS_QUADROTOR_MLP)
     return fail(MPPI_EINVAL, "cost-to-go weighting is not available with the learned dynamics");
   if (c->u_nominal0 && !finite_all(c->u_nominal0, c->T * mm)) return fail(MPPI_EINVAL, "u_nominal0 has non-finite entries");
@@ -219,13 +220,34 @@ int rollout_lps(const mppi_config *c) {
   return c->K <= 8192 ? 16 : 4;
 }
 
-// The fused iteration: a step-split system under path weighting, every rollout block's
-// partials mergeable by one finalize block, and a rollout block's normals within its LDS share.
+// LDS floats of a four-lane (quadrotor) rollout block: controls, R u_i, u_i'R u_i / 2, the
+// obstacles and (fused) the block's normals and weights.
+static int64_t quad_rollout_lds_floats(const mppi_config *c, int n_obs, bool fused) {
+  const int64_t T = c->T, m = c->n_ctrl, G = (T * m + 3) / 4, spb = kBlock / MPPI_ROLLOUT_LPS;
+  int64_t fl = ((2 * T * m + ((T + 3) & ~3) + 3) & ~3) + (int64_t)QuadrotorSys::stage_floats(n_obs, 0);
+  if (fused) fl = ((fl + 3) & ~3) + spb * (G * 4 + 2);
+  return fl;
+}
+
+// The fused iteration under path weighting, with every rollout block's partials mergeable by
+// one finalize block: a step-split system whose rollout block's normals fit its LDS share, or
+// the quadrotor (without the crash indicator) whose block's normals fit the rest of the CU's
+// LDS.
 bool fused_available(const mppi_config *c) {
-  if (!rollout_split(c) || c->weighting != MPPI_WEIGHT_PATH) return false;
-  const int lps = rollout_lps(c), spb = kBlock / lps;
-  const int64_t n_roll = ((int64_t)c->K + spb - 1) / spb, G = ((int64_t)c->T * c->n_ctrl + 3) / 4;
-  return n_roll <= kMaxMergedParts && spb * G * 16 <= kMaxFusedNormalsBytes;
+  if (c->weighting != MPPI_WEIGHT_PATH) return false;
+  const int64_t G = ((int64_t)c->T * c->n_ctrl + 3) / 4;
+  if (rollout_split(c)) {
+    const int spb = kBlock / rollout_lps(c);
+    const int64_t n_roll = ((int64_t)c->K + spb - 1) / spb;
+    return n_roll <= kMaxMergedParts && spb * G * 16 <= kMaxFusedNormalsBytes;
+  }
+  if (c->system != MPPI_SYS_QUADROTOR) return false;
+  const auto *q = (const mppi_quadrotor_params *)c->params;
+  if (q->crash_cost > 0) return false;
+  const int spb = kBlock / MPPI_ROLLOUT_LPS;
+  const int64_t n_roll = ((int64_t)c->K + spb - 1) / spb;
+  return n_roll <= kMaxMergedParts &&
+         4 * quad_rollout_lds_floats(c, q->n_obstacles, true) + 64 <= kMaxBlockLdsBytes;
 }
 
 void compute_layout(const mppi_config *c, Layout *L) {
@@ -383,15 +405,34 @@ static int build_params(mppi_ctx *c) {
       qp.dt_m_inv = (float)(cfg.dt / p->mass);
       qp.dt_g = (float)(cfg.dt * p->gravity);
       for (int i = 0; i < 3; ++i) qp.dt_Jinv[i] = (float)(cfg.dt / p->inertia[i]);
+      qp.dt_rev = (float)(cfg.dt / (2.0 * M_PI));
       const int no = p->n_obstacles;
+      // the obstacle scale: the largest power of two (at most 1) with s (r + margin)^2 <= 1/4
+      double max_rr = 0.0;
+      for (int j = 0; j < no; ++j) {
+        const double rr = p->obstacles[4 * j + 3] + p->obs_margin;
+        max_rr = std::fmax(max_rr, rr * rr);
+      }
+      double sc = 1.0;
+      while (sc * max_rr > 0.25) sc *= 0.5;
+      qp.obs_scale = (float)sc;
+      qp.wo_s = (float)(p->w_obs / (sc * sc));
+      qp.gq = (float)(p->w_goal / sc);
+      double gg = 0.0;
+      for (int i = 0; i < 3; ++i) {
+        qp.glin[i] = (float)(-2.0 * p->w_goal * p->goal[i]);
+        gg += p->goal[i] * p->goal[i];
+      }
+      qp.gconst = (float)(p->w_goal * gg);
       float ob[(QuadrotorSys::kMaxObstacles + 1) * 5];
       std::memset(ob, 0, sizeof(ob));
-      for (int j = 0; j < no; ++j) {   // (2 c, (r + margin)^2 - |c|^2), then (r + margin)^2 - r^2
+      for (int j = 0; j < no; ++j) {   // s (2 c, (r + margin)^2 - |c|^2), then s ((r + margin)^2 - r^2)
         const double *o = p->obstacles + 4 * j;
         const double rr = o[3] + p->obs_margin;
-        ob[4 * j + 0] = (float)(2.0 * o[0]); ob[4 * j + 1] = (float)(2.0 * o[1]); ob[4 * j + 2] = (float)(2.0 * o[2]);
-        ob[4 * j + 3] = (float)(rr * rr - (o[0] * o[0] + o[1] * o[1] + o[2] * o[2]));
-        ob[4 * (size_t)no + j] = (float)(rr * rr - o[3] * o[3]);
+        ob[4 * j + 0] = (float)(sc * 2.0 * o[0]); ob[4 * j + 1] = (float)(sc * 2.0 * o[1]);
+        ob[4 * j + 2] = (float)(sc * 2.0 * o[2]);
+        ob[4 * j + 3] = (float)(sc * (rr * rr - (o[0] * o[0] + o[1] * o[1] + o[2] * o[2])));
+        ob[4 * (size_t)no + j] = (float)(sc * (rr * rr - o[3] * o[3]));
       }
       qp.obs = (const float4 *)(c->base + c->L.off_sys);
       HIP_TRY(hipMemcpy((void *)qp.obs, ob, (size_t)(no > 0 ? no : 1) * 5 * 4, hipMemcpyHostToDevice));
@@ -408,8 +449,8 @@ static size_t rollout_lds_bytes(const mppi_ctx *c) {
   size_t fl = (size_t)2 * T * m + ((T + 3) & ~3);
   fl = (fl + 3) & ~size_t(3);
   // the step-split body stages nothing beyond the controls (fused: and the block's normals
-  // and weights); the quadrotor its obstacles
-  if constexpr (!Sys::kStepSplit) fl += Sys::stage_floats(c->quad.n_obs, 0);
+  // and weights); the quadrotor its obstacles (fused: then the block's normals and weights)
+  if constexpr (!Sys::kStepSplit) return (size_t)quad_rollout_lds_floats(&c->cfg, c->quad.n_obs, c->L.fused) * 4;
   else if (c->L.fused) fl += (size_t)(kBlock / rollout_lps(&c->cfg)) * (c->L.G * 4 + 2);
   else if (c->L.ctg_fold) fl += (size_t)(kBlock / rollout_lps(&c->cfg)) * (c->cfg.T + 1) * 2;
   return fl * 4;
@@ -462,6 +503,7 @@ static const void *rollout_fn_for_base(int mode, int lps) {
   if (mode == (kStepSplit | kRecordPrefix | kDiagL)) return rollout_split_fn<Sys, kStepSplit | kRecordPrefix | kDiagL>(lps);
   switch (mode) {
     case kDiagL: return rollout_fn<Sys, kDiagL>();
+    case kFused | kDiagL: return rollout_fn<Sys, kFused | kDiagL>();
     case kRecordPrefix | kDiagL: return rollout_fn<Sys, kRecordPrefix | kDiagL>();
     case kCrashOn | kDiagL: return rollout_fn<Sys, kCrashOn | kDiagL>();
     case kRecordPrefix | kCrashOn | kDiagL: return rollout_fn<Sys, kRecordPrefix | kCrashOn | kDiagL>();

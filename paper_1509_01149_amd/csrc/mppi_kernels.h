@@ -18,9 +18,9 @@
 //                 U += dU (FP64 master, FP32 copy for the next rollout); on the last
 //                 iteration of a control step emit u0 and apply the warm shift.
 //
-// The step-split systems also run the iteration as two kernels (kFused): each rollout
-// block weights its own samples against its own minimum rho_b and writes
-// (rho_b, eta_b, N_b = sum_k exp(-(S_k - rho_b)/lambda) eps_k) from the normals it drew;
+// Under path weighting the iteration also runs as two kernels (kFused): each rollout
+// block keeps the normals it drew in LDS, weights its own samples against its own minimum
+// rho_b and writes (rho_b, eta_b, N_b = sum_k exp(-(S_k - rho_b)/lambda) eps_k);
 // the finalize rescales every block's partials by exp(-(rho_b - rho)/lambda), which turns
 // them into the weights of the global minimum exactly (the sample-independent factor of the
 // weights cancels in the normalised update, Section III-B).
@@ -71,11 +71,13 @@ struct IterArgs {
 };
 
 // Limits of the multi-block finalize and the fused variant: partial sums one finalize block
-// merges (one per thread), sequence components per finalize block, and LDS for a fused
-// rollout block's normals.
+// merges (one per thread), sequence components per finalize block, LDS for a fused step-split
+// rollout block's normals (several blocks share a CU), and the LDS a block may take (all of
+// a gfx950 CU's: the four-lane body runs one block per CU).
 constexpr int kMaxMergedParts = 1024;
 constexpr int kFinOut = 4;
 constexpr int kMaxFusedNormalsBytes = 32 * 1024;
+constexpr int kMaxBlockLdsBytes = 160 * 1024;
 
 struct FinalizeArgs {
   double *U64;             // [T*m] FP64 master
@@ -146,22 +148,36 @@ __device__ __forceinline__ float quad_sum(float v) {
 // kDiagLR: Ls and Mq are diagonal, so the noise and likelihood-ratio products keep their
 // diagonal terms only -- the general FMA chains add exact zeros to them, so both forms give
 // the same values bit for bit.
-// kFused (step-split only, path weighting): the rollout block also writes its weighted
-// partial sums, so no update kernel runs and the finalize merges the blocks' partials.
+// kFused (path weighting): the rollout block also writes its weighted partial sums, so no
+// update kernel runs and the finalize merges the blocks' partials.
 enum { kRecordPrefix = 1, kCrashOn = 2, kStepSplit = 4, kDiagLR = 8, kFused = 16 };
+// Inside the four-lane body only (never a launch variant): the system's split cost reads
+// all its data from registers, so its LDS pass is left out.
+constexpr int kRegOnly = 32;
 
-// Systems with their own FP32 Euler step for the rollout (Sys::euler).
+// Systems with their own folded FP32 Euler step for the rollout (Sys::euler_folded, with
+// Sys::init_state and Sys::fold_controls), and systems whose state cost has a per-step
+// constant that the per-step control cost carries (Sys::step_const).
 template <class Sys, class = void>
 struct has_folded_euler : std::false_type {};
 template <class Sys>
 struct has_folded_euler<Sys, std::void_t<decltype(Sys::kFoldedEuler)>> : std::bool_constant<Sys::kFoldedEuler> {};
+template <class Sys, class = void>
+struct has_step_const : std::false_type {};
+template <class Sys>
+struct has_step_const<Sys, std::void_t<decltype(Sys::kStepConst)>> : std::bool_constant<Sys::kStepConst> {};
+// The folded step runs in every variant but the crash indicator's.
+template <class Sys, int Mode>
+constexpr bool folded_step() { return has_folded_euler<Sys>::value && (Mode & kCrashOn) == 0; }
 
-// One horizon step of one sample from the four normals `e` of its noise group.
+// One horizon step of one sample from the four normals `e` of its noise group.  With the
+// folded step, sU holds the fold of each step's nominal controls and W the fold of the
+// noise map's columns (else W is unused).
 template <class Sys, int LPS, int Mode>
 __device__ __forceinline__ void rollout_step(const IterArgs &a, const typename Sys::Params &p, const StageView &sv,
                                              const typename Sys::Regs &rg, const float *mrow, const float *sU,
                                              const float *sRU, const float *sC, int i, int s, int lane_j, int k,
-                                             const float e[4], float *x, double &S, bool &crashed) {
+                                             const float e[4], const float4 *W, float *x, double &S, bool &crashed) {
   if constexpr ((Mode & kRecordPrefix) != 0)
     if (lane_j == 0 && k < a.K) a.pre[(size_t)i * a.K + k] = S;        // cost of steps before i
   constexpr int N = Sys::N, M = Sys::M;
@@ -184,8 +200,10 @@ __device__ __forceinline__ void rollout_step(const IterArgs &a, const typename S
 #pragma unroll
       for (int r = 0; r < N; ++r) x[r] += a.dt * xd[r];
     }
-  } else if constexpr (has_folded_euler<Sys>::value) {
-    Sys::euler(p, x, v, a.dt);
+  } else if constexpr (folded_step<Sys, Mode>()) {
+    static_assert(M == 4, "the folded step maps four normals");
+    Sys::template euler_folded<(Mode & kDiagLR) != 0>(p, a.dt, x, reinterpret_cast<const float4 *>(sU)[i], W,
+                                                       e + s * M);
   } else {
     Sys::xdot(p, x, v, xd);
 #pragma unroll
@@ -197,16 +215,23 @@ __device__ __forceinline__ void rollout_step(const IterArgs &a, const typename S
   constexpr bool kSplitLR = LPS == 4 && Sys::kSplitCost && M == 4;
   float quad = 0.f, lin = 0.f, lr_in = 0.f;         // lr_in: this lane's share (split form)
   if constexpr (kSplitLR) {
-    const float duj = lane_j == 0 ? du[0] : (lane_j == 1 ? du[1] : (lane_j == 2 ? du[2] : du[3]));
-    float t = 0.f;
+    // t = (Mq du)_j + (R u_i)_j, the chain started from the second term
+    float duj, t = sRU[i * M + lane_j];
     if constexpr ((Mode & kDiagLR) != 0) {
-      t = fmaf(mrow[4], duj, 0.f);                   // mrow[4]: this lane's diagonal entry
+      // mrow[4], mrow[5]: this lane's diagonal entries of Mq and of the noise map
+      // this lane's normal, by a two-level select on the lane's bits (three v_cndmask)
+      const bool odd = (lane_j & 1) != 0;
+      const float elo = odd ? e[s * M + 1] : e[s * M], ehi = odd ? e[s * M + 3] : e[s * M + 2];
+      const float ej = (lane_j & 2) != 0 ? ehi : elo;
+      duj = fmaf(mrow[5], ej, 0.f);
+      t = fmaf(mrow[4], duj, t);
     } else {
+      duj = lane_j == 0 ? du[0] : (lane_j == 1 ? du[1] : (lane_j == 2 ? du[2] : du[3]));
 #pragma unroll
-      for (int j = 0; j < M; ++j) t += mrow[j] * du[j];
+      for (int j = 0; j < M; ++j) t = fmaf(mrow[j], du[j], t);
     }
     const float c0 = sC[i];                          // every lane reads it; lane 0 adds it
-    lr_in = duj * t + sRU[i * M + lane_j] * duj + (lane_j == 0 ? c0 : 0.f);
+    lr_in = fmaf(duj, t, lane_j == 0 ? c0 : 0.f);
   } else {
 #pragma unroll
     for (int r = 0; r < M; ++r) {
@@ -226,20 +251,57 @@ __device__ __forceinline__ void rollout_step(const IterArgs &a, const typename S
     static_assert(Sys::kCrash, "system has no crash indicator");
     float hit;
     if constexpr (LPS == 4) {
-      q = quad_sum(Sys::q_part_crash(p, sv, rg, x, lane_j, 4, hit) + lr_in);
+      q = quad_sum(Sys::template q_part_crash<(Mode & kRegOnly) != 0>(p, sv, rg, x, lane_j, 4, lr_in, hit));
       hit = quad_sum(hit);
     } else {
-      q = Sys::q_part_crash(p, sv, rg, x, 0, 1, hit);
+      q = Sys::template q_part_crash<false>(p, sv, rg, x, 0, 1, 0.f, hit);
     }
     crashed = crashed || hit > 0.f;
     if (crashed) q += p.crash;
   } else if constexpr (LPS == 4 && Sys::kSplitCost) {
-    q = quad_sum(Sys::q_part(p, sv, rg, x, lane_j, 4) + lr_in);
+    q = quad_sum(Sys::template q_part<(Mode & kRegOnly) != 0>(p, sv, rg, x, lane_j, 4, lr_in));
   } else {
     q = Sys::q(p, sv, x);
   }
   const float qt = kSplitLR ? q : q + (quad + lin + sC[i]);
   S += (double)qt;
+}
+
+// The fused iteration's block tail: the block's weights against its own minimum bm, then its
+// partial sums sum_k w_k eps_k over its samples in sample order and its normaliser.  sE holds
+// the block's normals [SPB][G*4] (published by block_min's barriers), sW [SPB] doubles;
+// `owner` marks the lane that holds sample sb's path cost S (`valid`: a sample of this
+// controller).
+template <int SPB>
+__device__ __forceinline__ void fused_tail(const IterArgs &a, int blk, int M, bool owner, int sb, bool valid, double S,
+                                           double bm, const float *sE, double *sW) {
+  if (owner) sW[sb] = valid && S < __builtin_inf() ? exp(-(S - bm) * a.inv_lambda) : 0.0;
+  __syncthreads();
+  // a thread per four components (four independent FMA chains, one 16-byte read per sample;
+  // F is a multiple of four, so a quad never leaves its sample's row), each summed over the
+  // samples in order
+  const int TM = a.T * M, F = a.G * 4, nq = (TM + 3) / 4;
+  for (int q = threadIdx.x; q < nq; q += kBlock) {
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 16
+    for (int j = 0; j < SPB; ++j) {
+      const float4 e = *reinterpret_cast<const float4 *>(sE + j * F + 4 * q);
+      const double w = sW[j];
+      acc[0] = fma(w, (double)e.x, acc[0]);
+      acc[1] = fma(w, (double)e.y, acc[1]);
+      acc[2] = fma(w, (double)e.z, acc[2]);
+      acc[3] = fma(w, (double)e.w, acc[3]);
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      if (4 * q + c < TM) a.part[(size_t)blk * F + 4 * q + c] = acc[c];
+  }
+  if (threadIdx.x == kBlock - 1) {                  // the last wave has the fewest quads
+    double e = 0.0;
+#pragma unroll
+    for (int j = 0; j < SPB; ++j) e += sW[j];
+    a.eta_part[blk] = e;
+  }
 }
 
 template <class Sys, int LPS, int Mode>
@@ -251,14 +313,29 @@ __device__ __forceinline__ void rollout_body(const IterArgs &a, const typename S
   float *sRU = sU + a.T * M;                        // [T*M]  R u_i
   float *sC = sRU + a.T * M;                        // [T]    u_i'R u_i / 2
   float *sSys = sU + ((2 * a.T * M + ((a.T + 3) & ~3) + 3) & ~3);   // system staging, 16-B aligned
+  // kFused: the block's normals [SPB][G*4] and its samples' weights [SPB] (FP64), after the
+  // system's staging (16-B aligned)
+  constexpr int SPB = kBlock / LPS;
+  static_assert((Mode & kFused) == 0 || (Mode & kRecordPrefix) == 0, "fused: path weighting only");
+  float *sE = nullptr;
+  double *sW = nullptr;
+  if constexpr ((Mode & kFused) != 0) {
+    sE = sSys + ((Sys::staged_floats(p) + 3) & ~3);
+    sW = reinterpret_cast<double *>(sE + SPB * a.G * 4);
+  }
   __shared__ double red[4];
 
   const uint64_t it = *a.iter;
+  constexpr bool kFold = folded_step<Sys, Mode>();
   // Preamble loads first (start state, this thread's first control, then the system's
   // staging loads), so their memory latencies overlap instead of following each other.
   float x[N];
+  if constexpr (kFold) {
+    Sys::init_state(x0, a.n, x);
+  } else {
 #pragma unroll
-  for (int r = 0; r < N; ++r) x[r] = r < a.n ? (float)x0[r] : 0.f;
+    for (int r = 0; r < N; ++r) x[r] = r < a.n ? (float)x0[r] : 0.f;
+  }
   float u_first[M];
 #pragma unroll
   for (int j = 0; j < M; ++j) u_first[j] = threadIdx.x < a.T ? a.U32[threadIdx.x * M + j] : 0.f;
@@ -274,24 +351,34 @@ __device__ __forceinline__ void rollout_body(const IterArgs &a, const typename S
       float s = 0.f;
 #pragma unroll
       for (int j = 0; j < M; ++j) s += a.R[r * M + j] * u[j];
-      sU[i * M + r] = u[r];
+      if constexpr (!kFold) sU[i * M + r] = u[r];
       sRU[i * M + r] = s;
       c += u[r] * s;
     }
-    sC[i] = 0.5f * c;
+    if constexpr (kFold) reinterpret_cast<float4 *>(sU)[i] = Sys::fold_controls(p, u[0], u[1], u[2], u[3]);
+    if constexpr (has_step_const<Sys>::value) sC[i] = fmaf(0.5f, c, Sys::step_const(p));
+    else sC[i] = 0.5f * c;
   }
   __syncthreads();
   const StageView sv{sSys, ti, tj};
+  // the folded step's map of the normals: W[l] = the fold of column l of A chol(Sigma)
+  float4 W[4];
+  if constexpr (kFold) {
+#pragma unroll
+    for (int l = 0; l < 4; ++l) W[l] = Sys::fold_controls(p, a.Ls[l], a.Ls[4 + l], a.Ls[8 + l], a.Ls[12 + l]);
+  }
 
   const int lane_j = threadIdx.x % LPS;
   typename Sys::Regs rg;                            // per-lane register copy of system data
   Sys::load_regs(p, sv, lane_j, LPS, rg);
-  float mrow[5] = {0.f, 0.f, 0.f, 0.f, 0.f};        // row lane_j of Mq, then its diagonal entry
+  // row lane_j of Mq, then its diagonal entry and the noise map's
+  float mrow[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   if constexpr (LPS == 4 && M == 4) {
 #pragma unroll
     for (int l = 0; l < 4; ++l)
       mrow[l] = lane_j == 0 ? a.Mq[l] : (lane_j == 1 ? a.Mq[4 + l] : (lane_j == 2 ? a.Mq[8 + l] : a.Mq[12 + l]));
     mrow[4] = lane_j == 0 ? mrow[0] : (lane_j == 1 ? mrow[1] : (lane_j == 2 ? mrow[2] : mrow[3]));
+    mrow[5] = lane_j == 0 ? a.Ls[0] : (lane_j == 1 ? a.Ls[5] : (lane_j == 2 ? a.Ls[10] : a.Ls[15]));
   }
   const int k = blk * (kBlock / LPS) + threadIdx.x / LPS;
   double S = 0.0;
@@ -303,21 +390,32 @@ __device__ __forceinline__ void rollout_body(const IterArgs &a, const typename S
 #pragma unroll
       for (int s = 0; s < SPG; ++s) {
         const int i = g * SPG + s;
-        if (i < a.T) rollout_step<Sys, LPS, Mode>(a, p, sv, rg, mrow, sU, sRU, sC, i, s, 0, k, e, x, S, crashed);
+        if (i < a.T) rollout_step<Sys, LPS, Mode>(a, p, sv, rg, mrow, sU, sRU, sC, i, s, 0, k, e, W, x, S, crashed);
       }
     }
   } else {
     static_assert(LPS == 4, "LPS is 1 or 4");
-    for (int g0 = 0; g0 < a.G; g0 += 4) {
+    // One chunk of four noise groups: lane j draws group g0 + j and the quad takes the groups
+    // in turn.  kFull: all four groups lie inside the horizon (no group is guarded, nor, with
+    // one step per group, any step).  MD carries kRegOnly when the system's cost needs no
+    // LDS pass (decided once per block, so the step loop holds no such branch).
+    auto chunk = [&](int g0, auto full_c, auto mode_c) {
+      constexpr bool kFull = decltype(full_c)::value;
+      constexpr int MD = decltype(mode_c)::value;
       float mine[4];
       normals4((uint32_t)(g0 + lane_j), (uint32_t)k, it, a.key0, a.key1, mine);
+      if constexpr ((MD & kFused) != 0)             // kept for the block's partial sums
+        if (kFull || g0 + lane_j < a.G)
+          *reinterpret_cast<float4 *>(sE + ((threadIdx.x / LPS) * a.G + g0 + lane_j) * 4) =
+              make_float4(mine[0], mine[1], mine[2], mine[3]);
 #define MPPI_QUAD_GROUP(J)                                                              \
-      if (g0 + J < a.G) {                                                               \
+      if (kFull || g0 + J < a.G) {                                                      \
         float e[4];                                                                     \
         for (int c = 0; c < 4; ++c) e[c] = quad_bcast<J>(mine[c]);                      \
         _Pragma("unroll") for (int s = 0; s < SPG; ++s) {                               \
           const int i = (g0 + J) * SPG + s;                                             \
-          if (i < a.T) rollout_step<Sys, LPS, Mode>(a, p, sv, rg, mrow, sU, sRU, sC, i, s, lane_j, k, e, x, S, crashed); \
+          if ((kFull && SPG == 1) || i < a.T)                                           \
+            rollout_step<Sys, LPS, MD>(a, p, sv, rg, mrow, sU, sRU, sC, i, s, lane_j, k, e, W, x, S, crashed); \
         }                                                                               \
       }
       MPPI_QUAD_GROUP(0)
@@ -325,7 +423,14 @@ __device__ __forceinline__ void rollout_body(const IterArgs &a, const typename S
       MPPI_QUAD_GROUP(2)
       MPPI_QUAD_GROUP(3)
 #undef MPPI_QUAD_GROUP
-    }
+    };
+    auto run = [&](auto mode_c) {
+      int g0 = 0;
+      for (; g0 + 4 <= a.G; g0 += 4) chunk(g0, std::true_type{}, mode_c);
+      if (g0 < a.G) chunk(g0, std::false_type{}, mode_c);
+    };
+    if (Sys::lds_pass(p, LPS)) run(std::integral_constant<int, Mode>{});
+    else run(std::integral_constant<int, Mode | kRegOnly>{});
   }
   S += (double)Sys::phi(p, x);
   if (!isfinite(S)) S = __builtin_inf();
@@ -333,6 +438,7 @@ __device__ __forceinline__ void rollout_body(const IterArgs &a, const typename S
   if (valid) a.S[k] = S;
   const double bm = block_min(valid ? S : __builtin_inf(), red);
   if (threadIdx.x == 0) a.blk_min[blk] = bm;
+  if constexpr ((Mode & kFused) != 0) fused_tail<SPB>(a, blk, M, lane_j == 0, threadIdx.x / LPS, valid, S, bm, sE, sW);
 }
 
 // ------------------------------------------------------------- step-split rollout
@@ -545,26 +651,7 @@ __device__ __forceinline__ void rollout_body_split(const IterArgs &a, const type
       }
     }
   }
-  if constexpr ((Mode & kFused) != 0) {
-    // the block's weights against its own minimum, then its partial sums in sample order
-    // (the normals were published by block_min's barriers)
-    if (lane_j == 0)
-      sW[threadIdx.x / LPS] = valid && S < __builtin_inf() ? exp(-(S - bm) * a.inv_lambda) : 0.0;
-    __syncthreads();
-    const int TM = a.T * M, F = a.G * 4;
-    for (int f = threadIdx.x; f < TM; f += kBlock) {
-      double acc = 0.0;
-#pragma unroll
-      for (int sb = 0; sb < SPB; ++sb) acc = fma(sW[sb], (double)sE[sb * F + f], acc);
-      a.part[(size_t)blk * F + f] = acc;
-    }
-    if (threadIdx.x == 0) {
-      double e = 0.0;
-#pragma unroll
-      for (int sb = 0; sb < SPB; ++sb) e += sW[sb];
-      a.eta_part[blk] = e;
-    }
-  }
+  if constexpr ((Mode & kFused) != 0) fused_tail<SPB>(a, blk, M, lane_j == 0, threadIdx.x / LPS, valid, S, bm, sE, sW);
 }
 
 // Multi-block finalize: the block past a controller's rollout blocks, off the critical paths:

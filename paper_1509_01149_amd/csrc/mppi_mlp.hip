@@ -643,7 +643,7 @@ static __global__ __launch_bounds__(256) void mlp_rollout_kernel(const IterArgs 
     const float px = __shfl(v[0], nn, 64), py = __shfl(v[1], nn, 64), pz = __shfl(v[2], nn, 64);
     const float4 *ob = reinterpret_cast<const float4 *>(sObs);
     const float pos[3] = {px, py, pz};
-    const float xx = fmaf(px, px, fmaf(py, py, pz * pz));
+    const float xx = QuadrotorSys::scaled_sq(p, pos);   // the obstacles are scaled by p.obs_scale
     float bar = 0.f;
     for (int j = q; j < p.n_obs; j += 4) {
       const float pen = fmaxf(0.f, QuadrotorSys::barrier_arg(ob[j], pos, xx));
@@ -666,7 +666,7 @@ static __global__ __launch_bounds__(256) void mlp_rollout_kernel(const IterArgs 
     }
     lr = __shfl(lr, 48 + nn, 64);
     const float dx = px - p.goal[0], dy = py - p.goal[1], dz = pz - p.goal[2];
-    const float qt = (p.wg * (dx * dx + dy * dy + dz * dz) + p.wo * bar) + lr;
+    const float qt = (p.wg * (dx * dx + dy * dy + dz * dz) + p.wo_s * bar) + lr;
     S += (double)qt;
   }
   if (!isfinite(S)) S = __builtin_inf();

@@ -22,7 +22,7 @@ namespace {
 // rollout instantiations: linear m=1,2,4, cart-pole, bicycle, quadrotor, swing-up, quadrotor
 // with the crash indicator; kinds 8 + (0, 1, 2, 3, 4, 6) are the step-split systems at 16
 // lanes per sample (at 4 below that), kind 16 + 4 the bicycle at 32; kFusedKind + k is the
-// fused variant of step-split kind k
+// fused variant of kind k (the step-split kinds and the quadrotor's)
 constexpr int kWide = 8;
 constexpr int kFusedKind = 24;
 constexpr int kKinds = 48;
@@ -136,6 +136,7 @@ const void *roll_fn(int k) {
     case kFusedKind + 2: return (const void *)rollout_batched<LinearSys<4>, 4, kStepSplit | kFused>;
     case kFusedKind + 3: return (const void *)rollout_batched<CartPoleSys, 4, kStepSplit | kFused>;
     case kFusedKind + 4: return (const void *)rollout_batched<BicycleSys, 4, kStepSplit | kFused>;
+    case kFusedKind + 5: return (const void *)rollout_batched<QuadrotorSys, QuadrotorSys::kLPS, kFused>;
     case kFusedKind + 6: return (const void *)rollout_batched<SwingUpSys, 4, kStepSplit | kFused>;
     case kFusedKind + kWide + 0: return (const void *)rollout_batched<LinearSys<1>, 16, kStepSplit | kFused>;
     case kFusedKind + kWide + 1: return (const void *)rollout_batched<LinearSys<2>, 16, kStepSplit | kFused>;
@@ -579,9 +580,10 @@ extern "C" int mppi_server_admit(mppi_server *s, const mppi_config *cfg, int32_t
   if (!cfg || !slot) return fail(MPPI_EINVAL, "cfg and slot must be non-NULL");
   if (cfg->system == MPPI_SYS_QUADROTOR_MLP) return fail(MPPI_EINVAL, "the server runs the analytic systems");
   if (cfg->weighting != MPPI_WEIGHT_PATH) return fail(MPPI_EINVAL, "the server runs path-cost weighting only");
+  mppi_config c = *cfg;
   std::lock_guard<std::mutex> lk(s->mu);
   uint64_t bytes = 0;
-  rc = mppi_workspace_bytes(cfg, &bytes);
+  rc = mppi_workspace_bytes(&c, &bytes);
   if (rc) return rc;
   int free_slot = -1;
   for (int i = 0; i < (int)s->slots.size(); ++i)
@@ -590,7 +592,6 @@ extern "C" int mppi_server_admit(mppi_server *s, const mppi_config *cfg, int32_t
   if (s->used + bytes > s->cfg.hbm_budget_bytes)
     return fail(MPPI_EBUSY, "HBM budget: %llu + %llu > %llu bytes", (unsigned long long)s->used,
                 (unsigned long long)bytes, (unsigned long long)s->cfg.hbm_budget_bytes);
-  mppi_config c = *cfg;
   c.device = s->cfg.device;
   c.stream = s->batches[0].stream;
   c.workspace = nullptr;

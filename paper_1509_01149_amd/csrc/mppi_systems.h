@@ -449,6 +449,16 @@ struct QuadrotorSys {
     const float4 *obs;
     float crash, ground; // crash indicator cost (0: off) and ground height
     float dt_m_inv, dt_g, dt_Jinv[3];   // dt / m, dt g, dt / J_i (the folded Euler step)
+    float dt_rev;                       // dt / (2 pi): the folded step holds the attitude in revolutions
+    // The obstacle scale s, a power of two with s (r + margin)^2 <= 1/4 for every obstacle:
+    // the device obstacles hold s (2 c, (r + margin)^2 - |c|^2) and s ((r + margin)^2 - r^2),
+    // so the barrier argument comes out times s (exactly: s is a power of two) and lies in
+    // (-inf, 1/4]; wo_s = w_obs / s^2 restores the barrier's weight.
+    float obs_scale, wo_s;
+    // The goal term w_g |p - goal|^2 expanded as gq s|p|^2 + glin . p + gconst, with
+    // gq = w_g / s, glin = -2 w_g goal, gconst = w_g |goal|^2 (which joins the per-step
+    // control cost, so the cost chain starts from the likelihood-ratio terms).
+    float gq, glin[3], gconst;
     double dm_inv, dg, darm, dkap, dJ[3], dJinv[3];
   };
   template <typename F>
@@ -486,48 +496,71 @@ struct QuadrotorSys {
     xd[10] = fma(wx, hz, fma(-wz, hx, ty)) * Ji1;
     xd[11] = fma(wy, hx, fma(-wx, hy, tz)) * Ji2;
   }
-  // One FP32 Euler step x <- x + dt xdot(x, f) of the rollout, with dt folded into the
-  // constants (dt / m, dt g, dt / J_i) so the products by dt merge into the update FMAs.
-  // The attitude's sines and cosines take the revolution x / 2 pi straight to the hardware
-  // sin / cos, which reduce it themselves (|x| up to 1608 rad; for |x| < pi the argument
-  // is the one `rev` forms, bit for bit).  The crash indicator's rollout keeps xdot and a
-  // separate update (a crashed sample does not move).
+  // The rollout's FP32 Euler step x <- x + dt xdot(x, u) with its constants folded:
+  //  - dt enters the constants (dt / m, dt g, dt / J_i, dt / 2 pi), so the products by dt
+  //    merge into the update FMAs;
+  //  - the attitude is held in revolutions (init_state), which the hardware sin / cos take
+  //    directly and reduce themselves (|x| up to 256 revolutions);
+  //  - the thrusts enter the dynamics only through four linear combinations, the collective
+  //    thrust times dt / m and the three body torques; the rollout forms them for the nominal
+  //    controls once per step (fold_controls on u_i, staged in LDS) and adds the fold of the
+  //    perturbation as a fixed 4 x 4 map of the step's normals (fold_controls on each column
+  //    of the noise map A chol(Sigma)).
+  // The crash indicator's rollout keeps xdot and a separate update (a crashed sample does
+  // not move).
   static constexpr bool kFoldedEuler = true;
-  __device__ static void sincos_rev(float x, float &s, float &c) {
-    const float r = x * 0.159154943091895335769f;
-    s = __builtin_amdgcn_sinf(r);
-    c = __builtin_amdgcn_cosf(r);
+  __device__ static void init_state(const double *x0, int n, float *x) {
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+      const double v = r < n ? x0[r] : 0.0;
+      x[r] = (float)(r >= 6 && r < 9 ? v * 0.15915494309189533577 : v);
+    }
   }
-  __device__ static void euler(const Params &p, float *x, const float *f, float dt) {
-    float sr, cr, sp, cp, sy, cy;
-    sincos_rev(x[6], sr, cr);
-    sincos_rev(x[7], sp, cp);
-    sincos_rev(x[8], sy, cy);
+  // (dt / m sum u, arm (u_1 - u_3), arm (u_2 - u_0), kap (u_0 - u_1 + u_2 - u_3))
+  __device__ static float4 fold_controls(const Params &p, float u0, float u1, float u2, float u3) {
+    return make_float4(((u0 + u1) + (u2 + u3)) * p.dt_m_inv, p.arm * (u1 - u3), p.arm * (u2 - u0),
+                       p.kap * ((u0 - u1) + (u2 - u3)));
+  }
+  // nom: the fold of u_i; W[l]: the fold of column l of the noise map; e: the step's normals.
+  // kDiag: the noise map is diagonal, so the torques about x and y take two normals each
+  // (the other two coefficients are exact zeros).
+  template <bool kDiag>
+  __device__ static void euler_folded(const Params &p, float dt, float *x, float4 nom, const float4 *W, const float *e) {
+    float ad = nom.x, tx = nom.y, ty = nom.z, tz = nom.w;
+#pragma unroll
+    for (int l = 3; l >= 0; --l) {
+      ad = fmaf(W[l].x, e[l], ad);
+      if (!kDiag || l == 1 || l == 3) tx = fmaf(W[l].y, e[l], tx);
+      if (!kDiag || l == 0 || l == 2) ty = fmaf(W[l].z, e[l], ty);
+      tz = fmaf(W[l].w, e[l], tz);
+    }
+    const float sr = __builtin_amdgcn_sinf(x[6]), cr = __builtin_amdgcn_cosf(x[6]);
+    const float sp = __builtin_amdgcn_sinf(x[7]), cp = __builtin_amdgcn_cosf(x[7]);
+    const float sy = __builtin_amdgcn_sinf(x[8]), cy = __builtin_amdgcn_cosf(x[8]);
     const float icp = frcp(cp);
-    const float ad = (f[0] + f[1] + f[2] + f[3]) * p.dt_m_inv;
     const float wx = x[9], wy = x[10], wz = x[11];
-    const float tx = p.arm * (f[1] - f[3]);
-    const float ty = p.arm * (f[2] - f[0]);
-    const float tz = p.kap * (f[0] - f[1] + f[2] - f[3]);
-    const float hx = p.J[0] * wx, hy = p.J[1] * wy, hz = p.J[2] * wz;
+    const float spcr = sp * cr;
+    const float b = fmaf(cr, wz, sr * wy);           // sr wy + cr wz
     const float tp = sp * icp;
-    // position with the old velocity, velocity with the old attitude, attitude with the old
-    // body rates, body rates last
+    // position with the old velocity, velocity with the old attitude (third column of
+    // Rz(yaw) Ry(pitch) Rx(roll)), attitude with the old body rates, body rates last
     x[0] = fmaf(dt, x[3], x[0]);
     x[1] = fmaf(dt, x[4], x[1]);
     x[2] = fmaf(dt, x[5], x[2]);
-    x[3] = fmaf(ad, cy * sp * cr + sy * sr, x[3]);
-    x[4] = fmaf(ad, sy * sp * cr - cy * sr, x[4]);
+    x[3] = fmaf(ad, fmaf(cy, spcr, sy * sr), x[3]);
+    x[4] = fmaf(ad, fmaf(sy, spcr, -(cy * sr)), x[4]);
     x[5] = fmaf(ad, cp * cr, x[5]) - p.dt_g;
-    x[6] = fmaf(dt, wx + sr * tp * wy + cr * tp * wz, x[6]);
-    x[7] = fmaf(dt, cr * wy - sr * wz, x[7]);
-    x[8] = fmaf(dt, (sr * wy + cr * wz) * icp, x[8]);
-    x[9] = fmaf(fmaf(wz, hy, fmaf(-wy, hz, tx)), p.dt_Jinv[0], x[9]);
-    x[10] = fmaf(fmaf(wx, hz, fmaf(-wz, hx, ty)), p.dt_Jinv[1], x[10]);
-    x[11] = fmaf(fmaf(wy, hx, fmaf(-wx, hy, tz)), p.dt_Jinv[2], x[11]);
+    x[6] = fmaf(p.dt_rev, fmaf(tp, b, wx), x[6]);
+    x[7] = fmaf(p.dt_rev, fmaf(cr, wy, -(sr * wz)), x[7]);
+    x[8] = fmaf(p.dt_rev, b * icp, x[8]);
+    // tau - w x (J w) of a diagonal J: tau_x + (J_y - J_z) w_y w_z and its cyclic shifts
+    x[9] = fmaf(fmaf(p.J[1] - p.J[2], wy * wz, tx), p.dt_Jinv[0], x[9]);
+    x[10] = fmaf(fmaf(p.J[2] - p.J[0], wz * wx, ty), p.dt_Jinv[1], x[10]);
+    x[11] = fmaf(fmaf(p.J[0] - p.J[1], wx * wy, tz), p.dt_Jinv[2], x[11]);
   }
   // LDS: the obstacles' float4s, then (crash indicator on) their crash thresholds
   static constexpr int stage_floats(int n_obs, int) { return 5 * n_obs; }
+  __device__ static int staged_floats(const Params &p) { return stage_floats(p.n_obs, 0); }
   __device__ static void stage(const Params &p, float *lds, const double *, int *, int *) {
     for (int e = threadIdx.x; e < p.n_obs; e += kBlock) reinterpret_cast<float4 *>(lds)[e] = p.obs[e];
     if (p.crash > 0.f) {
@@ -535,18 +568,29 @@ struct QuadrotorSys {
       for (int e = threadIdx.x; e < p.n_obs; e += kBlock) lds[4 * p.n_obs + e] = th[e];
     }
   }
-  // (r + margin)^2 - |p - c|^2 of obstacle o at position x with xx = |x|^2
+  // s ((r + margin)^2 - |p - c|^2) of (scaled) obstacle o at position x, with xx = s |x|^2
   __device__ __forceinline__ static float barrier_arg(const float4 &o, const float *x, float xx) {
     return fmaf(x[0], o.x, fmaf(x[1], o.y, fmaf(x[2], o.z, o.w))) - xx;
   }
+  // s |x|^2 of a position
+  __device__ __forceinline__ static float scaled_sq(const Params &p, const float *x) {
+    return fmaf(x[0], x[0], fmaf(x[1], x[1], x[2] * x[2])) * p.obs_scale;
+  }
+  // The barrier's penalty max(0, arg) of a scaled argument.  The argument is at most 1/4
+  // in exact arithmetic, so clamping to [0, 1] gives the same value (a rollout far enough
+  // out for rounding to push it past 1 has diverged); the clamp folds into the subtract
+  // that forms the argument.
+  __device__ __forceinline__ static float penalty(float arg) { return fminf(fmaxf(arg, 0.f), 1.f); }
   // The obstacles a lane visits first (j, j + nj, ... for kRegObs of them) are held in
   // registers for the whole rollout, the rest are read from LDS each step: with one wave
   // per SIMD, an LDS round trip per obstacle per step would dominate the step.  Unused
-  // register slots hold a zero obstacle (argument -|p|^2 <= 0: no barrier, no hit).
+  // register slots hold a zero obstacle (argument -s|p|^2 <= 0: no barrier, no hit).  The
+  // goal term's coefficients sit in lane 0 of the group; the other lanes hold zeros.
   static constexpr int kRegObs = 8;
   struct Regs {
     float4 o[kRegObs];
     float th[kRegObs];
+    float gq, glin[3];
   };
   __device__ static void load_regs(const Params &p, const StageView &sv, int j, int nj, Regs &rg) {
     const float4 *ob = reinterpret_cast<const float4 *>(sv.lds);
@@ -558,61 +602,73 @@ struct QuadrotorSys {
       rg.o[t] = in ? ob[o] : make_float4(0.f, 0.f, 0.f, 0.f);
       rg.th[t] = in && p.crash > 0.f ? th[o] : 0.f;
     }
+    rg.gq = j == 0 ? p.gq : 0.f;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) rg.glin[d] = j == 0 ? p.glin[d] : 0.f;
   }
-  // Lane j of nj: the goal term (j = 0) plus the barriers of obstacles j, j + nj, ...; with
-  // kHit also the count of crash conditions among the same obstacles (and the ground for
-  // j = 0), from the same barrier arguments.
-  template <bool kHit>
+  // The per-step constant of the state cost (the goal term's w_g |goal|^2): the rollout
+  // adds it to the per-step control cost u_i'R u_i / 2, which lane 0 carries into `base`.
+  static constexpr bool kStepConst = true;
+  __device__ static float step_const(const Params &p) { return p.gconst; }
+  // Lane j of nj: base (this lane's likelihood-ratio share), the goal term (j = 0) and the
+  // barriers of obstacles j, j + nj, ...; with kHit also the count of crash conditions among
+  // the same obstacles (and the ground for j = 0), from the same barrier arguments (there
+  // the penalty keeps max(0, arg): the argument has a second use, so no clamp would fold).
+  // Whether lanes of nj-lane groups need the LDS pass (more obstacles than registers hold).
+  __device__ static bool lds_pass(const Params &p, int nj) { return p.n_obs > nj * kRegObs; }
+  template <bool kHit, bool kRegOnly>
   __device__ static float cost_part(const Params &p, const StageView &sv, const Regs &rg, const float *x, int j,
-                                    int nj, float &hit) {
-    const float dx = x[0] - p.goal[0], dy = x[1] - p.goal[1], dz = x[2] - p.goal[2];
-    const float c = j == 0 ? p.wg * (dx * dx + dy * dy + dz * dz) : 0.f;
-    const float xx = fmaf(x[0], x[0], fmaf(x[1], x[1], x[2] * x[2]));
+                                    int nj, float base, float &hit) {
+    const float xx = scaled_sq(p, x);
+    const float c = fmaf(rg.gq, xx, fmaf(x[0], rg.glin[0], fmaf(x[1], rg.glin[1], fmaf(x[2], rg.glin[2], base))));
     float barrier = 0.f, h = (kHit && j == 0 && x[2] < p.ground) ? 1.f : 0.f;
 #pragma unroll
     for (int t = 0; t < kRegObs; ++t) {
       const float arg = barrier_arg(rg.o[t], x, xx);
-      const float pen = fmaxf(0.f, arg);
+      const float pen = kHit ? fmaxf(arg, 0.f) : penalty(arg);
       barrier = fmaf(pen, pen, barrier);
       if (kHit) h += arg > rg.th[t] ? 1.f : 0.f;
     }
     const float4 *ob = reinterpret_cast<const float4 *>(sv.lds);
     const float *th = sv.lds + 4 * p.n_obs;
     // block-uniform: skipped when all fit in registers (the per-lane bounds are formed
-    // inside the branch only)
-    if (__builtin_expect(p.n_obs > nj * kRegObs, 0)) {
+    // inside the branch only); left out of the code with kRegOnly
+    if (!kRegOnly && __builtin_expect(lds_pass(p, nj), 0)) {
       for (int o = j + nj * kRegObs; o < p.n_obs; o += nj) {
         const float arg = barrier_arg(ob[o], x, xx);
-        const float pen = fmaxf(0.f, arg);
+        const float pen = kHit ? fmaxf(arg, 0.f) : penalty(arg);
         barrier = fmaf(pen, pen, barrier);
         if (kHit) h += arg > th[o] ? 1.f : 0.f;
       }
     }
     hit = h;
-    return c + p.wo * barrier;
+    return fmaf(p.wo_s, barrier, c);
   }
   static constexpr bool kCrash = true;
+  template <bool kRegOnly>
   __device__ static float q_part_crash(const Params &p, const StageView &sv, const Regs &rg, const float *x, int j,
-                                       int nj, float &hit) {
-    return cost_part<true>(p, sv, rg, x, j, nj, hit);
+                                       int nj, float base, float &hit) {
+    return cost_part<true, kRegOnly>(p, sv, rg, x, j, nj, base, hit);
   }
   static constexpr bool kSplitCost = true;
   static constexpr int kLPS = MPPI_ROLLOUT_LPS;
-  __device__ static float q_part(const Params &p, const StageView &sv, const Regs &rg, const float *x, int j, int nj) {
+  template <bool kRegOnly>
+  __device__ static float q_part(const Params &p, const StageView &sv, const Regs &rg, const float *x, int j, int nj,
+                                 float base) {
     float unused;
-    return cost_part<false>(p, sv, rg, x, j, nj, unused);
+    return cost_part<false, kRegOnly>(p, sv, rg, x, j, nj, base, unused);
   }
+  // The whole state cost in one lane (less step_const, which the control cost carries).
   __device__ static float q(const Params &p, const StageView &sv, const float *x) {
-    const float dx = x[0] - p.goal[0], dy = x[1] - p.goal[1], dz = x[2] - p.goal[2];
-    const float c = p.wg * (dx * dx + dy * dy + dz * dz);
-    const float xx = fmaf(x[0], x[0], fmaf(x[1], x[1], x[2] * x[2]));
+    const float xx = scaled_sq(p, x);
+    const float c = fmaf(p.gq, xx, fmaf(x[0], p.glin[0], fmaf(x[1], p.glin[1], x[2] * p.glin[2])));
     const float4 *ob = reinterpret_cast<const float4 *>(sv.lds);
     float barrier = 0.f;
     for (int j = 0; j < p.n_obs; ++j) {
-      const float pen = fmaxf(0.f, barrier_arg(ob[j], x, xx));
+      const float pen = penalty(barrier_arg(ob[j], x, xx));
       barrier = fmaf(pen, pen, barrier);
     }
-    return c + p.wo * barrier;
+    return fmaf(p.wo_s, barrier, c);
   }
   __device__ static float phi(const Params &, const float *) { return 0.f; }
 };

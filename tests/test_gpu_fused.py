@@ -1,6 +1,7 @@
-"""The two-kernel iteration (rollout blocks that also form their samples' weighted noise sums
-against their own minimum; a multi-block finalize that rescales and merges them) against the
-three-kernel iteration (rollout, update, finalize) on the same inputs, through the C ABI.
+"""The two-kernel iteration (rollout blocks that keep their normals in LDS and also form their
+samples' weighted noise sums against their own minimum; a multi-block finalize that rescales
+and merges them) against the three-kernel iteration (rollout, update, finalize) on the same
+inputs, through the C ABI: the step-split systems and the quadrotor's four-lane body.
 
 Both compute the update law of Section III-C from the same path costs and the same normals;
 the per-block factor exp(-(rho_b - rho)/lambda) is the sample-independent factor that
@@ -40,6 +41,11 @@ CASES = [
     W.cartpole(K=65536, T=16),                                         # 4 lanes, 1024 blocks
     W.cartpole_swingup(nu=100.0),
     W.linear_double_integrator(K=300, R=0.3),
+    W.quadrotor(),                                                     # 256 blocks, 150 KiB of normals each
+    W.quadrotor(K=1000, T=37),                                         # ragged K
+    W.quadrotor(K=2048, T=153),                                        # the longest horizon whose normals fit
+    W.quadrotor(K=2048, T=80).replace(sigma=0.2 * np.eye(4) + 0.05 * np.ones((4, 4))),   # full covariance
+    W.quadrotor(nu=np.array([1.0, 2.0, 4.0, 8.0]), lam=420.0, K=4096, T=60),              # per-dimension nu
 ]
 
 
@@ -84,7 +90,7 @@ def test_both_iterations_match_the_oracle(kernels):
     """First iteration at full size against the FP64 oracle, to the parity bars (the library
     picks the fused iteration for these by default; the three-kernel one is asked for)."""
     for wl in (W.bicycle().replace(seed=5), W.cartpole(nu=2.0).replace(seed=5),
-               W.cartpole_swingup(nu=100.0).replace(seed=5)):
+               W.cartpole_swingup(nu=100.0).replace(seed=5), W.quadrotor(K=2048).replace(seed=5)):
         with P.controller_for(wl, kernels=kernels) as c:
             fused = bool(c.info()["rollout_mode"] & P.binding.ROLLOUT_FUSED)
             assert fused == (kernels == P.KERNELS_FUSED)
@@ -96,7 +102,8 @@ def test_fused_closed_loop_with_the_plant():
     """The fused finalize with the plant step: a closed-loop run equals single steps bitwise,
     and stays with the three-kernel run to FP64 reassociation."""
     dev = torch.device("cuda:0")
-    for wl in (W.bicycle(K=2048, T=50), W.cartpole(nu=2.0), W.cartpole_swingup(nu=1000.0, K=1024, T=50)):
+    for wl in (W.bicycle(K=2048, T=50), W.cartpole(nu=2.0), W.cartpole_swingup(nu=1000.0, K=1024, T=50),
+               W.quadrotor(K=2048, T=100)):
         wl = wl.replace(seed=41)
         n = 7
         xs = {k: torch.tensor(wl.x0, dtype=torch.float64, device=dev) for k in ("run", "single", "three")}
