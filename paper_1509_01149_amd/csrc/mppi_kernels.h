@@ -170,12 +170,49 @@ struct has_step_const<Sys, std::void_t<decltype(Sys::kStepConst)>> : std::bool_c
 template <class Sys, int Mode>
 constexpr bool folded_step() { return has_folded_euler<Sys>::value && (Mode & kCrashOn) == 0; }
 
+// The likelihood-ratio control terms of one step (m = 4) from its four normals e:
+// du = A L e, then du'Mq du + (R u_i)'du + u_i'R u_i / 2 as sum_r du_r ((Mq du)_r + (R u_i)_r)
+// + C_i, with ru = R u_i and c = C_i.  The diagonal form keeps the diagonal products only
+// (the general chains add exact zeros to them: the same bits).
+template <int Mode>
+__device__ __forceinline__ float lr_terms4(const IterArgs &a, const float *e, float4 ru, float c) {
+  constexpr int M = 4;
+  const float rv[4] = {ru.x, ru.y, ru.z, ru.w};
+  float du[M];
+#pragma unroll
+  for (int r = 0; r < M; ++r) {
+    if constexpr ((Mode & kDiagLR) != 0) {
+      du[r] = fmaf(a.Ls[r * M + r], e[r], 0.f);
+    } else {
+      float t = 0.f;
+#pragma unroll
+      for (int l = 0; l <= r; ++l) t = fmaf(a.Ls[r * M + l], e[l], t);
+      du[r] = t;
+    }
+  }
+  float acc = c;
+#pragma unroll
+  for (int r = 0; r < M; ++r) {
+    float t = rv[r];
+    if constexpr ((Mode & kDiagLR) != 0) {
+      t = fmaf(a.Mq[r * M + r], du[r], t);
+    } else {
+#pragma unroll
+      for (int j = 0; j < M; ++j) t = fmaf(a.Mq[r * M + j], du[j], t);
+    }
+    acc = fmaf(du[r], t, acc);
+  }
+  return acc;
+}
+
 // One horizon step of one sample from the four normals `e` of its noise group.  With the
 // folded step, sU holds the fold of each step's nominal controls and W the fold of the
-// noise map's columns (else W is unused).
+// noise map's columns (else W is unused).  With the four-lane split cost (m = 4), lr_base is
+// this lane's share of the step's likelihood-ratio terms (all of them in the lane that drew
+// the step's group, zero in the others).
 template <class Sys, int LPS, int Mode>
 __device__ __forceinline__ void rollout_step(const IterArgs &a, const typename Sys::Params &p, const StageView &sv,
-                                             const typename Sys::Regs &rg, const float *mrow, const float *sU,
+                                             const typename Sys::Regs &rg, float lr_base, const float *sU,
                                              const float *sRU, const float *sC, int i, int s, int lane_j, int k,
                                              const float e[4], const float4 *W, float *x, double &S, bool &crashed) {
   if constexpr ((Mode & kRecordPrefix) != 0)
@@ -210,28 +247,12 @@ __device__ __forceinline__ void rollout_step(const IterArgs &a, const typename S
     for (int r = 0; r < N; ++r) x[r] += a.dt * xd[r];
   }
   // likelihood-ratio control terms du'Mq du + (R u_i)'du + u_i'R u_i / 2: with a split
-  // cost and one control per lane (m = 4), lane j takes row j (mrow = row j of Mq) and
-  // the terms join the state cost in the same quad sum
+  // cost (m = 4) the lane that drew the step's group formed them (lr_terms4) and they join
+  // the state cost in the same quad sum
   constexpr bool kSplitLR = LPS == 4 && Sys::kSplitCost && M == 4;
   float quad = 0.f, lin = 0.f, lr_in = 0.f;         // lr_in: this lane's share (split form)
   if constexpr (kSplitLR) {
-    // t = (Mq du)_j + (R u_i)_j, the chain started from the second term
-    float duj, t = sRU[i * M + lane_j];
-    if constexpr ((Mode & kDiagLR) != 0) {
-      // mrow[4], mrow[5]: this lane's diagonal entries of Mq and of the noise map
-      // this lane's normal, by a two-level select on the lane's bits (three v_cndmask)
-      const bool odd = (lane_j & 1) != 0;
-      const float elo = odd ? e[s * M + 1] : e[s * M], ehi = odd ? e[s * M + 3] : e[s * M + 2];
-      const float ej = (lane_j & 2) != 0 ? ehi : elo;
-      duj = fmaf(mrow[5], ej, 0.f);
-      t = fmaf(mrow[4], duj, t);
-    } else {
-      duj = lane_j == 0 ? du[0] : (lane_j == 1 ? du[1] : (lane_j == 2 ? du[2] : du[3]));
-#pragma unroll
-      for (int j = 0; j < M; ++j) t = fmaf(mrow[j], du[j], t);
-    }
-    const float c0 = sC[i];                          // every lane reads it; lane 0 adds it
-    lr_in = fmaf(duj, t, lane_j == 0 ? c0 : 0.f);
+    lr_in = lr_base;
   } else {
 #pragma unroll
     for (int r = 0; r < M; ++r) {
@@ -371,15 +392,6 @@ __device__ __forceinline__ void rollout_body(const IterArgs &a, const typename S
   const int lane_j = threadIdx.x % LPS;
   typename Sys::Regs rg;                            // per-lane register copy of system data
   Sys::load_regs(p, sv, lane_j, LPS, rg);
-  // row lane_j of Mq, then its diagonal entry and the noise map's
-  float mrow[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-  if constexpr (LPS == 4 && M == 4) {
-#pragma unroll
-    for (int l = 0; l < 4; ++l)
-      mrow[l] = lane_j == 0 ? a.Mq[l] : (lane_j == 1 ? a.Mq[4 + l] : (lane_j == 2 ? a.Mq[8 + l] : a.Mq[12 + l]));
-    mrow[4] = lane_j == 0 ? mrow[0] : (lane_j == 1 ? mrow[1] : (lane_j == 2 ? mrow[2] : mrow[3]));
-    mrow[5] = lane_j == 0 ? a.Ls[0] : (lane_j == 1 ? a.Ls[5] : (lane_j == 2 ? a.Ls[10] : a.Ls[15]));
-  }
   const int k = blk * (kBlock / LPS) + threadIdx.x / LPS;
   double S = 0.0;
   bool crashed = false;                             // set only in the kCrashOn variant
@@ -390,7 +402,7 @@ __device__ __forceinline__ void rollout_body(const IterArgs &a, const typename S
 #pragma unroll
       for (int s = 0; s < SPG; ++s) {
         const int i = g * SPG + s;
-        if (i < a.T) rollout_step<Sys, LPS, Mode>(a, p, sv, rg, mrow, sU, sRU, sC, i, s, 0, k, e, W, x, S, crashed);
+        if (i < a.T) rollout_step<Sys, LPS, Mode>(a, p, sv, rg, 0.f, sU, sRU, sC, i, s, 0, k, e, W, x, S, crashed);
       }
     }
   } else {
@@ -408,6 +420,13 @@ __device__ __forceinline__ void rollout_body(const IterArgs &a, const typename S
         if (kFull || g0 + lane_j < a.G)
           *reinterpret_cast<float4 *>(sE + ((threadIdx.x / LPS) * a.G + g0 + lane_j) * 4) =
               make_float4(mine[0], mine[1], mine[2], mine[3]);
+      // split cost (m = 4, one step per group): this lane's step's likelihood-ratio terms,
+      // once per chunk (a lane past the horizon forms those of the last step, never used)
+      float lr_mine = 0.f;
+      if constexpr (LPS == 4 && Sys::kSplitCost && M == 4) {
+        const int im = min(g0 + lane_j, a.T - 1);
+        lr_mine = lr_terms4<MD>(a, mine, reinterpret_cast<const float4 *>(sRU)[im], sC[im]);
+      }
 #define MPPI_QUAD_GROUP(J)                                                              \
       if (kFull || g0 + J < a.G) {                                                      \
         float e[4];                                                                     \
@@ -415,7 +434,8 @@ __device__ __forceinline__ void rollout_body(const IterArgs &a, const typename S
         _Pragma("unroll") for (int s = 0; s < SPG; ++s) {                               \
           const int i = (g0 + J) * SPG + s;                                             \
           if ((kFull && SPG == 1) || i < a.T)                                           \
-            rollout_step<Sys, LPS, MD>(a, p, sv, rg, mrow, sU, sRU, sC, i, s, lane_j, k, e, W, x, S, crashed); \
+            rollout_step<Sys, LPS, MD>(a, p, sv, rg, lane_j == J ? lr_mine : 0.f, sU, sRU, sC, i, s, lane_j, k, e, W, \
+                                       x, S, crashed);                                 \
         }                                                                               \
       }
       MPPI_QUAD_GROUP(0)
