@@ -143,8 +143,8 @@ int validate_config(const mppi_config *c) {
     return fail(MPPI_EINVAL, "unknown kernels value %d", c->kernels);
   if (c->kernels == MPPI_KERNELS_FUSED && !fused_available(c))
     return fail(MPPI_EINVAL, "the fused iteration needs path weighting, at most %d rollout blocks and a block's "
-                "normals within its LDS (%d bytes on the step-split systems, the rest of %d on the quadrotor, "
-                "whose crash indicator it does not run)", kMaxMergedParts, kMaxFusedNormalsBytes, kMaxBlockLdsBytes);
+                "normals within its LDS (%d bytes on the step-split systems, the rest of %d on the quadrotor)",
+                kMaxMergedParts, kMaxFusedNormalsBytes, kMaxBlockLdsBytes);
   if (c->weighting == MPPI_WEIGHT_COST_TO_GO && c->system == MPPI_SYS_QUADROTOR_MLP)
     return fail(MPPI_EINVAL, "cost-to-go weighting is not available with the learned dynamics");
   if (c->u_nominal0 && !finite_all(c->u_nominal0, c->T * mm)) return fail(MPPI_EINVAL, "u_nominal0 has non-finite entries");
@@ -231,8 +231,7 @@ static int64_t quad_rollout_lds_floats(const mppi_config *c, int n_obs, bool fus
 
 // The fused iteration under path weighting, with every rollout block's partials mergeable by
 // one finalize block: a step-split system whose rollout block's normals fit its LDS share, or
-// the quadrotor (without the crash indicator) whose block's normals fit the rest of the CU's
-// LDS.
+// the quadrotor whose block's normals fit the rest of the CU's LDS.
 bool fused_available(const mppi_config *c) {
   if (c->weighting != MPPI_WEIGHT_PATH) return false;
   const int64_t G = ((int64_t)c->T * c->n_ctrl + 3) / 4;
@@ -243,7 +242,6 @@ bool fused_available(const mppi_config *c) {
   }
   if (c->system != MPPI_SYS_QUADROTOR) return false;
   const auto *q = (const mppi_quadrotor_params *)c->params;
-  if (q->crash_cost > 0) return false;
   const int spb = kBlock / MPPI_ROLLOUT_LPS;
   const int64_t n_roll = ((int64_t)c->K + spb - 1) / spb;
   return n_roll <= kMaxMergedParts &&
@@ -506,6 +504,7 @@ static const void *rollout_fn_for_base(int mode, int lps) {
     case kFused | kDiagL: return rollout_fn<Sys, kFused | kDiagL>();
     case kRecordPrefix | kDiagL: return rollout_fn<Sys, kRecordPrefix | kDiagL>();
     case kCrashOn | kDiagL: return rollout_fn<Sys, kCrashOn | kDiagL>();
+    case kCrashOn | kFused | kDiagL: return rollout_fn<Sys, kCrashOn | kFused | kDiagL>();
     case kRecordPrefix | kCrashOn | kDiagL: return rollout_fn<Sys, kRecordPrefix | kCrashOn | kDiagL>();
     default: return nullptr;
   }

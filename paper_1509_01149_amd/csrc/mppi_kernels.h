@@ -139,6 +139,11 @@ __device__ __forceinline__ float quad_sum(float v) {
   v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, false));   // quad_perm(2,3,0,1)
   return v;
 }
+__device__ __forceinline__ float quad_max(float v) {
+  v = fmaxf(v, __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false)));
+  v = fmaxf(v, __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, false)));
+  return v;
+}
 
 // Rollout variants (compile-time, so the default path carries none of their code):
 // kRecordPrefix records each sample's cost before every step (cost-to-go weighting);
@@ -166,9 +171,10 @@ template <class Sys, class = void>
 struct has_step_const : std::false_type {};
 template <class Sys>
 struct has_step_const<Sys, std::void_t<decltype(Sys::kStepConst)>> : std::bool_constant<Sys::kStepConst> {};
-// The folded step runs in every variant but the crash indicator's.
+// The folded step runs in every variant of such a system (under the crash indicator only
+// while the sample has not crashed).
 template <class Sys, int Mode>
-constexpr bool folded_step() { return has_folded_euler<Sys>::value && (Mode & kCrashOn) == 0; }
+constexpr bool folded_step() { return has_folded_euler<Sys>::value; }
 
 // The likelihood-ratio control terms of one step (m = 4) from its four normals e:
 // du = A L e, then du'Mq du + (R u_i)'du + u_i'R u_i / 2 as sum_r du_r ((Mq du)_r + (R u_i)_r)
@@ -231,16 +237,18 @@ __device__ __forceinline__ void rollout_step(const IterArgs &a, const typename S
     du[j] = t;
     v[j] = sU[i * M + j] + t;
   }
-  if constexpr ((Mode & kCrashOn) != 0) {
+  if constexpr (folded_step<Sys, Mode>()) {
+    static_assert(M == 4, "the folded step maps four normals");
+    // a crashed rollout stays where it is (its quad agrees, so the branch is quad-uniform)
+    if ((Mode & kCrashOn) == 0 || !crashed)
+      Sys::template euler_folded<(Mode & kDiagLR) != 0>(p, a.dt, x, reinterpret_cast<const float4 *>(sU)[i], W,
+                                                         e + s * M);
+  } else if constexpr ((Mode & kCrashOn) != 0) {
     Sys::xdot(p, x, v, xd);
     if (!crashed) {                                 // a crashed rollout stays where it is
 #pragma unroll
       for (int r = 0; r < N; ++r) x[r] += a.dt * xd[r];
     }
-  } else if constexpr (folded_step<Sys, Mode>()) {
-    static_assert(M == 4, "the folded step maps four normals");
-    Sys::template euler_folded<(Mode & kDiagLR) != 0>(p, a.dt, x, reinterpret_cast<const float4 *>(sU)[i], W,
-                                                       e + s * M);
   } else {
     Sys::xdot(p, x, v, xd);
 #pragma unroll
@@ -273,7 +281,7 @@ __device__ __forceinline__ void rollout_step(const IterArgs &a, const typename S
     float hit;
     if constexpr (LPS == 4) {
       q = quad_sum(Sys::template q_part_crash<(Mode & kRegOnly) != 0>(p, sv, rg, x, lane_j, 4, lr_in, hit));
-      hit = quad_sum(hit);
+      hit = quad_max(hit);
     } else {
       q = Sys::template q_part_crash<false>(p, sv, rg, x, 0, 1, 0.f, hit);
     }

@@ -138,6 +138,7 @@ const void *roll_fn(int k) {
     case kFusedKind + 4: return (const void *)rollout_batched<BicycleSys, 4, kStepSplit | kFused>;
     case kFusedKind + 5: return (const void *)rollout_batched<QuadrotorSys, QuadrotorSys::kLPS, kFused>;
     case kFusedKind + 6: return (const void *)rollout_batched<SwingUpSys, 4, kStepSplit | kFused>;
+    case kFusedKind + 7: return (const void *)rollout_batched<QuadrotorSys, QuadrotorSys::kLPS, kCrashOn | kFused>;
     case kFusedKind + kWide + 0: return (const void *)rollout_batched<LinearSys<1>, 16, kStepSplit | kFused>;
     case kFusedKind + kWide + 1: return (const void *)rollout_batched<LinearSys<2>, 16, kStepSplit | kFused>;
     case kFusedKind + kWide + 2: return (const void *)rollout_batched<LinearSys<4>, 16, kStepSplit | kFused>;

@@ -506,8 +506,7 @@ struct QuadrotorSys {
   //    controls once per step (fold_controls on u_i, staged in LDS) and adds the fold of the
   //    perturbation as a fixed 4 x 4 map of the step's normals (fold_controls on each column
   //    of the noise map A chol(Sigma)).
-  // The crash indicator's rollout keeps xdot and a separate update (a crashed sample does
-  // not move).
+  // Under the crash indicator a crashed sample skips the step (it does not move).
   static constexpr bool kFoldedEuler = true;
   __device__ static void init_state(const double *x0, int n, float *x) {
 #pragma unroll
@@ -610,24 +609,27 @@ struct QuadrotorSys {
   // adds it to the per-step control cost u_i'R u_i / 2, which lane 0 carries into `base`.
   static constexpr bool kStepConst = true;
   __device__ static float step_const(const Params &p) { return p.gconst; }
-  // Lane j of nj: base (this lane's likelihood-ratio share), the goal term (j = 0) and the
-  // barriers of obstacles j, j + nj, ...; with kHit also the count of crash conditions among
-  // the same obstacles (and the ground for j = 0), from the same barrier arguments (there
-  // the penalty keeps max(0, arg): the argument has a second use, so no clamp would fold).
   // Whether lanes of nj-lane groups need the LDS pass (more obstacles than registers hold).
   __device__ static bool lds_pass(const Params &p, int nj) { return p.n_obs > nj * kRegObs; }
+  // Lane j of nj: base (this lane's likelihood-ratio share), the goal term (j = 0) and the
+  // barriers of obstacles j, j + nj, ...; with kHit also, in `hit`, the largest crash margin
+  // among the same obstacles (and the ground for j = 0): max of arg - (the obstacle's
+  // threshold) and ground - z, positive exactly when one crash condition holds (the sign of
+  // a rounded difference is the sign of the exact one), from the same barrier arguments
+  // (there the penalty keeps max(0, arg): the argument has a second use, so no clamp folds).
   template <bool kHit, bool kRegOnly>
   __device__ static float cost_part(const Params &p, const StageView &sv, const Regs &rg, const float *x, int j,
                                     int nj, float base, float &hit) {
     const float xx = scaled_sq(p, x);
     const float c = fmaf(rg.gq, xx, fmaf(x[0], rg.glin[0], fmaf(x[1], rg.glin[1], fmaf(x[2], rg.glin[2], base))));
-    float barrier = 0.f, h = (kHit && j == 0 && x[2] < p.ground) ? 1.f : 0.f;
+    float barrier = 0.f, h = 0.f;
+    if constexpr (kHit) h = j == 0 ? p.ground - x[2] : -__builtin_inff();
 #pragma unroll
     for (int t = 0; t < kRegObs; ++t) {
       const float arg = barrier_arg(rg.o[t], x, xx);
       const float pen = kHit ? fmaxf(arg, 0.f) : penalty(arg);
       barrier = fmaf(pen, pen, barrier);
-      if (kHit) h += arg > rg.th[t] ? 1.f : 0.f;
+      if constexpr (kHit) h = fmaxf(h, arg - rg.th[t]);
     }
     const float4 *ob = reinterpret_cast<const float4 *>(sv.lds);
     const float *th = sv.lds + 4 * p.n_obs;
@@ -638,7 +640,7 @@ struct QuadrotorSys {
         const float arg = barrier_arg(ob[o], x, xx);
         const float pen = kHit ? fmaxf(arg, 0.f) : penalty(arg);
         barrier = fmaf(pen, pen, barrier);
-        if (kHit) h += arg > th[o] ? 1.f : 0.f;
+        if constexpr (kHit) h = fmaxf(h, arg - th[o]);
       }
     }
     hit = h;

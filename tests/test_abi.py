@@ -120,14 +120,14 @@ def test_extension_fields_are_validated():
         c, keep = _cfg(wl, **over)
         assert _ws(c)[0] == B.EINVAL, over
     # the fused iteration under path weighting: the step-split systems, and the quadrotor
-    # without the crash indicator while a rollout block's normals fit the CU's LDS
+    # (with or without the crash indicator) while a rollout block's normals fit the CU's LDS
     # (T = 153 with 32 obstacles is the longest horizon that does)
     for w, kernels, rc in ((wl, B.KERNELS_FUSED, B.OK), (wl, B.KERNELS_THREE, B.OK),
                            (W.quadrotor(), B.KERNELS_FUSED, B.OK), (W.quadrotor(), B.KERNELS_THREE, B.OK),
                            (W.quadrotor(T=153), B.KERNELS_FUSED, B.OK),
                            (W.quadrotor(T=154), B.KERNELS_FUSED, B.EINVAL),
                            (W.quadrotor(T=154), B.KERNELS_THREE, B.OK),
-                           (W.quadrotor(crash=True), B.KERNELS_FUSED, B.EINVAL),
+                           (W.quadrotor(crash=True), B.KERNELS_FUSED, B.OK),
                            (W.cartpole(), B.KERNELS_FUSED, B.OK)):
         c, keep = _cfg(w, kernels=kernels)
         assert _ws(c)[0] == rc, (w.name, w.T, kernels)
