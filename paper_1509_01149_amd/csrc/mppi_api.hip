@@ -248,6 +248,17 @@ bool fused_available(const mppi_config *c) {
          4 * quad_rollout_lds_floats(c, q->n_obstacles, true) + 64 <= kMaxBlockLdsBytes;
 }
 
+// Whether MPPI_KERNELS_AUTO takes the fused iteration where it is available: always on the
+// step-split systems; on the quadrotor while its rollout blocks number at most the MI355X's
+// 256 CUs (K <= 16384).  Its blocks' normals fill a CU's LDS, one block per CU: past that
+// count the three-kernel rollout, several blocks per CU, measured faster (K = 65536:
+// 0.177 against 0.185 ms per control step; even at K = 32768; 5 % the other way at 16384).
+static bool auto_fused(const mppi_config *c) {
+  if (rollout_split(c)) return true;
+  const int spb = kBlock / MPPI_ROLLOUT_LPS;
+  return ((int64_t)c->K + spb - 1) / spb <= kQuadFusedAutoBlocks;
+}
+
 void compute_layout(const mppi_config *c, Layout *L) {
   const int K = c->K, T = c->T, m = c->n_ctrl;
   L->TM = T * m;
@@ -264,7 +275,7 @@ void compute_layout(const mppi_config *c, Layout *L) {
   else if (ctg_w || ((K + 255) / 256) * gblk <= 1200) L->upd_chunk = 256;
   else L->upd_chunk = 512;
   L->n_kc = (K + L->upd_chunk - 1) / L->upd_chunk;
-  L->fused = c->kernels != MPPI_KERNELS_THREE && fused_available(c);
+  L->fused = fused_available(c) && (c->kernels == MPPI_KERNELS_FUSED || (c->kernels == MPPI_KERNELS_AUTO && auto_fused(c)));
   // the multi-block finalize with the fused rollout (its P rollout partials are too many for
   // one block); the update's few chunk partials merge faster in one block
   L->multi = L->fused;

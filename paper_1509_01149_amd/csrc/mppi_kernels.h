@@ -78,6 +78,7 @@ constexpr int kMaxMergedParts = 1024;
 constexpr int kFinOut = 4;
 constexpr int kMaxFusedNormalsBytes = 32 * 1024;
 constexpr int kMaxBlockLdsBytes = 160 * 1024;
+constexpr int kQuadFusedAutoBlocks = 256;           // the MI355X's CUs
 
 struct FinalizeArgs {
   double *U64;             // [T*m] FP64 master

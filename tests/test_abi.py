@@ -71,8 +71,10 @@ def test_valid_configs_size_their_workspace(make):
     c, keep = _cfg(wl)
     rc, n = _ws(c)
     assert rc == B.OK and n >= wl.K * 8 + wl.T * wl.m * 12
-    c2, keep2 = _cfg(wl, K=wl.K * 2)
-    assert _ws(c2)[1] > n
+    # more samples, more state (one kernel choice: AUTO may switch it with K)
+    c, keep = _cfg(wl, kernels=B.KERNELS_THREE)
+    c2, keep2 = _cfg(wl, K=wl.K * 2, kernels=B.KERNELS_THREE)
+    assert _ws(c2)[1] > _ws(c)[1]
 
 
 @pytest.mark.parametrize("field,value", [
@@ -168,3 +170,17 @@ def test_null_handles_are_rejected():
     u = np.zeros(4)
     assert lib.mppi_step(None, B._ptr(u), 1, B._ptr(u)) == B.EINVAL
     assert lib.mppi_destroy(None) == B.OK
+
+
+def test_auto_kernels_on_the_quadrotor_follow_the_block_count():
+    """AUTO takes the fused quadrotor iteration while its rollout blocks (64 samples each)
+    fit one per CU (256), the three-kernel one past that; the workspace shows which."""
+    for K, fused in ((16384, True), (16385, False)):
+        sizes = {}
+        for kern in (B.KERNELS_AUTO, B.KERNELS_FUSED, B.KERNELS_THREE):
+            c, keep = _cfg(W.quadrotor(K=K), kernels=kern)
+            rc, n = _ws(c)
+            assert rc == B.OK
+            sizes[kern] = n
+        assert sizes[B.KERNELS_FUSED] != sizes[B.KERNELS_THREE]
+        assert sizes[B.KERNELS_AUTO] == sizes[B.KERNELS_FUSED if fused else B.KERNELS_THREE], (K, sizes)
