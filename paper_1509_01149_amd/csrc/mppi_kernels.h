@@ -140,6 +140,22 @@ __device__ __forceinline__ float quad_sum(float v) {
   v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, false));   // quad_perm(2,3,0,1)
   return v;
 }
+// Sum over a sample's LPS lanes; lane 0 of the group holds the fixed-order total.
+template <int LPS>
+__device__ __forceinline__ double group_sum(double v) {
+  v += dpp_f64<0xB1>(v);                            // quad_perm(1,0,3,2)
+  v += dpp_f64<0x4E>(v);                            // quad_perm(2,3,0,1)
+  if constexpr (LPS >= 16) {
+    v += dpp_f64<0x124>(v);                         // row_ror:4
+    v += dpp_f64<0x128>(v);                         // row_ror:8
+  }
+  if constexpr (LPS == 32) {                        // lane 0 adds lane 16's row total
+    const int lo = __builtin_amdgcn_ds_swizzle(__double2loint(v), (16 << 10) | 0x1F);   // lane ^ 16
+    const int hi = __builtin_amdgcn_ds_swizzle(__double2hiint(v), (16 << 10) | 0x1F);
+    v += __hiloint2double(hi, lo);
+  }
+  return v;
+}
 __device__ __forceinline__ float quad_max(float v) {
   v = fmaxf(v, __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false)));
   v = fmaxf(v, __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, false)));
@@ -212,16 +228,23 @@ __device__ __forceinline__ float lr_terms4(const IterArgs &a, const float *e, fl
   return acc;
 }
 
+// Whether the four-lane body sums a sample's path cost per lane (each lane its share of every
+// step, in FP64; the lanes' sums added in a fixed tree at the end) rather than per step across
+// the quad: wherever no step's running total is recorded.
+template <class Sys, int LPS, int Mode>
+constexpr bool lane_sums() { return LPS == 4 && Sys::kSplitCost && (Mode & kRecordPrefix) == 0; }
+
 // One horizon step of one sample from the four normals `e` of its noise group.  With the
-// folded step, sU holds the fold of each step's nominal controls and W the fold of the
-// noise map's columns (else W is unused).  With the four-lane split cost (m = 4), lr_base is
-// this lane's share of the step's likelihood-ratio terms (all of them in the lane that drew
-// the step's group, zero in the others).
+// folded step, sU holds the fold of each step's nominal controls and nf is the fold of the
+// step's perturbation (e is then used only by the one-lane likelihood-ratio terms).  With
+// the four-lane split cost (m = 4), lr_base is this lane's share of the step's
+// likelihood-ratio terms (all of them in the lane that drew the step's group, zero in the
+// others).  With lane_sums, S is this lane's share of the path cost.
 template <class Sys, int LPS, int Mode>
 __device__ __forceinline__ void rollout_step(const IterArgs &a, const typename Sys::Params &p, const StageView &sv,
                                              const typename Sys::Regs &rg, float lr_base, const float *sU,
                                              const float *sRU, const float *sC, int i, int s, int lane_j, int k,
-                                             const float e[4], const float4 *W, float *x, double &S, bool &crashed) {
+                                             const float e[4], float4 nf, float *x, double &S, bool &crashed) {
   if constexpr ((Mode & kRecordPrefix) != 0)
     if (lane_j == 0 && k < a.K) a.pre[(size_t)i * a.K + k] = S;        // cost of steps before i
   constexpr int N = Sys::N, M = Sys::M;
@@ -241,9 +264,7 @@ __device__ __forceinline__ void rollout_step(const IterArgs &a, const typename S
   if constexpr (folded_step<Sys, Mode>()) {
     static_assert(M == 4, "the folded step maps four normals");
     // a crashed rollout stays where it is (its quad agrees, so the branch is quad-uniform)
-    if ((Mode & kCrashOn) == 0 || !crashed)
-      Sys::template euler_folded<(Mode & kDiagLR) != 0>(p, a.dt, x, reinterpret_cast<const float4 *>(sU)[i], W,
-                                                         e + s * M);
+    if ((Mode & kCrashOn) == 0 || !crashed) Sys::euler_folded(p, a.dt, x, reinterpret_cast<const float4 *>(sU)[i], nf);
   } else if constexpr ((Mode & kCrashOn) != 0) {
     Sys::xdot(p, x, v, xd);
     if (!crashed) {                                 // a crashed rollout stays where it is
@@ -276,20 +297,23 @@ __device__ __forceinline__ void rollout_step(const IterArgs &a, const typename S
       lin += sRU[i * M + r] * du[r];
     }
   }
+  constexpr bool kLane = lane_sums<Sys, LPS, Mode>();
   float q;
   if constexpr ((Mode & kCrashOn) != 0) {          // crash indicator: sticky, crash cost per step
     static_assert(Sys::kCrash, "system has no crash indicator");
     float hit;
     if constexpr (LPS == 4) {
-      q = quad_sum(Sys::template q_part_crash<(Mode & kRegOnly) != 0>(p, sv, rg, x, lane_j, 4, lr_in, hit));
+      q = Sys::template q_part_crash<(Mode & kRegOnly) != 0>(p, sv, rg, x, lane_j, 4, lr_in, hit);
+      if constexpr (!kLane) q = quad_sum(q);
       hit = quad_max(hit);
     } else {
       q = Sys::template q_part_crash<false>(p, sv, rg, x, 0, 1, 0.f, hit);
     }
     crashed = crashed || hit > 0.f;
-    if (crashed) q += p.crash;
+    if (crashed && (!kLane || lane_j == 0)) q += p.crash;
   } else if constexpr (LPS == 4 && Sys::kSplitCost) {
-    q = quad_sum(Sys::template q_part<(Mode & kRegOnly) != 0>(p, sv, rg, x, lane_j, 4, lr_in));
+    q = Sys::template q_part<(Mode & kRegOnly) != 0>(p, sv, rg, x, lane_j, 4, lr_in);
+    if constexpr (!kLane) q = quad_sum(q);
   } else {
     q = Sys::q(p, sv, x);
   }
@@ -411,7 +435,11 @@ __device__ __forceinline__ void rollout_body(const IterArgs &a, const typename S
 #pragma unroll
       for (int s = 0; s < SPG; ++s) {
         const int i = g * SPG + s;
-        if (i < a.T) rollout_step<Sys, LPS, Mode>(a, p, sv, rg, 0.f, sU, sRU, sC, i, s, 0, k, e, W, x, S, crashed);
+        if (i < a.T) {
+          float4 nf = make_float4(0.f, 0.f, 0.f, 0.f);
+          if constexpr (kFold) nf = Sys::template fold_noise<(Mode & kDiagLR) != 0>(W, e + s * M);
+          rollout_step<Sys, LPS, Mode>(a, p, sv, rg, 0.f, sU, sRU, sC, i, s, 0, k, e, nf, x, S, crashed);
+        }
       }
     }
   } else {
@@ -436,14 +464,24 @@ __device__ __forceinline__ void rollout_body(const IterArgs &a, const typename S
         const int im = min(g0 + lane_j, a.T - 1);
         lr_mine = lr_terms4<MD>(a, mine, reinterpret_cast<const float4 *>(sRU)[im], sC[im]);
       }
+      // folded step (m = 4, one step per group): the lane that drew a group folds its
+      // perturbation once and the quad broadcasts the fold instead of the normals
+      float4 nf_mine = make_float4(0.f, 0.f, 0.f, 0.f);
+      if constexpr (kFold) nf_mine = Sys::template fold_noise<(MD & kDiagLR) != 0>(W, mine);
 #define MPPI_QUAD_GROUP(J)                                                              \
       if (kFull || g0 + J < a.G) {                                                      \
         float e[4];                                                                     \
-        for (int c = 0; c < 4; ++c) e[c] = quad_bcast<J>(mine[c]);                      \
+        float4 nf = make_float4(0.f, 0.f, 0.f, 0.f);                                    \
+        if constexpr (kFold) {                                                          \
+          nf = make_float4(quad_bcast<J>(nf_mine.x), quad_bcast<J>(nf_mine.y), quad_bcast<J>(nf_mine.z), \
+                           quad_bcast<J>(nf_mine.w));                                   \
+        } else {                                                                        \
+          for (int c = 0; c < 4; ++c) e[c] = quad_bcast<J>(mine[c]);                    \
+        }                                                                               \
         _Pragma("unroll") for (int s = 0; s < SPG; ++s) {                               \
           const int i = (g0 + J) * SPG + s;                                             \
           if ((kFull && SPG == 1) || i < a.T)                                           \
-            rollout_step<Sys, LPS, MD>(a, p, sv, rg, lane_j == J ? lr_mine : 0.f, sU, sRU, sC, i, s, lane_j, k, e, W, \
+            rollout_step<Sys, LPS, MD>(a, p, sv, rg, lane_j == J ? lr_mine : 0.f, sU, sRU, sC, i, s, lane_j, k, e, nf, \
                                        x, S, crashed);                                 \
         }                                                                               \
       }
@@ -461,6 +499,7 @@ __device__ __forceinline__ void rollout_body(const IterArgs &a, const typename S
     if (Sys::lds_pass(p, LPS)) run(std::integral_constant<int, Mode>{});
     else run(std::integral_constant<int, Mode | kRegOnly>{});
   }
+  if constexpr (lane_sums<Sys, LPS, Mode>()) S = group_sum<LPS>(S);   // the lanes' shares, fixed order
   S += (double)Sys::phi(p, x);
   if (!isfinite(S)) S = __builtin_inf();
   const bool valid = k < a.K && lane_j == 0;
@@ -485,22 +524,6 @@ __device__ __forceinline__ void rollout_body(const IterArgs &a, const typename S
 // by the lane owning the step, from an FP64 scan of the lanes' step costs across the
 // group; the path cost is the same tree sum in both variants, so the two weightings see
 // bitwise the same S.
-// Sum over a sample's LPS lanes; lane 0 of the group holds the fixed-order total.
-template <int LPS>
-__device__ __forceinline__ double group_sum(double v) {
-  v += dpp_f64<0xB1>(v);                            // quad_perm(1,0,3,2)
-  v += dpp_f64<0x4E>(v);                            // quad_perm(2,3,0,1)
-  if constexpr (LPS >= 16) {
-    v += dpp_f64<0x124>(v);                         // row_ror:4
-    v += dpp_f64<0x128>(v);                         // row_ror:8
-  }
-  if constexpr (LPS == 32) {                        // lane 0 adds lane 16's row total
-    const int lo = __builtin_amdgcn_ds_swizzle(__double2loint(v), (16 << 10) | 0x1F);   // lane ^ 16
-    const int hi = __builtin_amdgcn_ds_swizzle(__double2hiint(v), (16 << 10) | 0x1F);
-    v += __hiloint2double(hi, lo);
-  }
-  return v;
-}
 
 template <class Sys, int LPS, int Mode>
 __device__ __forceinline__ void rollout_body_split(const IterArgs &a, const typename Sys::Params &p,

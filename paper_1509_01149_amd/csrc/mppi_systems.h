@@ -520,12 +520,12 @@ struct QuadrotorSys {
     return make_float4(((u0 + u1) + (u2 + u3)) * p.dt_m_inv, p.arm * (u1 - u3), p.arm * (u2 - u0),
                        p.kap * ((u0 - u1) + (u2 - u3)));
   }
-  // nom: the fold of u_i; W[l]: the fold of column l of the noise map; e: the step's normals.
-  // kDiag: the noise map is diagonal, so the torques about x and y take two normals each
-  // (the other two coefficients are exact zeros).
+  // The fold of a step's perturbation from its normals e, W[l] the fold of column l of the
+  // noise map.  kDiag: the noise map is diagonal, so the torques about x and y take two
+  // normals each (the other two coefficients are exact zeros).
   template <bool kDiag>
-  __device__ static void euler_folded(const Params &p, float dt, float *x, float4 nom, const float4 *W, const float *e) {
-    float ad = nom.x, tx = nom.y, ty = nom.z, tz = nom.w;
+  __device__ static float4 fold_noise(const float4 *W, const float *e) {
+    float ad = 0.f, tx = 0.f, ty = 0.f, tz = 0.f;
 #pragma unroll
     for (int l = 3; l >= 0; --l) {
       ad = fmaf(W[l].x, e[l], ad);
@@ -533,6 +533,11 @@ struct QuadrotorSys {
       if (!kDiag || l == 0 || l == 2) ty = fmaf(W[l].z, e[l], ty);
       tz = fmaf(W[l].w, e[l], tz);
     }
+    return make_float4(ad, tx, ty, tz);
+  }
+  // nom: the fold of u_i; nf: the fold of the step's perturbation.
+  __device__ static void euler_folded(const Params &p, float dt, float *x, float4 nom, float4 nf) {
+    const float ad = nom.x + nf.x, tx = nom.y + nf.y, ty = nom.z + nf.z, tz = nom.w + nf.w;
     const float sr = __builtin_amdgcn_sinf(x[6]), cr = __builtin_amdgcn_cosf(x[6]);
     const float sp = __builtin_amdgcn_sinf(x[7]), cp = __builtin_amdgcn_cosf(x[7]);
     const float sy = __builtin_amdgcn_sinf(x[8]), cy = __builtin_amdgcn_cosf(x[8]);
