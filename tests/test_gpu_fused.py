@@ -47,6 +47,8 @@ CASES = [
     W.quadrotor(K=2048, T=80).replace(sigma=0.2 * np.eye(4) + 0.05 * np.ones((4, 4))),   # full covariance
     W.quadrotor(nu=np.array([1.0, 2.0, 4.0, 8.0]), lam=420.0, K=4096, T=60),              # per-dimension nu
     W.quadrotor(K=4096, T=150, crash=True),                            # the crash indicator
+    W.quadrotor(K=2048, T=100, obstacles=W.obstacle_field(n=100)),     # 68 obstacles read from LDS
+    W.quadrotor(K=2048, T=100, obstacles=W.obstacle_field(n=100), crash=True),
 ]
 
 

@@ -84,6 +84,14 @@ CASES = {
     "bicycle_4lanes": lambda: W.bicycle(K=9000, T=37),
     "bicycle_16lanes_k8192": lambda: W.bicycle(K=8192, T=100),
     "bicycle_32lanes_ragged": lambda: W.bicycle(K=4000, T=37),
+    # obstacle counts around the 32 the quad holds in registers: 100 (the rest read from LDS
+    # each step), 5 (most register slots empty), none; and spheres large enough that the
+    # obstacle scale (a power of two with s (r + margin)^2 <= 1/4) is 2^-8
+    "quadrotor_100_obstacles": lambda: W.quadrotor(K=2048, T=100, obstacles=W.obstacle_field(n=100)),
+    "quadrotor_5_obstacles": lambda: W.quadrotor(K=2048, T=100, obstacles=W.obstacle_field(n=5)),
+    "quadrotor_no_obstacles": lambda: W.quadrotor(K=2048, T=60, obstacles=np.zeros((0, 4))),
+    "quadrotor_large_obstacles": lambda: W.quadrotor(K=2048, T=100, obstacles=np.array(
+        [[4.0, 3.5, 1.5, 2.5], [4.0, -4.0, 1.0, 3.0], [9.0, 8.0, 2.0, 6.5]])),
 }
 
 
