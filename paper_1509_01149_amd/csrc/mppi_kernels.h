@@ -470,7 +470,7 @@ __device__ __forceinline__ void rollout_body(const IterArgs &a, const typename S
       if constexpr (kFold) nf_mine = Sys::template fold_noise<(MD & kDiagLR) != 0>(W, mine);
 #define MPPI_QUAD_GROUP(J)                                                              \
       if (kFull || g0 + J < a.G) {                                                      \
-        float e[4];                                                                     \
+        float e[4] = {0.f, 0.f, 0.f, 0.f};          /* the normals, if not folded */    \
         float4 nf = make_float4(0.f, 0.f, 0.f, 0.f);                                    \
         if constexpr (kFold) {                                                          \
           nf = make_float4(quad_bcast<J>(nf_mine.x), quad_bcast<J>(nf_mine.y), quad_bcast<J>(nf_mine.z), \
