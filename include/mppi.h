@@ -165,10 +165,11 @@ typedef struct {
 
 /* Kernels per iteration.  THREE: rollout, update (regenerates the noise to form the weighted
  * sums), finalize.  FUSED: the rollout keeps its block's normals in LDS and also forms the
- * weighted sums of its samples, and the finalize merges them (MPPI_ROLLOUT_FUSED; path
- * weighting only, with at most 1024 rollout blocks and a block's normals within its LDS:
- * 32 KiB on the step-split systems; on the quadrotor the rest of a 160 KiB CU, 64 samples x
- * T*4 floats, so T <= 153 with 32 obstacles; else MPPI_EINVAL).  AUTO takes FUSED wherever it is
+ * weighted sums of its samples, and the finalize merges them (MPPI_ROLLOUT_FUSED; with at
+ * most 1024 rollout blocks and a block's normals within its LDS: 32 KiB on the step-split
+ * systems, which under cost-to-go weighting also keep their samples' running costs, at most
+ * 32 KiB; on the quadrotor, under path weighting only, the rest of a 160 KiB CU, 64 samples
+ * x T*4 floats, so T <= 153 with 32 obstacles; else MPPI_EINVAL).  AUTO takes FUSED wherever it is
  * available, on the quadrotor only while its rollout blocks (64 samples each) number at
  * most 256, one per CU of an MI355X (K <= 16384).  Both compute the update law of
  * Section III-C; their results differ by FP64 summation order only. */

@@ -142,8 +142,9 @@ int validate_config(const mppi_config *c) {
   if (c->kernels != MPPI_KERNELS_AUTO && c->kernels != MPPI_KERNELS_FUSED && c->kernels != MPPI_KERNELS_THREE)
     return fail(MPPI_EINVAL, "unknown kernels value %d", c->kernels);
   if (c->kernels == MPPI_KERNELS_FUSED && !fused_available(c))
-    return fail(MPPI_EINVAL, "the fused iteration needs path weighting, at most %d rollout blocks and a block's "
-                "normals within its LDS (%d bytes on the step-split systems, the rest of %d on the quadrotor)",
+    return fail(MPPI_EINVAL, "the fused iteration needs at most %d rollout blocks and a block's normals within "
+                "its LDS (%d bytes on the step-split systems, which under cost-to-go weighting also keep 32 KiB "
+                "of running costs; the rest of %d on the quadrotor, under path weighting only)",
                 kMaxMergedParts, kMaxFusedNormalsBytes, kMaxBlockLdsBytes);
   if (c->weighting == MPPI_WEIGHT_COST_TO_GO && c->system == MPPI_SYS_QUADROTOR_MLP)
     return fail(MPPI_EINVAL, "cost-to-go weighting is not available with the learned dynamics");
@@ -229,18 +230,26 @@ static int64_t quad_rollout_lds_floats(const mppi_config *c, int n_obs, bool fus
   return fl;
 }
 
-// The fused iteration under path weighting, with every rollout block's partials mergeable by
-// one finalize block: a step-split system whose rollout block's normals fit its LDS share, or
-// the quadrotor whose block's normals fit the rest of the CU's LDS.
+// Whether a step-split rollout block keeps its samples' running costs in LDS under cost-to-go
+// weighting (at most 32 KiB of them), forming its own per-step minima.
+static bool ctg_fold_fits(const mppi_config *c) {
+  if (!rollout_split(c)) return false;
+  return (int64_t)(kBlock / rollout_lps(c)) * (c->T + 1) * 8 <= 32768;
+}
+
+// The fused iteration, with every rollout block's partials mergeable by one finalize block: a
+// step-split system whose rollout block's normals fit its LDS share (under cost-to-go
+// weighting also its running costs), or the quadrotor under path weighting whose block's
+// normals fit the rest of the CU's LDS.
 bool fused_available(const mppi_config *c) {
-  if (c->weighting != MPPI_WEIGHT_PATH) return false;
   const int64_t G = ((int64_t)c->T * c->n_ctrl + 3) / 4;
   if (rollout_split(c)) {
+    if (c->weighting != MPPI_WEIGHT_PATH && !ctg_fold_fits(c)) return false;
     const int spb = kBlock / rollout_lps(c);
     const int64_t n_roll = ((int64_t)c->K + spb - 1) / spb;
     return n_roll <= kMaxMergedParts && spb * G * 16 <= kMaxFusedNormalsBytes;
   }
-  if (c->system != MPPI_SYS_QUADROTOR) return false;
+  if (c->system != MPPI_SYS_QUADROTOR || c->weighting != MPPI_WEIGHT_PATH) return false;
   const auto *q = (const mppi_quadrotor_params *)c->params;
   const int spb = kBlock / MPPI_ROLLOUT_LPS;
   const int64_t n_roll = ((int64_t)c->K + spb - 1) / spb;
@@ -297,11 +306,10 @@ void compute_layout(const mppi_config *c, Layout *L) {
   L->off_basis = L->multi ? take((uint64_t)5 * 16 * 8) : 0;
   // cost-to-go on the step-split body: the rollout blocks form each step's minimum over their
   // samples from running costs kept in LDS (at most 32 KiB of them), the update reduces those
-  const int lps_c = rollout_split(c) ? rollout_lps(c) : 0;
-  L->ctg_fold = ctg_w && lps_c > 0 && (uint64_t)(kBlock / lps_c) * (T + 1) * 8 <= 32768;
+  L->ctg_fold = ctg_w && ctg_fold_fits(c);
   L->off_blk_tail = L->ctg_fold ? take((uint64_t)L->n_roll_blocks * T * 8) : 0;
   L->off_dbg = take((uint64_t)(2 + L->TM) * 8);
-  L->off_pre = ctg ? take((uint64_t)T * K * 8) : 0;
+  L->off_pre = ctg && !L->fused ? take((uint64_t)T * K * 8) : 0;   // read by the update only
   L->off_rho_step = ctg ? take((uint64_t)T * 8) : 0;
   L->off_rho = take(sizeof(double));
   uint64_t sys_bytes = 0;
@@ -460,6 +468,8 @@ static size_t rollout_lds_bytes(const mppi_ctx *c) {
   // the step-split body stages nothing beyond the controls (fused: and the block's normals
   // and weights); the quadrotor its obstacles (fused: then the block's normals and weights)
   if constexpr (!Sys::kStepSplit) return (size_t)quad_rollout_lds_floats(&c->cfg, c->quad.n_obs, c->L.fused) * 4;
+  else if (c->L.fused && c->L.ctg_fold)           // normals, running costs, path costs, step minima
+    fl += (size_t)(kBlock / rollout_lps(&c->cfg)) * (c->L.G * 4 + (c->cfg.T + 1) * 2) + (size_t)c->cfg.T * 2;
   else if (c->L.fused) fl += (size_t)(kBlock / rollout_lps(&c->cfg)) * (c->L.G * 4 + 2);
   else if (c->L.ctg_fold) fl += (size_t)(kBlock / rollout_lps(&c->cfg)) * (c->cfg.T + 1) * 2;
   return fl * 4;
@@ -510,6 +520,8 @@ static const void *rollout_fn_for_base(int mode, int lps) {
   if (mode == (kStepSplit | kDiagL)) return rollout_split_fn<Sys, kStepSplit | kDiagL>(lps);
   if (mode == (kStepSplit | kFused | kDiagL)) return rollout_split_fn<Sys, kStepSplit | kFused | kDiagL>(lps);
   if (mode == (kStepSplit | kRecordPrefix | kDiagL)) return rollout_split_fn<Sys, kStepSplit | kRecordPrefix | kDiagL>(lps);
+  if (mode == (kStepSplit | kFused | kRecordPrefix | kDiagL))
+    return rollout_split_fn<Sys, kStepSplit | kFused | kRecordPrefix | kDiagL>(lps);
   switch (mode) {
     case kDiagL: return rollout_fn<Sys, kDiagL>();
     case kFused | kDiagL: return rollout_fn<Sys, kFused | kDiagL>();
@@ -584,7 +596,7 @@ static IterArgs make_iter_args(mppi_ctx *c, const double *x0) {
   a.part = (double *)(c->base + L.off_part);
   a.eta_part = (double *)(c->base + L.off_eta_part);
   if (c->cfg.weighting == MPPI_WEIGHT_COST_TO_GO) {
-    a.pre = (double *)(c->base + L.off_pre);
+    if (!L.fused) a.pre = (double *)(c->base + L.off_pre);
     a.rho_step = (double *)(c->base + L.off_rho_step);
     if (L.ctg_fold) a.blk_tail = (double *)(c->base + L.off_blk_tail);
   }
@@ -626,6 +638,10 @@ static FinalizeArgs make_fin_args(mppi_ctx *c, double *u0_out, int emit) {
     f.n_parts = L.n_roll_blocks;
     f.blk_min = (const double *)(c->base + L.off_blk_min);
     f.Ushadow = (const double *)(c->base + L.off_shadow);
+    if (f.ctg) {
+      f.blk_tail = (const double *)(c->base + L.off_blk_tail);
+      f.rho_step = (double *)(c->base + L.off_rho_step);
+    }
   }
   f.inv_lambda = 1.0 / c->cfg.lambda;
   for (int i = 0; i < 16; ++i) f.Ls[i] = c->Ls[i];

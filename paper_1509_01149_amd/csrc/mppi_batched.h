@@ -88,7 +88,7 @@ static __global__ __launch_bounds__(kFinBlock) void finalize_batched(const CtrlD
   const int j = find_item(prefix, n, blockIdx.x);
   const WorkItem &w = items[j];
   const FinalizeArgs &f = descs[w.desc].fin;
-  if (f.multi) finalize_multi_body(f, blockIdx.x - prefix[j], w.out, w.out + 4, u0_s, [] {});
+  if (f.multi) finalize_multi_body<1>(f, blockIdx.x - prefix[j], w.out, w.out + 4, u0_s, [] {});   // path weighting
   else finalize_body(f, w.out, w.out + 4, u0_s);
 }
 

@@ -97,6 +97,8 @@ struct FinalizeArgs {
   int n_parts;             //   the partials of n_parts rollout blocks
   const double *blk_min;   // multi-block: [n_parts] the rollout blocks' minima
   const double *Ushadow;   // multi-block: the master before this iteration
+  const double *blk_tail;  // multi-block, cost-to-go: [T][n_parts] the rollout blocks' per-step minima
+  double *rho_step;        // multi-block, cost-to-go: [T] receives each step's minimum
   double inv_lambda;
   double Ls[16];           // A chol(Sigma)
   double u_init[4];
@@ -530,18 +532,20 @@ __device__ __forceinline__ void rollout_body_split(const IterArgs &a, const type
                                                    const double *x0, int blk, float4 *lds4) {
   static_assert((Mode & kCrashOn) == 0, "the step-split body has no crash indicator");
   static_assert(Sys::kStepSplit, "system cost acts on the state");
-  static_assert((Mode & kFused) == 0 || (Mode & kRecordPrefix) == 0, "fused: path weighting only");
   constexpr int N = Sys::N, M = Sys::M, NQ = Sys::NQ;
+  constexpr bool kFusedCtg = (Mode & kFused) != 0 && (Mode & kRecordPrefix) != 0;
   constexpr int SPG = 4 / M;                        // steps per noise group
   constexpr int SPB = kBlock / LPS;                 // samples per block
   float *sU = reinterpret_cast<float *>(lds4);      // [T*M]
   float *sRU = sU + a.T * M;                        // [T*M]  R u_i
   float *sC = sRU + a.T * M;                        // [T]    u_i'R u_i / 2
   // kFused: the block's normals [SPB][G*4] and its samples' weights [SPB] (FP64); cost-to-go
-  // with blk_tail: the running cost before each step [SPB][T] and the path costs [SPB] (FP64)
+  // with blk_tail: the running cost before each step [SPB][T] and the path costs [SPB] (FP64);
+  // both (the fused cost-to-go iteration): the normals, then the running costs (which become
+  // the samples' per-step weights), the path costs and the block's per-step minima [T]
   float *sE = sU + ((2 * a.T * M + ((a.T + 3) & ~3) + 3) & ~3);
   double *sW = reinterpret_cast<double *>(sE + SPB * a.G * 4);
-  double *sPre = reinterpret_cast<double *>(sE);
+  double *sPre = kFusedCtg ? sW : reinterpret_cast<double *>(sE);
   __shared__ double red[4];
 
   const uint64_t it = *a.iter;
@@ -672,7 +676,7 @@ __device__ __forceinline__ void rollout_body_split(const IterArgs &a, const type
 #pragma unroll
       for (int s = 0; s < SPG; ++s) {
         const int i = g * SPG + s;
-        if (i < a.T && k < a.K) a.pre[(size_t)i * a.K + k] = r;
+        if (!kFusedCtg && i < a.T && k < a.K) a.pre[(size_t)i * a.K + k] = r;   // the update reads these
         if (a.blk_tail && i < a.T) sPre[(threadIdx.x / LPS) * a.T + i] = r;
         r += (double)qt[s];
       }
@@ -691,6 +695,7 @@ __device__ __forceinline__ void rollout_body_split(const IterArgs &a, const type
     // reduces these instead of a separate pass over the [T][K] prefix costs
     if (a.blk_tail) {
       double *sS = sPre + SPB * a.T;
+      double *sRho = sS + SPB;                      // kFusedCtg: the block's per-step minima
       if (lane_j == 0) sS[threadIdx.x / LPS] = valid ? S : __builtin_inf();
       __syncthreads();
       for (int i = threadIdx.x; i < a.T; i += kBlock) {
@@ -700,10 +705,39 @@ __device__ __forceinline__ void rollout_body_split(const IterArgs &a, const type
           m = fmin(m, sv < __builtin_inf() ? sv - sPre[sb * a.T + i] : __builtin_inf());
         }
         a.blk_tail[(size_t)i * a.n_roll_blocks + blk] = m;
+        if constexpr (kFusedCtg) sRho[i] = m;
+      }
+      if constexpr (kFusedCtg) {
+        // the fused cost-to-go iteration: each sample's per-step weights against the block's
+        // own per-step minima, w = exp(-((S - cost before step i) - rho_b,i) / lambda) (in
+        // place of the running costs), then the block's per-step sums in sample order: for
+        // component f of step i = f / m, sum_k w_k,i eps_k,f, and eta_b,i = sum_k w_k,i
+        __syncthreads();
+        for (int q = threadIdx.x; q < SPB * a.T; q += kBlock) {
+          const int sb = q / a.T, i = q - sb * a.T;
+          const double sv = sS[sb];
+          sPre[q] = sv < __builtin_inf() ? exp(-((sv - sPre[q]) - sRho[i]) * a.inv_lambda) : 0.0;
+        }
+        __syncthreads();
+        const int TM = a.T * M, F = a.G * 4;
+        for (int f = threadIdx.x; f < TM; f += kBlock) {
+          const int i = f / M;
+          double acc = 0.0;
+#pragma unroll
+          for (int sb = 0; sb < SPB; ++sb) acc = fma(sPre[sb * a.T + i], (double)sE[sb * F + f], acc);
+          a.part[(size_t)blk * F + f] = acc;
+        }
+        for (int i = threadIdx.x; i < a.T; i += kBlock) {
+          double e = 0.0;
+#pragma unroll
+          for (int sb = 0; sb < SPB; ++sb) e += sPre[sb * a.T + i];
+          a.eta_part[(size_t)blk * a.T + i] = e;
+        }
       }
     }
   }
-  if constexpr ((Mode & kFused) != 0) fused_tail<SPB>(a, blk, M, lane_j == 0, threadIdx.x / LPS, valid, S, bm, sE, sW);
+  if constexpr ((Mode & kFused) != 0 && !kFusedCtg)
+    fused_tail<SPB>(a, blk, M, lane_j == 0, threadIdx.x / LPS, valid, S, bm, sE, sW);
 }
 
 // Multi-block finalize: the block past a controller's rollout blocks, off the critical paths:
@@ -1087,56 +1121,100 @@ static __global__ __launch_bounds__(kFinBlock) void finalize_kernel(const Finali
   finalize_body(a, a.u0_out, nullptr, u0_s);
 }
 
-// Min and fixed-order sum over a kFinBlock-thread block (16 waves); every thread gets the result.
-__device__ __forceinline__ double fin_block_min(double v, double *scratch16) {
+// Min and fixed-order sum over a kFinBlock-thread block (16 waves) of up to NS values at
+// once (the first ns), with one pair of barriers: each wave reduces, then every thread
+// combines the sixteen waves' results in order and holds the block's.
+template <int NS>
+__device__ __forceinline__ void fin_block_min_n(double (&v)[NS], int ns, double (*scratch)[NS]) {
   constexpr int NW = kFinBlock / kWave;
-  v = wave_min(v);
-  __syncthreads();
-  if ((threadIdx.x & (kWave - 1)) == 0) scratch16[threadIdx.x / kWave] = v;
-  __syncthreads();
-  double r = scratch16[0];
 #pragma unroll
-  for (int w = 1; w < NW; ++w) r = fmin(r, scratch16[w]);
-  return r;
+  for (int s = 0; s < NS; ++s)
+    if (s < ns) v[s] = wave_min(v[s]);
+  __syncthreads();
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+      if (s < ns) scratch[threadIdx.x / kWave][s] = v[s];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    if (s < ns) {
+      double r = scratch[0][s];
+#pragma unroll
+      for (int w = 1; w < NW; ++w) r = fmin(r, scratch[w][s]);
+      v[s] = r;
+    }
+  }
 }
-__device__ __forceinline__ double fin_block_sum(double v, double *scratch16) {
+template <int NS>
+__device__ __forceinline__ void fin_block_sum_n(double (&v)[NS], int ns, double (*scratch)[NS]) {
   constexpr int NW = kFinBlock / kWave;
-  v = wave_sum(v);
-  __syncthreads();
-  if ((threadIdx.x & (kWave - 1)) == 0) scratch16[threadIdx.x / kWave] = v;
-  __syncthreads();
-  double r = 0.0;
 #pragma unroll
-  for (int w = 0; w < NW; ++w) r += scratch16[w];
-  return r;
+  for (int s = 0; s < NS; ++s)
+    if (s < ns) v[s] = wave_sum(v[s]);
+  __syncthreads();
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+      if (s < ns) scratch[threadIdx.x / kWave][s] = v[s];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    if (s < ns) {
+      double r = 0.0;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) r += scratch[w][s];
+      v[s] = r;
+    }
+  }
 }
 
 // Multi-block finalize, block fb of ceil(T*m / kFinOut): components [4 fb, 4 fb + 4), whole
 // time steps since m divides 4.  Every block forms rho = min_b rho_b, the factors
 // alpha_b = exp(-(rho_b - rho)/lambda) and eta = sum_b alpha_b eta_b from the same loads in
-// the same order, so all agree bit for bit.  Thread (r, c) = (t / 4, t % 4) sums
+// the same order, so all agree bit for bit.  Under cost-to-go weighting each of the block's
+// steps i has its own: rho_i = min_b rho_b,i (the rollout blocks' per-step minima), alpha_b,i
+// and eta_i = sum_b alpha_b,i eta_b,i, and a component is rescaled and normalised by those
+// of its step (the block's first step's minimum is finite exactly when some path cost is).  Thread (r, c) = (t / 4, t % 4) sums
 // alpha_b N_b,c over the rollout blocks b = r + 256 j in order of j; the sixteen runs of a
 // wave that share c are added by a butterfly, then the sixteen waves' sums in order.  The old
 // sequence comes from the shadow the rollout wrote, so the shifted write-back into U64 cannot
 // race with another block's read.  Block 0 emits u0, counts the iteration and writes the
 // diagnostics.  `after_loads` runs once the loads are issued, before the first barrier.
 // Returns with u0 in u0_s (block 0, when a.emit).
-template <class Hook>
+// kSteps: 1 under path weighting, kFinOut (the most steps a block holds, m = 1) under
+// cost-to-go weighting; the kernels pick the instance from a.ctg.
+template <int kSteps, class Hook>
 __device__ __forceinline__ void finalize_multi_body(const FinalizeArgs &a, int fb, double *u0_out,
                                                     double *status_out, double *u0_s, Hook after_loads) {
   constexpr int NT = kFinBlock, NR = NT / kFinOut, NW = NT / kWave, kPerRun = kMaxMergedParts / NR;
   static_assert(kFinOut % 4 == 0 && kWave % kFinOut == 0 && kPerRun >= 1, "multi-block finalize layout");
-  __shared__ double alpha[kMaxMergedParts];
+  static_assert(kSteps == 1 || kSteps == kFinOut, "one step or a block's worth");
+  __shared__ double alpha[kSteps][kMaxMergedParts];   // per step
   __shared__ double wsum[NW][kFinOut];
   __shared__ double N_s[kFinOut];
-  __shared__ double red[NW];
+  __shared__ double red[NW][1];
   const int TM = a.T * a.m, P = a.n_parts, F = a.G * 4;
   const int c = threadIdx.x % kFinOut, r = threadIdx.x / kFinOut;
   const int f = fb * kFinOut + c;
-  // every load up front: block minima and normalisers (one each per thread), this thread's
-  // partials, the old sequence and its row of A chol(Sigma), the counter
-  const double mb = (int)threadIdx.x < P ? a.blk_min[threadIdx.x] : __builtin_inf();
-  const double eb = (int)threadIdx.x < P ? a.eta_part[threadIdx.x] : 0.0;
+  const int i0 = fb * kFinOut / a.m;                  // the block's first step
+  const int ns = kSteps > 1 ? min(kFinOut / a.m, a.T - i0) : 1;
+  // every load up front: block minima and normalisers (one each per thread and step), this
+  // thread's partials, the old sequence and its row of A chol(Sigma), the counter
+  double mb[kSteps], eb[kSteps];
+#pragma unroll
+  for (int st = 0; st < kSteps; ++st) {
+    const bool in = st < ns && (int)threadIdx.x < P;
+    if constexpr (kSteps > 1) {
+      mb[st] = in ? a.blk_tail[(size_t)(i0 + st) * P + threadIdx.x] : __builtin_inf();
+      eb[st] = in ? a.eta_part[(size_t)threadIdx.x * a.T + i0 + st] : 0.0;
+    } else {
+      mb[st] = in ? a.blk_min[threadIdx.x] : __builtin_inf();
+      eb[st] = in ? a.eta_part[threadIdx.x] : 0.0;
+    }
+  }
   double pv[kPerRun];
 #pragma unroll
   for (int j = 0; j < kPerRun; ++j) {
@@ -1151,14 +1229,29 @@ __device__ __forceinline__ void finalize_multi_body(const FinalizeArgs &a, int f
   for (int l = 0; l < 4; ++l) Lrow[l] = owner && l <= jc ? a.Ls[jc * a.m + l] : 0.0;
   const uint64_t it0 = fb == 0 && threadIdx.x == 0 ? a.iter[0] : 0;
   after_loads();
-  const double rho = fin_block_min(mb, red);
-  const bool ok = rho < __builtin_inf();
-  const double al = ok && mb < __builtin_inf() ? exp(-(mb - rho) * a.inv_lambda) : 0.0;
-  alpha[threadIdx.x] = al;                            // 0 past the last block
-  const double eta = fin_block_sum(al * eb, red);     // its barriers publish alpha
+  // each step's minimum, factors and normaliser (a reduction pair per step: measured faster
+  // than one pair for all of the block's steps at once)
+  double rho[kSteps], eta[kSteps];
+#pragma unroll
+  for (int st = 0; st < kSteps; ++st) {
+    rho[st] = __builtin_inf();
+    eta[st] = 0.0;
+    if (st < ns) {                                    // block-uniform
+      double v[1] = {mb[st]};
+      fin_block_min_n<1>(v, 1, red);
+      rho[st] = v[0];
+      const double al = rho[st] < __builtin_inf() && mb[st] < __builtin_inf() ? exp(-(mb[st] - rho[st]) * a.inv_lambda)
+                                                                               : 0.0;
+      alpha[st][threadIdx.x] = al;                    // 0 past the last block
+      double w[1] = {al * eb[st]};
+      fin_block_sum_n<1>(w, 1, red);                  // its barriers publish alpha
+      eta[st] = w[0];
+    }
+  }
+  const int sc = kSteps > 1 && f < TM ? f / a.m - i0 : 0;   // this component's step in the block
   double acc = 0.0;
 #pragma unroll
-  for (int j = 0; j < kPerRun; ++j) acc = fma(alpha[r + NR * j], pv[j], acc);
+  for (int j = 0; j < kPerRun; ++j) acc = fma(alpha[sc][r + NR * j], pv[j], acc);
   // the wave's runs of component c (lanes c + kFinOut q) by an xor butterfly: partners
   // add the same two values, so every lane ends with the same bits
 #pragma unroll
@@ -1172,9 +1265,14 @@ __device__ __forceinline__ void finalize_multi_body(const FinalizeArgs &a, int f
     N_s[threadIdx.x] = sum;
   }
   __syncthreads();
+  const bool ok = rho[0] < __builtin_inf();
   if (owner) {
     const int base = i * a.m - fb * kFinOut;
-    const double inv_eta = ok ? 1.0 / eta : 0.0;
+    double eta_c = eta[0];                            // this component's step's normaliser
+#pragma unroll
+    for (int st = 1; st < kSteps; ++st)
+      if (st == sc) eta_c = eta[st];
+    const double inv_eta = ok ? 1.0 / eta_c : 0.0;
     double d = 0.0;
 #pragma unroll
     for (int l = 0; l < 4; ++l)
@@ -1199,9 +1297,14 @@ __device__ __forceinline__ void finalize_multi_body(const FinalizeArgs &a, int f
       }
     }
   }
+  if (kSteps > 1 && threadIdx.x == 0) {
+#pragma unroll
+    for (int st = 0; st < kSteps; ++st)
+      if (st < ns) a.rho_step[i0 + st] = rho[st];
+  }
   if (fb == 0 && threadIdx.x == 0) {
-    a.dbg[0] = rho;
-    a.dbg[1] = ok ? eta : 0.0;
+    a.dbg[0] = rho[0];
+    a.dbg[1] = ok ? eta[0] : 0.0;
     if (!ok) a.flags[0] += 1;
     if (status_out) *status_out = ok ? 0.0 : -5.0;
     a.iter[0] = it0 + 1;
@@ -1211,7 +1314,8 @@ __device__ __forceinline__ void finalize_multi_body(const FinalizeArgs &a, int f
 
 static __global__ __launch_bounds__(kFinBlock) void finalize_multi_kernel(const FinalizeArgs a) {
   __shared__ double u0_s[4];
-  finalize_multi_body(a, blockIdx.x, a.u0_out, nullptr, u0_s, [] {});
+  if (a.ctg) finalize_multi_body<kFinOut>(a, blockIdx.x, a.u0_out, nullptr, u0_s, [] {});
+  else finalize_multi_body<1>(a, blockIdx.x, a.u0_out, nullptr, u0_s, [] {});
 }
 
 // finalize + the plant step on the emitted control.  The last wave evaluates the plant
@@ -1234,7 +1338,8 @@ template <class Sys>
 __global__ __launch_bounds__(kFinBlock) void finalize_multi_plant_kernel(const FinalizeArgs a, double *x, double dt,
                                                                          int n, const double *basis) {
   __shared__ double u0_s[4];
-  finalize_multi_body(a, blockIdx.x, a.u0_out, nullptr, u0_s, [] {});
+  if (a.ctg) finalize_multi_body<kFinOut>(a, blockIdx.x, a.u0_out, nullptr, u0_s, [] {});
+  else finalize_multi_body<1>(a, blockIdx.x, a.u0_out, nullptr, u0_s, [] {});
   if (blockIdx.x == 0 && threadIdx.x == 0)
     plant_combine<Sys>(x, n, dt, reinterpret_cast<const double (*)[Sys::N]>(basis), u0_s);
 }

@@ -133,14 +133,21 @@ def test_extension_fields_are_validated():
                            (W.cartpole(), B.KERNELS_FUSED, B.OK)):
         c, keep = _cfg(w, kernels=kernels)
         assert _ws(c)[0] == rc, (w.name, w.T, kernels)
+    # cost-to-go: fused on the step-split systems (running costs kept in LDS), not on the quadrotor
     c, keep = _cfg(wl, kernels=B.KERNELS_FUSED, weighting=B.WEIGHT_COST_TO_GO)
+    assert _ws(c)[0] == B.OK
+    c, keep = _cfg(W.quadrotor(), kernels=B.KERNELS_FUSED, weighting=B.WEIGHT_COST_TO_GO)
+    assert _ws(c)[0] == B.EINVAL
+    c, keep = _cfg(wl.replace(T=1024), kernels=B.KERNELS_FUSED, weighting=B.WEIGHT_COST_TO_GO)   # 66 KiB of running costs
     assert _ws(c)[0] == B.EINVAL
     c, keep = _cfg(wl.replace(K=1 << 20), kernels=B.KERNELS_FUSED)       # 16384 rollout blocks
     assert _ws(c)[0] == B.EINVAL
-    c, keep = _cfg(wl, weighting=B.WEIGHT_COST_TO_GO)
+    # the three-kernel cost-to-go iteration keeps every sample's prefix costs [T][K] for the update
+    c, keep = _cfg(wl, weighting=B.WEIGHT_COST_TO_GO, kernels=B.KERNELS_THREE)
     rc, n_ctg = _ws(c)
-    n_three = _ws(_cfg(wl, kernels=B.KERNELS_THREE)[0])[1]
-    assert rc == B.OK and n_ctg >= n_three + wl.T * wl.K * 8              # prefix costs [T][K]
+    c3, keep3 = _cfg(wl, kernels=B.KERNELS_THREE)
+    n_three = _ws(c3)[1]
+    assert rc == B.OK and n_ctg >= n_three + wl.T * wl.K * 8
     q = W.quadrotor(crash=True)
     c, keep = _cfg(q)
     assert _ws(c)[0] == B.OK

@@ -101,6 +101,48 @@ def test_both_iterations_match_the_oracle(kernels):
         assert_parity(m, label=f"{wl.name} kernels={kernels}")
 
 
+CTG_CASES = [
+    W.bicycle(),                                                       # 32 lanes, 512 blocks
+    W.bicycle(K=1000, T=37),                                           # ragged K and T*m
+    W.bicycle(K=2048, T=60).replace(sigma=np.array([[0.5, 0.1], [0.1, 0.3]])),   # full covariance
+    W.cartpole(nu=2.0),                                                # m = 1: four steps per finalize block
+    W.cartpole(K=257, T=7),                                            # one finalize block, ragged
+    W.linear_double_integrator(K=300, R=0.3),
+]
+
+
+@pytest.mark.parametrize("wl", CTG_CASES, ids=_ids)
+def test_fused_cost_to_go_equals_three_kernel_cost_to_go(wl):
+    """Cost-to-go weighting through two kernels (each rollout block weights its samples'
+    steps against its own per-step minima, the finalize rescales by
+    exp(-(rho_b,i - rho_i)/lambda) per step) against the three-kernel iteration: the same
+    costs bitwise, each step's minimum exactly, the normaliser and the update to FP64
+    reassociation."""
+    ctg = P.WEIGHT_COST_TO_GO
+    f = P.controller_for(wl, weighting=ctg, kernels=P.KERNELS_FUSED)
+    t = P.controller_for(wl, weighting=ctg, kernels=P.KERNELS_THREE)
+    with f, t:
+        fi, ti = f.info(), t.info()
+        assert fi["rollout_mode"] & P.binding.ROLLOUT_FUSED and fi["update_blocks"] == 0, fi
+        assert not ti["rollout_mode"] & P.binding.ROLLOUT_FUSED, ti
+        uf, ut = f.step(wl.x0), t.step(wl.x0)
+        Sf, rf, ef, dUf = f.debug_last()
+        St, rt, et, dUt = t.debug_last()
+        assert np.array_equal(Sf, St)
+        assert rf == rt                                 # step 0's minimum (the path minimum)
+        assert abs(ef - et) <= TOL_ETA * et, (ef, et)   # step 0's normaliser
+        scale = float(np.max(np.abs(dUt)))
+        assert np.max(np.abs(dUf - dUt)) <= TOL_DU * scale, (np.max(np.abs(dUf - dUt)), scale)
+        U_scale = max(1.0, float(np.max(np.abs(t.get_controls()))))
+        assert np.max(np.abs(f.get_controls() - t.get_controls())) <= TOL_DU * U_scale
+        assert np.max(np.abs(uf - ut)) <= TOL_DU * U_scale
+        for it in (1, 2):
+            uf, ut = f.step(wl.x0), t.step(wl.x0)
+            U_scale = max(1.0, float(np.max(np.abs(t.get_controls()))))
+            assert np.max(np.abs(f.get_controls() - t.get_controls())) <= TOL_LATER * U_scale, it
+        assert f.iteration() == t.iteration() == 3
+
+
 def test_fused_closed_loop_with_the_plant():
     """The fused finalize with the plant step: a closed-loop run equals single steps bitwise,
     and stays with the three-kernel run to FP64 reassociation."""

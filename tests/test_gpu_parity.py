@@ -256,16 +256,20 @@ def test_cost_to_go_parity(name):
 
 def test_cost_to_go_first_step_equals_path_weighting():
     """At step 0 the cost-to-go is the whole path cost: u_0 must be bitwise the same under
-    both weightings through the same kernels (the three-kernel iteration; cost-to-go has no
-    fused one), and the same to FP64 reassociation through the fused path iteration; later
-    steps must differ."""
+    both weightings through the same kernels (three per iteration, or two: the fused
+    iterations weight step 0 against the same block minima), and the same to FP64
+    reassociation across the two kernel counts; later steps must differ."""
     wl = W.bicycle(K=2048, T=50).replace(seed=9)
-    with controller(wl, kernels=P.KERNELS_THREE) as a, controller(wl, weighting=P.WEIGHT_COST_TO_GO) as b, \
-            controller(wl) as f:
-        ua, ub, uf = a.step(wl.x0), b.step(wl.x0), f.step(wl.x0)
+    ctg = P.WEIGHT_COST_TO_GO
+    with controller(wl, kernels=P.KERNELS_THREE) as a, controller(wl, weighting=ctg, kernels=P.KERNELS_THREE) as b, \
+            controller(wl, kernels=P.KERNELS_FUSED) as f, controller(wl, weighting=ctg, kernels=P.KERNELS_FUSED) as g:
+        assert g.info()["rollout_mode"] & P.binding.ROLLOUT_FUSED
+        ua, ub, uf, ug = a.step(wl.x0), b.step(wl.x0), f.step(wl.x0), g.step(wl.x0)
         assert np.array_equal(ua, ub)
+        assert np.array_equal(uf, ug)
         assert np.max(np.abs(uf - ub)) <= 1e-9 * max(1.0, np.max(np.abs(ub)))
         assert not np.array_equal(a.get_controls(), b.get_controls())
+        assert not np.array_equal(f.get_controls(), g.get_controls())
 
 
 def test_swingup_closed_loop_exploration_variance():
