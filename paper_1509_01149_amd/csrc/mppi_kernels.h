@@ -18,12 +18,13 @@
 //                 U += dU (FP64 master, FP32 copy for the next rollout); on the last
 //                 iteration of a control step emit u0 and apply the warm shift.
 //
-// Under path weighting the iteration also runs as two kernels (kFused): each rollout
-// block keeps the normals it drew in LDS, weights its own samples against its own minimum
-// rho_b and writes (rho_b, eta_b, N_b = sum_k exp(-(S_k - rho_b)/lambda) eps_k);
-// the finalize rescales every block's partials by exp(-(rho_b - rho)/lambda), which turns
-// them into the weights of the global minimum exactly (the sample-independent factor of the
-// weights cancels in the normalised update, Section III-B).
+// The iteration also runs as two kernels (kFused): each rollout block keeps the normals it
+// drew in LDS, weights its own samples against its own minimum rho_b and writes
+// (rho_b, eta_b, N_b = sum_k exp(-(S_k - rho_b)/lambda) eps_k); the finalize rescales every
+// block's partials by exp(-(rho_b - rho)/lambda), which turns them into the weights of the
+// global minimum exactly (the sample-independent factor of the weights cancels in the
+// normalised update, Section III-B).  Under cost-to-go weighting (step-split body) the same
+// holds step by step, with the blocks' per-step minima and normalisers.
 //
 // The fused iteration's finalize runs as one block per four sequence components (the
 // multi-block finalize): it reads the old sequence from a shadow that an extra rollout block
@@ -132,10 +133,11 @@ __device__ __forceinline__ void plant_combine(double *x, int n, double dt, const
 // ------------------------------------------------------------------------ rollout
 // One block of one controller (`blk` indexes the controller's blocks): 256 / LPS samples,
 // LPS adjacent lanes per sample.  With LPS = 4 the four lanes of a DPP quad share a
-// sample: lane j generates every fourth noise group (g = 4r + j) and broadcasts it across
-// the quad, a system with a decomposable cost splits it over the quad and sums with two
-// DPP steps, and the dynamics run redundantly, so all four lanes hold the same state and
-// the same path cost.  The single-controller kernel and the batched serving kernel both
+// sample: lane j generates every fourth noise group (g = 4r + j) and broadcasts it (with
+// the folded step, its fold) across the quad, a system with a decomposable cost splits it
+// over the quad (each lane summing its share in FP64, the shares added after the horizon;
+// per step with two DPP steps where the running total is recorded), and the dynamics run
+// redundantly, so all four lanes hold the same state.  The single-controller kernel and the batched serving kernel both
 // call this body, so a controller's results do not depend on what else shares a launch.
 __device__ __forceinline__ float quad_sum(float v) {
   v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));   // quad_perm(1,0,3,2)
