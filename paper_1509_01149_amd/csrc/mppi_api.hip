@@ -670,7 +670,7 @@ template <class Sys>
 static void launch_finalize_plant(mppi_ctx *c, const FinalizeArgs &f, double *x, const typename Sys::Params &p,
                                   hipStream_t s) {
   if (c->L.multi)
-    hipLaunchKernelGGL(finalize_multi_plant_kernel<Sys>, dim3(c->L.n_fin_blocks), dim3(kFinBlock), 0, s, f, x,
+    hipLaunchKernelGGL(finalize_multi_plant_kernel<Sys>, dim3(c->L.n_fin_blocks), dim3(kFinMultiBlock), 0, s, f, x,
                        c->cfg.dt, c->cfg.n_state, (const double *)(c->base + c->L.off_basis));
   else
     hipLaunchKernelGGL(finalize_plant_kernel<Sys>, dim3(1), dim3(kFinBlock), 0, s, f, x, c->cfg.dt, c->cfg.n_state, p);
@@ -679,7 +679,7 @@ static void launch_finalize_plant(mppi_ctx *c, const FinalizeArgs &f, double *x,
 // Last finalize of a step with the plant step fused (plant_x != NULL).
 static void launch_finalize(mppi_ctx *c, const FinalizeArgs &f, double *plant_x, hipStream_t s) {
   if (!plant_x) {
-    if (c->L.multi) hipLaunchKernelGGL(finalize_multi_kernel, dim3(c->L.n_fin_blocks), dim3(kFinBlock), 0, s, f);
+    if (c->L.multi) hipLaunchKernelGGL(finalize_multi_kernel, dim3(c->L.n_fin_blocks), dim3(kFinMultiBlock), 0, s, f);
     else hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kFinBlock), 0, s, f);
     return;
   }

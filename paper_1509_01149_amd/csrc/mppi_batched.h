@@ -79,8 +79,9 @@ static __global__ __launch_bounds__(kBlock) void update_batched(const CtrlDesc *
   update_body(d.it, l % d.it.n_kc, l / d.it.n_kc);
 }
 
-// One block per controller, or ceil(T*m / kFinOut) with the multi-block finalize (prefix over
-// the items).
+// One block per controller, or with the multi-block finalize ceil(ceil(T*m / kFinOut) / 4):
+// each 1024-thread block then holds four multi-block finalize blocks (prefix over the items).
+static_assert(kFinBlock == 4 * kFinMultiBlock, "four multi-block finalize blocks per batched block");
 static __global__ __launch_bounds__(kFinBlock) void finalize_batched(const CtrlDesc *__restrict__ descs,
                                                                      const WorkItem *__restrict__ items,
                                                                      const int *__restrict__ prefix, int n) {
@@ -88,8 +89,12 @@ static __global__ __launch_bounds__(kFinBlock) void finalize_batched(const CtrlD
   const int j = find_item(prefix, n, blockIdx.x);
   const WorkItem &w = items[j];
   const FinalizeArgs &f = descs[w.desc].fin;
-  if (f.multi) finalize_multi_body<1>(f, blockIdx.x - prefix[j], w.out, w.out + 4, u0_s, [] {});   // path weighting
-  else finalize_body(f, w.out, w.out + 4, u0_s);
+  if (f.multi) {                                       // path weighting
+    const int fb = 4 * (blockIdx.x - prefix[j]) + (int)threadIdx.x / kFinMultiBlock;
+    finalize_multi_body<1, 4>(f, fb, w.out, w.out + 4, u0_s, [] {});
+  } else {
+    finalize_body(f, w.out, w.out + 4, u0_s);
+  }
 }
 
 }  // namespace mppi

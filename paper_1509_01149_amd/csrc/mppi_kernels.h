@@ -77,6 +77,7 @@ struct IterArgs {
 // a gfx950 CU's: the four-lane body runs one block per CU).
 constexpr int kMaxMergedParts = 1024;
 constexpr int kFinOut = 4;
+constexpr int kFinMultiBlock = 256;                  // threads of a multi-block finalize block
 constexpr int kMaxFusedNormalsBytes = 32 * 1024;
 constexpr int kMaxBlockLdsBytes = 160 * 1024;
 constexpr int kQuadFusedAutoBlocks = 256;           // the MI355X's CUs
@@ -1123,56 +1124,6 @@ static __global__ __launch_bounds__(kFinBlock) void finalize_kernel(const Finali
   finalize_body(a, a.u0_out, nullptr, u0_s);
 }
 
-// Min and fixed-order sum over a kFinBlock-thread block (16 waves) of up to NS values at
-// once (the first ns), with one pair of barriers: each wave reduces, then every thread
-// combines the sixteen waves' results in order and holds the block's.
-template <int NS>
-__device__ __forceinline__ void fin_block_min_n(double (&v)[NS], int ns, double (*scratch)[NS]) {
-  constexpr int NW = kFinBlock / kWave;
-#pragma unroll
-  for (int s = 0; s < NS; ++s)
-    if (s < ns) v[s] = wave_min(v[s]);
-  __syncthreads();
-  if ((threadIdx.x & (kWave - 1)) == 0) {
-#pragma unroll
-    for (int s = 0; s < NS; ++s)
-      if (s < ns) scratch[threadIdx.x / kWave][s] = v[s];
-  }
-  __syncthreads();
-#pragma unroll
-  for (int s = 0; s < NS; ++s) {
-    if (s < ns) {
-      double r = scratch[0][s];
-#pragma unroll
-      for (int w = 1; w < NW; ++w) r = fmin(r, scratch[w][s]);
-      v[s] = r;
-    }
-  }
-}
-template <int NS>
-__device__ __forceinline__ void fin_block_sum_n(double (&v)[NS], int ns, double (*scratch)[NS]) {
-  constexpr int NW = kFinBlock / kWave;
-#pragma unroll
-  for (int s = 0; s < NS; ++s)
-    if (s < ns) v[s] = wave_sum(v[s]);
-  __syncthreads();
-  if ((threadIdx.x & (kWave - 1)) == 0) {
-#pragma unroll
-    for (int s = 0; s < NS; ++s)
-      if (s < ns) scratch[threadIdx.x / kWave][s] = v[s];
-  }
-  __syncthreads();
-#pragma unroll
-  for (int s = 0; s < NS; ++s) {
-    if (s < ns) {
-      double r = 0.0;
-#pragma unroll
-      for (int w = 0; w < NW; ++w) r += scratch[w][s];
-      v[s] = r;
-    }
-  }
-}
-
 // Multi-block finalize, block fb of ceil(T*m / kFinOut): components [4 fb, 4 fb + 4), whole
 // time steps since m divides 4.  Every block forms rho = min_b rho_b, the factors
 // alpha_b = exp(-(rho_b - rho)/lambda) and eta = sum_b alpha_b eta_b from the same loads in
@@ -1187,36 +1138,50 @@ __device__ __forceinline__ void fin_block_sum_n(double (&v)[NS], int ns, double 
 // diagnostics.  `after_loads` runs once the loads are issued, before the first barrier.
 // Returns with u0 in u0_s (block 0, when a.emit).
 // kSteps: 1 under path weighting, kFinOut (the most steps a block holds, m = 1) under
-// cost-to-go weighting; the kernels pick the instance from a.ctg.
-template <int kSteps, class Hook>
+// cost-to-go weighting; the kernels pick the instance from a.ctg.  A finalize block is
+// kFinMultiBlock threads; kSub of them share a workgroup (the batched server's 1024-thread
+// blocks hold four: each runs the same code on its own LDS, and every barrier is taken by all
+// four together), so a controller's results do not depend on how its blocks are packed.
+// Thread t of a block loads the minima and normalisers of rollout blocks t, t + 256, ...
+// and sums its share of the weighted normalisers in that order before the wave sums.
+template <int kSteps, int kSub, class Hook>
 __device__ __forceinline__ void finalize_multi_body(const FinalizeArgs &a, int fb, double *u0_out,
                                                     double *status_out, double *u0_s, Hook after_loads) {
-  constexpr int NT = kFinBlock, NR = NT / kFinOut, NW = NT / kWave, kPerRun = kMaxMergedParts / NR;
-  static_assert(kFinOut % 4 == 0 && kWave % kFinOut == 0 && kPerRun >= 1, "multi-block finalize layout");
+  constexpr int NT = kFinMultiBlock, NR = NT / kFinOut, NW = NT / kWave, kPerRun = kMaxMergedParts / NR;
+  constexpr int U = kMaxMergedParts / NT;             // rollout blocks per thread for the minima
+  static_assert(kFinOut % 4 == 0 && kWave % kFinOut == 0 && kPerRun >= 1 && U >= 1, "multi-block finalize layout");
   static_assert(kSteps == 1 || kSteps == kFinOut, "one step or a block's worth");
-  __shared__ double alpha[kSteps][kMaxMergedParts];   // per step
-  __shared__ double wsum[NW][kFinOut];
-  __shared__ double N_s[kFinOut];
-  __shared__ double red[NW][1];
+  __shared__ double alpha_all[kSub][kSteps][kMaxMergedParts];   // per step
+  __shared__ double wsum_all[kSub][NW][kFinOut];
+  __shared__ double N_all[kSub][kFinOut];
+  __shared__ double red_all[kSub][NW];
+  const int sub = kSub > 1 ? (int)threadIdx.x / NT : 0;
+  const int lt = kSub > 1 ? (int)threadIdx.x % NT : (int)threadIdx.x;
+  double (*alpha)[kMaxMergedParts] = alpha_all[sub];
+  double (*wsum)[kFinOut] = wsum_all[sub];
+  double *N_s = N_all[sub], *red = red_all[sub];
   const int TM = a.T * a.m, P = a.n_parts, F = a.G * 4;
-  const int c = threadIdx.x % kFinOut, r = threadIdx.x / kFinOut;
+  const int c = lt % kFinOut, r = lt / kFinOut;
   const int f = fb * kFinOut + c;
   const int i0 = fb * kFinOut / a.m;                  // the block's first step
   const int ns = kSteps > 1 ? min(kFinOut / a.m, a.T - i0) : 1;
-  // every load up front: block minima and normalisers (one each per thread and step), this
+  // every load up front: block minima and normalisers (U each per thread and step), this
   // thread's partials, the old sequence and its row of A chol(Sigma), the counter
-  double mb[kSteps], eb[kSteps];
+  double mb[kSteps][U], eb[kSteps][U];
 #pragma unroll
-  for (int st = 0; st < kSteps; ++st) {
-    const bool in = st < ns && (int)threadIdx.x < P;
-    if constexpr (kSteps > 1) {
-      mb[st] = in ? a.blk_tail[(size_t)(i0 + st) * P + threadIdx.x] : __builtin_inf();
-      eb[st] = in ? a.eta_part[(size_t)threadIdx.x * a.T + i0 + st] : 0.0;
-    } else {
-      mb[st] = in ? a.blk_min[threadIdx.x] : __builtin_inf();
-      eb[st] = in ? a.eta_part[threadIdx.x] : 0.0;
+  for (int st = 0; st < kSteps; ++st)
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int b = lt + NT * u;
+      const bool in = st < ns && b < P;
+      if constexpr (kSteps > 1) {
+        mb[st][u] = in ? a.blk_tail[(size_t)(i0 + st) * P + b] : __builtin_inf();
+        eb[st][u] = in ? a.eta_part[(size_t)b * a.T + i0 + st] : 0.0;
+      } else {
+        mb[st][u] = in ? a.blk_min[b] : __builtin_inf();
+        eb[st][u] = in ? a.eta_part[b] : 0.0;
+      }
     }
-  }
   double pv[kPerRun];
 #pragma unroll
   for (int j = 0; j < kPerRun; ++j) {
@@ -1229,25 +1194,42 @@ __device__ __forceinline__ void finalize_multi_body(const FinalizeArgs &a, int f
   double Lrow[4];
 #pragma unroll
   for (int l = 0; l < 4; ++l) Lrow[l] = owner && l <= jc ? a.Ls[jc * a.m + l] : 0.0;
-  const uint64_t it0 = fb == 0 && threadIdx.x == 0 ? a.iter[0] : 0;
+  const uint64_t it0 = fb == 0 && lt == 0 ? a.iter[0] : 0;
   after_loads();
-  // each step's minimum, factors and normaliser (a reduction pair per step: measured faster
-  // than one pair for all of the block's steps at once)
+  // each step's minimum, factors and normaliser (a reduction pair per step)
   double rho[kSteps], eta[kSteps];
 #pragma unroll
   for (int st = 0; st < kSteps; ++st) {
     rho[st] = __builtin_inf();
     eta[st] = 0.0;
-    if (st < ns) {                                    // block-uniform
-      double v[1] = {mb[st]};
-      fin_block_min_n<1>(v, 1, red);
-      rho[st] = v[0];
-      const double al = rho[st] < __builtin_inf() && mb[st] < __builtin_inf() ? exp(-(mb[st] - rho[st]) * a.inv_lambda)
-                                                                               : 0.0;
-      alpha[st][threadIdx.x] = al;                    // 0 past the last block
-      double w[1] = {al * eb[st]};
-      fin_block_sum_n<1>(w, 1, red);                  // its barriers publish alpha
-      eta[st] = w[0];
+    if (st < ns) {                                    // uniform over the workgroup
+      double m = mb[st][0];
+#pragma unroll
+      for (int u = 1; u < U; ++u) m = fmin(m, mb[st][u]);
+      m = wave_min(m);
+      __syncthreads();
+      if ((lt & (kWave - 1)) == 0) red[lt / kWave] = m;
+      __syncthreads();
+      double rr = red[0];
+#pragma unroll
+      for (int w = 1; w < NW; ++w) rr = fmin(rr, red[w]);
+      rho[st] = rr;
+      double e = 0.0;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const double al = rr < __builtin_inf() && mb[st][u] < __builtin_inf()
+                              ? exp(-(mb[st][u] - rr) * a.inv_lambda) : 0.0;
+        alpha[st][lt + NT * u] = al;                  // 0 past the last block
+        e = fma(al, eb[st][u], e);
+      }
+      e = wave_sum(e);
+      __syncthreads();                                // also publishes alpha
+      if ((lt & (kWave - 1)) == 0) red[lt / kWave] = e;
+      __syncthreads();
+      double es = 0.0;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) es += red[w];
+      eta[st] = es;
     }
   }
   const int sc = kSteps > 1 && f < TM ? f / a.m - i0 : 0;   // this component's step in the block
@@ -1258,13 +1240,13 @@ __device__ __forceinline__ void finalize_multi_body(const FinalizeArgs &a, int f
   // add the same two values, so every lane ends with the same bits
 #pragma unroll
   for (int st = kFinOut; st < kWave; st *= 2) acc += __shfl_xor(acc, st);
-  if ((threadIdx.x & (kWave - 1)) < kFinOut) wsum[threadIdx.x / kWave][c] = acc;
+  if ((lt & (kWave - 1)) < kFinOut) wsum[lt / kWave][c] = acc;
   __syncthreads();
-  if ((int)threadIdx.x < kFinOut) {
+  if (lt < kFinOut) {
     double sum = 0.0;
 #pragma unroll
-    for (int w = 0; w < NW; ++w) sum += wsum[w][threadIdx.x];
-    N_s[threadIdx.x] = sum;
+    for (int w = 0; w < NW; ++w) sum += wsum[w][lt];
+    N_s[lt] = sum;
   }
   __syncthreads();
   const bool ok = rho[0] < __builtin_inf();
@@ -1299,12 +1281,12 @@ __device__ __forceinline__ void finalize_multi_body(const FinalizeArgs &a, int f
       }
     }
   }
-  if (kSteps > 1 && threadIdx.x == 0) {
+  if (kSteps > 1 && lt == 0) {
 #pragma unroll
     for (int st = 0; st < kSteps; ++st)
       if (st < ns) a.rho_step[i0 + st] = rho[st];
   }
-  if (fb == 0 && threadIdx.x == 0) {
+  if (fb == 0 && lt == 0) {
     a.dbg[0] = rho[0];
     a.dbg[1] = ok ? eta[0] : 0.0;
     if (!ok) a.flags[0] += 1;
@@ -1314,10 +1296,10 @@ __device__ __forceinline__ void finalize_multi_body(const FinalizeArgs &a, int f
   if (a.emit) __syncthreads();                        // u0_s for the plant step
 }
 
-static __global__ __launch_bounds__(kFinBlock) void finalize_multi_kernel(const FinalizeArgs a) {
+static __global__ __launch_bounds__(kFinMultiBlock) void finalize_multi_kernel(const FinalizeArgs a) {
   __shared__ double u0_s[4];
-  if (a.ctg) finalize_multi_body<kFinOut>(a, blockIdx.x, a.u0_out, nullptr, u0_s, [] {});
-  else finalize_multi_body<1>(a, blockIdx.x, a.u0_out, nullptr, u0_s, [] {});
+  if (a.ctg) finalize_multi_body<kFinOut, 1>(a, blockIdx.x, a.u0_out, nullptr, u0_s, [] {});
+  else finalize_multi_body<1, 1>(a, blockIdx.x, a.u0_out, nullptr, u0_s, [] {});
 }
 
 // finalize + the plant step on the emitted control.  The last wave evaluates the plant
@@ -1337,11 +1319,11 @@ __global__ __launch_bounds__(kFinBlock) void finalize_plant_kernel(const Finaliz
 // The multi-block finalize + the plant step: block 0, which emits u0, combines it with the
 // plant basis the rollout's extra block wrote; no other block touches x.
 template <class Sys>
-__global__ __launch_bounds__(kFinBlock) void finalize_multi_plant_kernel(const FinalizeArgs a, double *x, double dt,
-                                                                         int n, const double *basis) {
+__global__ __launch_bounds__(kFinMultiBlock) void finalize_multi_plant_kernel(const FinalizeArgs a, double *x,
+                                                                              double dt, int n, const double *basis) {
   __shared__ double u0_s[4];
-  if (a.ctg) finalize_multi_body<kFinOut>(a, blockIdx.x, a.u0_out, nullptr, u0_s, [] {});
-  else finalize_multi_body<1>(a, blockIdx.x, a.u0_out, nullptr, u0_s, [] {});
+  if (a.ctg) finalize_multi_body<kFinOut, 1>(a, blockIdx.x, a.u0_out, nullptr, u0_s, [] {});
+  else finalize_multi_body<1, 1>(a, blockIdx.x, a.u0_out, nullptr, u0_s, [] {});
   if (blockIdx.x == 0 && threadIdx.x == 0)
     plant_combine<Sys>(x, n, dt, reinterpret_cast<const double (*)[Sys::N]>(basis), u0_s);
 }

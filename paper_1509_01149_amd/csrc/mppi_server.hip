@@ -614,7 +614,7 @@ extern "C" int mppi_server_admit(mppi_server *s, const mppi_config *cfg, int32_t
   S.m = c.n_ctrl;
   S.n_roll = ctx->L.n_roll_blocks + (ctx->L.multi ? 1 : 0);   // the shadow block
   S.n_upd = ctx->L.fused ? 0 : ctx->L.n_kc * ((ctx->L.G + kUpdGroups - 1) / kUpdGroups);
-  S.n_fin = ctx->L.n_fin_blocks;
+  S.n_fin = ctx->L.multi ? (ctx->L.n_fin_blocks + 3) / 4 : 1;   // four multi-block finalize blocks per block
   S.lds = ctx_rollout_lds(ctx);
   S.rollout_steps = (int64_t)c.K * c.T;
   s->used += bytes;
