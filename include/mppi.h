@@ -107,7 +107,9 @@ typedef struct {
  *   euler' = W(euler)^-1 w,  w' = J^-1 (tau - w x J w),
  *   tau = (arm (f2 - f4), arm (f3 - f1), yaw_coef (f1 - f2 + f3 - f4)),  J = diag(inertia)
  * q = w_goal |p - goal|^2 + w_obs sum_j max(0, (r_j + obs_margin)^2 - |p - c_j|^2)^2,
- * phi = 0.  obstacles: n_obstacles x 4 (cx, cy, cz, r) FP64, copied; n_obstacles <= 256.
+ * phi = 0.  obstacles: n_obstacles x 4 (cx, cy, cz, r) FP64, copied; n_obstacles <= 256;
+ * finite centres, r >= 0 and r + obs_margin <= 1e6, obs_margin >= 0, w_obs in [0, 1e12]
+ * (else MPPI_EINVAL).
  * crash_cost > 0 adds the crash indicator C (Section V-C): C = 1 once p_z < ground_z or
  * |p - c_j| < r_j; from then on the rollout stops simulating, the vehicle stays where it
  * is and every remaining step adds crash_cost (not with MPPI_SYS_QUADROTOR_MLP). */

@@ -188,6 +188,18 @@ int validate_config(const mppi_config *c) {
     if (p->n_obstacles < 0 || p->n_obstacles > QuadrotorSys::kMaxObstacles)
       return fail(MPPI_EINVAL, "quadrotor params: n_obstacles outside [0, %d]", QuadrotorSys::kMaxObstacles);
     if (p->n_obstacles > 0 && !p->obstacles) return fail(MPPI_EINVAL, "quadrotor params: obstacles is NULL");
+    // finite spheres of radius + margin at most 1e6 and w_obs at most 1e12: the device obstacles
+    // are scaled by a power of two s with s (r + margin)^2 <= 1/4, their weight by 1 / s^2,
+    // which then stays finite in FP32
+    if (!(p->obs_margin >= 0) || !std::isfinite(p->obs_margin) || !(p->w_obs >= 0) || !(p->w_obs <= 1e12) ||
+        !std::isfinite(p->w_goal))
+      return fail(MPPI_EINVAL, "quadrotor params: obs_margin must be finite and >= 0, w_obs in [0, 1e12], w_goal finite");
+    for (int j = 0; j < p->n_obstacles; ++j) {
+      const double *o = p->obstacles + 4 * j;
+      if (!std::isfinite(o[0]) || !std::isfinite(o[1]) || !std::isfinite(o[2]) || !(o[3] >= 0) ||
+          !(o[3] + p->obs_margin <= 1e6))
+        return fail(MPPI_EINVAL, "quadrotor params: obstacle %d needs a finite centre and a radius in [0, 1e6 - margin]", j);
+    }
     if (!(p->mass > 0) || !(p->inertia[0] > 0) || !(p->inertia[1] > 0) || !(p->inertia[2] > 0))
       return fail(MPPI_EINVAL, "quadrotor params: mass and inertia must be > 0");
     if (c->system == MPPI_SYS_QUADROTOR_MLP && !((const mppi_quadrotor_mlp_params *)c->params)->mlp)

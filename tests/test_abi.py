@@ -104,6 +104,13 @@ def test_bicycle_map_and_quadrotor_obstacles_are_validated():
     q = W.quadrotor()
     c, keep = _cfg(q.replace(params=dict(q.params, obstacles=np.zeros((300, 4)))))
     assert _ws(c)[0] == B.EINVAL
+    for bad in ([[1.0, np.nan, 1.0, 0.5]], [[1.0, 2.0, 1.0, -0.5]], [[1.0, 2.0, 1.0, 2e6]]):
+        c, keep = _cfg(q.replace(params=dict(q.params, obstacles=np.array(bad))))
+        assert _ws(c)[0] == B.EINVAL, bad
+    c, keep = _cfg(q.replace(params=dict(q.params, obstacles=np.array([[1.0, 2.0, 1.0, 1e5]]))))
+    assert _ws(c)[0] == B.OK
+    c, keep = _cfg(q.replace(params=dict(q.params, w_obs=-1.0)))
+    assert _ws(c)[0] == B.EINVAL
     c, keep = _cfg(q.replace(params=dict(q.params, mass=0.0)))
     assert _ws(c)[0] == B.EINVAL
 
