@@ -77,16 +77,20 @@ MLP_PROFILE = "mlp_quadrotor_rollout_K16384_T100_and_training_B4096.md"
 
 
 def rollout_source_hash(sources=ROLLOUT_SOURCES):
-    """SHA-256 of the kernel sources' code: comments and blank lines removed, so a committed
-    counter summary stays valid across edits that do not change what is compiled."""
+    """SHA-256 of the kernel sources' code (comments and blank lines removed) and of the extra
+    compile flags a source has, so a committed counter summary stays valid across edits that
+    do not change what is compiled."""
     import hashlib
     import re
+    from paper_1509_01149_amd.build import SOURCE_FLAGS
     h = hashlib.sha256()
     for f in sources:
         text = open(os.path.join(ROOT, "paper_1509_01149_amd", "csrc", f), encoding="utf-8").read()
         text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
         lines = [re.sub(r"//.*$", "", ln).rstrip() for ln in text.splitlines()]
         h.update("\n".join(ln for ln in lines if ln.strip()).encode())
+        if f in SOURCE_FLAGS:
+            h.update((" " + " ".join(SOURCE_FLAGS[f])).encode())
     return h.hexdigest()
 
 
