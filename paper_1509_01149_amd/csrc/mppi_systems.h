@@ -618,10 +618,12 @@ struct QuadrotorSys {
   __device__ static bool lds_pass(const Params &p, int nj) { return p.n_obs > nj * kRegObs; }
   // Lane j of nj: base (this lane's likelihood-ratio share), the goal term (j = 0) and the
   // barriers of obstacles j, j + nj, ...; with kHit also, in `hit`, the largest crash margin
-  // among the same obstacles (and the ground for j = 0): max of arg - (the obstacle's
+  // among the same obstacles (and the ground for j = 0): max of pen - (the obstacle's
   // threshold) and ground - z, positive exactly when one crash condition holds (the sign of
-  // a rounded difference is the sign of the exact one), from the same barrier arguments
-  // (there the penalty keeps max(0, arg): the argument has a second use, so no clamp folds).
+  // a rounded difference is the sign of the exact one).  pen is the clamped argument, so
+  // the clamp still folds into the subtract: a threshold lies in [0, 1/4], so pen - th > 0
+  // exactly when arg - th > 0 (equal values for arg in [0, 1]; both negative or zero below
+  // 0, both positive above 1).
   template <bool kHit, bool kRegOnly>
   __device__ static float cost_part(const Params &p, const StageView &sv, const Regs &rg, const float *x, int j,
                                     int nj, float base, float &hit) {
@@ -631,10 +633,9 @@ struct QuadrotorSys {
     if constexpr (kHit) h = j == 0 ? p.ground - x[2] : -__builtin_inff();
 #pragma unroll
     for (int t = 0; t < kRegObs; ++t) {
-      const float arg = barrier_arg(rg.o[t], x, xx);
-      const float pen = kHit ? fmaxf(arg, 0.f) : penalty(arg);
+      const float pen = penalty(barrier_arg(rg.o[t], x, xx));
       barrier = fmaf(pen, pen, barrier);
-      if constexpr (kHit) h = fmaxf(h, arg - rg.th[t]);
+      if constexpr (kHit) h = fmaxf(h, pen - rg.th[t]);
     }
     const float4 *ob = reinterpret_cast<const float4 *>(sv.lds);
     const float *th = sv.lds + 4 * p.n_obs;
@@ -642,10 +643,9 @@ struct QuadrotorSys {
     // inside the branch only); left out of the code with kRegOnly
     if (!kRegOnly && __builtin_expect(lds_pass(p, nj), 0)) {
       for (int o = j + nj * kRegObs; o < p.n_obs; o += nj) {
-        const float arg = barrier_arg(ob[o], x, xx);
-        const float pen = kHit ? fmaxf(arg, 0.f) : penalty(arg);
+        const float pen = penalty(barrier_arg(ob[o], x, xx));
         barrier = fmaf(pen, pen, barrier);
-        if constexpr (kHit) h = fmaxf(h, arg - th[o]);
+        if constexpr (kHit) h = fmaxf(h, pen - th[o]);
       }
     }
     hit = h;
