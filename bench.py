@@ -39,8 +39,8 @@ METRIC = "rollout-steps/sec (K*T) and MPPI iters/sec; p50/p99 step latency batch
 
 # Algorithmic FLOP per rollout-step (FMA = 2; the transcendentals and the noise
 # generator's integer work are not counted): the dynamics and state cost of one Euler
-# step plus 5 m for the likelihood-ratio control terms of q-tilde, as in the survey's
-# hand counts.  Quadrotor: about 480 for dynamics and cost, of which the 32 obstacle
+# step plus 5 m for the likelihood-ratio control terms of q-tilde, counted by hand.
+# Quadrotor: about 480 for dynamics and cost, of which the 32 obstacle
 # barriers take about 350, plus 20 -> 500.  Bicycle 45 + 10, cart-pole 40 + 5.  The
 # swing-up cart-pole: 27 + 5.  The crash indicator adds one comparison per obstacle and
 # the ground test and crash cost (500 + 34).
@@ -443,7 +443,8 @@ def time_controller(P, torch, wl, steps, warmup, spl, weighting=0, kernels=0):
 def alu_roofline(wl, times):
     """Roofline of the rollout kernel of an analytic system: algorithmic FP32 FLOP per launch
     (FLOP per rollout-step x K T) over its mean event-timed duration, against the published
-    FP32 peak; with the same rate against this build's unpacked-FP32 issue ceiling, the ops
+    FP32 peak; with the same rate against the unpacked-FP32 issue ceiling (the library is
+    compiled without packed FP32), the ops
     including the noise generator, and the SQ VALU issue share of the committed profile."""
     roll_ms = times["rollout"][0]
     rs = wl.K * wl.T
