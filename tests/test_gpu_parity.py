@@ -295,15 +295,18 @@ def test_swingup_closed_loop_exploration_variance():
     assert avg[1.0] > 2.0 * avg[1000.0]
 
 
-@pytest.mark.parametrize("T", [100, 150])
-def test_crash_indicator_parity(T):
+@pytest.mark.parametrize("T,margin", [(100, 0.1), (150, 0.1), (150, 0.0)])
+def test_crash_indicator_parity(T, margin):
     """Quadrotor with the crash indicator (Section V-C).  The indicator is a threshold on
     the FP32 state, so a sample grazing the ground or an obstacle may crash one step earlier
     or later than in the FP64 oracle: such a flip changes its cost by about crash_cost per
     step.  Flips must be rare (<= 0.5 % of samples); every other sample meets the usual
     per-sample cost tolerance; the update meets the usual bar plus what the flipped samples'
-    weights can move it (sum of their weights on either side times max |du|)."""
+    weights can move it (sum of their weights on either side times max |du|).  With no
+    safety margin the barrier and the obstacle coincide: every obstacle's crash threshold on
+    the barrier argument is zero."""
     wl = W.quadrotor(nu=2.0, K=4096, T=T, crash=True).replace(seed=3)
+    wl = wl.replace(params=dict(wl.params, obs_margin=margin))
     U0 = mppi.initial_sequence(wl)
     with controller(wl) as c:
         m = one_step(wl, c, wl.x0, U0, 0)
